@@ -1,0 +1,20 @@
+"""TEST INFRASTRUCTURE ONLY -- the CPU oracle of the Fisher/SNR path.
+
+A plain, slow, FP64 reference written from the paper (arXiv:2207.06910):
+``gwf_oracle.cpp`` evaluates the strain, SNR and Fisher matrices literally
+(tensor-form antenna patterns, full complex phase, dual-number derivatives,
+compensated trapezoid sums); ``invert.py`` inverts Fisher matrices with
+mpmath, the arbitrary-precision library the paper itself uses (sec. 4.1).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The GPU library shares no code with
+it and never calls it.
+"""
+from .core import (build, load, fisher, strain, strain_cstep, strain_plain, phase_tau,
+                   phase_dpsi_df_cstep, antenna, delay, cut_frequency, psd, grid, constants,
+                   ifos, n_ifo)
+from .invert import covariance
+
+__all__ = ["build", "load", "fisher", "strain", "strain_cstep", "strain_plain", "phase_tau",
+           "phase_dpsi_df_cstep", "antenna", "delay", "cut_frequency", "psd", "grid",
+           "constants", "ifos", "n_ifo", "covariance"]

@@ -1,0 +1,196 @@
+"""TEST INFRASTRUCTURE ONLY -- ctypes front end of the C++ oracle.
+
+Builds ``liboracle.so`` from ``gwf_oracle.cpp`` with g++ (no fast-math, so
+IEEE semantics are kept) and exposes its entry points on numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "gwf_oracle.cpp")
+LIB = os.path.join(HERE, "liboracle.so")
+
+FLAG_EARTH_ROT = 1
+FLAG_TIDAL = 2
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int32)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle (always when force; otherwise only if missing)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
+                               "-fno-fast-math", "-o", tmp, SRC])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        lib = ctypes.CDLL(LIB)
+        lib.orc_cut_frequency.restype = ctypes.c_double
+        lib.orc_psd.restype = ctypes.c_double
+        lib.orc_delay.restype = ctypes.c_double
+        lib.orc_fisher.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_int, _D, _D, _D,
+                                   _I, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
+        lib.orc_strain.argtypes = [_D, ctypes.c_double, ctypes.c_int, _D, ctypes.c_int, _D,
+                                   ctypes.c_int, _D, _D]
+        lib.orc_strain_cstep.argtypes = [_D, ctypes.c_double, ctypes.c_int, _D, ctypes.c_int, _D,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_double, _D]
+        lib.orc_strain_plain.argtypes = [_D, ctypes.c_double, ctypes.c_double, ctypes.c_int, _D,
+                                         ctypes.c_int, _D, ctypes.c_int, _D]
+        lib.orc_phase_tau.argtypes = [_D, ctypes.c_int, ctypes.c_int, _D, _D, _D]
+        lib.orc_phase_cstep_f.argtypes = [_D, ctypes.c_int, ctypes.c_int, _D, ctypes.c_double, _D]
+        lib.orc_antenna.argtypes = [ctypes.c_double] * 7 + [_D, _D]
+        lib.orc_delay.argtypes = [ctypes.c_double] * 4
+        lib.orc_cut_frequency.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.orc_psd.argtypes = [ctypes.c_double] * 3
+        lib.orc_grid.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, _D, _D]
+        lib.orc_constants.argtypes = [_D]
+        lib.orc_n_ifo.argtypes = [ctypes.c_int, _D]
+        lib.orc_ifos.argtypes = [ctypes.c_int, _D, _D]
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def constants() -> dict:
+    out = np.zeros(6)
+    load().orc_constants(_p(out))
+    return dict(zip(["T_SUN", "GPC_S", "OMEGA_E", "R_EARTH_S", "EULER_GAMMA", "PI"], out))
+
+
+def cut_frequency(Mc, eta):
+    return load().orc_cut_frequency(float(Mc), float(eta))
+
+
+def psd(S0, f0, f):
+    return load().orc_psd(float(S0), float(f0), float(f))
+
+
+def grid(fmin, fmax, n):
+    f = np.zeros(n)
+    w = np.zeros(n)
+    load().orc_grid(float(fmin), float(fmax), int(n), _p(f), _p(w))
+    return f, w
+
+
+def n_ifo(sites):
+    s = _f64(sites)
+    return load().orc_n_ifo(len(s), _p(s))
+
+
+def ifos(sites):
+    s = _f64(sites)
+    out = np.zeros((n_ifo(s), 4))
+    load().orc_ifos(len(s), _p(s), _p(out))
+    return out
+
+
+def antenna(lat, gamma, zeta, lst, theta, phi, psi):
+    fp = ctypes.c_double()
+    fx = ctypes.c_double()
+    load().orc_antenna(lat, gamma, zeta, lst, theta, phi, psi, ctypes.byref(fp), ctypes.byref(fx))
+    return fp.value, fx.value
+
+
+def delay(lat, lst, theta, phi):
+    return load().orc_delay(lat, lst, theta, phi)
+
+
+def phase_tau(par13, f, flags=0):
+    par = _f64(par13)
+    f = _f64(f)
+    psi = np.zeros_like(f)
+    tau = np.zeros_like(f)
+    load().orc_phase_tau(_p(par), flags, len(f), _p(f), _p(psi), _p(tau))
+    return psi, tau
+
+
+def phase_dpsi_df_cstep(par13, f, flags=0, h=1e-30):
+    par = _f64(par13)
+    f = _f64(f)
+    out = np.zeros_like(f)
+    load().orc_phase_cstep_f(_p(par), flags, len(f), _p(f), h, _p(out))
+    return out
+
+
+def strain(par13, sites, f, flags, tc_s=0.0, derivs=True):
+    """h[n_ifo][nf] complex and, if derivs, dh[n_ifo][nf][P] complex."""
+    par = _f64(par13)
+    s = _f64(sites)
+    f = _f64(f)
+    ni = n_ifo(s)
+    P = 13 if flags & FLAG_TIDAL else 11
+    h = np.zeros((ni, len(f), 2))
+    dh = np.zeros((ni, len(f), P, 2)) if derivs else None
+    load().orc_strain(_p(par), float(tc_s), len(s), _p(s), len(f), _p(f), flags, _p(h), _p(dh))
+    hc = h[..., 0] + 1j * h[..., 1]
+    if not derivs:
+        return hc
+    return hc, dh[..., 0] + 1j * dh[..., 1]
+
+
+def strain_cstep(par13, sites, f, flags, j, step=1e-30, tc_s=0.0):
+    par = _f64(par13)
+    s = _f64(sites)
+    f = _f64(f)
+    out = np.zeros((n_ifo(s), len(f), 2))
+    load().orc_strain_cstep(_p(par), float(tc_s), len(s), _p(s), len(f), _p(f), flags, int(j),
+                            float(step), _p(out))
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def strain_plain(par13, sites, f, flags, tc_s=0.0, dt=0.0):
+    par = _f64(par13)
+    s = _f64(sites)
+    f = _f64(f)
+    out = np.zeros((n_ifo(s), len(f), 2))
+    load().orc_strain_plain(_p(par), float(tc_s), float(dt), len(s), _p(s), len(f), _p(f), flags,
+                            _p(out))
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def fisher(wl, want_fisher=True, per_ifo=False, nthreads=0):
+    """SNR (and Fisher) of a synthetic workload, as a dict of numpy arrays:
+    snr[N], snr_ifo[n_ifo][N], fisher[P][P][N], fisher_ifo[n_ifo][P][P][N]."""
+    par = _f64(wl.par)
+    n = par.shape[1]
+    s = _f64(wl.site_array())
+    ni = n_ifo(s)
+    P = 13 if wl.flags & FLAG_TIDAL else 11
+    fmin = _f64(wl.fmin)
+    fmax = None if wl.fmax is None else _f64(wl.fmax)
+    npts = np.ascontiguousarray(wl.npts, dtype=np.int32)
+    tc = None if wl.tc_s is None else _f64(wl.tc_s)
+    snr = np.zeros(n)
+    snr_ifo = np.zeros((ni, n))
+    F = np.zeros((P, P, n)) if want_fisher else None
+    Fi = np.zeros((ni, P, P, n)) if (want_fisher and per_ifo) else None
+    load().orc_fisher(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
+                      npts.ctypes.data_as(_I), wl.flags, int(nthreads), _p(snr), _p(snr_ifo),
+                      _p(F), _p(Fi))
+    out = {"snr": snr, "snr_ifo": snr_ifo}
+    if want_fisher:
+        out["fisher"] = F
+    if Fi is not None:
+        out["fisher_ifo"] = Fi
+    return out

@@ -1,0 +1,637 @@
+// gwf_oracle.cpp -- TEST INFRASTRUCTURE ONLY.
+//
+// Plain, slow FP64 CPU reference ("the oracle") for the Fisher/SNR path of
+// the GWFAST method (arXiv:2207.06910).  Only the test-suite, the smoke
+// check and the CPU-baseline leg of the benchmark may load it; the product
+// path never does.  It shares no source with the GPU library.
+//
+// What it computes, literally as defined:
+//   * the TaylorF2 restricted-PN strain of a compact binary (sec. 2.2), with
+//     aligned spins and the tidal terms built from the combinations of
+//     eq. (LamTdelLam_def);
+//   * its projection onto each interferometer with antenna patterns written
+//     as a contraction of the 3D detector tensor with the polarisation
+//     tensors, evaluated at the time t(f) = tc - tau*(f) so that the Earth's
+//     rotation enters both the patterns and the arrival-time (Doppler) phase
+//     (sec. 3, footnote on Earth motion; tau* at 3.5PN as cited in sec. 2.2);
+//   * SNR_i^2 = 4 int |h_i|^2 / S_n,i df and the network sum (sec. 3.2);
+//   * Gamma_ij = 4 Re int d_i h d_j h^* / S_n df summed over interferometers
+//     (sec. 3.2), with all derivatives taken by forward-mode dual numbers,
+//     the same mathematics as the automatic differentiation the paper uses
+//     (sec. 3.3);
+//   * quadrature: the trapezoid rule on the log-spaced grid the paper builds
+//     with geomspace (sec. 2.2), summed with Neumaier compensation.
+//
+// Readings where the paper is silent (PN coefficients, constants, sign and
+// frame conventions) are listed in the design doc; each block below names the
+// source it follows.  The scalar type is a template parameter so that the
+// same code runs on double, on dual numbers (derivatives), on nested dual
+// numbers (gradients of Fisher figures of merit w.r.t. detector parameters)
+// and on std::complex<double> (complex-step derivative checks).
+
+#include <array>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace orc {
+
+// ---------------------------------------------------------------- constants
+// The paper fixes none of these numerically; IAU 2015 nominal values.
+constexpr double PI = 3.14159265358979323846;
+const double C_SI = 299792458.0;                       // m/s
+const double GM_SUN = 1.3271244e20;                    // m^3/s^2
+const double T_SUN = GM_SUN / (C_SI * C_SI * C_SI);    // G Msun / c^3 [s]
+const double AU_M = 149597870700.0;                    // m
+const double PC_M = AU_M * 648000.0 / PI;              // m
+const double GPC_S = 1e9 * PC_M / C_SI;                // 1 Gpc / c [s]
+const double SIDEREAL_DAY = 86164.0905;                // s
+const double OMEGA_E = 2.0 * PI / SIDEREAL_DAY;        // rad/s
+const double R_EARTH = 6.371e6;                        // m (spherical Earth)
+const double EULER_GAMMA = 0.5772156649015329;
+
+enum : int { FLAG_EARTH_ROT = 1, FLAG_TIDAL = 2 };
+enum : int { NPAR = 13 };
+
+// ------------------------------------------------------------ dual numbers
+// Forward-mode automatic differentiation: value plus N partials.
+template <class T, int N>
+struct Dual {
+  T v;
+  T d[N];
+  Dual() : v(0.0) { for (int i = 0; i < N; ++i) d[i] = T(0.0); }
+  Dual(double x) : v(x) { for (int i = 0; i < N; ++i) d[i] = T(0.0); }
+  static Dual lift(const T& x) { Dual r; r.v = x; return r; }
+};
+
+template <class X> struct is_dual { static constexpr bool value = false; };
+template <class T, int N> struct is_dual<Dual<T, N>> { static constexpr bool value = true; };
+
+template <class T, int N>
+Dual<T, N> operator+(const Dual<T, N>& a, const Dual<T, N>& b) {
+  Dual<T, N> r; r.v = a.v + b.v;
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i];
+  return r;
+}
+template <class T, int N>
+Dual<T, N> operator-(const Dual<T, N>& a, const Dual<T, N>& b) {
+  Dual<T, N> r; r.v = a.v - b.v;
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i];
+  return r;
+}
+template <class T, int N>
+Dual<T, N> operator-(const Dual<T, N>& a) {
+  Dual<T, N> r; r.v = -a.v;
+  for (int i = 0; i < N; ++i) r.d[i] = -a.d[i];
+  return r;
+}
+template <class T, int N>
+Dual<T, N> operator*(const Dual<T, N>& a, const Dual<T, N>& b) {
+  Dual<T, N> r; r.v = a.v * b.v;
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+  return r;
+}
+template <class T, int N>
+Dual<T, N> operator/(const Dual<T, N>& a, const Dual<T, N>& b) {
+  Dual<T, N> r; r.v = a.v / b.v;
+  for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - r.v * b.d[i]) / b.v;
+  return r;
+}
+template <class T, int N> Dual<T, N> operator+(const Dual<T, N>& a, double b) { Dual<T, N> r = a; r.v = r.v + b; return r; }
+template <class T, int N> Dual<T, N> operator+(double b, const Dual<T, N>& a) { return a + b; }
+template <class T, int N> Dual<T, N> operator-(const Dual<T, N>& a, double b) { Dual<T, N> r = a; r.v = r.v - b; return r; }
+template <class T, int N> Dual<T, N> operator-(double b, const Dual<T, N>& a) { return (-a) + b; }
+template <class T, int N> Dual<T, N> operator*(const Dual<T, N>& a, double b) {
+  Dual<T, N> r; r.v = a.v * b;
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b;
+  return r;
+}
+template <class T, int N> Dual<T, N> operator*(double b, const Dual<T, N>& a) { return a * b; }
+template <class T, int N> Dual<T, N> operator/(const Dual<T, N>& a, double b) { return a * (1.0 / b); }
+template <class T, int N> Dual<T, N> operator/(double b, const Dual<T, N>& a) { return Dual<T, N>(b) / a; }
+
+// Chain rule for a scalar function with value fv and derivative dfv at a.v.
+template <class T, int N>
+Dual<T, N> chain(const Dual<T, N>& a, const T& fv, const T& dfv) {
+  Dual<T, N> r; r.v = fv;
+  for (int i = 0; i < N; ++i) r.d[i] = dfv * a.d[i];
+  return r;
+}
+template <class T, int N> Dual<T, N> sin(const Dual<T, N>& a) { using std::sin; using std::cos; return chain(a, sin(a.v), cos(a.v)); }
+template <class T, int N> Dual<T, N> cos(const Dual<T, N>& a) { using std::sin; using std::cos; return chain(a, cos(a.v), -sin(a.v)); }
+template <class T, int N> Dual<T, N> exp(const Dual<T, N>& a) { using std::exp; T e = exp(a.v); return chain(a, e, e); }
+template <class T, int N> Dual<T, N> log(const Dual<T, N>& a) { using std::log; return chain(a, log(a.v), T(1.0) / a.v); }
+template <class T, int N> Dual<T, N> sqrt(const Dual<T, N>& a) { using std::sqrt; T s = sqrt(a.v); return chain(a, s, T(0.5) / s); }
+template <class T, int N> Dual<T, N> pow(const Dual<T, N>& a, double p) {
+  using std::pow;
+  return chain(a, pow(a.v, p), T(p) * pow(a.v, p - 1.0));
+}
+
+// Promote a detector-parameter value of type T to the working scalar S.
+template <class S, class T> struct Lift { static S go(const T& x) { return S(x); } };
+template <class T, int N> struct Lift<Dual<T, N>, T> { static Dual<T, N> go(const T& x) { return Dual<T, N>::lift(x); } };
+template <class S, class T> S lift(const T& x) { return Lift<S, T>::go(x); }
+
+// Real value of any scalar type used here.
+inline double val(double x) { return x; }
+inline double val(const std::complex<double>& x) { return x.real(); }
+template <class T, int N> double val(const Dual<T, N>& x) { return val(x.v); }
+
+// ------------------------------------------------------------ summation
+// Neumaier's compensated summation.
+struct NeumaierSum {
+  double s = 0.0, c = 0.0;
+  void add(double x) {
+    double t = s + x;
+    if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x; else c += (x - t) + s;
+    s = t;
+  }
+  double get() const { return s + c; }
+};
+
+// --------------------------------------------------------------- sources
+template <class S>
+struct Source {
+  S Mc, eta, dL, theta, phi, iota, psi, dt, Phic, chi1, chi2, L1, L2;
+  double tcoal_days = 0.0;   // GMST of coalescence in sidereal days
+  double tc_s = 0.0;         // coalescence time used in the 2 pi f tc phase term [s]
+};
+
+// Interferometer geometry; T is the type of the detector parameters.
+template <class T>
+struct Ifo {
+  T lat, lon, gamma;   // radians; gamma = arm-bisector angle from local East
+  double zeta;         // opening angle of the arms
+  T S0;                // analytic PSD scale [1/Hz]
+  double f0;           // analytic PSD knee [Hz]
+};
+
+// Expand sites [lat, lon, gamma, zeta, shape, S0, f0] into interferometers.
+// An L site is one interferometer.  A triangle site is three co-located
+// interferometers with 60-degree arms in a closed loop (sec. 3.1); the first
+// arm points at gamma, so the first interferometer's bisector is at
+// gamma + 30 deg and the other two follow at 120 deg steps.
+inline std::vector<Ifo<double>> expand_sites(int n_site, const double* s) {
+  std::vector<Ifo<double>> out;
+  for (int i = 0; i < n_site; ++i) {
+    const double* r = s + 7 * i;
+    if (r[4] == 1.0) {
+      for (int k = 0; k < 3; ++k)
+        out.push_back({r[0], r[1], r[2] + PI / 6.0 + 2.0 * PI * k / 3.0, PI / 3.0, r[5], r[6]});
+    } else {
+      out.push_back({r[0], r[1], r[2], r[3], r[5], r[6]});
+    }
+  }
+  return out;
+}
+
+// ----------------------------------------------------------- waveform
+// Total mass in seconds and the cut frequency: twice the ISCO orbital
+// frequency, i.e. 1/(6^{3/2} pi G M/c^3) (sec. 2.2 footnote).
+inline double cut_frequency(double Mc, double eta) {
+  double Ms = Mc * std::pow(eta, -0.6) * T_SUN;
+  return 1.0 / (std::pow(6.0, 1.5) * PI * Ms);
+}
+
+// Tidal combinations of eq. (LamTdelLam_def), sec. 2.1.
+template <class S>
+void lambda_tilde(const S& eta, const S& L1, const S& L2, S& Lt, S& dLt) {
+  using std::sqrt;
+  S d = sqrt(1.0 - 4.0 * eta);
+  S e2 = eta * eta, e3 = e2 * eta;
+  S sum = L1 + L2, dif = L1 - L2;
+  Lt = (8.0 / 13.0) * ((1.0 + 7.0 * eta - 31.0 * e2) * sum + d * (1.0 + 9.0 * eta - 11.0 * e2) * dif);
+  dLt = 0.5 * (d * (1.0 - (13272.0 / 1319.0) * eta + (8944.0 / 1319.0) * e2) * sum +
+               (1.0 - (15910.0 / 1319.0) * eta + (32850.0 / 1319.0) * e2 + (3380.0 / 1319.0) * e3) * dif);
+}
+
+// TaylorF2 post-Newtonian phase (without the 2 pi f tc - Phic - pi/4 part),
+// 3.5PN point-particle terms with aligned-spin spin-orbit and 2PN spin-spin
+// corrections, plus the 5PN/6PN tidal terms (refs. of sec. 2.2).
+template <class S>
+S pn_phase(const Source<S>& s, const S& v, bool tidal) {
+  using std::log; using std::sqrt;
+  const double pi = PI, pi2 = PI * PI;
+  S eta = s.eta, e2 = eta * eta, e3 = e2 * eta;
+  S d = sqrt(1.0 - 4.0 * eta);
+  S xs = 0.5 * (s.chi1 + s.chi2), xa = 0.5 * (s.chi1 - s.chi2);
+  S lv = log(v);
+  S p0 = S(1.0);
+  S p2 = 3715.0 / 756.0 + (55.0 / 9.0) * eta;
+  S p3 = -16.0 * pi + (113.0 / 3.0) * d * xa + (113.0 / 3.0 - (76.0 / 3.0) * eta) * xs;
+  S p4 = 15293365.0 / 508032.0 + (27145.0 / 504.0) * eta + (3085.0 / 72.0) * e2
+       + (-405.0 / 8.0 + 200.0 * eta) * xa * xa - (405.0 / 4.0) * d * xa * xs
+       + (-405.0 / 8.0 + 2.5 * eta) * xs * xs;
+  S p5 = (1.0 + 3.0 * lv) * (pi * (38645.0 / 756.0 - (65.0 / 9.0) * eta)
+       - (732985.0 / 2268.0 + (140.0 / 9.0) * eta) * d * xa
+       + (-732985.0 / 2268.0 + (24260.0 / 81.0) * eta + (340.0 / 9.0) * e2) * xs);
+  S p6 = 11583231236531.0 / 4694215680.0 - (640.0 / 3.0) * pi2 - (6848.0 / 21.0) * EULER_GAMMA
+       - (6848.0 / 21.0) * log(4.0 * v)
+       + (-15737765635.0 / 3048192.0 + (2255.0 / 12.0) * pi2) * eta
+       + (76055.0 / 1728.0) * e2 - (127825.0 / 1296.0) * e3
+       + pi * ((2270.0 / 3.0) * d * xa + (2270.0 / 3.0 - 520.0 * eta) * xs);
+  S p7 = pi * (77096675.0 / 254016.0 + (378515.0 / 1512.0) * eta - (74045.0 / 756.0) * e2)
+       + (-25150083775.0 / 3048192.0 + (26804935.0 / 6048.0) * eta - (1985.0 / 48.0) * e2) * d * xa
+       + (-25150083775.0 / 3048192.0 + (10566655595.0 / 762048.0) * eta - (1042165.0 / 3024.0) * e2
+          + (5345.0 / 36.0) * e3) * xs;
+  S v2 = v * v;
+  S series = p0 + v2 * (p2 + v * (p3 + v * (p4 + v * (p5 + v * (p6 + v * p7)))));
+  if (tidal) {
+    S Lt, dLt;
+    lambda_tilde(eta, s.L1, s.L2, Lt, dLt);
+    S v10 = v2 * v2 * v2 * v2 * v2;
+    series = series + (-19.5) * Lt * v10
+           + ((-3115.0 / 64.0) * Lt + (6595.0 / 364.0) * d * dLt) * v10 * v2;
+  }
+  S v5 = v2 * v2 * v;
+  return 3.0 / (128.0 * eta * v5) * series;
+}
+
+// Time to coalescence tau*(f), 3.5PN, non-spinning (the paper cites
+// Buonanno et al. 2009, eq. 3.8b, sec. 2.2).
+template <class S>
+S tau_star(const Source<S>& s, const S& Ms, const S& v) {
+  using std::log;
+  const double pi = PI, pi2 = PI * PI;
+  S eta = s.eta, e2 = eta * eta, e3 = e2 * eta;
+  S t2 = 743.0 / 252.0 + (11.0 / 3.0) * eta;
+  S t3 = S(-32.0 * pi / 5.0);
+  S t4 = 3058673.0 / 508032.0 + (5429.0 / 504.0) * eta + (617.0 / 72.0) * e2;
+  S t5 = pi * (-7729.0 / 252.0 + (13.0 / 3.0) * eta);
+  S t6 = -10052469856691.0 / 23471078400.0 + (128.0 / 3.0) * pi2 + (6848.0 / 105.0) * EULER_GAMMA
+       + (3147553127.0 / 3048192.0 - (451.0 / 12.0) * pi2) * eta
+       - (15211.0 / 1728.0) * e2 + (25565.0 / 1296.0) * e3
+       + (3424.0 / 105.0) * log(16.0 * v * v);
+  S t7 = pi * (-15419335.0 / 127008.0 - (75703.0 / 756.0) * eta + (14809.0 / 378.0) * e2);
+  S v2 = v * v;
+  S series = 1.0 + v2 * (t2 + v * (t3 + v * (t4 + v * (t5 + v * (t6 + v * t7)))));
+  S v8 = v2 * v2 * v2 * v2;
+  return 5.0 * Ms / (256.0 * eta * v8) * series;
+}
+
+// ------------------------------------------------------ detector response
+template <class S> using Vec3 = std::array<S, 3>;
+template <class S> S dot(const Vec3<S>& a, const Vec3<S>& b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Antenna patterns as tensor contractions F+ = D:e+, Fx = D:ex with the
+// detector tensor D = (u u^T - w w^T)/2 built from the unit arm vectors u, w
+// at azimuths gamma -/+ zeta/2 (measured from local East towards North) in
+// the tangent plane at (lat, local sidereal time lst), and the polarisation
+// tensors e+ = X X^T - Y Y^T, ex = X Y^T + Y X^T with X = cos psi e_phi +
+// sin psi e_theta, Y = -sin psi e_phi + cos psi e_theta in the equatorial
+// frame (sec. 3.1 for gamma and zeta; frame conventions are a reading).
+template <class S>
+void antenna_tensor(const S& lat, const S& gamma, double zeta, const S& lst,
+                    const S& theta, const S& phi, const S& psi, S& Fp, S& Fx) {
+  using std::sin; using std::cos;
+  S sl = sin(lst), cl = cos(lst), sa = sin(lat), ca = cos(lat);
+  Vec3<S> E = {-sl, cl, S(0.0)};
+  Vec3<S> N = {-sa * cl, -sa * sl, ca};
+  S au = gamma - 0.5 * zeta, aw = gamma + 0.5 * zeta;
+  Vec3<S> u, w;
+  for (int i = 0; i < 3; ++i) {
+    u[i] = cos(au) * E[i] + sin(au) * N[i];
+    w[i] = cos(aw) * E[i] + sin(aw) * N[i];
+  }
+  S st = sin(theta), ct = cos(theta), sp = sin(phi), cp = cos(phi);
+  Vec3<S> et = {ct * cp, ct * sp, -st};
+  Vec3<S> ep = {-sp, cp, S(0.0)};
+  S cs = cos(psi), ss = sin(psi);
+  Vec3<S> X, Y;
+  for (int i = 0; i < 3; ++i) {
+    X[i] = cs * ep[i] + ss * et[i];
+    Y[i] = -ss * ep[i] + cs * et[i];
+  }
+  S fp = S(0.0), fx = S(0.0);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      S D = 0.5 * (u[i] * u[j] - w[i] * w[j]);
+      fp = fp + D * (X[i] * X[j] - Y[i] * Y[j]);
+      fx = fx + D * (X[i] * Y[j] + Y[i] * X[j]);
+    }
+  Fp = fp; Fx = fx;
+}
+
+// Arrival-time offset of the interferometer w.r.t. the geocentre:
+// -(n . r_det)/c with n the unit vector to the source and r_det the site
+// on a spherical Earth (the Doppler term of the Earth-motion footnote).
+template <class S>
+S geocentre_delay(const S& lat, const S& lst, const S& theta, const S& phi) {
+  using std::sin; using std::cos;
+  Vec3<S> n = {sin(theta) * cos(phi), sin(theta) * sin(phi), cos(theta)};
+  Vec3<S> r = {cos(lat) * cos(lst), cos(lat) * sin(lst), sin(lat)};
+  return -(R_EARTH / C_SI) * dot(n, r);
+}
+
+// Analytic PSD used by the benchmark networks.
+template <class T>
+T psd(const T& S0, double f0, double f) {
+  double x = f / f0, x2 = x * x;
+  double shape = std::pow(x, -4.14) - 5.0 / x2 + 111.0 * (1.0 - x2 + 0.5 * x2 * x2) / (1.0 + 0.5 * x2);
+  return S0 * shape;
+}
+
+// Strain h_i(f) at one interferometer: restricted amplitude (Newtonian
+// order, sqrt(5/24) pi^{-2/3} (G Mc/c^3)^{5/6} f^{-7/6} c/dL) times the
+// pattern-weighted polarisations, h+ ~ (1+cos^2 iota)/2, hx ~ i cos iota,
+// with the phase Psi = 2 pi f (tc + dt + Delta) - Phic - pi/4 + Psi_PN.
+template <class S, class T>
+void strain(const Source<S>& s, const Ifo<T>& ifo, double f, int flags, S& hre, S& him) {
+  using std::sin; using std::cos; using std::pow; using std::sqrt;
+  S Ms = s.Mc * pow(s.eta, -0.6) * T_SUN;
+  S v = pow(PI * Ms * f, 1.0 / 3.0);
+  S tau = tau_star(s, Ms, v);
+  // GMST at t(f): 2 pi tcoal + Omega (dt - tau*(f)); without rotation the
+  // patterns are frozen at the coalescence time.
+  S thG = (flags & FLAG_EARTH_ROT) ? (2.0 * PI * s.tcoal_days + OMEGA_E * (s.dt - tau))
+                                   : (2.0 * PI * s.tcoal_days + OMEGA_E * s.dt);
+  S lat = lift<S>(ifo.lat), lon = lift<S>(ifo.lon), gam = lift<S>(ifo.gamma);
+  S lst = thG + lon;
+  S Fp, Fx;
+  antenna_tensor(lat, gam, ifo.zeta, lst, s.theta, s.phi, s.psi, Fp, Fx);
+  S Delta = geocentre_delay(lat, lst, s.theta, s.phi);
+  S ci = cos(s.iota);
+  S amp = (sqrt(5.0 / 24.0) * pow(PI, -2.0 / 3.0)) * pow(s.Mc * T_SUN, 5.0 / 6.0) * pow(f, -7.0 / 6.0) /
+          (s.dL * GPC_S);
+  S qre = amp * Fp * 0.5 * (1.0 + ci * ci);
+  S qim = amp * Fx * ci;
+  S Psi = 2.0 * PI * f * (s.tc_s + s.dt + Delta) - s.Phic - 0.25 * PI + pn_phase(s, v, (flags & FLAG_TIDAL) != 0);
+  S c = cos(Psi), sn = sin(Psi);
+  hre = qre * c - qim * sn;
+  him = qre * sn + qim * c;
+}
+
+// ------------------------------------------------------------------ grid
+// Log-spaced grid with fixed end points, as numpy's geomspace builds it
+// (sec. 2.2 example): f_k = fmin exp(k D), D = ln(fmax/fmin)/(n-1), with
+// f_0 = fmin and f_{n-1} = fmax exactly.  Trapezoid weights, literally:
+// w_0 = (f_1-f_0)/2, w_k = (f_{k+1}-f_{k-1})/2, w_{n-1} = (f_{n-1}-f_{n-2})/2.
+inline void make_grid(double fmin, double fmax, int n, std::vector<double>& f, std::vector<double>& w) {
+  f.assign(n, 0.0);
+  w.assign(n, 0.0);
+  double D = std::log(fmax / fmin) / (n - 1);
+  for (int k = 0; k < n; ++k) f[k] = fmin * std::exp(k * D);
+  f[0] = fmin;
+  f[n - 1] = fmax;
+  for (int k = 0; k < n; ++k) {
+    double hi = f[k < n - 1 ? k + 1 : k], lo = f[k > 0 ? k - 1 : k];
+    w[k] = 0.5 * (hi - lo);
+  }
+}
+
+// ----------------------------------------------------- per-event sums
+template <class S>
+Source<S> make_source(const double* par, double tc_s) {
+  Source<S> s;
+  s.Mc = S(par[0]); s.eta = S(par[1]); s.dL = S(par[2]); s.theta = S(par[3]);
+  s.phi = S(par[4]); s.iota = S(par[5]); s.psi = S(par[6]); s.dt = S(0.0);
+  s.Phic = S(par[8]); s.chi1 = S(par[9]); s.chi2 = S(par[10]);
+  s.L1 = S(par[11]); s.L2 = S(par[12]);
+  s.tcoal_days = par[7];
+  s.tc_s = tc_s;
+  return s;
+}
+
+// Slot i of the Fisher matrix, in the parameter order of the public tables.
+template <class S>
+S& slot(Source<S>& s, int i) {
+  switch (i) {
+    case 0: return s.Mc; case 1: return s.eta; case 2: return s.dL; case 3: return s.theta;
+    case 4: return s.phi; case 5: return s.iota; case 6: return s.psi; case 7: return s.dt;
+    case 8: return s.Phic; case 9: return s.chi1; case 10: return s.chi2; case 11: return s.L1;
+    default: return s.L2;
+  }
+}
+
+// SNR^2 per interferometer and Fisher per interferometer (optional) for one
+// event, derivatives by Dual<double,P>; all sums compensated.
+template <int P>
+void fisher_event(const double* par, double tc_s, const std::vector<Ifo<double>>& ifos,
+                  double fmin, double fmax, int n, int flags,
+                  double* snr2_ifo, double* F_ifo /* [n_ifo][P][P] */) {
+  using S = Dual<double, P>;
+  Source<S> s = make_source<S>(par, tc_s);
+  for (int i = 0; i < P; ++i) slot(s, i).d[i] = 1.0;
+  std::vector<double> f, w;
+  make_grid(fmin, fmax, n, f, w);
+  const int nifo = (int)ifos.size();
+  for (int d = 0; d < nifo; ++d) {
+    NeumaierSum snr;
+    std::vector<NeumaierSum> G(P * P);
+    for (int k = 0; k < n; ++k) {
+      S hre, him;
+      strain(s, ifos[d], f[k], flags, hre, him);
+      double om = 4.0 * w[k] / psd(ifos[d].S0, ifos[d].f0, f[k]);
+      snr.add(om * (hre.v * hre.v + him.v * him.v));
+      for (int a = 0; a < P; ++a)
+        for (int b = a; b < P; ++b)
+          G[a * P + b].add(om * (hre.d[a] * hre.d[b] + him.d[a] * him.d[b]));
+    }
+    snr2_ifo[d] = snr.get();
+    for (int a = 0; a < P; ++a)
+      for (int b = a; b < P; ++b) {
+        double g = G[a * P + b].get();
+        F_ifo[(d * P + a) * P + b] = g;
+        F_ifo[(d * P + b) * P + a] = g;
+      }
+  }
+}
+
+void snr_event(const double* par, double tc_s, const std::vector<Ifo<double>>& ifos, double fmin,
+               double fmax, int n, int flags, double* snr2_ifo) {
+  Source<double> s = make_source<double>(par, tc_s);
+  std::vector<double> f, w;
+  make_grid(fmin, fmax, n, f, w);
+  for (size_t d = 0; d < ifos.size(); ++d) {
+    NeumaierSum snr;
+    for (int k = 0; k < n; ++k) {
+      double hre, him;
+      strain(s, ifos[d], f[k], flags, hre, him);
+      snr.add(4.0 * w[k] / psd(ifos[d].S0, ifos[d].f0, f[k]) * (hre * hre + him * him));
+    }
+    snr2_ifo[d] = snr.get();
+  }
+}
+
+}  // namespace orc
+
+// =================================================================== C API
+using namespace orc;
+
+extern "C" {
+
+// Constants, for the record of what the oracle assumed.
+void orc_constants(double* out /* [6] */) {
+  out[0] = T_SUN; out[1] = GPC_S; out[2] = OMEGA_E; out[3] = R_EARTH / C_SI; out[4] = EULER_GAMMA; out[5] = PI;
+}
+
+double orc_cut_frequency(double Mc, double eta) { return cut_frequency(Mc, eta); }
+double orc_psd(double S0, double f0, double f) { return psd(S0, f0, f); }
+
+void orc_grid(double fmin, double fmax, int n, double* f, double* w) {
+  std::vector<double> ff, ww;
+  make_grid(fmin, fmax, n, ff, ww);
+  std::memcpy(f, ff.data(), n * sizeof(double));
+  std::memcpy(w, ww.data(), n * sizeof(double));
+}
+
+int orc_n_ifo(int n_site, const double* sites) { return (int)expand_sites(n_site, sites).size(); }
+
+// Interferometer geometry after expanding triangles: [n_ifo][4] = lat, lon, gamma, zeta.
+void orc_ifos(int n_site, const double* sites, double* out) {
+  auto v = expand_sites(n_site, sites);
+  for (size_t i = 0; i < v.size(); ++i) {
+    out[4 * i] = v[i].lat; out[4 * i + 1] = v[i].lon; out[4 * i + 2] = v[i].gamma; out[4 * i + 3] = v[i].zeta;
+  }
+}
+
+void orc_antenna(double lat, double gamma, double zeta, double lst, double theta, double phi,
+                 double psi, double* Fp, double* Fx) {
+  antenna_tensor(lat, gamma, zeta, lst, theta, phi, psi, *Fp, *Fx);
+}
+
+double orc_delay(double lat, double lst, double theta, double phi) {
+  return geocentre_delay(lat, lst, theta, phi);
+}
+
+// PN phase and tau*(f) of one event on nf frequencies.
+void orc_phase_tau(const double* par, int flags, int nf, const double* f, double* psi_pn, double* tau) {
+  Source<double> s = make_source<double>(par, 0.0);
+  double Ms = s.Mc * std::pow(s.eta, -0.6) * T_SUN;
+  for (int k = 0; k < nf; ++k) {
+    double v = std::pow(PI * Ms * f[k], 1.0 / 3.0);
+    psi_pn[k] = pn_phase(s, v, (flags & FLAG_TIDAL) != 0);
+    tau[k] = tau_star(s, Ms, v);
+  }
+}
+
+// Complex-step version of the PN phase: Im(Psi(f + i h))/h = dPsi/df.
+void orc_phase_cstep_f(const double* par, int flags, int nf, const double* f, double h, double* dpsi_df) {
+  using C = std::complex<double>;
+  Source<C> s = make_source<C>(par, 0.0);
+  C Ms = s.Mc * std::pow(s.eta, -0.6) * T_SUN;
+  for (int k = 0; k < nf; ++k) {
+    C v = std::pow(PI * Ms * C(f[k], h), 1.0 / 3.0);
+    dpsi_df[k] = pn_phase(s, v, (flags & FLAG_TIDAL) != 0).imag() / h;
+  }
+}
+
+// Strain of one event at every interferometer on an explicit frequency list,
+// h[(i*nf + k)*2 + {0,1}], and optionally its P derivatives by dual numbers,
+// dh[((i*nf + k)*P + j)*2 + {0,1}].
+int orc_strain(const double* par, double tc_s, int n_site, const double* sites, int nf,
+               const double* f, int flags, double* h, double* dh) {
+  auto ifos = expand_sites(n_site, sites);
+  const int P = (flags & FLAG_TIDAL) ? 13 : 11;
+  for (size_t i = 0; i < ifos.size(); ++i)
+    for (int k = 0; k < nf; ++k) {
+      if (P == 13) {
+        using S = Dual<double, 13>;
+        Source<S> s = make_source<S>(par, tc_s);
+        for (int j = 0; j < 13; ++j) slot(s, j).d[j] = 1.0;
+        S hr, hi;
+        strain(s, ifos[i], f[k], flags, hr, hi);
+        h[(i * nf + k) * 2] = hr.v; h[(i * nf + k) * 2 + 1] = hi.v;
+        if (dh) for (int j = 0; j < 13; ++j) {
+          dh[((i * nf + k) * 13 + j) * 2] = hr.d[j]; dh[((i * nf + k) * 13 + j) * 2 + 1] = hi.d[j];
+        }
+      } else {
+        using S = Dual<double, 11>;
+        Source<S> s = make_source<S>(par, tc_s);
+        for (int j = 0; j < 11; ++j) slot(s, j).d[j] = 1.0;
+        S hr, hi;
+        strain(s, ifos[i], f[k], flags, hr, hi);
+        h[(i * nf + k) * 2] = hr.v; h[(i * nf + k) * 2 + 1] = hi.v;
+        if (dh) for (int j = 0; j < 11; ++j) {
+          dh[((i * nf + k) * 11 + j) * 2] = hr.d[j]; dh[((i * nf + k) * 11 + j) * 2 + 1] = hi.d[j];
+        }
+      }
+    }
+  return 0;
+}
+
+// Complex-step derivative of the strain w.r.t. parameter slot j (slot 7 is
+// the coalescence-time shift in seconds): dh = Im h(par + i step e_j)/step,
+// applied to the real and the imaginary part of h separately.
+int orc_strain_cstep(const double* par, double tc_s, int n_site, const double* sites, int nf,
+                     const double* f, int flags, int j, double step, double* dh) {
+  using C = std::complex<double>;
+  auto ifos = expand_sites(n_site, sites);
+  Source<C> s = make_source<C>(par, tc_s);
+  slot(s, j) = slot(s, j) + C(0.0, step);
+  for (size_t i = 0; i < ifos.size(); ++i)
+    for (int k = 0; k < nf; ++k) {
+      C hr, hi;
+      strain(s, ifos[i], f[k], flags, hr, hi);
+      dh[(i * nf + k) * 2] = hr.imag() / step;
+      dh[(i * nf + k) * 2 + 1] = hi.imag() / step;
+    }
+  return 0;
+}
+
+// Plain strain (double) with the coalescence-time slot shifted by dt seconds
+// and the other slots as given; used for finite-difference checks.
+int orc_strain_plain(const double* par, double tc_s, double dt, int n_site, const double* sites,
+                     int nf, const double* f, int flags, double* h) {
+  auto ifos = expand_sites(n_site, sites);
+  Source<double> s = make_source<double>(par, tc_s);
+  s.dt = dt;
+  for (size_t i = 0; i < ifos.size(); ++i)
+    for (int k = 0; k < nf; ++k) strain(s, ifos[i], f[k], flags, h[(i * nf + k) * 2], h[(i * nf + k) * 2 + 1]);
+  return 0;
+}
+
+// SNR and Fisher matrices of n events (parameters [13][ld], event fastest).
+// Outputs (any may be NULL except snr):
+//   snr[n]; snr_ifo[n_ifo][n] (SNR of each interferometer);
+//   fisher[P][P][n] network Fisher; fisher_ifo[n_ifo][P][P][n].
+// fmax NULL means each grid ends at the event's cut frequency.
+int orc_fisher(int64_t n, const double* par, int64_t ld, const double* tc_s, int n_site,
+               const double* sites, const double* fmin, const double* fmax, const int32_t* npts,
+               int flags, int nthreads, double* snr, double* snr_ifo, double* fisher,
+               double* fisher_ifo) {
+  auto ifos = expand_sites(n_site, sites);
+  const int nifo = (int)ifos.size();
+  const int P = (flags & FLAG_TIDAL) ? 13 : 11;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t e = 0; e < n; ++e) {
+    double p[13];
+    for (int i = 0; i < 13; ++i) p[i] = par[i * ld + e];
+    double fhi = fmax ? fmax[e] : cut_frequency(p[0], p[1]);
+    double tcs = tc_s ? tc_s[e] : 0.0;
+    std::vector<double> s2(nifo), F;
+    if (fisher || fisher_ifo) {
+      F.assign((size_t)nifo * P * P, 0.0);
+      if (P == 13) fisher_event<13>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data(), F.data());
+      else fisher_event<11>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data(), F.data());
+    } else {
+      snr_event(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data());
+    }
+    NeumaierSum tot;
+    for (int d = 0; d < nifo; ++d) tot.add(s2[d]);
+    snr[e] = std::sqrt(tot.get());
+    if (snr_ifo) for (int d = 0; d < nifo; ++d) snr_ifo[d * n + e] = std::sqrt(s2[d]);
+    if (fisher)
+      for (int a = 0; a < P; ++a)
+        for (int b = 0; b < P; ++b) {
+          NeumaierSum g;
+          for (int d = 0; d < nifo; ++d) g.add(F[((size_t)d * P + a) * P + b]);
+          fisher[((int64_t)a * P + b) * n + e] = g.get();
+        }
+    if (fisher_ifo)
+      for (int d = 0; d < nifo; ++d)
+        for (int a = 0; a < P * P; ++a) fisher_ifo[((int64_t)d * P * P + a) * n + e] = F[(size_t)d * P * P + a];
+  }
+  return 0;
+}
+
+}  // extern "C"

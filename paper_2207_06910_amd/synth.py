@@ -1,0 +1,204 @@
+"""Seeded synthetic workloads for the Fisher/SNR path.
+
+This module only *draws* inputs: event parameters, detector sites and
+frequency-grid descriptors, with the shapes and distributions of the
+compact-binary catalogues the method is run on.  It contains none of the
+method's arithmetic (no waveform, no antenna pattern, no PSD evaluation);
+both the GPU path and the CPU oracle read the same arrays from it.
+
+Parameter order (the Fisher row order, with aligned spins given as
+chi1z/chi2z and the two tidal deformabilities last):
+
+    0 Mc [Msun, detector frame]   1 eta            2 dL [Gpc]
+    3 theta [rad]                 4 phi [rad]      5 iota [rad]
+    6 psi [rad]                   7 tcoal [GMST days; Fisher column per s]
+    8 Phicoal [rad]               9 chi1z          10 chi2z
+    11 Lambda1                    12 Lambda2
+
+Units follow the paper's parameter table (sec. 2.1, Table 1).  The sky
+angles are theta = pi/2 - dec and phi = RA.  Masses are ordered m1 >= m2,
+so chi1z and Lambda1 belong to the heavier body.
+
+Grid lengths of the BNS catalogue are set by the total mass, i.e. by the
+cut frequency that scales as 1/M: n_e = 2000 + floor(18000 u_e) with
+u_e = ln(4.4 Msun / M_e) / ln 2 for M_e in [2.2, 4.4] Msun.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+NPAR_MAX = 13
+PAR_NAMES = ("Mc", "eta", "dL", "theta", "phi", "iota", "psi", "tcoal",
+             "Phicoal", "chi1z", "chi2z", "Lambda1", "Lambda2")
+PAR = {n: i for i, n in enumerate(PAR_NAMES)}
+
+SHAPE_L = 0
+SHAPE_T = 1
+
+FLAG_EARTH_ROT = 1
+FLAG_TIDAL = 2
+
+DEG = math.pi / 180.0
+
+# Detector sites of the paper's Table 2 (lat, lon, gamma in degrees; zeta; shape).
+SITES = {
+    "H1": (46.5, -119.4, 171.0, 90.0, SHAPE_L),
+    "L1": (30.6, -90.8, 242.7, 90.0, SHAPE_L),
+    "Virgo": (43.6, 10.5, 115.6, 90.0, SHAPE_L),
+    "KAGRA": (36.4, 137.3, 15.4, 90.0, SHAPE_L),
+    "LIGOI": (19.6, 77.0, 287.4, 90.0, SHAPE_L),
+    "ETS": (40.5, 9.4, 0.0, 60.0, SHAPE_T),
+    "ETMR": (50.7, 5.9, 0.0, 60.0, SHAPE_T),
+    "CE1Id": (43.8, -112.8, -45.0, 90.0, SHAPE_L),
+    "CE2NM": (33.2, -106.5, -105.0, 90.0, SHAPE_L),
+    "CE2NSW": (-34.0, 145.0, 0.0, 90.0, SHAPE_L),
+}
+
+SEEDS = {"bbh100": 2207069100, "bns1e4": 2207069101, "mixed1e4": 2207069103,
+         "catalog1e6": 2207069104}
+
+
+@dataclass
+class Site:
+    """One detector site in radians. A triangle (shape T) is three
+    co-located 60-degree interferometers; gamma is its first arm's angle
+    from local East, for an L it is the arm bisector's angle."""
+    lat: float
+    lon: float
+    gamma: float
+    zeta: float
+    shape: int
+    S0: float = 1e-49      # analytic PSD scale [1/Hz]
+    f0: float = 215.0      # analytic PSD knee [Hz]
+
+    @property
+    def n_ifo(self) -> int:
+        return 3 if self.shape == SHAPE_T else 1
+
+
+@dataclass
+class Workload:
+    name: str
+    par: np.ndarray              # float64 [13][N]
+    sites: list
+    fmin: np.ndarray             # float64 [N]
+    npts: np.ndarray             # int32 [N]
+    fmax: np.ndarray | None      # float64 [N] or None: grid ends at each event's cut frequency
+    flags: int
+    npar: int                    # 11 (no tides) or 13
+    tc_s: np.ndarray | None = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.par.shape[1]
+
+    @property
+    def n_ifo(self) -> int:
+        return sum(s.n_ifo for s in self.sites)
+
+    def subset(self, idx) -> "Workload":
+        idx = np.asarray(idx)
+        return Workload(self.name + "[sub]", np.ascontiguousarray(self.par[:, idx]),
+                        list(self.sites), self.fmin[idx].copy(), self.npts[idx].copy(),
+                        None if self.fmax is None else self.fmax[idx].copy(),
+                        self.flags, self.npar,
+                        None if self.tc_s is None else self.tc_s[idx].copy(), dict(self.meta))
+
+    def with_npts(self, n: int) -> "Workload":
+        w = self.subset(np.arange(self.n))
+        w.npts = np.full(self.n, n, dtype=np.int32)
+        return w
+
+    def site_array(self) -> np.ndarray:
+        """[n_site][7] = lat, lon, gamma, zeta, shape, S0, f0."""
+        return np.array([[s.lat, s.lon, s.gamma, s.zeta, float(s.shape), s.S0, s.f0]
+                         for s in self.sites], dtype=np.float64).reshape(-1, 7)
+
+
+def site(name: str, S0: float = 1e-49, f0: float = 215.0) -> Site:
+    lat, lon, gam, zeta, shape = SITES[name]
+    return Site(lat * DEG, lon * DEG, gam * DEG, zeta * DEG, shape, S0, f0)
+
+
+def _masses_to_mc_eta(m1, m2):
+    m = m1 + m2
+    eta = m1 * m2 / (m * m)
+    mc = m * eta ** 0.6
+    return mc, eta
+
+
+def _isotropic(rng, n, par):
+    par[3] = np.arccos(rng.uniform(-1.0, 1.0, n))
+    par[4] = rng.uniform(0.0, 2 * np.pi, n)
+    par[5] = np.arccos(rng.uniform(-1.0, 1.0, n))
+    par[6] = rng.uniform(0.0, np.pi, n)
+    par[7] = rng.uniform(0.0, 1.0, n)
+    par[8] = rng.uniform(0.0, 2 * np.pi, n)
+
+
+def _random_sites(rng, shapes):
+    out = []
+    for shape in shapes:
+        lat = float(np.arcsin(rng.uniform(-1.0, 1.0)))
+        lon = float(rng.uniform(-np.pi, np.pi))
+        gam = float(rng.uniform(0.0, np.pi))
+        s0 = float(10.0 ** rng.uniform(-51.0, -49.0))
+        f0 = float(rng.uniform(100.0, 300.0))
+        zeta = np.pi / 3 if shape == SHAPE_T else np.pi / 2
+        out.append(Site(lat, lon, gam, zeta, shape, s0, f0))
+    return out
+
+
+def bbh100(n: int = 100, npts: int = 1000, seed: int = SEEDS["bbh100"]) -> Workload:
+    """100 BBH events, one L-shaped detector at the H1 site, no Earth
+    rotation, analytic PSD with S0 = 1e-49 /Hz and a 215 Hz knee, 1000
+    log-spaced points from 10 Hz to the cut frequency, 11 parameters."""
+    rng = np.random.default_rng(seed)
+    par = np.zeros((NPAR_MAX, n))
+    par[0] = rng.uniform(5.0, 40.0, n)
+    par[1] = rng.uniform(0.1, 0.25, n)
+    par[2] = rng.uniform(100.0, 3000.0, n) / 1000.0
+    _isotropic(rng, n, par)
+    par[9] = rng.uniform(-0.5, 0.5, n)
+    par[10] = rng.uniform(-0.5, 0.5, n)
+    return Workload("bbh100", par, [site("H1")], np.full(n, 10.0),
+                    np.full(n, npts, dtype=np.int32), None, 0, 11)
+
+
+def bns_masses(rng, n):
+    m = rng.uniform(1.1, 2.2, (2, n))
+    m1 = np.maximum(m[0], m[1])
+    m2 = np.minimum(m[0], m[1])
+    return m1, m2
+
+
+def bns1e4(n: int = 10000, seed: int = SEEDS["bns1e4"], nmin: int = 2000,
+           nspan: int = 18000) -> Workload:
+    """10^4 BNS events on a 3G-like network: one triangle (three 60-degree
+    interferometers) and two L-shaped sites at seeded positions, each with
+    its own analytic PSD scale and knee; Earth rotation on; tidal terms on
+    (13 parameters); grids from 2 Hz to the cut frequency with 2000-20000
+    log-spaced points set by the total mass."""
+    rng = np.random.default_rng(seed)
+    par = np.zeros((NPAR_MAX, n))
+    m1, m2 = bns_masses(rng, n)
+    par[0], par[1] = _masses_to_mc_eta(m1, m2)
+    par[2] = rng.uniform(50.0, 2000.0, n) / 1000.0
+    _isotropic(rng, n, par)
+    par[9] = rng.uniform(-0.05, 0.05, n)
+    par[10] = rng.uniform(-0.05, 0.05, n)
+    par[11] = rng.uniform(0.0, 2000.0, n)
+    par[12] = rng.uniform(0.0, 2000.0, n)
+    sites = _random_sites(rng, [SHAPE_T, SHAPE_L, SHAPE_L])
+    mtot = m1 + m2
+    u = np.clip(np.log(4.4 / mtot) / np.log(2.0), 0.0, 1.0)
+    npts = (nmin + np.floor(nspan * u)).astype(np.int32)
+    return Workload("bns1e4", par, sites, np.full(n, 2.0), npts, None,
+                    FLAG_EARTH_ROT | FLAG_TIDAL, 13, meta={"m1": m1, "m2": m2})
+
+
+WORKLOADS = {"bbh100": bbh100, "bns1e4": bns1e4}

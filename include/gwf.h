@@ -1,0 +1,206 @@
+/*
+ * gwf.h -- C ABI of libgwf, the MI355X (gfx950) Fisher/SNR library.
+ *
+ * The library computes, for catalogues of compact-binary signals seen by a
+ * network of ground-based interferometers, the matched-filter SNR and the
+ * Fisher information matrix of the GWFAST method (arXiv:2207.06910), and
+ * inverts the Fisher matrices into covariances:
+ *
+ *   SNR_i^2     = 4 int |h_i(f)|^2 / S_n,i(f) df                 (sec. 3.2)
+ *   SNR^2       = sum_i SNR_i^2                                     (sec. 3.2)
+ *   Gamma_ab    = sum_i 4 Re int d_a h_i d_b h_i^* / S_n,i df     (sec. 3.2)
+ *   Cov         = Gamma^-1 by normalised Cholesky                  (sec. 4.1)
+ *
+ * with h_i the TaylorF2 restricted-PN strain (sec. 2.2, aligned spins,
+ * optional tidal terms) projected on interferometer i with its antenna
+ * patterns and arrival-time phase evaluated at the time t(f) = tc - tau*(f),
+ * so that the Earth's rotation during the signal is included (sec. 3).
+ * Integrals are trapezoid sums over log-spaced grids (sec. 2.2).
+ *
+ * Conventions
+ *   - All array arguments are DEVICE pointers owned by the caller (for
+ *     example the data of torch tensors on a ROCm device).  Descriptor
+ *     structs (gwf_events, gwf_network, gwf_grid) live in host memory and are
+ *     read only during the call.
+ *   - Every compute call is asynchronous on `stream` (a hipStream_t; NULL is
+ *     the null stream) and never synchronises it.  Outputs are valid once
+ *     the stream has reached the call.
+ *   - Structural argument errors (NULL pointers, sizes, descriptor fields,
+ *     non-finite host-side geometry) are detected on the host before any
+ *     launch and reported as GWF_E_INVALID_ARG; nothing is launched then.
+ *     Per-event problems never fail a call: they are reported per event in
+ *     the status[] array (bit flags GWF_EV_*), and the outputs of such an
+ *     event are set to 0 (SNR/Fisher) or NaN (inversion outputs).
+ *   - HIP failures at launch are reported as GWF_E_HIP; gwf_last_error()
+ *     returns a message.  Device faults surface at the caller's next
+ *     synchronisation.
+ *   - The library holds no device memory of its own between calls except
+ *     inside a plan (gwf_plan_*), and never frees caller memory.
+ */
+#ifndef GWF_H
+#define GWF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GWF_VERSION 1
+
+/* ------------------------------------------------------------- statuses */
+typedef int32_t gwf_status;
+enum {
+  GWF_OK = 0,
+  GWF_E_INVALID_ARG = 1,
+  GWF_E_UNSUPPORTED = 2,
+  GWF_E_HIP = 3,
+  GWF_E_NOMEM = 4
+};
+
+/* per-event status bits */
+enum {
+  GWF_EV_OK = 0,
+  GWF_EV_INVALID_PARAM = 1, /* Mc<=0, eta outside (0,1/4], dL<=0, |chi|>1,
+                               Lambda<0, grid with n<2 or fmax<=fmin<=0     */
+  GWF_EV_NOT_PD = 2,        /* Cholesky of the normalised Fisher failed     */
+  GWF_EV_ILL_COND = 4,      /* condition number above cond_max: not inverted */
+  GWF_EV_NONFINITE = 8,     /* a non-finite parameter or result            */
+  GWF_EV_SKIPPED_SNR = 16   /* SNR <= snr_th: Fisher not computed           */
+};
+
+/* --------------------------------------------------------- parameters */
+/* Row order of the parameter array and of the Fisher matrix (sec. 3.2,
+ * with chi1z/chi2z as the spin basis and the two tidal deformabilities
+ * last).  Units as in the paper's Table 1: Mc in solar masses (detector
+ * frame), dL in Gpc, angles in radians, theta = pi/2 - dec, phi = RA.
+ * Row GWF_TCOAL holds the GMST of coalescence in sidereal days (1 day =
+ * 2 pi of Earth rotation); the matching Fisher row/column is the derivative
+ * with respect to the coalescence time in SECONDS.  Masses are ordered
+ * m1 >= m2 (chi1z, Lambda1 belong to the heavier body). */
+enum {
+  GWF_MC = 0, GWF_ETA, GWF_DL, GWF_THETA, GWF_PHI, GWF_IOTA, GWF_PSI,
+  GWF_TCOAL, GWF_PHICOAL, GWF_CHI1Z, GWF_CHI2Z, GWF_LAMBDA1, GWF_LAMBDA2,
+  GWF_NPAR_MAX = 13
+};
+
+/* call flags */
+enum {
+  GWF_EARTH_ROT = 1, /* patterns and arrival-time phase at t(f); otherwise
+                        frozen at the coalescence time (sec. 3, footnote)  */
+  GWF_TIDAL = 2      /* 5PN/6PN tidal phase; Fisher has 13 rows instead of 11 */
+};
+
+typedef struct gwf_events {
+  int64_t n;           /* number of events, >= 1                              */
+  int64_t ld;          /* row stride of par in elements, >= n                 */
+  const double* par;   /* device [GWF_NPAR_MAX][ld]: row r, event e at par[r*ld+e].
+                          Rows LAMBDA1/LAMBDA2 are read only with GWF_TIDAL.   */
+  const double* tc_s;  /* device [n] or NULL: coalescence time in seconds used
+                          only in the 2 pi f tc term of the waveform phase     */
+} gwf_events;
+
+/* ------------------------------------------------------------ detectors */
+enum { GWF_SHAPE_L = 0, GWF_SHAPE_T = 1 };
+enum { GWF_PSD_ANALYTIC = 0 };
+
+/* One detector site (sec. 3.1, Table 2), angles in radians.  An L site is
+ * one interferometer whose arm bisector makes the angle gamma with local
+ * East (counted towards North) and whose arms open by zeta.  A T site is
+ * three co-located interferometers with 60-degree arms in a closed loop;
+ * gamma is its first arm's angle, so the three bisectors are at
+ * gamma + 30 deg + k 120 deg (zeta is ignored).
+ * PSD (GWF_PSD_ANALYTIC): S_n(f) = S0 [x^-4.14 - 5 x^-2 + 111 (1 - x^2 +
+ * x^4/2)/(1 + x^2/2)] with x = f/f0; the three arms of a T share it. */
+typedef struct gwf_site {
+  double lat, lon, gamma, zeta;
+  int32_t shape;
+  int32_t psd_kind;
+  double S0;   /* > 0, 1/Hz */
+  double f0;   /* > 0, Hz   */
+} gwf_site;
+
+#define GWF_MAX_SITES 8
+#define GWF_MAX_IFO 16
+
+typedef struct gwf_network {
+  int32_t n_site;          /* 1..GWF_MAX_SITES; at most GWF_MAX_IFO interferometers */
+  const gwf_site* site;    /* host [n_site] */
+} gwf_network;
+
+/* ----------------------------------------------------------------- grids */
+enum { GWF_GRID_LOG = 0 };
+
+/* Per-event log-spaced grid (sec. 2.2: geomspace from fmin to fmax):
+ * f_k = fmin exp(k D), D = ln(fmax/fmin)/(n-1), k = 0..n-1, trapezoid
+ * weights.  fmax == NULL means every grid ends at the event's cut frequency
+ * 1/(6^{3/2} pi G M/c^3) (twice the ISCO orbital frequency, sec. 2.2). */
+typedef struct gwf_grid {
+  int32_t kind;            /* GWF_GRID_LOG                     */
+  const double* fmin;      /* device [n], Hz                   */
+  const double* fmax;      /* device [n] or NULL               */
+  const int32_t* npts;     /* device [n], 2 <= npts <= 2^30    */
+} gwf_grid;
+
+/* -------------------------------------------------------------- calls */
+
+/* Network SNR (sec. 3.2) of every event.
+ *   snr     device [n], required
+ *   snr_ifo device [n_ifo][n] or NULL: SNR of each interferometer (a T site
+ *           contributes its three arms in order), the `return_all` output
+ *   status  device int32 [n] or NULL
+ * Same definitions and grids as gwf_fisher. */
+gwf_status gwf_snr(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
+                   uint32_t flags, double* snr, double* snr_ifo, int32_t* status,
+                   void* stream);
+
+/* Network Fisher matrix (sec. 3.2) and SNR of every event, fused.
+ *   fisher  device [P][P][n], required, P = 13 with GWF_TIDAL else 11, the
+ *           "array of matrices in the last dimension" layout of sec. 3.2;
+ *           both triangles are written
+ *   snr, snr_ifo, status as in gwf_snr (snr required, status required)
+ *   snr_th  <= 0: every event; > 0: the Fisher is computed only where the
+ *           network SNR exceeds snr_th (decided by a first SNR pass), other
+ *           events get GWF_EV_SKIPPED_SNR and a zero Fisher.
+ * Derivatives are exact partial derivatives of the model with the grid held
+ * fixed (the cut frequency is not differentiated); they include the
+ * dependence of the patterns and of the arrival-time phase on tc and, with
+ * GWF_EARTH_ROT, on Mc and eta through tau*(f). */
+gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
+                      uint32_t flags, double snr_th, double* fisher, double* snr,
+                      double* snr_ifo, int32_t* status, void* stream);
+
+/* Batched FP64 inversion (sec. 4.1) of n Fisher matrices of size P
+ * (1 <= P <= 13) in the [P][P][n] layout: each matrix is normalised by the
+ * square root of its diagonal (skipped when a diagonal entry is not > 0),
+ * Cholesky-factorised and inverted, and the normalisation is undone.
+ *   cov      device [P][P][n] or NULL     covariance
+ *   sigma    device [P][n], required      sqrt of the covariance diagonal
+ *   cond     device [n] or NULL           condition number of the normalised
+ *                                         matrix (ratio of extreme |eigenvalues|,
+ *                                         cyclic Jacobi)
+ *   inv_err  device [n] or NULL           max_ij |(Gamma Cov - 1)_ij| (sec. 4.1)
+ *   status   device int32 [n], required   bits are OR-ed into what is there
+ *                                         (pass the gwf_fisher status through, or
+ *                                         zeros)
+ *   cond_max matrices with cond > cond_max are not inverted (GWF_EV_ILL_COND);
+ *            the paper's default is 1e50.
+ * Events with GWF_EV_INVALID_PARAM or GWF_EV_SKIPPED_SNR already set are
+ * skipped.  Failed or skipped events get NaN cov/sigma/inv_err. */
+gwf_status gwf_invert(int32_t P, int64_t n, const double* fisher, double cond_max,
+                      double* cov, double* sigma, double* cond, double* inv_err,
+                      int32_t* status, void* stream);
+
+/* Number of interferometers of a network (T sites count 3); -1 if invalid. */
+int32_t gwf_network_n_ifo(const gwf_network* net);
+
+/* Human-readable text of the last error of this thread. */
+const char* gwf_last_error(void);
+
+int32_t gwf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GWF_H */

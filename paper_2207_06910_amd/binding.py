@@ -1,0 +1,200 @@
+"""Thin Python binding of libgwf (include/gwf.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of ``libgwf.so``; PyTorch only
+provides device memory and the stream.  The library must have been built
+(``python -m paper_2207_06910_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgwf.so")
+
+GWF_OK, GWF_E_INVALID_ARG, GWF_E_UNSUPPORTED, GWF_E_HIP, GWF_E_NOMEM = 0, 1, 2, 3, 4
+EV_INVALID_PARAM, EV_NOT_PD, EV_ILL_COND, EV_NONFINITE, EV_SKIPPED_SNR = 1, 2, 4, 8, 16
+EARTH_ROT, TIDAL = 1, 2
+SHAPE_L, SHAPE_T = 0, 1
+NPAR_MAX = 13
+
+
+class Events(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("ld", ctypes.c_int64), ("par", ctypes.c_void_p),
+                ("tc_s", ctypes.c_void_p)]
+
+
+class SiteDesc(ctypes.Structure):
+    _fields_ = [("lat", ctypes.c_double), ("lon", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("zeta", ctypes.c_double), ("shape", ctypes.c_int32), ("psd_kind", ctypes.c_int32),
+                ("S0", ctypes.c_double), ("f0", ctypes.c_double)]
+
+
+class Network(ctypes.Structure):
+    _fields_ = [("n_site", ctypes.c_int32), ("site", ctypes.POINTER(SiteDesc))]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("fmin", ctypes.c_void_p), ("fmax", ctypes.c_void_p),
+                ("npts", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+class GwfError(RuntimeError):
+    pass
+
+
+def load():
+    """Load libgwf.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise GwfError(f"{LIB_PATH} is missing: build it with `python -m paper_2207_06910_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, d, i32, i64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int64
+        lib.gwf_snr.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network), ctypes.POINTER(Grid),
+                                ctypes.c_uint32, vp, vp, vp, vp]
+        lib.gwf_snr.restype = i32
+        lib.gwf_fisher.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
+                                   ctypes.POINTER(Grid), ctypes.c_uint32, d, vp, vp, vp, vp, vp]
+        lib.gwf_fisher.restype = i32
+        lib.gwf_invert.argtypes = [i32, i64, vp, d, vp, vp, vp, vp, vp, vp]
+        lib.gwf_invert.restype = i32
+        lib.gwf_network_n_ifo.argtypes = [ctypes.POINTER(Network)]
+        lib.gwf_network_n_ifo.restype = i32
+        lib.gwf_last_error.restype = ctypes.c_char_p
+        lib.gwf_version.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _check(code, what):
+    if code != GWF_OK:
+        msg = load().gwf_last_error().decode()
+        raise GwfError(f"{what} failed with status {code}: {msg}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise GwfError("expected a contiguous float64 tensor on a HIP device")
+    return t
+
+
+def network(sites) -> tuple:
+    """ctypes network descriptor from a list of objects with lat, lon, gamma,
+    zeta, shape, S0, f0 attributes (radians, 1/Hz, Hz)."""
+    arr = (SiteDesc * len(sites))()
+    for i, s in enumerate(sites):
+        arr[i] = SiteDesc(s.lat, s.lon, s.gamma, s.zeta, int(s.shape), 0, s.S0, s.f0)
+    net = Network(len(sites), ctypes.cast(arr, ctypes.POINTER(SiteDesc)))
+    return net, arr   # keep arr alive with net
+
+
+def n_ifo(sites) -> int:
+    net, keep = network(sites)
+    n = load().gwf_network_n_ifo(ctypes.byref(net))
+    if n < 0:
+        _check(GWF_E_INVALID_ARG, "gwf_network_n_ifo")
+    return n
+
+
+class DeviceWorkload:
+    """Device-resident inputs of a synthetic workload (parameters [13][N],
+    grid descriptors), plus the host-side network and flags."""
+
+    def __init__(self, wl, device="cuda"):
+        import torch
+        self.wl = wl
+        self.n = wl.n
+        self.flags = wl.flags
+        self.npar = wl.npar
+        self.sites = list(wl.sites)
+        self.par = torch.as_tensor(np.ascontiguousarray(wl.par), dtype=torch.float64, device=device)
+        self.fmin = torch.as_tensor(np.ascontiguousarray(wl.fmin), dtype=torch.float64, device=device)
+        self.fmax = None if wl.fmax is None else torch.as_tensor(
+            np.ascontiguousarray(wl.fmax), dtype=torch.float64, device=device)
+        self.npts = torch.as_tensor(np.ascontiguousarray(wl.npts), dtype=torch.int32, device=device)
+        self.tc_s = None if wl.tc_s is None else torch.as_tensor(
+            np.ascontiguousarray(wl.tc_s), dtype=torch.float64, device=device)
+        self.n_ifo = n_ifo(self.sites)
+
+    def descriptors(self):
+        ev = Events(self.n, self.par.shape[1], self.par.data_ptr(),
+                    None if self.tc_s is None else self.tc_s.data_ptr())
+        net, keep = network(self.sites)
+        grid = Grid(0, self.fmin.data_ptr(), None if self.fmax is None else self.fmax.data_ptr(),
+                    self.npts.data_ptr())
+        return ev, net, grid, keep
+
+
+def snr(dw: DeviceWorkload, per_ifo=False, stream=None, out=None):
+    import torch
+    dev = dw.par.device
+    res = out if out is not None else {}
+    res.setdefault("snr", torch.empty(dw.n, dtype=torch.float64, device=dev))
+    if per_ifo:
+        res.setdefault("snr_ifo", torch.empty((dw.n_ifo, dw.n), dtype=torch.float64, device=dev))
+    res.setdefault("status", torch.empty(dw.n, dtype=torch.int32, device=dev))
+    ev, net, grid, keep = dw.descriptors()
+    _check(load().gwf_snr(ctypes.byref(ev), ctypes.byref(net), ctypes.byref(grid), dw.flags,
+                          _ptr(res["snr"]), _ptr(res.get("snr_ifo")), _ptr(res["status"]),
+                          _stream(stream)), "gwf_snr")
+    return res
+
+
+def fisher(dw: DeviceWorkload, snr_th=0.0, per_ifo_snr=False, stream=None, out=None):
+    """Fisher matrices [P][P][N], SNR [N] and status [N] of every event."""
+    import torch
+    dev = dw.par.device
+    P = 13 if dw.flags & TIDAL else 11
+    res = out if out is not None else {}
+    res.setdefault("fisher", torch.empty((P, P, dw.n), dtype=torch.float64, device=dev))
+    res.setdefault("snr", torch.empty(dw.n, dtype=torch.float64, device=dev))
+    res.setdefault("status", torch.empty(dw.n, dtype=torch.int32, device=dev))
+    if per_ifo_snr:
+        res.setdefault("snr_ifo", torch.empty((dw.n_ifo, dw.n), dtype=torch.float64, device=dev))
+    ev, net, grid, keep = dw.descriptors()
+    _check(load().gwf_fisher(ctypes.byref(ev), ctypes.byref(net), ctypes.byref(grid), dw.flags,
+                             float(snr_th), _ptr(res["fisher"]), _ptr(res["snr"]),
+                             _ptr(res.get("snr_ifo")), _ptr(res["status"]), _stream(stream)),
+           "gwf_fisher")
+    return res
+
+
+def invert(F, status=None, cond_max=1e50, want_cov=True, stream=None, out=None):
+    """Covariances of Fisher matrices F [P][P][N] (float64, on the device)."""
+    import torch
+    _dev_f64(F)
+    P, P2, n = F.shape
+    if P != P2:
+        raise GwfError("Fisher array must be [P][P][N]")
+    dev = F.device
+    res = out if out is not None else {}
+    if want_cov:
+        res.setdefault("cov", torch.empty((P, P, n), dtype=torch.float64, device=dev))
+    res.setdefault("sigma", torch.empty((P, n), dtype=torch.float64, device=dev))
+    res.setdefault("cond", torch.empty(n, dtype=torch.float64, device=dev))
+    res.setdefault("inv_err", torch.empty(n, dtype=torch.float64, device=dev))
+    st = status.clone() if status is not None else torch.zeros(n, dtype=torch.int32, device=dev)
+    res["status"] = st
+    _check(load().gwf_invert(P, n, _ptr(F), float(cond_max), _ptr(res.get("cov")),
+                             _ptr(res["sigma"]), _ptr(res["cond"]), _ptr(res["inv_err"]), _ptr(st),
+                             _stream(stream)), "gwf_invert")
+    return res

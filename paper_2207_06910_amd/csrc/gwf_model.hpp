@@ -1,0 +1,689 @@
+// gwf_model.hpp -- per-event, per-site and per-frequency mathematics of the
+// Fisher/SNR path, shared by the HIP kernels of libgwf.
+//
+// The strain at interferometer i is h_i = A(f) Q_i(f) exp(i Psi_i(f)) with
+//   A      restricted (Newtonian) amplitude, |h~| = sqrt(5/24) pi^{-2/3}
+//          (G Mc/c^3)^{5/6} f^{-7/6} c/dL                          (sec. 2.2)
+//   Q_i    F+_i (1+cos^2 iota)/2 + i Fx_i cos iota, the pattern-weighted
+//          polarisations (sec. 3.1, GWAmplitudes)
+//   Psi_i  2 pi f (tc + Delta_i) - Phic - pi/4 + Psi_PN, with Delta_i the
+//          arrival-time offset of the site (Doppler term of the Earth-motion
+//          footnote of sec. 3) and Psi_PN the TaylorF2 phase (sec. 2.2).
+// Patterns and Delta_i are evaluated at the sidereal angle of t(f) = tc -
+// tau*(f) when the Earth rotates (sec. 2.2, tau_star).
+//
+// Because every product entering SNR^2 and the Fisher matrix has the form
+// d_a h d_b h^*, the common factor exp(i Psi_i) cancels:
+//   d_a h_i = A (D_a + ...) exp(i Psi_i),  D_a = d_a Q_i + Q_i d_a ln A + i Q_i d_a Psi_i,
+// so no sine or cosine of the (large) phase is ever needed here, only its
+// derivatives.  Those of the PN phase are polynomials in v = (pi G M f/c^3)^{1/3}
+// and ln v whose per-event coefficients are built once (PhaseSeries).
+//
+// Antenna patterns are written in closed form in the hour angle H of the
+// source at the site: with E, N the local East/North unit vectors and the
+// polarisation frame (e_phi, e_theta) of the source,
+//   EX = E.e_phi = cos H,           EY = E.e_theta = -cos th sin H,
+//   NX = N.e_phi = -sin lat sin H,  NY = N.e_theta = -sin lat cos th cos H - cos lat sin th,
+// the detector tensor (sin zeta/2)[sin 2g (EE-NN) - cos 2g (EN+NE)] gives
+//   F+ = sin z [a cos 2psi + b sin 2psi],  Fx = sin z [b cos 2psi - a sin 2psi],
+//   a = sin2g P1 - cos2g P2,  b = sin2g P3 - cos2g P4,
+//   P1 = (EX^2 - NX^2 - EY^2 + NY^2)/2, P2 = EX NX - EY NY,
+//   P3 = EX EY - NX NY,  P4 = EX NY + NX EY,
+// a derivation of this library (equivalent to the tensor contraction).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace gwf {
+
+// ----------------------------------------------------------- constants
+// IAU 2015 nominal values (the paper fixes none numerically).
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 2.0 * kPi;
+constexpr double kC = 299792458.0;
+constexpr double kGMsun = 1.3271244e20;
+constexpr double kTsun = kGMsun / (kC * kC * kC);           // s
+constexpr double kAU = 149597870700.0;
+constexpr double kPc = kAU * 648000.0 / kPi;                 // m
+constexpr double kGpcS = 1e9 * kPc / kC;                     // s
+constexpr double kSiderealDay = 86164.0905;                  // s
+constexpr double kOmegaE = kTwoPi / kSiderealDay;            // rad/s
+constexpr double kREarthS = 6.371e6 / kC;                    // s
+constexpr double kEulerGamma = 0.5772156649015329;
+constexpr double kLn2 = 0.69314718055994530942;
+
+constexpr int kMaxSites = 8;
+constexpr int kMaxIfo = 16;
+constexpr uint32_t kFlagRot = 1;
+constexpr uint32_t kFlagTidal = 2;
+
+enum : int32_t { kEvInvalid = 1, kEvNotPD = 2, kEvIllCond = 4, kEvNonFinite = 8, kEvSkipped = 16 };
+
+// ------------------------------------------------------------ series
+// Per-event coefficients of a PN-phase derivative:
+//   s(v) = v^-5 (c0 + c1 v + ... + c7 v^7) + ln v (l5 + l6 v) + v^5 (t10 + t12 v^2)
+struct PhaseSeries {
+  double c[8];
+  double l5, l6, t10, t12;
+};
+// Per-event coefficients of a tau*-type series:
+//   s(v) = v^-8 (c0 + c1 v + ... + c7 v^7) + l6 ln v v^-2
+struct TauSeries {
+  double c[8];
+  double l6;
+};
+
+// Index of the phase-derivative series in EventC::ps.
+enum { kPsMc = 0, kPsEta, kPsChi1, kPsChi2, kPsL1, kPsL2 };
+// Index of the tau-type series in EventC::ts: the rotation angle offset
+// -Omega tau*, and the derivatives of the sidereal angle w.r.t. Mc and eta.
+enum { kTsTheta = 0, kTsMc, kTsEta };
+
+struct EventC {
+  // grid: v_k = exp(lnv0 + k dlnv), f_k = v_k^3 / (pi M), trapezoid weights
+  double lnv0, dlnv, inv_piM, piM, wint, wfirst, wlast;
+  int32_t n;
+  int32_t status;
+  // amplitude: A^2 = KA v^-7 (factor 4 of the inner product included)
+  double KA4;
+  double dlnA_dMc, inv_dL;
+  // sky/orientation
+  double thc;                  // sidereal angle at coalescence, 2 pi tcoal
+  double cplus, ccross, dcplus, dcross;   // (1+cos^2 i)/2, cos i and d/d iota
+  PhaseSeries ps[6];
+  TauSeries ts[3];
+};
+
+struct SiteC {
+  double cdl, sdl;             // cos, sin of (site longitude - phi)
+  double ct, slct, clst, sl, st;   // cos th, sin lat cos th, cos lat sin th, sin lat, sin th
+  double cl;                   // cos lat
+  double k1, k0, k1t, k0t;     // Delta = k1 cos H + k0;  dDelta/dth = k1t cos H + k0t
+  double lnx_off, ix_fac, x_fac;  // ln(f/f0) = 3 ln v + lnx_off; f0/f = ix_fac v^-3; f/f0 = x_fac v^3
+  double S0inv;                // 1/S0
+  double alpha[2][4], beta[2][4], weff[2];  // effective interferometers (pattern maps)
+  double arm_alpha[3][4], arm_beta[3][4];   // individual arms (SNR per interferometer)
+  int32_t n_eff, n_arm;
+};
+
+// Site description as passed at the boundary (radians).
+struct SiteDesc {
+  double lat, lon, gamma, zeta, S0, f0;
+  int32_t shape, pad;
+};
+
+struct NetDesc {
+  SiteDesc site[kMaxSites];
+  int32_t n_site, n_ifo;
+};
+
+// ------------------------------------------------ per-event coefficients
+// Coefficients a_k (k = 0..7), b_5, b_6 (ln v parts) and tidal a_10, a_12 of
+// the TaylorF2 phase Psi_PN = 3/(128 eta) v^-5 sum_k (a_k + b_k ln v) v^k,
+// together with their partial derivatives with respect to eta (at fixed
+// component spins and deformabilities), chi_s, chi_a, Lambda1, Lambda2.
+// Point-particle terms to 3.5PN, aligned-spin spin-orbit terms to 3.5PN and
+// 2PN spin-spin terms, tidal terms at 5PN/6PN through the combinations of
+// eq. (LamTdelLam_def) (refs. of sec. 2.2).
+struct PNCoef {
+  double a[8], ae[8], as[8], aa[8];   // value, d/deta, d/dchi_s, d/dchi_a
+  double b5, b5e, b5s, b5a, b6;
+  double a10, a10e, a10_1, a10_2, a12, a12e, a12_1, a12_2;
+};
+
+__host__ __device__ inline void pn_coefficients(double eta, double chi1, double chi2, double L1,
+                                                double L2, bool tidal, PNCoef& p) {
+  const double pi = kPi, pi2 = kPi * kPi;
+  const double e2 = eta * eta, e3 = e2 * eta;
+  const double dl = sqrt(1.0 - 4.0 * eta);
+  const double ddl = -2.0 / dl;     // d delta / d eta
+  const double xs = 0.5 * (chi1 + chi2), xa = 0.5 * (chi1 - chi2);
+  for (int k = 0; k < 8; ++k) { p.a[k] = 0.0; p.ae[k] = 0.0; p.as[k] = 0.0; p.aa[k] = 0.0; }
+  p.a[0] = 1.0;
+  // 1PN
+  p.a[2] = 3715.0 / 756.0 + (55.0 / 9.0) * eta;
+  p.ae[2] = 55.0 / 9.0;
+  // 1.5PN: tail and spin-orbit
+  p.a[3] = -16.0 * pi + (113.0 / 3.0) * dl * xa + (113.0 / 3.0 - (76.0 / 3.0) * eta) * xs;
+  p.ae[3] = (113.0 / 3.0) * ddl * xa - (76.0 / 3.0) * xs;
+  p.as[3] = 113.0 / 3.0 - (76.0 / 3.0) * eta;
+  p.aa[3] = (113.0 / 3.0) * dl;
+  // 2PN: point particle and spin-spin
+  p.a[4] = 15293365.0 / 508032.0 + (27145.0 / 504.0) * eta + (3085.0 / 72.0) * e2 +
+           (-405.0 / 8.0 + 200.0 * eta) * xa * xa - (405.0 / 4.0) * dl * xa * xs +
+           (-405.0 / 8.0 + 2.5 * eta) * xs * xs;
+  p.ae[4] = 27145.0 / 504.0 + (3085.0 / 36.0) * eta + 200.0 * xa * xa -
+            (405.0 / 4.0) * ddl * xa * xs + 2.5 * xs * xs;
+  p.as[4] = -(405.0 / 4.0) * dl * xa + 2.0 * (-405.0 / 8.0 + 2.5 * eta) * xs;
+  p.aa[4] = 2.0 * (-405.0 / 8.0 + 200.0 * eta) * xa - (405.0 / 4.0) * dl * xs;
+  // 2.5PN: X5 (1 + 3 ln v)
+  const double q5 = 732985.0 / 2268.0 + (140.0 / 9.0) * eta;
+  const double r5 = -732985.0 / 2268.0 + (24260.0 / 81.0) * eta + (340.0 / 9.0) * e2;
+  const double X5 = pi * (38645.0 / 756.0 - (65.0 / 9.0) * eta) - q5 * dl * xa + r5 * xs;
+  const double X5e = -(65.0 / 9.0) * pi - (140.0 / 9.0) * dl * xa - q5 * ddl * xa +
+                     (24260.0 / 81.0 + (680.0 / 9.0) * eta) * xs;
+  const double X5s = r5;
+  const double X5a = -q5 * dl;
+  p.a[5] = X5; p.ae[5] = X5e; p.as[5] = X5s; p.aa[5] = X5a;
+  p.b5 = 3.0 * X5; p.b5e = 3.0 * X5e; p.b5s = 3.0 * X5s; p.b5a = 3.0 * X5a;
+  // 3PN: Y6 - (6848/21) ln(4 v)
+  const double Y6 = 11583231236531.0 / 4694215680.0 - (640.0 / 3.0) * pi2 -
+                    (6848.0 / 21.0) * kEulerGamma +
+                    (-15737765635.0 / 3048192.0 + (2255.0 / 12.0) * pi2) * eta +
+                    (76055.0 / 1728.0) * e2 - (127825.0 / 1296.0) * e3 +
+                    pi * ((2270.0 / 3.0) * dl * xa + (2270.0 / 3.0 - 520.0 * eta) * xs);
+  const double Y6e = (-15737765635.0 / 3048192.0 + (2255.0 / 12.0) * pi2) +
+                     (76055.0 / 864.0) * eta - (127825.0 / 432.0) * e2 +
+                     pi * ((2270.0 / 3.0) * ddl * xa - 520.0 * xs);
+  p.a[6] = Y6 - (6848.0 / 21.0) * (2.0 * kLn2);
+  p.ae[6] = Y6e;
+  p.as[6] = pi * (2270.0 / 3.0 - 520.0 * eta);
+  p.aa[6] = pi * (2270.0 / 3.0) * dl;
+  p.b6 = -6848.0 / 21.0;
+  // 3.5PN
+  const double u7 = -25150083775.0 / 3048192.0 + (26804935.0 / 6048.0) * eta - (1985.0 / 48.0) * e2;
+  const double w7 = -25150083775.0 / 3048192.0 + (10566655595.0 / 762048.0) * eta -
+                    (1042165.0 / 3024.0) * e2 + (5345.0 / 36.0) * e3;
+  p.a[7] = pi * (77096675.0 / 254016.0 + (378515.0 / 1512.0) * eta - (74045.0 / 756.0) * e2) +
+           u7 * dl * xa + w7 * xs;
+  p.ae[7] = pi * (378515.0 / 1512.0 - (74045.0 / 378.0) * eta) +
+            (26804935.0 / 6048.0 - (1985.0 / 24.0) * eta) * dl * xa + u7 * ddl * xa +
+            (10566655595.0 / 762048.0 - (1042165.0 / 1512.0) * eta + (5345.0 / 12.0) * e2) * xs;
+  p.as[7] = w7;
+  p.aa[7] = u7 * dl;
+  // tides: a10 = -(39/2) Lt, a12 = -(3115/64) Lt + (6595/364) delta dLt
+  p.a10 = p.a10e = p.a10_1 = p.a10_2 = 0.0;
+  p.a12 = p.a12e = p.a12_1 = p.a12_2 = 0.0;
+  if (tidal) {
+    const double s = L1 + L2, d = L1 - L2;
+    const double q1 = 1.0 + 7.0 * eta - 31.0 * e2, q1e = 7.0 - 62.0 * eta;
+    const double q2 = 1.0 + 9.0 * eta - 11.0 * e2, q2e = 9.0 - 22.0 * eta;
+    const double Lt = (8.0 / 13.0) * (q1 * s + dl * q2 * d);
+    const double Lte = (8.0 / 13.0) * (q1e * s + (ddl * q2 + dl * q2e) * d);
+    const double Lt1 = (8.0 / 13.0) * (q1 + dl * q2), Lt2 = (8.0 / 13.0) * (q1 - dl * q2);
+    const double r1 = 1.0 - (13272.0 / 1319.0) * eta + (8944.0 / 1319.0) * e2;
+    const double r1e = -13272.0 / 1319.0 + (17888.0 / 1319.0) * eta;
+    const double r2 = 1.0 - (15910.0 / 1319.0) * eta + (32850.0 / 1319.0) * e2 + (3380.0 / 1319.0) * e3;
+    const double r2e = -15910.0 / 1319.0 + (65700.0 / 1319.0) * eta + (10140.0 / 1319.0) * e2;
+    const double dLt = 0.5 * (dl * r1 * s + r2 * d);
+    const double dLte = 0.5 * ((ddl * r1 + dl * r1e) * s + r2e * d);
+    const double dLt1 = 0.5 * (dl * r1 + r2), dLt2 = 0.5 * (dl * r1 - r2);
+    p.a10 = -19.5 * Lt; p.a10e = -19.5 * Lte; p.a10_1 = -19.5 * Lt1; p.a10_2 = -19.5 * Lt2;
+    const double k12 = 6595.0 / 364.0;
+    p.a12 = -(3115.0 / 64.0) * Lt + k12 * dl * dLt;
+    p.a12e = -(3115.0 / 64.0) * Lte + k12 * (ddl * dLt + dl * dLte);
+    p.a12_1 = -(3115.0 / 64.0) * Lt1 + k12 * dl * dLt1;
+    p.a12_2 = -(3115.0 / 64.0) * Lt2 + k12 * dl * dLt2;
+  }
+}
+
+// tau*(f) = 5 M/(256 eta) v^-8 sum_k (t_k + l_k ln v) v^k at 3.5PN, non-spinning
+// (the paper cites Buonanno et al. 2009, eq. 3.8b); t_k and d t_k/d eta.
+__host__ __device__ inline void tau_coefficients(double eta, double t[8], double te[8], double& l6) {
+  const double pi = kPi, pi2 = kPi * kPi, e2 = eta * eta, e3 = e2 * eta;
+  for (int k = 0; k < 8; ++k) { t[k] = 0.0; te[k] = 0.0; }
+  t[0] = 1.0;
+  t[2] = 743.0 / 252.0 + (11.0 / 3.0) * eta;               te[2] = 11.0 / 3.0;
+  t[3] = -32.0 * pi / 5.0;
+  t[4] = 3058673.0 / 508032.0 + (5429.0 / 504.0) * eta + (617.0 / 72.0) * e2;
+  te[4] = 5429.0 / 504.0 + (617.0 / 36.0) * eta;
+  t[5] = pi * (-7729.0 / 252.0 + (13.0 / 3.0) * eta);     te[5] = pi * 13.0 / 3.0;
+  // (3424/105) ln(16 v^2) = (3424/105) (4 ln 2 + 2 ln v)
+  t[6] = -10052469856691.0 / 23471078400.0 + (128.0 / 3.0) * pi2 + (6848.0 / 105.0) * kEulerGamma +
+         (3147553127.0 / 3048192.0 - (451.0 / 12.0) * pi2) * eta - (15211.0 / 1728.0) * e2 +
+         (25565.0 / 1296.0) * e3 + (3424.0 / 105.0) * 4.0 * kLn2;
+  te[6] = (3147553127.0 / 3048192.0 - (451.0 / 12.0) * pi2) - (15211.0 / 864.0) * eta +
+          (25565.0 / 432.0) * e2;
+  t[7] = pi * (-15419335.0 / 127008.0 - (75703.0 / 756.0) * eta + (14809.0 / 378.0) * e2);
+  te[7] = pi * (-75703.0 / 756.0 + (14809.0 / 189.0) * eta);
+  l6 = 2.0 * 3424.0 / 105.0;
+}
+
+// Cut frequency: twice the ISCO orbital frequency, 1/(6^{3/2} pi G M/c^3)
+// (sec. 2.2 footnote).
+__host__ __device__ inline double cut_frequency_of(double M_s) {
+  return 1.0 / (6.0 * sqrt(6.0) * kPi * M_s);
+}
+
+// x is neither infinite nor NaN (x - x is 0 exactly for finite x).
+__host__ __device__ inline bool finite(double x) { return (x - x) == 0.0; }
+
+// Parameter validity; returns the status bits of an event.
+__host__ __device__ inline int32_t check_event(const double* p, bool tidal, double fmin, double fmax,
+                                               int32_t n) {
+  int32_t st = 0;
+  const int np = tidal ? 13 : 11;
+  for (int i = 0; i < np; ++i)
+    if (!finite(p[i])) st |= kEvNonFinite;
+  if (!finite(fmin) || !finite(fmax)) st |= kEvNonFinite;
+  if (st) return st;
+  if (!(p[0] > 0.0) || !(p[1] > 0.0) || !(p[1] <= 0.25) || !(p[2] > 0.0)) st |= kEvInvalid;
+  if (fabs(p[9]) > 1.0 || fabs(p[10]) > 1.0) st |= kEvInvalid;
+  if (tidal && (p[11] < 0.0 || p[12] < 0.0)) st |= kEvInvalid;
+  if (n < 2 || !(fmin > 0.0) || !(fmax > fmin)) st |= kEvInvalid;
+  return st;
+}
+
+// Build the per-event constants.  p[13] are the parameters in boundary
+// order; fmax <= 0 selects the cut frequency.
+__host__ __device__ inline void event_setup(const double* p, double fmin, double fmax, int32_t n,
+                                            uint32_t flags, EventC& ec) {
+  const bool tidal = (flags & kFlagTidal) != 0;
+  const bool rot = (flags & kFlagRot) != 0;
+  const double Mc = p[0], eta = p[1], dL = p[2];
+  const double Ms = Mc * pow(eta, -0.6) * kTsun;
+  if (!(fmax > 0.0)) fmax = cut_frequency_of(Ms);
+  ec.n = n;
+  ec.status = check_event(p, tidal, fmin, fmax, n);
+  if (ec.status) return;
+  // grid
+  const double D = log(fmax / fmin) / (double)(n - 1);
+  ec.piM = kPi * Ms;
+  ec.inv_piM = 1.0 / ec.piM;
+  ec.lnv0 = (log(ec.piM) + log(fmin)) / 3.0;
+  ec.dlnv = D / 3.0;
+  ec.wint = sinh(D);                  // interior weight / f_k
+  ec.wfirst = 0.5 * expm1(D);         // (f_1 - f_0)/2 / f_0
+  ec.wlast = -0.5 * expm1(-D);        // (f_{n-1} - f_{n-2})/2 / f_{n-1}
+  // amplitude: 4 A^2 = 4 (5/24) pi^{-4/3} (G Mc/c^3)^{5/3} f^{-7/3} (c/dL)^2, f^{-7/3} = (pi M)^{7/3} v^{-7}
+  const double Mcs = Mc * kTsun, dLs = dL * kGpcS;
+  ec.KA4 = 4.0 * (5.0 / 24.0) * pow(kPi, -4.0 / 3.0) * pow(Mcs, 5.0 / 3.0) * pow(ec.piM, 7.0 / 3.0) /
+           (dLs * dLs);
+  ec.dlnA_dMc = 5.0 / (6.0 * Mc);
+  ec.inv_dL = 1.0 / dL;
+  // 2 pi tcoal reduced to [0, 2 pi)
+  const double tfrac = p[7] - floor(p[7]);
+  ec.thc = kTwoPi * tfrac;
+  const double ci = cos(p[5]), si = sin(p[5]);
+  ec.cplus = 0.5 * (1.0 + ci * ci);
+  ec.ccross = ci;
+  ec.dcplus = -ci * si;
+  ec.dcross = -si;
+
+  // ---- phase-derivative series
+  PNCoef c;
+  pn_coefficients(eta, p[9], p[10], tidal ? p[11] : 0.0, tidal ? p[12] : 0.0, tidal, c);
+  const double A = 3.0 / (128.0 * eta);
+  double b[8] = {0, 0, 0, 0, 0, c.b5, c.b6, 0};
+  double be[8] = {0, 0, 0, 0, 0, c.b5e, 0.0, 0};
+  // d Psi/d Mc = (1/(3 Mc)) v dPsi/dv
+  {
+    PhaseSeries& s = ec.ps[kPsMc];
+    const double K = A / (3.0 * Mc);
+    for (int k = 0; k < 8; ++k) s.c[k] = K * ((k - 5) * c.a[k] + b[k]);
+    s.l5 = 0.0;
+    s.l6 = K * c.b6;
+    s.t10 = K * 5.0 * c.a10;
+    s.t12 = K * 7.0 * c.a12;
+  }
+  // d Psi/d eta = explicit eta dependence - (1/(5 eta)) v dPsi/dv (v ~ eta^{-1/5})
+  {
+    PhaseSeries& s = ec.ps[kPsEta];
+    const double K = A / (5.0 * eta);
+    for (int k = 0; k < 8; ++k) s.c[k] = A * (c.ae[k] - c.a[k] / eta) - K * ((k - 5) * c.a[k] + b[k]);
+    s.c[0] = 0.0;   // the leading term does not depend on eta at fixed Mc
+    s.l5 = A * (be[5] - b[5] / eta);
+    s.l6 = A * (-c.b6 / eta) - K * c.b6;
+    s.t10 = A * (c.a10e - c.a10 / eta) - K * 5.0 * c.a10;
+    s.t12 = A * (c.a12e - c.a12 / eta) - K * 7.0 * c.a12;
+  }
+  // spins: d/dchi1 = (d/dchi_s + d/dchi_a)/2, d/dchi2 = (d/dchi_s - d/dchi_a)/2
+  for (int j = 0; j < 2; ++j) {
+    PhaseSeries& s = ec.ps[kPsChi1 + j];
+    const double sg = j == 0 ? 1.0 : -1.0;
+    for (int k = 0; k < 8; ++k) s.c[k] = 0.5 * A * (c.as[k] + sg * c.aa[k]);
+    s.l5 = 0.5 * A * (c.b5s + sg * c.b5a);
+    s.l6 = 0.0;
+    s.t10 = 0.0;
+    s.t12 = 0.0;
+  }
+  // tides
+  for (int j = 0; j < 2; ++j) {
+    PhaseSeries& s = ec.ps[kPsL1 + j];
+    for (int k = 0; k < 8; ++k) s.c[k] = 0.0;
+    s.l5 = s.l6 = 0.0;
+    s.t10 = A * (j == 0 ? c.a10_1 : c.a10_2);
+    s.t12 = A * (j == 0 ? c.a12_1 : c.a12_2);
+  }
+
+  // ---- rotation: sidereal-angle offset -Omega tau* and its Mc, eta derivatives
+  double t[8], te[8], l6;
+  tau_coefficients(eta, t, te, l6);
+  const double Kt = 5.0 * Ms / (256.0 * eta);
+  const double om = rot ? kOmegaE : 0.0;
+  double lk[8] = {0, 0, 0, 0, 0, 0, l6, 0};
+  for (int k = 0; k < 8; ++k) {
+    ec.ts[kTsTheta].c[k] = -om * Kt * t[k];
+    // d tau*/d Mc = (Kt/Mc) sum [(t_k + l_k L)(1 + (k-8)/3) + l_k/3] v^(k-8)
+    ec.ts[kTsMc].c[k] = -om * (Kt / Mc) * ((1.0 + (k - 8) / 3.0) * t[k] + lk[k] / 3.0);
+    // d tau*/d eta = Kt sum [t_k' - (k t_k + l_k)/(5 eta)] v^(k-8) + log part
+    ec.ts[kTsEta].c[k] = -om * Kt * (te[k] - (k * t[k] + lk[k]) / (5.0 * eta));
+  }
+  ec.ts[kTsEta].c[0] = 0.0;   // leading tau* does not depend on eta at fixed Mc
+  ec.ts[kTsTheta].l6 = -om * Kt * l6;
+  ec.ts[kTsMc].l6 = -om * (Kt / Mc) * (1.0 + (6 - 8) / 3.0) * l6;
+  ec.ts[kTsEta].l6 = -om * Kt * (-6.0 * l6 / (5.0 * eta));
+}
+
+// Pattern maps of one interferometer: F+ = alpha.P, Fx = beta.P.
+__host__ __device__ inline void pattern_map(double gamma, double zeta, double c2p, double s2p,
+                                            double al[4], double be[4]) {
+  const double sz = sin(zeta), s2g = sin(2.0 * gamma), c2g = cos(2.0 * gamma);
+  al[0] = sz * s2g * c2p; al[1] = -sz * c2g * c2p; al[2] = sz * s2g * s2p; al[3] = -sz * c2g * s2p;
+  be[0] = -sz * s2g * s2p; be[1] = sz * c2g * s2p; be[2] = sz * s2g * c2p; be[3] = -sz * c2g * c2p;
+}
+
+// Per (event, site) constants.  A triangle (shape 1) is three 60-degree
+// interferometers with bisectors at gamma + 30 deg + k 120 deg; since the
+// third arm's response is minus the sum of the other two (closed loop,
+// sec. 3.3), the Gram sum over its arms a a^T + b b^T + (a+b)(a+b)^T equals
+// (3/2)(a+b)(a+b)^T + (1/2)(a-b)(a-b)^T: two effective interferometers.
+__host__ __device__ inline void site_setup(const double* p, const SiteDesc& sd, const EventC& ec,
+                                           SiteC& sc) {
+  const double th = p[3], ph = p[4], psi = p[6];
+  const double c2p = cos(2.0 * psi), s2p = sin(2.0 * psi);
+  sc.cdl = cos(sd.lon - ph);
+  sc.sdl = sin(sd.lon - ph);
+  const double ct = cos(th), st = sin(th), sl = sin(sd.lat), cl = cos(sd.lat);
+  sc.ct = ct; sc.st = st; sc.sl = sl; sc.cl = cl;
+  sc.slct = sl * ct;
+  sc.clst = cl * st;
+  // arrival-time offset -(n . r)/c with n.r/R = sin th cos lat cos H + cos th sin lat
+  sc.k1 = -kREarthS * cl * st;
+  sc.k0 = -kREarthS * sl * ct;
+  sc.k1t = -kREarthS * cl * ct;
+  sc.k0t = kREarthS * sl * st;
+  sc.lnx_off = -log(ec.piM) - log(sd.f0);
+  sc.ix_fac = sd.f0 * ec.piM;
+  sc.x_fac = 1.0 / sc.ix_fac;
+  sc.S0inv = 1.0 / sd.S0;
+  if (sd.shape == 1) {
+    double al[3][4], be[3][4];
+    for (int k = 0; k < 3; ++k) {
+      pattern_map(sd.gamma + kPi / 6.0 + kTwoPi * k / 3.0, kPi / 3.0, c2p, s2p, al[k], be[k]);
+      for (int j = 0; j < 4; ++j) { sc.arm_alpha[k][j] = al[k][j]; sc.arm_beta[k][j] = be[k][j]; }
+    }
+    for (int j = 0; j < 4; ++j) {
+      sc.alpha[0][j] = al[0][j] + al[1][j]; sc.beta[0][j] = be[0][j] + be[1][j];
+      sc.alpha[1][j] = al[0][j] - al[1][j]; sc.beta[1][j] = be[0][j] - be[1][j];
+    }
+    sc.weff[0] = 1.5; sc.weff[1] = 0.5;
+    sc.n_eff = 2; sc.n_arm = 3;
+  } else {
+    pattern_map(sd.gamma, sd.zeta, c2p, s2p, sc.alpha[0], sc.beta[0]);
+    for (int j = 0; j < 4; ++j) {
+      sc.arm_alpha[0][j] = sc.alpha[0][j]; sc.arm_beta[0][j] = sc.beta[0][j];
+      sc.alpha[1][j] = 0.0; sc.beta[1][j] = 0.0;
+    }
+    sc.weff[0] = 1.0; sc.weff[1] = 0.0;
+    sc.n_eff = 1; sc.n_arm = 1;
+  }
+}
+
+// ---------------------------------------------------------- sin and cos
+// sin and cos of a moderate angle (|x| < 1e5): Cody-Waite reduction by pi/2
+// with a three-part constant, then the Taylor series of sin (to x^17) and
+// cos (to x^18) on [-pi/4, pi/4], whose truncation errors (< 1e-19) are far
+// below one ulp.  Used for the sidereal angle, which stays within tens of
+// radians, instead of a general routine built for arbitrary arguments.
+__host__ __device__ inline void sincos_moderate(double x, double* s, double* c) {
+  // pi/2 = C1 + C2 + C3 (+1e-37): C1 and C2 are pi/2 and its remainder
+  // rounded to 33 significant bits, so k*C1 and k*C2 are exact for |k| < 2^20
+  constexpr double kInvPio2 = 0.63661977236758134308;
+  constexpr double C1 = 1.5707963267341256e+00;
+  constexpr double C2 = 6.077100506303966e-11;
+  constexpr double C3 = 2.0222662487959506e-21;
+  const double kf = rint(x * kInvPio2);
+  double r = fma(-kf, C1, x);
+  r = fma(-kf, C2, r);
+  r = fma(-kf, C3, r);
+  const double r2 = r * r;
+  // sin r = r (1 - r^2/3! + r^4/5! - ...), cos r = 1 - r^2/2! + r^4/4! - ...
+  double ps = -1.0 / 355687428096000.0;          // -1/17!
+  ps = fma(ps, r2, 1.0 / 1307674368000.0);       //  1/15!
+  ps = fma(ps, r2, -1.0 / 6227020800.0);         // -1/13!
+  ps = fma(ps, r2, 1.0 / 39916800.0);            //  1/11!
+  ps = fma(ps, r2, -1.0 / 362880.0);             // -1/9!
+  ps = fma(ps, r2, 1.0 / 5040.0);                //  1/7!
+  ps = fma(ps, r2, -1.0 / 120.0);                // -1/5!
+  ps = fma(ps, r2, 1.0 / 6.0);                   //  1/3!
+  const double sr = fma(-r * r2, ps, r);
+  double pc = 1.0 / 6402373705728000.0;          //  1/18!
+  pc = fma(pc, r2, -1.0 / 20922789888000.0);     // -1/16!
+  pc = fma(pc, r2, 1.0 / 87178291200.0);         //  1/14!
+  pc = fma(pc, r2, -1.0 / 479001600.0);          // -1/12!
+  pc = fma(pc, r2, 1.0 / 3628800.0);             //  1/10!
+  pc = fma(pc, r2, -1.0 / 40320.0);              // -1/8!
+  pc = fma(pc, r2, 1.0 / 720.0);                 //  1/6!
+  pc = fma(pc, r2, -1.0 / 24.0);                 // -1/4!
+  pc = fma(pc, r2, 0.5);                         //  1/2!
+  const double cr = fma(-r2, pc, 1.0);
+  const int q = (int)kf & 3;
+  const double ss = (q & 1) ? cr : sr;
+  const double cc = (q & 1) ? sr : cr;
+  *s = (q & 2) ? -ss : ss;
+  *c = ((q + 1) & 2) ? -cc : cc;
+}
+
+// ------------------------------------------------------ per-point pieces
+__host__ __device__ inline double eval_phase(const PhaseSeries& s, double v, double iv5, double v5,
+                                             double v2, double L) {
+  double h = s.c[7];
+  for (int k = 6; k >= 0; --k) h = fma(h, v, s.c[k]);
+  return fma(h, iv5, fma(L, fma(s.l6, v, s.l5), v5 * fma(s.t12, v2, s.t10)));
+}
+__host__ __device__ inline double eval_tau(const TauSeries& s, double v, double iv8, double iv2,
+                                           double L) {
+  double h = s.c[7];
+  for (int k = 6; k >= 0; --k) h = fma(h, v, s.c[k]);
+  return fma(h, iv8, s.l6 * L * iv2);
+}
+
+// Frequency-point quantities shared by all sites.
+struct Point {
+  double v, iv, L, f, tf, w4A2;   // tf = 2 pi f; w4A2 = 4 w A^2 (PSD not yet applied)
+  double cth, sth;                // cos, sin of the sidereal angle at t(f)
+  double gMc, gEta;               // d(sidereal angle)/dMc, /deta
+  double pMc, pEta;               // dPsi_PN/dMc, /deta
+};
+
+__host__ __device__ inline void point_setup(const EventC& ec, int32_t k, bool need_derivs, bool rot,
+                                            Point& q) {
+  const double L = fma((double)k, ec.dlnv, ec.lnv0);
+  const double v = exp(L);
+  const double iv = 1.0 / v;
+  const double iv2 = iv * iv, iv4 = iv2 * iv2, iv5 = iv4 * iv, iv7 = iv5 * iv2, iv8 = iv4 * iv4;
+  const double f = v * v * v * ec.inv_piM;
+  double w = ec.wint;
+  if (k == 0) w = ec.wfirst;
+  if (k == ec.n - 1) w = ec.wlast;
+  q.v = v; q.iv = iv; q.L = L; q.f = f;
+  q.tf = kTwoPi * f;
+  q.w4A2 = w * f * ec.KA4 * iv7;
+  const double th = rot ? ec.thc + eval_tau(ec.ts[kTsTheta], v, iv8, iv2, L) : ec.thc;
+  sincos_moderate(th, &q.sth, &q.cth);
+  if (need_derivs) {
+    const double v2 = v * v, v5 = v2 * v2 * v;
+    q.gMc = rot ? eval_tau(ec.ts[kTsMc], v, iv8, iv2, L) : 0.0;
+    q.gEta = rot ? eval_tau(ec.ts[kTsEta], v, iv8, iv2, L) : 0.0;
+    q.pMc = eval_phase(ec.ps[kPsMc], v, iv5, v5, v2, L);
+    q.pEta = eval_phase(ec.ps[kPsEta], v, iv5, v5, v2, L);
+  }
+}
+
+// Site-level quantities at one frequency: the P vectors and their hour-angle
+// and theta derivatives, the delay derivatives and the noise weight.
+struct SitePoint {
+  double P[4], PH[4], Pt[4];
+  double dH, dT;      // dDelta/dH, dDelta/dtheta
+  double om;          // 4 w A^2 / S_n(f)
+};
+
+__host__ __device__ inline void psd_weight(const SiteC& sc, const Point& q, double& om) {
+  // S_n = S0 [x^-4.14 - 5 x^-2 + 111 (1 - x^2 + x^4/2)/(1 + x^2/2)], x = f/f0
+  const double lnx = fma(3.0, q.L, sc.lnx_off);
+  const double xp = exp(-4.14 * lnx);
+  const double ix = sc.ix_fac * q.iv * q.iv * q.iv;   // f0/f
+  const double x = sc.x_fac * q.v * q.v * q.v;        // f/f0
+  const double ix2 = ix * ix;
+  const double x2 = x * x;
+  const double num = fma(0.5 * x2, x2, 1.0 - x2);
+  const double den = fma(0.5, x2, 1.0);
+  // shape = [(x^-4.14 - 5 x^-2) den + 111 num] / den
+  const double top = fma(fma(-5.0, ix2, xp), den, 111.0 * num);
+  om = q.w4A2 * sc.S0inv * den / top;
+}
+
+__host__ __device__ inline void site_point(const SiteC& sc, const Point& q, bool need_derivs,
+                                           SitePoint& sp) {
+  const double cH = q.cth * sc.cdl - q.sth * sc.sdl;
+  const double sH = q.sth * sc.cdl + q.cth * sc.sdl;
+  const double EX = cH, EY = -sc.ct * sH, NX = -sc.sl * sH, NY = -(sc.slct * cH + sc.clst);
+  sp.P[0] = 0.5 * (EX * EX - NX * NX - EY * EY + NY * NY);
+  sp.P[1] = EX * NX - EY * NY;
+  sp.P[2] = EX * EY - NX * NY;
+  sp.P[3] = EX * NY + NX * EY;
+  psd_weight(sc, q, sp.om);
+  if (!need_derivs) return;
+  const double EXh = -sH, EYh = -sc.ct * cH, NXh = -sc.sl * cH, NYh = sc.slct * sH;
+  sp.PH[0] = EX * EXh - NX * NXh - EY * EYh + NY * NYh;
+  sp.PH[1] = EXh * NX + EX * NXh - EYh * NY - EY * NYh;
+  sp.PH[2] = EXh * EY + EX * EYh - NXh * NY - NX * NYh;
+  sp.PH[3] = EXh * NY + EX * NYh + NXh * EY + NX * EYh;
+  const double EYt = sc.st * sH, NYt = sc.sl * sc.st * cH - sc.cl * sc.ct;
+  sp.Pt[0] = -EY * EYt + NY * NYt;
+  sp.Pt[1] = -(EYt * NY + EY * NYt);
+  sp.Pt[2] = EX * EYt - NX * NYt;
+  sp.Pt[3] = EX * NYt + NX * EYt;
+  sp.dH = -sc.k1 * sH;
+  sp.dT = fma(sc.k1t, cH, sc.k0t);
+}
+
+__host__ __device__ inline double dot4(const double a[4], const double b[4]) {
+  return fma(a[0], b[0], fma(a[1], b[1], fma(a[2], b[2], a[3] * b[3])));
+}
+
+// ------------------------------------------------ one frequency point
+// Adds the contribution of grid point k of an event to
+//   G[36]  the 8x8 upper-triangle block of (Mc, eta, dL, theta, phi, iota,
+//          psi, tc), row-major;
+//   xy     the phase-only blocks: xy[(b*NPI + i)*xs] += U_b c_i (b < 8) and
+//          then the upper triangle of W c_i c_j, with NPI = P - 8 and
+//          c = (-1, dPsi/dchi1, dPsi/dchi2[, dPsi/dLambda1, dPsi/dLambda2]).
+// The phase-only derivative vectors are i Q c(f) with the same real c(f) at
+// every interferometer, so their blocks need only the per-frequency network
+// sums W = sum_i w_i |Q_i|^2 and U_b = sum_i w_i Re(i Q_i D_b,i^*).
+template <bool TIDAL, bool ROT>
+__host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* sc, int n_site,
+                                                 int32_t k, double* G, double* xy, int xs) {
+  constexpr int NPI = TIDAL ? 5 : 3;
+  const double cplus = ec.cplus, ccross = ec.ccross, dcp = ec.dcplus, dcx = ec.dcross;
+  const double dlnA = ec.dlnA_dMc, idL = ec.inv_dL;
+  Point q;
+  point_setup(ec, k, true, ROT, q);
+  double W = 0.0, U[8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) U[b] = 0.0;
+  for (int s = 0; s < n_site; ++s) {
+    const SiteC& st = sc[s];
+    SitePoint sp;
+    site_point(st, q, true, sp);
+    const double phMc = fma(q.tf * sp.dH, q.gMc, q.pMc);
+    const double phEta = fma(q.tf * sp.dH, q.gEta, q.pEta);
+    const double phT = q.tf * sp.dT;
+    const double phP = -q.tf * sp.dH;
+    const double phTc = q.tf * fma(kOmegaE, sp.dH, 1.0);
+    for (int j = 0; j < st.n_eff; ++j) {
+      const double om = sp.om * st.weff[j];
+      const double Fp = dot4(st.alpha[j], sp.P), Fx = dot4(st.beta[j], sp.P);
+      const double FpH = dot4(st.alpha[j], sp.PH), FxH = dot4(st.beta[j], sp.PH);
+      const double Fpt = dot4(st.alpha[j], sp.Pt), Fxt = dot4(st.beta[j], sp.Pt);
+      const double Qr = cplus * Fp, Qi = ccross * Fx;
+      const double QHr = cplus * FpH, QHi = ccross * FxH;
+      const double Qtr = cplus * Fpt, Qti = ccross * Fxt;
+      double Dr[8], Di[8];
+      // D = dQ + Q dlnA + i Q dPsi, with i Q x = (-Qi x, Qr x)
+      Dr[0] = fma(Qr, dlnA, fma(QHr, q.gMc, -Qi * phMc));     // Mc
+      Di[0] = fma(Qi, dlnA, fma(QHi, q.gMc, Qr * phMc));
+      Dr[1] = fma(QHr, q.gEta, -Qi * phEta);                  // eta
+      Di[1] = fma(QHi, q.gEta, Qr * phEta);
+      Dr[2] = -Qr * idL;                                      // dL
+      Di[2] = -Qi * idL;
+      Dr[3] = fma(-Qi, phT, Qtr);                             // theta
+      Di[3] = fma(Qr, phT, Qti);
+      Dr[4] = fma(-Qi, phP, -QHr);                            // phi (H = ... - phi)
+      Di[4] = fma(Qr, phP, -QHi);
+      Dr[5] = dcp * Fp;                                       // iota
+      Di[5] = dcx * Fx;
+      Dr[6] = 2.0 * cplus * Fx;                               // psi: dF+ = 2Fx, dFx = -2F+
+      Di[6] = -2.0 * ccross * Fp;
+      Dr[7] = fma(kOmegaE, QHr, -Qi * phTc);                  // tc [s]
+      Di[7] = fma(kOmegaE, QHi, Qr * phTc);
+      int g = 0;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const double wr = om * Dr[r], wi = om * Di[r];
+#pragma unroll
+        for (int c = r; c < 8; ++c) {
+          G[g] = fma(wr, Dr[c], fma(wi, Di[c], G[g]));
+          ++g;
+        }
+        U[r] = fma(om, fma(-Qi, Dr[r], Qr * Di[r]), U[r]);
+      }
+      W = fma(om, fma(Qr, Qr, Qi * Qi), W);
+    }
+  }
+  double cph[NPI];
+  {
+    const double v = q.v, iv = q.iv, L = q.L;
+    const double iv2 = iv * iv, iv5 = iv2 * iv2 * iv, v2 = v * v, v5 = v2 * v2 * v;
+    cph[0] = -1.0;
+    cph[1] = eval_phase(ec.ps[kPsChi1], v, iv5, v5, v2, L);
+    cph[2] = eval_phase(ec.ps[kPsChi2], v, iv5, v5, v2, L);
+    if (TIDAL) {
+      cph[NPI - 2] = eval_phase(ec.ps[kPsL1], v, iv5, v5, v2, L);
+      cph[NPI - 1] = eval_phase(ec.ps[kPsL2], v, iv5, v5, v2, L);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+#pragma unroll
+    for (int i = 0; i < NPI; ++i) xy[(b * NPI + i) * xs] = fma(U[b], cph[i], xy[(b * NPI + i) * xs]);
+  int y = 8 * NPI;
+#pragma unroll
+  for (int i = 0; i < NPI; ++i) {
+    const double wc = W * cph[i];
+#pragma unroll
+    for (int j = i; j < NPI; ++j) {
+      xy[y * xs] = fma(wc, cph[j], xy[y * xs]);
+      ++y;
+    }
+  }
+}
+
+// Position (r, c) in the P x P Fisher matrix of accumulator slot t, with
+// slots ordered as: 36 entries of the 8x8 upper block (row-major), then the
+// 8 x NPI block, then the NPI x NPI upper block.
+__host__ __device__ inline void slot_position(int t, int NPI, int& r, int& c) {
+  if (t < 36) {
+    int i = t;
+    r = 0;
+    while (i >= 8 - r) { i -= 8 - r; ++r; }
+    c = r + i;
+  } else if (t < 36 + 8 * NPI) {
+    const int i = t - 36;
+    r = i / NPI;
+    c = 8 + i % NPI;
+  } else {
+    int i = t - 36 - 8 * NPI;
+    r = 0;
+    while (i >= NPI - r) { i -= NPI - r; ++r; }
+    c = 8 + r + i;
+    r = 8 + r;
+  }
+}
+
+}  // namespace gwf

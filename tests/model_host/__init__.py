@@ -1,0 +1,44 @@
+"""TEST ONLY: host build of the kernels' per-point mathematics (see model_host.hip)."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "model_host.hip")
+LIB = os.path.join(HERE, "libmodel_host.so")
+DEPS = [SRC, os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_model.hpp")]
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is None:
+        stale = not os.path.exists(LIB) or any(os.path.getmtime(d) > os.path.getmtime(LIB) for d in DEPS)
+        if stale:
+            subprocess.check_call(["/opt/rocm/bin/hipcc", "-O2", "-std=c++17", "-fPIC", "-shared",
+                                   "--offload-arch=gfx950", SRC, "-o", LIB + ".tmp"],
+                                  stderr=subprocess.DEVNULL)
+            os.replace(LIB + ".tmp", LIB)
+        _lib = ctypes.CDLL(LIB)
+    return _lib
+
+
+def fisher(wl):
+    lib = load()
+    P = 13 if wl.flags & 2 else 11
+    n = wl.n
+    par = np.ascontiguousarray(wl.par, dtype=np.float64)
+    sites = np.ascontiguousarray(wl.site_array())
+    fmin = np.ascontiguousarray(wl.fmin, dtype=np.float64)
+    fmax = None if wl.fmax is None else np.ascontiguousarray(wl.fmax, dtype=np.float64)
+    npts = np.ascontiguousarray(wl.npts, dtype=np.int32)
+    F = np.zeros((P, P, n))
+    snr = np.zeros(n)
+    st = np.zeros(n, dtype=np.int32)
+    P_ = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    lib.model_fisher_host(ctypes.c_int64(n), P_(par), ctypes.c_int64(n), P_(fmin), P_(fmax), P_(npts),
+                          ctypes.c_int(len(sites)), P_(sites), ctypes.c_uint32(wl.flags), P_(F),
+                          P_(snr), P_(st))
+    return {"fisher": F, "snr": snr, "status": st}

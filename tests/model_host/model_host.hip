@@ -1,0 +1,59 @@
+// model_host.hip -- TEST ONLY: the per-point mathematics of the GPU kernels
+// (gwf_model.hpp, the same source the kernels compile) run on the host, so
+// that the CPU test-suite can compare the kernel math with the oracle
+// without a GPU.  Never linked into libgwf; no product path calls it.
+#include <cmath>
+#include <vector>
+
+#include "../../paper_2207_06910_amd/csrc/gwf_model.hpp"
+
+using namespace gwf;
+
+template <bool TIDAL, bool ROT>
+static void one_event(const double* p, double fmin, double fmax, int32_t n, const NetDesc& nd,
+                      double* F, double* snr, int32_t* status) {
+  constexpr int P = TIDAL ? 13 : 11, NPI = P - 8, NACC = 36 + 8 * NPI + NPI * (NPI + 1) / 2;
+  const uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u);
+  EventC ec;
+  event_setup(p, fmin, fmax, n, flags, ec);
+  *status = ec.status;
+  if (ec.status) return;
+  SiteC sc[kMaxSites];
+  for (int s = 0; s < nd.n_site; ++s) site_setup(p, nd.site[s], ec, sc[s]);
+  double G[36] = {0}, xy[64] = {0};
+  for (int32_t k = 0; k < ec.n; ++k) accumulate_point<TIDAL, ROT>(ec, sc, nd.n_site, k, G, xy, 1);
+  for (int t = 0; t < NACC; ++t) {
+    int r, c;
+    slot_position(t, NPI, r, c);
+    const double v = t < 36 ? G[t] : xy[t - 36];
+    F[r * P + c] = v;
+    F[c * P + r] = v;
+  }
+  *snr = std::sqrt(F[8 * P + 8]);
+}
+
+extern "C" int model_fisher_host(int64_t n, const double* par, int64_t ld, const double* fmin,
+                                 const double* fmax, const int32_t* npts, int n_site,
+                                 const double* sites, uint32_t flags, double* fisher, double* snr,
+                                 int32_t* status) {
+  NetDesc nd{};
+  nd.n_site = n_site;
+  for (int s = 0; s < n_site; ++s) {
+    const double* r = sites + 7 * s;
+    nd.site[s] = SiteDesc{r[0], r[1], r[2], r[3], r[5], r[6], (int32_t)r[4], 0};
+  }
+  const bool tidal = flags & kFlagTidal, rot = flags & kFlagRot;
+  const int P = tidal ? 13 : 11;
+  std::vector<double> F(P * P);
+  for (int64_t e = 0; e < n; ++e) {
+    double p[13];
+    for (int r = 0; r < 13; ++r) p[r] = par[r * ld + e];
+    const double fx = fmax ? fmax[e] : 0.0;
+    if (tidal && rot) one_event<true, true>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
+    else if (tidal) one_event<true, false>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
+    else if (rot) one_event<false, true>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
+    else one_event<false, false>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
+    for (int i = 0; i < P * P; ++i) fisher[i * n + e] = status[e] ? 0.0 : F[i];
+  }
+  return 0;
+}

@@ -18,10 +18,12 @@
 // and only the 8x8 block of (Mc, eta, dL, theta, phi, iota, psi, tc) needs a
 // per-interferometer rank-2 update.
 //
-// Register budget: the 8x8 block (36 doubles) is accumulated in registers;
-// the phase-only blocks (up to 55 doubles per lane, updated once per
-// frequency) are accumulated in LDS, laid out [entry][lane] so each access
-// of a wavefront touches 64 consecutive doubles.
+// The 8x8 block (36 doubles) is accumulated in registers.  The phase-only
+// blocks are a small dense contraction over frequency, X = sum_f a_f c_f^T
+// with a_f = (U_0..U_7, W c_0..W c_{NPI-1}) and c_f = (c_0..c_{NPI-1}):
+// every iteration each wavefront stages its 64 points' a_f and c_f in LDS
+// and folds them into a 16x16 FP64 accumulator with 16 MFMA 16x16x4 steps
+// (k = frequency), which keeps those 55 sums out of the lanes' registers.
 #include "gwf_kernels.hpp"
 
 namespace gwf {
@@ -30,6 +32,11 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
+constexpr int kRowsA = 13;        // 8 U rows + up to 5 W c rows
+constexpr int kRowsB = 5;         // up to 5 c rows
+constexpr int kTileLd = 64 + 2;   // padded row stride (doubles)
+
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ inline double wave_sum(double x) {
 #pragma unroll
@@ -45,8 +52,12 @@ __device__ inline void load_par(const double* __restrict__ par, int64_t ld, int6
 
 }  // namespace
 
+// Declared for 2 x kBlock lanes so that the register budget is that of two
+// wavefronts per SIMD (256 registers); launched with kBlock lanes, two
+// workgroups (45 KB of LDS each) then share a compute unit, which hides the
+// latency of the LDS constant reads and of the transcendental sequences.
 template <bool TIDAL, bool ROT>
-__global__ __launch_bounds__(kBlock) void fisher_kernel(FisherArgs a) {
+__global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(FisherArgs a) {
   constexpr int P = TIDAL ? 13 : 11;
   constexpr int NPI = P - 8;                       // phase-only parameters
   constexpr int NG = 36, NX = 8 * NPI, NY = NPI * (NPI + 1) / 2;
@@ -56,7 +67,8 @@ __global__ __launch_bounds__(kBlock) void fisher_kernel(FisherArgs a) {
   __shared__ EventC ec;
   __shared__ SiteC sc[kMaxSites];
   __shared__ double red[kWaves][NACC];
-  __shared__ double xy[NX + NY][kBlock];           // per-lane phase-only accumulators
+  __shared__ double stA[kWaves][kRowsA][kTileLd];   // staged a_f, [row][point]
+  __shared__ double stB[kWaves][kRowsB][kTileLd];   // staged c_f
   __shared__ int32_t skip;
 
   const int64_t e = blockIdx.x;
@@ -85,27 +97,61 @@ __global__ __launch_bounds__(kBlock) void fisher_kernel(FisherArgs a) {
   double G[NG];
 #pragma unroll
   for (int i = 0; i < NG; ++i) G[i] = 0.0;
-#pragma unroll
-  for (int i = 0; i < NX + NY; ++i) xy[i][tid] = 0.0;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  const int wave = tid >> 6, lane = tid & 63;
+  const int mrow = lane & 15, mk = lane >> 4;      // MFMA operand position of this lane
+  double(*A)[kTileLd] = stA[wave];
+  double(*B)[kTileLd] = stB[wave];
 
   const int n = ec.n;
-  for (int k = tid; k < n; k += kBlock) {
+  const int iters = (n + kBlock - 1) / kBlock;    // same trip count for every lane
+  for (int it = 0; it < iters; ++it) {
     // The per-event constants stay in LDS and are re-read every iteration
     // (uniform broadcast reads); hoisting them out of the loop would need
     // more registers than a lane has.
     __asm__ volatile("" ::: "memory");
-    accumulate_point<TIDAL, ROT>(ec, sc, n_site, k, G, &xy[0][tid], kBlock);
+    const int k = it * kBlock + tid;
+    double U[8], W = 0.0, cph[NPI];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) U[b] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NPI; ++i) cph[i] = 0.0;
+    if (k < n) accumulate_point<TIDAL, ROT>(ec, sc, n_site, k, G, U, W, cph);
+    // stage this point's row (points past the grid end contribute zeros)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) A[b][lane] = U[b];
+#pragma unroll
+    for (int i = 0; i < NPI; ++i) {
+      A[8 + i][lane] = W * cph[i];
+      B[i][lane] = cph[i];
+    }
+    __builtin_amdgcn_wave_barrier();
+    // X += A^T B over this wavefront's 64 points: k-step s takes points 16 mk + s
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2) {
+      const double av = mrow < 8 + NPI ? A[mrow][16 * mk + s2] : 0.0;
+      const double bv = mrow < NPI ? B[mrow][16 * mk + s2] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 
   // ---- deterministic reduction: wavefront butterflies, then the 4 waves in order
-  const int wave = tid >> 6, lane = tid & 63;
 #pragma unroll
   for (int i = 0; i < NG; ++i) { double t = wave_sum(G[i]); if (lane == 0) red[wave][i] = t; }
-  // each lane's LDS accumulators are its own: reduce them per wave, in order
+  // register r of lane (mk, mrow) holds accumulator element (4 r + mk, mrow):
+  // rows 0..7 are the U_b rows (cols 0..NPI-1), rows 8..8+NPI-1 the W c_i
+  // rows (upper triangle kept)
 #pragma unroll
-  for (int i = 0; i < NX + NY; ++i) {
-    double t = wave_sum(xy[i][tid]);
-    if (lane == 0) red[wave][NG + i] = t;
+  for (int r = 0; r < 4; ++r) {
+    const int row = 4 * r + mk, col = mrow;
+    int slot = -1;
+    if (row < 8 && col < NPI) slot = NG + row * NPI + col;
+    else if (row >= 8 && row < 8 + NPI && col >= row - 8 && col < NPI) {
+      const int i = row - 8;
+      slot = NG + NX + i * NPI - (i * (i - 1)) / 2 + (col - i);
+    }
+    if (slot >= 0) red[wave][slot] = acc[r];
   }
   __syncthreads();
   __shared__ int32_t bad;

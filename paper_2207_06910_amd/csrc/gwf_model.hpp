@@ -567,24 +567,26 @@ __host__ __device__ inline double dot4(const double a[4], const double b[4]) {
 }
 
 // ------------------------------------------------ one frequency point
-// Adds the contribution of grid point k of an event to
-//   G[36]  the 8x8 upper-triangle block of (Mc, eta, dL, theta, phi, iota,
-//          psi, tc), row-major;
-//   xy     the phase-only blocks: xy[(b*NPI + i)*xs] += U_b c_i (b < 8) and
-//          then the upper triangle of W c_i c_j, with NPI = P - 8 and
-//          c = (-1, dPsi/dchi1, dPsi/dchi2[, dPsi/dLambda1, dPsi/dLambda2]).
+// Adds the contribution of grid point k of an event to G[36], the 8x8
+// upper-triangle block of (Mc, eta, dL, theta, phi, iota, psi, tc)
+// (row-major), and returns the point's phase-only quantities:
+//   U[8]   U_b = sum_i w_i Re(i Q_i D_b,i^*)
+//   W      sum_i w_i |Q_i|^2 (the SNR^2 density)
+//   c[NPI] (-1, dPsi/dchi1, dPsi/dchi2[, dPsi/dLambda1, dPsi/dLambda2]).
 // The phase-only derivative vectors are i Q c(f) with the same real c(f) at
-// every interferometer, so their blocks need only the per-frequency network
-// sums W = sum_i w_i |Q_i|^2 and U_b = sum_i w_i Re(i Q_i D_b,i^*).
+// every interferometer, so the blocks they span are
+//   Gamma_{b, 8+i} += U_b c_i,   Gamma_{8+i, 8+j} += W c_i c_j,
+// which the caller accumulates (see add_phase_blocks).
 template <bool TIDAL, bool ROT>
 __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* sc, int n_site,
-                                                 int32_t k, double* G, double* xy, int xs) {
+                                                 int32_t k, double* G, double* U, double& W,
+                                                 double* cph) {
   constexpr int NPI = TIDAL ? 5 : 3;
   const double cplus = ec.cplus, ccross = ec.ccross, dcp = ec.dcplus, dcx = ec.dcross;
   const double dlnA = ec.dlnA_dMc, idL = ec.inv_dL;
   Point q;
   point_setup(ec, k, true, ROT, q);
-  double W = 0.0, U[8];
+  W = 0.0;
 #pragma unroll
   for (int b = 0; b < 8; ++b) U[b] = 0.0;
   for (int s = 0; s < n_site; ++s) {
@@ -636,7 +638,6 @@ __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* 
       W = fma(om, fma(Qr, Qr, Qi * Qi), W);
     }
   }
-  double cph[NPI];
   {
     const double v = q.v, iv = q.iv, L = q.L;
     const double iv2 = iv * iv, iv5 = iv2 * iv2 * iv, v2 = v * v, v5 = v2 * v2 * v;
@@ -648,15 +649,17 @@ __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* 
       cph[NPI - 1] = eval_phase(ec.ps[kPsL2], v, iv5, v5, v2, L);
     }
   }
-#pragma unroll
+}
+
+// Plain accumulation of the phase-only blocks of one point into
+// xy[(b*NPI + i)*xs] (b < 8) and then the upper triangle of W c_i c_j.
+__host__ __device__ inline void add_phase_blocks(int NPI, const double* U, double W, const double* cph,
+                                                 double* xy, int xs) {
   for (int b = 0; b < 8; ++b)
-#pragma unroll
     for (int i = 0; i < NPI; ++i) xy[(b * NPI + i) * xs] = fma(U[b], cph[i], xy[(b * NPI + i) * xs]);
   int y = 8 * NPI;
-#pragma unroll
   for (int i = 0; i < NPI; ++i) {
     const double wc = W * cph[i];
-#pragma unroll
     for (int j = i; j < NPI; ++j) {
       xy[y * xs] = fma(wc, cph[j], xy[y * xs]);
       ++y;

@@ -77,7 +77,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--cpu-sample", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -104,21 +104,21 @@ def main():
         binding.fisher(dw, out=outf)
         binding.invert(outf["fisher"], outf["status"], out=outi)
 
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    # ---- plain form: one workgroup per event, ordinary launches
     for i in range(args.warmup):
         step()
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    log(f"timed {args.steps} steps: {ms:.3f} ms/step")
-
-    # per-kernel durations with HIP events on the launch stream
+    plain_ms = timed(step, args.steps)
+    log(f"plain: {args.steps} steps, {plain_ms:.3f} ms/step")
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     tf, ti = [], []
@@ -134,15 +134,38 @@ def main():
     fisher_ms = float(np.mean(tf))
     invert_ms = float(np.mean(ti))
     st = outf["status"].cpu().numpy()
-    n_ok = int(np.sum(st == 0))
-    log(f"fisher kernel {fisher_ms:.3f} ms, invert kernel {invert_ms:.3f} ms, status ok {n_ok}/{wl.n}")
+    log(f"plain fisher kernel {fisher_ms:.3f} ms, invert kernel {invert_ms:.3f} ms, "
+        f"status ok {int(np.sum(st == 0))}/{wl.n}")
+
+    # ---- batched form: work items, persistent workgroups, one HIP graph per step
+    plan = binding.Plan(dw)                     # autotunes item length and workgroups per CU
+    info = plan.info()
+    outb = {}
+    for i in range(args.warmup):
+        plan.run(invert=True, out=outb)
+    batched_ms = timed(lambda: plan.run(invert=True, out=outb), args.steps)
+    log(f"batched: chunk {info['chunk']}, {info['wg_per_cu']} WG/CU, {info['n_items']} items, "
+        f"{batched_ms:.3f} ms/step")
+    prof = binding.Plan(dw, chunk=info["chunk"], wg_per_cu=info["wg_per_cu"], use_graph=False,
+                        profile=True)
+    items = []
+    for i in range(args.steps):
+        prof.run(invert=True, out=outb)
+        items.append(prof.info()["items_ms"])
+    items_ms = float(np.mean(items))
+    prof.close()
+    sb = outb["status"].cpu().numpy()
+    log(f"batched items kernel {items_ms:.3f} ms, status ok {int(np.sum(sb == 0))}/{wl.n}")
 
     flops = algorithmic_flops(wl)
-    achieved = flops / (fisher_ms * 1e-3) / 1e12
+    if batched_ms < plain_ms:
+        form, ms, kname, kms = "batched FP64", batched_ms, "items_kernel<tidal,rot>", items_ms
+    else:
+        form, ms, kname, kms = "plain FP64", plain_ms, "fisher_kernel<tidal,rot>", fisher_ms
+    achieved = flops / (kms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
-                "kernel": "fisher_kernel<tidal,rot>", "kernel_ms": round(fisher_ms, 4),
-                "flops_per_launch": flops}
+                "kernel": kname, "kernel_ms": round(kms, 4), "flops_per_launch": flops}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -151,6 +174,13 @@ def main():
         log(f"cpu baseline {cpu['value']:.3f} events/s")
 
     value = wl.n / (ms * 1e-3)
+    forms = {"plain_fp64": {"events_per_s": round(wl.n / (plain_ms * 1e-3), 1),
+                            "ms_per_step": round(plain_ms, 4), "fisher_ms": round(fisher_ms, 4),
+                            "invert_ms": round(invert_ms, 4)},
+             "batched_fp64": {"events_per_s": round(wl.n / (batched_ms * 1e-3), 1),
+                              "ms_per_step": round(batched_ms, 4), "items_ms": round(items_ms, 4),
+                              "chunk": info["chunk"], "wg_per_cu": info["wg_per_cu"],
+                              "n_items": info["n_items"], "graph": True}}
     out = {
         "metric": "Fisher events/s (BNS, 3-det, Earth-rot) plain FP64 vs mixed/batched @tol",
         "value": round(value, 1), "unit": "events/s", "n_gpus": 1, "steps": args.steps,
@@ -159,9 +189,8 @@ def main():
         "config": {"workload": "bns1e4: 10^4 BNS (m1,m2 in 1.1-2.2 Msun, tides, aligned spins), "
                                "triangle + 2 L sites (5 interferometers), Earth rotation, 13 "
                                "parameters, log grids 2 Hz to f_cut of 2000-20000 points",
-                   "events": wl.n, "grid_points": int(wl.npts.sum()), "form": "plain FP64"},
-        "forms": {"plain_fp64": {"events_per_s": round(value, 1), "fisher_ms": round(fisher_ms, 4),
-                                 "invert_ms": round(invert_ms, 4)}},
+                   "events": wl.n, "grid_points": int(wl.npts.sum()), "form": form},
+        "forms": forms,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -191,6 +191,60 @@ gwf_status gwf_invert(int32_t P, int64_t n, const double* fisher, double cond_ma
                       double* cov, double* sigma, double* cond, double* inv_err,
                       int32_t* status, void* stream);
 
+/* ------------------------------------------------------ batched form */
+/* A plan runs the Fisher (and optionally the inversion) of one catalogue
+ * repeatedly: the work is cut into items of at most `chunk` grid points
+ * (events with long grids give several items), persistent workgroups pull
+ * items from a device counter, and each event's item sums are combined in
+ * item order, so results are deterministic and independent of scheduling.
+ * The set-up, item, combine and inversion kernels are captured once into a
+ * HIP graph and replayed.  This is the batched persistent form of the path
+ * for catalogues with uneven grid lengths (the paper's counterpart is its
+ * batch/process parallelism over catalogues, sec. 5).
+ *
+ * gwf_plan_create reads the grid lengths (npts) back to the host and
+ * synchronises `stream`; with chunk or wg_per_cu left at 0 it also times
+ * the candidate configurations on the given events (autotuning).  The event,
+ * grid and network descriptors are captured: later runs read the device
+ * arrays at the same addresses, whose values (parameters, fmin, fmax) may
+ * change, but the grid lengths may not (an event whose npts differs from
+ * the plan's gets GWF_EV_INVALID_PARAM).  The plan owns its workspace
+ * (about 2 KB per event plus 0.75 KB per work item) until gwf_plan_destroy. */
+typedef struct gwf_plan gwf_plan;
+
+typedef struct gwf_plan_options {
+  int32_t chunk;       /* points per work item, a multiple of 256; 0 = autotune     */
+  int32_t wg_per_cu;   /* persistent workgroups per compute unit, 1..8; 0 = autotune */
+  int32_t use_graph;   /* nonzero: capture and replay a HIP graph                     */
+  int32_t profile;     /* nonzero (with use_graph = 0): time the work-item kernel of
+                          each run with HIP events on its stream                     */
+} gwf_plan_options;
+
+typedef struct gwf_plan_info {
+  int32_t chunk, wg_per_cu, n_items, use_graph;
+  int64_t workspace_bytes;
+  double tuned_ms;     /* time of the chosen configuration during autotuning, or 0 */
+  double items_ms;     /* with profile: work-item kernel time of the last run (this
+                          call waits for that run to finish), else 0               */
+} gwf_plan_info;
+
+/* opt NULL: autotune both knobs, use a graph. */
+gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
+                           uint32_t flags, const gwf_plan_options* opt, gwf_plan** plan,
+                           void* stream);
+
+/* Fisher, SNR and status of the plan's catalogue (same layouts and meaning
+ * as gwf_fisher with snr_th = 0).  With sigma non-NULL the inversion of
+ * gwf_invert follows in the same graph (cov, cond, inv_err optional). */
+gwf_status gwf_plan_fisher(gwf_plan* plan, double* fisher, double* snr, int32_t* status,
+                           double cond_max, double* cov, double* sigma, double* cond,
+                           double* inv_err, void* stream);
+
+gwf_status gwf_plan_get_info(const gwf_plan* plan, gwf_plan_info* info);
+
+/* Frees the plan and its workspace (NULL is allowed). */
+gwf_status gwf_plan_destroy(gwf_plan* plan);
+
 /* Number of interferometers of a network (T sites count 3); -1 if invalid. */
 int32_t gwf_network_n_ifo(const gwf_network* net);
 

@@ -41,6 +41,18 @@ class Grid(ctypes.Structure):
                 ("npts", ctypes.c_void_p)]
 
 
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("profile", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("n_items", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_int64), ("tuned_ms", ctypes.c_double),
+                ("items_ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -64,6 +76,16 @@ def load():
         lib.gwf_fisher.restype = i32
         lib.gwf_invert.argtypes = [i32, i64, vp, d, vp, vp, vp, vp, vp, vp]
         lib.gwf_invert.restype = i32
+        lib.gwf_plan_create.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
+                                        ctypes.POINTER(Grid), ctypes.c_uint32,
+                                        ctypes.POINTER(PlanOptions), ctypes.POINTER(vp), vp]
+        lib.gwf_plan_create.restype = i32
+        lib.gwf_plan_fisher.argtypes = [vp, vp, vp, vp, d, vp, vp, vp, vp, vp]
+        lib.gwf_plan_fisher.restype = i32
+        lib.gwf_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        lib.gwf_plan_get_info.restype = i32
+        lib.gwf_plan_destroy.argtypes = [vp]
+        lib.gwf_plan_destroy.restype = i32
         lib.gwf_network_n_ifo.argtypes = [ctypes.POINTER(Network)]
         lib.gwf_network_n_ifo.restype = i32
         lib.gwf_last_error.restype = ctypes.c_char_p
@@ -198,3 +220,55 @@ def invert(F, status=None, cond_max=1e50, want_cov=True, stream=None, out=None):
                              _ptr(res["sigma"]), _ptr(res["cond"]), _ptr(res["inv_err"]), _ptr(st),
                              _stream(stream)), "gwf_invert")
     return res
+
+
+class Plan:
+    """Batched persistent form (gwf_plan_*): built once for a device-resident
+    catalogue, then replayed.  Keeps a reference to the DeviceWorkload, whose
+    arrays the plan reads at every run."""
+
+    def __init__(self, dw: DeviceWorkload, chunk=0, wg_per_cu=0, use_graph=True, profile=False,
+                 stream=None):
+        self.dw = dw
+        self.handle = ctypes.c_void_p()
+        ev, net, grid, keep = dw.descriptors()
+        opt = PlanOptions(int(chunk), int(wg_per_cu), 1 if use_graph else 0, 1 if profile else 0)
+        _check(load().gwf_plan_create(ctypes.byref(ev), ctypes.byref(net), ctypes.byref(grid),
+                                      dw.flags, ctypes.byref(opt), ctypes.byref(self.handle),
+                                      _stream(stream)), "gwf_plan_create")
+        self.P = 13 if dw.flags & TIDAL else 11
+
+    def info(self) -> dict:
+        i = PlanInfo()
+        _check(load().gwf_plan_get_info(self.handle, ctypes.byref(i)), "gwf_plan_get_info")
+        return {f: getattr(i, f) for f, _ in PlanInfo._fields_}
+
+    def run(self, invert=False, cond_max=1e50, stream=None, out=None):
+        import torch
+        dev = self.dw.par.device
+        n, P = self.dw.n, self.P
+        res = out if out is not None else {}
+        res.setdefault("fisher", torch.empty((P, P, n), dtype=torch.float64, device=dev))
+        res.setdefault("snr", torch.empty(n, dtype=torch.float64, device=dev))
+        res.setdefault("status", torch.empty(n, dtype=torch.int32, device=dev))
+        if invert:
+            res.setdefault("cov", torch.empty((P, P, n), dtype=torch.float64, device=dev))
+            res.setdefault("sigma", torch.empty((P, n), dtype=torch.float64, device=dev))
+            res.setdefault("cond", torch.empty(n, dtype=torch.float64, device=dev))
+            res.setdefault("inv_err", torch.empty(n, dtype=torch.float64, device=dev))
+        _check(load().gwf_plan_fisher(self.handle, _ptr(res["fisher"]), _ptr(res["snr"]),
+                                      _ptr(res["status"]), float(cond_max), _ptr(res.get("cov")),
+                                      _ptr(res.get("sigma")), _ptr(res.get("cond")),
+                                      _ptr(res.get("inv_err")), _stream(stream)), "gwf_plan_fisher")
+        return res
+
+    def close(self):
+        if self.handle:
+            load().gwf_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,14 +7,16 @@
 #include <string>
 
 #include "../../include/gwf.h"
+#include "gwf_api_internal.hpp"
 #include "gwf_kernels.hpp"
 
 namespace {
 
 thread_local std::string g_last_error;
 
-gwf_status fail(gwf_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-gwf_status fail(gwf_status code, const char* fmt, ...) {
+}  // namespace
+
+gwf_status api_fail(gwf_status code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -24,9 +26,11 @@ gwf_status fail(gwf_status code, const char* fmt, ...) {
   return code;
 }
 
-gwf_status hip_fail(hipError_t err, const char* where) {
-  return fail(GWF_E_HIP, "%s: %s", where, hipGetErrorString(err));
+gwf_status api_hip_fail(hipError_t err, const char* where) {
+  return api_fail(GWF_E_HIP, "%s: %s", where, hipGetErrorString(err));
 }
+
+namespace {
 
 bool finite_all(std::initializer_list<double> xs) {
   for (double x : xs)
@@ -34,50 +38,50 @@ bool finite_all(std::initializer_list<double> xs) {
   return true;
 }
 
+}  // namespace
+
 // Validate and pack the network into the kernels' by-value descriptor.
-gwf_status pack_network(const gwf_network* net, gwf::NetDesc& nd) {
-  if (!net || !net->site) return fail(GWF_E_INVALID_ARG, "network or its site array is NULL");
+gwf_status api_pack_network(const gwf_network* net, gwf::NetDesc& nd) {
+  if (!net || !net->site) return api_fail(GWF_E_INVALID_ARG, "network or its site array is NULL");
   if (net->n_site < 1 || net->n_site > GWF_MAX_SITES)
-    return fail(GWF_E_INVALID_ARG, "n_site=%d outside 1..%d", net->n_site, GWF_MAX_SITES);
+    return api_fail(GWF_E_INVALID_ARG, "n_site=%d outside 1..%d", net->n_site, GWF_MAX_SITES);
   std::memset(&nd, 0, sizeof nd);
   int n_ifo = 0;
   for (int s = 0; s < net->n_site; ++s) {
     const gwf_site& in = net->site[s];
     if (in.shape != GWF_SHAPE_L && in.shape != GWF_SHAPE_T)
-      return fail(GWF_E_INVALID_ARG, "site %d: shape %d is neither L nor T", s, in.shape);
+      return api_fail(GWF_E_INVALID_ARG, "site %d: shape %d is neither L nor T", s, in.shape);
     if (in.psd_kind != GWF_PSD_ANALYTIC)
-      return fail(GWF_E_UNSUPPORTED, "site %d: psd_kind %d is not supported", s, in.psd_kind);
+      return api_fail(GWF_E_UNSUPPORTED, "site %d: psd_kind %d is not supported", s, in.psd_kind);
     if (!finite_all({in.lat, in.lon, in.gamma, in.zeta, in.S0, in.f0}))
-      return fail(GWF_E_INVALID_ARG, "site %d: non-finite geometry or PSD parameter", s);
+      return api_fail(GWF_E_INVALID_ARG, "site %d: non-finite geometry or PSD parameter", s);
     if (!(in.S0 > 0.0) || !(in.f0 > 0.0))
-      return fail(GWF_E_INVALID_ARG, "site %d: S0 and f0 must be > 0", s);
+      return api_fail(GWF_E_INVALID_ARG, "site %d: S0 and f0 must be > 0", s);
     if (std::fabs(in.lat) > 0.5 * M_PI + 1e-12)
-      return fail(GWF_E_INVALID_ARG, "site %d: latitude outside [-pi/2, pi/2]", s);
+      return api_fail(GWF_E_INVALID_ARG, "site %d: latitude outside [-pi/2, pi/2]", s);
     gwf::SiteDesc& o = nd.site[s];
     o.lat = in.lat; o.lon = in.lon; o.gamma = in.gamma; o.zeta = in.zeta;
     o.S0 = in.S0; o.f0 = in.f0; o.shape = in.shape;
     n_ifo += in.shape == GWF_SHAPE_T ? 3 : 1;
   }
-  if (n_ifo > GWF_MAX_IFO) return fail(GWF_E_INVALID_ARG, "%d interferometers > %d", n_ifo, GWF_MAX_IFO);
+  if (n_ifo > GWF_MAX_IFO) return api_fail(GWF_E_INVALID_ARG, "%d interferometers > %d", n_ifo, GWF_MAX_IFO);
   nd.n_site = net->n_site;
   nd.n_ifo = n_ifo;
   return GWF_OK;
 }
 
-gwf_status check_common(const gwf_events* ev, const gwf_grid* grid, uint32_t flags) {
-  if (!ev || !grid) return fail(GWF_E_INVALID_ARG, "events or grid descriptor is NULL");
-  if (ev->n < 1) return fail(GWF_E_INVALID_ARG, "n=%lld must be >= 1", (long long)ev->n);
-  if (ev->n > 0x7fffffffLL) return fail(GWF_E_INVALID_ARG, "n=%lld exceeds 2^31-1", (long long)ev->n);
-  if (ev->ld < ev->n) return fail(GWF_E_INVALID_ARG, "ld=%lld < n", (long long)ev->ld);
-  if (!ev->par) return fail(GWF_E_INVALID_ARG, "par is NULL");
-  if (grid->kind != GWF_GRID_LOG) return fail(GWF_E_UNSUPPORTED, "grid kind %d", grid->kind);
-  if (!grid->fmin || !grid->npts) return fail(GWF_E_INVALID_ARG, "grid fmin or npts is NULL");
+gwf_status api_check_common(const gwf_events* ev, const gwf_grid* grid, uint32_t flags) {
+  if (!ev || !grid) return api_fail(GWF_E_INVALID_ARG, "events or grid descriptor is NULL");
+  if (ev->n < 1) return api_fail(GWF_E_INVALID_ARG, "n=%lld must be >= 1", (long long)ev->n);
+  if (ev->n > 0x7fffffffLL) return api_fail(GWF_E_INVALID_ARG, "n=%lld exceeds 2^31-1", (long long)ev->n);
+  if (ev->ld < ev->n) return api_fail(GWF_E_INVALID_ARG, "ld=%lld < n", (long long)ev->ld);
+  if (!ev->par) return api_fail(GWF_E_INVALID_ARG, "par is NULL");
+  if (grid->kind != GWF_GRID_LOG) return api_fail(GWF_E_UNSUPPORTED, "grid kind %d", grid->kind);
+  if (!grid->fmin || !grid->npts) return api_fail(GWF_E_INVALID_ARG, "grid fmin or npts is NULL");
   if (flags & ~(uint32_t)(GWF_EARTH_ROT | GWF_TIDAL))
-    return fail(GWF_E_INVALID_ARG, "unknown flag bits 0x%x", flags);
+    return api_fail(GWF_E_INVALID_ARG, "unknown flag bits 0x%x", flags);
   return GWF_OK;
 }
-
-}  // namespace
 
 extern "C" {
 
@@ -87,35 +91,35 @@ int32_t gwf_version(void) { return GWF_VERSION; }
 
 int32_t gwf_network_n_ifo(const gwf_network* net) {
   gwf::NetDesc nd;
-  if (pack_network(net, nd) != GWF_OK) return -1;
+  if (api_pack_network(net, nd) != GWF_OK) return -1;
   return nd.n_ifo;
 }
 
 gwf_status gwf_snr(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
                    uint32_t flags, double* snr, double* snr_ifo, int32_t* status, void* stream) {
-  gwf_status st = check_common(ev, grid, flags);
+  gwf_status st = api_check_common(ev, grid, flags);
   if (st) return st;
-  if (!snr) return fail(GWF_E_INVALID_ARG, "snr is NULL");
+  if (!snr) return api_fail(GWF_E_INVALID_ARG, "snr is NULL");
   gwf::SnrArgs a{};
-  if ((st = pack_network(net, a.net))) return st;
+  if ((st = api_pack_network(net, a.net))) return st;
   a.par = ev->par; a.ld = ev->ld; a.n = ev->n;
   a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
   a.tidal = (flags & GWF_TIDAL) ? 1 : 0;
   a.snr = snr; a.snr_ifo = snr_ifo; a.status = status;
   hipError_t err = gwf::launch_snr(a, (flags & GWF_EARTH_ROT) != 0, (hipStream_t)stream);
-  if (err != hipSuccess) return hip_fail(err, "snr kernel launch");
+  if (err != hipSuccess) return api_hip_fail(err, "snr kernel launch");
   return GWF_OK;
 }
 
 gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
                       uint32_t flags, double snr_th, double* fisher, double* snr, double* snr_ifo,
                       int32_t* status, void* stream) {
-  gwf_status st = check_common(ev, grid, flags);
+  gwf_status st = api_check_common(ev, grid, flags);
   if (st) return st;
-  if (!fisher || !snr || !status) return fail(GWF_E_INVALID_ARG, "fisher, snr and status are required");
-  if (!std::isfinite(snr_th)) return fail(GWF_E_INVALID_ARG, "snr_th is not finite");
+  if (!fisher || !snr || !status) return api_fail(GWF_E_INVALID_ARG, "fisher, snr and status are required");
+  if (!std::isfinite(snr_th)) return api_fail(GWF_E_INVALID_ARG, "snr_th is not finite");
   gwf::FisherArgs a{};
-  if ((st = pack_network(net, a.net))) return st;
+  if ((st = api_pack_network(net, a.net))) return st;
   a.par = ev->par; a.ld = ev->ld; a.n = ev->n;
   a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
   a.snr_th = snr_th;
@@ -129,25 +133,25 @@ gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_gr
     b.fmin = a.fmin; b.fmax = a.fmax; b.npts = a.npts; b.tidal = tidal;
     b.snr = snr; b.snr_ifo = snr_ifo; b.status = nullptr;
     hipError_t err = gwf::launch_snr(b, rot, s);
-    if (err != hipSuccess) return hip_fail(err, "snr kernel launch");
+    if (err != hipSuccess) return api_hip_fail(err, "snr kernel launch");
     if (snr_th > 0.0) a.snr_pre = snr;
   }
   hipError_t err = gwf::launch_fisher(a, tidal, rot, s);
-  if (err != hipSuccess) return hip_fail(err, "fisher kernel launch");
+  if (err != hipSuccess) return api_hip_fail(err, "fisher kernel launch");
   return GWF_OK;
 }
 
 gwf_status gwf_invert(int32_t P, int64_t n, const double* fisher, double cond_max, double* cov,
                       double* sigma, double* cond, double* inv_err, int32_t* status, void* stream) {
-  if (P < 1 || P > GWF_NPAR_MAX) return fail(GWF_E_INVALID_ARG, "P=%d outside 1..13", P);
-  if (n < 1) return fail(GWF_E_INVALID_ARG, "n=%lld must be >= 1", (long long)n);
-  if (!fisher || !sigma || !status) return fail(GWF_E_INVALID_ARG, "fisher, sigma and status are required");
-  if (std::isnan(cond_max)) return fail(GWF_E_INVALID_ARG, "cond_max is NaN");
+  if (P < 1 || P > GWF_NPAR_MAX) return api_fail(GWF_E_INVALID_ARG, "P=%d outside 1..13", P);
+  if (n < 1) return api_fail(GWF_E_INVALID_ARG, "n=%lld must be >= 1", (long long)n);
+  if (!fisher || !sigma || !status) return api_fail(GWF_E_INVALID_ARG, "fisher, sigma and status are required");
+  if (std::isnan(cond_max)) return api_fail(GWF_E_INVALID_ARG, "cond_max is NaN");
   gwf::InvertArgs a{};
   a.n = n; a.fisher = fisher; a.cond_max = cond_max; a.cov = cov; a.sigma = sigma;
   a.cond = cond; a.inv_err = inv_err; a.status = status;
   hipError_t err = gwf::launch_invert(a, P, (hipStream_t)stream);
-  if (err != hipSuccess) return hip_fail(err, "invert kernel launch");
+  if (err != hipSuccess) return api_hip_fail(err, "invert kernel launch");
   return GWF_OK;
 }
 

@@ -1,0 +1,144 @@
+// gwf_batched.hip -- batched form of the Fisher/SNR path for catalogues with
+// uneven grid lengths.
+//
+//   setup_kernel    one lane per event (and per event x site): the per-event
+//                   and per-site constants, written once to a workspace.
+//   items_kernel    persistent workgroups pull work items (event, point range
+//                   [k0, k1), at most `chunk` points) from a device counter
+//                   and write each item's partial sums to its own slot, so
+//                   long and short events are spread evenly over the chip
+//                   and the result does not depend on which workgroup took
+//                   which item.
+//   combine_kernel  sums each event's item partials in item order and writes
+//                   the Fisher matrix, SNR and status.
+// Every step is an ordinary kernel on one stream, so the sequence can be
+// captured in a HIP graph and replayed.
+#include "gwf_batched.hpp"
+#include "gwf_fisher_body.hpp"
+
+namespace gwf {
+
+static_assert(sizeof(EventC) % 8 == 0 && sizeof(SiteC) % 8 == 0, "constants copied as doubles");
+
+__global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void setup_kernel(SetupArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.n) return;
+  const bool tidal = (a.flags & kFlagTidal) != 0;
+  double p[13];
+  for (int r = 0; r < 13; ++r) p[r] = (r < 11 || tidal) ? a.par[r * a.ld + t] : 0.0;
+  EventC ec;
+  event_setup(p, a.fmin[t], a.fmax ? a.fmax[t] : 0.0, a.npts[t], a.flags, ec);
+  if (!ec.status && a.npts[t] != a.npts_plan[t]) ec.status = kEvInvalid;   // grid changed since plan creation
+  a.evc[t] = ec;
+  if (!ec.status)
+    for (int s = 0; s < a.net.n_site; ++s) {
+      SiteC sc;
+      site_setup(p, a.net.site[s], ec, sc);
+      a.sic[t * a.net.n_site + s] = sc;
+    }
+}
+
+template <bool TIDAL, bool ROT>
+__global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void items_kernel(ItemsArgs a) {
+  using Dm = FisherDims<TIDAL>;
+  constexpr int NACC = Dm::NACC;
+  __shared__ EventC ec;
+  __shared__ SiteC sc[kMaxSites];
+  __shared__ FisherLds L;
+  __shared__ int32_t item;
+  const int tid = threadIdx.x;
+  const int n_site = a.n_site;
+  for (;;) {
+    if (tid == 0) item = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int32_t it = item;
+    if (it >= a.n_items) break;                  // every wave leaves on the same item count
+    const Item w = a.items[it];
+    {
+      const double* src = reinterpret_cast<const double*>(a.evc + w.e);
+      double* dst = reinterpret_cast<double*>(&ec);
+      for (int i = tid; i < (int)(sizeof(EventC) / 8); i += kBlock) dst[i] = src[i];
+      const double* ss = reinterpret_cast<const double*>(a.sic + (int64_t)w.e * n_site);
+      double* sd = reinterpret_cast<double*>(sc);
+      for (int i = tid; i < (int)(n_site * sizeof(SiteC) / 8); i += kBlock) sd[i] = ss[i];
+    }
+    __syncthreads();
+    double* out = a.partial + (int64_t)it * NACC;
+    if (ec.status) {
+      if (tid < NACC) out[tid] = 0.0;
+    } else {
+      double t = 0.0;
+      fisher_sums<TIDAL, ROT>(ec, sc, n_site, w.k0, w.k1, L, &t);
+      if (tid < NACC) out[tid] = t;
+    }
+    __syncthreads();                             // LDS is reused by the next item
+  }
+}
+
+template <bool TIDAL>
+__global__ void combine_kernel(CombineArgs a) {
+  using Dm = FisherDims<TIDAL>;
+  constexpr int P = Dm::P, NPI = Dm::NPI, NACC = Dm::NACC;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.n * NACC) return;
+  const int64_t e = t / NACC;
+  const int slot = (int)(t - e * NACC);
+  const int32_t st0 = a.evc[e].status;
+  double s = 0.0;
+  if (!st0)
+    for (int32_t i = a.item_first[e]; i < a.item_first[e + 1]; ++i) s += a.partial[(int64_t)i * NACC + slot];
+  int r, c;
+  slot_position(slot, NPI, r, c);
+  a.fisher[((int64_t)r * P + c) * a.n + e] = s;
+  a.fisher[((int64_t)c * P + r) * a.n + e] = s;
+  if (r == 8 && c == 8) {
+    a.snr[e] = sqrt(s);
+    // status: parameter problems from the set-up, else a non-finite result
+    bool finite_all = true;
+    if (!st0)
+      for (int q = 0; q < NACC; ++q) {
+        double u = 0.0;
+        for (int32_t i = a.item_first[e]; i < a.item_first[e + 1]; ++i) u += a.partial[(int64_t)i * NACC + q];
+        finite_all = finite_all && finite(u);
+      }
+    a.status[e] = st0 ? st0 : (finite_all ? 0 : kEvNonFinite);
+  }
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(setup_kernel, dim3((unsigned)((a.n + 127) / 128)), dim3(128), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_items(const ItemsArgs& a, bool tidal, bool rot, int n_wg, hipStream_t s) {
+  dim3 grid((unsigned)n_wg), block(kBlock);
+  if (tidal && rot) hipLaunchKernelGGL((items_kernel<true, true>), grid, block, 0, s, a);
+  else if (tidal) hipLaunchKernelGGL((items_kernel<true, false>), grid, block, 0, s, a);
+  else if (rot) hipLaunchKernelGGL((items_kernel<false, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((items_kernel<false, false>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const CombineArgs& a, bool tidal, hipStream_t s) {
+  const int nacc = tidal ? FisherDims<true>::NACC : FisherDims<false>::NACC;
+  const int64_t threads = a.n * nacc;
+  dim3 grid((unsigned)((threads + 255) / 256)), block(256);
+  if (tidal) hipLaunchKernelGGL((combine_kernel<true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((combine_kernel<false>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+int fisher_nacc(bool tidal) { return tidal ? FisherDims<true>::NACC : FisherDims<false>::NACC; }
+int fisher_block() { return kBlock; }
+
+}  // namespace gwf

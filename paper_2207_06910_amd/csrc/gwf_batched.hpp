@@ -1,0 +1,52 @@
+// gwf_batched.hpp -- argument blocks and launchers of the batched form.
+#pragma once
+
+#include "gwf_kernels.hpp"
+
+namespace gwf {
+
+struct Item {
+  int32_t e, k0, k1, pad;   // event, grid-point range [k0, k1)
+};
+
+struct SetupArgs {
+  const double* par;
+  int64_t ld, n;
+  const double* fmin;
+  const double* fmax;
+  const int32_t* npts;
+  const int32_t* npts_plan;   // grid lengths the items were built from
+  NetDesc net;
+  uint32_t flags;
+  EventC* evc;                // [n]
+  SiteC* sic;                 // [n][n_site]
+};
+
+struct ItemsArgs {
+  const EventC* evc;
+  const SiteC* sic;
+  int32_t n_site;
+  const Item* items;
+  int32_t n_items;
+  int32_t* counter;           // work-item counter, zeroed before the launch
+  double* partial;            // [n_items][NACC]
+};
+
+struct CombineArgs {
+  int64_t n;
+  const EventC* evc;
+  const int32_t* item_first;  // [n+1]: items of event e are item_first[e] .. item_first[e+1]-1
+  const double* partial;
+  double* fisher;             // [P][P][n]
+  double* snr;                // [n]
+  int32_t* status;            // [n]
+};
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
+hipError_t launch_items(const ItemsArgs& a, bool tidal, bool rot, int n_wg, hipStream_t s);
+hipError_t launch_combine(const CombineArgs& a, bool tidal, hipStream_t s);
+int fisher_nacc(bool tidal);
+int fisher_block();
+
+}  // namespace gwf

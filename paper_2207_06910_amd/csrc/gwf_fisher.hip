@@ -9,6 +9,9 @@
 // LDS reduction produces the event's matrix.  Nothing is atomically added,
 // so results are bitwise reproducible.
 //
+// The accumulation itself (gwf_fisher_body.hpp) is shared with the batched
+// work-item form (gwf_batched.hip).
+//
 // Gram structure exploited (exact algebra, no approximation): the derivative
 // vectors with respect to Phic, chi1, chi2, Lambda1, Lambda2 are i Q c_a(f)
 // with the same real c_a(f) for every interferometer, so their blocks follow
@@ -17,59 +20,26 @@
 //   Gamma_ab += W c_a c_b   (a, b phase-only),   Gamma_ba += U_b c_a,
 // and only the 8x8 block of (Mc, eta, dL, theta, phi, iota, psi, tc) needs a
 // per-interferometer rank-2 update.
-//
-// The 8x8 block (36 doubles) is accumulated in registers.  The phase-only
-// blocks are a small dense contraction over frequency, X = sum_f a_f c_f^T
-// with a_f = (U_0..U_7, W c_0..W c_{NPI-1}) and c_f = (c_0..c_{NPI-1}):
-// every iteration each wavefront stages its 64 points' a_f and c_f in LDS
-// and folds them into a 16x16 FP64 accumulator with 16 MFMA 16x16x4 steps
-// (k = frequency), which keeps those 55 sums out of the lanes' registers.
-#include "gwf_kernels.hpp"
+#include "gwf_fisher_body.hpp"
 
 namespace gwf {
-
-namespace {
-
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
-constexpr int kRowsA = 13;        // 8 U rows + up to 5 W c rows
-constexpr int kRowsB = 5;         // up to 5 c rows
-constexpr int kTileLd = 64 + 2;   // padded row stride (doubles)
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-__device__ inline double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
-}
-
-// Load an event's 13 parameters (missing tidal rows read as zero).
-__device__ inline void load_par(const double* __restrict__ par, int64_t ld, int64_t e, bool tidal,
-                                double p[13]) {
-  for (int r = 0; r < 13; ++r) p[r] = (r < 11 || tidal) ? par[r * ld + e] : 0.0;
-}
-
-}  // namespace
 
 // Declared for 2 x kBlock lanes so that the register budget is that of two
 // wavefronts per SIMD (256 registers); launched with kBlock lanes, two
 // workgroups (45 KB of LDS each) then share a compute unit, which hides the
 // latency of the LDS constant reads and of the transcendental sequences.
+// (The P = 11 instantiation keeps the one-wavefront budget: under the
+// two-wavefront cap it spills.)
 template <bool TIDAL, bool ROT>
 __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(FisherArgs a) {
-  constexpr int P = TIDAL ? 13 : 11;
-  constexpr int NPI = P - 8;                       // phase-only parameters
-  constexpr int NG = 36, NX = 8 * NPI, NY = NPI * (NPI + 1) / 2;
-  constexpr int NACC = NG + NX + NY;               // SNR^2 = Gamma_{Phic,Phic}
+  using Dm = FisherDims<TIDAL>;
+  constexpr int P = Dm::P, NPI = Dm::NPI, NACC = Dm::NACC;
   constexpr uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u);
 
   __shared__ EventC ec;
   __shared__ SiteC sc[kMaxSites];
-  __shared__ double red[kWaves][NACC];
-  __shared__ double stA[kWaves][kRowsA][kTileLd];   // staged a_f, [row][point]
-  __shared__ double stB[kWaves][kRowsB][kTileLd];   // staged c_f
-  __shared__ int32_t skip;
+  __shared__ FisherLds L;
+  __shared__ int32_t skip, bad;
 
   const int64_t e = blockIdx.x;
   const int tid = threadIdx.x;
@@ -81,6 +51,7 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(Fis
     int32_t sk = ec.status;
     if (!sk && a.snr_pre && !(a.snr_pre[e] > a.snr_th)) sk = kEvSkipped;
     skip = sk;
+    bad = 0;
   }
   __syncthreads();
   if (skip) {
@@ -94,81 +65,15 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(Fis
   if (tid < n_site) site_setup(p, a.net.site[tid], ec, sc[tid]);
   __syncthreads();
 
-  double G[NG];
-#pragma unroll
-  for (int i = 0; i < NG; ++i) G[i] = 0.0;
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
-  const int wave = tid >> 6, lane = tid & 63;
-  const int mrow = lane & 15, mk = lane >> 4;      // MFMA operand position of this lane
-  double(*A)[kTileLd] = stA[wave];
-  double(*B)[kTileLd] = stB[wave];
-
-  const int n = ec.n;
-  const int iters = (n + kBlock - 1) / kBlock;    // same trip count for every lane
-  for (int it = 0; it < iters; ++it) {
-    // The per-event constants stay in LDS and are re-read every iteration
-    // (uniform broadcast reads); hoisting them out of the loop would need
-    // more registers than a lane has.
-    __asm__ volatile("" ::: "memory");
-    const int k = it * kBlock + tid;
-    double U[8], W = 0.0, cph[NPI];
-#pragma unroll
-    for (int b = 0; b < 8; ++b) U[b] = 0.0;
-#pragma unroll
-    for (int i = 0; i < NPI; ++i) cph[i] = 0.0;
-    if (k < n) accumulate_point<TIDAL, ROT>(ec, sc, n_site, k, G, U, W, cph);
-    // stage this point's row (points past the grid end contribute zeros)
-#pragma unroll
-    for (int b = 0; b < 8; ++b) A[b][lane] = U[b];
-#pragma unroll
-    for (int i = 0; i < NPI; ++i) {
-      A[8 + i][lane] = W * cph[i];
-      B[i][lane] = cph[i];
-    }
-    __builtin_amdgcn_wave_barrier();
-    // X += A^T B over this wavefront's 64 points: k-step s takes points 16 mk + s
-#pragma unroll
-    for (int s2 = 0; s2 < 16; ++s2) {
-      const double av = mrow < 8 + NPI ? A[mrow][16 * mk + s2] : 0.0;
-      const double bv = mrow < NPI ? B[mrow][16 * mk + s2] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-
-  // ---- deterministic reduction: wavefront butterflies, then the 4 waves in order
-#pragma unroll
-  for (int i = 0; i < NG; ++i) { double t = wave_sum(G[i]); if (lane == 0) red[wave][i] = t; }
-  // register r of lane (mk, mrow) holds accumulator element (4 r + mk, mrow):
-  // rows 0..7 are the U_b rows (cols 0..NPI-1), rows 8..8+NPI-1 the W c_i
-  // rows (upper triangle kept)
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int row = 4 * r + mk, col = mrow;
-    int slot = -1;
-    if (row < 8 && col < NPI) slot = NG + row * NPI + col;
-    else if (row >= 8 && row < 8 + NPI && col >= row - 8 && col < NPI) {
-      const int i = row - 8;
-      slot = NG + NX + i * NPI - (i * (i - 1)) / 2 + (col - i);
-    }
-    if (slot >= 0) red[wave][slot] = acc[r];
-  }
-  __syncthreads();
-  __shared__ int32_t bad;
-  if (tid == 0) bad = 0;
-  __syncthreads();
+  double t = 0.0;
+  fisher_sums<TIDAL, ROT>(ec, sc, n_site, 0, ec.n, L, &t);
   if (tid < NACC) {
-    double t = red[0][tid];
-#pragma unroll
-    for (int w = 1; w < kWaves; ++w) t += red[w][tid];
     if (!isfinite(t)) atomicOr(&bad, 1);
     int r, c;
     slot_position(tid, NPI, r, c);
     if (r == 8 && c == 8) a.snr[e] = sqrt(t);     // Gamma_{Phic,Phic} = SNR^2
-    {
-      a.fisher[((int64_t)r * P + c) * a.n + e] = t;
-      a.fisher[((int64_t)c * P + r) * a.n + e] = t;
-    }
+    a.fisher[((int64_t)r * P + c) * a.n + e] = t;
+    a.fisher[((int64_t)c * P + r) * a.n + e] = t;
   }
   __syncthreads();
   if (tid == 0) a.status[e] = bad ? kEvNonFinite : 0;

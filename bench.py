@@ -79,6 +79,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--chunk", type=int, default=0, help="batched form: fixed item length (0: autotune)")
+    ap.add_argument("--wg-per-cu", type=int, default=0, help="batched form: fixed WGs per CU (0: autotune)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the run, copy MIB MiB device-to-device (a plain copy kernel of "
+                         "known size, for calibrating HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the path shards "
@@ -138,7 +143,7 @@ def main():
         f"status ok {int(np.sum(st == 0))}/{wl.n}")
 
     # ---- batched form: work items, persistent workgroups, one HIP graph per step
-    plan = binding.Plan(dw)                     # autotunes item length and workgroups per CU
+    plan = binding.Plan(dw, chunk=args.chunk, wg_per_cu=args.wg_per_cu)   # 0: autotuned
     info = plan.info()
     outb = {}
     for i in range(args.warmup):
@@ -155,7 +160,9 @@ def main():
     items_ms = float(np.mean(items))
     prof.close()
     sb = outb["status"].cpu().numpy()
-    log(f"batched items kernel {items_ms:.3f} ms, status ok {int(np.sum(sb == 0))}/{wl.n}")
+    n_notpd = int(np.sum((sb & 2) != 0))
+    log(f"batched items kernel {items_ms:.3f} ms, Fisher ok {int(np.sum((sb & ~6) == 0))}/{wl.n}, "
+        f"inverted {int(np.sum(sb == 0))}/{wl.n} (Cholesky failed on {n_notpd})")
 
     flops = algorithmic_flops(wl)
     if batched_ms < plain_ms:
@@ -172,6 +179,15 @@ def main():
         log(f"cpu baseline on {args.cpu_sample} events ...")
         cpu = cpu_baseline(wl, args.cpu_sample)
         log(f"cpu baseline {cpu['value']:.3f} events/s")
+
+    if args.copy_calibration > 0:
+        nd = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(nd, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for i in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {args.copy_calibration} MiB")
 
     value = wl.n / (ms * 1e-3)
     forms = {"plain_fp64": {"events_per_s": round(wl.n / (plain_ms * 1e-3), 1),

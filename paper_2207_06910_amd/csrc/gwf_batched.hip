@@ -8,7 +8,10 @@
 //                   and write each item's partial sums to its own slot, so
 //                   long and short events are spread evenly over the chip
 //                   and the result does not depend on which workgroup took
-//                   which item.
+//                   which item.  The event's constants are read from the
+//                   workspace through the constant address space, i.e. by
+//                   scalar loads into SGPRs, which costs neither LDS traffic
+//                   nor vector registers.
 //   combine_kernel  sums each event's item partials in item order and writes
 //                   the Fisher matrix, SNR and status.
 // Every step is an ordinary kernel on one stream, so the sequence can be
@@ -17,8 +20,6 @@
 #include "gwf_fisher_body.hpp"
 
 namespace gwf {
-
-static_assert(sizeof(EventC) % 8 == 0 && sizeof(SiteC) % 8 == 0, "constants copied as doubles");
 
 __global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -35,6 +36,7 @@ __global__ void setup_kernel(SetupArgs a) {
   event_setup(p, a.fmin[t], a.fmax ? a.fmax[t] : 0.0, a.npts[t], a.flags, ec);
   if (!ec.status && a.npts[t] != a.npts_plan[t]) ec.status = kEvInvalid;   // grid changed since plan creation
   a.evc[t] = ec;
+  a.status[t] = ec.status;
   if (!ec.status)
     for (int s = 0; s < a.net.n_site; ++s) {
       SiteC sc;
@@ -47,8 +49,6 @@ template <bool TIDAL, bool ROT>
 __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void items_kernel(ItemsArgs a) {
   using Dm = FisherDims<TIDAL>;
   constexpr int NACC = Dm::NACC;
-  __shared__ EventC ec;
-  __shared__ SiteC sc[kMaxSites];
   __shared__ FisherLds L;
   __shared__ int32_t item;
   const int tid = threadIdx.x;
@@ -58,22 +58,24 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void items_kernel(Item
     __syncthreads();
     const int32_t it = item;
     if (it >= a.n_items) break;                  // every wave leaves on the same item count
-    const Item w = a.items[it];
-    {
-      const double* src = reinterpret_cast<const double*>(a.evc + w.e);
-      double* dst = reinterpret_cast<double*>(&ec);
-      for (int i = tid; i < (int)(sizeof(EventC) / 8); i += kBlock) dst[i] = src[i];
-      const double* ss = reinterpret_cast<const double*>(a.sic + (int64_t)w.e * n_site);
-      double* sd = reinterpret_cast<double*>(sc);
-      for (int i = tid; i < (int)(n_site * sizeof(SiteC) / 8); i += kBlock) sd[i] = ss[i];
-    }
-    __syncthreads();
+    const Item w = a.items[__builtin_amdgcn_readfirstlane(it)];
+    const int32_t ew = __builtin_amdgcn_readfirstlane(w.e);
+    const int32_t k0 = __builtin_amdgcn_readfirstlane(w.k0);
+    const int32_t k1 = __builtin_amdgcn_readfirstlane(w.k1);
+    // constants read through the constant address space: uniform, never
+    // written during the kernel, so the compiler may use scalar loads
+    typedef const __attribute__((address_space(4))) EventC CEventC;
+    typedef const __attribute__((address_space(4))) SiteC CSiteC;
+    CEventC* ecp = (CEventC*)(a.evc) + ew;
+    CSiteC* scp = (CSiteC*)(a.sic) + (int64_t)ew * n_site;
+    const EventC& ecg = *(const EventC*)ecp;
+    const SiteC* scg = (const SiteC*)scp;
     double* out = a.partial + (int64_t)it * NACC;
-    if (ec.status) {
+    if (ecg.status) {
       if (tid < NACC) out[tid] = 0.0;
     } else {
       double t = 0.0;
-      fisher_sums<TIDAL, ROT>(ec, sc, n_site, w.k0, w.k1, L, &t);
+      fisher_sums<TIDAL, ROT>(ecg, scg, n_site, k0, k1, L, &t);
       if (tid < NACC) out[tid] = t;
     }
     __syncthreads();                             // LDS is reused by the next item
@@ -96,18 +98,9 @@ __global__ void combine_kernel(CombineArgs a) {
   slot_position(slot, NPI, r, c);
   a.fisher[((int64_t)r * P + c) * a.n + e] = s;
   a.fisher[((int64_t)c * P + r) * a.n + e] = s;
-  if (r == 8 && c == 8) {
-    a.snr[e] = sqrt(s);
-    // status: parameter problems from the set-up, else a non-finite result
-    bool finite_all = true;
-    if (!st0)
-      for (int q = 0; q < NACC; ++q) {
-        double u = 0.0;
-        for (int32_t i = a.item_first[e]; i < a.item_first[e + 1]; ++i) u += a.partial[(int64_t)i * NACC + q];
-        finite_all = finite_all && finite(u);
-      }
-    a.status[e] = st0 ? st0 : (finite_all ? 0 : kEvNonFinite);
-  }
+  if (r == 8 && c == 8) a.snr[e] = sqrt(s);
+  // the set-up kernel wrote the parameter status; a non-finite sum adds its bit
+  if (!st0 && !finite(s)) atomicOr(a.status + e, (int32_t)kEvNonFinite);
 }
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {

@@ -20,6 +20,7 @@ struct SetupArgs {
   uint32_t flags;
   EventC* evc;                // [n]
   SiteC* sic;                 // [n][n_site]
+  int32_t* status;            // [n] output: parameter status of each event
 };
 
 struct ItemsArgs {

@@ -21,9 +21,10 @@ namespace gwf {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kRowsA = 13;        // 8 U rows + up to 5 W c rows
-constexpr int kRowsB = 5;         // up to 5 c rows
-constexpr int kTileLd = 64 + 2;   // padded row stride (doubles)
+constexpr int kRowsA = 16;        // 8 U rows, up to 5 W c rows, zero rows up to the MFMA size
+constexpr int kRowsB = 16;        // up to 5 c rows, zero rows up to the MFMA size
+constexpr int kTileLd = 64 + 1;   // odd row stride (doubles): the 64 lanes of an operand
+                                  // read (16 rows x 4 k-groups) fall in distinct banks
 constexpr int kNaccMax = 91;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -72,6 +73,11 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
   const int mrow = lane & 15, mk = lane >> 4;      // MFMA operand position of this lane
   double(*A)[kTileLd] = L.stA[wave];
   double(*B)[kTileLd] = L.stB[wave];
+  // rows no point ever writes stay zero
+#pragma unroll
+  for (int r = 8 + NPI; r < kRowsA; ++r) A[r][lane] = 0.0;
+#pragma unroll
+  for (int r = NPI; r < kRowsB; ++r) B[r][lane] = 0.0;
 
   const int iters = (k1 - k0 + kBlock - 1) / kBlock;   // same trip count for every lane
   for (int it = 0; it < iters; ++it) {
@@ -98,8 +104,8 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
     // X += A^T B over this wavefront's 64 points: k-step s takes points 16 mk + s
 #pragma unroll
     for (int s2 = 0; s2 < 16; ++s2) {
-      const double av = mrow < 8 + NPI ? A[mrow][16 * mk + s2] : 0.0;
-      const double bv = mrow < NPI ? B[mrow][16 * mk + s2] : 0.0;
+      const double av = A[mrow][16 * mk + s2];
+      const double bv = B[mrow][16 * mk + s2];
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
     }
     __builtin_amdgcn_wave_barrier();

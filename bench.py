@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 vector peak
+PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
 
 def log(msg):
@@ -164,6 +165,26 @@ def main():
     log(f"batched items kernel {items_ms:.3f} ms, Fisher ok {int(np.sum((sb & ~6) == 0))}/{wl.n}, "
         f"inverted {int(np.sum(sb == 0))}/{wl.n} (Cholesky failed on {n_notpd})")
 
+    # ---- strain output (gwf_waveform): HBM-bound, 16 B per point and interferometer
+    ends = torch.cumsum(dw.npts.to(torch.int64), 0)
+    offsets = ends - dw.npts.to(torch.int64)
+    total = int(ends[-1].item())
+    outw = {"h": torch.empty((wl.n_ifo, total), dtype=torch.complex128, device="cuda")}
+    for i in range(2):
+        binding.waveform(dw, offsets=offsets, total=total, out=outw)
+    tw = []
+    for i in range(max(3, args.steps // 4)):
+        ev[0].record(stream)
+        binding.waveform(dw, offsets=offsets, total=total, out=outw)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        tw.append(ev[0].elapsed_time(ev[1]))
+    wave_ms = float(np.mean(tw))
+    wave_bytes = 16.0 * wl.n_ifo * total + 8.0 * (13 * wl.n + 3 * wl.n + 1)
+    wave_gbs = wave_bytes / (wave_ms * 1e-3) / 1e9
+    log(f"waveform kernel {wave_ms:.3f} ms, {wave_bytes / 1e9:.2f} GB written, {wave_gbs:.0f} GB/s")
+    del outw
+
     flops = algorithmic_flops(wl)
     if batched_ms < plain_ms:
         form, ms, kname, kms = "batched FP64", batched_ms, "items_kernel<tidal,rot>", items_ms
@@ -196,7 +217,10 @@ def main():
              "batched_fp64": {"events_per_s": round(wl.n / (batched_ms * 1e-3), 1),
                               "ms_per_step": round(batched_ms, 4), "items_ms": round(items_ms, 4),
                               "chunk": info["chunk"], "wg_per_cu": info["wg_per_cu"],
-                              "n_items": info["n_items"], "graph": True}}
+                              "n_items": info["n_items"], "graph": True},
+             "waveform": {"kernel": "waveform_kernel<rot,tidal>", "kernel_ms": round(wave_ms, 4),
+                          "bytes": wave_bytes, "achieved_GBs": round(wave_gbs, 1),
+                          "peak_GBs": PEAK_HBM_GBS, "frac": round(wave_gbs / PEAK_HBM_GBS, 4)}}
     out = {
         "metric": "Fisher events/s (BNS, 3-det, Earth-rot) plain FP64 vs mixed/batched @tol",
         "value": round(value, 1), "unit": "events/s", "n_gpus": 1, "steps": args.steps,

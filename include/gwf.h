@@ -144,6 +144,32 @@ typedef struct gwf_grid {
 
 /* -------------------------------------------------------------- calls */
 
+/* Detector strain h_i(f) of every event at every interferometer (sec. 3.1,
+ * the full strain of the detector class, with the amplitude and phase of
+ * sec. 2.2):
+ *   h_i(f) = A(f) [F+_i (1 + cos^2 iota)/2 + i Fx_i cos iota] exp(i Psi_i)
+ *   Psi_i  = 2 pi f (tc_s + Delta_i) - Phic - pi/4 + Psi_PN(f)
+ * with the patterns F+/Fx and the geocentre delay Delta_i at t(f) under
+ * GWF_EARTH_ROT, on the same log grids as gwf_fisher.  The phase is formed
+ * in cycles and every term is reduced modulo one exactly before sin/cos, so
+ * the result is limited by the FP64 evaluation of Psi_PN (relative error a
+ * few 1e-16 of |Psi_PN|) and by how exactly f itself is known (the 2 pi f
+ * tc_s term moves by 2 pi tc_s df).
+ *   offsets device int64 [n]: event e writes columns offsets[e] ..
+ *           offsets[e] + npts[e] - 1 of every row (packed grids: the
+ *           exclusive prefix sum of npts; gaps between events are allowed
+ *           and left untouched).  An event whose range does not lie in
+ *           [0, total) gets GWF_EV_INVALID_PARAM and writes nothing.  The
+ *           ranges of different events must not overlap (not checked).
+ *   total   points per row, >= 1
+ *   h       device [n_ifo][total][2] (re, im), required; a T site gives
+ *           its three arms in order.  Points of events with a status
+ *           are not written.
+ *   status  device int32 [n] or NULL */
+gwf_status gwf_waveform(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
+                        uint32_t flags, const int64_t* offsets, int64_t total, double* h,
+                        int32_t* status, void* stream);
+
 /* Network SNR (sec. 3.2) of every event.
  *   snr     device [n], required
  *   snr_ifo device [n_ifo][n] or NULL: SNR of each interferometer (a T site

@@ -21,6 +21,7 @@ FLAG_TIDAL = 2
 _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
 _I = ctypes.POINTER(ctypes.c_int32)
+_L = ctypes.POINTER(ctypes.c_int64)
 
 
 def build(force: bool = True) -> str:
@@ -44,6 +45,8 @@ def load():
         lib.orc_delay.restype = ctypes.c_double
         lib.orc_fisher.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_int, _D, _D, _D,
                                    _I, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
+        lib.orc_waveform.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_int, _D, _D, _D,
+                                     _I, ctypes.c_int, ctypes.c_int, _L, ctypes.c_int64, _D]
         lib.orc_strain.argtypes = [_D, ctypes.c_double, ctypes.c_int, _D, ctypes.c_int, _D,
                                    ctypes.c_int, _D, _D]
         lib.orc_strain_cstep.argtypes = [_D, ctypes.c_double, ctypes.c_int, _D, ctypes.c_int, _D,
@@ -194,3 +197,27 @@ def fisher(wl, want_fisher=True, per_ifo=False, nthreads=0):
     if Fi is not None:
         out["fisher_ifo"] = Fi
     return out
+
+
+def waveform(wl, offsets=None, total=None, nthreads=0):
+    """Strain of every event of a workload at every interferometer on its own
+    grid, as complex h[n_ifo][total]; event e fills columns offsets[e] ..
+    offsets[e]+npts[e]-1 (default: packed in event order, total = sum npts)."""
+    par = _f64(wl.par)
+    n = par.shape[1]
+    s = _f64(wl.site_array())
+    ni = n_ifo(s)
+    npts = np.ascontiguousarray(wl.npts, dtype=np.int32)
+    if offsets is None:
+        offsets = np.concatenate([[0], np.cumsum(npts, dtype=np.int64)[:-1]])
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    if total is None:
+        total = int(np.max(offsets + npts))
+    fmin = _f64(wl.fmin)
+    fmax = None if wl.fmax is None else _f64(wl.fmax)
+    tc = None if wl.tc_s is None else _f64(wl.tc_s)
+    h = np.zeros((ni, total, 2))
+    load().orc_waveform(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
+                        npts.ctypes.data_as(_I), wl.flags, int(nthreads),
+                        offsets.ctypes.data_as(_L), int(total), _p(h))
+    return h[..., 0] + 1j * h[..., 1]

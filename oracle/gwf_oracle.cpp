@@ -587,6 +587,35 @@ int orc_strain_plain(const double* par, double tc_s, double dt, int n_site, cons
   return 0;
 }
 
+// Strain of n events at every interferometer on each event's own log grid
+// (the detector strain of sec. 3.1 on the grids of sec. 2.2), written to
+// h[((i * total) + offsets[e] + k) * 2 + {0,1}] for interferometer i, grid
+// point k (offsets[n] are the events' first columns).  fmax NULL means each grid ends at the event's cut frequency.
+int orc_waveform(int64_t n, const double* par, int64_t ld, const double* tc_s, int n_site,
+                 const double* sites, const double* fmin, const double* fmax, const int32_t* npts,
+                 int flags, int nthreads, const int64_t* offsets, int64_t total, double* h) {
+  auto ifos = expand_sites(n_site, sites);
+  const int nifo = (int)ifos.size();
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t e = 0; e < n; ++e) {
+    double p[13];
+    for (int i = 0; i < 13; ++i) p[i] = par[i * ld + e];
+    double fhi = fmax ? fmax[e] : cut_frequency(p[0], p[1]);
+    Source<double> s = make_source<double>(p, tc_s ? tc_s[e] : 0.0);
+    std::vector<double> f, w;
+    make_grid(fmin[e], fhi, npts[e], f, w);
+    for (int d = 0; d < nifo; ++d)
+      for (int k = 0; k < npts[e]; ++k) {
+        double* o = h + ((int64_t)d * total + offsets[e] + k) * 2;
+        strain(s, ifos[d], f[k], flags, o[0], o[1]);
+      }
+  }
+  return 0;
+}
+
 // SNR and Fisher matrices of n events (parameters [13][ld], event fastest).
 // Outputs (any may be NULL except snr):
 //   snr[n]; snr_ifo[n_ifo][n] (SNR of each interferometer);

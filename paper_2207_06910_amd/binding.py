@@ -74,6 +74,9 @@ def load():
         lib.gwf_fisher.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
                                    ctypes.POINTER(Grid), ctypes.c_uint32, d, vp, vp, vp, vp, vp]
         lib.gwf_fisher.restype = i32
+        lib.gwf_waveform.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
+                                     ctypes.POINTER(Grid), ctypes.c_uint32, vp, i64, vp, vp, vp]
+        lib.gwf_waveform.restype = i32
         lib.gwf_invert.argtypes = [i32, i64, vp, d, vp, vp, vp, vp, vp, vp]
         lib.gwf_invert.restype = i32
         lib.gwf_plan_create.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
@@ -197,6 +200,36 @@ def fisher(dw: DeviceWorkload, snr_th=0.0, per_ifo_snr=False, stream=None, out=N
                              float(snr_th), _ptr(res["fisher"]), _ptr(res["snr"]),
                              _ptr(res.get("snr_ifo")), _ptr(res["status"]), _stream(stream)),
            "gwf_fisher")
+    return res
+
+
+def waveform(dw: DeviceWorkload, offsets=None, total=None, stream=None, out=None):
+    """Strain h [n_ifo][total] (complex128 on the device) of every event on
+    its own grid; event e writes columns offsets[e] .. offsets[e]+npts[e]-1
+    (default: the grids packed in event order, total = sum of npts)."""
+    import torch
+    dev = dw.par.device
+    if offsets is None:
+        ends = torch.cumsum(dw.npts.to(torch.int64), 0)
+        offsets = ends - dw.npts.to(torch.int64)
+        if total is None:
+            total = int(ends[-1].item())
+    if not (offsets.is_cuda and offsets.dtype == torch.int64 and offsets.is_contiguous()
+            and offsets.numel() == dw.n):
+        raise GwfError("offsets must be a contiguous int64 device tensor of n entries")
+    if total is None:
+        raise GwfError("total is required with explicit offsets")
+    res = out if out is not None else {}
+    res.setdefault("h", torch.empty((dw.n_ifo, total), dtype=torch.complex128, device=dev))
+    res.setdefault("status", torch.empty(dw.n, dtype=torch.int32, device=dev))
+    h = res["h"]
+    if not (h.is_cuda and h.dtype == torch.complex128 and h.is_contiguous()
+            and tuple(h.shape) == (dw.n_ifo, total)):
+        raise GwfError(f"h must be a contiguous complex128 device tensor of shape ({dw.n_ifo}, {total})")
+    ev, net, grid, keep = dw.descriptors()
+    _check(load().gwf_waveform(ctypes.byref(ev), ctypes.byref(net), ctypes.byref(grid), dw.flags,
+                               _ptr(offsets), int(total), _ptr(h), _ptr(res["status"]),
+                               _stream(stream)), "gwf_waveform")
     return res
 
 

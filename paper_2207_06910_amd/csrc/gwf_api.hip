@@ -141,6 +141,24 @@ gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_gr
   return GWF_OK;
 }
 
+gwf_status gwf_waveform(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
+                        uint32_t flags, const int64_t* offsets, int64_t total, double* h,
+                        int32_t* status, void* stream) {
+  gwf_status st = api_check_common(ev, grid, flags);
+  if (st) return st;
+  if (!offsets || !h) return api_fail(GWF_E_INVALID_ARG, "offsets and h are required");
+  if (total < 1) return api_fail(GWF_E_INVALID_ARG, "total=%lld must be >= 1", (long long)total);
+  gwf::WaveformArgs a{};
+  if ((st = api_pack_network(net, a.net))) return st;
+  a.par = ev->par; a.ld = ev->ld; a.n = ev->n; a.tc_s = ev->tc_s;
+  a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
+  a.offsets = offsets; a.total = total; a.h = h; a.status = status;
+  hipError_t err = gwf::launch_waveform(a, (flags & GWF_TIDAL) != 0, (flags & GWF_EARTH_ROT) != 0,
+                                        (hipStream_t)stream);
+  if (err != hipSuccess) return api_hip_fail(err, "waveform kernel launch");
+  return GWF_OK;
+}
+
 gwf_status gwf_invert(int32_t P, int64_t n, const double* fisher, double cond_max, double* cov,
                       double* sigma, double* cond, double* inv_err, int32_t* status, void* stream) {
   if (P < 1 || P > GWF_NPAR_MAX) return api_fail(GWF_E_INVALID_ARG, "P=%d outside 1..13", P);

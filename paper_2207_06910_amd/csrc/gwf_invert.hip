@@ -11,15 +11,18 @@
 //
 // The working matrix lives in registers (packed upper triangle, all
 // indices compile-time constants after unrolling); a second packed copy per
-// lane lives in LDS as [entry][lane] so that the 64 lanes of a wavefront hit
-// 64 consecutive doubles.
+// lane lives in LDS as [entry][lane], consecutive lanes on consecutive doubles.
 #include "gwf_kernels.hpp"
 
 namespace gwf {
 
 namespace {
 
-constexpr int kInvBlock = 64;
+// 32 lanes per workgroup (a half-filled wavefront): one lane per event is
+// latency-bound, so twice as many waves as with full wavefronts spread the
+// events over more SIMDs (measured on 10^4 13x13 matrices: 32 lanes as
+// fast as 64 or slightly faster, 16 and 128 about 12% slower).
+constexpr int kInvBlock = 32;
 
 template <int P>
 struct Packed {

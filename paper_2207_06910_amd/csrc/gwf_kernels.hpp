@@ -43,8 +43,23 @@ struct InvertArgs {
   int32_t* status;          // [n]
 };
 
+struct WaveformArgs {
+  const double* par;
+  int64_t ld, n;
+  const double* tc_s;       // [n] or NULL
+  const double* fmin;
+  const double* fmax;       // NULL: cut frequency
+  const int32_t* npts;
+  NetDesc net;
+  const int64_t* offsets;   // [n]: event e writes columns [offsets[e], offsets[e] + npts[e])
+  int64_t total;            // points per interferometer row of h
+  double* h;                // [n_ifo][total] complex (re, im)
+  int32_t* status;          // [n] or NULL
+};
+
 hipError_t launch_fisher(const FisherArgs& a, bool tidal, bool rot, hipStream_t stream);
 hipError_t launch_snr(const SnrArgs& a, bool rot, hipStream_t stream);
 hipError_t launch_invert(const InvertArgs& a, int P, hipStream_t stream);
+hipError_t launch_waveform(const WaveformArgs& a, bool tidal, bool rot, hipStream_t stream);
 
 }  // namespace gwf

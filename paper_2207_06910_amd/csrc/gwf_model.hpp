@@ -95,6 +95,10 @@ struct EventC {
   double cplus, ccross, dcplus, dcross;   // (1+cos^2 i)/2, cos i and d/d iota
   PhaseSeries ps[6];
   TauSeries ts[3];
+  // waveform only: Psi_PN / (2 pi) in cycles, ln of the amplitude factor
+  // (A = exp(lnA - 3.5 ln v)), and -(Phic + pi/4)/(2 pi)
+  PhaseSeries cyc;
+  double lnA, cyc0;
 };
 
 struct SiteC {
@@ -348,6 +352,19 @@ __host__ __device__ inline void event_setup(const double* p, double fmin, double
     s.t10 = A * (j == 0 ? c.a10_1 : c.a10_2);
     s.t12 = A * (j == 0 ? c.a12_1 : c.a12_2);
   }
+
+  // Psi_PN itself, in cycles, for the strain output
+  {
+    PhaseSeries& s = ec.cyc;
+    const double K = A / kTwoPi;
+    for (int k = 0; k < 8; ++k) s.c[k] = K * c.a[k];
+    s.l5 = K * c.b5;
+    s.l6 = K * c.b6;
+    s.t10 = K * c.a10;
+    s.t12 = K * c.a12;
+  }
+  ec.lnA = 0.5 * log(0.25 * ec.KA4);
+  ec.cyc0 = -(p[8] + 0.25 * kPi) / kTwoPi;
 
   // ---- rotation: sidereal-angle offset -Omega tau* and its Mc, eta derivatives
   double t[8], te[8], l6;

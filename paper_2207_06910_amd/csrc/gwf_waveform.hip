@@ -1,0 +1,146 @@
+// gwf_waveform.hip -- the strain itself at every interferometer and grid
+// point (the paper's GWstrain, sec. 3.1):
+//   h_i(f) = A(f) [F+_i (1+cos^2 iota)/2 + i Fx_i cos iota] exp(i Psi_i),
+//   Psi_i  = 2 pi f (tc + Delta_i) - Phic - pi/4 + Psi_PN(f),
+// with the patterns and the arrival-time offset Delta_i at t(f) when the
+// Earth rotates.  Unlike SNR and Fisher this needs the phase itself, which
+// reaches ~1e7 rad at a few Hz for neutron-star binaries and 2 pi f tc for
+// GPS-scale tc; the phase is therefore assembled in cycles, each term
+// reduced to its fractional part (f tc from the exact product inside a fused
+// multiply-add), and only the final fraction in [-1/2, 1/2] goes through
+// sin/cos.
+//
+// One workgroup per event, lanes over grid points: each interferometer's
+// output row is written with consecutive lanes on consecutive 16-byte
+// complex values, so the kernel streams its output at HBM rate.
+#include "gwf_kernels.hpp"
+
+namespace gwf {
+
+namespace {
+
+constexpr int kWBlock = 256;
+
+// Per-site constants of the strain loop: rotation to the site's hour angle,
+// the geometry of its E/N vectors, the delay, and for each computed arm the
+// pattern maps with the inclination factors folded in:
+// Re part of the projected amplitude = m[j][0..3] . P, Im part = m[j][4..7] . P.
+struct WaveSite {
+  double cdl, sdl, ct, sl, slct, clst, k1, k0;
+  double m[2][8];
+  int32_t n_arm, pad;
+};
+
+// x reduced to [-1/2, 1/2] by subtracting the nearest integer (exact).
+__device__ inline double frac_center(double x) { return x - rint(x); }
+
+__device__ inline double dot4p(const double* m, const double P[4]) {
+  return fma(m[0], P[0], fma(m[1], P[1], fma(m[2], P[2], m[3] * P[3])));
+}
+
+template <bool ROT, bool TIDAL>
+__global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
+  constexpr uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u);
+  __shared__ EventC ec;
+  __shared__ WaveSite ws[kMaxSites];
+  __shared__ int32_t ok;
+  const int64_t e = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int n_site = a.net.n_site;
+  if (tid == 0) {
+    double p[13];
+    for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
+    event_setup(p, a.fmin[e], a.fmax ? a.fmax[e] : 0.0, a.npts[e], flags, ec);
+    // the event's columns [b, b + npts) must lie inside a row of h
+    const int64_t b = a.offsets[e];
+    const bool range_ok = b >= 0 && b <= a.total - (int64_t)a.npts[e];
+    int32_t st = ec.status;
+    if (!range_ok) st |= kEvInvalid;
+    ok = st == 0;
+    if (a.status) a.status[e] = st;
+  }
+  __syncthreads();
+  if (!ok) return;
+  if (tid < n_site) {
+    double p[13];
+    for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
+    SiteC sc;
+    site_setup(p, a.net.site[tid], ec, sc);
+    WaveSite& w = ws[tid];
+    w.cdl = sc.cdl; w.sdl = sc.sdl; w.ct = sc.ct; w.sl = sc.sl; w.slct = sc.slct; w.clst = sc.clst;
+    w.k1 = sc.k1; w.k0 = sc.k0;
+    for (int j = 0; j < 2; ++j)
+      for (int i = 0; i < 4; ++i) {
+        w.m[j][i] = ec.cplus * sc.arm_alpha[j][i];
+        w.m[j][4 + i] = ec.ccross * sc.arm_beta[j][i];
+      }
+    w.n_arm = sc.n_arm;
+  }
+  __syncthreads();
+
+  const double tc = a.tc_s ? a.tc_s[e] : 0.0;
+  const int64_t base = a.offsets[e];
+  const double amp0 = exp(ec.lnA);
+  double2* __restrict__ out = reinterpret_cast<double2*>(a.h) + base;
+  const int64_t row = a.total;
+  for (int k = tid; k < ec.n; k += kWBlock) {
+    const double L = fma((double)k, ec.dlnv, ec.lnv0);
+    const double v = exp(L);
+    const double iv = 1.0 / v;
+    const double iv2 = iv * iv, iv5 = iv2 * iv2 * iv, v2 = v * v, v5 = v2 * v2 * v;
+    const double f = v2 * v * ec.inv_piM;
+    const double amp = amp0 * iv2 * iv * sqrt(iv);           // A(f) = A0 v^-7/2
+    double cth, sth;
+    {
+      const double th = ROT ? ec.thc + eval_tau(ec.ts[kTsTheta], v, iv5 * iv2 * iv, iv2, L) : ec.thc;
+      sincos_moderate(th, &sth, &cth);
+    }
+    // cycles: Psi_PN/(2 pi) + f tc - (Phic + pi/4)/(2 pi), each reduced
+    // modulo one.  f tc - n with n the integer nearest to the rounded product
+    // is formed by one fused multiply-add from the exact product, so the
+    // reduced fraction carries a single rounding however large f tc is.
+    const double pn = frac_center(eval_phase(ec.cyc, v, iv5, v5, v2, L));
+    const double ftr = fma(f, tc, -rint(f * tc));
+    const double cyc = frac_center(pn + ftr + ec.cyc0);
+    double2* o = out + k;
+    for (int s = 0; s < n_site; ++s) {
+      asm volatile("" ::: "memory");   // site constants stay in LDS rather than occupying registers
+      const WaveSite& w = ws[s];
+      const double cH = cth * w.cdl - sth * w.sdl;
+      const double sH = sth * w.cdl + cth * w.sdl;
+      const double EX = cH, EY = -w.ct * sH, NX = -w.sl * sH, NY = -(w.slct * cH + w.clst);
+      double P[4];
+      P[0] = 0.5 * (EX * EX - NX * NX - EY * EY + NY * NY);
+      P[1] = EX * NX - EY * NY;
+      P[2] = EX * EY - NX * NY;
+      P[3] = EX * NY + NX * EY;
+      double sn, cs;
+      sincos_moderate(kTwoPi * frac_center(fma(f, fma(w.k1, cH, w.k0), cyc)), &sn, &cs);
+      const double ca = amp * cs, sa = amp * sn;
+      const double qr0 = dot4p(w.m[0], P), qi0 = dot4p(w.m[0] + 4, P);
+      const double2 h0 = make_double2(qr0 * ca - qi0 * sa, qr0 * sa + qi0 * ca);
+      *o = h0;
+      o += row;
+      if (w.n_arm == 3) {                 // closed triangle: third arm = -(first + second)
+        const double qr1 = dot4p(w.m[1], P), qi1 = dot4p(w.m[1] + 4, P);
+        const double2 h1 = make_double2(qr1 * ca - qi1 * sa, qr1 * sa + qi1 * ca);
+        o[0] = h1;
+        o[row] = make_double2(-(h0.x + h1.x), -(h0.y + h1.y));
+        o += 2 * row;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_waveform(const WaveformArgs& a, bool tidal, bool rot, hipStream_t stream) {
+  dim3 grid((unsigned)a.n), block(kWBlock);
+  if (tidal && rot) hipLaunchKernelGGL((waveform_kernel<true, true>), grid, block, 0, stream, a);
+  else if (tidal) hipLaunchKernelGGL((waveform_kernel<false, true>), grid, block, 0, stream, a);
+  else if (rot) hipLaunchKernelGGL((waveform_kernel<true, false>), grid, block, 0, stream, a);
+  else hipLaunchKernelGGL((waveform_kernel<false, false>), grid, block, 0, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace gwf

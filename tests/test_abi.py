@@ -61,6 +61,10 @@ def test_invalid_arguments_rejected_on_host():
     for sites in ([s] * 9, [synth.Site(float("nan"), 0, 0, 1, 0)], [synth.Site(0, 0, 0, 1, 0, 0.0)]):
         n2, k2 = binding.network(sites)
         assert lib.gwf_snr(B(ev), B(n2), B(grid), 0, 8, None, None, None) == 1
+    # waveform: missing offsets or h, total < 1
+    assert lib.gwf_waveform(B(ev), B(net), B(grid), 0, None, 10, 8, None, None) == 1
+    assert lib.gwf_waveform(B(ev), B(net), B(grid), 0, 8, 10, None, None, None) == 1
+    assert lib.gwf_waveform(B(ev), B(net), B(grid), 0, 8, 0, 8, None, None) == 1
     # inversion: P out of range, NaN threshold
     assert lib.gwf_invert(14, 3, 8, 1e50, None, 8, None, None, 8, None) == 1
     assert lib.gwf_invert(13, 3, 8, float("nan"), None, 8, None, None, 8, None) == 1

@@ -448,3 +448,39 @@ def test_mpmath_inversion_known_inverse(orc):
     F2 = F.copy(); F2[0, 0] = -F2[0, 0]
     nd = orc.covariance(F2[:, :, None])
     assert nd["status"][0] in (2, 4)
+
+
+# ---------------------------------------------------------------- strain out
+def test_waveform_layout_and_phase_shifts(orc):
+    """The catalogue strain writer: each event's columns hold the strain on
+    that event's own log grid (sec. 2.2), interferometers in expansion order;
+    the noise-weighted sum of |h|^2 reproduces SNR_i^2 (sec. 3.2); a shift
+    of tc by dt multiplies h by exp(2 pi i f dt) and a shift of Phic by dphi
+    by exp(-i dphi), the signs of the phase Psi = 2 pi f tc - Phic - ...;
+    a triangle's three arms sum to zero (closed loop)."""
+    from paper_2207_06910_amd import synth
+    wl = synth.bns1e4(n=3).with_npts(400)
+    h = orc.waveform(wl)
+    off = np.r_[0, np.cumsum(wl.npts)]
+    sites = wl.site_array()
+    snr = orc.fisher(wl, want_fisher=False)["snr_ifo"]
+    ifo_sites = [s for s in wl.sites for _ in range(s.n_ifo)]
+    for e in range(wl.n):
+        p = wl.par[:, e]
+        f, w = orc.grid(wl.fmin[e], orc.cut_frequency(p[0], p[1]), int(wl.npts[e]))
+        ref = orc.strain(p, sites, f, wl.flags, derivs=False)
+        np.testing.assert_array_equal(h[:, off[e]:off[e + 1]], ref)
+        for i, s in enumerate(ifo_sites):
+            S = np.array([orc.psd(s.S0, s.f0, fk) for fk in f])
+            snr2 = 4.0 * np.sum(w * np.abs(h[i, off[e]:off[e + 1]]) ** 2 / S)
+            assert abs(snr2 / snr[i, e] ** 2 - 1) < 1e-12
+    np.testing.assert_allclose(np.abs(h[0] + h[1] + h[2]), 0, atol=1e-14 * np.abs(h[:3]).max())
+    dt, dphi = 0.0123, 0.7
+    wl2 = wl.subset(np.arange(wl.n))
+    wl2.tc_s = np.full(wl.n, dt)
+    wl2.par[8] += dphi
+    h2 = orc.waveform(wl2)
+    fcol = np.concatenate([orc.grid(wl.fmin[e], orc.cut_frequency(*wl.par[:2, e]), int(wl.npts[e]))[0]
+                           for e in range(wl.n)])
+    want = h * np.exp(1j * (2 * np.pi * fcol * dt - dphi))[None, :]
+    np.testing.assert_allclose(h2, want, rtol=0, atol=1e-9 * np.abs(h).max())

@@ -88,7 +88,22 @@ enum {
 enum {
   GWF_EARTH_ROT = 1, /* patterns and arrival-time phase at t(f); otherwise
                         frozen at the coalescence time (sec. 3, footnote)  */
-  GWF_TIDAL = 2      /* 5PN/6PN tidal phase; Fisher has 13 rows instead of 11 */
+  GWF_TIDAL = 2,     /* 5PN/6PN tidal phase; Fisher has 13 rows instead of 11 */
+  GWF_MIXED = 4      /* mixed-precision form, accepted by gwf_plan_create and
+                        gwf_waveform (gwf_snr and gwf_fisher return
+                        GWF_E_UNSUPPORTED).  Plans: the noise weight
+                        4 w A^2 / S_n(f) is evaluated with the PSD shape in
+                        FP32; being a positive factor per grid point, its
+                        relative error e (about 1e-6) moves SNR^2 by at most e
+                        and each sigma_i by at most about e/2 at any condition
+                        number.  Derivatives, sums and the inversion stay FP64
+                        (FP32 products or sums would move the sigmas of
+                        Fisher matrices with condition numbers of 1e10-1e17 by
+                        far more than their size).  gwf_waveform: amplitude
+                        and the sin/cos of the reduced phase in FP32 (the
+                        phase itself, including the hour angle that sets the
+                        arrival-time term, is assembled and reduced in FP64):
+                        strain error below 1e-6 of the point's largest |h|.   */
 };
 
 typedef struct gwf_events {

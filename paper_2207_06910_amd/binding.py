@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libgwf.so")
 
 GWF_OK, GWF_E_INVALID_ARG, GWF_E_UNSUPPORTED, GWF_E_HIP, GWF_E_NOMEM = 0, 1, 2, 3, 4
 EV_INVALID_PARAM, EV_NOT_PD, EV_ILL_COND, EV_NONFINITE, EV_SKIPPED_SNR = 1, 2, 4, 8, 16
-EARTH_ROT, TIDAL = 1, 2
+EARTH_ROT, TIDAL, MIXED = 1, 2, 4
 SHAPE_L, SHAPE_T = 0, 1
 NPAR_MAX = 13
 
@@ -203,10 +203,11 @@ def fisher(dw: DeviceWorkload, snr_th=0.0, per_ifo_snr=False, stream=None, out=N
     return res
 
 
-def waveform(dw: DeviceWorkload, offsets=None, total=None, stream=None, out=None):
+def waveform(dw: DeviceWorkload, offsets=None, total=None, mixed=False, stream=None, out=None):
     """Strain h [n_ifo][total] (complex128 on the device) of every event on
     its own grid; event e writes columns offsets[e] .. offsets[e]+npts[e]-1
-    (default: the grids packed in event order, total = sum of npts)."""
+    (default: the grids packed in event order, total = sum of npts).
+    mixed: FP32 amplitude and sin/cos of the reduced phase."""
     import torch
     dev = dw.par.device
     if offsets is None:
@@ -227,7 +228,8 @@ def waveform(dw: DeviceWorkload, offsets=None, total=None, stream=None, out=None
             and tuple(h.shape) == (dw.n_ifo, total)):
         raise GwfError(f"h must be a contiguous complex128 device tensor of shape ({dw.n_ifo}, {total})")
     ev, net, grid, keep = dw.descriptors()
-    _check(load().gwf_waveform(ctypes.byref(ev), ctypes.byref(net), ctypes.byref(grid), dw.flags,
+    _check(load().gwf_waveform(ctypes.byref(ev), ctypes.byref(net), ctypes.byref(grid),
+                               dw.flags | (MIXED if mixed else 0),
                                _ptr(offsets), int(total), _ptr(h), _ptr(res["status"]),
                                _stream(stream)), "gwf_waveform")
     return res
@@ -261,13 +263,14 @@ class Plan:
     arrays the plan reads at every run."""
 
     def __init__(self, dw: DeviceWorkload, chunk=0, wg_per_cu=0, use_graph=True, profile=False,
-                 stream=None):
+                 mixed=False, stream=None):
         self.dw = dw
         self.handle = ctypes.c_void_p()
         ev, net, grid, keep = dw.descriptors()
         opt = PlanOptions(int(chunk), int(wg_per_cu), 1 if use_graph else 0, 1 if profile else 0)
         _check(load().gwf_plan_create(ctypes.byref(ev), ctypes.byref(net), ctypes.byref(grid),
-                                      dw.flags, ctypes.byref(opt), ctypes.byref(self.handle),
+                                      dw.flags | (MIXED if mixed else 0), ctypes.byref(opt),
+                                      ctypes.byref(self.handle),
                                       _stream(stream)), "gwf_plan_create")
         self.P = 13 if dw.flags & TIDAL else 11
 

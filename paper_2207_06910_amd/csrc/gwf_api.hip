@@ -78,7 +78,7 @@ gwf_status api_check_common(const gwf_events* ev, const gwf_grid* grid, uint32_t
   if (!ev->par) return api_fail(GWF_E_INVALID_ARG, "par is NULL");
   if (grid->kind != GWF_GRID_LOG) return api_fail(GWF_E_UNSUPPORTED, "grid kind %d", grid->kind);
   if (!grid->fmin || !grid->npts) return api_fail(GWF_E_INVALID_ARG, "grid fmin or npts is NULL");
-  if (flags & ~(uint32_t)(GWF_EARTH_ROT | GWF_TIDAL))
+  if (flags & ~(uint32_t)(GWF_EARTH_ROT | GWF_TIDAL | GWF_MIXED))
     return api_fail(GWF_E_INVALID_ARG, "unknown flag bits 0x%x", flags);
   return GWF_OK;
 }
@@ -100,6 +100,7 @@ gwf_status gwf_snr(const gwf_events* ev, const gwf_network* net, const gwf_grid*
   gwf_status st = api_check_common(ev, grid, flags);
   if (st) return st;
   if (!snr) return api_fail(GWF_E_INVALID_ARG, "snr is NULL");
+  if (flags & GWF_MIXED) return api_fail(GWF_E_UNSUPPORTED, "the mixed form runs through a plan");
   gwf::SnrArgs a{};
   if ((st = api_pack_network(net, a.net))) return st;
   a.par = ev->par; a.ld = ev->ld; a.n = ev->n;
@@ -118,6 +119,7 @@ gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_gr
   if (st) return st;
   if (!fisher || !snr || !status) return api_fail(GWF_E_INVALID_ARG, "fisher, snr and status are required");
   if (!std::isfinite(snr_th)) return api_fail(GWF_E_INVALID_ARG, "snr_th is not finite");
+  if (flags & GWF_MIXED) return api_fail(GWF_E_UNSUPPORTED, "the mixed form runs through a plan");
   gwf::FisherArgs a{};
   if ((st = api_pack_network(net, a.net))) return st;
   a.par = ev->par; a.ld = ev->ld; a.n = ev->n;
@@ -154,7 +156,7 @@ gwf_status gwf_waveform(const gwf_events* ev, const gwf_network* net, const gwf_
   a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
   a.offsets = offsets; a.total = total; a.h = h; a.status = status;
   hipError_t err = gwf::launch_waveform(a, (flags & GWF_TIDAL) != 0, (flags & GWF_EARTH_ROT) != 0,
-                                        (hipStream_t)stream);
+                                        (flags & GWF_MIXED) != 0, (hipStream_t)stream);
   if (err != hipSuccess) return api_hip_fail(err, "waveform kernel launch");
   return GWF_OK;
 }

@@ -45,7 +45,7 @@ __global__ void setup_kernel(SetupArgs a) {
     }
 }
 
-template <bool TIDAL, bool ROT>
+template <bool TIDAL, bool ROT, bool MIXED>
 __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void items_kernel(ItemsArgs a) {
   using Dm = FisherDims<TIDAL>;
   constexpr int NACC = Dm::NACC;
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void items_kernel(Item
       if (tid < NACC) out[tid] = 0.0;
     } else {
       double t = 0.0;
-      fisher_sums<TIDAL, ROT>(ecg, scg, n_site, k0, k1, L, &t);
+      fisher_sums<TIDAL, ROT, MIXED>(ecg, scg, n_site, k0, k1, L, &t);
       if (tid < NACC) out[tid] = t;
     }
     __syncthreads();                             // LDS is reused by the next item
@@ -113,12 +113,18 @@ hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_items(const ItemsArgs& a, bool tidal, bool rot, int n_wg, hipStream_t s) {
+template <bool MIXED>
+void launch_items_t(const ItemsArgs& a, bool tidal, bool rot, dim3 grid, dim3 block, hipStream_t s) {
+  if (tidal && rot) hipLaunchKernelGGL((items_kernel<true, true, MIXED>), grid, block, 0, s, a);
+  else if (tidal) hipLaunchKernelGGL((items_kernel<true, false, MIXED>), grid, block, 0, s, a);
+  else if (rot) hipLaunchKernelGGL((items_kernel<false, true, MIXED>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((items_kernel<false, false, MIXED>), grid, block, 0, s, a);
+}
+
+hipError_t launch_items(const ItemsArgs& a, bool tidal, bool rot, bool mixed, int n_wg, hipStream_t s) {
   dim3 grid((unsigned)n_wg), block(kBlock);
-  if (tidal && rot) hipLaunchKernelGGL((items_kernel<true, true>), grid, block, 0, s, a);
-  else if (tidal) hipLaunchKernelGGL((items_kernel<true, false>), grid, block, 0, s, a);
-  else if (rot) hipLaunchKernelGGL((items_kernel<false, true>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((items_kernel<false, false>), grid, block, 0, s, a);
+  if (mixed) launch_items_t<true>(a, tidal, rot, grid, block, s);
+  else launch_items_t<false>(a, tidal, rot, grid, block, s);
   return hipGetLastError();
 }
 

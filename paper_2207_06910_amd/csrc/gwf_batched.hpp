@@ -45,7 +45,7 @@ struct CombineArgs {
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
-hipError_t launch_items(const ItemsArgs& a, bool tidal, bool rot, int n_wg, hipStream_t s);
+hipError_t launch_items(const ItemsArgs& a, bool tidal, bool rot, bool mixed, int n_wg, hipStream_t s);
 hipError_t launch_combine(const CombineArgs& a, bool tidal, hipStream_t s);
 int fisher_nacc(bool tidal);
 int fisher_block();

@@ -60,6 +60,6 @@ struct WaveformArgs {
 hipError_t launch_fisher(const FisherArgs& a, bool tidal, bool rot, hipStream_t stream);
 hipError_t launch_snr(const SnrArgs& a, bool rot, hipStream_t stream);
 hipError_t launch_invert(const InvertArgs& a, int P, hipStream_t stream);
-hipError_t launch_waveform(const WaveformArgs& a, bool tidal, bool rot, hipStream_t stream);
+hipError_t launch_waveform(const WaveformArgs& a, bool tidal, bool rot, bool mixed, hipStream_t stream);
 
 }  // namespace gwf

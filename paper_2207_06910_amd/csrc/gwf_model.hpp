@@ -59,6 +59,7 @@ constexpr int kMaxSites = 8;
 constexpr int kMaxIfo = 16;
 constexpr uint32_t kFlagRot = 1;
 constexpr uint32_t kFlagTidal = 2;
+constexpr uint32_t kFlagMixed = 4;
 
 enum : int32_t { kEvInvalid = 1, kEvNotPD = 2, kEvIllCond = 4, kEvNonFinite = 8, kEvSkipped = 16 };
 
@@ -554,6 +555,30 @@ __host__ __device__ inline void psd_weight(const SiteC& sc, const Point& q, doub
   om = q.w4A2 * sc.S0inv * den / top;
 }
 
+// The same weight with the PSD shape evaluated in FP32 (mixed form).  The
+// weight is a positive factor per grid point, so a relative error e in it
+// keeps the Fisher matrix between (1 - e) Gamma and (1 + e) Gamma in the
+// positive-semidefinite order: SNR^2 moves by at most e and every sigma_i by
+// at most about e/2, whatever the condition number.  Errors in the
+// derivative vectors or in the sums have no such bound, which is why they
+// stay FP64.  x^-4.14 = 2^y with y = -4.14 log2 x formed in FP64 and its
+// integer part split off exactly, so the FP32 exponential sees |r| <= 1/2
+// and the argument's rounding costs below 1e-7; x^2 and x^-2 are FP64
+// products rounded once.
+__host__ __device__ inline void psd_weight_f32(const SiteC& sc, const Point& q, double& om) {
+  const double y = (-4.14 / kLn2) * fma(3.0, q.L, sc.lnx_off);
+  const double n = rint(y);
+  const float xp = ldexpf(exp2f((float)(y - n)), (int)n);
+  const double v3 = q.v * q.v * q.v, iv3 = q.iv * q.iv * q.iv;
+  const double x = sc.x_fac * v3, ix = sc.ix_fac * iv3;
+  const float x2 = (float)(x * x), ix2 = (float)(ix * ix);
+  const float num = fmaf(0.5f * x2, x2, 1.0f - x2);
+  const float den = fmaf(0.5f, x2, 1.0f);
+  const float top = fmaf(fmaf(-5.0f, ix2, xp), den, 111.0f * num);
+  om = q.w4A2 * sc.S0inv * (double)(den / top);
+}
+
+template <bool MIXED = false>
 __host__ __device__ inline void site_point(const SiteC& sc, const Point& q, bool need_derivs,
                                            SitePoint& sp) {
   const double cH = q.cth * sc.cdl - q.sth * sc.sdl;
@@ -563,7 +588,8 @@ __host__ __device__ inline void site_point(const SiteC& sc, const Point& q, bool
   sp.P[1] = EX * NX - EY * NY;
   sp.P[2] = EX * EY - NX * NY;
   sp.P[3] = EX * NY + NX * EY;
-  psd_weight(sc, q, sp.om);
+  if (MIXED) psd_weight_f32(sc, q, sp.om);
+  else psd_weight(sc, q, sp.om);
   if (!need_derivs) return;
   const double EXh = -sH, EYh = -sc.ct * cH, NXh = -sc.sl * cH, NYh = sc.slct * sH;
   sp.PH[0] = EX * EXh - NX * NXh - EY * EYh + NY * NYh;
@@ -594,7 +620,7 @@ __host__ __device__ inline double dot4(const double a[4], const double b[4]) {
 // every interferometer, so the blocks they span are
 //   Gamma_{b, 8+i} += U_b c_i,   Gamma_{8+i, 8+j} += W c_i c_j,
 // which the caller accumulates (see add_phase_blocks).
-template <bool TIDAL, bool ROT>
+template <bool TIDAL, bool ROT, bool MIXED = false>
 __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* sc, int n_site,
                                                  int32_t k, double* G, double* U, double& W,
                                                  double* cph) {
@@ -609,7 +635,7 @@ __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* 
   for (int s = 0; s < n_site; ++s) {
     const SiteC& st = sc[s];
     SitePoint sp;
-    site_point(st, q, true, sp);
+    site_point<MIXED>(st, q, true, sp);
     const double phMc = fma(q.tf * sp.dH, q.gMc, q.pMc);
     const double phEta = fma(q.tf * sp.dH, q.gEta, q.pEta);
     const double phT = q.tf * sp.dT;

@@ -25,7 +25,7 @@ struct gwf_plan {
   uint32_t flags = 0;
   int64_t n = 0;
   int P = 0, nacc = 0, n_cu = 0;
-  bool tidal = false, rot = false;
+  bool tidal = false, rot = false, mixed = false;
   std::vector<int32_t> npts_host;
   // tuning
   int chunk = 0, wg_per_cu = 0, n_items = 0;
@@ -120,7 +120,7 @@ gwf_status enqueue(gwf_plan* p, const Outs& o, hipStream_t s) {
     const int n_wg = std::max(1, std::min(p->n_items, p->n_cu * p->wg_per_cu));
     const bool timed = p->profile && p->ev0;
     if (timed) (void)hipEventRecord(p->ev0, s);
-    err = launch_items(ia, p->tidal, p->rot, n_wg, s);
+    err = launch_items(ia, p->tidal, p->rot, p->mixed, n_wg, s);
     if (timed) (void)hipEventRecord(p->ev1, s);
   }
   if (err == hipSuccess) {
@@ -190,6 +190,7 @@ gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const g
   p->ev = *ev; p->grid = *grid; p->flags = flags; p->n = ev->n;
   p->tidal = (flags & GWF_TIDAL) != 0;
   p->rot = (flags & GWF_EARTH_ROT) != 0;
+  p->mixed = (flags & GWF_MIXED) != 0;
   p->P = p->tidal ? 13 : 11;
   p->nacc = fisher_nacc(p->tidal);
   p->use_graph = o.use_graph != 0;

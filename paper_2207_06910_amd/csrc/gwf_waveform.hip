@@ -38,7 +38,38 @@ __device__ inline double dot4p(const double* m, const double P[4]) {
   return fma(m[0], P[0], fma(m[1], P[1], fma(m[2], P[2], m[3] * P[3])));
 }
 
-template <bool ROT, bool TIDAL>
+// sin and cos of 2 pi x for |x| <= 1/2.  FP64: the series of
+// sincos_moderate.  Mixed form: the quarter-turn q = rint(4x) and the rest
+// r = x - q/4 (exact, |r| <= 1/8) are taken in FP64, then the Taylor series
+// of sin (to the 9th power) and cos (to the 10th) of 2 pi r in FP32, whose
+// truncation errors (< 2e-9, < 2e-10 on |2 pi r| <= pi/4) lie below the
+// FP32 rounding; the absolute error is a few 1e-8 rad from rounding r and
+// about 1e-7 from the FP32 arithmetic.
+template <bool MIXED>
+__device__ inline void sincos_cycles(double x, double* s, double* c) {
+  if (MIXED) {
+    const double q = rint(4.0 * x);
+    const float t = (float)kTwoPi * (float)fma(-0.25, q, x);
+    const float t2 = t * t;
+    float ps = fmaf(t2, 1.0f / 362880.0f, -1.0f / 5040.0f);
+    ps = fmaf(ps, t2, 1.0f / 120.0f);
+    ps = fmaf(ps, t2, -1.0f / 6.0f);
+    const float sr = fmaf(t * t2, ps, t);
+    float pc = fmaf(t2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+    pc = fmaf(pc, t2, -1.0f / 720.0f);
+    pc = fmaf(pc, t2, 1.0f / 24.0f);
+    pc = fmaf(pc, t2, -0.5f);
+    const float cr = fmaf(t2, pc, 1.0f);
+    const int k = (int)q & 3;                  // angle = k quarter turns + t
+    const float ss = (k & 1) ? cr : sr, cc = (k & 1) ? sr : cr;
+    *s = (double)((k & 2) ? -ss : ss);
+    *c = (double)(((k + 1) & 2) ? -cc : cc);
+  } else {
+    sincos_moderate(kTwoPi * x, s, c);
+  }
+}
+
+template <bool ROT, bool TIDAL, bool MIXED>
 __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
   constexpr uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u);
   __shared__ EventC ec;
@@ -89,10 +120,21 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
     const double iv = 1.0 / v;
     const double iv2 = iv * iv, iv5 = iv2 * iv2 * iv, v2 = v * v, v5 = v2 * v2 * v;
     const double f = v2 * v * ec.inv_piM;
-    const double amp = amp0 * iv2 * iv * sqrt(iv);           // A(f) = A0 v^-7/2
+    // A(f) = A0 v^-7/2; mixed form: 2^y, y = -3.5 log2 v, with the integer
+    // part of y split off exactly before the FP32 exponential
+    double amp;
+    if (MIXED) {
+      const double y = (-3.5 / kLn2) * L, n = rint(y);
+      amp = amp0 * (double)ldexpf(exp2f((float)(y - n)), (int)n);
+    } else {
+      amp = amp0 * iv2 * iv * sqrt(iv);
+    }
     double cth, sth;
     {
       const double th = ROT ? ec.thc + eval_tau(ec.ts[kTsTheta], v, iv5 * iv2 * iv, iv2, L) : ec.thc;
+      // FP64 in both forms: the hour angle also sets the arrival-time phase
+      // 2 pi f Delta (tens of cycles at kHz), which an FP32 cos H would move
+      // by ~1e-5 rad
       sincos_moderate(th, &sth, &cth);
     }
     // cycles: Psi_PN/(2 pi) + f tc - (Phic + pi/4)/(2 pi), each reduced
@@ -115,7 +157,7 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
       P[2] = EX * EY - NX * NY;
       P[3] = EX * NY + NX * EY;
       double sn, cs;
-      sincos_moderate(kTwoPi * frac_center(fma(f, fma(w.k1, cH, w.k0), cyc)), &sn, &cs);
+      sincos_cycles<MIXED>(frac_center(fma(f, fma(w.k1, cH, w.k0), cyc)), &sn, &cs);
       const double ca = amp * cs, sa = amp * sn;
       const double qr0 = dot4p(w.m[0], P), qi0 = dot4p(w.m[0] + 4, P);
       const double2 h0 = make_double2(qr0 * ca - qi0 * sa, qr0 * sa + qi0 * ca);
@@ -134,12 +176,19 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
 
 }  // namespace
 
-hipError_t launch_waveform(const WaveformArgs& a, bool tidal, bool rot, hipStream_t stream) {
+template <bool MIXED>
+void launch_waveform_t(const WaveformArgs& a, bool tidal, bool rot, dim3 grid, dim3 block,
+                       hipStream_t stream) {
+  if (tidal && rot) hipLaunchKernelGGL((waveform_kernel<true, true, MIXED>), grid, block, 0, stream, a);
+  else if (tidal) hipLaunchKernelGGL((waveform_kernel<false, true, MIXED>), grid, block, 0, stream, a);
+  else if (rot) hipLaunchKernelGGL((waveform_kernel<true, false, MIXED>), grid, block, 0, stream, a);
+  else hipLaunchKernelGGL((waveform_kernel<false, false, MIXED>), grid, block, 0, stream, a);
+}
+
+hipError_t launch_waveform(const WaveformArgs& a, bool tidal, bool rot, bool mixed, hipStream_t stream) {
   dim3 grid((unsigned)a.n), block(kWBlock);
-  if (tidal && rot) hipLaunchKernelGGL((waveform_kernel<true, true>), grid, block, 0, stream, a);
-  else if (tidal) hipLaunchKernelGGL((waveform_kernel<false, true>), grid, block, 0, stream, a);
-  else if (rot) hipLaunchKernelGGL((waveform_kernel<true, false>), grid, block, 0, stream, a);
-  else hipLaunchKernelGGL((waveform_kernel<false, false>), grid, block, 0, stream, a);
+  if (mixed) launch_waveform_t<true>(a, tidal, rot, grid, block, stream);
+  else launch_waveform_t<false>(a, tidal, rot, grid, block, stream);
   return hipGetLastError();
 }
 

@@ -25,8 +25,9 @@ def load():
     return _lib
 
 
-def fisher(wl):
+def fisher(wl, flags=None):
     lib = load()
+    flags = wl.flags if flags is None else flags
     P = 13 if wl.flags & 2 else 11
     n = wl.n
     par = np.ascontiguousarray(wl.par, dtype=np.float64)
@@ -39,6 +40,6 @@ def fisher(wl):
     st = np.zeros(n, dtype=np.int32)
     P_ = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
     lib.model_fisher_host(ctypes.c_int64(n), P_(par), ctypes.c_int64(n), P_(fmin), P_(fmax), P_(npts),
-                          ctypes.c_int(len(sites)), P_(sites), ctypes.c_uint32(wl.flags), P_(F),
+                          ctypes.c_int(len(sites)), P_(sites), ctypes.c_uint32(flags), P_(F),
                           P_(snr), P_(st))
     return {"fisher": F, "snr": snr, "status": st}

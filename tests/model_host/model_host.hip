@@ -9,7 +9,7 @@
 
 using namespace gwf;
 
-template <bool TIDAL, bool ROT>
+template <bool TIDAL, bool ROT, bool MIXED>
 static void one_event(const double* p, double fmin, double fmax, int32_t n, const NetDesc& nd,
                       double* F, double* snr, int32_t* status) {
   constexpr int P = TIDAL ? 13 : 11, NPI = P - 8, NACC = 36 + 8 * NPI + NPI * (NPI + 1) / 2;
@@ -23,7 +23,7 @@ static void one_event(const double* p, double fmin, double fmax, int32_t n, cons
   double G[36] = {0}, xy[64] = {0};
   for (int32_t k = 0; k < ec.n; ++k) {
     double U[8], W, c[5];
-    accumulate_point<TIDAL, ROT>(ec, sc, nd.n_site, k, G, U, W, c);
+    accumulate_point<TIDAL, ROT, MIXED>(ec, sc, nd.n_site, k, G, U, W, c);
     add_phase_blocks(NPI, U, W, c, xy, 1);
   }
   for (int t = 0; t < NACC; ++t) {
@@ -53,10 +53,17 @@ extern "C" int model_fisher_host(int64_t n, const double* par, int64_t ld, const
     double p[13];
     for (int r = 0; r < 13; ++r) p[r] = par[r * ld + e];
     const double fx = fmax ? fmax[e] : 0.0;
-    if (tidal && rot) one_event<true, true>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
-    else if (tidal) one_event<true, false>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
-    else if (rot) one_event<false, true>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
-    else one_event<false, false>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
+    if (flags & kFlagMixed) {
+      if (tidal && rot) one_event<true, true, true>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
+      else if (tidal) one_event<true, false, true>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
+      else if (rot) one_event<false, true, true>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
+      else one_event<false, false, true>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
+    } else {
+      if (tidal && rot) one_event<true, true, false>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
+      else if (tidal) one_event<true, false, false>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
+      else if (rot) one_event<false, true, false>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
+      else one_event<false, false, false>(p, fmin[e], fx, npts[e], nd, F.data(), snr + e, status + e);
+    }
     for (int i = 0; i < P * P; ++i) fisher[i * n + e] = status[e] ? 0.0 : F[i];
   }
   return 0;

@@ -85,3 +85,55 @@ def test_plan_follows_parameter_updates_and_rejects_grid_changes(lib):
     torch.cuda.synchronize()
     assert c["status"][3] == 1 and np.all(np.delete(c["status"], 3) == 0)
     plan.close()
+
+
+# ----------------------------------------------------------- mixed form
+EPS_W = 1e-6   # relative error of the FP32 noise weight: FP32 exponential of an
+               # argument in [-1/2, 1/2] (a few ulp on the device) and about five
+               # FP32 roundings, ~5e-7, with a factor of two to spare
+
+
+def test_mixed_plan_bounds(lib, orc):
+    """Mixed form (FP32 noise weight, everything else FP64).  A per-point
+    weight error |e_k| <= EPS_W keeps (1 - EPS_W) G <= G' <= (1 + EPS_W) G,
+    hence SNR within EPS_W/2 and |G'_ij - G_ij| <= EPS_W sqrt(G_ii G_jj)
+    (Cauchy-Schwarz), both checked against the oracle; sigma_i (mpmath
+    inversion of the GPU matrices) within 1e-3 of the oracle's on every event
+    whose condition number is below 1e13, where FP64 rounding in the sums
+    moves sigma by less than that."""
+    full = synth.bns1e4()
+    idx = np.unique(np.r_[np.argmin(full.npts), np.argmax(full.npts),
+                          np.random.default_rng(21).choice(full.n, 14, replace=False)])
+    wl = full.subset(idx)
+    dw = lib.DeviceWorkload(wl)
+    pm = lib.Plan(dw, chunk=2048, mixed=True)
+    m = _np(pm.run(invert=True))
+    pm.close()
+    torch.cuda.synchronize()
+    assert np.all(m["status"] & 1 == 0)
+    ref = orc.fisher(wl)
+    np.testing.assert_allclose(m["snr"], ref["snr"], rtol=EPS_W / 2 + 1e-12)
+    e = _ferr(m["fisher"], ref["fisher"])
+    assert e <= EPS_W + 1e-9, e
+    inv = orc.covariance(ref["fisher"], dps=40)
+    invm = orc.covariance(m["fisher"], dps=40)
+    ok = inv["cond"] < 1e13
+    assert ok.sum() >= 5
+    rel = np.abs(invm["sigma"][:, ok] / inv["sigma"][:, ok] - 1)
+    assert rel.max() <= 1e-3, rel.max()
+    print(f"mixed: SNR {np.abs(m['snr'] / ref['snr'] - 1).max():.1e}, Fisher {e:.1e}, "
+          f"sigma (kappa < 1e13, {ok.sum()} events) {rel.max():.1e}")
+
+
+def test_mixed_waveform(lib, orc):
+    """Mixed strain: FP32 amplitude (exponential of a reduced argument) and
+    FP32 sin/cos of the FP64-reduced phases, each accurate to ~1e-7, so the
+    strain stays within 1e-6 of the FP64 kernel's, relative to the point's
+    largest |h| over interferometers."""
+    wl = synth.bns1e4(n=6)
+    dw = lib.DeviceWorkload(wl)
+    h = lib.waveform(dw)["h"].cpu().numpy()
+    hm = lib.waveform(dw, mixed=True)["h"].cpu().numpy()
+    scale = np.abs(h).max(axis=0)
+    err = (np.abs(hm - h) / scale[None, :]).max()
+    assert err <= 1e-6, err

@@ -42,3 +42,17 @@ def test_host_model_invalid_events_flagged():
     wl.par[3, 2] = np.nan       # theta
     a = model_host.fisher(wl)
     assert a["status"][0] == 1 and a["status"][1] == 1 and a["status"][2] == 8 and a["status"][3] == 0
+
+
+def test_host_model_mixed_weight_bound(orc):
+    """Mixed form on the host: only the noise weight is FP32, so SNR^2 and
+    every Fisher element move by at most eps (relative to sqrt(G_ii G_jj)),
+    eps the weight's relative error; here eps = 3e-7 covers the FP32
+    exponential of an argument in [-1/2, 1/2] and a few FP32 roundings."""
+    wl = synth.bns1e4(n=5).with_npts(1500)
+    a = model_host.fisher(wl, flags=wl.flags | 4)
+    b = model_host.fisher(wl)
+    assert np.all(a["status"] == 0)
+    np.testing.assert_allclose(a["snr"] ** 2, b["snr"] ** 2, rtol=3e-7)
+    e = _err(a, b).max()
+    assert 0 < e < 3e-7, e

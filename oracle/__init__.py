@@ -10,11 +10,11 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The GPU library shares no code with
 it and never calls it.
 """
-from .core import (build, load, fisher, waveform, strain, strain_cstep, strain_plain, phase_tau,
+from .core import (build, load, fisher, fisher_tangent, waveform, strain, strain_cstep, strain_plain, phase_tau,
                    phase_dpsi_df_cstep, antenna, delay, cut_frequency, psd, grid, constants,
                    ifos, n_ifo)
 from .invert import covariance
 
-__all__ = ["build", "load", "fisher", "waveform", "strain", "strain_cstep", "strain_plain", "phase_tau",
+__all__ = ["build", "load", "fisher", "fisher_tangent", "waveform", "strain", "strain_cstep", "strain_plain", "phase_tau",
            "phase_dpsi_df_cstep", "antenna", "delay", "cut_frequency", "psd", "grid",
            "constants", "ifos", "n_ifo", "covariance"]

@@ -47,6 +47,9 @@ def load():
                                    _I, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
         lib.orc_waveform.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_int, _D, _D, _D,
                                      _I, ctypes.c_int, ctypes.c_int, _L, ctypes.c_int64, _D]
+        lib.orc_fisher_tangent.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_int, _D,
+                                           _D, _D, _I, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, _D, _D]
         lib.orc_strain.argtypes = [_D, ctypes.c_double, ctypes.c_int, _D, ctypes.c_int, _D,
                                    ctypes.c_int, _D, _D]
         lib.orc_strain_cstep.argtypes = [_D, ctypes.c_double, ctypes.c_int, _D, ctypes.c_int, _D,
@@ -221,3 +224,24 @@ def waveform(wl, offsets=None, total=None, nthreads=0):
                         npts.ctypes.data_as(_I), wl.flags, int(nthreads),
                         offsets.ctypes.data_as(_L), int(total), _p(h))
     return h[..., 0] + 1j * h[..., 1]
+
+
+def fisher_tangent(wl, site, which, nthreads=0):
+    """SNR^2 and Fisher matrices of a workload with their derivatives along
+    one detector parameter (which: 0 latitude, 1 longitude, 2 arm angle,
+    3 ln S0, of site `site`): snr2[2][N], fisher[2][P][P][N], index 0 the
+    value and 1 the derivative."""
+    par = _f64(wl.par)
+    n = par.shape[1]
+    s = _f64(wl.site_array())
+    P = 13 if wl.flags & FLAG_TIDAL else 11
+    fmin = _f64(wl.fmin)
+    fmax = None if wl.fmax is None else _f64(wl.fmax)
+    npts = np.ascontiguousarray(wl.npts, dtype=np.int32)
+    tc = None if wl.tc_s is None else _f64(wl.tc_s)
+    snr2 = np.zeros((2, n))
+    F = np.zeros((2, P, P, n))
+    load().orc_fisher_tangent(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
+                              npts.ctypes.data_as(_I), wl.flags, int(nthreads), int(site),
+                              int(which), _p(snr2), _p(F))
+    return {"snr2": snr2, "fisher": F}

@@ -443,6 +443,46 @@ void fisher_event(const double* par, double tc_s, const std::vector<Ifo<double>>
   }
 }
 
+// Network SNR^2 and Fisher matrix of one event together with their
+// derivatives along one detector parameter: the detector parameters carry a
+// one-component dual number (type D1) inside the P-component dual numbers of
+// the source parameters, so every strain derivative d_i h also carries its
+// own derivative along the detector parameter.  Plain sums of values and of
+// tangents, each compensated.
+using D1 = Dual<double, 1>;
+
+template <int P>
+void fisher_event_tangent(const double* par, double tc_s, const std::vector<Ifo<D1>>& ifos,
+                          double fmin, double fmax, int n, int flags, double* snr2 /* [2] */,
+                          double* F /* [2][P][P] */) {
+  using S = Dual<D1, P>;
+  Source<S> s = make_source<S>(par, tc_s);
+  for (int i = 0; i < P; ++i) slot(s, i).d[i] = D1(1.0);
+  std::vector<double> f, w;
+  make_grid(fmin, fmax, n, f, w);
+  NeumaierSum sv, st;
+  std::vector<NeumaierSum> Gv(P * P), Gt(P * P);
+  for (size_t d = 0; d < ifos.size(); ++d)
+    for (int k = 0; k < n; ++k) {
+      S hre, him;
+      strain(s, ifos[d], f[k], flags, hre, him);
+      D1 om = D1(4.0 * w[k]) / psd(ifos[d].S0, ifos[d].f0, f[k]);
+      D1 a = om * (hre.v * hre.v + him.v * him.v);
+      sv.add(a.v); st.add(a.d[0]);
+      for (int i = 0; i < P; ++i)
+        for (int j = i; j < P; ++j) {
+          D1 g = om * (hre.d[i] * hre.d[j] + him.d[i] * him.d[j]);
+          Gv[i * P + j].add(g.v); Gt[i * P + j].add(g.d[0]);
+        }
+    }
+  snr2[0] = sv.get(); snr2[1] = st.get();
+  for (int i = 0; i < P; ++i)
+    for (int j = i; j < P; ++j) {
+      F[i * P + j] = F[j * P + i] = Gv[i * P + j].get();
+      F[P * P + i * P + j] = F[P * P + j * P + i] = Gt[i * P + j].get();
+    }
+}
+
 void snr_event(const double* par, double tc_s, const std::vector<Ifo<double>>& ifos, double fmin,
                double fmax, int n, int flags, double* snr2_ifo) {
   Source<double> s = make_source<double>(par, tc_s);
@@ -612,6 +652,51 @@ int orc_waveform(int64_t n, const double* par, int64_t ld, const double* tc_s, i
         double* o = h + ((int64_t)d * total + offsets[e] + k) * 2;
         strain(s, ifos[d], f[k], flags, o[0], o[1]);
       }
+  }
+  return 0;
+}
+
+// SNR^2 and Fisher matrix of n events and their derivatives along one
+// detector parameter: parameter `which` (0 latitude, 1 longitude, 2 arm angle
+// gamma, 3 ln S0) of site `site`.  Outputs snr2[2][n] (value, derivative)
+// and fisher[2][P][P][n].
+int orc_fisher_tangent(int64_t n, const double* par, int64_t ld, const double* tc_s, int n_site,
+                       const double* sites, const double* fmin, const double* fmax,
+                       const int32_t* npts, int flags, int nthreads, int site, int which,
+                       double* snr2, double* fisher) {
+  std::vector<Ifo<D1>> ifos;
+  for (int i = 0; i < n_site; ++i) {
+    const double* r = sites + 7 * i;
+    const double seed = (i == site) ? 1.0 : 0.0;
+    for (const Ifo<double>& g : expand_sites(1, r)) {
+      Ifo<D1> t;
+      t.lat = D1(g.lat); t.lon = D1(g.lon); t.gamma = D1(g.gamma); t.zeta = g.zeta;
+      t.S0 = D1(g.S0); t.f0 = g.f0;
+      if (which == 0) t.lat.d[0] = seed;
+      if (which == 1) t.lon.d[0] = seed;
+      if (which == 2) t.gamma.d[0] = seed;
+      if (which == 3) t.S0.d[0] = seed * g.S0;       // dS0 / d ln S0
+      ifos.push_back(t);
+    }
+  }
+  const int P = (flags & FLAG_TIDAL) ? 13 : 11;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t e = 0; e < n; ++e) {
+    double p[13];
+    for (int i = 0; i < 13; ++i) p[i] = par[i * ld + e];
+    double fhi = fmax ? fmax[e] : cut_frequency(p[0], p[1]);
+    double tcs = tc_s ? tc_s[e] : 0.0;
+    double s2[2];
+    std::vector<double> F(2 * P * P);
+    if (P == 13) fisher_event_tangent<13>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2, F.data());
+    else fisher_event_tangent<11>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2, F.data());
+    snr2[e] = s2[0];
+    snr2[n + e] = s2[1];
+    for (int t = 0; t < 2; ++t)
+      for (int a = 0; a < P * P; ++a) fisher[((int64_t)t * P * P + a) * n + e] = F[t * P * P + a];
   }
   return 0;
 }

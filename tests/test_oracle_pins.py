@@ -484,3 +484,59 @@ def test_waveform_layout_and_phase_shifts(orc):
                            for e in range(wl.n)])
     want = h * np.exp(1j * (2 * np.pi * fcol * dt - dphi))[None, :]
     np.testing.assert_allclose(h2, want, rtol=0, atol=1e-9 * np.abs(h).max())
+
+
+# ------------------------------------------- derivatives along detectors
+def _site_shift(wl, s, which, h):
+    import dataclasses
+    out = wl.subset(np.arange(wl.n))
+    site = out.sites[s]
+    name = ("lat", "lon", "gamma")[which]
+    out.sites = list(out.sites)
+    out.sites[s] = dataclasses.replace(site, **{name: getattr(site, name) + h})
+    return out
+
+
+@pytest.mark.parametrize("s,which", [(0, 0), (0, 1), (0, 2), (1, 0), (2, 1), (2, 2)])
+def test_fisher_tangent_against_finite_differences(orc, s, which):
+    """The derivative of SNR^2 and of every Fisher element along a site's
+    latitude, longitude or arm angle (nested dual numbers) against a
+    fourth-order central difference of the plain oracle, triangle and L
+    sites, Earth rotation and tides on."""
+    from paper_2207_06910_amd import synth
+    wl = synth.bns1e4(n=2).with_npts(400)
+    t = orc.fisher_tangent(wl, s, which)
+    h = 1e-4
+    f = {k: orc.fisher(_site_shift(wl, s, which, k * h)) for k in (-2, -1, 1, 2)}
+    fd = lambda key: (8 * (f[1][key] - f[-1][key]) - (f[2][key] - f[-2][key])) / (12 * h)
+    F = t["fisher"][0]
+    d = np.sqrt(np.einsum("iie->ie", F))
+    scale = d[:, None, :] * d[None, :, :]
+    dF = fd("fisher")
+    assert np.abs(t["fisher"][1] - dF).max() / scale.max() < 1e-8
+    assert np.all(np.abs(t["fisher"][1] - dF) <= 1e-7 * scale + 1e-9 * np.abs(dF))
+    snr2 = lambda r: r["snr"] ** 2
+    dS = (8 * (snr2(f[1]) - snr2(f[-1])) - (snr2(f[2]) - snr2(f[-2]))) / (12 * h)
+    np.testing.assert_allclose(t["snr2"][1], dS, rtol=1e-7, atol=1e-9 * t["snr2"][0].max())
+    if wl.sites[s].shape == synth.SHAPE_T and which == 2:
+        # turning a closed triangle in its plane leaves the sum over its three
+        # arms of any product of responses unchanged (three spin-2 responses
+        # 120 degrees apart average to an isotropic one)
+        assert np.abs(t["snr2"][1]).max() < 1e-12 * t["snr2"][0].max()
+        assert np.abs(t["fisher"][1]).max() < 1e-12 * scale.max()
+    else:
+        assert np.abs(t["snr2"][1]).max() > 1e-6 * t["snr2"][0].max()
+
+
+def test_fisher_tangent_psd_scale_closed_form(orc):
+    """Along ln S0 of a site the weight 4 w / S_n scales by exp(-x), so
+    dSNR^2 = -SNR_site^2 and dGamma = -Gamma_site (the site's own
+    interferometers, a triangle's three arms together)."""
+    from paper_2207_06910_amd import synth
+    wl = synth.bns1e4(n=2).with_npts(300)
+    r = orc.fisher(wl, per_ifo=True)
+    for s, arms in ((0, [0, 1, 2]), (1, [3]), (2, [4])):
+        t = orc.fisher_tangent(wl, s, 3)
+        np.testing.assert_allclose(t["snr2"][1], -np.sum(r["snr_ifo"][arms] ** 2, axis=0), rtol=1e-12)
+        Fs = r["fisher_ifo"][arms].sum(axis=0)
+        np.testing.assert_allclose(t["fisher"][1], -Fs, rtol=1e-10, atol=1e-12 * np.abs(Fs).max())

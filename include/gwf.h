@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define GWF_VERSION 1
+#define GWF_VERSION 2
 
 /* ------------------------------------------------------------- statuses */
 typedef int32_t gwf_status;
@@ -211,6 +211,29 @@ gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_gr
                       uint32_t flags, double snr_th, double* fisher, double* snr,
                       double* snr_ifo, int32_t* status, void* stream);
 
+/* Adjoint (reverse mode) of the Fisher/SNR map with respect to the detector
+ * parameters: the gradient of a network figure of merit
+ *   J = sum_e [ w_snr ln SNR_e + w_fisher sum_ij Gbar_e,ij Gamma_e,ij ]
+ * along xi[s] = (latitude, longitude, gamma [rad], ln S0) of every site s,
+ * with Gbar held fixed.  Passing Gbar = Gamma^-1 (the cov output of
+ * gwf_invert) makes the second term the gradient of sum_e ln det Gamma_e;
+ * any other Gbar = dJ/dGamma chains an arbitrary function of the Fisher
+ * matrices.  The strain derivatives are recomputed at every grid point and
+ * contracted on the fly (no Jacobian is stored); the SNR^2 that divides the
+ * first term is recomputed too.  Triangle sites move as one (all three
+ * arms).  Same definitions, grids and flags as gwf_fisher (no GWF_MIXED).
+ *   gbar       device [P][P][n]; only its symmetric part enters
+ *   status     device int32 [n] or NULL: events with a nonzero status (and
+ *              events whose parameters are invalid or whose gbar holds a
+ *              non-finite value) contribute zero
+ *   grad_event device [n][n_site][4], required: each event's terms
+ *   grad       device [n_site][4], required: their sum over events, taken in
+ *              a fixed order (bitwise reproducible) */
+gwf_status gwf_fisher_adjoint(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
+                              uint32_t flags, const double* gbar, const int32_t* status,
+                              double w_snr, double w_fisher, double* grad_event, double* grad,
+                              void* stream);
+
 /* Batched FP64 inversion (sec. 4.1) of n Fisher matrices of size P
  * (1 <= P <= 13) in the [P][P][n] layout: each matrix is normalised by the
  * square root of its diagonal (skipped when a diagonal entry is not > 0),
@@ -221,16 +244,18 @@ gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_gr
  *                                         matrix (ratio of extreme |eigenvalues|,
  *                                         cyclic Jacobi)
  *   inv_err  device [n] or NULL           max_ij |(Gamma Cov - 1)_ij| (sec. 4.1)
+ *   logdet   device [n] or NULL           ln det Gamma from the Cholesky factor of
+ *                                         the normalised matrix and the diagonal
  *   status   device int32 [n], required   bits are OR-ed into what is there
  *                                         (pass the gwf_fisher status through, or
  *                                         zeros)
  *   cond_max matrices with cond > cond_max are not inverted (GWF_EV_ILL_COND);
  *            the paper's default is 1e50.
  * Events with GWF_EV_INVALID_PARAM or GWF_EV_SKIPPED_SNR already set are
- * skipped.  Failed or skipped events get NaN cov/sigma/inv_err. */
+ * skipped.  Failed or skipped events get NaN cov/sigma/inv_err/logdet. */
 gwf_status gwf_invert(int32_t P, int64_t n, const double* fisher, double cond_max,
                       double* cov, double* sigma, double* cond, double* inv_err,
-                      int32_t* status, void* stream);
+                      double* logdet, int32_t* status, void* stream);
 
 /* ------------------------------------------------------ batched form */
 /* A plan runs the Fisher (and optionally the inversion) of one catalogue

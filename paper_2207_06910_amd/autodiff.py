@@ -1,0 +1,88 @@
+"""Differentiable network figure of merit over the detector parameters.
+
+    J(xi) = w_snr * sum_e ln SNR_e + w_logdet * sum_e ln det Gamma_e[A, A]
+
+as a function of xi [n_site, 4] = (latitude, longitude, arm angle gamma,
+ln S0) of every site, for the events whose Fisher matrix (restricted to the
+parameter rows A, all of them by default) inverts.  The forward pass runs
+gwf_fisher and gwf_invert (which returns ln det Gamma and Gamma^-1); the
+backward pass runs the hand-written adjoint gwf_fisher_adjoint with
+Gbar = Gamma^-1 embedded in the full matrix, recomputing the strain
+derivatives at every grid point instead of storing them.  Every per-point
+and per-event step runs in the library's kernels; this module only moves
+tensors and adds the per-event values.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+from . import binding
+
+
+def _sites_at(sites, xi):
+    x = xi.detach().to("cpu", dtype=__import__("torch").float64).numpy()
+    if x.shape != (len(sites), 4):
+        raise binding.GwfError(f"xi must have shape ({len(sites)}, 4)")
+    return [dataclasses.replace(s, lat=float(r[0]), lon=float(r[1]), gamma=float(r[2]),
+                                S0=math.exp(float(r[3]))) for s, r in zip(sites, x)]
+
+
+def site_parameters(dw):
+    """xi [n_site, 4] of a workload's network, float64 on the CPU."""
+    import torch
+    return torch.tensor([[s.lat, s.lon, s.gamma, math.log(s.S0)] for s in dw.sites],
+                        dtype=torch.float64)
+
+
+def _forward(dw, xi, w_snr, w_logdet, rows):
+    import torch
+    dwx = dw.with_sites(_sites_at(dw.sites, xi))
+    r = binding.fisher(dwx)
+    F = r["fisher"]
+    if rows is not None:
+        idx = torch.as_tensor(rows, dtype=torch.long, device=F.device)
+        F = F.index_select(0, idx).index_select(1, idx).contiguous()
+    inv = binding.invert(F, r["status"])
+    ok = inv["status"] == 0
+    J = (w_snr * torch.log(r["snr"][ok]).sum() + w_logdet * inv["logdet"][ok].sum()).to(torch.float64)
+    return dwx, r, inv, ok, J
+
+
+class NetworkFoM(__import__("torch").autograd.Function):
+    """J(xi); see the module docstring.  Use network_fom()."""
+
+    @staticmethod
+    def forward(ctx, xi, dw, w_snr, w_logdet, rows):
+        import torch
+        dwx, r, inv, ok, J = _forward(dw, xi, w_snr, w_logdet, rows)
+        P = r["fisher"].shape[0]
+        gbar = inv["cov"]
+        if rows is not None:
+            full = torch.zeros((P, P, dw.n), dtype=torch.float64, device=gbar.device)
+            idx = torch.as_tensor(rows, dtype=torch.long, device=gbar.device)
+            full[idx.view(-1, 1), idx.view(1, -1)] = gbar
+            gbar = full
+        ctx.dwx, ctx.gbar, ctx.status = dwx, gbar, inv["status"]
+        ctx.w = (float(w_snr), float(w_logdet))
+        ctx.xi_device, ctx.xi_dtype = xi.device, xi.dtype
+        return J.to(device=xi.device, dtype=xi.dtype)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        g = binding.fisher_adjoint(ctx.dwx, ctx.gbar, status=ctx.status, w_snr=ctx.w[0],
+                                   w_fisher=ctx.w[1])["grad"]
+        g = g.to(device=ctx.xi_device, dtype=ctx.xi_dtype)
+        return gJ * g, None, None, None, None
+
+
+def network_fom(xi, dw, w_snr=1.0, w_logdet=1.0, rows=None):
+    """J(xi) as a differentiable scalar (see the module docstring); rows
+    selects the Fisher rows whose ln det enters (None: all)."""
+    return NetworkFoM.apply(xi, dw, float(w_snr), float(w_logdet), None if rows is None else tuple(rows))
+
+
+def network_fom_value(xi, dw, w_snr=1.0, w_logdet=1.0, rows=None):
+    """J(xi) without gradient bookkeeping, and the mask of events that entered."""
+    dwx, r, inv, ok, J = _forward(dw, xi, w_snr, w_logdet, None if rows is None else tuple(rows))
+    return J, ok

@@ -77,8 +77,12 @@ def load():
         lib.gwf_waveform.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
                                      ctypes.POINTER(Grid), ctypes.c_uint32, vp, i64, vp, vp, vp]
         lib.gwf_waveform.restype = i32
-        lib.gwf_invert.argtypes = [i32, i64, vp, d, vp, vp, vp, vp, vp, vp]
+        lib.gwf_invert.argtypes = [i32, i64, vp, d, vp, vp, vp, vp, vp, vp, vp]
         lib.gwf_invert.restype = i32
+        lib.gwf_fisher_adjoint.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
+                                           ctypes.POINTER(Grid), ctypes.c_uint32, vp, vp, d, d,
+                                           vp, vp, vp]
+        lib.gwf_fisher_adjoint.restype = i32
         lib.gwf_plan_create.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
                                         ctypes.POINTER(Grid), ctypes.c_uint32,
                                         ctypes.POINTER(PlanOptions), ctypes.POINTER(vp), vp]
@@ -159,6 +163,15 @@ class DeviceWorkload:
         self.tc_s = None if wl.tc_s is None else torch.as_tensor(
             np.ascontiguousarray(wl.tc_s), dtype=torch.float64, device=device)
         self.n_ifo = n_ifo(self.sites)
+
+    def with_sites(self, sites) -> "DeviceWorkload":
+        """The same device arrays with another network of the same shapes."""
+        import copy
+        if [s.shape for s in sites] != [s.shape for s in self.sites]:
+            raise GwfError("with_sites keeps the network's site shapes")
+        out = copy.copy(self)
+        out.sites = list(sites)
+        return out
 
     def descriptors(self):
         ev = Events(self.n, self.par.shape[1], self.par.data_ptr(),
@@ -249,11 +262,33 @@ def invert(F, status=None, cond_max=1e50, want_cov=True, stream=None, out=None):
     res.setdefault("sigma", torch.empty((P, n), dtype=torch.float64, device=dev))
     res.setdefault("cond", torch.empty(n, dtype=torch.float64, device=dev))
     res.setdefault("inv_err", torch.empty(n, dtype=torch.float64, device=dev))
+    res.setdefault("logdet", torch.empty(n, dtype=torch.float64, device=dev))
     st = status.clone() if status is not None else torch.zeros(n, dtype=torch.int32, device=dev)
     res["status"] = st
     _check(load().gwf_invert(P, n, _ptr(F), float(cond_max), _ptr(res.get("cov")),
-                             _ptr(res["sigma"]), _ptr(res["cond"]), _ptr(res["inv_err"]), _ptr(st),
-                             _stream(stream)), "gwf_invert")
+                             _ptr(res["sigma"]), _ptr(res["cond"]), _ptr(res["inv_err"]),
+                             _ptr(res["logdet"]), _ptr(st), _stream(stream)), "gwf_invert")
+    return res
+
+
+def fisher_adjoint(dw: DeviceWorkload, gbar, status=None, w_snr=1.0, w_fisher=1.0, stream=None,
+                   out=None):
+    """Gradient [n_site][4] of sum_e (w_snr ln SNR_e + w_fisher sum_ij gbar_ij Gamma_ij) along
+    (latitude, longitude, gamma, ln S0) of every site, gbar [P][P][N] held fixed
+    (gbar = Gamma^-1 gives the gradient of sum ln det Gamma); also the per-event
+    terms grad_event [N][n_site][4]."""
+    import torch
+    dev = dw.par.device
+    _dev_f64(gbar)
+    ns = len(dw.sites)
+    res = out if out is not None else {}
+    res.setdefault("grad_event", torch.empty((dw.n, ns, 4), dtype=torch.float64, device=dev))
+    res.setdefault("grad", torch.empty((ns, 4), dtype=torch.float64, device=dev))
+    ev, net, grid, keep = dw.descriptors()
+    _check(load().gwf_fisher_adjoint(ctypes.byref(ev), ctypes.byref(net), ctypes.byref(grid),
+                                     dw.flags, _ptr(gbar), _ptr(status), float(w_snr),
+                                     float(w_fisher), _ptr(res["grad_event"]), _ptr(res["grad"]),
+                                     _stream(stream)), "gwf_fisher_adjoint")
     return res
 
 

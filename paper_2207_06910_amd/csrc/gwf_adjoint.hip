@@ -1,0 +1,131 @@
+// gwf_adjoint.hip -- the adjoint (backward) pass of the Fisher/SNR map with
+// respect to the detector parameters; the per-point mathematics and its
+// derivation are in gwf_adjoint.hpp.
+//
+//   adjoint_kernel  one workgroup per event: the event's constants, its
+//                   symmetrised Gbar and the sites' constants with their
+//                   tangents in LDS; for each site every lane walks the grid
+//                   with a stride of the workgroup size, recomputing the
+//                   derivative vectors and contracting them; the per-site
+//                   sums are reduced over the workgroup in a fixed order and
+//                   combined into the event's gradient terms.
+//   reduce_kernel   one workgroup per output component sums the events'
+//                   terms in a fixed order, so the gradient is bitwise
+//                   reproducible.
+#include "gwf_adjoint.hpp"
+#include "gwf_kernels.hpp"
+
+namespace gwf {
+
+namespace {
+
+constexpr int kABlock = 256;
+
+__device__ inline double wave_sum_a(double x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+template <bool TIDAL, bool ROT>
+__global__ __launch_bounds__(kABlock) void adjoint_kernel(AdjointArgs a) {
+  constexpr int P = TIDAL ? 13 : 11;
+  constexpr uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u);
+  __shared__ EventC ec;
+  __shared__ SiteA sa[kMaxSites];
+  __shared__ double Gb[P * P];
+  __shared__ double red[kABlock / 64][kAdjN];
+  __shared__ double site_acc[kMaxSites][kAdjN];
+  __shared__ int32_t ok;
+  const int64_t e = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int n_site = a.net.n_site;
+  if (tid == 0) {
+    double p[13];
+    for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
+    event_setup(p, a.fmin[e], a.fmax ? a.fmax[e] : 0.0, a.npts[e], flags, ec);
+    ok = ec.status == 0 && (a.status == nullptr || a.status[e] == 0);
+  }
+  __syncthreads();
+  if (tid < P * P) {
+    const int i = tid / P, j = tid - i * P;
+    const double g = 0.5 * (a.gbar[(int64_t)(i * P + j) * a.n + e] + a.gbar[(int64_t)(j * P + i) * a.n + e]);
+    Gb[tid] = g;
+    if (!finite(g)) ok = 0;          // every writer stores the same value
+  }
+  __syncthreads();
+  double* ge = a.grad_event + e * (int64_t)(n_site * 4);
+  if (!ok) {
+    if (tid < n_site * 4) ge[tid] = 0.0;
+    return;
+  }
+  if (tid < n_site) {
+    double p[13];
+    for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
+    site_setup_adj(p, a.net.site[tid], ec, sa[tid]);
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int s = 0; s < n_site; ++s) {
+    double acc[kAdjN];
+#pragma unroll
+    for (int i = 0; i < kAdjN; ++i) acc[i] = 0.0;
+    for (int k = tid; k < ec.n; k += kABlock) {
+      asm volatile("" ::: "memory");   // constants stay in LDS rather than occupying registers
+      adjoint_point<TIDAL, ROT>(ec, sa[s], Gb, k, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < kAdjN; ++i) {
+      const double t = wave_sum_a(acc[i]);
+      if (lane == 0) red[wave][i] = t;
+    }
+    __syncthreads();
+    if (tid < kAdjN) {
+      double t = 0.0;
+      for (int w = 0; w < kABlock / 64; ++w) t += red[w][tid];
+      site_acc[s][tid] = t;
+    }
+    __syncthreads();
+  }
+  if (tid < n_site * 4) {
+    const int s = tid >> 2, m = tid & 3;
+    double W = 0.0;
+    for (int u = 0; u < n_site; ++u) W += site_acc[u][kAdjW];
+    // w_fisher sum Gbar dGamma + w_snr d ln SNR, d ln SNR = dSNR^2 / (2 SNR^2)
+    ge[tid] = fma(a.w_fisher, site_acc[s][kAdjT + m], a.w_snr * site_acc[s][kAdjS + m] / (2.0 * W));
+  }
+}
+
+__global__ __launch_bounds__(kABlock) void reduce_kernel(const double* __restrict__ terms, int64_t n,
+                                                         int width, double* __restrict__ out) {
+  __shared__ double red[kABlock / 64];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  double t = 0.0;
+  for (int64_t e = tid; e < n; e += kABlock) t += terms[e * width + c];
+  t = wave_sum_a(t);
+  if ((tid & 63) == 0) red[tid >> 6] = t;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kABlock / 64; ++w) s += red[w];
+    out[c] = s;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const AdjointArgs& a, bool tidal, bool rot, hipStream_t stream) {
+  dim3 grid((unsigned)a.n), block(kABlock);
+  if (tidal && rot) hipLaunchKernelGGL((adjoint_kernel<true, true>), grid, block, 0, stream, a);
+  else if (tidal) hipLaunchKernelGGL((adjoint_kernel<true, false>), grid, block, 0, stream, a);
+  else if (rot) hipLaunchKernelGGL((adjoint_kernel<false, true>), grid, block, 0, stream, a);
+  else hipLaunchKernelGGL((adjoint_kernel<false, false>), grid, block, 0, stream, a);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const int width = a.net.n_site * 4;
+  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)width), block, 0, stream, a.grad_event, a.n, width,
+                     a.grad);
+  return hipGetLastError();
+}
+
+}  // namespace gwf

@@ -161,15 +161,38 @@ gwf_status gwf_waveform(const gwf_events* ev, const gwf_network* net, const gwf_
   return GWF_OK;
 }
 
+gwf_status gwf_fisher_adjoint(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
+                              uint32_t flags, const double* gbar, const int32_t* status,
+                              double w_snr, double w_fisher, double* grad_event, double* grad,
+                              void* stream) {
+  gwf_status st = api_check_common(ev, grid, flags);
+  if (st) return st;
+  if (flags & GWF_MIXED) return api_fail(GWF_E_UNSUPPORTED, "the adjoint has no mixed form");
+  if (!gbar || !grad_event || !grad) return api_fail(GWF_E_INVALID_ARG, "gbar, grad_event and grad are required");
+  if (!std::isfinite(w_snr) || !std::isfinite(w_fisher))
+    return api_fail(GWF_E_INVALID_ARG, "w_snr and w_fisher must be finite");
+  gwf::AdjointArgs a{};
+  if ((st = api_pack_network(net, a.net))) return st;
+  a.par = ev->par; a.ld = ev->ld; a.n = ev->n;
+  a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
+  a.gbar = gbar; a.status = status; a.w_snr = w_snr; a.w_fisher = w_fisher;
+  a.grad_event = grad_event; a.grad = grad;
+  hipError_t err = gwf::launch_adjoint(a, (flags & GWF_TIDAL) != 0, (flags & GWF_EARTH_ROT) != 0,
+                                       (hipStream_t)stream);
+  if (err != hipSuccess) return api_hip_fail(err, "adjoint kernel launch");
+  return GWF_OK;
+}
+
 gwf_status gwf_invert(int32_t P, int64_t n, const double* fisher, double cond_max, double* cov,
-                      double* sigma, double* cond, double* inv_err, int32_t* status, void* stream) {
+                      double* sigma, double* cond, double* inv_err, double* logdet, int32_t* status,
+                      void* stream) {
   if (P < 1 || P > GWF_NPAR_MAX) return api_fail(GWF_E_INVALID_ARG, "P=%d outside 1..13", P);
   if (n < 1) return api_fail(GWF_E_INVALID_ARG, "n=%lld must be >= 1", (long long)n);
   if (!fisher || !sigma || !status) return api_fail(GWF_E_INVALID_ARG, "fisher, sigma and status are required");
   if (std::isnan(cond_max)) return api_fail(GWF_E_INVALID_ARG, "cond_max is NaN");
   gwf::InvertArgs a{};
   a.n = n; a.fisher = fisher; a.cond_max = cond_max; a.cov = cov; a.sigma = sigma;
-  a.cond = cond; a.inv_err = inv_err; a.status = status;
+  a.cond = cond; a.inv_err = inv_err; a.logdet = logdet; a.status = status;
   hipError_t err = gwf::launch_invert(a, P, (hipStream_t)stream);
   if (err != hipSuccess) return api_hip_fail(err, "invert kernel launch");
   return GWF_OK;

@@ -88,6 +88,7 @@ __global__ __launch_bounds__(kInvBlock) void invert_kernel(InvertArgs a) {
         for (int j = 0; j < P; ++j) a.cov[((int64_t)i * P + j) * a.n + e] = nan;
     }
     if (a.inv_err) a.inv_err[e] = nan;
+    if (a.logdet) a.logdet[e] = nan;
     a.status[e] = st;
   };
   if (st & (kEvInvalid | kEvSkipped)) {
@@ -167,6 +168,14 @@ __global__ __launch_bounds__(kInvBlock) void invert_kernel(InvertArgs a) {
   if (!pd) {
     fail(kEvNotPD);
     return;
+  }
+  // ln det Gamma = sum_i ln Gamma_ii + ln det of the normalised matrix
+  //             = 2 sum_i ln(d_i L_ii)
+  if (a.logdet) {
+    double ld = 0.0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) ld += log(d[i] * A[S::idx(i, i)]);
+    a.logdet[e] = 2.0 * ld;
   }
   // L^-1 in place, row by row, columns ascending
 #pragma unroll

@@ -40,6 +40,7 @@ struct InvertArgs {
   double* sigma;            // [P][n]
   double* cond;             // [n] or NULL
   double* inv_err;          // [n] or NULL
+  double* logdet;           // [n] or NULL
   int32_t* status;          // [n]
 };
 
@@ -57,9 +58,24 @@ struct WaveformArgs {
   int32_t* status;          // [n] or NULL
 };
 
+struct AdjointArgs {
+  const double* par;
+  int64_t ld, n;
+  const double* fmin;
+  const double* fmax;       // NULL: cut frequency
+  const int32_t* npts;
+  NetDesc net;
+  const double* gbar;       // [P][P][n]
+  const int32_t* status;    // [n] or NULL
+  double w_snr, w_fisher;
+  double* grad_event;       // [n][n_site][4]
+  double* grad;             // [n_site][4]
+};
+
 hipError_t launch_fisher(const FisherArgs& a, bool tidal, bool rot, hipStream_t stream);
 hipError_t launch_snr(const SnrArgs& a, bool rot, hipStream_t stream);
 hipError_t launch_invert(const InvertArgs& a, int P, hipStream_t stream);
 hipError_t launch_waveform(const WaveformArgs& a, bool tidal, bool rot, bool mixed, hipStream_t stream);
+hipError_t launch_adjoint(const AdjointArgs& a, bool tidal, bool rot, hipStream_t stream);
 
 }  // namespace gwf

@@ -540,19 +540,24 @@ struct SitePoint {
   double om;          // 4 w A^2 / S_n(f)
 };
 
-__host__ __device__ inline void psd_weight(const SiteC& sc, const Point& q, double& om) {
+__host__ __device__ inline double psd_weight_of(double lnx_off, double ix_fac, double x_fac,
+                                                double S0inv, const Point& q) {
   // S_n = S0 [x^-4.14 - 5 x^-2 + 111 (1 - x^2 + x^4/2)/(1 + x^2/2)], x = f/f0
-  const double lnx = fma(3.0, q.L, sc.lnx_off);
+  const double lnx = fma(3.0, q.L, lnx_off);
   const double xp = exp(-4.14 * lnx);
-  const double ix = sc.ix_fac * q.iv * q.iv * q.iv;   // f0/f
-  const double x = sc.x_fac * q.v * q.v * q.v;        // f/f0
+  const double ix = ix_fac * q.iv * q.iv * q.iv;   // f0/f
+  const double x = x_fac * q.v * q.v * q.v;        // f/f0
   const double ix2 = ix * ix;
   const double x2 = x * x;
   const double num = fma(0.5 * x2, x2, 1.0 - x2);
   const double den = fma(0.5, x2, 1.0);
   // shape = [(x^-4.14 - 5 x^-2) den + 111 num] / den
   const double top = fma(fma(-5.0, ix2, xp), den, 111.0 * num);
-  om = q.w4A2 * sc.S0inv * den / top;
+  return q.w4A2 * S0inv * den / top;
+}
+
+__host__ __device__ inline void psd_weight(const SiteC& sc, const Point& q, double& om) {
+  om = psd_weight_of(sc.lnx_off, sc.ix_fac, sc.x_fac, sc.S0inv, q);
 }
 
 // The same weight with the PSD shape evaluated in FP32 (mixed form).  The

@@ -201,4 +201,75 @@ def bns1e4(n: int = 10000, seed: int = SEEDS["bns1e4"], nmin: int = 2000,
                     FLAG_EARTH_ROT | FLAG_TIDAL, 13, meta={"m1": m1, "m2": m2})
 
 
-WORKLOADS = {"bbh100": bbh100, "bns1e4": bns1e4}
+def _population(rng, n, fractions, bbh_mc):
+    """Masses, spins, deformabilities and distances of a mixed BBH / BNS /
+    NSBH population (kind 0 / 1 / 2 drawn with the given fractions)."""
+    kind = rng.choice(3, n, p=np.asarray(fractions, dtype=np.float64) / np.sum(fractions))
+    par = np.zeros((NPAR_MAX, n))
+    m1, m2 = np.zeros(n), np.zeros(n)
+    b = kind == 0
+    mc = rng.uniform(bbh_mc[0], bbh_mc[1], n)
+    eta = rng.uniform(0.1, 0.25, n)
+    mt = mc * eta ** -0.6
+    d = np.sqrt(np.maximum(1.0 - 4.0 * eta, 0.0))
+    m1[b], m2[b] = 0.5 * mt[b] * (1 + d[b]), 0.5 * mt[b] * (1 - d[b])
+    ns = kind == 1
+    bm1, bm2 = bns_masses(rng, n)
+    m1[ns], m2[ns] = bm1[ns], bm2[ns]
+    nb = kind == 2
+    m1[nb], m2[nb] = rng.uniform(5.0, 20.0, n)[nb], rng.uniform(1.2, 2.0, n)[nb]
+    par[0], par[1] = _masses_to_mc_eta(m1, m2)
+    par[1] = np.minimum(par[1], 0.25)
+    par[2] = np.where(kind == 1, rng.uniform(50.0, 2000.0, n), rng.uniform(100.0, 3000.0, n)) / 1000.0
+    _isotropic(rng, n, par)
+    big = rng.uniform(-0.5, 0.5, (2, n))
+    small = rng.uniform(-0.05, 0.05, (2, n))
+    par[9] = np.where(kind == 1, small[0], big[0])
+    par[10] = np.where(kind == 0, big[1], small[1])
+    lam = rng.uniform(0.0, 2000.0, (2, n))
+    par[11] = np.where(kind == 1, lam[0], 0.0)
+    par[12] = np.where(kind == 0, 0.0, lam[1])
+    return par, kind, m1 + m2
+
+
+def _grid_lengths(mtot, nmin, nmax, m_lo, m_hi):
+    """n = nmin + floor((nmax - nmin) u), u = ln(m_hi / M) / ln(m_hi / m_lo)
+    clipped to [0, 1]: lighter systems, whose grids from the same fmin reach
+    higher cut frequencies, get more points."""
+    u = np.clip(np.log(m_hi / mtot) / np.log(m_hi / m_lo), 0.0, 1.0)
+    return (nmin + np.floor((nmax - nmin) * u)).astype(np.int32)
+
+
+def mixed1e4(n: int = 10000, seed: int = SEEDS["mixed1e4"]) -> Workload:
+    """10^4 events, half BBH (Mc 5-40 Msun, eta 0.1-0.25, spins up to 0.5)
+    and half BNS (as the BNS catalogue), on five L-shaped sites at seeded
+    positions and orientations with their own analytic PSDs; Earth rotation
+    and tidal terms on (13 parameters, Lambda = 0 for black holes); grids
+    from 2 Hz to the cut frequency with 500-20000 points set by the total
+    mass.  The detector-gradient workload."""
+    rng = np.random.default_rng(seed)
+    par, kind, mtot = _population(rng, n, (0.5, 0.5, 0.0), (5.0, 40.0))
+    sites = _random_sites(rng, [SHAPE_L] * 5)
+    npts = _grid_lengths(mtot, 500, 20000, 2.2, 100.0)
+    return Workload("mixed1e4", par, sites, np.full(n, 2.0), npts, None,
+                    FLAG_EARTH_ROT | FLAG_TIDAL, 13, meta={"kind": kind})
+
+
+def catalog1e6(n: int = 1000000, seed: int = SEEDS["catalog1e6"]) -> Workload:
+    """10^6 events: 60% BBH (Mc 5-60 Msun), 35% BNS (m 1.1-2.2 Msun), 5%
+    NSBH (m1 5-20, m2 1.2-2 Msun), on three L-shaped detectors at the
+    Cosmic-Explorer and ET-like sites of Table 2 (CE1Id, CE2NM and the ET
+    Sardinia site, as L) with analytic PSDs; Earth rotation and tides on (13
+    parameters); grids from 2 Hz with 500-20000 points set by the total mass.
+    The batched-catalogue workload (total points exceed 2^31)."""
+    rng = np.random.default_rng(seed)
+    par, kind, mtot = _population(rng, n, (0.60, 0.35, 0.05), (5.0, 60.0))
+    sites = [site("CE1Id", 1e-50, 150.0), site("CE2NM", 1e-50, 150.0), site("ETS", 3e-50, 200.0)]
+    sites[2] = Site(sites[2].lat, sites[2].lon, sites[2].gamma, 90.0 * DEG, SHAPE_L, sites[2].S0,
+                    sites[2].f0)
+    npts = _grid_lengths(mtot, 500, 20000, 2.2, 60.0)
+    return Workload("catalog1e6", par, sites, np.full(n, 2.0), npts, None,
+                    FLAG_EARTH_ROT | FLAG_TIDAL, 13, meta={"kind": kind})
+
+
+WORKLOADS = {"bbh100": bbh100, "bns1e4": bns1e4, "mixed1e4": mixed1e4, "catalog1e6": catalog1e6}

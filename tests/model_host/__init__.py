@@ -8,7 +8,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "model_host.hip")
 LIB = os.path.join(HERE, "libmodel_host.so")
-DEPS = [SRC, os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_model.hpp")]
+DEPS = [SRC, os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_model.hpp"),
+        os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_adjoint.hpp")]
 _lib = None
 
 
@@ -43,3 +44,21 @@ def fisher(wl, flags=None):
                           ctypes.c_int(len(sites)), P_(sites), ctypes.c_uint32(flags), P_(F),
                           P_(snr), P_(st))
     return {"fisher": F, "snr": snr, "status": st}
+
+
+def adjoint(wl, gbar, w_snr=1.0, w_fisher=1.0):
+    """Per-event gradient terms grad_event[N][n_site][4] of the host build."""
+    lib = load()
+    n = wl.n
+    par = np.ascontiguousarray(wl.par, dtype=np.float64)
+    sites = np.ascontiguousarray(wl.site_array())
+    fmin = np.ascontiguousarray(wl.fmin, dtype=np.float64)
+    fmax = None if wl.fmax is None else np.ascontiguousarray(wl.fmax, dtype=np.float64)
+    npts = np.ascontiguousarray(wl.npts, dtype=np.int32)
+    G = np.ascontiguousarray(gbar, dtype=np.float64)
+    out = np.zeros((n, len(sites), 4))
+    P_ = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    lib.model_adjoint_host(ctypes.c_int64(n), P_(par), ctypes.c_int64(n), P_(fmin), P_(fmax), P_(npts),
+                           ctypes.c_int(len(sites)), P_(sites), ctypes.c_uint32(wl.flags), P_(G),
+                           ctypes.c_double(w_snr), ctypes.c_double(w_fisher), P_(out))
+    return out

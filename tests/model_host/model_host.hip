@@ -68,3 +68,57 @@ extern "C" int model_fisher_host(int64_t n, const double* par, int64_t ld, const
   }
   return 0;
 }
+
+// Host build of the adjoint's per-point mathematics (gwf_adjoint.hpp): the
+// per-event gradient terms grad_event[e][s][m] for a given gbar [P][P][n].
+#include "../../paper_2207_06910_amd/csrc/gwf_adjoint.hpp"
+
+template <bool TIDAL, bool ROT>
+static void one_event_adjoint(const double* p, double fmin, double fmax, int32_t n, const NetDesc& nd,
+                              const double* Gb, double w_snr, double w_fisher, double* ge) {
+  const uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u);
+  EventC ec;
+  event_setup(p, fmin, fmax, n, flags, ec);
+  for (int i = 0; i < nd.n_site * 4; ++i) ge[i] = 0.0;
+  if (ec.status) return;
+  double acc[kMaxSites][kAdjN] = {};
+  for (int s = 0; s < nd.n_site; ++s) {
+    SiteA sa;
+    site_setup_adj(p, nd.site[s], ec, sa);
+    for (int32_t k = 0; k < ec.n; ++k) adjoint_point<TIDAL, ROT>(ec, sa, Gb, k, acc[s]);
+  }
+  double W = 0.0;
+  for (int s = 0; s < nd.n_site; ++s) W += acc[s][kAdjW];
+  for (int s = 0; s < nd.n_site; ++s)
+    for (int m = 0; m < 4; ++m)
+      ge[s * 4 + m] = w_fisher * acc[s][kAdjT + m] + w_snr * acc[s][kAdjS + m] / (2.0 * W);
+}
+
+extern "C" int model_adjoint_host(int64_t n, const double* par, int64_t ld, const double* fmin,
+                                  const double* fmax, const int32_t* npts, int n_site,
+                                  const double* sites, uint32_t flags, const double* gbar,
+                                  double w_snr, double w_fisher, double* grad_event) {
+  NetDesc nd{};
+  nd.n_site = n_site;
+  for (int s = 0; s < n_site; ++s) {
+    const double* r = sites + 7 * s;
+    nd.site[s] = SiteDesc{r[0], r[1], r[2], r[3], r[5], r[6], (int32_t)r[4], 0};
+  }
+  const bool tidal = flags & kFlagTidal, rot = flags & kFlagRot;
+  const int P = tidal ? 13 : 11;
+  std::vector<double> G(P * P);
+  for (int64_t e = 0; e < n; ++e) {
+    double p[13];
+    for (int r = 0; r < 13; ++r) p[r] = par[r * ld + e];
+    for (int i = 0; i < P; ++i)
+      for (int j = 0; j < P; ++j)
+        G[i * P + j] = 0.5 * (gbar[(i * P + j) * n + e] + gbar[(j * P + i) * n + e]);
+    const double fx = fmax ? fmax[e] : 0.0;
+    double* ge = grad_event + e * n_site * 4;
+    if (tidal && rot) one_event_adjoint<true, true>(p, fmin[e], fx, npts[e], nd, G.data(), w_snr, w_fisher, ge);
+    else if (tidal) one_event_adjoint<true, false>(p, fmin[e], fx, npts[e], nd, G.data(), w_snr, w_fisher, ge);
+    else if (rot) one_event_adjoint<false, true>(p, fmin[e], fx, npts[e], nd, G.data(), w_snr, w_fisher, ge);
+    else one_event_adjoint<false, false>(p, fmin[e], fx, npts[e], nd, G.data(), w_snr, w_fisher, ge);
+  }
+  return 0;
+}

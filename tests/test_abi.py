@@ -23,7 +23,7 @@ def test_library_exports_every_declared_symbol():
     assert {"gwf_snr", "gwf_fisher", "gwf_invert"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.gwf_version() == 1
+    assert lib.gwf_version() == 2
 
 
 def test_network_interferometer_count():
@@ -66,8 +66,12 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.gwf_waveform(B(ev), B(net), B(grid), 0, 8, 10, None, None, None) == 1
     assert lib.gwf_waveform(B(ev), B(net), B(grid), 0, 8, 0, 8, None, None) == 1
     # inversion: P out of range, NaN threshold
-    assert lib.gwf_invert(14, 3, 8, 1e50, None, 8, None, None, 8, None) == 1
-    assert lib.gwf_invert(13, 3, 8, float("nan"), None, 8, None, None, 8, None) == 1
+    assert lib.gwf_invert(14, 3, 8, 1e50, None, 8, None, None, None, 8, None) == 1
+    assert lib.gwf_invert(13, 3, 8, float("nan"), None, 8, None, None, None, 8, None) == 1
+    # adjoint: missing outputs, non-finite weight, no mixed form
+    assert lib.gwf_fisher_adjoint(B(ev), B(net), B(grid), 0, 8, None, 1.0, 1.0, None, 8, None) == 1
+    assert lib.gwf_fisher_adjoint(B(ev), B(net), B(grid), 0, 8, None, float("inf"), 1.0, 8, 8, None) == 1
+    assert lib.gwf_fisher_adjoint(B(ev), B(net), B(grid), 4, 8, None, 1.0, 1.0, 8, 8, None) == 2
     assert len(lib.gwf_last_error()) > 0
 
 

@@ -1,0 +1,163 @@
+"""GPU: the adjoint of the Fisher/SNR map with respect to the detector
+parameters (gwf_fisher_adjoint) and the differentiable figure of merit built
+on it, against the oracle's nested-dual derivatives and central finite
+differences.
+
+The adjoint returns, per event e and site parameter xi,
+    w_fisher sum_ij Gbar_ij dGamma_ij/dxi + w_snr dSNR^2/dxi / (2 SNR^2),
+a linear function of Gbar.  With a Gbar scaled like an inverse Fisher
+matrix (random symmetric entries / sqrt(G_ii G_jj)) the sum has no
+cancellation and must match the oracle to ~1e-10 of its size.  With
+Gbar = Gamma^-1 the terms cancel by up to the condition number, so that case
+is compared relative to sum_ij |Gbar_ij dGamma_ij|, the size of what is
+summed.
+"""
+import numpy as np
+import pytest
+
+from paper_2207_06910_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2207_06910_amd import binding
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    binding.load()
+    return binding
+
+
+def _tangents(orc, wl):
+    """dGamma [n_site][4][P][P][N], dSNR^2 and SNR^2 [n_site][4][N] from the oracle."""
+    ns = len(wl.sites)
+    out = []
+    for s in range(ns):
+        out.append([orc.fisher_tangent(wl, s, m) for m in range(4)])
+    dF = np.array([[t["fisher"][1] for t in row] for row in out])
+    dS = np.array([[t["snr2"][1] for t in row] for row in out])
+    S = out[0][0]["snr2"][0]
+    return dF, dS, S
+
+
+def _reference(gbar, dF, dS, S, w_snr, w_fisher):
+    Gs = 0.5 * (gbar + gbar.transpose(1, 0, 2))
+    terms = np.einsum("ije,smije->esm", Gs, dF)
+    size = np.einsum("ije,smije->esm", np.abs(Gs), np.abs(dF))
+    ref = w_fisher * terms + w_snr * np.transpose(dS, (2, 0, 1)) / (2 * S[:, None, None])
+    return ref, w_fisher * size + np.abs(w_snr * np.transpose(dS, (2, 0, 1)) / (2 * S[:, None, None]))
+
+
+def _adjoint(lib, wl, gbar, status=None, w_snr=1.0, w_fisher=1.0):
+    dw = lib.DeviceWorkload(wl)
+    g = torch.as_tensor(np.ascontiguousarray(gbar), device="cuda")
+    st = None if status is None else torch.as_tensor(status, dtype=torch.int32, device="cuda")
+    r = lib.fisher_adjoint(dw, g, status=st, w_snr=w_snr, w_fisher=w_fisher)
+    torch.cuda.synchronize()
+    return r["grad_event"].cpu().numpy(), r["grad"].cpu().numpy()
+
+
+@pytest.mark.parametrize("flags", [synth.FLAG_EARTH_ROT | synth.FLAG_TIDAL, synth.FLAG_EARTH_ROT, 0])
+def test_adjoint_random_gbar_against_oracle(lib, orc, flags):
+    """Triangle + 2 L network, grids around the 256-lane stride, every site
+    parameter; and the summed gradient equals the sum of the event terms."""
+    wl = synth.bns1e4(n=4)
+    wl.npts = np.array([257, 600, 1023, 2], dtype=np.int32)
+    wl.flags = flags
+    P = 13 if flags & synth.FLAG_TIDAL else 11
+    F = orc.fisher(wl)["fisher"]
+    d = np.sqrt(np.einsum("iie->ie", F))
+    gbar = np.random.default_rng(9).normal(size=(P, P, wl.n)) / (d[:, None, :] * d[None, :, :])
+    ge, g = _adjoint(lib, wl, gbar, w_snr=0.7, w_fisher=1.3)
+    ref, size = _reference(gbar, *_tangents(orc, wl), 0.7, 1.3)
+    scale = np.abs(ref).max(axis=(1, 2), keepdims=True)
+    err = np.abs(ge - ref) / scale
+    assert err.max() < 1e-10, (err.max(), np.unravel_index(err.argmax(), err.shape))
+    np.testing.assert_allclose(g, ge.sum(axis=0), rtol=1e-12, atol=1e-14 * np.abs(ge).max())
+
+
+def test_adjoint_logdet_gradient_against_oracle(lib, orc):
+    """Gbar = Gamma^-1 (mpmath inverse of the oracle's matrices): the gradient
+    of sum ln det Gamma + sum ln SNR on full 2 Hz grids of the mixed
+    BBH/BNS workload (five L sites), every site parameter."""
+    full = synth.mixed1e4()
+    kind = full.meta["kind"]
+    idx = np.r_[np.flatnonzero(kind == 0)[:2], np.flatnonzero(kind == 1)[:2]]
+    wl = full.subset(idx)
+    ref_f = orc.fisher(wl)
+    inv = orc.covariance(ref_f["fisher"], dps=50)
+    assert np.all(inv["status"] == 0)
+    gbar = inv["cov"]
+    ge, g = _adjoint(lib, wl, gbar)
+    ref, size = _reference(gbar, *_tangents(orc, wl), 1.0, 1.0)
+    err = np.abs(ge - ref) / size
+    assert err.max() < 1e-9, (err.max(), np.unravel_index(err.argmax(), err.shape))
+
+
+def test_adjoint_skips_flagged_events(lib, orc):
+    """Events with a nonzero status, or a non-finite Gbar, contribute zero;
+    the others are unchanged."""
+    wl = synth.bns1e4(n=5).with_npts(300)
+    F = orc.fisher(wl)["fisher"]
+    d = np.sqrt(np.einsum("iie->ie", F))
+    gbar = np.random.default_rng(2).normal(size=(13, 13, wl.n)) / (d[:, None, :] * d[None, :, :])
+    ge0, _ = _adjoint(lib, wl, gbar)
+    gbar2 = gbar.copy()
+    gbar2[3, 5, 4] = np.nan
+    status = np.array([0, 2, 0, 0, 0])
+    ge, g = _adjoint(lib, wl, gbar2, status=status)
+    assert np.all(ge[[1, 4]] == 0)
+    assert np.array_equal(ge[[0, 2, 3]], ge0[[0, 2, 3]])
+    np.testing.assert_allclose(g, ge.sum(axis=0), rtol=1e-12)
+
+
+def test_figure_of_merit_backward_against_finite_differences(lib):
+    """torch.autograd: the backward of J = sum ln SNR + sum ln det of the
+    extrinsic block (dL, theta, phi, iota, psi) of each Fisher matrix against
+    fourth-order central differences of the forward value, all 20 site
+    parameters of the five-site network, 32 events on full grids.  (The
+    block keeps ln det well conditioned; the full-matrix gradient is checked
+    against the oracle above.)"""
+    from paper_2207_06910_amd import autodiff
+    wl = synth.mixed1e4().subset(np.arange(32))
+    dw = lib.DeviceWorkload(wl)
+    rows = (2, 3, 4, 5, 6)
+    xi = autodiff.site_parameters(dw).requires_grad_(True)
+    J = autodiff.network_fom(xi, dw, w_snr=1.0, w_logdet=1.0, rows=rows)
+    J.backward()
+    grad = xi.grad.numpy()
+    J0, ok0 = autodiff.network_fom_value(xi.detach(), dw, rows=rows)
+    assert bool(ok0.all())
+    h = 1e-4
+    fd = np.zeros_like(grad)
+    for s in range(grad.shape[0]):
+        for m in range(4):
+            vals = []
+            for k in (-2, -1, 1, 2):
+                x = xi.detach().clone()
+                x[s, m] += k * h
+                v, ok = autodiff.network_fom_value(x, dw, rows=rows)
+                assert bool(ok.all())
+                vals.append(float(v))
+            fd[s, m] = (8 * (vals[2] - vals[1]) - (vals[3] - vals[0])) / (12 * h)
+    err = np.abs(grad - fd)
+    assert np.all(err <= 1e-6 * np.abs(grad).max() + 1e-5 * np.abs(grad)), (grad, fd)
+
+
+def test_adjoint_full_workload_reproducible(lib):
+    """The whole 10^4-event mixed workload with Gbar = the inversion's
+    Gamma^-1: finite, and bitwise identical on a second run."""
+    wl = synth.mixed1e4()
+    dw = lib.DeviceWorkload(wl)
+    r = lib.fisher(dw)
+    inv = lib.invert(r["fisher"], r["status"])
+    a = lib.fisher_adjoint(dw, inv["cov"], status=inv["status"])
+    ga, gea = a["grad"].clone(), a["grad_event"].clone()
+    b = lib.fisher_adjoint(dw, inv["cov"], status=inv["status"])
+    torch.cuda.synchronize()
+    assert torch.equal(ga, b["grad"]) and torch.equal(gea, b["grad_event"])
+    assert bool(torch.isfinite(ga).all())
+    ok = int((inv["status"] == 0).sum())
+    assert ok > 0.9 * wl.n

@@ -56,3 +56,39 @@ def test_host_model_mixed_weight_bound(orc):
     np.testing.assert_allclose(a["snr"] ** 2, b["snr"] ** 2, rtol=3e-7)
     e = _err(a, b).max()
     assert 0 < e < 3e-7, e
+
+
+def _adjoint_reference(orc, wl, gbar, w_snr, w_fisher):
+    """Oracle: w_fisher sum_ij gbar_ij dGamma_ij + w_snr dSNR^2 / (2 SNR^2)
+    from the nested-dual tangents, for every site and parameter."""
+    ns = len(wl.sites)
+    out = np.zeros((wl.n, ns, 4))
+    Gs = 0.5 * (gbar + gbar.transpose(1, 0, 2))
+    for s in range(ns):
+        for m in range(4):
+            t = orc.fisher_tangent(wl, s, m)
+            out[:, s, m] = (w_fisher * np.einsum("ije,ije->e", Gs, t["fisher"][1])
+                            + w_snr * t["snr2"][1] / (2 * t["snr2"][0]))
+    return out
+
+
+@pytest.mark.parametrize("flags", [synth.FLAG_EARTH_ROT | synth.FLAG_TIDAL, 0])
+def test_host_adjoint_matches_oracle_tangents(orc, flags):
+    """The adjoint's per-point mathematics (reverse-mode weights of the
+    derivative building blocks, forward tangents through the site geometry)
+    against the oracle's nested-dual derivatives, contracted with a random
+    symmetric Gbar scaled like an inverse Fisher matrix, on a triangle + 2 L
+    network; relative to the size of the terms being summed."""
+    wl = synth.bns1e4(n=3).with_npts(500)
+    wl.flags = flags
+    P = 13 if flags & synth.FLAG_TIDAL else 11
+    F = orc.fisher(wl)["fisher"]
+    d = np.sqrt(np.einsum("iie->ie", F))
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=(P, P, wl.n))
+    gbar = X / (d[:, None, :] * d[None, :, :])
+    got = model_host.adjoint(wl, gbar, w_snr=0.7, w_fisher=1.3)
+    want = _adjoint_reference(orc, wl, gbar, 0.7, 1.3)
+    scale = np.abs(want).max(axis=(1, 2), keepdims=True)
+    err = np.abs(got - want) / scale
+    assert err.max() < 1e-10, (err.max(), np.unravel_index(err.argmax(), err.shape))

@@ -26,6 +26,18 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 vector peak
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
+# HBM bytes per launch of each kernel on the BNS catalogue, from the
+# FETCH_SIZE and WRITE_SIZE counter passes summarised in
+# profiles/bns1e4_hbm_counters.md (calibrated against a 256 MiB copy: fetch
+# x 2.000, write x 1.000).  Set an entry to None when its kernel changes.
+MEASURED_TRAFFIC = {
+    "items_kernel<tidal,rot,mixed>": 58.08e6,
+    "items_kernel<tidal,rot>": 57.65e6,
+    "fisher_kernel<tidal,rot>": 103.42e6,
+    "waveform_kernel<rot,tidal>": 7850.02e6,
+    "waveform_kernel<rot,tidal,mixed>": 7857.46e6,
+}
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -96,6 +108,66 @@ def error_report(res, ref) -> dict:
             "events_kappa_lt_1e13": int(ok.sum()), "events": int(len(i))}
 
 
+def gradient_form(binding, synth, torch, args, timed) -> dict:
+    """Forward (Fisher + inversion with ln det) and backward (adjoint) of
+    J = sum ln SNR + sum ln det Gamma over the 10^4-event mixed BBH/BNS
+    workload on five L sites, gradient along the 20 site parameters."""
+    from paper_2207_06910_amd import autodiff
+    wl = synth.mixed1e4()
+    dw = binding.DeviceWorkload(wl)
+    xi = autodiff.site_parameters(dw)
+
+    def step():
+        x = xi.clone().requires_grad_(True)
+        J = autodiff.network_fom(x, dw)
+        J.backward()
+        return x.grad
+
+    for i in range(2):
+        step()
+    ms = timed(step, max(3, args.steps // 4))
+    r = binding.fisher(dw)
+    inv = binding.invert(r["fisher"], r["status"])
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    tb = []
+    for i in range(max(3, args.steps // 4)):
+        ev[0].record()
+        binding.fisher_adjoint(dw, inv["cov"], status=inv["status"])
+        ev[1].record()
+        ev[1].synchronize()
+        tb.append(ev[0].elapsed_time(ev[1]))
+    bwd = float(np.mean(tb))
+    log(f"gradient (mixed1e4): {ms:.3f} ms per forward+backward, adjoint kernels {bwd:.3f} ms")
+    return {"gradient_mixed1e4": {"workload": "mixed1e4: 10^4 events (half BBH, half BNS), five L "
+                                              "sites, 13 parameters, d/d(lat, lon, gamma, ln S0)",
+                                  "grid_points": int(wl.npts.sum()),
+                                  "ms_per_forward_backward": round(ms, 4),
+                                  "adjoint_ms": round(bwd, 4),
+                                  "events_per_s": round(wl.n / (ms * 1e-3), 1)}}
+
+
+def catalogue_form(binding, synth, torch, args, timed, info) -> dict:
+    """The batched FP64 form (same item length and workgroups per CU as on
+    the BNS catalogue) on the 10^6-event BBH/BNS/NSBH catalogue."""
+    wl = synth.catalog1e6()
+    dw = binding.DeviceWorkload(wl)
+    plan = binding.Plan(dw, chunk=info["chunk"], wg_per_cu=info["wg_per_cu"])
+    out = {}
+    plan.run(invert=True, out=out)
+    ms = timed(lambda: plan.run(invert=True, out=out), 3)
+    st = out["status"].cpu().numpy()
+    pinfo = plan.info()
+    plan.close()
+    log(f"catalogue (catalog1e6): {ms:.3f} ms per step, {pinfo['n_items']} items, "
+        f"inverted {int(np.sum(st == 0))}/{wl.n}")
+    return {"batched_fp64_catalog1e6": {
+        "workload": "catalog1e6: 10^6 events (60% BBH, 35% BNS, 5% NSBH), three L sites, 13 "
+                    "parameters, 500-20000 points from 2 Hz",
+        "grid_points": int(wl.npts.sum()), "ms_per_step": round(ms, 3),
+        "events_per_s": round(wl.n / (ms * 1e-3), 1), "n_items": pinfo["n_items"],
+        "inverted": int(np.sum(st == 0)), "ill_conditioned_or_not_pd": int(np.sum((st & 6) != 0))}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +177,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk", type=int, default=0, help="batched form: fixed item length (0: autotune)")
     ap.add_argument("--wg-per-cu", type=int, default=0, help="batched form: fixed WGs per CU (0: autotune)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the detector-gradient and 10^6-event catalogue measurements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device-to-device (a plain copy kernel of "
                          "known size, for calibrating HBM byte counters)")
@@ -221,8 +295,14 @@ def main():
         wave[name] = {"kernel": "waveform_kernel<rot,tidal%s>" % (",mixed" if mixed else ""),
                       "kernel_ms": round(wave_ms, 4), "bytes": wave_bytes,
                       "achieved_GBs": round(wave_gbs, 1), "peak_GBs": PEAK_HBM_GBS,
-                      "frac": round(wave_gbs / PEAK_HBM_GBS, 4)}
+                      "frac": round(wave_gbs / PEAK_HBM_GBS, 4),
+                      "traffic": MEASURED_TRAFFIC.get("waveform_kernel<rot,tidal%s>" % (",mixed" if mixed else ""))}
     del outw
+
+    extra = {}
+    if not args.no_extra:
+        extra.update(gradient_form(binding, synth, torch, args, timed))
+        extra.update(catalogue_form(binding, synth, torch, args, timed, info))
 
     cpu, errs = None, {}
     if not args.no_cpu_baseline:
@@ -265,7 +345,8 @@ def main():
     flops = algorithmic_flops(wl)
     achieved = flops / (kms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                "traffic": MEASURED_TRAFFIC.get(kname),
                 "kernel": kname, "kernel_ms": round(kms, 4), "flops_per_launch": flops}
 
     value = wl.n / (ms * 1e-3)
@@ -283,6 +364,7 @@ def main():
     for k, v in errs.items():
         forms[k]["errors_vs_oracle"] = v
     forms.update(wave)
+    forms.update(extra)
     out = {
         "metric": "Fisher events/s (BNS, 3-det, Earth-rot) plain FP64 vs mixed/batched @tol",
         "value": round(value, 1), "unit": "events/s", "n_gpus": 1, "steps": args.steps,

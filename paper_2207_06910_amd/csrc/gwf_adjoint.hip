@@ -4,11 +4,12 @@
 //
 //   adjoint_kernel  one workgroup per event: the event's constants, its
 //                   symmetrised Gbar and the sites' constants with their
-//                   tangents in LDS; for each site every lane walks the grid
-//                   with a stride of the workgroup size, recomputing the
-//                   derivative vectors and contracting them; the per-site
-//                   sums are reduced over the workgroup in a fixed order and
-//                   combined into the event's gradient terms.
+//                   tangents in LDS; every lane walks the grid with a stride
+//                   of the workgroup size, forms the point quantities once
+//                   and, for each site, recomputes the derivative vectors and
+//                   contracts them into that site's sums, kept per lane in
+//                   LDS; the sums are reduced over the workgroup in a fixed
+//                   order and combined into the event's gradient terms.
 //   reduce_kernel   one workgroup per output component sums the events'
 //                   terms in a fixed order, so the gradient is bitwise
 //                   reproducible.
@@ -19,13 +20,19 @@ namespace gwf {
 
 namespace {
 
-constexpr int kABlock = 256;
+constexpr int kABlock = 128;
+// accumulator slots kept per (site, lane) in LDS: the four Gbar:dGamma terms,
+// the three geometric SNR^2 derivatives and the site's SNR^2 (its ln S0
+// derivative is minus that)
+constexpr int kSlots = 8;
 
 __device__ inline double wave_sum_a(double x) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
   return x;
 }
+
+__device__ inline int slot_of(int i) { return i < 7 ? i : kAdjW; }   // LDS slot -> acc index
 
 template <bool TIDAL, bool ROT>
 __global__ __launch_bounds__(kABlock) void adjoint_kernel(AdjointArgs a) {
@@ -34,8 +41,9 @@ __global__ __launch_bounds__(kABlock) void adjoint_kernel(AdjointArgs a) {
   __shared__ EventC ec;
   __shared__ SiteA sa[kMaxSites];
   __shared__ double Gb[P * P];
-  __shared__ double red[kABlock / 64][kAdjN];
-  __shared__ double site_acc[kMaxSites][kAdjN];
+  __shared__ double accl[kMaxSites][kSlots][kABlock];   // each lane owns column tid
+  __shared__ double red[kABlock / 64][kSlots];
+  __shared__ double site_acc[kMaxSites][kSlots];
   __shared__ int32_t ok;
   const int64_t e = blockIdx.x;
   const int tid = threadIdx.x;
@@ -47,10 +55,10 @@ __global__ __launch_bounds__(kABlock) void adjoint_kernel(AdjointArgs a) {
     ok = ec.status == 0 && (a.status == nullptr || a.status[e] == 0);
   }
   __syncthreads();
-  if (tid < P * P) {
-    const int i = tid / P, j = tid - i * P;
+  for (int t = tid; t < P * P; t += kABlock) {
+    const int i = t / P, j = t - i * P;
     const double g = 0.5 * (a.gbar[(int64_t)(i * P + j) * a.n + e] + a.gbar[(int64_t)(j * P + i) * a.n + e]);
-    Gb[tid] = g;
+    Gb[t] = g;
     if (!finite(g)) ok = 0;          // every writer stores the same value
   }
   __syncthreads();
@@ -64,23 +72,37 @@ __global__ __launch_bounds__(kABlock) void adjoint_kernel(AdjointArgs a) {
     for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
     site_setup_adj(p, a.net.site[tid], ec, sa[tid]);
   }
+  for (int s = 0; s < n_site; ++s)
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) accl[s][i][tid] = 0.0;
   __syncthreads();
+  // every lane walks its grid points once; the point quantities are shared by
+  // all sites, whose sums stay in the lane's own LDS column
+  for (int k = tid; k < ec.n; k += kABlock) {
+    asm volatile("" ::: "memory");   // constants stay in LDS rather than occupying registers
+    AdjPoint ap;
+    adjoint_point_setup<TIDAL, ROT>(ec, Gb, k, ap);
+    for (int s = 0; s < n_site; ++s) {
+      asm volatile("" ::: "memory");
+      double acc[kAdjN];
+#pragma unroll
+      for (int i = 0; i < kAdjN; ++i) acc[i] = 0.0;
+#pragma unroll
+      for (int i = 0; i < kSlots; ++i) acc[slot_of(i)] = accl[s][i][tid];
+      adjoint_site<TIDAL>(ec, sa[s], Gb, ap, acc);
+#pragma unroll
+      for (int i = 0; i < kSlots; ++i) accl[s][i][tid] = acc[slot_of(i)];
+    }
+  }
   const int wave = tid >> 6, lane = tid & 63;
   for (int s = 0; s < n_site; ++s) {
-    double acc[kAdjN];
 #pragma unroll
-    for (int i = 0; i < kAdjN; ++i) acc[i] = 0.0;
-    for (int k = tid; k < ec.n; k += kABlock) {
-      asm volatile("" ::: "memory");   // constants stay in LDS rather than occupying registers
-      adjoint_point<TIDAL, ROT>(ec, sa[s], Gb, k, acc);
-    }
-#pragma unroll
-    for (int i = 0; i < kAdjN; ++i) {
-      const double t = wave_sum_a(acc[i]);
+    for (int i = 0; i < kSlots; ++i) {
+      const double t = wave_sum_a(accl[s][i][tid]);
       if (lane == 0) red[wave][i] = t;
     }
     __syncthreads();
-    if (tid < kAdjN) {
+    if (tid < kSlots) {
       double t = 0.0;
       for (int w = 0; w < kABlock / 64; ++w) t += red[w][tid];
       site_acc[s][tid] = t;
@@ -90,9 +112,11 @@ __global__ __launch_bounds__(kABlock) void adjoint_kernel(AdjointArgs a) {
   if (tid < n_site * 4) {
     const int s = tid >> 2, m = tid & 3;
     double W = 0.0;
-    for (int u = 0; u < n_site; ++u) W += site_acc[u][kAdjW];
+    for (int u = 0; u < n_site; ++u) W += site_acc[u][7];
+    // d SNR^2 along ln S0 of a site is minus that site's SNR^2
+    const double dS = m < 3 ? site_acc[s][4 + m] : -site_acc[s][7];
     // w_fisher sum Gbar dGamma + w_snr d ln SNR, d ln SNR = dSNR^2 / (2 SNR^2)
-    ge[tid] = fma(a.w_fisher, site_acc[s][kAdjT + m], a.w_snr * site_acc[s][kAdjS + m] / (2.0 * W));
+    ge[tid] = fma(a.w_fisher, site_acc[s][m], a.w_snr * dS / (2.0 * W));
   }
 }
 

@@ -61,7 +61,7 @@ __host__ __device__ inline T3 dot4t(const T3 a[4], const T3 b[4]) {
 struct SiteA {
   T3 cdl, sdl, sl, cl, slct, clst, k1, k0, k1t, k0t;
   T3 alpha[2][4], beta[2][4];
-  double ct, st, lnx_off, ix_fac, x_fac, S0inv, weff[2];
+  double ct, st, xp_fac, ix_fac, x_fac, S0inv, weff[2];
   int32_t n_eff, pad;
 };
 
@@ -101,7 +101,7 @@ __host__ __device__ inline void site_setup_adj(const double* p, const SiteDesc& 
   sa.k0 = (-kREarthS * ct) * tsl;
   sa.k1t = (-kREarthS * ct) * tcl;
   sa.k0t = (kREarthS * st) * tsl;
-  sa.lnx_off = -log(ec.piM) - log(sd.f0);
+  sa.xp_fac = exp(4.14 * (log(ec.piM) + log(sd.f0)));
   sa.ix_fac = sd.f0 * ec.piM;
   sa.x_fac = 1.0 / sa.ix_fac;
   sa.S0inv = 1.0 / sd.S0;
@@ -140,26 +140,52 @@ enum { kAdjT = 0, kAdjS = 4, kAdjW = 8, kAdjN = 9 };
 // the building blocks (reverse mode through the D formulas, values only) and
 // then contracts them with the building blocks' tangents along latitude,
 // longitude and gamma (forward mode through the site geometry).
+// Per grid point, shared by all sites: the point quantities, and
+//   gc_a = sum_i Gbar_{a, 8+i} c_i  (a < 8),   cgc = sum_ij c_i Gbar_{8+i, 8+j} c_j,
+// so that with D_{8+i} = i Q c_i the rows z_a = (Gbar D)_a for a < 8 and the
+// contraction c . z_{8:} of the phase-only rows need only Gbar[:8, :8], gc
+// and cgc (Gbar symmetric).
+struct AdjPoint {
+  Point q;
+  double gc[8], cgc;
+};
+
 template <bool TIDAL, bool ROT>
-__host__ __device__ inline void adjoint_point(const EventC& ec, const SiteA& sa, const double* Gb,
-                                              int32_t k, double* acc) {
+__host__ __device__ inline void adjoint_point_setup(const EventC& ec, const double* Gb, int32_t k,
+                                                    AdjPoint& ap) {
   constexpr int NPI = TIDAL ? 5 : 3;
   constexpr int P = 8 + NPI;
-  Point q;
-  point_setup(ec, k, true, ROT, q);
-  // phase-only derivative coefficients: D_{8+i} = i Q c_i
+  point_setup(ec, k, true, ROT, ap.q);
   double c[NPI];
-  {
-    const double v = q.v, iv = q.iv, L = q.L;
-    const double iv2 = iv * iv, iv5 = iv2 * iv2 * iv, v2 = v * v, v5 = v2 * v2 * v;
-    c[0] = -1.0;
-    c[1] = eval_phase(ec.ps[kPsChi1], v, iv5, v5, v2, L);
-    c[2] = eval_phase(ec.ps[kPsChi2], v, iv5, v5, v2, L);
-    if (TIDAL) {
-      c[NPI - 2] = eval_phase(ec.ps[kPsL1], v, iv5, v5, v2, L);
-      c[NPI - 1] = eval_phase(ec.ps[kPsL2], v, iv5, v5, v2, L);
-    }
+  phase_only_coefficients<TIDAL>(ec, ap.q, c);
+  double cg[NPI];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NPI; ++i) t = fma(Gb[a * P + 8 + i], c[i], t);
+    ap.gc[a] = t;
   }
+#pragma unroll
+  for (int i = 0; i < NPI; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < NPI; ++j) t = fma(Gb[(8 + i) * P + 8 + j], c[j], t);
+    cg[i] = t;
+  }
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NPI; ++i) t = fma(c[i], cg[i], t);
+  ap.cgc = t;
+}
+
+// Adds the contribution of one site at the point to acc[kAdjN].
+template <bool TIDAL>
+__host__ __device__ inline void adjoint_site(const EventC& ec, const SiteA& sa, const double* Gb,
+                                             const AdjPoint& ap, double* acc) {
+  constexpr int NPI = TIDAL ? 5 : 3;
+  constexpr int P = 8 + NPI;
+  const Point& q = ap.q;
   // hour angle, pattern vectors, arrival-time offset derivatives (tangents)
   const T3 cH = q.cth * sa.cdl - q.sth * sa.sdl;
   const T3 sH = q.sth * sa.cdl + q.cth * sa.sdl;
@@ -184,7 +210,7 @@ __host__ __device__ inline void adjoint_point(const EventC& ec, const SiteA& sa,
   }
   const T3 dH = -(sa.k1 * sH);
   const T3 dT = fmat(sa.k1t, cH, sa.k0t);
-  const double om0 = psd_weight_of(sa.lnx_off, sa.ix_fac, sa.x_fac, sa.S0inv, q);
+  const double om0 = psd_weight_of(sa.xp_fac, 0.0, sa.ix_fac, sa.x_fac, sa.S0inv, q);
   const double tf = q.tf;
   const double phMc = fma(tf * dH.v, q.gMc, q.pMc), phEta = fma(tf * dH.v, q.gEta, q.pEta);
   const double phT = tf * dT.v, phP = -tf * dH.v, phTc = tf * fma(kOmegaE, dH.v, 1.0);
@@ -219,27 +245,26 @@ __host__ __device__ inline void adjoint_point(const EventC& ec, const SiteA& sa,
     Di[6] = -2.0 * ccross * Fp.v;
     Dr[7] = fma(kOmegaE, QHr, -Qi * phTc);
     Di[7] = fma(kOmegaE, QHi, Qr * phTc);
-    // z = Gbar D, row by row; rows >= 8 only enter through c . z
-    double zr[8], zi[8], czr = 0.0, czi = 0.0;
+    // z = Gbar D for rows a < 8, and c . z over the phase-only rows, from
+    // Gbar[:8, :8], gc and cgc (see AdjPoint)
+    double zr[8], zi[8];
 #pragma unroll
-    for (int a = 0; a < P; ++a) {
+    for (int a = 0; a < 8; ++a) {
       asm volatile("" ::: "memory");
-      double g8 = 0.0;
-#pragma unroll
-      for (int i = 0; i < NPI; ++i) g8 = fma(Gb[a * P + 8 + i], c[i], g8);
-      double sr = -Qi * g8, si = Qr * g8;
+      double sr = -Qi * ap.gc[a], si = Qr * ap.gc[a];
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
         sr = fma(Gb[a * P + b], Dr[b], sr);
         si = fma(Gb[a * P + b], Di[b], si);
       }
-      if (a < 8) {
-        zr[a] = sr;
-        zi[a] = si;
-      } else {
-        czr = fma(c[a - 8], sr, czr);
-        czi = fma(c[a - 8], si, czi);
-      }
+      zr[a] = sr;
+      zi[a] = si;
+    }
+    double czr = -Qi * ap.cgc, czi = Qr * ap.cgc;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      czr = fma(ap.gc[b], Dr[b], czr);
+      czi = fma(ap.gc[b], Di[b], czi);
     }
     // Re(D^H z) for the ln S0 term
     double dz = fma(-Qi, czr, Qr * czi);
@@ -283,6 +308,15 @@ __host__ __device__ inline void adjoint_point(const EventC& ec, const SiteA& sa,
     acc[kAdjS + 3] = fma(-om, q2, acc[kAdjS + 3]);
     acc[kAdjW] = fma(om, q2, acc[kAdjW]);
   }
+}
+
+// One grid point and one site (host checks).
+template <bool TIDAL, bool ROT>
+__host__ __device__ inline void adjoint_point(const EventC& ec, const SiteA& sa, const double* Gb,
+                                              int32_t k, double* acc) {
+  AdjPoint ap;
+  adjoint_point_setup<TIDAL, ROT>(ec, Gb, k, ap);
+  adjoint_site<TIDAL>(ec, sa, Gb, ap, acc);
 }
 
 }  // namespace gwf

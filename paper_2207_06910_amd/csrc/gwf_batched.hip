@@ -75,7 +75,9 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void items_kernel(Item
       if (tid < NACC) out[tid] = 0.0;
     } else {
       double t = 0.0;
-      fisher_sums<TIDAL, ROT, MIXED>(ecg, scg, n_site, k0, k1, L, &t);
+      // FP64: sums of products over shared powers and the PSD power law once
+      // per point; mixed: Horner (measured faster there, see horner7)
+      fisher_sums<TIDAL, ROT, MIXED, !MIXED>(ecg, scg, n_site, k0, k1, L, &t);
       if (tid < NACC) out[tid] = t;
     }
     __syncthreads();                             // LDS is reused by the next item

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(Fis
   __syncthreads();
 
   double t = 0.0;
-  fisher_sums<TIDAL, ROT>(ec, sc, n_site, 0, ec.n, L, &t);
+  fisher_sums<TIDAL, ROT, false, false>(ec, sc, n_site, 0, ec.n, L, &t);
   if (tid < NACC) {
     if (!isfinite(t)) atomicOr(&bad, 1);
     int r, c;
@@ -113,13 +113,13 @@ __global__ __launch_bounds__(kBlock) void snr_kernel(SnrArgs a) {
   for (int k = tid; k < ec.n; k += kBlock) {
     __asm__ volatile("" ::: "memory");
     Point q;
-    point_setup(ec, k, false, ROT, q);
+    point_setup<false>(ec, k, false, ROT, q);
 #pragma unroll
     for (int s = 0; s < kMaxSites; ++s) {
       if (s < n_site) {
         const SiteC& st = sc[s];
         SitePoint sp;
-        site_point(st, q, false, sp);
+        site_point<false, false>(st, q, false, sp);
         if (st.n_arm == 3) {
           const double p0 = cplus * dot4(st.arm_alpha[0], sp.P), x0 = ccross * dot4(st.arm_beta[0], sp.P);
           const double p1 = cplus * dot4(st.arm_alpha[1], sp.P), x1 = ccross * dot4(st.arm_beta[1], sp.P);

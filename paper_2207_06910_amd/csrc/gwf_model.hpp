@@ -108,6 +108,7 @@ struct SiteC {
   double cl;                   // cos lat
   double k1, k0, k1t, k0t;     // Delta = k1 cos H + k0;  dDelta/dth = k1t cos H + k0t
   double lnx_off, ix_fac, x_fac;  // ln(f/f0) = 3 ln v + lnx_off; f0/f = ix_fac v^-3; f/f0 = x_fac v^3
+  double xp_fac;               // (f/f0)^-4.14 = xp_fac v^-12.42
   double S0inv;                // 1/S0
   double alpha[2][4], beta[2][4], weff[2];  // effective interferometers (pattern maps)
   double arm_alpha[3][4], arm_beta[3][4];   // individual arms (SNR per interferometer)
@@ -415,6 +416,7 @@ __host__ __device__ inline void site_setup(const double* p, const SiteDesc& sd, 
   sc.k1t = -kREarthS * cl * ct;
   sc.k0t = kREarthS * sl * st;
   sc.lnx_off = -log(ec.piM) - log(sd.f0);
+  sc.xp_fac = exp(-4.14 * sc.lnx_off);
   sc.ix_fac = sd.f0 * ec.piM;
   sc.x_fac = 1.0 / sc.ix_fac;
   sc.S0inv = 1.0 / sd.S0;
@@ -487,17 +489,74 @@ __host__ __device__ inline void sincos_moderate(double x, double* s, double* c) 
 }
 
 // ------------------------------------------------------ per-point pieces
-__host__ __device__ inline double eval_phase(const PhaseSeries& s, double v, double iv5, double v5,
-                                             double v2, double L) {
-  double h = s.c[7];
-  for (int k = 6; k >= 0; --k) h = fma(h, v, s.c[k]);
-  return fma(h, iv5, fma(L, fma(s.l6, v, s.l5), v5 * fma(s.t12, v2, s.t10)));
+// Powers of v at one grid point, shared by every PN series of the point.
+struct VPow {
+  double p1, p2, p3, p4, p5, p6, p7;   // v^1 .. v^7
+  double L, Lv;                        // ln v and v ln v
+};
+
+__host__ __device__ inline void vpow(double v, double L, VPow& w) {
+  w.p1 = v;
+  w.p2 = v * v;
+  w.p3 = w.p2 * v;
+  w.p4 = w.p2 * w.p2;
+  w.p5 = w.p4 * v;
+  w.p6 = w.p3 * w.p3;
+  w.p7 = w.p4 * w.p3;
+  w.L = L;
+  w.Lv = L * v;
 }
-__host__ __device__ inline double eval_tau(const TauSeries& s, double v, double iv8, double iv2,
-                                           double L) {
-  double h = s.c[7];
-  for (int k = 6; k >= 0; --k) h = fma(h, v, s.c[k]);
-  return fma(h, iv8, s.l6 * L * iv2);
+
+// c0 + c1 v + ... + c7 v^7 as a sum of products with the powers, lowest
+// order first and c0 last.  Each fused multiply-add keeps the running sum as
+// its addend, so per-event coefficients held in scalar registers enter every
+// step directly (a Horner recurrence makes the coefficient the addend, which
+// costs two register copies per step on this ISA).
+__host__ __device__ inline double series7(const double c[8], const VPow& w) {
+  double h = c[1] * w.p1;
+  h = fma(c[2], w.p2, h);
+  h = fma(c[3], w.p3, h);
+  h = fma(c[4], w.p4, h);
+  h = fma(c[5], w.p5, h);
+  h = fma(c[6], w.p6, h);
+  h = fma(c[7], w.p7, h);
+  return h + c[0];
+}
+
+// The same polynomial by Horner's rule.  Kernels that re-read the per-event
+// coefficients from LDS into vector registers keep fewer values live this
+// way than with the sum of products, whose loads the compiler issues all
+// at once; kernels holding the coefficients in scalar registers use the sum.
+__host__ __device__ inline double horner7(const double c[8], double v) {
+  double h = c[7];
+  for (int k = 6; k >= 0; --k) h = fma(h, v, c[k]);
+  return h;
+}
+template <bool PSUM>
+__host__ __device__ inline double poly7(const double c[8], const VPow& w) {
+  return PSUM ? series7(c, w) : horner7(c, w.p1);
+}
+
+// A phase series (PhaseSeries) at v: v^-5 (sum c_k v^k) + (l5 + l6 v) ln v
+// + t10 v^5 + t12 v^7.
+template <bool PSUM = true>
+__host__ __device__ inline double eval_phase(const PhaseSeries& s, const VPow& w, double iv5) {
+  const double rest = fma(s.l6, w.Lv, fma(s.l5, w.L, fma(s.t12, w.p7, s.t10 * w.p5)));
+  return fma(poly7<PSUM>(s.c, w), iv5, rest);
+}
+// The spin series, whose l6, t10 and t12 are zero by construction.
+template <bool PSUM = true>
+__host__ __device__ inline double eval_phase_spin(const PhaseSeries& s, const VPow& w, double iv5) {
+  return fma(poly7<PSUM>(s.c, w), iv5, s.l5 * w.L);
+}
+// The deformability series, which only have the tidal terms.
+__host__ __device__ inline double eval_phase_tidal(const PhaseSeries& s, const VPow& w) {
+  return fma(s.t12, w.p7, s.t10 * w.p5);
+}
+// A tau*-type series at v: v^-8 (sum c_k v^k) + l6 ln v v^-2.
+template <bool PSUM = true>
+__host__ __device__ inline double eval_tau(const TauSeries& s, const VPow& w, double iv8, double iv2) {
+  return fma(poly7<PSUM>(s.c, w), iv8, s.l6 * (w.L * iv2));
 }
 
 // Frequency-point quantities shared by all sites.
@@ -506,10 +565,14 @@ struct Point {
   double cth, sth;                // cos, sin of the sidereal angle at t(f)
   double gMc, gEta;               // d(sidereal angle)/dMc, /deta
   double pMc, pEta;               // dPsi_PN/dMc, /deta
+  double vpsd;                    // v^-12.42: the PSD's power law, shared by all sites
 };
 
+// PSUM: the evaluation form of the PN series (see horner7) and of the PSD's
+// power law (once per point when true, once per site otherwise).
+template <bool PSUM = true>
 __host__ __device__ inline void point_setup(const EventC& ec, int32_t k, bool need_derivs, bool rot,
-                                            Point& q) {
+                                            Point& q, bool need_psd = true) {
   const double L = fma((double)k, ec.dlnv, ec.lnv0);
   const double v = exp(L);
   const double iv = 1.0 / v;
@@ -521,14 +584,42 @@ __host__ __device__ inline void point_setup(const EventC& ec, int32_t k, bool ne
   q.v = v; q.iv = iv; q.L = L; q.f = f;
   q.tf = kTwoPi * f;
   q.w4A2 = w * f * ec.KA4 * iv7;
-  const double th = rot ? ec.thc + eval_tau(ec.ts[kTsTheta], v, iv8, iv2, L) : ec.thc;
+  q.vpsd = (PSUM && need_psd) ? exp(-12.42 * L) : 0.0;
+  VPow pw;
+  vpow(v, L, pw);
+  const double th = rot ? ec.thc + eval_tau<PSUM>(ec.ts[kTsTheta], pw, iv8, iv2) : ec.thc;
   sincos_moderate(th, &q.sth, &q.cth);
   if (need_derivs) {
-    const double v2 = v * v, v5 = v2 * v2 * v;
-    q.gMc = rot ? eval_tau(ec.ts[kTsMc], v, iv8, iv2, L) : 0.0;
-    q.gEta = rot ? eval_tau(ec.ts[kTsEta], v, iv8, iv2, L) : 0.0;
-    q.pMc = eval_phase(ec.ps[kPsMc], v, iv5, v5, v2, L);
-    q.pEta = eval_phase(ec.ps[kPsEta], v, iv5, v5, v2, L);
+    q.gMc = rot ? eval_tau<PSUM>(ec.ts[kTsMc], pw, iv8, iv2) : 0.0;
+    q.gEta = rot ? eval_tau<PSUM>(ec.ts[kTsEta], pw, iv8, iv2) : 0.0;
+    q.pMc = eval_phase<PSUM>(ec.ps[kPsMc], pw, iv5);
+    q.pEta = eval_phase<PSUM>(ec.ps[kPsEta], pw, iv5);
+  }
+}
+
+// The phase-only derivative coefficients of a point: c = (-1, dPsi/dchi1,
+// dPsi/dchi2[, dPsi/dLambda1, dPsi/dLambda2]).
+template <bool TIDAL, bool PSUM = true>
+__host__ __device__ inline void phase_only_coefficients(const EventC& ec, const Point& q, double* c) {
+  constexpr int NPI = TIDAL ? 5 : 3;
+  const double iv = q.iv, iv2 = iv * iv, iv5 = iv2 * iv2 * iv;
+  VPow pw;
+  vpow(q.v, q.L, pw);
+  c[0] = -1.0;
+  if (PSUM) {      // the spin and deformability series' structural zeros skipped
+    c[1] = eval_phase_spin<true>(ec.ps[kPsChi1], pw, iv5);
+    c[2] = eval_phase_spin<true>(ec.ps[kPsChi2], pw, iv5);
+    if (TIDAL) {
+      c[NPI - 2] = eval_phase_tidal(ec.ps[kPsL1], pw);
+      c[NPI - 1] = eval_phase_tidal(ec.ps[kPsL2], pw);
+    }
+  } else {         // the general form (fewer live values in the LDS-constant kernels)
+    c[1] = eval_phase<false>(ec.ps[kPsChi1], pw, iv5);
+    c[2] = eval_phase<false>(ec.ps[kPsChi2], pw, iv5);
+    if (TIDAL) {
+      c[NPI - 2] = eval_phase<false>(ec.ps[kPsL1], pw, iv5);
+      c[NPI - 1] = eval_phase<false>(ec.ps[kPsL2], pw, iv5);
+    }
   }
 }
 
@@ -540,11 +631,13 @@ struct SitePoint {
   double om;          // 4 w A^2 / S_n(f)
 };
 
-__host__ __device__ inline double psd_weight_of(double lnx_off, double ix_fac, double x_fac,
-                                                double S0inv, const Point& q) {
-  // S_n = S0 [x^-4.14 - 5 x^-2 + 111 (1 - x^2 + x^4/2)/(1 + x^2/2)], x = f/f0
-  const double lnx = fma(3.0, q.L, lnx_off);
-  const double xp = exp(-4.14 * lnx);
+template <bool PSUM = true>
+__host__ __device__ inline double psd_weight_of(double xp_fac, double lnx_off, double ix_fac,
+                                                double x_fac, double S0inv, const Point& q) {
+  // S_n = S0 [x^-4.14 - 5 x^-2 + 111 (1 - x^2 + x^4/2)/(1 + x^2/2)], x = f/f0;
+  // x^-4.14 = xp_fac v^-12.42 with the power of v evaluated once per point
+  // (PSUM), or exp(-4.14 ln x) here
+  const double xp = PSUM ? xp_fac * q.vpsd : exp(-4.14 * fma(3.0, q.L, lnx_off));
   const double ix = ix_fac * q.iv * q.iv * q.iv;   // f0/f
   const double x = x_fac * q.v * q.v * q.v;        // f/f0
   const double ix2 = ix * ix;
@@ -556,8 +649,9 @@ __host__ __device__ inline double psd_weight_of(double lnx_off, double ix_fac, d
   return q.w4A2 * S0inv * den / top;
 }
 
+template <bool PSUM = true>
 __host__ __device__ inline void psd_weight(const SiteC& sc, const Point& q, double& om) {
-  om = psd_weight_of(sc.lnx_off, sc.ix_fac, sc.x_fac, sc.S0inv, q);
+  om = psd_weight_of<PSUM>(sc.xp_fac, sc.lnx_off, sc.ix_fac, sc.x_fac, sc.S0inv, q);
 }
 
 // The same weight with the PSD shape evaluated in FP32 (mixed form).  The
@@ -583,7 +677,7 @@ __host__ __device__ inline void psd_weight_f32(const SiteC& sc, const Point& q, 
   om = q.w4A2 * sc.S0inv * (double)(den / top);
 }
 
-template <bool MIXED = false>
+template <bool MIXED = false, bool PSUM = true>
 __host__ __device__ inline void site_point(const SiteC& sc, const Point& q, bool need_derivs,
                                            SitePoint& sp) {
   const double cH = q.cth * sc.cdl - q.sth * sc.sdl;
@@ -594,7 +688,7 @@ __host__ __device__ inline void site_point(const SiteC& sc, const Point& q, bool
   sp.P[2] = EX * EY - NX * NY;
   sp.P[3] = EX * NY + NX * EY;
   if (MIXED) psd_weight_f32(sc, q, sp.om);
-  else psd_weight(sc, q, sp.om);
+  else psd_weight<PSUM>(sc, q, sp.om);
   if (!need_derivs) return;
   const double EXh = -sH, EYh = -sc.ct * cH, NXh = -sc.sl * cH, NYh = sc.slct * sH;
   sp.PH[0] = EX * EXh - NX * NXh - EY * EYh + NY * NYh;
@@ -625,7 +719,7 @@ __host__ __device__ inline double dot4(const double a[4], const double b[4]) {
 // every interferometer, so the blocks they span are
 //   Gamma_{b, 8+i} += U_b c_i,   Gamma_{8+i, 8+j} += W c_i c_j,
 // which the caller accumulates (see add_phase_blocks).
-template <bool TIDAL, bool ROT, bool MIXED = false>
+template <bool TIDAL, bool ROT, bool MIXED = false, bool PSUM = true>
 __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* sc, int n_site,
                                                  int32_t k, double* G, double* U, double& W,
                                                  double* cph) {
@@ -633,14 +727,14 @@ __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* 
   const double cplus = ec.cplus, ccross = ec.ccross, dcp = ec.dcplus, dcx = ec.dcross;
   const double dlnA = ec.dlnA_dMc, idL = ec.inv_dL;
   Point q;
-  point_setup(ec, k, true, ROT, q);
+  point_setup<PSUM>(ec, k, true, ROT, q, !MIXED);
   W = 0.0;
 #pragma unroll
   for (int b = 0; b < 8; ++b) U[b] = 0.0;
   for (int s = 0; s < n_site; ++s) {
     const SiteC& st = sc[s];
     SitePoint sp;
-    site_point<MIXED>(st, q, true, sp);
+    site_point<MIXED, PSUM>(st, q, true, sp);
     const double phMc = fma(q.tf * sp.dH, q.gMc, q.pMc);
     const double phEta = fma(q.tf * sp.dH, q.gEta, q.pEta);
     const double phT = q.tf * sp.dT;
@@ -686,17 +780,7 @@ __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* 
       W = fma(om, fma(Qr, Qr, Qi * Qi), W);
     }
   }
-  {
-    const double v = q.v, iv = q.iv, L = q.L;
-    const double iv2 = iv * iv, iv5 = iv2 * iv2 * iv, v2 = v * v, v5 = v2 * v2 * v;
-    cph[0] = -1.0;
-    cph[1] = eval_phase(ec.ps[kPsChi1], v, iv5, v5, v2, L);
-    cph[2] = eval_phase(ec.ps[kPsChi2], v, iv5, v5, v2, L);
-    if (TIDAL) {
-      cph[NPI - 2] = eval_phase(ec.ps[kPsL1], v, iv5, v5, v2, L);
-      cph[NPI - 1] = eval_phase(ec.ps[kPsL2], v, iv5, v5, v2, L);
-    }
-  }
+  phase_only_coefficients<TIDAL, PSUM>(ec, q, cph);
 }
 
 // Plain accumulation of the phase-only blocks of one point into

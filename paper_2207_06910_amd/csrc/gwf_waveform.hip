@@ -118,7 +118,10 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
     const double L = fma((double)k, ec.dlnv, ec.lnv0);
     const double v = exp(L);
     const double iv = 1.0 / v;
-    const double iv2 = iv * iv, iv5 = iv2 * iv2 * iv, v2 = v * v, v5 = v2 * v2 * v;
+    const double iv2 = iv * iv, iv5 = iv2 * iv2 * iv;
+    VPow pw;
+    vpow(v, L, pw);
+    const double v2 = pw.p2;
     const double f = v2 * v * ec.inv_piM;
     // A(f) = A0 v^-7/2; mixed form: 2^y, y = -3.5 log2 v, with the integer
     // part of y split off exactly before the FP32 exponential
@@ -131,7 +134,7 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
     }
     double cth, sth;
     {
-      const double th = ROT ? ec.thc + eval_tau(ec.ts[kTsTheta], v, iv5 * iv2 * iv, iv2, L) : ec.thc;
+      const double th = ROT ? ec.thc + eval_tau(ec.ts[kTsTheta], pw, iv5 * iv2 * iv, iv2) : ec.thc;
       // FP64 in both forms: the hour angle also sets the arrival-time phase
       // 2 pi f Delta (tens of cycles at kHz), which an FP32 cos H would move
       // by ~1e-5 rad
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
     // modulo one.  f tc - n with n the integer nearest to the rounded product
     // is formed by one fused multiply-add from the exact product, so the
     // reduced fraction carries a single rounding however large f tc is.
-    const double pn = frac_center(eval_phase(ec.cyc, v, iv5, v5, v2, L));
+    const double pn = frac_center(eval_phase(ec.cyc, pw, iv5));
     const double ftr = fma(f, tc, -rint(f * tc));
     const double cyc = frac_center(pn + ftr + ec.cyc0);
     double2* o = out + k;

@@ -161,3 +161,36 @@ def test_adjoint_full_workload_reproducible(lib):
     assert bool(torch.isfinite(ga).all())
     ok = int((inv["status"] == 0).sum())
     assert ok > 0.9 * wl.n
+
+
+def test_logdet_gradient_end_to_end_against_oracle(lib, orc):
+    """The product chain of the figure of merit, per event: GPU Fisher ->
+    GPU inversion (Gbar = its Gamma^-1) -> adjoint, against the oracle's
+    Fisher, mpmath inverse and nested-dual derivatives.  The GPU's Gamma^-1
+    differs from the exact one by kappa times the Fisher elements' relative
+    error (1.2e-13 measured against the oracle, normalised) plus kappa u from
+    the inversion, in its ill-conditioned directions; the allowance is
+    (2e-13 kappa + 1e-9) of sum_ij |Gbar_ij dGamma_ij|, the bound of that
+    error in the contracted sum.  Events are those with kappa < 1e12."""
+    full = synth.mixed1e4()
+    kind = full.meta["kind"]
+    cand = np.r_[np.flatnonzero(kind == 0)[:6], np.flatnonzero(kind == 1)[:6]]
+    k0 = orc.covariance(orc.fisher(full.subset(cand))["fisher"], dps=30)["cond"]
+    idx = cand[k0 < 1e12][:6]
+    assert len(idx) >= 3
+    wl = full.subset(idx)
+    dw = lib.DeviceWorkload(wl)
+    r = lib.fisher(dw)
+    inv = lib.invert(r["fisher"], r["status"])
+    assert bool((inv["status"] == 0).all())
+    ge = lib.fisher_adjoint(dw, inv["cov"], status=inv["status"])["grad_event"].cpu().numpy()
+    ref_f = orc.fisher(wl)
+    oinv = orc.covariance(ref_f["fisher"], dps=50)
+    ref, size = _reference(oinv["cov"], *_tangents(orc, wl), 1.0, 1.0)
+    kappa = oinv["cond"][:, None, None]
+    err = np.abs(ge - ref)
+    tol = (2e-13 * kappa + 1e-9) * size
+    assert np.all(err <= tol), np.max(err / tol)
+    print(f"ln det gradient: max |error| / allowance {np.max(err / tol):.2e}, "
+          f"max relative {np.max(err / np.maximum(np.abs(ref), 1e-300)):.2e}, kappa {oinv['cond'].min():.1e}"
+          f"-{oinv['cond'].max():.1e}")

@@ -4,11 +4,12 @@
 //   setup_kernel    one lane per event (and per event x site): the per-event
 //                   and per-site constants, written once to a workspace.
 //   items_kernel    persistent workgroups pull work items (event, point range
-//                   [k0, k1), at most `chunk` points) from a device counter
-//                   and write each item's partial sums to its own slot, so
-//                   long and short events are spread evenly over the chip
-//                   and the result does not depend on which workgroup took
-//                   which item.  The event's constants are read from the
+//                   [k0, k1), at most `chunk` points) from a device counter,
+//                   longest first, and write each item's partial sums to its
+//                   own slot (the item's position in event order), so long
+//                   and short events are spread evenly over the chip, the
+//                   last items to start are the shortest, and the result
+//                   does not depend on which workgroup took which item.  The event's constants are read from the
 //                   workspace through the constant address space, i.e. by
 //                   scalar loads into SGPRs, which costs neither LDS traffic
 //                   nor vector registers.
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void items_kernel(Item
     CSiteC* scp = (CSiteC*)(a.sic) + (int64_t)ew * n_site;
     const EventC& ecg = *(const EventC*)ecp;
     const SiteC* scg = (const SiteC*)scp;
-    double* out = a.partial + (int64_t)it * NACC;
+    double* out = a.partial + (int64_t)__builtin_amdgcn_readfirstlane(w.slot) * NACC;
     if (ecg.status) {
       if (tid < NACC) out[tid] = 0.0;
     } else {

@@ -6,7 +6,8 @@
 namespace gwf {
 
 struct Item {
-  int32_t e, k0, k1, pad;   // event, grid-point range [k0, k1)
+  int32_t e, k0, k1;        // event, grid-point range [k0, k1)
+  int32_t slot;             // partial-sum slot: the item's position in event order
 };
 
 struct SetupArgs {

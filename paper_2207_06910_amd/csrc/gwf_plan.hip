@@ -59,7 +59,10 @@ hipError_t dev_alloc(T** p, size_t count, int64_t& total) {
   return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
 }
 
-// Work items of at most `chunk` points, in event order.
+// Work items of at most `chunk` points.  Their slots (partial-sum positions)
+// follow event order, so an event's items occupy slots first[e] ..
+// first[e+1]-1; the processing order is longest first (ties in slot order),
+// which leaves the shortest items for the end of the launch.
 void build_items(const std::vector<int32_t>& npts, int chunk, std::vector<Item>& items,
                  std::vector<int32_t>& first) {
   items.clear();
@@ -67,9 +70,12 @@ void build_items(const std::vector<int32_t>& npts, int chunk, std::vector<Item>&
   for (size_t e = 0; e < npts.size(); ++e) {
     first[e] = (int32_t)items.size();
     const int32_t n = npts[e] >= 2 ? npts[e] : 2;     // invalid events still get one (skipped) item
-    for (int32_t k0 = 0; k0 < n; k0 += chunk) items.push_back(Item{(int32_t)e, k0, std::min(n, k0 + chunk), 0});
+    for (int32_t k0 = 0; k0 < n; k0 += chunk)
+      items.push_back(Item{(int32_t)e, k0, std::min(n, k0 + chunk), (int32_t)items.size()});
   }
   first[npts.size()] = (int32_t)items.size();
+  std::stable_sort(items.begin(), items.end(),
+                   [](const Item& a, const Item& b) { return a.k1 - a.k0 > b.k1 - b.k0; });
 }
 
 gwf_status set_items(gwf_plan* p, int chunk) {

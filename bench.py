@@ -31,8 +31,8 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # profiles/bns1e4_hbm_counters.md (calibrated against a 256 MiB copy: fetch
 # x 2.000, write x 1.000).  Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
-    "items_kernel<tidal,rot,mixed>": 60.57e6,
-    "items_kernel<tidal,rot>": 68.30e6,
+    "items_kernel<tidal,rot,mixed>": None,
+    "items_kernel<tidal,rot>": None,
     "fisher_kernel<tidal,rot>": 114.51e6,
     "waveform_kernel<rot,tidal>": 7849.06e6,
     "waveform_kernel<rot,tidal,mixed>": 7864.54e6,

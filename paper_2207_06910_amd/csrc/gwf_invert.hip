@@ -1,234 +1,258 @@
 // gwf_invert.hip -- batched FP64 inversion of Fisher matrices (sec. 4.1).
 //
-// One lane per event, matrices of compile-time size P.  Steps, in the
-// paper's order: normalise rows/columns by sqrt(diag) (skipped when a
-// diagonal entry is not > 0); condition number of the normalised matrix as
-// the ratio of its extreme |eigenvalues| (cyclic Jacobi, which resolves the
-// small eigenvalues of a unit-diagonal positive matrix to high relative
-// accuracy); no inversion above cond_max; Cholesky G^ = L L^T, L^-1 in place,
-// G^-1 = L^-T L^-1; undo the normalisation; sigma_i = sqrt(Cov_ii) and the
-// inversion error max_ij |(Gamma Cov - 1)_ij|.
+// Steps, in the paper's order: normalise rows/columns by sqrt(diag) (skipped
+// when a diagonal entry is not > 0); condition number of the normalised
+// matrix as the ratio of its extreme |eigenvalues|; no inversion above
+// cond_max; Cholesky G^ = L L^T, L^-1, G^-1 = L^-T L^-1; undo the
+// normalisation; sigma_i = sqrt(Cov_ii), ln det Gamma and the inversion error
+// max_ij |(Gamma Cov - 1)_ij|.
 //
-// The working matrix lives in registers (packed upper triangle, all
-// indices compile-time constants after unrolling); a second packed copy per
-// lane lives in LDS as [entry][lane], consecutive lanes on consecutive doubles.
+// Sixteen lanes per matrix, lane j holding column j in registers; a
+// wavefront (one workgroup) works on four matrices.
+//
+// Condition number.  The |eigenvalues| of the symmetric normalised matrix
+// are its singular values, found by one-sided (Hestenes) Jacobi: at each
+// step the columns are paired by a round-robin schedule, each lane fetches
+// its partner's column through cross-lane permutes, and both lanes of a pair
+// compute the same rotation from bitwise identical inputs and update their
+// own column, so one step makes P/2 rotations with no further exchange.  For
+// a matrix with unit diagonal the singular values come out with relative
+// errors of order kappa u (Demmel and Veselic, SIAM J. Matrix Anal. Appl. 13,
+// 1992), the accuracy of a two-sided Jacobi on the same matrix.
+//
+// Inversion.  The Cholesky factorisation is right-looking over columns: at
+// step k the pivot lane's column is broadcast and every later column updates
+// itself; the updates keep the two copies of each off-diagonal element
+// bitwise equal, so lane j reads L_jk from its own registers.  Lane j then
+// forms column j of L^-1 by forward substitution against L (staged in LDS),
+// and column j of the upper triangle of C = L^-T L^-1 from the staged
+// columns of L^-1.  Every element is computed with the same operations in
+// the same order as the textbook one-thread-per-matrix loops (left-looking
+// Cholesky, row-wise L^-1, C_ij = sum_{k >= max(i,j)} Li_ki Li_kj), so the
+// lane layout changes no result bit.
+#include "gwf_invert.hpp"
 #include "gwf_kernels.hpp"
 
 namespace gwf {
 
 namespace {
 
-// 32 lanes per workgroup (a half-filled wavefront): one lane per event is
-// latency-bound, so twice as many waves as with full wavefronts spread the
-// events over more SIMDs (measured on 10^4 13x13 matrices: 32 lanes as
-// fast as 64 or slightly faster, 16 and 128 about 12% slower).
-constexpr int kInvBlock = 32;
+constexpr int kGroup = 16;                 // lanes per matrix: one per column, P <= 13
+constexpr int kInvBlock = 64;              // one wavefront
+constexpr int kGroups = kInvBlock / kGroup;
+constexpr int kMaxSweeps = 40;
 
+// At least 3 waves per SIMD: left free, the compiler spends all 256 registers
+// on load scheduling and a SIMD runs one wave of this latency-bound kernel.
 template <int P>
-struct Packed {
-  static constexpr int N = P * (P + 1) / 2;
-  __host__ __device__ static constexpr int idx(int i, int j) {
-    return i <= j ? i * P - (i * (i - 1)) / 2 + (j - i) : j * P - (j * (j - 1)) / 2 + (i - j);
+__global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
+  constexpr int M = P + (P & 1);           // a zero column makes the count even
+  constexpr int LD = P + 1;
+  __shared__ double Gs[kGroups][P][LD];    // Gamma as stored, row i at Gs[g][i]
+  __shared__ double Ls[kGroups][P][LD];    // column k of L at Ls[g][k] (1/L_kk on the diagonal),
+                                           // later column j of Cov at Ls[g][j]
+  __shared__ double Ws[kGroups][P][LD];    // column i of L^-1 at Ws[g][i]
+  const int lane = threadIdx.x;
+  const int g = lane / kGroup, j = lane % kGroup;
+  const int64_t e = (int64_t)blockIdx.x * kGroups + g;
+  const bool live = e < a.n;
+  const bool own = live && j < P;          // lane owns a column of a real matrix
+  const double nan = __builtin_nan("");
+
+  int32_t st = live ? a.status[e] : kEvSkipped;
+  const bool use = live && !(st & (kEvInvalid | kEvSkipped));
+
+  // ---- Gamma, row j per lane, into LDS
+  if (use && j < P) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) Gs[g][j][k] = a.fisher[((int64_t)j * P + k) * a.n + e];
   }
-};
+  __syncthreads();
 
-template <int P>
-__device__ inline void jacobi_eigenvalues(double* A, double* ev) {
-  using S = Packed<P>;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    bool rotated = false;
+  // column j of the upper triangle (h_i = Gamma_{min(i,j), max(i,j)}) and the diagonal
+  double h[P], dg[P];
+  bool fin = true;
 #pragma unroll
-    for (int p = 0; p < P - 1; ++p) {
-#pragma unroll
-      for (int q = p + 1; q < P; ++q) {
-        const double apq = A[S::idx(p, q)];
-        const double app = A[S::idx(p, p)], aqq = A[S::idx(q, q)];
-        if (apq != 0.0 && fabs(apq) > 1e-300 &&
-            fabs(apq) > 0x1p-60 * sqrt(fabs(app) * fabs(aqq))) {
-          rotated = true;
-          const double th = (aqq - app) / (2.0 * apq);
-          const double t = fabs(th) > 1e150 ? 0.5 / th
-                                            : copysign(1.0, th) / (fabs(th) + sqrt(fma(th, th, 1.0)));
-          const double c = 1.0 / sqrt(fma(t, t, 1.0));
-          const double s = t * c;
-          A[S::idx(p, p)] = app - t * apq;
-          A[S::idx(q, q)] = aqq + t * apq;
-          A[S::idx(p, q)] = 0.0;
-#pragma unroll
-          for (int r = 0; r < P; ++r) {
-            if (r == p || r == q) continue;
-            const double arp = A[S::idx(r, p)], arq = A[S::idx(r, q)];
-            A[S::idx(r, p)] = c * arp - s * arq;
-            A[S::idx(r, q)] = s * arp + c * arq;
-          }
-        }
+  for (int i = 0; i < P; ++i) {
+    h[i] = 0.0;
+    dg[i] = 1.0;
+    if (use) {
+      dg[i] = Gs[g][i][i];
+      if (j < P) {
+        h[i] = i <= j ? Gs[g][i][j] : Gs[g][j][i];
+        fin = fin && isfinite(h[i]);
       }
     }
-    if (!rotated) break;
+  }
+  const uint64_t badm = __ballot(!fin);
+  const bool nonfinite = ((badm >> (g * kGroup)) & 0xffffull) != 0;
+  const bool go0 = use && !nonfinite;
+  bool normalise = true;
+#pragma unroll
+  for (int i = 0; i < P; ++i) normalise = normalise && (dg[i] > 0.0);
+  double d[P], dj = 1.0;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    d[i] = normalise ? sqrt(dg[i]) : 1.0;
+    if (i == j) dj = d[i];
   }
 #pragma unroll
-  for (int i = 0; i < P; ++i) ev[i] = A[S::idx(i, i)];
-}
+  for (int i = 0; i < P; ++i) h[i] = go0 ? h[i] / (d[i] * dj) : 0.0;
 
-template <int P>
-__global__ __launch_bounds__(kInvBlock) void invert_kernel(InvertArgs a) {
-  using S = Packed<P>;
-  constexpr int N = S::N;
-  __shared__ double B[N][kInvBlock];
-  const int lane = threadIdx.x;
-  const int64_t e = (int64_t)blockIdx.x * kInvBlock + lane;
-  if (e >= a.n) return;
-  const double nan = __builtin_nan("");
-  int32_t st = a.status[e];
-  auto fail = [&](int32_t bits) {
-    st |= bits;
-    for (int i = 0; i < P; ++i) {
-      a.sigma[(int64_t)i * a.n + e] = nan;
-      if (a.cov)
-        for (int j = 0; j < P; ++j) a.cov[((int64_t)i * P + j) * a.n + e] = nan;
+  // ---- condition number: one-sided Jacobi on a copy of the columns
+  double x[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) x[i] = h[i];
+  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+    bool rotated = false;
+#pragma unroll 1
+    for (int t = 0; t < M - 1; ++t) {
+      const int q = jacobi_partner<M>(j, t);
+      double nrm = 0.0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) nrm = fma(x[i], x[i], nrm);
+      double y[P];
+#pragma unroll
+      for (int i = 0; i < P; ++i) y[i] = __shfl(x[i], q, kGroup);
+      const double nq = __shfl(nrm, q, kGroup);
+      double gam = 0.0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) gam = fma(x[i], y[i], gam);
+      // both lanes of the pair see (ap, aq, gam) bit for bit
+      const bool first = j < q;
+      const double ap = first ? nrm : nq, aq = first ? nq : nrm;
+      double c = 1.0, s = 0.0;
+      if (q != j && hestenes_rotation(ap, aq, gam, c, s)) rotated = true;
+      const double sy = first ? -s : s;
+#pragma unroll
+      for (int i = 0; i < P; ++i) x[i] = fma(sy, y[i], c * x[i]);
     }
-    if (a.inv_err) a.inv_err[e] = nan;
-    if (a.logdet) a.logdet[e] = nan;
-    a.status[e] = st;
-  };
-  if (st & (kEvInvalid | kEvSkipped)) {
-    if (a.cond) a.cond[e] = nan;
-    fail(0);
-    return;
+    if (!__any(rotated)) break;
   }
-  double A[N], d[P];
-  bool finite = true, normalise = true;
+  double smax = 0.0, smin = INFINITY;
+  {
+    double nrm = 0.0;
 #pragma unroll
-  for (int i = 0; i < P; ++i)
-#pragma unroll
-    for (int j = i; j < P; ++j) {
-      const double g = a.fisher[((int64_t)i * P + j) * a.n + e];
-      A[S::idx(i, j)] = g;
-      finite = finite && isfinite(g);
-    }
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const double g = A[S::idx(i, i)];
-    normalise = normalise && (g > 0.0);
+    for (int i = 0; i < P; ++i) nrm = fma(x[i], x[i], nrm);
+    if (own) smax = smin = sqrt(nrm);
   }
 #pragma unroll
-  for (int i = 0; i < P; ++i) d[i] = normalise ? sqrt(A[S::idx(i, i)]) : 1.0;
-  if (!finite) {
-    if (a.cond) a.cond[e] = nan;
-    fail(kEvNonFinite);
-    return;
+  for (int off = kGroup / 2; off >= 1; off >>= 1) {
+    smax = fmax(smax, __shfl_xor(smax, off, kGroup));
+    smin = fmin(smin, __shfl_xor(smin, off, kGroup));
   }
+  const double cond = smin > 0.0 ? smax / smin : INFINITY;
+  const bool ill = go0 && !(cond <= a.cond_max);
+
+  // ---- Cholesky, right-looking over columns
+  double l[P];
 #pragma unroll
-  for (int i = 0; i < P; ++i)
-#pragma unroll
-    for (int j = i; j < P; ++j) {
-      const double h = A[S::idx(i, j)] / (d[i] * d[j]);
-      A[S::idx(i, j)] = h;
-      B[S::idx(i, j)][lane] = h;
-    }
-  // condition number
-  double ev[P];
-  jacobi_eigenvalues<P>(A, ev);
-  double emax = 0.0, emin = INFINITY;
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    emax = fmax(emax, fabs(ev[i]));
-    emin = fmin(emin, fabs(ev[i]));
-  }
-  const double cond = emin > 0.0 ? emax / emin : INFINITY;
-  if (a.cond) a.cond[e] = cond;
-  if (!(cond <= a.cond_max)) {
-    fail(kEvIllCond);
-    return;
-  }
-  // Cholesky of the normalised matrix (reloaded from the LDS copy), lower
-  // factor stored at idx(i, j), i >= j
-#pragma unroll
-  for (int i = 0; i < P; ++i)
-#pragma unroll
-    for (int j = i; j < P; ++j) A[S::idx(i, j)] = B[S::idx(i, j)][lane];
+  for (int i = 0; i < P; ++i) l[i] = h[i];
   bool pd = true;
+  double ljj = 1.0;
 #pragma unroll
-  for (int j = 0; j < P; ++j) {
-    double dj = A[S::idx(j, j)];
+  for (int k = 0; k < P; ++k) {
+    const double piv = __shfl(l[k], k, kGroup);   // updated Gamma^_kk
+    pd = pd && (piv > 0.0);
+    const double lkk = sqrt(fmax(piv, 0.0));
+    const double inv = 1.0 / lkk;
+    const double ljk = l[k] * inv;                // this column's L_jk (j > k)
 #pragma unroll
-    for (int k = 0; k < j; ++k) dj = fma(-A[S::idx(j, k)], A[S::idx(j, k)], dj);
-    pd = pd && (dj > 0.0);
-    const double ljj = sqrt(fmax(dj, 0.0));
-    A[S::idx(j, j)] = ljj;
-    const double inv = 1.0 / ljj;
-#pragma unroll
-    for (int i = j + 1; i < P; ++i) {
-      double s = A[S::idx(i, j)];
-#pragma unroll
-      for (int k = 0; k < j; ++k) s = fma(-A[S::idx(i, k)], A[S::idx(j, k)], s);
-      A[S::idx(i, j)] = s * inv;
+    for (int i = k + 1; i < P; ++i) {
+      const double lik = __shfl(l[i], k, kGroup) * inv;
+      if (j > k) l[i] = fma(-lik, ljk, l[i]);
+      else if (j == k) l[i] = lik;
+    }
+    if (j == k) {
+      ljj = lkk;
+      l[k] = inv;
     }
   }
-  if (!pd) {
-    fail(kEvNotPD);
-    return;
-  }
-  // ln det Gamma = sum_i ln Gamma_ii + ln det of the normalised matrix
-  //             = 2 sum_i ln(d_i L_ii)
-  if (a.logdet) {
-    double ld = 0.0;
+  const bool ok = go0 && !ill && pd;
+
+  // ln det Gamma = 2 sum_i ln(d_i L_ii)
+  double ld = own ? log(dj * ljj) : 0.0;
 #pragma unroll
-    for (int i = 0; i < P; ++i) ld += log(d[i] * A[S::idx(i, i)]);
-    a.logdet[e] = 2.0 * ld;
+  for (int off = kGroup / 2; off >= 1; off >>= 1) ld += __shfl_xor(ld, off, kGroup);
+
+  // ---- L^-1, column j by forward substitution
+  if (j < P) {
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+      if (i >= j) Ls[g][j][i] = l[i];
   }
-  // L^-1 in place, row by row, columns ascending
+  __syncthreads();
+  double y[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) {
-    const double inv_ii = 1.0 / A[S::idx(i, i)];
+    double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < i; ++j) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = j; k < i; ++k) s = fma(A[S::idx(i, k)], A[S::idx(k, j)], s);
-      A[S::idx(i, j)] = -s * inv_ii;
-    }
-    A[S::idx(i, i)] = inv_ii;
+    for (int k = 0; k < i; ++k) s = fma(Ls[g][k][i], y[k], s);   // y_k = 0 for k < j
+    const double inv_ii = Ls[g][i][i];
+    y[i] = i < j ? 0.0 : i == j ? inv_ii : -s * inv_ii;
   }
-  // C = L^-T L^-1: C_ij = sum_{k >= max(i,j)} Li_ki Li_kj; then undo normalisation
+  if (j < P) {
 #pragma unroll
-  for (int i = 0; i < P; ++i)
+    for (int k = 0; k < P; ++k) Ws[g][j][k] = y[k];
+  }
+  __syncthreads();
+
+  // ---- C_ij for i <= j, undone normalisation, both triangles into LDS
+  if (j < P) {
 #pragma unroll
-    for (int j = i; j < P; ++j) {
+    for (int i = 0; i < P; ++i) {
       double s = 0.0;
 #pragma unroll
-      for (int k = j; k < P; ++k) s = fma(A[S::idx(k, i)], A[S::idx(k, j)], s);
-      B[S::idx(i, j)][lane] = s / (d[i] * d[j]);
+      for (int k = i; k < P; ++k) s = fma(Ws[g][i][k], y[k], s);   // zero terms for k < j
+      if (i <= j) {
+        const double cij = s / (d[i] * dj);
+        Ls[g][j][i] = cij;
+        Ls[g][i][j] = cij;
+      }
     }
+  }
+  __syncthreads();
+
+  // ---- outputs
+  double cv[P];
 #pragma unroll
-  for (int i = 0; i < P; ++i) {
-    a.sigma[(int64_t)i * a.n + e] = sqrt(B[S::idx(i, i)][lane]);
+  for (int k = 0; k < P; ++k) cv[k] = Ls[g][j < P ? j : 0][k];   // column j of Cov
+  double err = 0.0;
+  if (a.inv_err && ok) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      double s = (i == j) ? -1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < P; ++k) s = fma(Gs[g][i][k], cv[k], s);
+      if (j < P) err = fmax(err, fabs(s));
+    }
+  }
+#pragma unroll
+  for (int off = kGroup / 2; off >= 1; off >>= 1) err = fmax(err, __shfl_xor(err, off, kGroup));
+
+  if (!live) return;
+  if (use) {
+    if (nonfinite) st |= kEvNonFinite;
+    else if (ill) st |= kEvIllCond;
+    else if (!pd) st |= kEvNotPD;
+  }
+  if (j < P) {
+    a.sigma[(int64_t)j * a.n + e] = ok ? sqrt(Ls[g][j][j]) : nan;
     if (a.cov)
 #pragma unroll
-      for (int j = 0; j < P; ++j) a.cov[((int64_t)i * P + j) * a.n + e] = B[S::idx(i, j)][lane];
+      for (int k = 0; k < P; ++k) a.cov[((int64_t)k * P + j) * a.n + e] = ok ? cv[k] : nan;
   }
-  if (a.inv_err) {
-    double err = 0.0;
-    for (int i = 0; i < P; ++i) {
-      double g[P];
-#pragma unroll
-      for (int k = 0; k < P; ++k) g[k] = a.fisher[((int64_t)i * P + k) * a.n + e];
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        double s = (i == j) ? -1.0 : 0.0;
-#pragma unroll
-        for (int k = 0; k < P; ++k) s = fma(g[k], B[S::idx(k, j)][lane], s);
-        err = fmax(err, fabs(s));
-      }
-    }
-    a.inv_err[e] = err;
+  if (j == 0) {
+    if (a.cond) a.cond[e] = go0 ? cond : nan;
+    if (a.inv_err) a.inv_err[e] = ok ? err : nan;
+    if (a.logdet) a.logdet[e] = ok ? 2.0 * ld : nan;
+    a.status[e] = st;
   }
-  a.status[e] = st;
 }
 
 template <int P>
 hipError_t launch_p(const InvertArgs& a, hipStream_t stream) {
-  const unsigned blocks = (unsigned)((a.n + kInvBlock - 1) / kInvBlock);
+  const unsigned blocks = (unsigned)((a.n + kGroups - 1) / kGroups);
   hipLaunchKernelGGL((invert_kernel<P>), dim3(blocks), dim3(kInvBlock), 0, stream, a);
   return hipGetLastError();
 }

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "model_host.hip")
 LIB = os.path.join(HERE, "libmodel_host.so")
 DEPS = [SRC, os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_model.hpp"),
-        os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_adjoint.hpp")]
+        os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_adjoint.hpp"),
+        os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_invert.hpp")]
 _lib = None
 
 
@@ -62,3 +63,21 @@ def adjoint(wl, gbar, w_snr=1.0, w_fisher=1.0):
                            ctypes.c_int(len(sites)), P_(sites), ctypes.c_uint32(wl.flags), P_(G),
                            ctypes.c_double(w_snr), ctypes.c_double(w_fisher), P_(out))
     return out
+
+
+def jacobi_partner(M, j, t):
+    return int(load().model_jacobi_partner(ctypes.c_int(M), ctypes.c_int(j), ctypes.c_int(t)))
+
+
+def jacobi_cond(F):
+    """Condition numbers of F [P][P][N] by the inversion kernel's one-sided
+    Jacobi (P in 2, 5, 9, 11, 13), and the sweeps it took."""
+    lib = load()
+    P, _, n = F.shape
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    cond = np.zeros(n)
+    sweeps = np.zeros(n, dtype=np.int32)
+    P_ = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    rc = lib.model_jacobi_cond_host(ctypes.c_int(P), ctypes.c_int64(n), P_(F), P_(cond), P_(sweeps))
+    assert rc == 0, "unsupported size"
+    return cond, sweeps

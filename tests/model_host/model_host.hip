@@ -5,6 +5,7 @@
 #include <cmath>
 #include <vector>
 
+#include "../../paper_2207_06910_amd/csrc/gwf_invert.hpp"
 #include "../../paper_2207_06910_amd/csrc/gwf_model.hpp"
 
 using namespace gwf;
@@ -119,6 +120,85 @@ extern "C" int model_adjoint_host(int64_t n, const double* par, int64_t ld, cons
     else if (tidal) one_event_adjoint<true, false>(p, fmin[e], fx, npts[e], nd, G.data(), w_snr, w_fisher, ge);
     else if (rot) one_event_adjoint<false, true>(p, fmin[e], fx, npts[e], nd, G.data(), w_snr, w_fisher, ge);
     else one_event_adjoint<false, false>(p, fmin[e], fx, npts[e], nd, G.data(), w_snr, w_fisher, ge);
+  }
+  return 0;
+}
+
+// ---- condition number by the inversion kernel's one-sided Jacobi: lane j
+// of the kernel is column j here; every step reads all partner columns
+// before any column is rotated, as the lanes' permutes do.
+extern "C" int model_jacobi_partner(int M, int j, int t) {
+  switch (M) {
+    case 2: return jacobi_partner<2>(j, t);
+    case 4: return jacobi_partner<4>(j, t);
+    case 6: return jacobi_partner<6>(j, t);
+    case 8: return jacobi_partner<8>(j, t);
+    case 10: return jacobi_partner<10>(j, t);
+    case 12: return jacobi_partner<12>(j, t);
+    case 14: return jacobi_partner<14>(j, t);
+    default: return -1;
+  }
+}
+
+template <int P>
+static void jacobi_cond_one(const double* F, int64_t n, int64_t e, double* cond, int32_t* sweeps) {
+  constexpr int M = P + (P & 1), G = 16;
+  double x[G][P] = {}, y[G][P];
+  double d[P];
+  bool normalise = true;
+  for (int i = 0; i < P; ++i) normalise = normalise && F[(i * P + i) * n + e] > 0.0;
+  for (int i = 0; i < P; ++i) d[i] = normalise ? std::sqrt(F[(i * P + i) * n + e]) : 1.0;
+  for (int j = 0; j < P; ++j)
+    for (int i = 0; i < P; ++i) {
+      const int r = i <= j ? i : j, c = i <= j ? j : i;
+      x[j][i] = F[(r * P + c) * n + e] / (d[i] * d[j]);
+    }
+  int sw = 0;
+  for (; sw < 40; ++sw) {
+    bool any = false;
+    for (int t = 0; t < M - 1; ++t) {
+      double nrm[G];
+      for (int j = 0; j < G; ++j) {
+        nrm[j] = 0.0;
+        for (int i = 0; i < P; ++i) nrm[j] = std::fma(x[j][i], x[j][i], nrm[j]);
+      }
+      for (int j = 0; j < G; ++j)
+        for (int i = 0; i < P; ++i) y[j][i] = x[jacobi_partner<M>(j, t)][i];
+      for (int j = 0; j < G; ++j) {
+        const int q = jacobi_partner<M>(j, t);
+        double gam = 0.0;
+        for (int i = 0; i < P; ++i) gam = std::fma(x[j][i], y[j][i], gam);
+        const bool first = j < q;
+        const double ap = first ? nrm[j] : nrm[q], aq = first ? nrm[q] : nrm[j];
+        double c = 1.0, s = 0.0;
+        if (q != j && hestenes_rotation(ap, aq, gam, c, s)) any = true;
+        const double sy = first ? -s : s;
+        for (int i = 0; i < P; ++i) x[j][i] = std::fma(sy, y[j][i], c * x[j][i]);
+      }
+    }
+    if (!any) break;
+  }
+  double smax = 0.0, smin = INFINITY;
+  for (int j = 0; j < P; ++j) {
+    double nrm = 0.0;
+    for (int i = 0; i < P; ++i) nrm = std::fma(x[j][i], x[j][i], nrm);
+    smax = std::fmax(smax, std::sqrt(nrm));
+    smin = std::fmin(smin, std::sqrt(nrm));
+  }
+  cond[e] = smin > 0.0 ? smax / smin : INFINITY;
+  sweeps[e] = sw + 1;
+}
+
+extern "C" int model_jacobi_cond_host(int P, int64_t n, const double* F, double* cond, int32_t* sweeps) {
+  for (int64_t e = 0; e < n; ++e) {
+    switch (P) {
+      case 2: jacobi_cond_one<2>(F, n, e, cond, sweeps); break;
+      case 5: jacobi_cond_one<5>(F, n, e, cond, sweeps); break;
+      case 9: jacobi_cond_one<9>(F, n, e, cond, sweeps); break;
+      case 11: jacobi_cond_one<11>(F, n, e, cond, sweeps); break;
+      case 13: jacobi_cond_one<13>(F, n, e, cond, sweeps); break;
+      default: return -1;
+    }
   }
   return 0;
 }

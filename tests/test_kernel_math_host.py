@@ -92,3 +92,53 @@ def test_host_adjoint_matches_oracle_tangents(orc, flags):
     scale = np.abs(want).max(axis=(1, 2), keepdims=True)
     err = np.abs(got - want) / scale
     assert err.max() < 1e-10, (err.max(), np.unravel_index(err.argmax(), err.shape))
+
+
+# ------------------------------------------------------------ inversion: condition number
+def test_jacobi_schedule_pairs_every_column_once():
+    """The inversion kernel's round-robin: each step pairs the columns into
+    disjoint pairs (lanes beyond the matrix with themselves), and a sweep of
+    M-1 steps meets every pair exactly once."""
+    for M in (2, 4, 6, 8, 10, 12, 14):
+        seen = set()
+        for t in range(M - 1):
+            part = [model_host.jacobi_partner(M, j, t) for j in range(16)]
+            for j, q in enumerate(part):
+                assert part[q] == j
+                if j >= M:
+                    assert q == j
+                else:
+                    assert q != j and q < M
+                if j < q:
+                    seen.add((j, q))
+        assert len(seen) == M * (M - 1) // 2
+
+
+def _spectrum_matrices(rng, P, n, log_kappa_max, indefinite=False):
+    F = np.zeros((P, P, n))
+    for e in range(n):
+        Q, _ = np.linalg.qr(rng.normal(size=(P, P)))
+        lam = np.geomspace(1.0, 10 ** rng.uniform(0, log_kappa_max), P)
+        if indefinite:
+            lam *= np.where(rng.random(P) < 0.3, -1.0, 1.0)
+        A = (Q * lam) @ Q.T
+        A = 0.5 * (A + A.T)
+        s = 10 ** rng.uniform(-3, 3, P)
+        F[:, :, e] = A * np.outer(s, s)
+    return F
+
+
+@pytest.mark.parametrize("P", [2, 5, 9, 11, 13])
+def test_jacobi_condition_number_against_mpmath(orc, P):
+    """The kernel's one-sided Jacobi (host build of its schedule and
+    rotation) against 30-digit eigenvalues of the normalised matrix:
+    condition numbers 1 to 1e11 within (1e-13 + 100 P kappa u), indefinite
+    matrices as the ratio of |eigenvalues|, in at most 15 sweeps."""
+    rng = np.random.default_rng(100 + P)
+    F = np.concatenate([_spectrum_matrices(rng, P, 8, 11),
+                        _spectrum_matrices(rng, P, 3, 3, indefinite=True)], axis=2)
+    cond, sweeps = model_host.jacobi_cond(F)
+    ref = orc.covariance(F, cond_max=0.0, dps=30)["cond"]
+    tol = 1e-13 + 100 * P * ref * 2.0 ** -53
+    assert np.all(np.abs(cond / ref - 1) <= tol), (cond / ref - 1, tol)
+    assert sweeps.max() <= 15, sweeps

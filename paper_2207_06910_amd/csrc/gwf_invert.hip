@@ -48,10 +48,14 @@ template <int P>
 __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
   constexpr int M = P + (P & 1);           // a zero column makes the count even
   constexpr int LD = P + 1;
-  __shared__ double Gs[kGroups][P][LD];    // Gamma as stored, row i at Gs[g][i]
-  __shared__ double Ls[kGroups][P][LD];    // column k of L at Ls[g][k] (1/L_kk on the diagonal),
-                                           // later column j of Cov at Ls[g][j]
-  __shared__ double Ws[kGroups][P][LD];    // column i of L^-1 at Ws[g][i]
+  // Two buffers per matrix (11.6 KB per workgroup at P = 13, so that the
+  // 2500 workgroups of 10^4 matrices are resident at once):
+  //   Gs: Gamma as stored (row i at Gs[g][i]), then column i of L^-1 at
+  //       Gs[g][i], then Gamma again for the residual;
+  //   Ls: column k of L at Ls[g][k] (1/L_kk on the diagonal), then column j
+  //       of Cov at Ls[g][j].
+  __shared__ double Gs[kGroups][P][LD];
+  __shared__ double Ls[kGroups][P][LD];
   const int lane = threadIdx.x;
   const int g = lane / kGroup, j = lane % kGroup;
   const int64_t e = (int64_t)blockIdx.x * kGroups + g;
@@ -108,34 +112,17 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
 #pragma unroll 1
     for (int t = 0; t < M - 1; ++t) {
       const int q = jacobi_partner<M>(j, t);
-      double nrm = 0.0;
-#pragma unroll
-      for (int i = 0; i < P; ++i) nrm = fma(x[i], x[i], nrm);
+      const double nx = col_dot<P>(x, x), sx = sqrt(nx);
       double y[P];
 #pragma unroll
       for (int i = 0; i < P; ++i) y[i] = __shfl(x[i], q, kGroup);
-      const double nq = __shfl(nrm, q, kGroup);
-      double gam = 0.0;
-#pragma unroll
-      for (int i = 0; i < P; ++i) gam = fma(x[i], y[i], gam);
-      // both lanes of the pair see (ap, aq, gam) bit for bit
-      const bool first = j < q;
-      const double ap = first ? nrm : nq, aq = first ? nq : nrm;
-      double c = 1.0, s = 0.0;
-      if (q != j && hestenes_rotation(ap, aq, gam, c, s)) rotated = true;
-      const double sy = first ? -s : s;
-#pragma unroll
-      for (int i = 0; i < P; ++i) x[i] = fma(sy, y[i], c * x[i]);
+      const double ny = __shfl(nx, q, kGroup), sy = __shfl(sx, q, kGroup);
+      if (jacobi_update<P>(x, y, nx, sx, ny, sy, j, q)) rotated = true;
     }
     if (!__any(rotated)) break;
   }
   double smax = 0.0, smin = INFINITY;
-  {
-    double nrm = 0.0;
-#pragma unroll
-    for (int i = 0; i < P; ++i) nrm = fma(x[i], x[i], nrm);
-    if (own) smax = smin = sqrt(nrm);
-  }
+  if (own) smax = smin = sqrt(col_dot<P>(x, x));
 #pragma unroll
   for (int off = kGroup / 2; off >= 1; off >>= 1) {
     smax = fmax(smax, __shfl_xor(smax, off, kGroup));
@@ -193,7 +180,7 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
   }
   if (j < P) {
 #pragma unroll
-    for (int k = 0; k < P; ++k) Ws[g][j][k] = y[k];
+    for (int k = 0; k < P; ++k) Gs[g][j][k] = y[k];
   }
   __syncthreads();
 
@@ -203,13 +190,19 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
     for (int i = 0; i < P; ++i) {
       double s = 0.0;
 #pragma unroll
-      for (int k = i; k < P; ++k) s = fma(Ws[g][i][k], y[k], s);   // zero terms for k < j
+      for (int k = i; k < P; ++k) s = fma(Gs[g][i][k], y[k], s);   // zero terms for k < j
       if (i <= j) {
         const double cij = s / (d[i] * dj);
         Ls[g][j][i] = cij;
         Ls[g][i][j] = cij;
       }
     }
+  }
+  __syncthreads();
+  // Gamma again (L2-resident) for the residual
+  if (a.inv_err && ok && j < P) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) Gs[g][j][k] = a.fisher[((int64_t)j * P + k) * a.n + e];
   }
   __syncthreads();
 

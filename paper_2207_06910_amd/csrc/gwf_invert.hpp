@@ -31,21 +31,65 @@ __host__ __device__ inline int jacobi_partner(int j, int t) {
 }
 
 // Rotation of the column pair (x_p, x_q) with ap = |x_p|^2, aq = |x_q|^2,
-// gam = x_p . x_q: x_p' = c x_p - s x_q, x_q' = s x_p + c x_q, with
-// t = s/c the smaller root of t^2 + 2 zeta t - 1 = 0, zeta = (aq-ap)/(2 gam),
-// makes x_p' . x_q' vanish.  Returns false (c = 1, s = 0) for a pair that is
+// gam = x_p . x_q and spq = |x_p| |x_q|: x_p' = c x_p - s x_q,
+// x_q' = s x_p + c x_q makes x_p' . x_q' vanish when t = s/c is the smaller
+// root of t^2 + 2 zeta t - 1 = 0, zeta = (aq - ap) / (2 gam), i.e. with
+// d = aq - ap and r = sqrt(d^2 + 4 gam^2),
+//   t = sign(d) 2 gam / (|d| + r),   c^2 = (1 + |d|/r) / 2.
+// (d, 2 gam) are scaled by a power of two first (exact; keeps d^2 + 4 gam^2
+// in range).  c comes from its own square root rather than 1/sqrt(1 + t^2),
+// one division fewer on the dependent chain; c^2 (1 + t^2) = 1 exactly in
+// exact arithmetic.  Returns false (c = 1, s = 0) for a pair that is
 // already orthogonal to kJacobiTol.
-__host__ __device__ inline bool hestenes_rotation(double ap, double aq, double gam, double& c,
+__host__ __device__ inline bool hestenes_rotation(double ap, double aq, double gam, double spq, double& c,
                                                   double& s) {
   c = 1.0;
   s = 0.0;
-  if (!(fabs(gam) > kJacobiTol * sqrt(ap * aq))) return false;
-  const double zeta = (aq - ap) / (2.0 * gam);
-  const double tn = fabs(zeta) > 1e150 ? 0.5 / zeta
-                                       : copysign(1.0, zeta) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
-  c = 1.0 / sqrt(fma(tn, tn, 1.0));
+  if (!(fabs(gam) > kJacobiTol * spq)) return false;
+  const double dl = aq - ap, g2 = 2.0 * gam;
+  int ex;
+  frexp(fmax(fabs(dl), fabs(g2)), &ex);
+  const double ds = ldexp(dl, -ex), gs = ldexp(g2, -ex);
+  const double ad = fabs(ds);
+  const double r = sqrt(fma(ds, ds, gs * gs));
+  const double tn = copysign(1.0, dl) * gs / (ad + r);
+  c = sqrt(fma(0.5, ad / r, 0.5));
   s = c * tn;
   return true;
+}
+
+// x . y in four interleaved partial sums added in a fixed order (short
+// dependency chains); x . y and y . x are bitwise equal.
+template <int P>
+__host__ __device__ inline double col_dot(const double* x, const double* y) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+  for (int i = 0; i < P; i += 4) {
+    s0 = fma(x[i], y[i], s0);
+    if (i + 1 < P) s1 = fma(x[i + 1], y[i + 1], s1);
+    if (i + 2 < P) s2 = fma(x[i + 2], y[i + 2], s2);
+    if (i + 3 < P) s3 = fma(x[i + 3], y[i + 3], s3);
+  }
+  return (s0 + s1) + (s2 + s3);
+}
+
+// One column's part of a Jacobi step: x is column j, y its partner column q
+// (q == j: no partner), nx = x . x, sx = sqrt(nx) and ny, sy the same for y,
+// each as its owner computed them.  Both columns of a pair compute the same
+// rotation from the same bits and update themselves.  Returns true if the
+// pair was rotated.
+template <int P>
+__host__ __device__ inline bool jacobi_update(double* x, const double* y, double nx, double sx, double ny,
+                                              double sy, int j, int q) {
+  if (q == j) return false;
+  const double gam = col_dot<P>(x, y);
+  const bool first = j < q;
+  double c, s;
+  const bool rot = hestenes_rotation(first ? nx : ny, first ? ny : nx, gam, sx * sy, c, s);
+  const double sg = first ? -s : s;
+#pragma unroll
+  for (int i = 0; i < P; ++i) x[i] = fma(sg, y[i], c * x[i]);
+  return rot;
 }
 
 }  // namespace gwf

@@ -157,33 +157,25 @@ static void jacobi_cond_one(const double* F, int64_t n, int64_t e, double* cond,
   for (; sw < 40; ++sw) {
     bool any = false;
     for (int t = 0; t < M - 1; ++t) {
-      double nrm[G];
+      double nrm[G], sn[G];
       for (int j = 0; j < G; ++j) {
-        nrm[j] = 0.0;
-        for (int i = 0; i < P; ++i) nrm[j] = std::fma(x[j][i], x[j][i], nrm[j]);
+        nrm[j] = col_dot<P>(x[j], x[j]);
+        sn[j] = std::sqrt(nrm[j]);
       }
       for (int j = 0; j < G; ++j)
         for (int i = 0; i < P; ++i) y[j][i] = x[jacobi_partner<M>(j, t)][i];
       for (int j = 0; j < G; ++j) {
         const int q = jacobi_partner<M>(j, t);
-        double gam = 0.0;
-        for (int i = 0; i < P; ++i) gam = std::fma(x[j][i], y[j][i], gam);
-        const bool first = j < q;
-        const double ap = first ? nrm[j] : nrm[q], aq = first ? nrm[q] : nrm[j];
-        double c = 1.0, s = 0.0;
-        if (q != j && hestenes_rotation(ap, aq, gam, c, s)) any = true;
-        const double sy = first ? -s : s;
-        for (int i = 0; i < P; ++i) x[j][i] = std::fma(sy, y[j][i], c * x[j][i]);
+        if (jacobi_update<P>(x[j], y[j], nrm[j], sn[j], nrm[q], sn[q], j, q)) any = true;
       }
     }
     if (!any) break;
   }
   double smax = 0.0, smin = INFINITY;
   for (int j = 0; j < P; ++j) {
-    double nrm = 0.0;
-    for (int i = 0; i < P; ++i) nrm = std::fma(x[j][i], x[j][i], nrm);
-    smax = std::fmax(smax, std::sqrt(nrm));
-    smin = std::fmin(smin, std::sqrt(nrm));
+    const double sv = std::sqrt(col_dot<P>(x[j], x[j]));
+    smax = std::fmax(smax, sv);
+    smin = std::fmin(smin, sv);
   }
   cond[e] = smin > 0.0 ? smax / smin : INFINITY;
   sweeps[e] = sw + 1;

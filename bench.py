@@ -33,7 +33,7 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 MEASURED_TRAFFIC = {
     "items_kernel<tidal,rot,mixed>": None,
     "items_kernel<tidal,rot>": None,
-    "fisher_kernel<tidal,rot>": 114.51e6,
+    "fisher_kernel<tidal,rot>": None,
     "waveform_kernel<rot,tidal>": 7849.06e6,
     "waveform_kernel<rot,tidal,mixed>": 7864.54e6,
 }

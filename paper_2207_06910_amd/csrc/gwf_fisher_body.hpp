@@ -9,8 +9,11 @@
 // dense contraction over frequency, X = sum_f a_f c_f^T with
 // a_f = (U_0..U_7, W c_0..W c_{NPI-1}) and c_f = (c_0..c_{NPI-1}): every
 // iteration each wavefront stages its 64 points' a_f and c_f in LDS and
-// folds them into a 16x16 FP64 accumulator with 16 MFMA 16x16x4 steps
-// (k = frequency), which keeps those 55 sums out of the lanes' registers.
+// folds them into 4x4 output tiles of X with the four-block FP64 MFMA
+// 4x4x4 (k = frequency), which keeps those sums out of the lanes' registers.
+// The 13 x 5 block (tides; 11 x 3 without) needs seven tiles (three): two
+// MFMAs (one) per four points, a quarter of the cycles of one 16x16x4 MFMA
+// per four points, which computes mostly padding.
 // The sums are then reduced in a fixed order (wavefront butterflies, then
 // the waves in index order), so results are bitwise reproducible.
 #pragma once
@@ -21,13 +24,13 @@ namespace gwf {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kRowsA = 16;        // 8 U rows, up to 5 W c rows, zero rows up to the MFMA size
-constexpr int kRowsB = 16;        // up to 5 c rows, zero rows up to the MFMA size
-constexpr int kTileLd = 64 + 1;   // odd row stride (doubles): the 64 lanes of an operand
-                                  // read (16 rows x 4 k-groups) fall in distinct banks
+constexpr int kRowsA = 16;        // 8 U rows, up to 5 W c rows, zero rows to a whole tile
+constexpr int kRowsB = 8;         // up to 5 c rows, zero rows to a whole tile
+constexpr int kZeroRowB = 7;      // a B row no point writes (operand of unused tile slots)
+constexpr int kZeroRowA = 15;
+constexpr int kTileLd = 64 + 4;   // row stride (doubles): an operand read touches 8 rows x
+                                  // 4 points, 2 (8 row + k) mod 64 distinct dword banks
 constexpr int kNaccMax = 91;
-
-typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <bool TIDAL>
 struct FisherDims {
@@ -35,6 +38,14 @@ struct FisherDims {
   static constexpr int NPI = P - 8;                  // phase-only parameters
   static constexpr int NG = 36, NX = 8 * NPI, NY = NPI * (NPI + 1) / 2;
   static constexpr int NACC = NG + NX + NY;          // SNR^2 = Gamma_{Phic,Phic}
+  // 4x4 output tiles (row group R of a_f, column group C of c_f) of the
+  // phase-only blocks: every tile of the U rows, and of the W c rows those
+  // holding an element of the upper triangle (4C + 3 >= 4R - 8)
+  static constexpr int RG = (8 + NPI + 3) / 4, CG = (NPI + 3) / 4;
+  static constexpr int NT = TIDAL ? 7 : 3;
+  static constexpr int NM = (NT + 3) / 4;            // MFMA accumulators (4 tiles each)
+  __host__ __device__ static constexpr int tile_r(int t) { return TIDAL ? (t < 4 ? t / 2 : t == 6 ? 3 : 2) : t; }
+  __host__ __device__ static constexpr int tile_c(int t) { return TIDAL ? (t < 4 ? t % 2 : t == 6 ? 1 : t - 4) : 0; }
 };
 
 // LDS working set of one workgroup.
@@ -68,9 +79,20 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
   double G[NG];
 #pragma unroll
   for (int i = 0; i < NG; ++i) G[i] = 0.0;
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  double acc[Dm::NM];
   const int wave = tid >> 6, lane = tid & 63;
-  const int mrow = lane & 15, mk = lane >> 4;      // MFMA operand position of this lane
+  // four-block MFMA 4x4x4 operand layout: lane 16 k + 4 q + i holds A[q][i][k]
+  // and B[q][k][i]; the result D[q][i][j] is in lane 16 i + 4 q + j.  Block q
+  // of accumulator m is tile 4 m + q; unused slots read zero rows.
+  const int kk = lane >> 4, q4 = (lane >> 2) & 3, i4 = lane & 3;
+  int arow[Dm::NM], bcol[Dm::NM];
+#pragma unroll
+  for (int m = 0; m < Dm::NM; ++m) {
+    acc[m] = 0.0;
+    const int t = 4 * m + q4;
+    arow[m] = t < Dm::NT ? 4 * Dm::tile_r(t) + i4 : kZeroRowA;
+    bcol[m] = t < Dm::NT ? 4 * Dm::tile_c(t) + i4 : kZeroRowB;
+  }
   double(*A)[kTileLd] = L.stA[wave];
   double(*B)[kTileLd] = L.stB[wave];
   // rows no point ever writes stay zero
@@ -101,12 +123,15 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
       B[i][lane] = cph[i];
     }
     __builtin_amdgcn_wave_barrier();
-    // X += A^T B over this wavefront's 64 points: k-step s takes points 16 mk + s
+    // X += A^T B over this wavefront's 64 points, four points per step
 #pragma unroll
     for (int s2 = 0; s2 < 16; ++s2) {
-      const double av = A[mrow][16 * mk + s2];
-      const double bv = B[mrow][16 * mk + s2];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+#pragma unroll
+      for (int m = 0; m < Dm::NM; ++m) {
+        const double av = A[arow[m]][4 * s2 + kk];
+        const double bv = B[bcol[m]][4 * s2 + kk];
+        acc[m] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, bv, acc[m], 0, 0, 0);
+      }
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -117,19 +142,21 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
     const double t = wave_sum(G[i]);
     if (lane == 0) L.red[wave][i] = t;
   }
-  // register r of lane (mk, mrow) holds accumulator element (4 r + mk, mrow):
-  // rows 0..7 are the U_b rows (cols 0..NPI-1), rows 8..8+NPI-1 the W c_i
-  // rows (upper triangle kept)
+  // lane 16 i + 4 q + j of accumulator m holds element (i, j) of tile 4 m + q:
+  // X rows 0..7 are the U_b rows (columns 0..NPI-1), rows 8..8+NPI-1 the
+  // W c_i rows (upper triangle kept)
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int row = 4 * r + mk, col = mrow;
+  for (int m = 0; m < Dm::NM; ++m) {
+    const int t = 4 * m + q4;
+    if (t >= Dm::NT) continue;
+    const int row = 4 * Dm::tile_r(t) + kk, col = 4 * Dm::tile_c(t) + i4;
     int slot = -1;
     if (row < 8 && col < NPI) slot = NG + row * NPI + col;
     else if (row >= 8 && row < 8 + NPI && col >= row - 8 && col < NPI) {
       const int i = row - 8;
       slot = NG + NX + i * NPI - (i * (i - 1)) / 2 + (col - i);
     }
-    if (slot >= 0) L.red[wave][slot] = acc[r];
+    if (slot >= 0) L.red[wave][slot] = acc[m];
   }
   __syncthreads();
   if (tid < NACC) {

@@ -31,11 +31,11 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # profiles/bns1e4_hbm_counters.md (calibrated against a 256 MiB copy: fetch
 # x 2.000, write x 1.000).  Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
-    "items_kernel<tidal,rot,mixed>": None,
-    "items_kernel<tidal,rot>": None,
-    "fisher_kernel<tidal,rot>": None,
-    "waveform_kernel<rot,tidal>": 7849.06e6,
-    "waveform_kernel<rot,tidal,mixed>": 7864.54e6,
+    "items_kernel<tidal,rot,mixed>": 58.29e6,
+    "items_kernel<tidal,rot>": 67.12e6,
+    "fisher_kernel<tidal,rot>": 113.94e6,
+    "waveform_kernel<rot,tidal>": 7848.22e6,
+    "waveform_kernel<rot,tidal,mixed>": 7858.03e6,
 }
 
 

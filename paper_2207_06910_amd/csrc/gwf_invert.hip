@@ -42,6 +42,15 @@ constexpr int kInvBlock = 64;              // one wavefront
 constexpr int kGroups = kInvBlock / kGroup;
 constexpr int kMaxSweeps = 40;
 
+// Workgroups are dealt to the 8 XCDs in turn (workgroup b to XCD b mod 8).
+// Renumbered so that each XCD takes one contiguous range of matrices, the
+// 128-byte lines of the [P][P][N] arrays (16 events, four workgroups) are
+// fetched into one XCD's L2 only.  A bijection on [0, nb) for any nb.
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t x = b % 8, t = b / 8, q = nb / 8, r = nb % 8;
+  return x * q + (x < r ? x : r) + t;
+}
+
 // At least 3 waves per SIMD: left free, the compiler spends all 256 registers
 // on load scheduling and a SIMD runs one wave of this latency-bound kernel.
 template <int P>
@@ -58,7 +67,7 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
   __shared__ double Ls[kGroups][P][LD];
   const int lane = threadIdx.x;
   const int g = lane / kGroup, j = lane % kGroup;
-  const int64_t e = (int64_t)blockIdx.x * kGroups + g;
+  const int64_t e = xcd_block(blockIdx.x, gridDim.x) * kGroups + g;
   const bool live = e < a.n;
   const bool own = live && j < P;          // lane owns a column of a real matrix
   const double nan = __builtin_nan("");

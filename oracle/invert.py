@@ -91,3 +91,88 @@ def covariance(fisher: np.ndarray, cond_max: float = 1e50, dps: int = 50, idx=No
             inv_err[k] = float(max(abs(R[i, j] - (1 if i == j else 0))
                                    for i in range(P) for j in range(P)))
     return {"cov": cov, "sigma": sigma, "cond": cond, "inv_err": inv_err, "status": status}
+
+
+# ---------------------------------------------------------------------------
+# Covariance epilogue (sec. 4.2 and the sky-localisation formula of sec. 4.1).
+#
+# Order, as the paper describes the manipulations: parameters held at their
+# fiducial values are removed from the Fisher matrix before inversion; a
+# diagonal Gaussian prior (its inverse variances) is added to the remaining
+# matrix before inversion; the result is inverted as above; the sky area is
+# taken from the covariance of the inverted matrix; parameters marginalised
+# over are removed from the covariance after inversion.
+
+def fix_params(fisher: np.ndarray, fixed) -> tuple[np.ndarray, np.ndarray]:
+    """Remove the rows and columns of the parameters in ``fixed`` (indices
+    into the P parameters) from fisher[P][P][N].  Returns the reduced matrix
+    and the original indices of the parameters it keeps, in order."""
+    P = fisher.shape[0]
+    keep = np.array([i for i in range(P) if i not in set(int(f) for f in fixed)], dtype=np.int64)
+    return fisher[np.ix_(keep, keep)], keep
+
+
+def add_prior(fisher: np.ndarray, values, idx) -> np.ndarray:
+    """Add values[k] to the diagonal entry idx[k] of every matrix (the
+    inverse variance of a Gaussian prior on that parameter)."""
+    out = np.array(fisher, dtype=np.float64, copy=True)
+    for v, i in zip(values, idx):
+        out[int(i), int(i)] += float(v)
+    return out
+
+
+def marginalise(cov: np.ndarray, over) -> tuple[np.ndarray, np.ndarray]:
+    """Remove the rows and columns of the parameters in ``over`` from the
+    covariance cov[P][P][N]; returns it and the indices kept."""
+    return fix_params(cov, over)
+
+
+def sky_area(cov: np.ndarray, theta: np.ndarray, i_theta: int, i_phi: int, perc_level: float = 90.0,
+             units: str = "SqDeg", dps: int = 30) -> np.ndarray:
+    """Sky localisation region containing perc_level percent of the
+    probability,
+        Delta Omega = -2 pi |sin theta| sqrt(C_tt C_pp - C_tp^2) ln(1 - X/100),
+    in steradians or square degrees, from the covariance entries of the
+    polar angle theta and the azimuth phi (NaN where the 2 x 2 determinant is
+    negative or an entry is not finite)."""
+    N = cov.shape[2]
+    out = np.full(N, np.nan)
+    with mp.workdps(dps):
+        lnq = mp.log(1 - mp.mpf(perc_level) / 100)
+        conv = (180 / mp.pi) ** 2 if units == "SqDeg" else mp.mpf(1)
+        for e in range(N):
+            ctt, cpp, ctp = cov[i_theta, i_theta, e], cov[i_phi, i_phi, e], cov[i_theta, i_phi, e]
+            if not (np.isfinite(ctt) and np.isfinite(cpp) and np.isfinite(ctp)):
+                continue
+            det = mp.mpf(float(ctt)) * mp.mpf(float(cpp)) - mp.mpf(float(ctp)) ** 2
+            if det < 0:
+                continue
+            out[e] = float(-2 * mp.pi * abs(mp.sin(mp.mpf(float(theta[e])))) * mp.sqrt(det) * lnq * conv)
+    return out
+
+
+def covariance_epilogue(fisher: np.ndarray, fixed=(), prior=None, marg=(), theta=None,
+                        i_theta: int = 3, i_phi: int = 4, perc_level: float = 90.0, units: str = "SqDeg",
+                        cond_max: float = 1e50, dps: int = 50):
+    """The manipulations in order: fix -> prior -> invert -> sky area ->
+    marginalise.  ``prior`` maps parameter index (of the full P) -> inverse
+    prior variance.  ``i_theta``/``i_phi`` are indices of the full P; both must
+    be kept for the sky area.  Returns the dictionary of ``covariance`` for
+    the inverted matrix, plus ``cov_out``/``sigma_out`` after
+    marginalisation, ``keep``/``out`` (original indices), ``sky`` and
+    ``fisher_inverted`` (the matrix that was inverted)."""
+    F, keep = fix_params(np.asarray(fisher, dtype=np.float64), fixed)
+    pos = {int(k): i for i, k in enumerate(keep)}
+    if prior:
+        F = add_prior(F, list(prior.values()), [pos[int(i)] for i in prior.keys()])
+    res = covariance(F, cond_max=cond_max, dps=dps)
+    res["fisher_inverted"] = F
+    res["keep"] = keep
+    if theta is not None:
+        res["sky"] = sky_area(res["cov"], np.asarray(theta), pos[i_theta], pos[i_phi], perc_level, units)
+    over = [pos[int(m)] for m in marg]
+    cov_out, kept_pos = marginalise(res["cov"], over)
+    res["cov_out"] = cov_out
+    res["sigma_out"] = res["sigma"][kept_pos]
+    res["out"] = keep[kept_pos]
+    return res

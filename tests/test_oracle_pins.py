@@ -540,3 +540,73 @@ def test_fisher_tangent_psd_scale_closed_form(orc):
         np.testing.assert_allclose(t["snr2"][1], -np.sum(r["snr_ifo"][arms] ** 2, axis=0), rtol=1e-12)
         Fs = r["fisher_ifo"][arms].sum(axis=0)
         np.testing.assert_allclose(t["fisher"][1], -Fs, rtol=1e-10, atol=1e-12 * np.abs(Fs).max())
+
+
+# ------------------------------------------------------------ covariance epilogue (sec. 4.1-4.2)
+def _two_by_two(a, b, c):
+    F = np.zeros((2, 2, 1))
+    F[:, :, 0] = [[a, b], [b, c]]
+    return F
+
+
+def test_fix_marginalise_prior_closed_forms(orc):
+    """2 x 2 Fisher [[a, b], [b, c]]: holding parameter 1 fixed leaves
+    sigma_0^2 = 1/a; marginalising over it gives the Schur-complement
+    variance c / (a c - b^2); a prior p on parameter 0 of a decoupled pair
+    gives 1 / (a + p)."""
+    a, b, c = 4.0, 1.5, 2.0
+    r = orc.covariance_epilogue(_two_by_two(a, b, c), fixed=[1], dps=40)
+    assert list(r["keep"]) == [0]
+    assert abs(r["cov_out"][0, 0, 0] - 1 / a) < 1e-15
+    r = orc.covariance_epilogue(_two_by_two(a, b, c), marg=[1], dps=40)
+    assert list(r["out"]) == [0]
+    assert abs(r["cov_out"][0, 0, 0] / (c / (a * c - b * b)) - 1) < 1e-14
+    assert abs(r["sigma_out"][0, 0] / math.sqrt(c / (a * c - b * b)) - 1) < 1e-14
+    r = orc.covariance_epilogue(_two_by_two(a, 0.0, c), prior={0: 0.25}, dps=40)
+    assert abs(r["cov_out"][0, 0, 0] / (1 / (a + 0.25)) - 1) < 1e-14
+    assert abs(r["cov_out"][1, 1, 0] / (1 / c) - 1) < 1e-14
+    # the matrix that was inverted carries the prior, and fixing then
+    # marginalising keeps the original order of the remaining parameters
+    assert r["fisher_inverted"][0, 0, 0] == a + 0.25
+    F = np.diag([1.0, 2.0, 3.0, 4.0, 5.0])[:, :, None] * np.ones((1, 1, 2))
+    r = orc.covariance_epilogue(F, fixed=[1], marg=[3], dps=30)
+    assert list(r["keep"]) == [0, 2, 3, 4] and list(r["out"]) == [0, 2, 4]
+    np.testing.assert_allclose(np.einsum("iie->ie", r["cov_out"]), [[1.0] * 2, [1 / 3] * 2, [1 / 5] * 2],
+                               rtol=1e-15)
+
+
+def test_sky_area_full_sphere_and_diagonal_case(orc):
+    """Units: 4 pi sr is 41252.96 square degrees.  A diagonal covariance
+    with sigma_theta = sigma_phi = 1e-2 rad at theta = pi/2 and the 90% level:
+    2 pi 1e-4 ln 10 sr."""
+    assert abs(4 * math.pi * (180 / math.pi) ** 2 - 41252.96125) < 1e-4
+    C = np.zeros((5, 5, 2))
+    C[3, 3] = C[4, 4] = 1e-4
+    th = np.array([math.pi / 2, math.pi / 6])
+    sr = orc.sky_area(C, th, 3, 4, 90.0, "Sterad")
+    np.testing.assert_allclose(sr, [2 * math.pi * 1e-4 * math.log(10), math.pi * 1e-4 * math.log(10)], rtol=1e-14)
+    deg = orc.sky_area(C, th, 3, 4, 90.0, "SqDeg")
+    np.testing.assert_allclose(deg / sr, (180 / math.pi) ** 2, rtol=1e-14)
+    C[3, 4] = C[4, 3] = 2e-4                        # determinant < 0: not a covariance
+    assert np.all(np.isnan(orc.sky_area(C, th, 3, 4)))
+
+
+def test_sky_area_contains_the_stated_probability(orc):
+    """Independent of the formula's algebra: draw (theta, phi) offsets from
+    the 2-D Gaussian of a correlated covariance, find the Mahalanobis radius
+    that holds 90% (and 50%) of them, and compare |sin theta| times the area
+    of that ellipse (pi r^2 sqrt(det C)) with the oracle's region."""
+    rng = np.random.default_rng(11)
+    Ctp = np.array([[4e-6, 1.5e-6], [1.5e-6, 2.5e-6]])
+    L = np.linalg.cholesky(Ctp)
+    x = rng.normal(size=(2, 2_000_000))
+    y = L @ x
+    m2 = np.einsum("in,ij,jn->n", y, np.linalg.inv(Ctp), y)
+    C = np.zeros((13, 13, 1))
+    C[3:5, 3:5, 0] = Ctp
+    th = np.array([1.1])
+    for level in (90.0, 50.0):
+        r2 = np.quantile(m2, level / 100)
+        mc = abs(math.sin(th[0])) * math.pi * r2 * math.sqrt(np.linalg.det(Ctp))
+        got = orc.sky_area(C, th, 3, 4, level, "Sterad")[0]
+        assert abs(got / mc - 1) < 3e-3, (level, got, mc)

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define GWF_VERSION 2
+#define GWF_VERSION 3
 
 /* ------------------------------------------------------------- statuses */
 typedef int32_t gwf_status;
@@ -242,7 +242,7 @@ gwf_status gwf_fisher_adjoint(const gwf_events* ev, const gwf_network* net, cons
  *   sigma    device [P][n], required      sqrt of the covariance diagonal
  *   cond     device [n] or NULL           condition number of the normalised
  *                                         matrix (ratio of extreme |eigenvalues|,
- *                                         cyclic Jacobi)
+ *                                         one-sided Jacobi)
  *   inv_err  device [n] or NULL           max_ij |(Gamma Cov - 1)_ij| (sec. 4.1)
  *   logdet   device [n] or NULL           ln det Gamma from the Cholesky factor of
  *                                         the normalised matrix and the diagonal
@@ -256,6 +256,52 @@ gwf_status gwf_fisher_adjoint(const gwf_events* ev, const gwf_network* net, cons
 gwf_status gwf_invert(int32_t P, int64_t n, const double* fisher, double cond_max,
                       double* cov, double* sigma, double* cond, double* inv_err,
                       double* logdet, int32_t* status, void* stream);
+
+/* Covariance manipulations (sec. 4.2) and the sky localisation region
+ * (sec. 4.1), around the inversion of gwf_invert, in this order:
+ *   1. parameters in fixed_mask are held at their fiducial values: their rows
+ *      and columns are removed from each Fisher matrix;
+ *   2. prior[i] (the inverse variance of a Gaussian prior on parameter i,
+ *      >= 0; 0 = none) is added to the diagonal of every kept parameter;
+ *   3. that matrix is inverted as by gwf_invert (cond, inv_err, logdet and
+ *      the status bits refer to it);
+ *   4. with sky_level > 0, the region holding sky_level percent of the
+ *      probability, -2 pi |sin theta| sqrt(C_tt C_pp - C_tp^2)
+ *      ln(1 - sky_level/100), from the covariance entries of parameters
+ *      i_theta and i_phi (NaN where that 2 x 2 determinant is negative);
+ *   5. parameters in marg_mask are marginalised over: their rows and
+ *      columns are left out of cov and sigma.
+ * Bit i of a mask is parameter i of the stored matrix (GWF_MC ... order for
+ * the Fisher output); fixed_mask and marg_mask must be disjoint and leave at
+ * least one parameter; theta and phi must not be fixed when the sky area is
+ * requested. */
+enum { GWF_SKY_STERAD = 0, GWF_SKY_SQDEG = 1 };
+
+typedef struct gwf_cov_opts {
+  uint32_t fixed_mask;              /* parameters held fixed (step 1)            */
+  uint32_t marg_mask;               /* parameters marginalised over (step 5)     */
+  double prior[GWF_NPAR_MAX];       /* inverse prior variances (step 2), host    */
+  double cond_max;                  /* as for gwf_invert; the paper's default 1e50 */
+  double sky_level;                 /* percent, 0 < level < 100; <= 0: no sky area */
+  int32_t i_theta, i_phi;           /* parameter indices of theta and phi
+                                       (GWF_THETA, GWF_PHI for Fisher output)    */
+  int32_t sky_units;                /* GWF_SKY_STERAD or GWF_SKY_SQDEG           */
+  int32_t pad;
+} gwf_cov_opts;
+
+/* P, n, fisher, status: as for gwf_invert (fisher is [P][P][n]).  With Po the
+ * number of parameters neither fixed nor marginalised, in their stored order:
+ *   cov      device [Po][Po][n] or NULL   covariance after marginalisation
+ *   sigma    device [Po][n], required
+ *   cond, inv_err, logdet   device [n] or NULL, of the matrix of step 3
+ *   theta    device [n], the events' polar angles; required with sky_level > 0
+ *   sky      device [n]; required with sky_level > 0, ignored otherwise
+ * opts is host memory read during the call.  Invalid masks, priors, levels
+ * or indices return GWF_E_INVALID_ARG before any launch. */
+gwf_status gwf_covariance(int32_t P, int64_t n, const double* fisher, const gwf_cov_opts* opts,
+                          const double* theta, double* cov, double* sigma, double* cond,
+                          double* inv_err, double* logdet, double* sky, int32_t* status,
+                          void* stream);
 
 /* ------------------------------------------------------ batched form */
 /* A plan runs the Fisher (and optionally the inversion) of one catalogue

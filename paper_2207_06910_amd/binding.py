@@ -56,6 +56,16 @@ class PlanInfo(ctypes.Structure):
 _lib = None
 
 
+class CovOptions(ctypes.Structure):
+    _fields_ = [("fixed_mask", ctypes.c_uint32), ("marg_mask", ctypes.c_uint32),
+                ("prior", ctypes.c_double * 13), ("cond_max", ctypes.c_double),
+                ("sky_level", ctypes.c_double), ("i_theta", ctypes.c_int32), ("i_phi", ctypes.c_int32),
+                ("sky_units", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+SKY_STERAD, SKY_SQDEG = 0, 1
+
+
 class GwfError(RuntimeError):
     pass
 
@@ -79,6 +89,9 @@ def load():
         lib.gwf_waveform.restype = i32
         lib.gwf_invert.argtypes = [i32, i64, vp, d, vp, vp, vp, vp, vp, vp, vp]
         lib.gwf_invert.restype = i32
+        lib.gwf_covariance.argtypes = [i32, i64, vp, ctypes.POINTER(CovOptions), vp, vp, vp, vp, vp, vp, vp,
+                                       vp, vp]
+        lib.gwf_covariance.restype = i32
         lib.gwf_fisher_adjoint.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
                                            ctypes.POINTER(Grid), ctypes.c_uint32, vp, vp, d, d,
                                            vp, vp, vp]
@@ -268,6 +281,52 @@ def invert(F, status=None, cond_max=1e50, want_cov=True, stream=None, out=None):
     _check(load().gwf_invert(P, n, _ptr(F), float(cond_max), _ptr(res.get("cov")),
                              _ptr(res["sigma"]), _ptr(res["cond"]), _ptr(res["inv_err"]),
                              _ptr(res["logdet"]), _ptr(st), _stream(stream)), "gwf_invert")
+    return res
+
+
+def covariance(F, status=None, fixed=(), prior=None, marg=(), theta=None, sky_level=90.0, units="SqDeg",
+               i_theta=3, i_phi=4, cond_max=1e50, want_cov=True, stream=None, out=None):
+    """Covariances of Fisher matrices F [P][P][N] after the manipulations of
+    gwf_covariance: parameters in ``fixed`` held at their fiducial values,
+    ``prior`` {index: inverse variance} added before inversion, parameters in
+    ``marg`` marginalised over; with ``theta`` [N] (device) the sky area at
+    ``sky_level`` percent in ``units`` ("SqDeg" or "Sterad").  Indices refer
+    to the P rows of F.  Returns cov [Po][Po][N], sigma [Po][N], cond, inv_err,
+    logdet, status, sky (if requested) and ``out``, the indices of F's rows
+    in cov and sigma."""
+    import torch
+    _dev_f64(F)
+    P, P2, n = F.shape
+    if P != P2:
+        raise GwfError("Fisher array must be [P][P][N]")
+    o = CovOptions()
+    o.fixed_mask = sum(1 << int(i) for i in set(fixed))
+    o.marg_mask = sum(1 << int(i) for i in set(marg))
+    for i, v in (prior or {}).items():
+        o.prior[int(i)] = float(v)
+    o.cond_max = float(cond_max)
+    o.i_theta, o.i_phi = int(i_theta), int(i_phi)
+    o.sky_units = {"SqDeg": SKY_SQDEG, "Sterad": SKY_STERAD}[units]
+    o.sky_level = float(sky_level) if theta is not None else 0.0
+    out_idx = [i for i in range(P) if not (o.fixed_mask >> i & 1) and not (o.marg_mask >> i & 1)]
+    po = len(out_idx)
+    dev = F.device
+    res = out if out is not None else {}
+    if want_cov:
+        res.setdefault("cov", torch.empty((po, po, n), dtype=torch.float64, device=dev))
+    res.setdefault("sigma", torch.empty((po, n), dtype=torch.float64, device=dev))
+    for k in ("cond", "inv_err", "logdet"):
+        res.setdefault(k, torch.empty(n, dtype=torch.float64, device=dev))
+    if theta is not None:
+        _dev_f64(theta)
+        res.setdefault("sky", torch.empty(n, dtype=torch.float64, device=dev))
+    st = status.clone() if status is not None else torch.zeros(n, dtype=torch.int32, device=dev)
+    res["status"] = st
+    _check(load().gwf_covariance(P, n, _ptr(F), ctypes.byref(o), _ptr(theta), _ptr(res.get("cov")),
+                                 _ptr(res["sigma"]), _ptr(res["cond"]), _ptr(res["inv_err"]),
+                                 _ptr(res["logdet"]), _ptr(res.get("sky")), _ptr(st), _stream(stream)),
+           "gwf_covariance")
+    res["out"] = out_idx
     return res
 
 

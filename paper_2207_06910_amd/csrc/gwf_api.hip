@@ -198,4 +198,64 @@ gwf_status gwf_invert(int32_t P, int64_t n, const double* fisher, double cond_ma
   return GWF_OK;
 }
 
+gwf_status gwf_covariance(int32_t P, int64_t n, const double* fisher, const gwf_cov_opts* opts,
+                          const double* theta, double* cov, double* sigma, double* cond,
+                          double* inv_err, double* logdet, double* sky, int32_t* status,
+                          void* stream) {
+  if (P < 1 || P > GWF_NPAR_MAX) return api_fail(GWF_E_INVALID_ARG, "P=%d outside 1..13", P);
+  if (n < 1) return api_fail(GWF_E_INVALID_ARG, "n=%lld must be >= 1", (long long)n);
+  if (!fisher || !sigma || !status || !opts)
+    return api_fail(GWF_E_INVALID_ARG, "fisher, opts, sigma and status are required");
+  const gwf_cov_opts& o = *opts;
+  const uint32_t all = (1u << P) - 1u;
+  if ((o.fixed_mask & ~all) || (o.marg_mask & ~all))
+    return api_fail(GWF_E_INVALID_ARG, "masks name parameters beyond P=%d", P);
+  if (o.fixed_mask & o.marg_mask)
+    return api_fail(GWF_E_INVALID_ARG, "a parameter cannot be both fixed and marginalised");
+  if (std::isnan(o.cond_max)) return api_fail(GWF_E_INVALID_ARG, "cond_max is NaN");
+  gwf::InvertArgs a{};
+  a.n = n; a.fisher = fisher; a.cond_max = o.cond_max; a.cov = cov; a.sigma = sigma;
+  a.cond = cond; a.inv_err = inv_err; a.logdet = logdet; a.status = status;
+  a.p_full = P;
+  int pk = 0, po = 0;
+  for (int i = 0; i < GWF_NPAR_MAX; ++i) { a.keep[i] = 0; a.out_pos[i] = -1; a.prior[i] = 0.0; }
+  a.i_theta = a.i_phi = -1;
+  for (int i = 0; i < P; ++i) {
+    if (o.fixed_mask >> i & 1u) continue;
+    if (!(o.prior[i] >= 0.0) || !std::isfinite(o.prior[i]))
+      return api_fail(GWF_E_INVALID_ARG, "prior[%d]=%g must be finite and >= 0", i, o.prior[i]);
+    a.keep[pk] = (int8_t)i;
+    a.prior[pk] = o.prior[i];
+    if (!(o.marg_mask >> i & 1u)) a.out_pos[pk] = (int8_t)po++;
+    if (i == o.i_theta) a.i_theta = pk;
+    if (i == o.i_phi) a.i_phi = pk;
+    ++pk;
+  }
+  for (int i = P; i < GWF_NPAR_MAX; ++i)
+    if (o.prior[i] != 0.0) return api_fail(GWF_E_INVALID_ARG, "prior[%d] set beyond P=%d", i, P);
+  if (po < 1) return api_fail(GWF_E_INVALID_ARG, "no parameter is left after fixing and marginalising");
+  a.n_out = po;
+  if (o.sky_level > 0.0) {
+    if (!(o.sky_level < 100.0)) return api_fail(GWF_E_INVALID_ARG, "sky_level=%g must be below 100", o.sky_level);
+    if (!theta || !sky) return api_fail(GWF_E_INVALID_ARG, "theta and sky are required for the sky area");
+    if (o.i_theta < 0 || o.i_theta >= P || o.i_phi < 0 || o.i_phi >= P || o.i_theta == o.i_phi)
+      return api_fail(GWF_E_INVALID_ARG, "i_theta=%d, i_phi=%d must be distinct indices below P", o.i_theta,
+                      o.i_phi);
+    if (a.i_theta < 0 || a.i_phi < 0) return api_fail(GWF_E_INVALID_ARG, "theta or phi is fixed");
+    if (o.sky_units != GWF_SKY_STERAD && o.sky_units != GWF_SKY_SQDEG)
+      return api_fail(GWF_E_INVALID_ARG, "sky_units=%d unknown", o.sky_units);
+    const double deg = 180.0 / 3.14159265358979323846;
+    a.sky_fac = -2.0 * 3.14159265358979323846 * std::log1p(-o.sky_level / 100.0) *
+                (o.sky_units == GWF_SKY_SQDEG ? deg * deg : 1.0);
+    a.theta = theta;
+    a.sky = sky;
+  } else {
+    a.i_theta = a.i_phi = -1;
+    a.sky = nullptr;
+  }
+  hipError_t err = gwf::launch_invert(a, pk, (hipStream_t)stream);
+  if (err != hipSuccess) return api_hip_fail(err, "covariance kernel launch");
+  return GWF_OK;
+}
+
 }  // extern "C"

@@ -51,6 +51,16 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
   return x * q + (x < r ? x : r) + t;
 }
 
+// Row j of the matrix that is inverted: the stored row of kept parameter j
+// restricted to the kept columns, with the prior added on the diagonal.
+template <int P>
+__device__ inline void load_row(const InvertArgs& a, int64_t e, int j, double* row) {
+  const int64_t rj = a.keep[j];
+#pragma unroll
+  for (int k = 0; k < P; ++k) row[k] = a.fisher[(rj * a.p_full + a.keep[k]) * a.n + e];
+  row[j] += a.prior[j];
+}
+
 // At least 3 waves per SIMD: left free, the compiler spends all 256 registers
 // on load scheduling and a SIMD runs one wave of this latency-bound kernel.
 template <int P>
@@ -75,11 +85,8 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
   int32_t st = live ? a.status[e] : kEvSkipped;
   const bool use = live && !(st & (kEvInvalid | kEvSkipped));
 
-  // ---- Gamma, row j per lane, into LDS
-  if (use && j < P) {
-#pragma unroll
-    for (int k = 0; k < P; ++k) Gs[g][j][k] = a.fisher[((int64_t)j * P + k) * a.n + e];
-  }
+  // ---- Gamma (kept rows and columns, prior on the diagonal), row j per lane, into LDS
+  if (use && j < P) load_row<P>(a, e, j, Gs[g][j]);
   __syncthreads();
 
   // column j of the upper triangle (h_i = Gamma_{min(i,j), max(i,j)}) and the diagonal
@@ -209,10 +216,7 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
   }
   __syncthreads();
   // Gamma again (L2-resident) for the residual
-  if (a.inv_err && ok && j < P) {
-#pragma unroll
-    for (int k = 0; k < P; ++k) Gs[g][j][k] = a.fisher[((int64_t)j * P + k) * a.n + e];
-  }
+  if (a.inv_err && ok && j < P) load_row<P>(a, e, j, Gs[g][j]);
   __syncthreads();
 
   // ---- outputs
@@ -238,13 +242,31 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
     else if (ill) st |= kEvIllCond;
     else if (!pd) st |= kEvNotPD;
   }
-  if (j < P) {
-    a.sigma[(int64_t)j * a.n + e] = ok ? sqrt(Ls[g][j][j]) : nan;
+  // column j of the covariance at its output position (marginalised
+  // parameters have none)
+  const int oj = j < P ? a.out_pos[j] : -1;
+  if (oj >= 0) {
+    const int64_t no = a.n_out;
+    a.sigma[oj * a.n + e] = ok ? sqrt(Ls[g][j][j]) : nan;
     if (a.cov)
 #pragma unroll
-      for (int k = 0; k < P; ++k) a.cov[((int64_t)k * P + j) * a.n + e] = ok ? cv[k] : nan;
+      for (int k = 0; k < P; ++k) {
+        const int ik = a.out_pos[k];
+        if (ik >= 0) a.cov[(ik * no + oj) * a.n + e] = ok ? cv[k] : nan;
+      }
   }
   if (j == 0) {
+    if (a.sky) {
+      // sky localisation region (sec. 4.1) from the theta-phi block
+      double area = nan;
+      if (ok) {
+        const double ctt = Ls[g][a.i_theta][a.i_theta], cpp = Ls[g][a.i_phi][a.i_phi];
+        const double ctp = Ls[g][a.i_phi][a.i_theta];
+        const double det = fma(ctt, cpp, -(ctp * ctp));
+        if (det >= 0.0) area = a.sky_fac * fabs(sin(a.theta[e])) * sqrt(det);
+      }
+      a.sky[e] = area;
+    }
     if (a.cond) a.cond[e] = go0 ? cond : nan;
     if (a.inv_err) a.inv_err[e] = ok ? err : nan;
     if (a.logdet) a.logdet[e] = ok ? 2.0 * ld : nan;
@@ -253,7 +275,19 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
 }
 
 template <int P>
-hipError_t launch_p(const InvertArgs& a, hipStream_t stream) {
+hipError_t launch_p(const InvertArgs& a0, hipStream_t stream) {
+  InvertArgs a = a0;
+  if (a.p_full == 0) {           // the whole matrix, no manipulations
+    a.p_full = P;
+    a.n_out = P;
+    for (int i = 0; i < 13; ++i) {
+      a.keep[i] = (int8_t)(i < P ? i : 0);
+      a.out_pos[i] = (int8_t)(i < P ? i : -1);
+      a.prior[i] = 0.0;
+    }
+    a.i_theta = a.i_phi = -1;
+    a.sky = nullptr;
+  }
   const unsigned blocks = (unsigned)((a.n + kGroups - 1) / kGroups);
   hipLaunchKernelGGL((invert_kernel<P>), dim3(blocks), dim3(kInvBlock), 0, stream, a);
   return hipGetLastError();

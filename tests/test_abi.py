@@ -23,7 +23,7 @@ def test_library_exports_every_declared_symbol():
     assert {"gwf_snr", "gwf_fisher", "gwf_invert"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.gwf_version() == 2
+    assert lib.gwf_version() == 3
 
 
 def test_network_interferometer_count():
@@ -73,6 +73,49 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.gwf_fisher_adjoint(B(ev), B(net), B(grid), 0, 8, None, float("inf"), 1.0, 8, 8, None) == 1
     assert lib.gwf_fisher_adjoint(B(ev), B(net), B(grid), 4, 8, None, 1.0, 1.0, 8, 8, None) == 2
     assert len(lib.gwf_last_error()) > 0
+
+
+def test_covariance_options_rejected_on_host():
+    """gwf_covariance: masks beyond P, fixed and marginalised overlapping,
+    nothing left, negative or non-finite priors, priors beyond P, a sky level
+    of 100% or more, theta or phi fixed or out of range, missing theta or sky
+    output, unknown units."""
+    lib = binding.load()
+    B = ctypes.byref
+
+    def opts(**kw):
+        o = binding.CovOptions()
+        o.cond_max = 1e50
+        o.i_theta, o.i_phi = 3, 4
+        for k, v in kw.items():
+            if k == "prior":
+                for i, x in v.items():
+                    o.prior[i] = x
+            else:
+                setattr(o, k, v)
+        return o
+
+    def call(o, P=13, theta=8, sky=8):
+        return lib.gwf_covariance(P, 3, 8, B(o), theta, None, 8, None, None, None, sky, 8, None)
+
+    assert lib.gwf_covariance(13, 3, 8, None, None, None, 8, None, None, None, None, 8, None) == 1
+    assert call(opts(fixed_mask=1 << 13)) == 1
+    assert call(opts(marg_mask=1 << 11), P=11) == 1
+    assert call(opts(fixed_mask=3, marg_mask=2)) == 1
+    assert b"both" in lib.gwf_last_error()
+    assert call(opts(fixed_mask=1, marg_mask=2), P=2) == 1
+    assert call(opts(prior={5: -1.0})) == 1
+    assert call(opts(prior={5: float("inf")})) == 1
+    assert call(opts(prior={12: 1.0}), P=11) == 1
+    assert call(opts(cond_max=float("nan"))) == 1
+    assert call(opts(sky_level=100.0)) == 1
+    assert call(opts(sky_level=90.0, fixed_mask=1 << 3)) == 1
+    assert b"fixed" in lib.gwf_last_error()
+    assert call(opts(sky_level=90.0, i_phi=3)) == 1
+    assert call(opts(sky_level=90.0, i_theta=13)) == 1
+    assert call(opts(sky_level=90.0), theta=None) == 1
+    assert call(opts(sky_level=90.0), sky=None) == 1
+    assert call(opts(sky_level=90.0, sky_units=2)) == 1
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

@@ -1,0 +1,153 @@
+"""GPU: the covariance manipulations and the sky area (gwf_covariance,
+sec. 4.1-4.2) against the oracle's mpmath epilogue on the same Fisher
+matrices.
+
+Tolerances as for the inversion: max(1e-9, 1e3 kappa u) relative for the
+condition number, sigma and the normalised covariance, u = 2^-53, kappa the
+condition number of the matrix that is inverted.  The sky area takes the
+square root of C_tt C_pp - C_tp^2, whose relative error is that of the
+entries times (C_tt C_pp + C_tp^2) / det; half of that enters the area.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2207_06910_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+# the paper's worked example: spins fixed, a Gaussian prior of variance
+# 2 pi^2 on the angles, the 90% region in square degrees; here the tidal
+# deformabilities are marginalised over as well
+FIXED = [9, 10]
+ANGLES = [3, 4, 5, 6, 8]
+PRIOR = {i: 1.0 / (2.0 * math.pi ** 2) for i in ANGLES}
+MARG = [11, 12]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2207_06910_amd import binding
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    binding.load()
+    return binding
+
+
+def _gpu(lib, F, theta=None, **kw):
+    Ft = torch.as_tensor(np.ascontiguousarray(F), device="cuda")
+    th = None if theta is None else torch.as_tensor(np.ascontiguousarray(theta, dtype=np.float64), device="cuda")
+    r = lib.covariance(Ft, theta=th, **kw)
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in r.items()}
+
+
+def _compare(g, ref, sky=True):
+    assert np.array_equal(g["status"], ref["status"])
+    assert list(g["out"]) == list(ref["out"])
+    ok = ref["status"] == 0
+    kap = ref["cond"]
+    tol = np.maximum(1e-9, 1e3 * kap * U)
+    assert np.all(np.abs(g["cond"] / kap - 1) <= tol)
+    relsig = np.abs(g["sigma"][:, ok] / ref["sigma_out"][:, ok] - 1).max(axis=0)
+    assert np.all(relsig <= tol[ok]), (relsig, tol[ok])
+    dc = np.sqrt(np.einsum("iie->ie", ref["cov_out"][:, :, ok]))
+    cerr = (np.abs(g["cov"][:, :, ok] - ref["cov_out"][:, :, ok]) / (dc[:, None, :] * dc[None, :, :])).max(axis=(0, 1))
+    assert np.all(cerr <= tol[ok])
+    assert np.all(g["inv_err"][ok] >= 0) and np.all(np.isnan(g["inv_err"][~ok]))
+    if sky:
+        C = ref["cov"]
+        it, ip = list(ref["keep"]).index(3), list(ref["keep"]).index(4)
+        ctt, cpp, ctp = C[it, it], C[ip, ip], C[it, ip]
+        amp = (np.abs(ctt * cpp) + ctp ** 2) / (ctt * cpp - ctp ** 2)
+        serr = np.abs(g["sky"][ok] / ref["sky"][ok] - 1)
+        assert np.all(serr <= tol[ok] * amp[ok]), (serr, tol[ok] * amp[ok])
+        assert np.all(np.isnan(g["sky"][~ok]))
+
+
+def test_epilogue_against_oracle(lib, orc):
+    """BNS Fisher matrices of the oracle: spins fixed, priors on the angles,
+    tides marginalised, 90% sky area in square degrees and in steradians."""
+    wl = synth.bns1e4(n=12).with_npts(2500)
+    F = orc.fisher(wl)["fisher"]
+    theta = wl.par[3]
+    for units in ("SqDeg", "Sterad"):
+        g = _gpu(lib, F, theta, fixed=FIXED, prior=PRIOR, marg=MARG, units=units)
+        ref = orc.covariance_epilogue(F, fixed=FIXED, prior=PRIOR, marg=MARG, theta=theta, units=units)
+        _compare(g, ref)
+    # 50% level, nothing fixed, only a prior
+    g = _gpu(lib, F, theta, prior={2: 1e-2}, sky_level=50.0)
+    ref = orc.covariance_epilogue(F, prior={2: 1e-2}, theta=theta, perc_level=50.0)
+    _compare(g, ref)
+
+
+def test_identity_options_equal_invert(lib, orc):
+    """No manipulation: every output bit equals gwf_invert's."""
+    wl = synth.bns1e4(n=64).with_npts(800)
+    F = torch.as_tensor(orc.fisher(wl)["fisher"], device="cuda")
+    a = lib.invert(F)
+    b = lib.covariance(F)
+    torch.cuda.synchronize()
+    for k in ("cov", "sigma", "cond", "inv_err", "logdet", "status"):
+        x, y = a[k].cpu().numpy(), b[k].cpu().numpy()
+        assert np.array_equal(x, y, equal_nan=x.dtype.kind == "f"), k
+
+
+def test_known_inverses(lib):
+    """Matrices A with set spectra (kappa <= 1e3 after normalisation): fixing
+    S leaves inv(A[~S, ~S]); a prior adds to the diagonal first;
+    marginalising keeps the block of that inverse."""
+    rng = np.random.default_rng(8)
+    P, n = 11, 40
+    F = np.zeros((P, P, n))
+    for e in range(n):
+        Q, _ = np.linalg.qr(rng.normal(size=(P, P)))
+        A = (Q * np.geomspace(1.0, 1e3, P)) @ Q.T
+        A = 0.5 * (A + A.T)
+        s = 10 ** rng.uniform(-2, 2, P)
+        F[:, :, e] = A * np.outer(s, s)
+    fixed, marg, prior = [1, 7], [0, 9], {2: 0.5, 4: 3.0}
+    keep = [i for i in range(P) if i not in fixed]
+    out = [i for i in keep if i not in marg]
+    g = _gpu(lib, F, fixed=fixed, marg=marg, prior=prior)
+    assert g["out"] == out
+    for e in range(n):
+        Fk = F[np.ix_(keep, keep, [e])][:, :, 0].copy()
+        for i, v in prior.items():
+            Fk[keep.index(i), keep.index(i)] += v
+        dk = np.sqrt(np.diag(Fk))                      # normalised: kappa <= 1e3, FP64 inverse to ~1e-13
+        C = np.linalg.inv(Fk / np.outer(dk, dk)) / np.outer(dk, dk)
+        pos = [keep.index(i) for i in out]
+        ref = C[np.ix_(pos, pos)]
+        d = np.sqrt(np.diag(ref))
+        assert np.max(np.abs(g["cov"][:, :, e] - ref) / np.outer(d, d)) < 1e-11
+        np.testing.assert_allclose(g["sigma"][:, e], d, rtol=1e-11)
+
+
+def test_full_catalogue_sampled_against_oracle(lib, orc):
+    """The 10^4-event BNS catalogue's Fisher matrices from the batched plan
+    (the benchmark configuration), the paper's example manipulations on all
+    of them; sampled events against the oracle's epilogue of the same
+    matrices; the sky area is finite and positive wherever the inversion
+    succeeded."""
+    wl = synth.bns1e4()
+    dw = lib.DeviceWorkload(wl)
+    plan = lib.Plan(dw, chunk=16384, wg_per_cu=4, use_graph=False)
+    F = plan.run()["fisher"]
+    theta = dw.par[3].contiguous()
+    r = lib.covariance(F, theta=theta, fixed=FIXED, prior=PRIOR, marg=MARG)
+    torch.cuda.synchronize()
+    st = r["status"].cpu().numpy()
+    sky = r["sky"].cpu().numpy()
+    ok = st == 0
+    assert ok.mean() > 0.95
+    assert np.all(np.isfinite(sky[ok]) & (sky[ok] > 0))
+    idx = np.random.default_rng(5).choice(wl.n, 8, replace=False)
+    Fs = F.cpu().numpy()[:, :, idx]
+    ref = orc.covariance_epilogue(Fs, fixed=FIXED, prior=PRIOR, marg=MARG, theta=wl.par[3][idx])
+    g = {k: (v.cpu().numpy()[..., idx] if hasattr(v, "cpu") else v) for k, v in r.items()}
+    _compare(g, ref)
+    plan.close()

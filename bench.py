@@ -271,6 +271,33 @@ def main():
     batched_ms, items_ms, info, batched_res = batched(False, args.chunk, args.wg_per_cu)
     mixed_ms, mitems_ms, minfo, mixed_res = batched(True, args.chunk, args.wg_per_cu)
 
+    # ---- covariance epilogue (gwf_covariance) on the plain form's Fisher matrices: the
+    # paper's worked example (spins fixed, Gaussian priors of variance 2 pi^2 on the
+    # angles, 90% sky area in square degrees) with the tidal deformabilities
+    # marginalised over
+    outc = {}
+    ckw = dict(theta=dw.par[3].contiguous(), fixed=(9, 10), marg=(11, 12), sky_level=90.0,
+               units="SqDeg", prior={i: 1.0 / (2.0 * np.pi ** 2) for i in (3, 4, 5, 6, 8)}, out=outc)
+    for i in range(2):
+        binding.covariance(outf["fisher"], outf["status"], **ckw)
+    tc = []
+    for i in range(args.steps):
+        ev[0].record(stream)
+        binding.covariance(outf["fisher"], outf["status"], **ckw)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        tc.append(ev[0].elapsed_time(ev[1]))
+    cov_ms = float(np.mean(tc))
+    stc, skyc = outc["status"].cpu().numpy(), outc["sky"].cpu().numpy()
+    log(f"covariance epilogue kernel {cov_ms:.3f} ms, inverted {int(np.sum(stc == 0))}/{wl.n}, "
+        f"median 90% sky area {float(np.median(skyc[stc == 0])):.3g} deg^2")
+    cov_form = {"covariance_epilogue": {
+        "workload": "bns1e4 Fisher matrices: chi1z, chi2z fixed; Gaussian priors of variance 2 pi^2 "
+                    "on theta, phi, iota, psi, Phicoal; Lambda1, Lambda2 marginalised; 90% sky area",
+        "kernel": "invert_kernel<11>", "kernel_ms": round(cov_ms, 4),
+        "events_per_s": round(wl.n / (cov_ms * 1e-3), 1), "inverted": int(np.sum(stc == 0)),
+        "median_sky_deg2": round(float(np.median(skyc[stc == 0])), 4)}}
+
     # ---- strain output (gwf_waveform): HBM-bound, 16 B per point and interferometer
     ends = torch.cumsum(dw.npts.to(torch.int64), 0)
     offsets = ends - dw.npts.to(torch.int64)
@@ -363,6 +390,7 @@ def main():
                                "n_items": minfo["n_items"], "graph": True}}
     for k, v in errs.items():
         forms[k]["errors_vs_oracle"] = v
+    forms.update(cov_form)
     forms.update(wave)
     forms.update(extra)
     out = {

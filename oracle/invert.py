@@ -9,6 +9,10 @@ paper's order:
    L^-T L^-1 (the default 'cho' method);
 3. undo the normalisation;
 
+or, on request, the SVD inversions the paper offers ('svd' with optional
+truncation of small singular values, 'svd_reg' leaving them out), and the
+SVD in place of a failed Cholesky (the paper's default behaviour);
+
 plus the diagnostics: the condition number (ratio of the largest to the
 smallest absolute eigenvalue, here of the normalised matrix), the
 threshold above which no inversion is attempted (default 1e50), and the
@@ -25,9 +29,11 @@ import numpy as np
 
 ST_NOT_PD = 2
 ST_ILL_COND = 4
+ST_SVD = 32          # Cholesky failed, inverted by SVD instead
 
 
-def _one(F: np.ndarray, cond_max: float, dps: int):
+def _one(F: np.ndarray, cond_max: float, dps: int, method: str = "cho", truncate: bool = False,
+         thresh: float = 1e-15):
     P = F.shape[0]
     with mp.workdps(dps):
         G = mp.matrix(P, P)
@@ -49,12 +55,18 @@ def _one(F: np.ndarray, cond_max: float, dps: int):
         status = 0
         if cond > cond_max:
             return None, float(cond), ST_ILL_COND
-        try:
-            L = mp.cholesky(Gh)
-        except ValueError:
-            return None, float(cond), ST_NOT_PD
-        Li = mp.inverse(L)
-        Ch = Li.T * Li
+        Ch = None
+        if method in ("cho", "cho_svd"):
+            try:
+                L = mp.cholesky(Gh)
+                Li = mp.inverse(L)
+                Ch = Li.T * Li
+            except ValueError:
+                if method == "cho":
+                    return None, float(cond), ST_NOT_PD
+                status = ST_SVD       # the paper's default: an SVD instead
+        if Ch is None:
+            Ch = _svd_inverse(Gh, method == "svd_reg", truncate and method == "svd", thresh)
         C = np.zeros((P, P))
         for i in range(P):
             for j in range(P):
@@ -62,11 +74,64 @@ def _one(F: np.ndarray, cond_max: float, dps: int):
         return C, float(cond), status
 
 
-def covariance(fisher: np.ndarray, cond_max: float = 1e50, dps: int = 50, idx=None):
+def _svd_inverse(Gh, drop: bool, truncate: bool, thresh: float):
+    """Inverse of Gh = U diag(s) V from its SVD, V^T diag(1/s) U^T (sec. 4.1):
+    with ``truncate`` every s below thresh * max(s) is raised to that value;
+    with ``drop`` (svd_reg) those singular values are left out."""
+    U, S, V = mp.svd_r(Gh)
+    P = Gh.rows
+    smax = max(S[i] for i in range(P))
+    w = []
+    for i in range(P):
+        s = S[i]
+        if s < thresh * smax:
+            if drop:
+                w.append(mp.mpf(0))
+                continue
+            if truncate:
+                s = thresh * smax
+        w.append(1 / s)
+    return V.T * mp.diag(w) * U.T
+
+
+def eigen(fisher: np.ndarray, dps: int = 50):
+    """Eigenvalues (ascending) and eigenvectors of each normalised Fisher
+    matrix (rows and columns divided by sqrt(diag), as for the inversion and
+    its condition number): eigval[P][N], eigvec[P][P][N] with column r the
+    eigenvector of eigenvalue r, signed so that its largest-magnitude
+    component is positive."""
+    P, _, N = fisher.shape
+    val = np.zeros((P, N))
+    vec = np.zeros((P, P, N))
+    for e in range(N):
+        with mp.workdps(dps):
+            G = mp.matrix([[mp.mpf(float(fisher[i, j, e])) for j in range(P)] for i in range(P)])
+            normalise = all(G[i, i] > 0 for i in range(P))
+            dn = [mp.sqrt(G[i, i]) if normalise else mp.mpf(1) for i in range(P)]
+            for i in range(P):
+                for j in range(P):
+                    G[i, j] = G[i, j] / (dn[i] * dn[j])
+            E, Q = mp.eigsy(G)
+            for r in range(P):
+                val[r, e] = float(E[r])
+                col = [Q[i, r] for i in range(P)]
+                big = max(range(P), key=lambda i: abs(col[i]))
+                sgn = 1 if col[big] > 0 else -1
+                for i in range(P):
+                    vec[i, r, e] = float(sgn * col[i])
+    return val, vec
+
+
+def covariance(fisher: np.ndarray, cond_max: float = 1e50, dps: int = 50, idx=None, method: str = "cho",
+               truncate: bool = False, svals_thresh: float = 1e-15):
     """Invert fisher[P][P][N] (events last).  Returns a dict with cov[P][P][n],
     sigma[P][n], cond[n], inv_err[n] and status[n] for the selected events
     (all events, or those in idx).  inv_err is eps evaluated exactly on the
-    FP64 values of Gamma and of the returned covariance."""
+    FP64 values of Gamma and of the returned covariance.  method: "cho"
+    (failed Cholesky flagged), "cho_svd" (the paper's default: an SVD where
+    the Cholesky fails, status ST_SVD), "svd" (with ``truncate``: singular
+    values below svals_thresh * max raised to it) or "svd_reg" (those left
+    out)."""
     P, _, N = fisher.shape
     idx = np.arange(N) if idx is None else np.asarray(idx)
     n = len(idx)
@@ -77,7 +142,7 @@ def covariance(fisher: np.ndarray, cond_max: float = 1e50, dps: int = 50, idx=No
     status = np.zeros(n, dtype=np.int32)
     for k, e in enumerate(idx):
         F = np.array(fisher[:, :, e], dtype=np.float64)
-        C, c, st = _one(F, cond_max, dps)
+        C, c, st = _one(F, cond_max, dps, method, truncate, svals_thresh)
         cond[k] = c
         status[k] = st
         if C is None:
@@ -153,7 +218,8 @@ def sky_area(cov: np.ndarray, theta: np.ndarray, i_theta: int, i_phi: int, perc_
 
 def covariance_epilogue(fisher: np.ndarray, fixed=(), prior=None, marg=(), theta=None,
                         i_theta: int = 3, i_phi: int = 4, perc_level: float = 90.0, units: str = "SqDeg",
-                        cond_max: float = 1e50, dps: int = 50):
+                        cond_max: float = 1e50, dps: int = 50, method: str = "cho", truncate: bool = False,
+                        svals_thresh: float = 1e-15):
     """The manipulations in order: fix -> prior -> invert -> sky area ->
     marginalise.  ``prior`` maps parameter index (of the full P) -> inverse
     prior variance.  ``i_theta``/``i_phi`` are indices of the full P; both must
@@ -165,7 +231,8 @@ def covariance_epilogue(fisher: np.ndarray, fixed=(), prior=None, marg=(), theta
     pos = {int(k): i for i, k in enumerate(keep)}
     if prior:
         F = add_prior(F, list(prior.values()), [pos[int(i)] for i in prior.keys()])
-    res = covariance(F, cond_max=cond_max, dps=dps)
+    res = covariance(F, cond_max=cond_max, dps=dps, method=method, truncate=truncate,
+                     svals_thresh=svals_thresh)
     res["fisher_inverted"] = F
     res["keep"] = keep
     if theta is not None:

@@ -610,3 +610,82 @@ def test_sky_area_contains_the_stated_probability(orc):
         mc = abs(math.sin(th[0])) * math.pi * r2 * math.sqrt(np.linalg.det(Ctp))
         got = orc.sky_area(C, th, 3, 4, level, "Sterad")[0]
         assert abs(got / mc - 1) < 3e-3, (level, got, mc)
+
+
+# ------------------------------------------------------------ SVD inversions and eigen-decomposition
+def test_svd_methods_closed_forms(orc):
+    """H = [[1, r], [r, 1]], r = 1 - 2^-50 (unit diagonal: the normalisation
+    is the identity), singular values 2 - 2^-50 and 2^-50 with vectors
+    (1, +-1)/sqrt 2.  Plain SVD: the exact inverse [[1, -r], [-r, 1]] / (1 - r^2);
+    svd_reg at 1e-15 leaves the small one out: [[1, 1], [1, 1]] / (2 s1);
+    truncation raises it to 1e-15 s1.  A Fisher matrix D H D (D diagonal)
+    gives D^-1 C D^-1."""
+    r = 1.0 - 2.0 ** -50
+    s1, s2 = 2.0 - 2.0 ** -50, 2.0 ** -50
+    D = np.array([3.0, 0.25])
+    F = np.zeros((2, 2, 1))
+    F[:, :, 0] = np.array([[1.0, r], [r, 1.0]]) * np.outer(D, D)
+    scale = np.outer(1 / D, 1 / D)
+    exact = np.array([[1.0, -r], [-r, 1.0]]) / (s1 * s2)     # 1 - r^2 = s1 s2
+    reg = np.full((2, 2), 1.0 / (2 * s1))
+    t = 1e-15 * s1
+    trunc = np.array([[1 / s1 + 1 / t, 1 / s1 - 1 / t], [1 / s1 - 1 / t, 1 / s1 + 1 / t]]) / 2
+    for method, kw, ref in (("svd", {}, exact), ("svd_reg", {}, reg), ("svd", {"truncate": True}, trunc)):
+        C = orc.covariance(F, method=method, **kw)["cov"][:, :, 0]
+        np.testing.assert_allclose(C, ref * scale, rtol=1e-13, err_msg=method)
+
+
+def test_svd_inverse_against_lu_inverse(orc):
+    """Away from truncation the SVD inverse is the inverse: for positive
+    definite and for indefinite matrices of set spectra it equals mpmath's LU
+    inverse of the same matrix; 'cho_svd' matches 'cho' where the Cholesky
+    succeeds and is the SVD inverse, with status 32, where it fails."""
+    rng = np.random.default_rng(21)
+    P, n = 6, 4
+    F = np.zeros((P, P, n))
+    for e in range(n):
+        Q, _ = np.linalg.qr(rng.normal(size=(P, P)))
+        lam = np.geomspace(1.0, 1e4, P)
+        if e >= 2:
+            lam[[1, 4]] *= -1                      # indefinite, positive diagonal kept below
+        A = (Q * lam) @ Q.T
+        A = 0.5 * (A + A.T) + np.eye(P) * (2.0 * np.abs(np.diag(A)).max() if e >= 2 else 0.0)
+        F[:, :, e] = A
+    for e in range(n):
+        with mp.workdps(40):
+            ref = mp.inverse(mp.matrix(F[:, :, e].tolist()))
+            ref = np.array([[float(ref[i, j]) for j in range(P)] for i in range(P)])
+        d = np.sqrt(np.abs(np.diag(ref)))
+        for method in ("svd", "cho_svd"):
+            g = orc.covariance(F[:, :, e:e + 1], method=method)
+            assert np.max(np.abs(g["cov"][:, :, 0] - ref) / np.outer(d, d)) < 1e-12, (e, method)
+    cho = orc.covariance(F, method="cho")
+    chs = orc.covariance(F, method="cho_svd")
+    pd = cho["status"] == 0
+    np.testing.assert_array_equal(chs["cov"][:, :, pd], cho["cov"][:, :, pd])
+    assert np.all(chs["status"][~pd] == 32) and np.all(cho["status"][~pd] == 2)
+
+
+def test_eigen_decomposition_properties(orc):
+    """eigen(): the 2 x 2 unit-diagonal case has eigenvalues 1 -+ r; in
+    general the columns are orthonormal, reconstruct the normalised matrix,
+    come in ascending order and have a positive largest component."""
+    r = 0.3
+    F = np.zeros((2, 2, 1))
+    F[:, :, 0] = [[4.0, r], [r, 0.25]]          # normalised: [[1, r], [r, 1]] (sqrt(4 x 0.25) = 1)
+    val, vec = orc.eigen(F)
+    np.testing.assert_allclose(val[:, 0], [1 - r, 1 + r], rtol=1e-15)
+    rng = np.random.default_rng(4)
+    P = 7
+    A = rng.normal(size=(P, P))
+    A = A @ A.T + np.eye(P)
+    F = A[:, :, None]
+    val, vec = orc.eigen(F)
+    d = np.sqrt(np.diag(A))
+    H = A / np.outer(d, d)
+    Q = vec[:, :, 0]
+    np.testing.assert_allclose(Q.T @ Q, np.eye(P), atol=1e-14)
+    np.testing.assert_allclose((Q * val[:, 0]) @ Q.T, H, atol=1e-13)
+    assert np.all(np.diff(val[:, 0]) > 0)
+    big = np.abs(Q).argmax(axis=0)
+    assert np.all(Q[big, np.arange(P)] > 0)

@@ -66,7 +66,10 @@ enum {
   GWF_EV_NOT_PD = 2,        /* Cholesky of the normalised Fisher failed     */
   GWF_EV_ILL_COND = 4,      /* condition number above cond_max: not inverted */
   GWF_EV_NONFINITE = 8,     /* a non-finite parameter or result            */
-  GWF_EV_SKIPPED_SNR = 16   /* SNR <= snr_th: Fisher not computed           */
+  GWF_EV_SKIPPED_SNR = 16,  /* SNR <= snr_th: Fisher not computed           */
+  GWF_EV_SVD = 32           /* gwf_covariance with GWF_INV_CHO_SVD: the
+                               Cholesky failed and the matrix was inverted
+                               by SVD instead (outputs are set)              */
 };
 
 /* --------------------------------------------------------- parameters */
@@ -277,6 +280,17 @@ gwf_status gwf_invert(int32_t P, int64_t n, const double* fisher, double cond_ma
  * requested. */
 enum { GWF_SKY_STERAD = 0, GWF_SKY_SQDEG = 1 };
 
+/* Inversion methods (sec. 4.1; the paper's 'cho' with its SVD fallback,
+ * 'svd', 'svd_reg'), applied to the normalised matrix:
+ *   GWF_INV_CHO      Cholesky; a failure is flagged GWF_EV_NOT_PD (gwf_invert)
+ *   GWF_INV_CHO_SVD  Cholesky, and an SVD where it fails (GWF_EV_SVD)
+ *   GWF_INV_SVD      SVD, H^-1 = V diag(1/s) U^T; with truncate, singular
+ *                    values below svals_thresh x max(s) are raised to it
+ *   GWF_INV_SVD_REG  SVD, singular values below svals_thresh x max(s) left out
+ * The SVD is the one-sided Jacobi of the condition number, run again with
+ * the rotations accumulated; it also gives the eigen-decomposition. */
+enum { GWF_INV_CHO = 0, GWF_INV_CHO_SVD = 1, GWF_INV_SVD = 2, GWF_INV_SVD_REG = 3 };
+
 typedef struct gwf_cov_opts {
   uint32_t fixed_mask;              /* parameters held fixed (step 1)            */
   uint32_t marg_mask;               /* parameters marginalised over (step 5)     */
@@ -286,7 +300,11 @@ typedef struct gwf_cov_opts {
   int32_t i_theta, i_phi;           /* parameter indices of theta and phi
                                        (GWF_THETA, GWF_PHI for Fisher output)    */
   int32_t sky_units;                /* GWF_SKY_STERAD or GWF_SKY_SQDEG           */
+  int32_t method;                   /* GWF_INV_*                                 */
+  int32_t truncate;                 /* GWF_INV_SVD: raise small singular values  */
   int32_t pad;
+  double svals_thresh;              /* ratio to the largest singular value; the
+                                       paper's default is 1e-15                  */
 } gwf_cov_opts;
 
 /* P, n, fisher, status: as for gwf_invert (fisher is [P][P][n]).  With Po the
@@ -296,12 +314,19 @@ typedef struct gwf_cov_opts {
  *   cond, inv_err, logdet   device [n] or NULL, of the matrix of step 3
  *   theta    device [n], the events' polar angles; required with sky_level > 0
  *   sky      device [n]; required with sky_level > 0, ignored otherwise
- * opts is host memory read during the call.  Invalid masks, priors, levels
- * or indices return GWF_E_INVALID_ARG before any launch. */
+ *   eigval   device [Pk][n] or NULL, eigvec device [Pk][Pk][n] or NULL: the
+ *            eigen-decomposition (the paper's CheckFisher) of the normalised
+ *            matrix of step 3 (Pk parameters, fixed ones removed): eigenvalues
+ *            ascending, eigvec[i][r] component i of eigenvector r, signed so
+ *            that its largest-magnitude component is positive; NaN for events
+ *            not processed (invalid, skipped or non-finite)
+ * opts is host memory read during the call.  Invalid masks, priors, levels,
+ * indices or methods return GWF_E_INVALID_ARG before any launch.  ln det is
+ * NaN where the SVD inverts a matrix with a non-positive eigenvalue. */
 gwf_status gwf_covariance(int32_t P, int64_t n, const double* fisher, const gwf_cov_opts* opts,
                           const double* theta, double* cov, double* sigma, double* cond,
-                          double* inv_err, double* logdet, double* sky, int32_t* status,
-                          void* stream);
+                          double* inv_err, double* logdet, double* sky, double* eigval,
+                          double* eigvec, int32_t* status, void* stream);
 
 /* ------------------------------------------------------ batched form */
 /* A plan runs the Fisher (and optionally the inversion) of one catalogue

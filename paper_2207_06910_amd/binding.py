@@ -60,10 +60,12 @@ class CovOptions(ctypes.Structure):
     _fields_ = [("fixed_mask", ctypes.c_uint32), ("marg_mask", ctypes.c_uint32),
                 ("prior", ctypes.c_double * 13), ("cond_max", ctypes.c_double),
                 ("sky_level", ctypes.c_double), ("i_theta", ctypes.c_int32), ("i_phi", ctypes.c_int32),
-                ("sky_units", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("sky_units", ctypes.c_int32), ("method", ctypes.c_int32), ("truncate", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("svals_thresh", ctypes.c_double)]
 
 
 SKY_STERAD, SKY_SQDEG = 0, 1
+INV_METHODS = {"cho": 0, "cho_svd": 1, "svd": 2, "svd_reg": 3}
 
 
 class GwfError(RuntimeError):
@@ -90,7 +92,7 @@ def load():
         lib.gwf_invert.argtypes = [i32, i64, vp, d, vp, vp, vp, vp, vp, vp, vp]
         lib.gwf_invert.restype = i32
         lib.gwf_covariance.argtypes = [i32, i64, vp, ctypes.POINTER(CovOptions), vp, vp, vp, vp, vp, vp, vp,
-                                       vp, vp]
+                                       vp, vp, vp, vp]
         lib.gwf_covariance.restype = i32
         lib.gwf_fisher_adjoint.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
                                            ctypes.POINTER(Grid), ctypes.c_uint32, vp, vp, d, d,
@@ -285,7 +287,8 @@ def invert(F, status=None, cond_max=1e50, want_cov=True, stream=None, out=None):
 
 
 def covariance(F, status=None, fixed=(), prior=None, marg=(), theta=None, sky_level=90.0, units="SqDeg",
-               i_theta=3, i_phi=4, cond_max=1e50, want_cov=True, stream=None, out=None):
+               i_theta=3, i_phi=4, cond_max=1e50, method="cho", truncate=False, svals_thresh=1e-15,
+               eigen=False, want_cov=True, stream=None, out=None):
     """Covariances of Fisher matrices F [P][P][N] after the manipulations of
     gwf_covariance: parameters in ``fixed`` held at their fiducial values,
     ``prior`` {index: inverse variance} added before inversion, parameters in
@@ -293,7 +296,9 @@ def covariance(F, status=None, fixed=(), prior=None, marg=(), theta=None, sky_le
     ``sky_level`` percent in ``units`` ("SqDeg" or "Sterad").  Indices refer
     to the P rows of F.  Returns cov [Po][Po][N], sigma [Po][N], cond, inv_err,
     logdet, status, sky (if requested) and ``out``, the indices of F's rows
-    in cov and sigma."""
+    in cov and sigma.  ``method``: "cho", "cho_svd", "svd" (with
+    ``truncate``) or "svd_reg"; ``eigen``: also eigval [Pk][N] and eigvec
+    [Pk][Pk][N] of the normalised matrix that is inverted."""
     import torch
     _dev_f64(F)
     P, P2, n = F.shape
@@ -308,6 +313,9 @@ def covariance(F, status=None, fixed=(), prior=None, marg=(), theta=None, sky_le
     o.i_theta, o.i_phi = int(i_theta), int(i_phi)
     o.sky_units = {"SqDeg": SKY_SQDEG, "Sterad": SKY_STERAD}[units]
     o.sky_level = float(sky_level) if theta is not None else 0.0
+    o.method = INV_METHODS[method]
+    o.truncate = int(bool(truncate))
+    o.svals_thresh = float(svals_thresh)
     out_idx = [i for i in range(P) if not (o.fixed_mask >> i & 1) and not (o.marg_mask >> i & 1)]
     po = len(out_idx)
     dev = F.device
@@ -320,11 +328,16 @@ def covariance(F, status=None, fixed=(), prior=None, marg=(), theta=None, sky_le
     if theta is not None:
         _dev_f64(theta)
         res.setdefault("sky", torch.empty(n, dtype=torch.float64, device=dev))
+    pk = P - len(set(fixed))
+    if eigen:
+        res.setdefault("eigval", torch.empty((pk, n), dtype=torch.float64, device=dev))
+        res.setdefault("eigvec", torch.empty((pk, pk, n), dtype=torch.float64, device=dev))
     st = status.clone() if status is not None else torch.zeros(n, dtype=torch.int32, device=dev)
     res["status"] = st
     _check(load().gwf_covariance(P, n, _ptr(F), ctypes.byref(o), _ptr(theta), _ptr(res.get("cov")),
                                  _ptr(res["sigma"]), _ptr(res["cond"]), _ptr(res["inv_err"]),
-                                 _ptr(res["logdet"]), _ptr(res.get("sky")), _ptr(st), _stream(stream)),
+                                 _ptr(res["logdet"]), _ptr(res.get("sky")), _ptr(res.get("eigval")),
+                                 _ptr(res.get("eigvec")), _ptr(st), _stream(stream)),
            "gwf_covariance")
     res["out"] = out_idx
     return res

@@ -200,8 +200,8 @@ gwf_status gwf_invert(int32_t P, int64_t n, const double* fisher, double cond_ma
 
 gwf_status gwf_covariance(int32_t P, int64_t n, const double* fisher, const gwf_cov_opts* opts,
                           const double* theta, double* cov, double* sigma, double* cond,
-                          double* inv_err, double* logdet, double* sky, int32_t* status,
-                          void* stream) {
+                          double* inv_err, double* logdet, double* sky, double* eigval,
+                          double* eigvec, int32_t* status, void* stream) {
   if (P < 1 || P > GWF_NPAR_MAX) return api_fail(GWF_E_INVALID_ARG, "P=%d outside 1..13", P);
   if (n < 1) return api_fail(GWF_E_INVALID_ARG, "n=%lld must be >= 1", (long long)n);
   if (!fisher || !sigma || !status || !opts)
@@ -213,7 +213,16 @@ gwf_status gwf_covariance(int32_t P, int64_t n, const double* fisher, const gwf_
   if (o.fixed_mask & o.marg_mask)
     return api_fail(GWF_E_INVALID_ARG, "a parameter cannot be both fixed and marginalised");
   if (std::isnan(o.cond_max)) return api_fail(GWF_E_INVALID_ARG, "cond_max is NaN");
+  if (o.method < GWF_INV_CHO || o.method > GWF_INV_SVD_REG)
+    return api_fail(GWF_E_INVALID_ARG, "method=%d unknown", o.method);
+  if (o.method >= GWF_INV_SVD && !(o.svals_thresh >= 0.0 && o.svals_thresh < 1.0))
+    return api_fail(GWF_E_INVALID_ARG, "svals_thresh=%g must be in [0, 1)", o.svals_thresh);
   gwf::InvertArgs a{};
+  a.method = o.method;
+  a.truncate = o.truncate != 0;
+  a.svals_thresh = o.method >= GWF_INV_SVD ? o.svals_thresh : 0.0;
+  a.eigval = eigval;
+  a.eigvec = eigvec;
   a.n = n; a.fisher = fisher; a.cond_max = o.cond_max; a.cov = cov; a.sigma = sigma;
   a.cond = cond; a.inv_err = inv_err; a.logdet = logdet; a.status = status;
   a.p_full = P;

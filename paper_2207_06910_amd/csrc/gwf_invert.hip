@@ -61,6 +61,25 @@ __device__ inline void load_row(const InvertArgs& a, int64_t e, int j, double* r
   row[j] += a.prior[j];
 }
 
+// Column j of the normalised matrix (the kept upper triangle with the prior
+// on the diagonal, divided by d_i d_j), the same bits as the values the
+// kernel starts from; zeros where valid is false.
+template <int P>
+__device__ inline void load_col(const InvertArgs& a, int64_t e, int j, bool valid, const double* d,
+                                double dj, double* h) {
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    double v = 0.0;
+    if (valid) {
+      const int r = i <= j ? i : j, c = i <= j ? j : i;
+      v = a.fisher[((int64_t)a.keep[r] * a.p_full + a.keep[c]) * a.n + e];
+      if (i == j) v += a.prior[j];
+      v = v / (d[i] * dj);
+    }
+    h[i] = v;
+  }
+}
+
 // At least 3 waves per SIMD: left free, the compiler spends all 256 registers
 // on load scheduling and a SIMD runs one wave of this latency-bound kernel.
 template <int P>
@@ -171,7 +190,7 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
       l[k] = inv;
     }
   }
-  const bool ok = go0 && !ill && pd;
+  bool ok = go0 && !ill && pd;
 
   // ln det Gamma = 2 sum_i ln(d_i L_ii)
   double ld = own ? log(dj * ljj) : 0.0;
@@ -215,6 +234,132 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
     }
   }
   __syncthreads();
+
+  // ---- SVD inversions and eigen-decomposition, on request: the one-sided
+  // Jacobi again from the normalised columns, now accumulating the rotations
+  // V, so that H V = X = U diag(s) with orthonormal U and V; then
+  // H^-1 = V diag(w) U^T with w = 1/s (or the paper's truncated or dropped
+  // small singular values), and eigenvalue j = sign(u_j . v_j) s_j with
+  // eigenvector v_j.  Only wavefronts holding such a matrix run it.
+  const bool svd_grp = go0 && !ill && (a.method >= 2 || (a.method == 1 && !pd));
+  const bool want_eig = a.eigval != nullptr || a.eigvec != nullptr;
+  bool svd_done = false;
+  if (__any(svd_grp) || want_eig) {
+    // the normalisation again from the stored diagonal (the same bits as d;
+    // recomputed so that d need not stay in registers through this block)
+    double dn[P], dnj = 1.0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int64_t ki = a.keep[i];
+      dn[i] = (go0 && normalise) ? sqrt(a.fisher[(ki * a.p_full + ki) * a.n + e] + a.prior[i]) : 1.0;
+      if (i == j) dnj = dn[i];
+    }
+    double xs[P], vs[P];
+    load_col<P>(a, e, j, go0 && j < P, dn, dnj, xs);
+#pragma unroll
+    for (int i = 0; i < P; ++i) vs[i] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+      bool rotated = false;
+#pragma unroll 1
+      for (int t = 0; t < M - 1; ++t) {
+        const int q = jacobi_partner<M>(j, t);
+        const double nx = col_dot<P>(xs, xs), sx = sqrt(nx);
+        double y[P], yv[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          y[i] = __shfl(xs[i], q, kGroup);
+          yv[i] = __shfl(vs[i], q, kGroup);
+        }
+        const double ny = __shfl(nx, q, kGroup), sy = __shfl(sx, q, kGroup);
+        double c, sg;
+        if (jacobi_pair<P>(xs, y, nx, sx, ny, sy, j, q, c, sg)) rotated = true;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          xs[i] = fma(sg, y[i], c * xs[i]);
+          vs[i] = fma(sg, yv[i], c * vs[i]);
+        }
+      }
+      if (!__any(rotated)) break;
+    }
+    const double sj = sqrt(col_dot<P>(xs, xs));
+    double smx = own ? sj : 0.0;
+#pragma unroll
+    for (int off = kGroup / 2; off >= 1; off >>= 1) smx = fmax(smx, __shfl_xor(smx, off, kGroup));
+    const double inv_s = sj > 0.0 ? 1.0 / sj : 0.0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) xs[i] *= inv_s;                    // u_j
+    const double lam = col_dot<P>(xs, vs) >= 0.0 ? sj : -sj;
+
+    if (want_eig) {
+      // ascending position of this eigenvalue; eigenvector signed so that
+      // its largest-magnitude component (the first, on ties) is positive
+      int rank = 0;
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        const double lm = __shfl(lam, m, kGroup);
+        if (lm < lam || (lm == lam && m < j)) ++rank;
+      }
+      double bv = -1.0, bs = 1.0;
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+        if (fabs(vs[i]) > bv) { bv = fabs(vs[i]); bs = vs[i]; }
+      const double fl = bs < 0.0 ? -1.0 : 1.0;
+      if (live && j < P) {
+        if (a.eigval) a.eigval[(int64_t)rank * a.n + e] = go0 ? lam : nan;
+        if (a.eigvec)
+#pragma unroll
+          for (int i = 0; i < P; ++i) a.eigvec[((int64_t)i * P + rank) * a.n + e] = go0 ? fl * vs[i] : nan;
+      }
+    }
+
+    // H^-1 = V diag(w) U^T: U and w into Gs (w in the padding column), V
+    // into Ls, then column j of the upper triangle, both triangles into Ls
+    const double thr = a.svals_thresh * smx;
+    double w = inv_s;
+    if (sj < thr) {
+      if (a.method == 3) w = 0.0;
+      else if (a.method == 2 && a.truncate) w = 1.0 / thr;
+    }
+    if (svd_grp && j < P) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        Gs[g][j][i] = xs[i];
+        Ls[g][j][i] = vs[i];
+      }
+      Gs[g][j][P] = w;
+    }
+    __syncthreads();
+    double cc[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      double t = 0.0;
+      if (svd_grp && j < P)
+#pragma unroll
+        for (int m = 0; m < P; ++m) t = fma(Ls[g][m][i] * Gs[g][m][P], Gs[g][m][j], t);
+      cc[i] = t;
+    }
+    __syncthreads();
+    if (svd_grp && j < P) {
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+        if (i <= j) {
+          const double cij = cc[i] / (dn[i] * dnj);
+          Ls[g][j][i] = cij;
+          Ls[g][i][j] = cij;
+        }
+    }
+    __syncthreads();
+    // ln det Gamma from the singular values where the Cholesky failed and all
+    // eigenvalues are positive
+    double lsv = own ? fma(2.0, log(dnj), log(sj)) : 0.0;
+#pragma unroll
+    for (int off = kGroup / 2; off >= 1; off >>= 1) lsv += __shfl_xor(lsv, off, kGroup);
+    const uint64_t negm = __ballot(own && !(lam > 0.0));
+    const bool allpos = ((negm >> (g * kGroup)) & 0xffffull) == 0;
+    if (svd_grp && !pd) ld = allpos ? lsv : nan;
+    svd_done = svd_grp;
+    ok = ok || svd_done;
+  }
   // Gamma again (L2-resident) for the residual
   if (a.inv_err && ok && j < P) load_row<P>(a, e, j, Gs[g][j]);
   __syncthreads();
@@ -240,7 +385,8 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
   if (use) {
     if (nonfinite) st |= kEvNonFinite;
     else if (ill) st |= kEvIllCond;
-    else if (!pd) st |= kEvNotPD;
+    else if (!pd && !svd_done) st |= kEvNotPD;
+    else if (!pd && a.method == 1) st |= kEvSvd;
   }
   // column j of the covariance at its output position (marginalised
   // parameters have none)

@@ -76,17 +76,28 @@ __host__ __device__ inline double col_dot(const double* x, const double* y) {
 // One column's part of a Jacobi step: x is column j, y its partner column q
 // (q == j: no partner), nx = x . x, sx = sqrt(nx) and ny, sy the same for y,
 // each as its owner computed them.  Both columns of a pair compute the same
-// rotation from the same bits and update themselves.  Returns true if the
-// pair was rotated.
+// rotation from the same bits; the new column is c x + sg y.  Returns true
+// if the pair was rotated (c = 1, sg = 0 otherwise).
 template <int P>
-__host__ __device__ inline bool jacobi_update(double* x, const double* y, double nx, double sx, double ny,
-                                              double sy, int j, int q) {
+__host__ __device__ inline bool jacobi_pair(const double* x, const double* y, double nx, double sx, double ny,
+                                            double sy, int j, int q, double& c, double& sg) {
+  c = 1.0;
+  sg = 0.0;
   if (q == j) return false;
   const double gam = col_dot<P>(x, y);
   const bool first = j < q;
-  double c, s;
+  double s;
   const bool rot = hestenes_rotation(first ? nx : ny, first ? ny : nx, gam, sx * sy, c, s);
-  const double sg = first ? -s : s;
+  sg = first ? -s : s;
+  return rot;
+}
+
+// The step applied to column j itself.
+template <int P>
+__host__ __device__ inline bool jacobi_update(double* x, const double* y, double nx, double sx, double ny,
+                                              double sy, int j, int q) {
+  double c, sg;
+  const bool rot = jacobi_pair<P>(x, y, nx, sx, ny, sy, j, q, c, sg);
 #pragma unroll
   for (int i = 0; i < P; ++i) x[i] = fma(sg, y[i], c * x[i]);
   return rot;

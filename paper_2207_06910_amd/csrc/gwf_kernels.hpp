@@ -53,6 +53,13 @@ struct InvertArgs {
   double sky_fac;           // -2 pi ln(1 - X/100) [x (180/pi)^2 for square degrees]
   const double* theta;      // [n], the events' polar angles (sky area only)
   double* sky;              // [n] or NULL
+  // Inversion method (sec. 4.1): 0 Cholesky, a failure flagged; 1 an SVD
+  // where the Cholesky fails; 2 SVD, with truncate: singular values below
+  // svals_thresh x max raised to that value; 3 SVD leaving them out.
+  int32_t method, truncate;
+  double svals_thresh;
+  double* eigval;           // [P][n] or NULL: eigenvalues of the normalised kept matrix
+  double* eigvec;           // [P][P][n] or NULL: its eigenvectors (columns)
 };
 
 struct WaveformArgs {

@@ -61,7 +61,7 @@ constexpr uint32_t kFlagRot = 1;
 constexpr uint32_t kFlagTidal = 2;
 constexpr uint32_t kFlagMixed = 4;
 
-enum : int32_t { kEvInvalid = 1, kEvNotPD = 2, kEvIllCond = 4, kEvNonFinite = 8, kEvSkipped = 16 };
+enum : int32_t { kEvInvalid = 1, kEvNotPD = 2, kEvIllCond = 4, kEvNonFinite = 8, kEvSkipped = 16, kEvSvd = 32 };
 
 // ------------------------------------------------------------ series
 // Per-event coefficients of a PN-phase derivative:

@@ -79,7 +79,7 @@ def test_covariance_options_rejected_on_host():
     """gwf_covariance: masks beyond P, fixed and marginalised overlapping,
     nothing left, negative or non-finite priors, priors beyond P, a sky level
     of 100% or more, theta or phi fixed or out of range, missing theta or sky
-    output, unknown units."""
+    output, unknown units, unknown method, SVD threshold outside [0, 1)."""
     lib = binding.load()
     B = ctypes.byref
 
@@ -96,9 +96,9 @@ def test_covariance_options_rejected_on_host():
         return o
 
     def call(o, P=13, theta=8, sky=8):
-        return lib.gwf_covariance(P, 3, 8, B(o), theta, None, 8, None, None, None, sky, 8, None)
+        return lib.gwf_covariance(P, 3, 8, B(o), theta, None, 8, None, None, None, sky, None, None, 8, None)
 
-    assert lib.gwf_covariance(13, 3, 8, None, None, None, 8, None, None, None, None, 8, None) == 1
+    assert lib.gwf_covariance(13, 3, 8, None, None, None, 8, None, None, None, None, None, None, 8, None) == 1
     assert call(opts(fixed_mask=1 << 13)) == 1
     assert call(opts(marg_mask=1 << 11), P=11) == 1
     assert call(opts(fixed_mask=3, marg_mask=2)) == 1
@@ -116,6 +116,9 @@ def test_covariance_options_rejected_on_host():
     assert call(opts(sky_level=90.0), theta=None) == 1
     assert call(opts(sky_level=90.0), sky=None) == 1
     assert call(opts(sky_level=90.0, sky_units=2)) == 1
+    assert call(opts(method=4)) == 1
+    assert call(opts(method=2, svals_thresh=1.0)) == 1
+    assert call(opts(method=3, svals_thresh=float("nan"))) == 1
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

@@ -151,3 +151,93 @@ def test_full_catalogue_sampled_against_oracle(lib, orc):
     g = {k: (v.cpu().numpy()[..., idx] if hasattr(v, "cpu") else v) for k, v in r.items()}
     _compare(g, ref)
     plan.close()
+
+
+# ------------------------------------------------------------ SVD inversions and eigen-decomposition
+def _spectra(rng, P, n, lam_fn):
+    F = np.zeros((P, P, n))
+    for e in range(n):
+        Q, _ = np.linalg.qr(rng.normal(size=(P, P)))
+        A = (Q * lam_fn(e)) @ Q.T
+        A = 0.5 * (A + A.T)
+        s = 10 ** rng.uniform(-2, 2, P)
+        F[:, :, e] = A * np.outer(s, s)
+    return F
+
+
+def _cov_close(g, ref, ok, tol):
+    dc = np.sqrt(np.abs(np.einsum("iie->ie", ref["cov"][:, :, ok])))
+    cerr = (np.abs(g["cov"][:, :, ok] - ref["cov"][:, :, ok]) / (dc[:, None, :] * dc[None, :, :])).max(axis=(0, 1))
+    assert np.all(cerr <= tol[ok]), (cerr, tol[ok])
+
+
+def test_svd_methods_against_oracle(lib, orc):
+    """'svd' (plain and truncated) and 'svd_reg' on BNS Fisher matrices
+    against the oracle's mpmath SVD inverses of the same matrices, within
+    max(1e-9, 1e3 kappa u); 'cho_svd' equals 'cho' where the Cholesky works."""
+    wl = synth.bns1e4(n=12).with_npts(2500)
+    F = orc.fisher(wl)["fisher"]
+    for method, trunc in (("svd", False), ("svd", True), ("svd_reg", False)):
+        g = _gpu(lib, F, method=method, truncate=trunc)
+        ref = orc.covariance(F, method=method, truncate=trunc)
+        assert np.array_equal(g["status"], ref["status"]), method
+        ok = ref["status"] == 0
+        kap = ref["cond"]
+        tol = np.maximum(1e-9, 1e3 * kap * U)
+        _cov_close(g, ref, ok, tol)
+        assert np.all(g["inv_err"][ok] >= 0)
+    a = _gpu(lib, F, method="cho")
+    b = _gpu(lib, F, method="cho_svd")
+    pd = a["status"] == 0
+    for k in ("cov", "sigma", "logdet", "cond", "inv_err"):
+        assert np.array_equal(a[k][..., pd], b[k][..., pd]), k
+
+
+def test_svd_fallback_on_indefinite_matrices(lib, orc):
+    """Matrices with negative eigenvalues (positive diagonal): 'cho' flags
+    them NOT_PD with NaN outputs; 'cho_svd' inverts them by SVD (status 32,
+    the exact inverse within max(1e-9, 1e3 kappa u), ln det NaN); positive
+    definite ones in the same launch keep the Cholesky result."""
+    rng = np.random.default_rng(31)
+    P, n = 9, 24
+
+    def lam(e):
+        v = np.geomspace(0.1, 100.0, P)
+        if e % 3 == 0:
+            v[[0, 3]] *= -1.0
+        return v
+    F = _spectra(rng, P, n, lam)
+    F[np.arange(P), np.arange(P), :] = np.abs(F[np.arange(P), np.arange(P), :]) + 1e-3
+    g0 = _gpu(lib, F, method="cho")
+    g1 = _gpu(lib, F, method="cho_svd")
+    ref = orc.covariance(F, method="cho_svd")
+    assert np.array_equal(g1["status"], ref["status"])
+    svd = ref["status"] == 32
+    assert svd.sum() >= 4 and np.all(g0["status"][svd] == 2) and np.all(np.isnan(g0["sigma"][:, svd]))
+    kap = ref["cond"]
+    tol = np.maximum(1e-9, 1e3 * kap * U)
+    _cov_close(g1, ref, np.ones(n, bool), tol)
+    neg = np.einsum("iie->ie", ref["cov"]) < 0
+    assert np.array_equal(np.isnan(g1["sigma"]), neg)
+    assert np.all(np.isnan(g1["logdet"][svd])) and np.all(np.isfinite(g1["logdet"][~svd]))
+
+
+def test_eigen_decomposition_against_oracle(lib, orc):
+    """Eigenvalues (ascending) and eigenvectors of the normalised matrices
+    against mpmath's: well-separated spectra, both signs, the sign
+    convention of the eigenvectors; with fixed parameters the decomposition
+    is of the kept matrix."""
+    rng = np.random.default_rng(12)
+    P, n = 11, 16
+    F = _spectra(rng, P, n, lambda e: np.linspace(1.0, 11.0, P) * (1 if e % 2 else -1) ** (np.arange(P) < 2))
+    g = _gpu(lib, F, eigen=True, method="cho_svd")
+    val, vec = orc.eigen(F)
+    scale = np.abs(val).max(axis=0)
+    assert np.max(np.abs(g["eigval"] - val) / scale) < 1e-13
+    assert np.max(np.abs(g["eigvec"] - vec)) < 1e-12
+    fixed = [2, 7]
+    keep = [i for i in range(P) if i not in fixed]
+    g = _gpu(lib, F, eigen=True, fixed=fixed)
+    val, vec = orc.eigen(np.ascontiguousarray(F[np.ix_(keep, keep)]))
+    assert np.max(np.abs(g["eigval"] - val) / np.abs(val).max(axis=0)) < 1e-12
+    assert np.max(np.abs(g["eigvec"] - vec)) < 1e-10

@@ -274,10 +274,12 @@ def main():
     # ---- covariance epilogue (gwf_covariance) on the plain form's Fisher matrices: the
     # paper's worked example (spins fixed, Gaussian priors of variance 2 pi^2 on the
     # angles, 90% sky area in square degrees) with the tidal deformabilities
-    # marginalised over
+    # marginalised over, inverted by the paper's default method (Cholesky, an SVD
+    # where it fails)
     outc = {}
     ckw = dict(theta=dw.par[3].contiguous(), fixed=(9, 10), marg=(11, 12), sky_level=90.0,
-               units="SqDeg", prior={i: 1.0 / (2.0 * np.pi ** 2) for i in (3, 4, 5, 6, 8)}, out=outc)
+               units="SqDeg", prior={i: 1.0 / (2.0 * np.pi ** 2) for i in (3, 4, 5, 6, 8)},
+               method="cho_svd", out=outc)
     for i in range(2):
         binding.covariance(outf["fisher"], outf["status"], **ckw)
     tc = []
@@ -289,14 +291,29 @@ def main():
         tc.append(ev[0].elapsed_time(ev[1]))
     cov_ms = float(np.mean(tc))
     stc, skyc = outc["status"].cpu().numpy(), outc["sky"].cpu().numpy()
-    log(f"covariance epilogue kernel {cov_ms:.3f} ms, inverted {int(np.sum(stc == 0))}/{wl.n}, "
-        f"median 90% sky area {float(np.median(skyc[stc == 0])):.3g} deg^2")
+    log(f"covariance epilogue kernel {cov_ms:.3f} ms, inverted {int(np.sum(stc == 0))}/{wl.n} "
+        f"(+{int(np.sum(stc == 32))} by SVD), median 90% sky area {float(np.median(skyc[stc == 0])):.3g} deg^2")
+    # every matrix by SVD, with its eigen-decomposition (the paper's 'svd' and CheckFisher)
+    outs = {}
+    for i in range(2):
+        binding.covariance(outf["fisher"], outf["status"], method="svd", eigen=True, out=outs)
+    ts = []
+    for i in range(args.steps):
+        ev[0].record(stream)
+        binding.covariance(outf["fisher"], outf["status"], method="svd", eigen=True, out=outs)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        ts.append(ev[0].elapsed_time(ev[1]))
+    svd_ms = float(np.mean(ts))
+    log(f"SVD inversion with eigen-decomposition {svd_ms:.3f} ms")
     cov_form = {"covariance_epilogue": {
         "workload": "bns1e4 Fisher matrices: chi1z, chi2z fixed; Gaussian priors of variance 2 pi^2 "
                     "on theta, phi, iota, psi, Phicoal; Lambda1, Lambda2 marginalised; 90% sky area",
         "kernel": "invert_kernel<11>", "kernel_ms": round(cov_ms, 4),
         "events_per_s": round(wl.n / (cov_ms * 1e-3), 1), "inverted": int(np.sum(stc == 0)),
-        "median_sky_deg2": round(float(np.median(skyc[stc == 0])), 4)}}
+        "inverted_by_svd": int(np.sum(stc == 32)),
+        "median_sky_deg2": round(float(np.median(skyc[stc == 0])), 4),
+        "svd_with_eigen_ms": round(svd_ms, 4)}}
 
     # ---- strain output (gwf_waveform): HBM-bound, 16 B per point and interferometer
     ends = torch.cumsum(dw.npts.to(torch.int64), 0)

@@ -7,9 +7,12 @@
 //                   tangents in LDS; every lane walks the grid with a stride
 //                   of the workgroup size, forms the point quantities once
 //                   and, for each site, recomputes the derivative vectors and
-//                   contracts them into that site's sums, kept per lane in
-//                   LDS; the sums are reduced over the workgroup in a fixed
-//                   order and combined into the event's gradient terms.
+//                   contracts them into that site's sums; each pair of lanes
+//                   adds its two contributions and keeps the running sums in
+//                   one LDS column (sized by the number of sites, so that two
+//                   wavefronts fit per SIMD); the sums are reduced over the
+//                   workgroup in a fixed order and combined into the event's
+//                   gradient terms.
 //   reduce_kernel   one workgroup per output component sums the events'
 //                   terms in a fixed order, so the gradient is bitwise
 //                   reproducible.
@@ -21,9 +24,10 @@ namespace gwf {
 namespace {
 
 constexpr int kABlock = 128;
-// accumulator slots kept per (site, lane) in LDS: the four Gbar:dGamma terms,
-// the three geometric SNR^2 derivatives and the site's SNR^2 (its ln S0
-// derivative is minus that)
+constexpr int kCols = kABlock / 2;        // LDS accumulator columns, one per lane pair
+// accumulator slots kept per (site, lane pair) in LDS: the four Gbar:dGamma
+// terms, the three geometric SNR^2 derivatives and the site's SNR^2 (its
+// ln S0 derivative is minus that)
 constexpr int kSlots = 8;
 
 __device__ inline double wave_sum_a(double x) {
@@ -34,15 +38,16 @@ __device__ inline double wave_sum_a(double x) {
 
 __device__ inline int slot_of(int i) { return i < 7 ? i : kAdjW; }   // LDS slot -> acc index
 
+// Two wavefronts per SIMD: the registers are capped at 256 (the sums live in
+// LDS, not in registers).
 template <bool TIDAL, bool ROT>
-__global__ __launch_bounds__(kABlock) void adjoint_kernel(AdjointArgs a) {
+__global__ __launch_bounds__(kABlock, 2) void adjoint_kernel(AdjointArgs a) {
   constexpr int P = TIDAL ? 13 : 11;
   constexpr uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u);
   __shared__ EventC ec;
   __shared__ SiteA sa[kMaxSites];
   __shared__ double Gb[P * P];
-  __shared__ double accl[kMaxSites][kSlots][kABlock];   // each lane owns column tid
-  __shared__ double red[kABlock / 64][kSlots];
+  extern __shared__ double accl[];      // [n_site][kSlots][kCols], column tid/2 per lane pair
   __shared__ double site_acc[kMaxSites][kSlots];
   __shared__ int32_t ok;
   const int64_t e = blockIdx.x;
@@ -72,43 +77,47 @@ __global__ __launch_bounds__(kABlock) void adjoint_kernel(AdjointArgs a) {
     for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
     site_setup_adj(p, a.net.site[tid], ec, sa[tid]);
   }
-  for (int s = 0; s < n_site; ++s)
+  const int col = tid >> 1;
+  if ((tid & 1) == 0)
+    for (int s = 0; s < n_site; ++s)
 #pragma unroll
-    for (int i = 0; i < kSlots; ++i) accl[s][i][tid] = 0.0;
+      for (int i = 0; i < kSlots; ++i) accl[(s * kSlots + i) * kCols + col] = 0.0;
   __syncthreads();
-  // every lane walks its grid points once; the point quantities are shared by
-  // all sites, whose sums stay in the lane's own LDS column
-  for (int k = tid; k < ec.n; k += kABlock) {
+  // every lane walks its grid points once (the same trip count for every
+  // lane, so that both lanes of a pair take part in each exchange; points
+  // past the grid add zero); the point quantities are shared by all sites
+  const int iters = (ec.n + kABlock - 1) / kABlock;
+  for (int it = 0; it < iters; ++it) {
     asm volatile("" ::: "memory");   // constants stay in LDS rather than occupying registers
+    const int k = it * kABlock + tid;
+    const bool in = k < ec.n;
     AdjPoint ap;
-    adjoint_point_setup<TIDAL, ROT>(ec, Gb, k, ap);
+    if (in) adjoint_point_setup<TIDAL, ROT>(ec, Gb, k, ap);
     for (int s = 0; s < n_site; ++s) {
       asm volatile("" ::: "memory");
       double acc[kAdjN];
 #pragma unroll
       for (int i = 0; i < kAdjN; ++i) acc[i] = 0.0;
+      if (in) adjoint_site<TIDAL>(ec, sa[s], Gb, ap, acc);
 #pragma unroll
-      for (int i = 0; i < kSlots; ++i) acc[slot_of(i)] = accl[s][i][tid];
-      adjoint_site<TIDAL>(ec, sa[s], Gb, ap, acc);
-#pragma unroll
-      for (int i = 0; i < kSlots; ++i) accl[s][i][tid] = acc[slot_of(i)];
+      for (int i = 0; i < kSlots; ++i) {
+        const double v = acc[slot_of(i)];
+        const double t = v + __shfl_xor(v, 1, 64);       // the lane pair's two points
+        if ((tid & 1) == 0) accl[(s * kSlots + i) * kCols + col] += t;
+      }
     }
   }
-  const int wave = tid >> 6, lane = tid & 63;
-  for (int s = 0; s < n_site; ++s) {
+  __syncthreads();
+  // the first wavefront sums the columns (kCols = 64 lanes)
+  if (tid < kCols) {
+    for (int s = 0; s < n_site; ++s)
 #pragma unroll
-    for (int i = 0; i < kSlots; ++i) {
-      const double t = wave_sum_a(accl[s][i][tid]);
-      if (lane == 0) red[wave][i] = t;
-    }
-    __syncthreads();
-    if (tid < kSlots) {
-      double t = 0.0;
-      for (int w = 0; w < kABlock / 64; ++w) t += red[w][tid];
-      site_acc[s][tid] = t;
-    }
-    __syncthreads();
+      for (int i = 0; i < kSlots; ++i) {
+        const double t = wave_sum_a(accl[(s * kSlots + i) * kCols + tid]);
+        if (tid == 0) site_acc[s][i] = t;
+      }
   }
+  __syncthreads();
   if (tid < n_site * 4) {
     const int s = tid >> 2, m = tid & 3;
     double W = 0.0;
@@ -140,10 +149,11 @@ __global__ __launch_bounds__(kABlock) void reduce_kernel(const double* __restric
 
 hipError_t launch_adjoint(const AdjointArgs& a, bool tidal, bool rot, hipStream_t stream) {
   dim3 grid((unsigned)a.n), block(kABlock);
-  if (tidal && rot) hipLaunchKernelGGL((adjoint_kernel<true, true>), grid, block, 0, stream, a);
-  else if (tidal) hipLaunchKernelGGL((adjoint_kernel<true, false>), grid, block, 0, stream, a);
-  else if (rot) hipLaunchKernelGGL((adjoint_kernel<false, true>), grid, block, 0, stream, a);
-  else hipLaunchKernelGGL((adjoint_kernel<false, false>), grid, block, 0, stream, a);
+  const size_t lds = sizeof(double) * (size_t)a.net.n_site * kSlots * kCols;
+  if (tidal && rot) hipLaunchKernelGGL((adjoint_kernel<true, true>), grid, block, lds, stream, a);
+  else if (tidal) hipLaunchKernelGGL((adjoint_kernel<true, false>), grid, block, lds, stream, a);
+  else if (rot) hipLaunchKernelGGL((adjoint_kernel<false, true>), grid, block, lds, stream, a);
+  else hipLaunchKernelGGL((adjoint_kernel<false, false>), grid, block, lds, stream, a);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   const int width = a.net.n_site * 4;

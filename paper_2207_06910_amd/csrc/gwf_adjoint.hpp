@@ -180,53 +180,73 @@ __host__ __device__ inline void adjoint_point_setup(const EventC& ec, const doub
 }
 
 // Adds the contribution of one site at the point to acc[kAdjN].
+//
+// Order of the work: the site geometry is evaluated as values only; for each
+// effective interferometer the derivative vectors, z and the reverse weights
+// kappa of the building blocks are formed and folded (times 2w) into the
+// adjoints of the site's pattern vectors P, PH, Pt (4 each) and of dH, dT,
+// since Fp = alpha . P etc. are linear in them; gamma moves only alpha and
+// beta, so its terms are taken per interferometer from their gamma
+// derivatives.  After the last interferometer, one forward pass through the
+// geometry gives the latitude and longitude tangents of P, PH, Pt, dH and dT,
+// contracted with those adjoints.  Only the values and the adjoints are live
+// across the interferometers.
 template <bool TIDAL>
 __host__ __device__ inline void adjoint_site(const EventC& ec, const SiteA& sa, const double* Gb,
                                              const AdjPoint& ap, double* acc) {
   constexpr int NPI = TIDAL ? 5 : 3;
   constexpr int P = 8 + NPI;
   const Point& q = ap.q;
-  // hour angle, pattern vectors, arrival-time offset derivatives (tangents)
-  const T3 cH = q.cth * sa.cdl - q.sth * sa.sdl;
-  const T3 sH = q.sth * sa.cdl + q.cth * sa.sdl;
-  const T3 EX = cH, EY = -(sa.ct * sH), NX = -(sa.sl * sH), NY = -(sa.slct * cH + sa.clst);
-  T3 Pv[4], PH[4], Pt[4];
-  Pv[0] = 0.5 * (EX * EX - NX * NX - EY * EY + NY * NY);
-  Pv[1] = EX * NX - EY * NY;
-  Pv[2] = EX * EY - NX * NY;
-  Pv[3] = EX * NY + NX * EY;
+  // hour angle, pattern vectors and arrival-time derivatives: values
+  double Pv[4], PH[4], Pt[4], dHv, dTv;
   {
-    const T3 EXh = -sH, EYh = -(sa.ct * cH), NXh = -(sa.sl * cH), NYh = sa.slct * sH;
+    const double cH = q.cth * sa.cdl.v - q.sth * sa.sdl.v;
+    const double sH = q.sth * sa.cdl.v + q.cth * sa.sdl.v;
+    const double EX = cH, EY = -(sa.ct * sH), NX = -(sa.sl.v * sH), NY = -(sa.slct.v * cH + sa.clst.v);
+    Pv[0] = 0.5 * (EX * EX - NX * NX - EY * EY + NY * NY);
+    Pv[1] = EX * NX - EY * NY;
+    Pv[2] = EX * EY - NX * NY;
+    Pv[3] = EX * NY + NX * EY;
+    const double EXh = -sH, EYh = -(sa.ct * cH), NXh = -(sa.sl.v * cH), NYh = sa.slct.v * sH;
     PH[0] = EX * EXh - NX * NXh - EY * EYh + NY * NYh;
     PH[1] = EXh * NX + EX * NXh - EYh * NY - EY * NYh;
     PH[2] = EXh * EY + EX * EYh - NXh * NY - NX * NYh;
     PH[3] = EXh * NY + EX * NYh + NXh * EY + NX * EYh;
-    // d/dtheta of EY and NY (theta is the source angle, not a detector parameter)
-    const T3 EYt = sa.st * sH, NYt = sa.st * (sa.sl * cH) - sa.ct * sa.cl;
+    const double EYt = sa.st * sH, NYt = sa.st * (sa.sl.v * cH) - sa.ct * sa.cl.v;
     Pt[0] = -(EY * EYt) + NY * NYt;
     Pt[1] = -(EYt * NY + EY * NYt);
     Pt[2] = EX * EYt - NX * NYt;
     Pt[3] = EX * NYt + NX * EYt;
+    dHv = -(sa.k1.v * sH);
+    dTv = fma(sa.k1t.v, cH, sa.k0t.v);
   }
-  const T3 dH = -(sa.k1 * sH);
-  const T3 dT = fmat(sa.k1t, cH, sa.k0t);
   const double om0 = psd_weight_of(sa.xp_fac, 0.0, sa.ix_fac, sa.x_fac, sa.S0inv, q);
   const double tf = q.tf;
-  const double phMc = fma(tf * dH.v, q.gMc, q.pMc), phEta = fma(tf * dH.v, q.gEta, q.pEta);
-  const double phT = tf * dT.v, phP = -tf * dH.v, phTc = tf * fma(kOmegaE, dH.v, 1.0);
+  const double phMc = fma(tf * dHv, q.gMc, q.pMc), phEta = fma(tf * dHv, q.gEta, q.pEta);
+  const double phT = tf * dTv, phP = -tf * dHv, phTc = tf * fma(kOmegaE, dHv, 1.0);
   const double cplus = ec.cplus, ccross = ec.ccross, dcp = ec.dcplus, dcx = ec.dcross;
   const double dlnA = ec.dlnA_dMc, idL = ec.inv_dL;
+  // adjoints, summed over the interferometers: Gbar:dGamma (b) and SNR^2 (s)
+  double bP[4] = {0.0, 0.0, 0.0, 0.0}, bPH[4] = {0.0, 0.0, 0.0, 0.0}, bPt[4] = {0.0, 0.0, 0.0, 0.0};
+  double sP[4] = {0.0, 0.0, 0.0, 0.0};
+  double bdH = 0.0, bdT = 0.0, bgam = 0.0, sgam = 0.0;
   for (int j = 0; j < sa.n_eff; ++j) {
     // compiler barrier: the constants below are loaded when needed rather
     // than all at once (register pressure)
     asm volatile("" ::: "memory");
     const double om = om0 * sa.weff[j];
-    const T3 Fp = dot4t(sa.alpha[j], Pv), Fx = dot4t(sa.beta[j], Pv);
-    const T3 FpH = dot4t(sa.alpha[j], PH), FxH = dot4t(sa.beta[j], PH);
-    const T3 Fpt = dot4t(sa.alpha[j], Pt), Fxt = dot4t(sa.beta[j], Pt);
-    const double Qr = cplus * Fp.v, Qi = ccross * Fx.v;
-    const double QHr = cplus * FpH.v, QHi = ccross * FxH.v;
-    const double Qtr = cplus * Fpt.v, Qti = ccross * Fxt.v;
+    double al[4], be[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      al[i] = sa.alpha[j][i].v;
+      be[i] = sa.beta[j][i].v;
+    }
+    const double Fp = dot4(al, Pv), Fx = dot4(be, Pv);
+    const double FpH = dot4(al, PH), FxH = dot4(be, PH);
+    const double Fpt = dot4(al, Pt), Fxt = dot4(be, Pt);
+    const double Qr = cplus * Fp, Qi = ccross * Fx;
+    const double QHr = cplus * FpH, QHi = ccross * FxH;
+    const double Qtr = cplus * Fpt, Qti = ccross * Fxt;
     // D values (as in accumulate_point)
     double Dr[8], Di[8];
     Dr[0] = fma(Qr, dlnA, fma(QHr, q.gMc, -Qi * phMc));
@@ -239,10 +259,10 @@ __host__ __device__ inline void adjoint_site(const EventC& ec, const SiteA& sa, 
     Di[3] = fma(Qr, phT, Qti);
     Dr[4] = fma(-Qi, phP, -QHr);
     Di[4] = fma(Qr, phP, -QHi);
-    Dr[5] = dcp * Fp.v;
-    Di[5] = dcx * Fx.v;
-    Dr[6] = 2.0 * cplus * Fx.v;
-    Di[6] = -2.0 * ccross * Fp.v;
+    Dr[5] = dcp * Fp;
+    Di[5] = dcx * Fx;
+    Dr[6] = 2.0 * cplus * Fx;
+    Di[6] = -2.0 * ccross * Fp;
     Dr[7] = fma(kOmegaE, QHr, -Qi * phTc);
     Di[7] = fma(kOmegaE, QHi, Qr * phTc);
     // z = Gbar D for rows a < 8, and c . z over the phase-only rows, from
@@ -284,30 +304,79 @@ __host__ __device__ inline void adjoint_site(const EventC& ec, const SiteA& sa, 
     const double kphP = fma(-Qi, zr[4], Qr * zi[4]);
     const double kphTc = fma(-Qi, zr[7], Qr * zi[7]);
     // ... mapped to the pattern values and the arrival-time derivatives
-    const double kFp = fma(cplus, kQr, fma(dcp, zr[5], -2.0 * ccross * zi[6]));
-    const double kFx = fma(ccross, kQi, fma(dcx, zi[5], 2.0 * cplus * zr[6]));
-    const double kFpH = cplus * kQHr, kFxH = ccross * kQHi;
-    const double kFpt = cplus * kQtr, kFxt = ccross * kQti;
-    const double kdH = tf * fma(q.gMc, kphMc, fma(q.gEta, kphEta, fma(kOmegaE, kphTc, -kphP)));
-    const double kdT = tf * kphT;
+    const double f = 2.0 * om;
+    const double kFp = f * fma(cplus, kQr, fma(dcp, zr[5], -2.0 * ccross * zi[6]));
+    const double kFx = f * fma(ccross, kQi, fma(dcx, zi[5], 2.0 * cplus * zr[6]));
+    const double kFpH = f * (cplus * kQHr), kFxH = f * (ccross * kQHi);
+    const double kFpt = f * (cplus * kQtr), kFxt = f * (ccross * kQti);
+    bdH = fma(f * tf, fma(q.gMc, kphMc, fma(q.gEta, kphEta, fma(kOmegaE, kphTc, -kphP))), bdH);
+    bdT = fma(f * tf, kphT, bdT);
+    const double sFp = f * (Qr * cplus), sFx = f * (Qi * ccross);
+    double ag[4], bg[4];                      // d alpha / d gamma, d beta / d gamma
 #pragma unroll
-    for (int x = 0; x < 3; ++x) {
-      double t = kFp * Fp.d[x];
-      t = fma(kFx, Fx.d[x], t);
-      t = fma(kFpH, FpH.d[x], t);
-      t = fma(kFxH, FxH.d[x], t);
-      t = fma(kFpt, Fpt.d[x], t);
-      t = fma(kFxt, Fxt.d[x], t);
-      t = fma(kdH, dH.d[x], t);
-      t = fma(kdT, dT.d[x], t);
-      acc[kAdjT + x] = fma(2.0 * om, t, acc[kAdjT + x]);
-      acc[kAdjS + x] = fma(2.0 * om, fma(Qr * cplus, Fp.d[x], Qi * ccross * Fx.d[x]), acc[kAdjS + x]);
+    for (int i = 0; i < 4; ++i) {
+      bP[i] = fma(kFp, al[i], fma(kFx, be[i], bP[i]));
+      bPH[i] = fma(kFpH, al[i], fma(kFxH, be[i], bPH[i]));
+      bPt[i] = fma(kFpt, al[i], fma(kFxt, be[i], bPt[i]));
+      sP[i] = fma(sFp, al[i], fma(sFx, be[i], sP[i]));
+      ag[i] = sa.alpha[j][i].d[2];
+      bg[i] = sa.beta[j][i].d[2];
     }
+    const double gFp = dot4(ag, Pv), gFx = dot4(bg, Pv);
+    bgam = fma(kFp, gFp, fma(kFx, gFx, fma(kFpH, dot4(ag, PH), fma(kFxH, dot4(bg, PH),
+           fma(kFpt, dot4(ag, Pt), fma(kFxt, dot4(bg, Pt), bgam))))));
+    sgam = fma(sFp, gFp, fma(sFx, gFx, sgam));
     const double q2 = fma(Qr, Qr, Qi * Qi);
     acc[kAdjT + 3] = fma(-om, dz, acc[kAdjT + 3]);
     acc[kAdjS + 3] = fma(-om, q2, acc[kAdjS + 3]);
     acc[kAdjW] = fma(om, q2, acc[kAdjW]);
   }
+  // latitude and longitude tangents of the geometry, contracted with the adjoints
+  asm volatile("" ::: "memory");
+  const T3 cH = q.cth * sa.cdl - q.sth * sa.sdl;
+  const T3 sH = q.sth * sa.cdl + q.cth * sa.sdl;
+  const T3 EX = cH, EY = -(sa.ct * sH), NX = -(sa.sl * sH), NY = -(sa.slct * cH + sa.clst);
+  double tb[2] = {0.0, 0.0}, ts[2] = {0.0, 0.0};
+  {
+    const T3 P0 = 0.5 * (EX * EX - NX * NX - EY * EY + NY * NY);
+    const T3 P1 = EX * NX - EY * NY;
+    const T3 P2 = EX * EY - NX * NY;
+    const T3 P3 = EX * NY + NX * EY;
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      tb[x] = fma(bP[0], P0.d[x], fma(bP[1], P1.d[x], fma(bP[2], P2.d[x], bP[3] * P3.d[x])));
+      ts[x] = fma(sP[0], P0.d[x], fma(sP[1], P1.d[x], fma(sP[2], P2.d[x], sP[3] * P3.d[x])));
+    }
+  }
+  {
+    const T3 EXh = -sH, EYh = -(sa.ct * cH), NXh = -(sa.sl * cH), NYh = sa.slct * sH;
+    const T3 H0 = EX * EXh - NX * NXh - EY * EYh + NY * NYh;
+    const T3 H1 = EXh * NX + EX * NXh - EYh * NY - EY * NYh;
+    const T3 H2 = EXh * EY + EX * EYh - NXh * NY - NX * NYh;
+    const T3 H3 = EXh * NY + EX * NYh + NXh * EY + NX * EYh;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+      tb[x] = fma(bPH[0], H0.d[x], fma(bPH[1], H1.d[x], fma(bPH[2], H2.d[x], fma(bPH[3], H3.d[x], tb[x]))));
+  }
+  {
+    const T3 EYt = sa.st * sH, NYt = sa.st * (sa.sl * cH) - sa.ct * sa.cl;
+    const T3 T0 = -(EY * EYt) + NY * NYt;
+    const T3 T1 = -(EYt * NY + EY * NYt);
+    const T3 T2 = EX * EYt - NX * NYt;
+    const T3 T3v = EX * NYt + NX * EYt;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+      tb[x] = fma(bPt[0], T0.d[x], fma(bPt[1], T1.d[x], fma(bPt[2], T2.d[x], fma(bPt[3], T3v.d[x], tb[x]))));
+  }
+  const T3 dH = -(sa.k1 * sH);
+  const T3 dT = fmat(sa.k1t, cH, sa.k0t);
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+    acc[kAdjT + x] += fma(bdH, dH.d[x], fma(bdT, dT.d[x], tb[x]));
+    acc[kAdjS + x] += ts[x];
+  }
+  acc[kAdjT + 2] += bgam;
+  acc[kAdjS + 2] += sgam;
 }
 
 // One grid point and one site (host checks).

@@ -689,3 +689,81 @@ def test_eigen_decomposition_properties(orc):
     assert np.all(np.diff(val[:, 0]) > 0)
     big = np.abs(Q).argmax(axis=0)
     assert np.all(Q[big, np.arange(P)] > 0)
+
+
+# ------------------------------------------------------------ parameter bases (sec. 2.1, 3.2)
+def _basis_case():
+    """A well-conditioned 13 x 13 Fisher matrix (condition number ~1e3 after
+    normalisation) at the parameters of a BNS event of the benchmark."""
+    wl = synth.bns1e4(n=3)
+    par = wl.par[:13, 1].copy()
+    rng = np.random.default_rng(17)
+    Q, _ = np.linalg.qr(rng.normal(size=(13, 13)))
+    A = (Q * np.geomspace(1.0, 1e3, 13)) @ Q.T
+    s = 10 ** rng.uniform(-2, 2, 13)
+    F = 0.5 * (A + A.T) * np.outer(s, s)
+    return F, par
+
+
+def _fwd_grad(fn, x0, dps=40):
+    with mp.workdps(dps):
+        return [float(mp.diff(lambda t, i=i: fn([x0[j] if j != i else t for j in range(len(x0))]), x0[i]))
+                for i in range(len(x0))]
+
+
+def test_basis_chi_sa_closed_form(orc):
+    """chi1 = chi_s + chi_a, chi2 = chi_s - chi_a: J has the block
+    [[1, 1], [1, -1]] and the identity elsewhere."""
+    F, par = _basis_case()
+    J = orc.basis_jacobian(par, orc.CHI_SA)
+    ref = np.eye(13)
+    ref[9:11, 9:11] = [[1, 1], [1, -1]]
+    np.testing.assert_allclose(J, ref, atol=1e-14)
+
+
+def test_basis_jacobian_inverts_the_forward_map(orc):
+    """J = d native / d new (the oracle differentiates the map from new to
+    native parameters, solving the tidal 2 x 2 system) times K = d new /
+    d native (differentiated here from the forward formulas: m1, m2 from
+    (Mc, eta), chi_s and chi_a, the paper's Lambda~ and delta Lambda~ of
+    (eta, Lambda1, Lambda2)) is the identity, for every basis combination;
+    so the covariance K C K^T of the new parameters is what J^T Gamma J
+    inverts to."""
+    F, par = _basis_case()
+
+    def forward(x, basis):
+        x = list(x)
+        out = list(x)
+        Mc, eta = x[0], x[1]
+        if basis & orc.M1M2:
+            M = Mc * eta ** (mp.mpf(-3) / 5)
+            de = mp.sqrt(1 - 4 * eta)
+            out[0], out[1] = M * (1 + de) / 2, M * (1 - de) / 2
+        if basis & orc.CHI_SA:
+            out[9], out[10] = (x[9] + x[10]) / 2, (x[9] - x[10]) / 2
+        if basis & orc.LAMBDA_TILDE:
+            S, D, de = x[11] + x[12], x[11] - x[12], mp.sqrt(1 - 4 * eta)
+            out[11] = mp.mpf(8) / 13 * ((1 + 7 * eta - 31 * eta ** 2) * S + de * (1 + 9 * eta - 11 * eta ** 2) * D)
+            out[12] = (de * (1 - mp.mpf(13272) / 1319 * eta + mp.mpf(8944) / 1319 * eta ** 2) * S
+                       + (1 - mp.mpf(15910) / 1319 * eta + mp.mpf(32850) / 1319 * eta ** 2
+                          + mp.mpf(3380) / 1319 * eta ** 3) * D) / 2
+        return out
+
+    for basis in (1, 2, 4, 3, 5, 6, 7):
+        J = orc.basis_jacobian(par, basis)
+        with mp.workdps(40):
+            x0 = [mp.mpf(v) for v in par]
+            K = np.zeros((13, 13))
+            for i in range(13):
+                for a in range(13):
+                    K[i, a] = float(mp.diff(lambda t: forward([x0[j] if j != a else t for j in range(13)],
+                                                              basis)[i], x0[a]))
+        np.testing.assert_allclose(J @ K, np.eye(13), atol=1e-10, err_msg=str(basis))
+
+
+def test_tidal_combinations_equal_mass_limit(orc):
+    """Equal masses (eta = 1/4) and Lambda1 = Lambda2 = L: Lambda~ = L and
+    delta Lambda~ = 0 (the combinations' defining property)."""
+    par = np.array([1.2, 0.25, 0.1, 1, 1, 1, 1, 0, 0, 0, 0, 400.0, 400.0])
+    q = orc.basis.new_parameters(par, orc.LAMBDA_TILDE)
+    assert abs(float(q[11]) - 400.0) < 1e-12 and abs(float(q[12])) < 1e-12

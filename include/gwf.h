@@ -328,6 +328,27 @@ gwf_status gwf_covariance(int32_t P, int64_t n, const double* fisher, const gwf_
                           double* inv_err, double* logdet, double* sky, double* eigval,
                           double* eigvec, int32_t* status, void* stream);
 
+/* The Fisher matrix in other parameter bases: chi_s = (chi1z + chi2z)/2,
+ * chi_a = (chi1z - chi2z)/2 in rows GWF_CHI1Z, GWF_CHI2Z; the paper's
+ * tidal combinations Lambda~, delta Lambda~ (sec. 2.1) in rows GWF_LAMBDA1,
+ * GWF_LAMBDA2; the component masses m1 >= m2 [solar masses] in rows GWF_MC,
+ * GWF_ETA (sec. 3.2, use_m1m2).  Gamma' = J^T Gamma J with J = d native /
+ * d new at each event's parameters; at fixed Lambda~, delta Lambda~ the
+ * Lambdas move with eta, so in that basis the eta row (or the m1, m2 rows)
+ * picks up the tidal rows.
+ *   P        11 or 13 (GWF_BASIS_LAMBDA_TILDE needs 13)
+ *   fisher   device [P][P][n] in the native basis (the gwf_fisher output)
+ *   ev       the events the matrices belong to (par rows read on the device)
+ *   basis    OR of GWF_BASIS_*; 0 copies
+ *   out      device [P][P][n]; may equal fisher (in place)
+ *   status   device int32 [n] or NULL: GWF_EV_NONFINITE is OR-ed in where the
+ *            result is not finite (e.g. the tidal basis at eta = 1/4, where
+ *            the map is singular) */
+enum { GWF_BASIS_CHI_SA = 1, GWF_BASIS_LAMBDA_TILDE = 2, GWF_BASIS_M1M2 = 4 };
+
+gwf_status gwf_fisher_basis(int32_t P, int64_t n, const double* fisher, const gwf_events* ev,
+                            uint32_t basis, double* out, int32_t* status, void* stream);
+
 /* ------------------------------------------------------ batched form */
 /* A plan runs the Fisher (and optionally the inversion) of one catalogue
  * repeatedly: the work is cut into items of at most `chunk` grid points

@@ -94,6 +94,8 @@ def load():
         lib.gwf_covariance.argtypes = [i32, i64, vp, ctypes.POINTER(CovOptions), vp, vp, vp, vp, vp, vp, vp,
                                        vp, vp, vp, vp]
         lib.gwf_covariance.restype = i32
+        lib.gwf_fisher_basis.argtypes = [i32, i64, vp, ctypes.POINTER(Events), ctypes.c_uint32, vp, vp, vp]
+        lib.gwf_fisher_basis.restype = i32
         lib.gwf_fisher_adjoint.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
                                            ctypes.POINTER(Grid), ctypes.c_uint32, vp, vp, d, d,
                                            vp, vp, vp]
@@ -340,6 +342,26 @@ def covariance(F, status=None, fixed=(), prior=None, marg=(), theta=None, sky_le
                                  _ptr(res.get("eigvec")), _ptr(st), _stream(stream)),
            "gwf_covariance")
     res["out"] = out_idx
+    return res
+
+
+BASES = {"chi_sa": 1, "lambda_tilde": 2, "m1m2": 4}
+
+
+def fisher_basis(F, dw: "DeviceWorkload", basis=("chi_sa", "lambda_tilde"), status=None, out=None, stream=None):
+    """The Fisher matrices F [P][P][N] of the workload's events in other
+    parameter bases (gwf_fisher_basis): any of "chi_sa", "lambda_tilde",
+    "m1m2".  out=F transforms in place."""
+    import torch
+    _dev_f64(F)
+    P, _, n = F.shape
+    res = out if out is not None else torch.empty_like(F)
+    ev, net, grid, keep = dw.descriptors()
+    bits = 0
+    for b in basis:
+        bits |= BASES[b]
+    _check(load().gwf_fisher_basis(P, n, _ptr(F), ctypes.byref(ev), bits, _ptr(res), _ptr(status),
+                                   _stream(stream)), "gwf_fisher_basis")
     return res
 
 

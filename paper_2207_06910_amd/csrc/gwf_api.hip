@@ -198,6 +198,22 @@ gwf_status gwf_invert(int32_t P, int64_t n, const double* fisher, double cond_ma
   return GWF_OK;
 }
 
+gwf_status gwf_fisher_basis(int32_t P, int64_t n, const double* fisher, const gwf_events* ev,
+                            uint32_t basis, double* out, int32_t* status, void* stream) {
+  if (P != 11 && P != 13) return api_fail(GWF_E_INVALID_ARG, "P=%d must be 11 or 13", P);
+  if (n < 1) return api_fail(GWF_E_INVALID_ARG, "n=%lld must be >= 1", (long long)n);
+  if (!fisher || !out || !ev || !ev->par) return api_fail(GWF_E_INVALID_ARG, "fisher, out and ev->par are required");
+  if (ev->n != n || ev->ld < n) return api_fail(GWF_E_INVALID_ARG, "ev->n must be n and ev->ld >= n");
+  if (basis & ~7u) return api_fail(GWF_E_INVALID_ARG, "basis=%u has unknown bits", basis);
+  if ((basis & GWF_BASIS_LAMBDA_TILDE) && P != 13)
+    return api_fail(GWF_E_INVALID_ARG, "the tidal basis needs P=13");
+  gwf::BasisArgs a{};
+  a.n = n; a.fisher = fisher; a.out = out; a.par = ev->par; a.ld = ev->ld; a.basis = basis; a.status = status;
+  hipError_t err = gwf::launch_basis(a, P, (hipStream_t)stream);
+  if (err != hipSuccess) return api_hip_fail(err, "basis kernel launch");
+  return GWF_OK;
+}
+
 gwf_status gwf_covariance(int32_t P, int64_t n, const double* fisher, const gwf_cov_opts* opts,
                           const double* theta, double* cov, double* sigma, double* cond,
                           double* inv_err, double* logdet, double* sky, double* eigval,

@@ -62,6 +62,16 @@ struct InvertArgs {
   double* eigvec;           // [P][P][n] or NULL: its eigenvectors (columns)
 };
 
+struct BasisArgs {
+  int64_t n;
+  const double* fisher;     // [P][P][n] in the native basis
+  double* out;              // [P][P][n], may equal fisher
+  const double* par;        // [13][ld] native parameters
+  int64_t ld;
+  uint32_t basis;           // 1 chi_s/chi_a, 2 Lambda~/delta Lambda~, 4 m1/m2
+  int32_t* status;          // [n] or NULL
+};
+
 struct WaveformArgs {
   const double* par;
   int64_t ld, n;
@@ -93,6 +103,7 @@ struct AdjointArgs {
 hipError_t launch_fisher(const FisherArgs& a, bool tidal, bool rot, hipStream_t stream);
 hipError_t launch_snr(const SnrArgs& a, bool rot, hipStream_t stream);
 hipError_t launch_invert(const InvertArgs& a, int P, hipStream_t stream);
+hipError_t launch_basis(const BasisArgs& a, int P, hipStream_t stream);
 hipError_t launch_waveform(const WaveformArgs& a, bool tidal, bool rot, bool mixed, hipStream_t stream);
 hipError_t launch_adjoint(const AdjointArgs& a, bool tidal, bool rot, hipStream_t stream);
 

@@ -121,6 +121,21 @@ def test_covariance_options_rejected_on_host():
     assert call(opts(method=3, svals_thresh=float("nan"))) == 1
 
 
+def test_basis_arguments_rejected_on_host():
+    """gwf_fisher_basis: P other than 11/13, the tidal basis without tides,
+    unknown basis bits, a descriptor for another number of events, missing
+    output."""
+    lib = binding.load()
+    B = ctypes.byref
+    ev = binding.Events(3, 3, 8, None)
+    assert lib.gwf_fisher_basis(12, 3, 8, B(ev), 1, 8, None, None) == 1
+    assert lib.gwf_fisher_basis(11, 3, 8, B(ev), 2, 8, None, None) == 1
+    assert lib.gwf_fisher_basis(13, 3, 8, B(ev), 8, 8, None, None) == 1
+    assert lib.gwf_fisher_basis(13, 4, 8, B(ev), 1, 8, None, None) == 1
+    assert lib.gwf_fisher_basis(13, 3, 8, B(ev), 1, None, None, None) == 1
+    assert b"required" in lib.gwf_last_error()
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(binding, "_lib", None)

@@ -1,0 +1,88 @@
+"""GPU: the Fisher matrix in the (chi_s, chi_a), (Lambda~, delta Lambda~) and
+(m1, m2) bases (gwf_fisher_basis) against the oracle's J^T Gamma J, whose J
+comes from 40-digit numerical differentiation of the parameter map.
+
+Tolerance: each entry of J^T Gamma J is a sum of products; its FP64 rounding
+is bounded by a small multiple of u (|J|^T |Gamma| |J|)_ij, u = 2^-53, with
+|J| the oracle's Jacobian in absolute value.  The test allows 64 u of it.
+"""
+import numpy as np
+import pytest
+
+from paper_2207_06910_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+NAMES = {1: ("chi_sa",), 2: ("lambda_tilde",), 4: ("m1m2",), 3: ("chi_sa", "lambda_tilde"),
+         5: ("chi_sa", "m1m2"), 6: ("lambda_tilde", "m1m2"), 7: ("chi_sa", "lambda_tilde", "m1m2")}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2207_06910_amd import binding
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    binding.load()
+    return binding
+
+
+def _check(orc, F, par, G, bits):
+    ref = orc.fisher_basis(F, par, bits)
+    for e in range(F.shape[2]):
+        J = np.abs(orc.basis_jacobian(par[:F.shape[0], e], bits))
+        bound = 64 * U * (J.T @ np.abs(F[:, :, e]) @ J)
+        err = np.abs(G[:, :, e] - ref[:, :, e])
+        assert np.all(err <= bound + 1e-300), (bits, e, np.max(err / (bound + 1e-300)))
+
+
+def test_all_bases_against_oracle(lib, orc):
+    """Every combination of the three bases on BNS Fisher matrices of the
+    oracle (13 parameters); chi_s/chi_a and m1/m2 also without tides."""
+    wl = synth.bns1e4(n=8).with_npts(1500)
+    F = orc.fisher(wl)["fisher"]
+    dw = lib.DeviceWorkload(wl)
+    Ft = torch.as_tensor(F, device="cuda")
+    for bits, names in NAMES.items():
+        G = lib.fisher_basis(Ft, dw, basis=names)
+        torch.cuda.synchronize()
+        _check(orc, F, wl.par, G.cpu().numpy(), bits)
+    wl.flags = synth.FLAG_EARTH_ROT
+    F11 = orc.fisher(wl)["fisher"]
+    dw = lib.DeviceWorkload(wl)
+    for bits in (1, 4, 5):
+        G = lib.fisher_basis(torch.as_tensor(F11, device="cuda"), dw, basis=NAMES[bits])
+        torch.cuda.synchronize()
+        _check(orc, F11, wl.par, G.cpu().numpy(), bits)
+
+
+def test_in_place_and_identity(lib, orc):
+    """out = fisher gives the same bits as a separate output; no basis
+    copies the matrices."""
+    wl = synth.bns1e4(n=40).with_npts(400)
+    dw = lib.DeviceWorkload(wl)
+    F = lib.fisher(dw)["fisher"]
+    a = lib.fisher_basis(F, dw, basis=("chi_sa", "lambda_tilde", "m1m2"))
+    b = F.clone()
+    lib.fisher_basis(b, dw, basis=("chi_sa", "lambda_tilde", "m1m2"), out=b)
+    c = lib.fisher_basis(F, dw, basis=())
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(c, F)
+
+
+def test_full_catalogue_sampled(lib, orc):
+    """The 10^4 BNS catalogue's Fisher matrices from the batched plan in the
+    paper's default basis (chi_s, chi_a, Lambda~, delta Lambda~); sampled
+    events against the oracle's transform of the same matrices; all finite."""
+    wl = synth.bns1e4()
+    dw = lib.DeviceWorkload(wl)
+    plan = lib.Plan(dw, chunk=16384, wg_per_cu=4, use_graph=False)
+    F = plan.run()["fisher"]
+    st = torch.zeros(wl.n, dtype=torch.int32, device="cuda")
+    G = lib.fisher_basis(F, dw, basis=("chi_sa", "lambda_tilde"), status=st)
+    torch.cuda.synchronize()
+    assert int(st.sum()) == 0 and bool(torch.isfinite(G).all())
+    idx = np.random.default_rng(9).choice(wl.n, 6, replace=False)
+    _check(orc, F.cpu().numpy()[:, :, idx], wl.par[:, idx], G.cpu().numpy()[:, :, idx], 3)
+    plan.close()

@@ -44,12 +44,12 @@ def load():
         lib.orc_psd.restype = ctypes.c_double
         lib.orc_delay.restype = ctypes.c_double
         lib.orc_fisher.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_int, _D, _D, _D,
-                                   _I, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
+                                   _I, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
         lib.orc_waveform.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_int, _D, _D, _D,
                                      _I, ctypes.c_int, ctypes.c_int, _L, ctypes.c_int64, _D]
         lib.orc_fisher_tangent.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_int, _D,
-                                           _D, _D, _I, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                           ctypes.c_int, _D, _D]
+                                           _D, _D, _I, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int, _D, _D]
         lib.orc_strain.argtypes = [_D, ctypes.c_double, ctypes.c_int, _D, ctypes.c_int, _D,
                                    ctypes.c_int, _D, _D]
         lib.orc_strain_cstep.argtypes = [_D, ctypes.c_double, ctypes.c_int, _D, ctypes.c_int, _D,
@@ -177,7 +177,9 @@ def strain_plain(par13, sites, f, flags, tc_s=0.0, dt=0.0):
 
 def fisher(wl, want_fisher=True, per_ifo=False, nthreads=0):
     """SNR (and Fisher) of a synthetic workload, as a dict of numpy arrays:
-    snr[N], snr_ifo[n_ifo][N], fisher[P][P][N], fisher_ifo[n_ifo][P][P][N]."""
+    snr[N], snr_ifo[n_ifo][N], fisher[P][P][N], fisher_ifo[n_ifo][P][P][N].
+    With wl.active (the duty factor's on/off draws, uint8 [n_ifo][N]) the
+    interferometers that are off for an event are left out of its sums."""
     par = _f64(wl.par)
     n = par.shape[1]
     s = _f64(wl.site_array())
@@ -191,9 +193,11 @@ def fisher(wl, want_fisher=True, per_ifo=False, nthreads=0):
     snr_ifo = np.zeros((ni, n))
     F = np.zeros((P, P, n)) if want_fisher else None
     Fi = np.zeros((ni, P, P, n)) if (want_fisher and per_ifo) else None
+    act = getattr(wl, "active", None)
+    act = None if act is None else np.ascontiguousarray(act, dtype=np.uint8)
     load().orc_fisher(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
-                      npts.ctypes.data_as(_I), wl.flags, int(nthreads), _p(snr), _p(snr_ifo),
-                      _p(F), _p(Fi))
+                      npts.ctypes.data_as(_I), None if act is None else act.ctypes.data_as(ctypes.c_void_p),
+                      wl.flags, int(nthreads), _p(snr), _p(snr_ifo), _p(F), _p(Fi))
     out = {"snr": snr, "snr_ifo": snr_ifo}
     if want_fisher:
         out["fisher"] = F
@@ -241,7 +245,9 @@ def fisher_tangent(wl, site, which, nthreads=0):
     tc = None if wl.tc_s is None else _f64(wl.tc_s)
     snr2 = np.zeros((2, n))
     F = np.zeros((2, P, P, n))
+    act = getattr(wl, "active", None)
+    act = None if act is None else np.ascontiguousarray(act, dtype=np.uint8)
     load().orc_fisher_tangent(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
-                              npts.ctypes.data_as(_I), wl.flags, int(nthreads), int(site),
-                              int(which), _p(snr2), _p(F))
+                              npts.ctypes.data_as(_I), None if act is None else act.ctypes.data_as(ctypes.c_void_p),
+                              wl.flags, int(nthreads), int(site), int(which), _p(snr2), _p(F))
     return {"snr2": snr2, "fisher": F}

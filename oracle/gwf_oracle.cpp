@@ -453,8 +453,8 @@ using D1 = Dual<double, 1>;
 
 template <int P>
 void fisher_event_tangent(const double* par, double tc_s, const std::vector<Ifo<D1>>& ifos,
-                          double fmin, double fmax, int n, int flags, double* snr2 /* [2] */,
-                          double* F /* [2][P][P] */) {
+                          const std::vector<char>& on, double fmin, double fmax, int n, int flags,
+                          double* snr2 /* [2] */, double* F /* [2][P][P] */) {
   using S = Dual<D1, P>;
   Source<S> s = make_source<S>(par, tc_s);
   for (int i = 0; i < P; ++i) slot(s, i).d[i] = D1(1.0);
@@ -464,6 +464,7 @@ void fisher_event_tangent(const double* par, double tc_s, const std::vector<Ifo<
   std::vector<NeumaierSum> Gv(P * P), Gt(P * P);
   for (size_t d = 0; d < ifos.size(); ++d)
     for (int k = 0; k < n; ++k) {
+      if (!on[d]) break;                       // interferometer off for this event
       S hre, him;
       strain(s, ifos[d], f[k], flags, hre, him);
       D1 om = D1(4.0 * w[k]) / psd(ifos[d].S0, ifos[d].f0, f[k]);
@@ -662,8 +663,8 @@ int orc_waveform(int64_t n, const double* par, int64_t ld, const double* tc_s, i
 // and fisher[2][P][P][n].
 int orc_fisher_tangent(int64_t n, const double* par, int64_t ld, const double* tc_s, int n_site,
                        const double* sites, const double* fmin, const double* fmax,
-                       const int32_t* npts, int flags, int nthreads, int site, int which,
-                       double* snr2, double* fisher) {
+                       const int32_t* npts, const uint8_t* active, int flags, int nthreads, int site,
+                       int which, double* snr2, double* fisher) {
   std::vector<Ifo<D1>> ifos;
   for (int i = 0; i < n_site; ++i) {
     const double* r = sites + 7 * i;
@@ -691,8 +692,11 @@ int orc_fisher_tangent(int64_t n, const double* par, int64_t ld, const double* t
     double tcs = tc_s ? tc_s[e] : 0.0;
     double s2[2];
     std::vector<double> F(2 * P * P);
-    if (P == 13) fisher_event_tangent<13>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2, F.data());
-    else fisher_event_tangent<11>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2, F.data());
+    std::vector<char> on(ifos.size(), 1);
+    if (active)
+      for (size_t d = 0; d < ifos.size(); ++d) on[d] = active[(int64_t)d * n + e] != 0;
+    if (P == 13) fisher_event_tangent<13>(p, tcs, ifos, on, fmin[e], fhi, npts[e], flags, s2, F.data());
+    else fisher_event_tangent<11>(p, tcs, ifos, on, fmin[e], fhi, npts[e], flags, s2, F.data());
     snr2[e] = s2[0];
     snr2[n + e] = s2[1];
     for (int t = 0; t < 2; ++t)
@@ -705,11 +709,13 @@ int orc_fisher_tangent(int64_t n, const double* par, int64_t ld, const double* t
 // Outputs (any may be NULL except snr):
 //   snr[n]; snr_ifo[n_ifo][n] (SNR of each interferometer);
 //   fisher[P][P][n] network Fisher; fisher_ifo[n_ifo][P][P][n].
-// fmax NULL means each grid ends at the event's cut frequency.
+// fmax NULL means each grid ends at the event's cut frequency.  active
+// [n_ifo][n] (NULL: all on): interferometers off for an event (the duty
+// factor) are left out of its network sums and report zero.
 int orc_fisher(int64_t n, const double* par, int64_t ld, const double* tc_s, int n_site,
                const double* sites, const double* fmin, const double* fmax, const int32_t* npts,
-               int flags, int nthreads, double* snr, double* snr_ifo, double* fisher,
-               double* fisher_ifo) {
+               const uint8_t* active, int flags, int nthreads, double* snr, double* snr_ifo,
+               double* fisher, double* fisher_ifo) {
   auto ifos = expand_sites(n_site, sites);
   const int nifo = (int)ifos.size();
   const int P = (flags & FLAG_TIDAL) ? 13 : 11;
@@ -730,6 +736,12 @@ int orc_fisher(int64_t n, const double* par, int64_t ld, const double* tc_s, int
     } else {
       snr_event(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data());
     }
+    if (active)
+      for (int d = 0; d < nifo; ++d)
+        if (!active[(int64_t)d * n + e]) {
+          s2[d] = 0.0;
+          if (!F.empty()) std::fill(F.begin() + (size_t)d * P * P, F.begin() + (size_t)(d + 1) * P * P, 0.0);
+        }
     NeumaierSum tot;
     for (int d = 0; d < nifo; ++d) tot.add(s2[d]);
     snr[e] = std::sqrt(tot.get());

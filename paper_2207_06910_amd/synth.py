@@ -91,6 +91,7 @@ class Workload:
     npar: int                    # 11 (no tides) or 13
     tc_s: np.ndarray | None = None
     meta: dict = field(default_factory=dict)
+    active: np.ndarray | None = None   # uint8 [n_ifo][N] or None: interferometers on (duty factor)
 
     @property
     def n(self) -> int:
@@ -106,7 +107,22 @@ class Workload:
                         list(self.sites), self.fmin[idx].copy(), self.npts[idx].copy(),
                         None if self.fmax is None else self.fmax[idx].copy(),
                         self.flags, self.npar,
-                        None if self.tc_s is None else self.tc_s[idx].copy(), dict(self.meta))
+                        None if self.tc_s is None else self.tc_s[idx].copy(), dict(self.meta),
+                        None if self.active is None else np.ascontiguousarray(self.active[:, idx]))
+
+    def with_duty_factor(self, duty, seed: int) -> "Workload":
+        """A copy whose interferometers are each on for an event with
+        probability duty (a number, or one per site; a triangle's three
+        interferometers are drawn separately): uniform draws of a seeded
+        PCG64, interferometer by interferometer, compared with the factor."""
+        w = self.subset(np.arange(self.n))
+        w.name = self.name + f"[duty {duty}]"
+        per_site = np.broadcast_to(np.asarray(duty, dtype=np.float64), (len(self.sites),))
+        fac = np.concatenate([np.full(s.n_ifo, per_site[i]) for i, s in enumerate(self.sites)])
+        rng = np.random.default_rng(seed)
+        u = rng.random((len(fac), self.n))
+        w.active = (u < fac[:, None]).astype(np.uint8)
+        return w
 
     def with_npts(self, n: int) -> "Workload":
         w = self.subset(np.arange(self.n))

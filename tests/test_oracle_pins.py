@@ -767,3 +767,29 @@ def test_tidal_combinations_equal_mass_limit(orc):
     par = np.array([1.2, 0.25, 0.1, 1, 1, 1, 1, 0, 0, 0, 0, 400.0, 400.0])
     q = orc.basis.new_parameters(par, orc.LAMBDA_TILDE)
     assert abs(float(q[11]) - 400.0) < 1e-12 and abs(float(q[12])) < 1e-12
+
+
+# ------------------------------------------------------------ duty factor (sec. 3.1)
+def test_duty_factor_mask_in_the_oracle(orc):
+    """An all-on mask changes nothing; with interferometers off the network
+    Fisher and SNR^2 are the sums of the others' (from an unmasked run with
+    the per-interferometer matrices), and the off ones report zero; the seeded
+    draws are reproducible and on about `duty` of the time."""
+    wl = synth.bns1e4(n=6).with_npts(300)
+    ref = orc.fisher(wl, per_ifo=True)
+    on = wl.with_duty_factor(1.0, seed=3)
+    assert np.all(on.active == 1)
+    a = orc.fisher(on)
+    assert np.array_equal(a["fisher"], ref["fisher"]) and np.array_equal(a["snr"], ref["snr"])
+    w = wl.with_duty_factor(0.5, seed=7)
+    m = orc.fisher(w, per_ifo=True)
+    act = w.active.astype(bool)
+    want = np.einsum("dijn,dn->ijn", ref["fisher_ifo"], act)
+    np.testing.assert_allclose(m["fisher"], want, rtol=1e-13, atol=1e-13 * np.abs(want).max())
+    np.testing.assert_allclose(m["snr"] ** 2, np.einsum("dn,dn->n", ref["snr_ifo"] ** 2, act), rtol=1e-13)
+    assert np.all(m["snr_ifo"][~act] == 0) and np.all(m["fisher_ifo"].transpose(0, 3, 1, 2)[~act] == 0)
+    big = synth.bns1e4(n=4000)
+    d = big.with_duty_factor([0.8, 0.5, 0.3], seed=11)
+    frac = d.active.mean(axis=1)
+    np.testing.assert_allclose(frac, [0.8, 0.8, 0.8, 0.5, 0.3], atol=0.03)
+    assert np.array_equal(d.active, big.with_duty_factor([0.8, 0.5, 0.3], seed=11).active)

@@ -33,7 +33,7 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 MEASURED_TRAFFIC = {
     "items_kernel<tidal,rot,mixed>": 58.29e6,
     "items_kernel<tidal,rot>": 67.12e6,
-    "fisher_kernel<tidal,rot>": 113.94e6,
+    "fisher_kernel<tidal,rot>": None,
     "waveform_kernel<rot,tidal>": 7848.22e6,
     "waveform_kernel<rot,tidal,mixed>": 7858.03e6,
 }

@@ -116,6 +116,13 @@ typedef struct gwf_events {
                           Rows LAMBDA1/LAMBDA2 are read only with GWF_TIDAL.   */
   const double* tc_s;  /* device [n] or NULL: coalescence time in seconds used
                           only in the 2 pi f tc term of the waveform phase     */
+  const uint8_t* active; /* device [n_ifo][ld] or NULL (all on): interferometer d
+                          (numbered site by site, three for a triangle) takes
+                          part in event e's SNR, Fisher and adjoint only where
+                          active[d*ld + e] != 0 -- the paper's duty factor
+                          (sec. 3.1), the random draws being the caller's; its
+                          per-interferometer SNR is then 0.  The strain
+                          (gwf_waveform) is not affected.                      */
 } gwf_events;
 
 /* ------------------------------------------------------------ detectors */

@@ -23,7 +23,7 @@ NPAR_MAX = 13
 
 class Events(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("ld", ctypes.c_int64), ("par", ctypes.c_void_p),
-                ("tc_s", ctypes.c_void_p)]
+                ("tc_s", ctypes.c_void_p), ("active", ctypes.c_void_p)]
 
 
 class SiteDesc(ctypes.Structure):
@@ -179,6 +179,9 @@ class DeviceWorkload:
         self.npts = torch.as_tensor(np.ascontiguousarray(wl.npts), dtype=torch.int32, device=device)
         self.tc_s = None if wl.tc_s is None else torch.as_tensor(
             np.ascontiguousarray(wl.tc_s), dtype=torch.float64, device=device)
+        act = getattr(wl, "active", None)
+        self.active = None if act is None else torch.as_tensor(
+            np.ascontiguousarray(act, dtype=np.uint8), device=device)
         self.n_ifo = n_ifo(self.sites)
 
     def with_sites(self, sites) -> "DeviceWorkload":
@@ -192,7 +195,8 @@ class DeviceWorkload:
 
     def descriptors(self):
         ev = Events(self.n, self.par.shape[1], self.par.data_ptr(),
-                    None if self.tc_s is None else self.tc_s.data_ptr())
+                    None if self.tc_s is None else self.tc_s.data_ptr(),
+                    None if self.active is None else self.active.data_ptr())
         net, keep = network(self.sites)
         grid = Grid(0, self.fmin.data_ptr(), None if self.fmax is None else self.fmax.data_ptr(),
                     self.npts.data_ptr())

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kABlock, 2) void adjoint_kernel(AdjointArgs a) {
   if (tid < n_site) {
     double p[13];
     for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
-    site_setup_adj(p, a.net.site[tid], ec, sa[tid]);
+    site_setup_adj(p, a.net.site[tid], ec, sa[tid], site_arms_on(a.active, a.ld, e, a.net, tid));
   }
   const int col = tid >> 1;
   if ((tid & 1) == 0)

@@ -83,8 +83,9 @@ __host__ __device__ inline void pattern_map_t(double gamma, double zeta, double 
   }
 }
 
+// arm_on as for site_setup.
 __host__ __device__ inline void site_setup_adj(const double* p, const SiteDesc& sd, const EventC& ec,
-                                               SiteA& sa) {
+                                               SiteA& sa, uint32_t arm_on = 7u) {
   const double th = p[3], ph = p[4], psi = p[6];
   const double c2p = cos(2.0 * psi), s2p = sin(2.0 * psi);
   const double cdl = cos(sd.lon - ph), sdl = sin(sd.lon - ph);
@@ -109,17 +110,32 @@ __host__ __device__ inline void site_setup_adj(const double* p, const SiteDesc& 
     T3 al[3][4], be[3][4];
     for (int k = 0; k < 3; ++k)
       pattern_map_t(sd.gamma + kPi / 6.0 + kTwoPi * k / 3.0, kPi / 3.0, c2p, s2p, al[k], be[k]);
-    for (int j = 0; j < 4; ++j) {
-      sa.alpha[0][j] = al[0][j] + al[1][j]; sa.beta[0][j] = be[0][j] + be[1][j];
-      sa.alpha[1][j] = al[0][j] - al[1][j]; sa.beta[1][j] = be[0][j] - be[1][j];
+    if ((arm_on & 7u) == 7u) {
+      for (int j = 0; j < 4; ++j) {
+        sa.alpha[0][j] = al[0][j] + al[1][j]; sa.beta[0][j] = be[0][j] + be[1][j];
+        sa.alpha[1][j] = al[0][j] - al[1][j]; sa.beta[1][j] = be[0][j] - be[1][j];
+      }
+      sa.weff[0] = 1.5; sa.weff[1] = 0.5;
+      sa.n_eff = 2;
+    } else {
+      int m = 0;
+      for (int k = 0; k < 3; ++k)
+        if (arm_on >> k & 1u) {
+          for (int j = 0; j < 4; ++j) { sa.alpha[m][j] = al[k][j]; sa.beta[m][j] = be[k][j]; }
+          sa.weff[m] = 1.0;
+          ++m;
+        }
+      for (int r = m; r < 2; ++r) {
+        for (int j = 0; j < 4; ++j) { sa.alpha[r][j] = t3c(0.0); sa.beta[r][j] = t3c(0.0); }
+        sa.weff[r] = 0.0;
+      }
+      sa.n_eff = m;
     }
-    sa.weff[0] = 1.5; sa.weff[1] = 0.5;
-    sa.n_eff = 2;
   } else {
     pattern_map_t(sd.gamma, sd.zeta, c2p, s2p, sa.alpha[0], sa.beta[0]);
     for (int j = 0; j < 4; ++j) { sa.alpha[1][j] = t3c(0.0); sa.beta[1][j] = t3c(0.0); }
     sa.weff[0] = 1.0; sa.weff[1] = 0.0;
-    sa.n_eff = 1;
+    sa.n_eff = (arm_on & 1u) ? 1 : 0;
   }
   sa.pad = 0;
 }

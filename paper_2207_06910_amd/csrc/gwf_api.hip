@@ -106,6 +106,7 @@ gwf_status gwf_snr(const gwf_events* ev, const gwf_network* net, const gwf_grid*
   a.par = ev->par; a.ld = ev->ld; a.n = ev->n;
   a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
   a.tidal = (flags & GWF_TIDAL) ? 1 : 0;
+  a.active = ev->active;
   a.snr = snr; a.snr_ifo = snr_ifo; a.status = status;
   hipError_t err = gwf::launch_snr(a, (flags & GWF_EARTH_ROT) != 0, (hipStream_t)stream);
   if (err != hipSuccess) return api_hip_fail(err, "snr kernel launch");
@@ -125,6 +126,7 @@ gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_gr
   a.par = ev->par; a.ld = ev->ld; a.n = ev->n;
   a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
   a.snr_th = snr_th;
+  a.active = ev->active;
   a.fisher = fisher; a.snr = snr; a.status = status;
   const bool rot = (flags & GWF_EARTH_ROT) != 0, tidal = (flags & GWF_TIDAL) != 0;
   hipStream_t s = (hipStream_t)stream;
@@ -132,7 +134,7 @@ gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_gr
   if (snr_ifo || snr_th > 0.0) {
     gwf::SnrArgs b{};
     b.net = a.net; b.par = a.par; b.ld = a.ld; b.n = a.n;
-    b.fmin = a.fmin; b.fmax = a.fmax; b.npts = a.npts; b.tidal = tidal;
+    b.fmin = a.fmin; b.fmax = a.fmax; b.npts = a.npts; b.tidal = tidal; b.active = a.active;
     b.snr = snr; b.snr_ifo = snr_ifo; b.status = nullptr;
     hipError_t err = gwf::launch_snr(b, rot, s);
     if (err != hipSuccess) return api_hip_fail(err, "snr kernel launch");
@@ -176,6 +178,7 @@ gwf_status gwf_fisher_adjoint(const gwf_events* ev, const gwf_network* net, cons
   a.par = ev->par; a.ld = ev->ld; a.n = ev->n;
   a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
   a.gbar = gbar; a.status = status; a.w_snr = w_snr; a.w_fisher = w_fisher;
+  a.active = ev->active;
   a.grad_event = grad_event; a.grad = grad;
   hipError_t err = gwf::launch_adjoint(a, (flags & GWF_TIDAL) != 0, (flags & GWF_EARTH_ROT) != 0,
                                        (hipStream_t)stream);

@@ -41,7 +41,7 @@ __global__ void setup_kernel(SetupArgs a) {
   if (!ec.status)
     for (int s = 0; s < a.net.n_site; ++s) {
       SiteC sc;
-      site_setup(p, a.net.site[s], ec, sc);
+      site_setup(p, a.net.site[s], ec, sc, site_arms_on(a.active, a.ld, t, a.net, s));
       a.sic[t * a.net.n_site + s] = sc;
     }
 }

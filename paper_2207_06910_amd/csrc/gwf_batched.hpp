@@ -17,6 +17,7 @@ struct SetupArgs {
   const double* fmax;
   const int32_t* npts;
   const int32_t* npts_plan;   // grid lengths the items were built from
+  const uint8_t* active;      // [n_ifo][ld] or NULL: interferometers taking part
   NetDesc net;
   uint32_t flags;
   EventC* evc;                // [n]

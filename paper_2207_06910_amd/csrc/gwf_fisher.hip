@@ -62,7 +62,7 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(Fis
     }
     return;
   }
-  if (tid < n_site) site_setup(p, a.net.site[tid], ec, sc[tid]);
+  if (tid < n_site) site_setup(p, a.net.site[tid], ec, sc[tid], site_arms_on(a.active, a.ld, e, a.net, tid));
   __syncthreads();
 
   double t = 0.0;
@@ -157,6 +157,7 @@ __global__ __launch_bounds__(kBlock) void snr_kernel(SnrArgs a) {
     for (int i = 0; i < a.net.n_ifo; ++i) {
       double t = red[0][i];
       for (int w = 1; w < kWaves; ++w) t += red[w][i];
+      if (a.active && !a.active[(int64_t)i * a.ld + e]) t = 0.0;   // off for this event
       tot += t;
       if (a.snr_ifo) a.snr_ifo[(int64_t)i * a.n + e] = sqrt(t);
     }

@@ -11,6 +11,7 @@ struct FisherArgs {
   const double* fmin;
   const double* fmax;       // NULL: cut frequency
   const int32_t* npts;
+  const uint8_t* active;    // [n_ifo][ld] or NULL: interferometers taking part (duty factor)
   NetDesc net;
   double snr_th;
   const double* snr_pre;    // NULL, or SNRs of a previous pass for the threshold
@@ -25,6 +26,7 @@ struct SnrArgs {
   const double* fmin;
   const double* fmax;
   const int32_t* npts;
+  const uint8_t* active;    // [n_ifo][ld] or NULL
   NetDesc net;
   int32_t tidal;
   double* snr;              // [n]
@@ -92,6 +94,7 @@ struct AdjointArgs {
   const double* fmin;
   const double* fmax;       // NULL: cut frequency
   const int32_t* npts;
+  const uint8_t* active;    // [n_ifo][ld] or NULL
   NetDesc net;
   const double* gbar;       // [P][P][n]
   const int32_t* status;    // [n] or NULL

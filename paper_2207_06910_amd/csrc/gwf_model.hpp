@@ -400,8 +400,13 @@ __host__ __device__ inline void pattern_map(double gamma, double zeta, double c2
 // third arm's response is minus the sum of the other two (closed loop,
 // sec. 3.3), the Gram sum over its arms a a^T + b b^T + (a+b)(a+b)^T equals
 // (3/2)(a+b)(a+b)^T + (1/2)(a-b)(a-b)^T: two effective interferometers.
+// arm_on: bit k set where arm k of the site takes part (the duty factor).
+// A triangle with all three arms uses the closure form (two effective
+// interferometers with weights 3/2 and 1/2); with some arms off, every arm
+// that is on is its own effective interferometer.  A site with no arm on has
+// none (its patterns are still set for the strain).
 __host__ __device__ inline void site_setup(const double* p, const SiteDesc& sd, const EventC& ec,
-                                           SiteC& sc) {
+                                           SiteC& sc, uint32_t arm_on = 7u) {
   const double th = p[3], ph = p[4], psi = p[6];
   const double c2p = cos(2.0 * psi), s2p = sin(2.0 * psi);
   sc.cdl = cos(sd.lon - ph);
@@ -426,12 +431,28 @@ __host__ __device__ inline void site_setup(const double* p, const SiteDesc& sd, 
       pattern_map(sd.gamma + kPi / 6.0 + kTwoPi * k / 3.0, kPi / 3.0, c2p, s2p, al[k], be[k]);
       for (int j = 0; j < 4; ++j) { sc.arm_alpha[k][j] = al[k][j]; sc.arm_beta[k][j] = be[k][j]; }
     }
-    for (int j = 0; j < 4; ++j) {
-      sc.alpha[0][j] = al[0][j] + al[1][j]; sc.beta[0][j] = be[0][j] + be[1][j];
-      sc.alpha[1][j] = al[0][j] - al[1][j]; sc.beta[1][j] = be[0][j] - be[1][j];
+    sc.n_arm = 3;
+    if ((arm_on & 7u) == 7u) {
+      for (int j = 0; j < 4; ++j) {
+        sc.alpha[0][j] = al[0][j] + al[1][j]; sc.beta[0][j] = be[0][j] + be[1][j];
+        sc.alpha[1][j] = al[0][j] - al[1][j]; sc.beta[1][j] = be[0][j] - be[1][j];
+      }
+      sc.weff[0] = 1.5; sc.weff[1] = 0.5;
+      sc.n_eff = 2;
+    } else {
+      int m = 0;
+      for (int k = 0; k < 3; ++k)
+        if (arm_on >> k & 1u) {
+          for (int j = 0; j < 4; ++j) { sc.alpha[m][j] = al[k][j]; sc.beta[m][j] = be[k][j]; }
+          sc.weff[m] = 1.0;
+          ++m;
+        }
+      for (int r = m; r < 2; ++r) {
+        for (int j = 0; j < 4; ++j) { sc.alpha[r][j] = 0.0; sc.beta[r][j] = 0.0; }
+        sc.weff[r] = 0.0;
+      }
+      sc.n_eff = m;
     }
-    sc.weff[0] = 1.5; sc.weff[1] = 0.5;
-    sc.n_eff = 2; sc.n_arm = 3;
   } else {
     pattern_map(sd.gamma, sd.zeta, c2p, s2p, sc.alpha[0], sc.beta[0]);
     for (int j = 0; j < 4; ++j) {
@@ -439,8 +460,23 @@ __host__ __device__ inline void site_setup(const double* p, const SiteDesc& sd, 
       sc.alpha[1][j] = 0.0; sc.beta[1][j] = 0.0;
     }
     sc.weff[0] = 1.0; sc.weff[1] = 0.0;
-    sc.n_eff = 1; sc.n_arm = 1;
+    sc.n_eff = (arm_on & 1u) ? 1 : 0; sc.n_arm = 1;
   }
+}
+
+// The arm mask of site s for event e from the per-interferometer flags
+// active[ifo][ld] (NULL: every arm on); interferometers are numbered site
+// by site, three for a triangle, one for an L.
+__host__ __device__ inline uint32_t site_arms_on(const uint8_t* active, int64_t ld, int64_t e,
+                                                 const NetDesc& net, int s) {
+  if (!active) return 7u;
+  int ifo0 = 0;
+  for (int u = 0; u < s; ++u) ifo0 += net.site[u].shape == 1 ? 3 : 1;
+  const int na = net.site[s].shape == 1 ? 3 : 1;
+  uint32_t m = 0;
+  for (int k = 0; k < na; ++k)
+    if (active[(int64_t)(ifo0 + k) * ld + e]) m |= 1u << k;
+  return m;
 }
 
 // ---------------------------------------------------------- sin and cos

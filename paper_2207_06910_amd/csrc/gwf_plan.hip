@@ -117,6 +117,7 @@ gwf_status enqueue(gwf_plan* p, const Outs& o, hipStream_t s) {
   sa.par = p->ev.par; sa.ld = p->ev.ld; sa.n = p->n;
   sa.fmin = p->grid.fmin; sa.fmax = p->grid.fmax; sa.npts = p->grid.npts; sa.npts_plan = p->npts_plan;
   sa.net = p->net; sa.flags = p->flags; sa.evc = p->evc; sa.sic = p->sic; sa.status = o.status;
+  sa.active = p->ev.active;
   hipError_t err = launch_setup(sa, s);
   if (err == hipSuccess) err = launch_fill_i32(p->counter, 0, 1, s);
   if (err == hipSuccess) {

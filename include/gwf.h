@@ -294,9 +294,13 @@ enum { GWF_SKY_STERAD = 0, GWF_SKY_SQDEG = 1 };
  *   GWF_INV_SVD      SVD, H^-1 = V diag(1/s) U^T; with truncate, singular
  *                    values below svals_thresh x max(s) are raised to it
  *   GWF_INV_SVD_REG  SVD, singular values below svals_thresh x max(s) left out
+ *   GWF_INV_CHO_DD   Cholesky, L^-1 and L^-T L^-1 in double-double arithmetic
+ *                    (about 106 bits): the covariance of the stored FP64 matrix
+ *                    to about kappa 2^-104 before its rounding to FP64, the
+ *                    GPU's counterpart of the paper's mpmath inversion
  * The SVD is the one-sided Jacobi of the condition number, run again with
  * the rotations accumulated; it also gives the eigen-decomposition. */
-enum { GWF_INV_CHO = 0, GWF_INV_CHO_SVD = 1, GWF_INV_SVD = 2, GWF_INV_SVD_REG = 3 };
+enum { GWF_INV_CHO = 0, GWF_INV_CHO_SVD = 1, GWF_INV_SVD = 2, GWF_INV_SVD_REG = 3, GWF_INV_CHO_DD = 4 };
 
 typedef struct gwf_cov_opts {
   uint32_t fixed_mask;              /* parameters held fixed (step 1)            */

@@ -65,7 +65,7 @@ class CovOptions(ctypes.Structure):
 
 
 SKY_STERAD, SKY_SQDEG = 0, 1
-INV_METHODS = {"cho": 0, "cho_svd": 1, "svd": 2, "svd_reg": 3}
+INV_METHODS = {"cho": 0, "cho_svd": 1, "svd": 2, "svd_reg": 3, "cho_dd": 4}
 
 
 class GwfError(RuntimeError):
@@ -303,7 +303,7 @@ def covariance(F, status=None, fixed=(), prior=None, marg=(), theta=None, sky_le
     to the P rows of F.  Returns cov [Po][Po][N], sigma [Po][N], cond, inv_err,
     logdet, status, sky (if requested) and ``out``, the indices of F's rows
     in cov and sigma.  ``method``: "cho", "cho_svd", "svd" (with
-    ``truncate``) or "svd_reg"; ``eigen``: also eigval [Pk][N] and eigvec
+    ``truncate``), "svd_reg" or "cho_dd" (double-double Cholesky); ``eigen``: also eigval [Pk][N] and eigvec
     [Pk][Pk][N] of the normalised matrix that is inverted."""
     import torch
     _dev_f64(F)

@@ -232,14 +232,15 @@ gwf_status gwf_covariance(int32_t P, int64_t n, const double* fisher, const gwf_
   if (o.fixed_mask & o.marg_mask)
     return api_fail(GWF_E_INVALID_ARG, "a parameter cannot be both fixed and marginalised");
   if (std::isnan(o.cond_max)) return api_fail(GWF_E_INVALID_ARG, "cond_max is NaN");
-  if (o.method < GWF_INV_CHO || o.method > GWF_INV_SVD_REG)
+  if (o.method < GWF_INV_CHO || o.method > GWF_INV_CHO_DD)
     return api_fail(GWF_E_INVALID_ARG, "method=%d unknown", o.method);
-  if (o.method >= GWF_INV_SVD && !(o.svals_thresh >= 0.0 && o.svals_thresh < 1.0))
+  if ((o.method == GWF_INV_SVD || o.method == GWF_INV_SVD_REG) &&
+      !(o.svals_thresh >= 0.0 && o.svals_thresh < 1.0))
     return api_fail(GWF_E_INVALID_ARG, "svals_thresh=%g must be in [0, 1)", o.svals_thresh);
   gwf::InvertArgs a{};
   a.method = o.method;
   a.truncate = o.truncate != 0;
-  a.svals_thresh = o.method >= GWF_INV_SVD ? o.svals_thresh : 0.0;
+  a.svals_thresh = (o.method == GWF_INV_SVD || o.method == GWF_INV_SVD_REG) ? o.svals_thresh : 0.0;
   a.eigval = eigval;
   a.eigvec = eigvec;
   a.n = n; a.fisher = fisher; a.cond_max = o.cond_max; a.cov = cov; a.sigma = sigma;

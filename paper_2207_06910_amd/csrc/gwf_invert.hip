@@ -30,6 +30,7 @@
 // the same order as the textbook one-thread-per-matrix loops (left-looking
 // Cholesky, row-wise L^-1, C_ij = sum_{k >= max(i,j)} Li_ki Li_kj), so the
 // lane layout changes no result bit.
+#include "gwf_dd.hpp"
 #include "gwf_invert.hpp"
 #include "gwf_kernels.hpp"
 
@@ -79,6 +80,8 @@ __device__ inline void load_col(const InvertArgs& a, int64_t e, int j, bool vali
     h[i] = v;
   }
 }
+
+__device__ inline dd shfl_dd(dd v, int src) { return dd{__shfl(v.hi, src, kGroup), __shfl(v.lo, src, kGroup)}; }
 
 // At least 3 waves per SIMD: left free, the compiler spends all 256 registers
 // on load scheduling and a SIMD runs one wave of this latency-bound kernel.
@@ -241,7 +244,7 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
   // H^-1 = V diag(w) U^T with w = 1/s (or the paper's truncated or dropped
   // small singular values), and eigenvalue j = sign(u_j . v_j) s_j with
   // eigenvector v_j.  Only wavefronts holding such a matrix run it.
-  const bool svd_grp = go0 && !ill && (a.method >= 2 || (a.method == 1 && !pd));
+  const bool svd_grp = go0 && !ill && (a.method == 2 || a.method == 3 || (a.method == 1 && !pd));
   const bool want_eig = a.eigval != nullptr || a.eigvec != nullptr;
   bool svd_done = false;
   if (__any(svd_grp) || want_eig) {
@@ -359,6 +362,111 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
     if (svd_grp && !pd) ld = allpos ? lsv : nan;
     svd_done = svd_grp;
     ok = ok || svd_done;
+  }
+  // ---- double-double Cholesky (method 4): normalisation, factorisation,
+  // L^-1 and C = L^-T L^-1 again in double-double arithmetic (~106 bits), so
+  // the covariance of the FP64 matrix comes out to about kappa 2^-104 before
+  // its rounding to FP64 -- what the paper obtains with mpmath.  Same lane
+  // layout and operation order as the FP64 steps; L and L^-1 are staged in
+  // LDS as (hi in Ls, lo in Gs).
+  if (a.method == 4) {
+    const bool ddg = go0 && !ill;
+    dd dn[P], dnj = dd_from(1.0);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      dn[i] = dd_from(1.0);
+      if (ddg && normalise) {
+        const int64_t ki = a.keep[i];
+        dn[i] = dd_sqrt(dd_from(a.fisher[(ki * a.p_full + ki) * a.n + e] + a.prior[i]));
+      }
+      if (i == j) dnj = dn[i];
+    }
+    dd lq[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      lq[i] = dd_from(0.0);
+      if (ddg && j < P) {
+        const int r = i <= j ? i : j, c = i <= j ? j : i;
+        double v = a.fisher[((int64_t)a.keep[r] * a.p_full + a.keep[c]) * a.n + e];
+        if (i == j) v += a.prior[j];
+        lq[i] = dd_div(dd_from(v), dd_mul(dn[i], dnj));
+      }
+    }
+    bool pdd = true;
+    dd lqjj = dd_from(1.0);
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const dd piv = shfl_dd(lq[k], k);
+      pdd = pdd && (piv.hi > 0.0);
+      const dd lkk = dd_sqrt(piv);
+      const dd inv = dd_div(dd_from(1.0), lkk);
+      const dd ljk = dd_mul(lq[k], inv);
+#pragma unroll
+      for (int i = k + 1; i < P; ++i) {
+        const dd lik = dd_mul(shfl_dd(lq[i], k), inv);
+        if (j > k) lq[i] = dd_sub(lq[i], dd_mul(lik, ljk));
+        else if (j == k) lq[i] = lik;
+      }
+      if (j == k) {
+        lqjj = lkk;
+        lq[k] = inv;
+      }
+    }
+    if (ddg && j < P) {
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+        if (i >= j) {
+          Ls[g][j][i] = lq[i].hi;
+          Gs[g][j][i] = lq[i].lo;
+        }
+    }
+    __syncthreads();
+    dd yq[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      dd sacc = dd_from(0.0);
+#pragma unroll
+      for (int k = 0; k < i; ++k) sacc = dd_add(sacc, dd_mul(dd{Ls[g][k][i], Gs[g][k][i]}, yq[k]));
+      const dd inv_ii = dd{Ls[g][i][i], Gs[g][i][i]};
+      yq[i] = i < j ? dd_from(0.0) : i == j ? inv_ii : dd_neg(dd_mul(sacc, inv_ii));
+    }
+    __syncthreads();
+    if (ddg && j < P) {
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        Ls[g][j][k] = yq[k].hi;
+        Gs[g][j][k] = yq[k].lo;
+      }
+    }
+    __syncthreads();
+    double cc[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      dd sacc = dd_from(0.0);
+      if (ddg && j < P && i <= j) {
+#pragma unroll
+        for (int k = i; k < P; ++k) sacc = dd_add(sacc, dd_mul(dd{Ls[g][i][k], Gs[g][i][k]}, yq[k]));
+        sacc = dd_div(sacc, dd_mul(dn[i], dnj));
+      }
+      cc[i] = sacc.hi + sacc.lo;
+    }
+    __syncthreads();
+    if (ddg && j < P) {
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+        if (i <= j) {
+          Ls[g][j][i] = cc[i];
+          Ls[g][i][j] = cc[i];
+        }
+    }
+    __syncthreads();
+    // ln det from the double-double factor
+    double ldd = own ? 2.0 * (log(dnj.hi) + dnj.lo / dnj.hi + log(lqjj.hi) + lqjj.lo / lqjj.hi) : 0.0;
+#pragma unroll
+    for (int off = kGroup / 2; off >= 1; off >>= 1) ldd += __shfl_xor(ldd, off, kGroup);
+    pd = pdd;
+    ld = 0.5 * ldd;
+    ok = ddg && pdd;
   }
   // Gamma again (L2-resident) for the residual
   if (a.inv_err && ok && j < P) load_row<P>(a, e, j, Gs[g][j]);

@@ -57,7 +57,8 @@ struct InvertArgs {
   double* sky;              // [n] or NULL
   // Inversion method (sec. 4.1): 0 Cholesky, a failure flagged; 1 an SVD
   // where the Cholesky fails; 2 SVD, with truncate: singular values below
-  // svals_thresh x max raised to that value; 3 SVD leaving them out.
+  // svals_thresh x max raised to that value; 3 SVD leaving them out;
+  // 4 Cholesky in double-double arithmetic.
   int32_t method, truncate;
   double svals_thresh;
   double* eigval;           // [P][n] or NULL: eigenvalues of the normalised kept matrix

@@ -10,7 +10,8 @@ SRC = os.path.join(HERE, "model_host.hip")
 LIB = os.path.join(HERE, "libmodel_host.so")
 DEPS = [SRC, os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_model.hpp"),
         os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_adjoint.hpp"),
-        os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_invert.hpp")]
+        os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_invert.hpp"),
+        os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_dd.hpp")]
 _lib = None
 
 
@@ -81,3 +82,15 @@ def jacobi_cond(F):
     rc = lib.model_jacobi_cond_host(ctypes.c_int(P), ctypes.c_int64(n), P_(F), P_(cond), P_(sweeps))
     assert rc == 0, "unsupported size"
     return cond, sweeps
+
+
+def dd_op(op, a, b=(0.0, 0.0)):
+    """The inversion's double-double primitive `op` (0 add, 1 sub, 2 mul,
+    3 mul swapped, 4 div, 5 sqrt) on (hi, lo) pairs; returns (hi, lo)."""
+    lib = load()
+    x = np.array(a, dtype=np.float64)
+    y = np.array(b, dtype=np.float64)
+    o = np.zeros(2)
+    P_ = lambda v: v.ctypes.data_as(ctypes.c_void_p)
+    lib.model_dd(ctypes.c_int(op), P_(x), P_(y), P_(o))
+    return float(o[0]), float(o[1])

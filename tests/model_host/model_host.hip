@@ -5,6 +5,7 @@
 #include <cmath>
 #include <vector>
 
+#include "../../paper_2207_06910_amd/csrc/gwf_dd.hpp"
 #include "../../paper_2207_06910_amd/csrc/gwf_invert.hpp"
 #include "../../paper_2207_06910_amd/csrc/gwf_model.hpp"
 
@@ -193,4 +194,21 @@ extern "C" int model_jacobi_cond_host(int P, int64_t n, const double* F, double*
     }
   }
   return 0;
+}
+
+// ---- double-double primitives of the inversion (op: 0 add, 1 sub, 2 mul,
+// 3 mul with the operands swapped, 4 div, 5 sqrt of a)
+extern "C" void model_dd(int op, const double* a, const double* b, double* out) {
+  const dd x{a[0], a[1]}, y{b[0], b[1]};
+  dd r{0.0, 0.0};
+  switch (op) {
+    case 0: r = dd_add(x, y); break;
+    case 1: r = dd_sub(x, y); break;
+    case 2: r = dd_mul(x, y); break;
+    case 3: r = dd_mul(y, x); break;
+    case 4: r = dd_div(x, y); break;
+    default: r = dd_sqrt(x); break;
+  }
+  out[0] = r.hi;
+  out[1] = r.lo;
 }

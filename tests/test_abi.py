@@ -116,7 +116,7 @@ def test_covariance_options_rejected_on_host():
     assert call(opts(sky_level=90.0), theta=None) == 1
     assert call(opts(sky_level=90.0), sky=None) == 1
     assert call(opts(sky_level=90.0, sky_units=2)) == 1
-    assert call(opts(method=4)) == 1
+    assert call(opts(method=5)) == 1
     assert call(opts(method=2, svals_thresh=1.0)) == 1
     assert call(opts(method=3, svals_thresh=float("nan"))) == 1
 

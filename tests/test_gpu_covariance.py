@@ -241,3 +241,48 @@ def test_eigen_decomposition_against_oracle(lib, orc):
     val, vec = orc.eigen(np.ascontiguousarray(F[np.ix_(keep, keep)]))
     assert np.max(np.abs(g["eigval"] - val) / np.abs(val).max(axis=0)) < 1e-12
     assert np.max(np.abs(g["eigvec"] - vec)) < 1e-10
+
+
+# ------------------------------------------------------------ double-double Cholesky
+def test_double_double_cholesky_against_oracle(lib, orc):
+    """'cho_dd' (the Cholesky inversion in double-double, the counterpart of
+    the paper's arbitrary-precision inversion) against the oracle's 50-digit
+    inverse of the same FP64 matrices: on BNS Fisher matrices and on
+    synthetic spectra up to kappa ~ 1e18, within max(1e-14, 1e3 kappa 2^-104)
+    of the normalised covariance, far inside the FP64 Cholesky's
+    1e3 kappa 2^-53 (which the worst of these exceed); the epilogue (fixed
+    parameters, priors, marginalisation, sky area) on top of it as for
+    'cho'."""
+    mp = pytest.importorskip("mpmath")
+    UD = 2.0 ** -104
+    wl = synth.bns1e4(n=12).with_npts(2500)
+    F = orc.fisher(wl)["fisher"]
+    rng = np.random.default_rng(41)
+    P = 13
+    S = _spectra(rng, P, 12, lambda e: np.geomspace(1.0, 10.0 ** (6 + e), P))
+    for M in (F, S):
+        g = _gpu(lib, M, method="cho_dd")
+        ref = orc.covariance(M, method="cho")
+        assert np.array_equal(g["status"], ref["status"])
+        ok = ref["status"] == 0
+        assert ok.sum() >= 10
+        kap = ref["cond"]
+        assert np.all(np.abs(g["cond"][ok] / kap[ok] - 1) <= np.maximum(1e-9, 1e3 * kap[ok] * U))
+        tol = np.maximum(1e-14, 1e3 * kap * UD)
+        _cov_close(g, ref, ok, tol)
+        rels = np.abs(g["sigma"][:, ok] / np.sqrt(np.einsum("iie->ie", ref["cov"][:, :, ok])) - 1)
+        assert np.all(rels <= tol[ok])
+        with mp.workdps(50):
+            ldr = np.array([float(mp.log(mp.det(mp.matrix(M[:, :, e].tolist())))) for e in np.flatnonzero(ok)])
+        assert np.all(np.abs(g["logdet"][ok] - ldr) <= 1e-13 * np.maximum(1.0, np.abs(ldr)))
+        assert np.all(g["inv_err"][ok] >= 0)
+    # the FP64 Cholesky misses the double-double bound on the worst spectra
+    g64 = _gpu(lib, S, method="cho")
+    ref = orc.covariance(S, method="cho")
+    dc = np.sqrt(np.einsum("iie->ie", ref["cov"]))
+    e64 = (np.abs(g64["cov"] - ref["cov"]) / (dc[:, None, :] * dc[None, :, :])).max(axis=(0, 1))
+    assert e64.max() > 1e-12
+    # the epilogue on the double-double inverse
+    g = _gpu(lib, F, theta=wl.par[3], fixed=FIXED, prior=PRIOR, marg=MARG, method="cho_dd")
+    ref = orc.covariance_epilogue(F, fixed=FIXED, prior=PRIOR, marg=MARG, theta=wl.par[3])
+    _compare(g, ref)

@@ -31,11 +31,11 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # profiles/bns1e4_hbm_counters.md (calibrated against a 256 MiB copy: fetch
 # x 2.000, write x 1.000).  Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
-    "items_kernel<tidal,rot,mixed>": 58.29e6,
+    "items_kernel<tidal,rot,mixed>": 58.42e6,
     "items_kernel<tidal,rot>": 67.12e6,
-    "fisher_kernel<tidal,rot>": None,
-    "waveform_kernel<rot,tidal>": 7848.22e6,
-    "waveform_kernel<rot,tidal,mixed>": 7858.03e6,
+    "fisher_kernel<tidal,rot>": 161.33e6,
+    "waveform_kernel<rot,tidal>": 7848.55e6,
+    "waveform_kernel<rot,tidal,mixed>": 7860.59e6,
 }
 
 
@@ -293,19 +293,23 @@ def main():
     stc, skyc = outc["status"].cpu().numpy(), outc["sky"].cpu().numpy()
     log(f"covariance epilogue kernel {cov_ms:.3f} ms, inverted {int(np.sum(stc == 0))}/{wl.n} "
         f"(+{int(np.sum(stc == 32))} by SVD), median 90% sky area {float(np.median(skyc[stc == 0])):.3g} deg^2")
-    # every matrix by SVD, with its eigen-decomposition (the paper's 'svd' and CheckFisher)
-    outs = {}
-    for i in range(2):
-        binding.covariance(outf["fisher"], outf["status"], method="svd", eigen=True, out=outs)
-    ts = []
-    for i in range(args.steps):
-        ev[0].record(stream)
-        binding.covariance(outf["fisher"], outf["status"], method="svd", eigen=True, out=outs)
-        ev[1].record(stream)
-        ev[1].synchronize()
-        ts.append(ev[0].elapsed_time(ev[1]))
-    svd_ms = float(np.mean(ts))
-    log(f"SVD inversion with eigen-decomposition {svd_ms:.3f} ms")
+    def time_cov(**kw):
+        o = {}
+        for i in range(2):
+            binding.covariance(outf["fisher"], outf["status"], out=o, **kw)
+        t = []
+        for i in range(args.steps):
+            ev[0].record(stream)
+            binding.covariance(outf["fisher"], outf["status"], out=o, **kw)
+            ev[1].record(stream)
+            ev[1].synchronize()
+            t.append(ev[0].elapsed_time(ev[1]))
+        return float(np.mean(t))
+    # every matrix by SVD, with its eigen-decomposition (the paper's 'svd' and
+    # CheckFisher), and every 13 x 13 matrix by the double-double Cholesky
+    svd_ms = time_cov(method="svd", eigen=True)
+    dd_ms = time_cov(method="cho_dd")
+    log(f"SVD inversion with eigen-decomposition {svd_ms:.3f} ms, double-double Cholesky {dd_ms:.3f} ms")
     cov_form = {"covariance_epilogue": {
         "workload": "bns1e4 Fisher matrices: chi1z, chi2z fixed; Gaussian priors of variance 2 pi^2 "
                     "on theta, phi, iota, psi, Phicoal; Lambda1, Lambda2 marginalised; 90% sky area",
@@ -313,7 +317,7 @@ def main():
         "events_per_s": round(wl.n / (cov_ms * 1e-3), 1), "inverted": int(np.sum(stc == 0)),
         "inverted_by_svd": int(np.sum(stc == 32)),
         "median_sky_deg2": round(float(np.median(skyc[stc == 0])), 4),
-        "svd_with_eigen_ms": round(svd_ms, 4)}}
+        "svd_with_eigen_ms": round(svd_ms, 4), "cho_dd_ms": round(dd_ms, 4)}}
 
     # ---- strain output (gwf_waveform): HBM-bound, 16 B per point and interferometer
     ends = torch.cumsum(dw.npts.to(torch.int64), 0)

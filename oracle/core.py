@@ -175,11 +175,25 @@ def strain_plain(par13, sites, f, flags, tc_s=0.0, dt=0.0):
     return out[..., 0] + 1j * out[..., 1]
 
 
+def restrict_rows(F, par_mask):
+    """Each event's Fisher matrix over its own parameter set: in F[P][P][N]
+    (in place), the rows and columns of parameters outside event e's set
+    (bit i of par_mask[e] clear) are set to 0."""
+    P = F.shape[0]
+    for i in range(P):
+        out = ((np.asarray(par_mask, dtype=np.int64) >> i) & 1) == 0
+        F[i, :, out] = 0.0
+        F[:, i, out] = 0.0
+    return F
+
+
 def fisher(wl, want_fisher=True, per_ifo=False, nthreads=0):
     """SNR (and Fisher) of a synthetic workload, as a dict of numpy arrays:
     snr[N], snr_ifo[n_ifo][N], fisher[P][P][N], fisher_ifo[n_ifo][P][P][N].
     With wl.active (the duty factor's on/off draws, uint8 [n_ifo][N]) the
-    interferometers that are off for an event are left out of its sums."""
+    interferometers that are off for an event are left out of its sums; with
+    wl.par_mask (uint32 [N]) each event's matrix covers its own parameters
+    only (restrict_rows)."""
     par = _f64(wl.par)
     n = par.shape[1]
     s = _f64(wl.site_array())
@@ -198,6 +212,12 @@ def fisher(wl, want_fisher=True, per_ifo=False, nthreads=0):
     load().orc_fisher(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
                       npts.ctypes.data_as(_I), None if act is None else act.ctypes.data_as(ctypes.c_void_p),
                       wl.flags, int(nthreads), _p(snr), _p(snr_ifo), _p(F), _p(Fi))
+    pm = getattr(wl, "par_mask", None)
+    if pm is not None and want_fisher:
+        restrict_rows(F, pm)
+        if Fi is not None:
+            for d in range(ni):
+                restrict_rows(Fi[d], pm)
     out = {"snr": snr, "snr_ifo": snr_ifo}
     if want_fisher:
         out["fisher"] = F
@@ -250,4 +270,8 @@ def fisher_tangent(wl, site, which, nthreads=0):
     load().orc_fisher_tangent(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
                               npts.ctypes.data_as(_I), None if act is None else act.ctypes.data_as(ctypes.c_void_p),
                               wl.flags, int(nthreads), int(site), int(which), _p(snr2), _p(F))
+    pm = getattr(wl, "par_mask", None)
+    if pm is not None:
+        restrict_rows(F[0], pm)
+        restrict_rows(F[1], pm)
     return {"snr2": snr2, "fisher": F}

@@ -18,6 +18,11 @@ smallest absolute eigenvalue, here of the normalised matrix), the
 threshold above which no inversion is attempted (default 1e50), and the
 inversion error eps = max_ij |(Gamma Gamma^-1 - 1)_ij|.
 
+Per-event parameter sets (par_mask, bit i for parameter i): an event's
+Fisher matrix is that of its own parameters, so only that block is inverted
+(or decomposed); the covariance of a parameter outside the set is 0 in its
+row and column and its sigma NaN (the layout the GPU library returns).
+
 Status bits: 2 = not positive definite (Cholesky failed; the paper would fall
 back to an SVD, here the event is only flagged), 4 = condition number above
 the threshold.  Flagged events get NaN covariances.
@@ -94,18 +99,27 @@ def _svd_inverse(Gh, drop: bool, truncate: bool, thresh: float):
     return V.T * mp.diag(w) * U.T
 
 
-def eigen(fisher: np.ndarray, dps: int = 50):
+def _in_set(par_mask, e: int, i: int) -> bool:
+    return par_mask is None or bool((int(par_mask[e]) >> i) & 1)
+
+
+def eigen(fisher: np.ndarray, dps: int = 50, par_mask=None):
     """Eigenvalues (ascending) and eigenvectors of each normalised Fisher
     matrix (rows and columns divided by sqrt(diag), as for the inversion and
     its condition number): eigval[P][N], eigvec[P][P][N] with column r the
     eigenvector of eigenvalue r, signed so that its largest-magnitude
-    component is positive."""
+    component is positive.  A parameter outside the event's set (par_mask)
+    is represented by a unit row and column (eigenvalue 1, eigenvector e_i)."""
     P, _, N = fisher.shape
     val = np.zeros((P, N))
     vec = np.zeros((P, P, N))
     for e in range(N):
         with mp.workdps(dps):
-            G = mp.matrix([[mp.mpf(float(fisher[i, j, e])) for j in range(P)] for i in range(P)])
+            def entry(i, j):
+                if _in_set(par_mask, e, i) and _in_set(par_mask, e, j):
+                    return mp.mpf(float(fisher[i, j, e]))
+                return mp.mpf(1) if i == j else mp.mpf(0)
+            G = mp.matrix([[entry(i, j) for j in range(P)] for i in range(P)])
             normalise = all(G[i, i] > 0 for i in range(P))
             dn = [mp.sqrt(G[i, i]) if normalise else mp.mpf(1) for i in range(P)]
             for i in range(P):
@@ -123,7 +137,7 @@ def eigen(fisher: np.ndarray, dps: int = 50):
 
 
 def covariance(fisher: np.ndarray, cond_max: float = 1e50, dps: int = 50, idx=None, method: str = "cho",
-               truncate: bool = False, svals_thresh: float = 1e-15):
+               truncate: bool = False, svals_thresh: float = 1e-15, par_mask=None):
     """Invert fisher[P][P][N] (events last).  Returns a dict with cov[P][P][n],
     sigma[P][n], cond[n], inv_err[n] and status[n] for the selected events
     (all events, or those in idx).  inv_err is eps evaluated exactly on the
@@ -131,7 +145,8 @@ def covariance(fisher: np.ndarray, cond_max: float = 1e50, dps: int = 50, idx=No
     (failed Cholesky flagged), "cho_svd" (the paper's default: an SVD where
     the Cholesky fails, status ST_SVD), "svd" (with ``truncate``: singular
     values below svals_thresh * max raised to it) or "svd_reg" (those left
-    out)."""
+    out).  par_mask [N] (or None): each event's parameter set; only that
+    block is inverted."""
     P, _, N = fisher.shape
     idx = np.arange(N) if idx is None else np.asarray(idx)
     n = len(idx)
@@ -141,20 +156,25 @@ def covariance(fisher: np.ndarray, cond_max: float = 1e50, dps: int = 50, idx=No
     inv_err = np.full(n, np.nan)
     status = np.zeros(n, dtype=np.int32)
     for k, e in enumerate(idx):
-        F = np.array(fisher[:, :, e], dtype=np.float64)
+        sel = [i for i in range(P) if _in_set(par_mask, e, i)]
+        if not sel:                      # an empty parameter set: nothing to invert
+            cov[:, :, k], cond[k], inv_err[k] = 0.0, 1.0, 0.0
+            continue
+        F = np.array(fisher[np.ix_(sel, sel, [e])][:, :, 0], dtype=np.float64)
         C, c, st = _one(F, cond_max, dps, method, truncate, svals_thresh)
         cond[k] = c
         status[k] = st
         if C is None:
             continue
-        cov[:, :, k] = C
-        sigma[:, k] = np.sqrt(np.diag(C))
+        cov[:, :, k] = 0.0
+        cov[np.ix_(sel, sel, [k])] = C[:, :, None]
+        sigma[sel, k] = np.sqrt(np.diag(C))
         with mp.workdps(dps):
             Fm = mp.matrix(F.tolist())
             Cm = mp.matrix(C.tolist())
             R = Fm * Cm
             inv_err[k] = float(max(abs(R[i, j] - (1 if i == j else 0))
-                                   for i in range(P) for j in range(P)))
+                                   for i in range(len(sel)) for j in range(len(sel))))
     return {"cov": cov, "sigma": sigma, "cond": cond, "inv_err": inv_err, "status": status}
 
 
@@ -219,24 +239,32 @@ def sky_area(cov: np.ndarray, theta: np.ndarray, i_theta: int, i_phi: int, perc_
 def covariance_epilogue(fisher: np.ndarray, fixed=(), prior=None, marg=(), theta=None,
                         i_theta: int = 3, i_phi: int = 4, perc_level: float = 90.0, units: str = "SqDeg",
                         cond_max: float = 1e50, dps: int = 50, method: str = "cho", truncate: bool = False,
-                        svals_thresh: float = 1e-15):
+                        svals_thresh: float = 1e-15, par_mask=None):
     """The manipulations in order: fix -> prior -> invert -> sky area ->
     marginalise.  ``prior`` maps parameter index (of the full P) -> inverse
     prior variance.  ``i_theta``/``i_phi`` are indices of the full P; both must
     be kept for the sky area.  Returns the dictionary of ``covariance`` for
     the inverted matrix, plus ``cov_out``/``sigma_out`` after
     marginalisation, ``keep``/``out`` (original indices), ``sky`` and
-    ``fisher_inverted`` (the matrix that was inverted)."""
+    ``fisher_inverted`` (the matrix that was inverted).  par_mask [N] (bit i:
+    parameter i of the full P, or None): each event's parameter set; the
+    sky area is NaN for an event without theta or phi."""
     F, keep = fix_params(np.asarray(fisher, dtype=np.float64), fixed)
     pos = {int(k): i for i, k in enumerate(keep)}
     if prior:
         F = add_prior(F, list(prior.values()), [pos[int(i)] for i in prior.keys()])
+    kmask = None
+    if par_mask is not None:
+        kmask = np.array([sum(((int(m) >> int(kk)) & 1) << i for i, kk in enumerate(keep)) for m in par_mask])
     res = covariance(F, cond_max=cond_max, dps=dps, method=method, truncate=truncate,
-                     svals_thresh=svals_thresh)
+                     svals_thresh=svals_thresh, par_mask=kmask)
     res["fisher_inverted"] = F
     res["keep"] = keep
     if theta is not None:
         res["sky"] = sky_area(res["cov"], np.asarray(theta), pos[i_theta], pos[i_phi], perc_level, units)
+        if kmask is not None:
+            has = (((kmask >> pos[i_theta]) & 1) & ((kmask >> pos[i_phi]) & 1)).astype(bool)
+            res["sky"][~has] = np.nan
     over = [pos[int(m)] for m in marg]
     cov_out, kept_pos = marginalise(res["cov"], over)
     res["cov_out"] = cov_out

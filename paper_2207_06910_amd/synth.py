@@ -92,6 +92,7 @@ class Workload:
     tc_s: np.ndarray | None = None
     meta: dict = field(default_factory=dict)
     active: np.ndarray | None = None   # uint8 [n_ifo][N] or None: interferometers on (duty factor)
+    par_mask: np.ndarray | None = None  # uint32 [N] or None: each event's Fisher rows (bit r: row r)
 
     @property
     def n(self) -> int:
@@ -107,8 +108,11 @@ class Workload:
                         list(self.sites), self.fmin[idx].copy(), self.npts[idx].copy(),
                         None if self.fmax is None else self.fmax[idx].copy(),
                         self.flags, self.npar,
-                        None if self.tc_s is None else self.tc_s[idx].copy(), dict(self.meta),
-                        None if self.active is None else np.ascontiguousarray(self.active[:, idx]))
+                        None if self.tc_s is None else self.tc_s[idx].copy(),
+                        {k: (v[idx] if isinstance(v, np.ndarray) and v.shape[:1] == (self.n,) else v)
+                         for k, v in self.meta.items()},
+                        None if self.active is None else np.ascontiguousarray(self.active[:, idx]),
+                        None if self.par_mask is None else self.par_mask[idx].copy())
 
     def with_duty_factor(self, duty, seed: int) -> "Workload":
         """A copy whose interferometers are each on for an event with
@@ -122,6 +126,16 @@ class Workload:
         rng = np.random.default_rng(seed)
         u = rng.random((len(fac), self.n))
         w.active = (u < fac[:, None]).astype(np.uint8)
+        return w
+
+    def with_par_masks(self) -> "Workload":
+        """A copy in which each event's Fisher matrix has the parameters of
+        its kind (meta["kind"]): black-hole pairs without deformabilities (11
+        rows), neutron-star pairs with both (13), NS-BH pairs with the
+        neutron star's Lambda2 only (12; m1 >= m2, so body 2 is the star)."""
+        w = self.subset(np.arange(self.n))
+        w.name = self.name + "[par masks]"
+        w.par_mask = population_masks(self.meta["kind"], self.npar)
         return w
 
     def with_npts(self, n: int) -> "Workload":
@@ -246,6 +260,19 @@ def _population(rng, n, fractions, bbh_mc):
     par[11] = np.where(kind == 1, lam[0], 0.0)
     par[12] = np.where(kind == 0, 0.0, lam[1])
     return par, kind, m1 + m2
+
+
+MASK_BBH = (1 << 11) - 1                  # rows Mc ... chi2z
+MASK_BNS = (1 << 13) - 1                  # and Lambda1, Lambda2
+MASK_NSBH = MASK_BBH | (1 << 12)          # and Lambda2 only
+
+
+def population_masks(kind, npar: int = 13) -> np.ndarray:
+    """uint32 [N] Fisher-row sets of a population's kinds (0 BBH, 1 BNS,
+    2 NSBH), restricted to npar rows."""
+    kind = np.asarray(kind)
+    m = np.select([kind == 0, kind == 1, kind == 2], [MASK_BBH, MASK_BNS, MASK_NSBH], MASK_BNS)
+    return (m & ((1 << npar) - 1)).astype(np.uint32)
 
 
 def _grid_lengths(mtot, nmin, nmax, m_lo, m_hi):

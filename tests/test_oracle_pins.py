@@ -793,3 +793,68 @@ def test_duty_factor_mask_in_the_oracle(orc):
     frac = d.active.mean(axis=1)
     np.testing.assert_allclose(frac, [0.8, 0.8, 0.8, 0.5, 0.3], atol=0.03)
     assert np.array_equal(d.active, big.with_duty_factor([0.8, 0.5, 0.3], seed=11).active)
+
+
+# ------------------------------------------------------------ per-event parameter sets
+def test_parameter_sets_reduce_to_the_untidal_fisher(orc):
+    """Black-hole pairs (Lambda1 = Lambda2 = 0) in a tidal run with their
+    11-row sets: rows 11 and 12 are zero and the kept block equals the Fisher
+    matrix of the same events computed without the tidal terms (the tidal
+    phase and its eta-derivative vanish at zero deformability).  NS-BH pairs
+    lose only the black hole's Lambda1 row; neutron-star pairs keep every
+    row of the full matrix."""
+    import dataclasses
+    full = synth.catalog1e6(n=400)
+    kind = full.meta["kind"]
+    idx = np.r_[[np.flatnonzero(kind == k)[:2] for k in range(3)]].ravel()
+    wl0 = full.subset(idx).with_npts(400)
+    wl = wl0.with_par_masks()
+    assert list(wl.par_mask) == [2047, 2047, 8191, 8191, 6143, 6143]
+    F0 = orc.fisher(wl0)["fisher"]
+    F = orc.fisher(wl)["fisher"]
+    wn = dataclasses.replace(wl0, flags=wl0.flags & ~synth.FLAG_TIDAL, npar=11)
+    Fn = orc.fisher(wn)["fisher"]
+    bbh = slice(0, 2)
+    d = np.sqrt(np.einsum("iie->ie", Fn[:, :, bbh]))
+    err = np.abs(F[:11, :11, bbh] - Fn[:, :, bbh]) / (d[:, None] * d[None, :])
+    assert err.max() < 1e-13, err.max()
+    assert np.all(F[11:, :, bbh] == 0) and np.all(F[:, 11:, bbh] == 0)
+    assert np.array_equal(F[:, :, 2:4], F0[:, :, 2:4])
+    keep = [i for i in range(13) if i != 11]
+    assert np.all(F[11, :, 4:] == 0) and np.all(F[:, 11, 4:] == 0)
+    assert np.array_equal(F[np.ix_(keep, keep, [4, 5])], F0[np.ix_(keep, keep, [4, 5])])
+
+
+def test_parameter_sets_invert_the_block(orc):
+    """With uncoupled parameters outside the set (a block-diagonal matrix,
+    whose inverse is block-diagonal with each block's inverse), inverting
+    with the set equals inverting the whole matrix on the kept block; the
+    other parameters get zero covariance rows and NaN sigmas.  The sky area
+    is NaN for an event whose set lacks phi.  The eigenvalues are those of
+    the normalised kept block (numpy) and one unit eigenvalue per left-out
+    parameter."""
+    rng = np.random.default_rng(5)
+    P, n, k = 13, 4, 11
+    F = np.zeros((P, P, n))
+    for e in range(n):
+        A = rng.normal(size=(k, k))
+        B = rng.normal(size=(P - k, P - k))
+        F[:k, :k, e] = (A @ A.T + k * np.eye(k)) * 10.0 ** rng.uniform(-3, 3)
+        F[k:, k:, e] = B @ B.T + np.eye(P - k)
+    mask = np.full(n, (1 << k) - 1, dtype=np.uint32)
+    a = orc.covariance(F, par_mask=mask)
+    b = orc.covariance(F)
+    np.testing.assert_allclose(a["cov"][:k, :k], b["cov"][:k, :k], rtol=1e-15, atol=0)
+    np.testing.assert_allclose(a["sigma"][:k], b["sigma"][:k], rtol=1e-15)
+    assert np.all(a["cov"][k:] == 0) and np.all(a["cov"][:, k:] == 0) and np.all(np.isnan(a["sigma"][k:]))
+    m2 = mask.copy()
+    m2[0] &= ~np.uint32(1 << 4)
+    theta = np.full(n, 1.0)
+    r = orc.covariance_epilogue(F, theta=theta, par_mask=m2)
+    assert np.isnan(r["sky"][0]) and np.all(np.isfinite(r["sky"][1:]))
+    val, vec = orc.eigen(F, par_mask=mask)
+    for e in range(n):
+        A = F[:k, :k, e]
+        dn = np.sqrt(np.diag(A))
+        want = np.sort(np.r_[np.linalg.eigvalsh(A / np.outer(dn, dn)), np.ones(P - k)])
+        np.testing.assert_allclose(val[:, e], want, rtol=1e-12)

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define GWF_VERSION 3
+#define GWF_VERSION 4
 
 /* ------------------------------------------------------------- statuses */
 typedef int32_t gwf_status;
@@ -123,6 +123,16 @@ typedef struct gwf_events {
                           (sec. 3.1), the random draws being the caller's; its
                           per-interferometer SNR is then 0.  The strain
                           (gwf_waveform) is not affected.                      */
+  const uint32_t* par_mask; /* device [n] or NULL (every row): the parameters of
+                          event e's Fisher matrix, bit r for row r (GWF_MC ...
+                          order; bits at or beyond the call's P are ignored),
+                          so that one launch serves a mixed population (black
+                          holes without their deformabilities).  A row outside
+                          the set is left out: its row and column of the Fisher
+                          output are 0, the inversions of a plan invert the rest
+                          (its covariance row and column 0, its sigma NaN), and
+                          the adjoint ignores gbar there.  SNR and strain are
+                          not affected.                                       */
 } gwf_events;
 
 /* ------------------------------------------------------------ detectors */
@@ -262,7 +272,10 @@ gwf_status gwf_fisher_adjoint(const gwf_events* ev, const gwf_network* net, cons
  *   cond_max matrices with cond > cond_max are not inverted (GWF_EV_ILL_COND);
  *            the paper's default is 1e50.
  * Events with GWF_EV_INVALID_PARAM or GWF_EV_SKIPPED_SNR already set are
- * skipped.  Failed or skipped events get NaN cov/sigma/inv_err/logdet. */
+ * skipped.  Failed or skipped events get NaN cov/sigma/inv_err/logdet.
+ * Every matrix is inverted whole; per-event parameter sets (gwf_events
+ * par_mask) are honoured by gwf_covariance (gwf_cov_opts par_mask) and by
+ * the inversion of a plan. */
 gwf_status gwf_invert(int32_t P, int64_t n, const double* fisher, double cond_max,
                       double* cov, double* sigma, double* cond, double* inv_err,
                       double* logdet, int32_t* status, void* stream);
@@ -316,6 +329,16 @@ typedef struct gwf_cov_opts {
   int32_t pad;
   double svals_thresh;              /* ratio to the largest singular value; the
                                        paper's default is 1e-15                  */
+  const uint32_t* par_mask;         /* device [n] or NULL: each event's parameter
+                                       set, bit i for parameter i of the stored
+                                       matrix (gwf_events par_mask); a parameter
+                                       outside it is left out of steps 2-4 (a unit
+                                       row and column stand in for it, so cond,
+                                       inv_err and logdet are those of the rest),
+                                       and its row and column of cov are 0, its
+                                       sigma NaN; the sky area is NaN for an event
+                                       without theta or phi; its eigenvalue is 1
+                                       with eigenvector e_i                      */
 } gwf_cov_opts;
 
 /* P, n, fisher, status: as for gwf_invert (fisher is [P][P][n]).  With Po the

@@ -8,8 +8,10 @@ parameter rows A, all of them by default) inverts with a condition number
 below cond_max (default 1e13).  The gradient of ln det Gamma is
 tr(Gamma^-1 dGamma), a sum whose terms cancel by up to the condition number;
 in FP64 it keeps about 1e-16 kappa relative accuracy per event, so events
-with larger kappa would add noise rather than signal.  The forward pass runs
-gwf_fisher and gwf_invert (which returns ln det Gamma and Gamma^-1); the
+with larger kappa would add noise rather than signal.  An event's own
+parameter set (the workload's par_mask) further restricts A for that event.
+The forward pass runs gwf_fisher and gwf_covariance (which returns
+ln det Gamma and Gamma^-1); the
 backward pass runs the hand-written adjoint gwf_fisher_adjoint with
 Gbar = Gamma^-1 embedded in the full matrix, recomputing the strain
 derivatives at every grid point instead of storing them.  Every per-point
@@ -44,10 +46,11 @@ def _forward(dw, xi, w_snr, w_logdet, rows, cond_max):
     dwx = dw.with_sites(_sites_at(dw.sites, xi))
     r = binding.fisher(dwx)
     F = r["fisher"]
-    if rows is not None:
-        idx = torch.as_tensor(rows, dtype=torch.long, device=F.device)
-        F = F.index_select(0, idx).index_select(1, idx).contiguous()
-    inv = binding.invert(F, r["status"], cond_max=cond_max)
+    P = F.shape[0]
+    # restriction to the rows A by fixing the others; each event's own
+    # parameter set (par_mask) is honoured by the inversion
+    fixed = () if rows is None else [i for i in range(P) if i not in set(int(k) for k in rows)]
+    inv = binding.covariance(F, r["status"], fixed=fixed, cond_max=cond_max, par_mask=dwx.par_mask)
     ok = inv["status"] == 0
     J = (w_snr * torch.log(r["snr"][ok]).sum() + w_logdet * inv["logdet"][ok].sum()).to(torch.float64)
     return dwx, r, inv, ok, J
@@ -62,9 +65,9 @@ class NetworkFoM(__import__("torch").autograd.Function):
         dwx, r, inv, ok, J = _forward(dw, xi, w_snr, w_logdet, rows, cond_max)
         P = r["fisher"].shape[0]
         gbar = inv["cov"]
-        if rows is not None:
+        if len(inv["out"]) != P:
             full = torch.zeros((P, P, dw.n), dtype=torch.float64, device=gbar.device)
-            idx = torch.as_tensor(rows, dtype=torch.long, device=gbar.device)
+            idx = torch.as_tensor(list(inv["out"]), dtype=torch.long, device=gbar.device)
             full[idx.view(-1, 1), idx.view(1, -1)] = gbar
             gbar = full
         ctx.dwx, ctx.gbar, ctx.status = dwx, gbar, inv["status"]

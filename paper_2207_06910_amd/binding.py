@@ -23,7 +23,7 @@ NPAR_MAX = 13
 
 class Events(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("ld", ctypes.c_int64), ("par", ctypes.c_void_p),
-                ("tc_s", ctypes.c_void_p), ("active", ctypes.c_void_p)]
+                ("tc_s", ctypes.c_void_p), ("active", ctypes.c_void_p), ("par_mask", ctypes.c_void_p)]
 
 
 class SiteDesc(ctypes.Structure):
@@ -61,7 +61,7 @@ class CovOptions(ctypes.Structure):
                 ("prior", ctypes.c_double * 13), ("cond_max", ctypes.c_double),
                 ("sky_level", ctypes.c_double), ("i_theta", ctypes.c_int32), ("i_phi", ctypes.c_int32),
                 ("sky_units", ctypes.c_int32), ("method", ctypes.c_int32), ("truncate", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("svals_thresh", ctypes.c_double)]
+                ("pad", ctypes.c_int32), ("svals_thresh", ctypes.c_double), ("par_mask", ctypes.c_void_p)]
 
 
 SKY_STERAD, SKY_SQDEG = 0, 1
@@ -182,6 +182,9 @@ class DeviceWorkload:
         act = getattr(wl, "active", None)
         self.active = None if act is None else torch.as_tensor(
             np.ascontiguousarray(act, dtype=np.uint8), device=device)
+        pm = getattr(wl, "par_mask", None)
+        self.par_mask = None if pm is None else torch.as_tensor(
+            np.ascontiguousarray(pm, dtype=np.uint32).view(np.int32), device=device)
         self.n_ifo = n_ifo(self.sites)
 
     def with_sites(self, sites) -> "DeviceWorkload":
@@ -196,7 +199,8 @@ class DeviceWorkload:
     def descriptors(self):
         ev = Events(self.n, self.par.shape[1], self.par.data_ptr(),
                     None if self.tc_s is None else self.tc_s.data_ptr(),
-                    None if self.active is None else self.active.data_ptr())
+                    None if self.active is None else self.active.data_ptr(),
+                    None if self.par_mask is None else self.par_mask.data_ptr())
         net, keep = network(self.sites)
         grid = Grid(0, self.fmin.data_ptr(), None if self.fmax is None else self.fmax.data_ptr(),
                     self.npts.data_ptr())
@@ -269,9 +273,16 @@ def waveform(dw: DeviceWorkload, offsets=None, total=None, mixed=False, stream=N
     return res
 
 
-def invert(F, status=None, cond_max=1e50, want_cov=True, stream=None, out=None):
-    """Covariances of Fisher matrices F [P][P][N] (float64, on the device)."""
+def invert(F, status=None, cond_max=1e50, want_cov=True, par_mask=None, stream=None, out=None):
+    """Covariances of Fisher matrices F [P][P][N] (float64, on the device).
+    With ``par_mask`` (per-event parameter sets, see covariance) the call
+    goes through gwf_covariance with no other manipulation."""
     import torch
+    if par_mask is not None:
+        res = covariance(F, status, cond_max=cond_max, par_mask=par_mask, want_cov=want_cov,
+                         stream=stream, out=out)
+        res.pop("out", None)
+        return res
     _dev_f64(F)
     P, P2, n = F.shape
     if P != P2:
@@ -294,7 +305,7 @@ def invert(F, status=None, cond_max=1e50, want_cov=True, stream=None, out=None):
 
 def covariance(F, status=None, fixed=(), prior=None, marg=(), theta=None, sky_level=90.0, units="SqDeg",
                i_theta=3, i_phi=4, cond_max=1e50, method="cho", truncate=False, svals_thresh=1e-15,
-               eigen=False, want_cov=True, stream=None, out=None):
+               eigen=False, par_mask=None, want_cov=True, stream=None, out=None):
     """Covariances of Fisher matrices F [P][P][N] after the manipulations of
     gwf_covariance: parameters in ``fixed`` held at their fiducial values,
     ``prior`` {index: inverse variance} added before inversion, parameters in
@@ -304,7 +315,10 @@ def covariance(F, status=None, fixed=(), prior=None, marg=(), theta=None, sky_le
     logdet, status, sky (if requested) and ``out``, the indices of F's rows
     in cov and sigma.  ``method``: "cho", "cho_svd", "svd" (with
     ``truncate``), "svd_reg" or "cho_dd" (double-double Cholesky); ``eigen``: also eigval [Pk][N] and eigvec
-    [Pk][Pk][N] of the normalised matrix that is inverted."""
+    [Pk][Pk][N] of the normalised matrix that is inverted; ``par_mask``: a
+    device int32 tensor [N] of per-event parameter sets (bit i: row i of F),
+    e.g. a DeviceWorkload's ``par_mask``: rows outside an event's set get
+    zero covariance rows and columns and a NaN sigma."""
     import torch
     _dev_f64(F)
     P, P2, n = F.shape
@@ -322,6 +336,11 @@ def covariance(F, status=None, fixed=(), prior=None, marg=(), theta=None, sky_le
     o.method = INV_METHODS[method]
     o.truncate = int(bool(truncate))
     o.svals_thresh = float(svals_thresh)
+    if par_mask is not None:
+        if not (par_mask.is_cuda and par_mask.dtype in (torch.int32, torch.uint32)
+                and par_mask.is_contiguous() and par_mask.shape == (n,)):
+            raise GwfError("par_mask must be a contiguous int32 tensor [N] on the device")
+        o.par_mask = par_mask.data_ptr()
     out_idx = [i for i in range(P) if not (o.fixed_mask >> i & 1) and not (o.marg_mask >> i & 1)]
     po = len(out_idx)
     dev = F.device

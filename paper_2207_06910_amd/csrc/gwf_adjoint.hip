@@ -60,9 +60,11 @@ __global__ __launch_bounds__(kABlock, 2) void adjoint_kernel(AdjointArgs a) {
     ok = ec.status == 0 && (a.status == nullptr || a.status[e] == 0);
   }
   __syncthreads();
+  const uint32_t pm = event_rows(a.par_mask, e);
   for (int t = tid; t < P * P; t += kABlock) {
     const int i = t / P, j = t - i * P;
-    const double g = 0.5 * (a.gbar[(int64_t)(i * P + j) * a.n + e] + a.gbar[(int64_t)(j * P + i) * a.n + e]);
+    const double g = rows_in(pm, i, j)
+        ? 0.5 * (a.gbar[(int64_t)(i * P + j) * a.n + e] + a.gbar[(int64_t)(j * P + i) * a.n + e]) : 0.0;
     Gb[t] = g;
     if (!finite(g)) ok = 0;          // every writer stores the same value
   }

@@ -127,6 +127,7 @@ gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_gr
   a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
   a.snr_th = snr_th;
   a.active = ev->active;
+  a.par_mask = ev->par_mask;
   a.fisher = fisher; a.snr = snr; a.status = status;
   const bool rot = (flags & GWF_EARTH_ROT) != 0, tidal = (flags & GWF_TIDAL) != 0;
   hipStream_t s = (hipStream_t)stream;
@@ -179,6 +180,7 @@ gwf_status gwf_fisher_adjoint(const gwf_events* ev, const gwf_network* net, cons
   a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
   a.gbar = gbar; a.status = status; a.w_snr = w_snr; a.w_fisher = w_fisher;
   a.active = ev->active;
+  a.par_mask = ev->par_mask;
   a.grad_event = grad_event; a.grad = grad;
   hipError_t err = gwf::launch_adjoint(a, (flags & GWF_TIDAL) != 0, (flags & GWF_EARTH_ROT) != 0,
                                        (hipStream_t)stream);
@@ -243,6 +245,7 @@ gwf_status gwf_covariance(int32_t P, int64_t n, const double* fisher, const gwf_
   a.svals_thresh = (o.method == GWF_INV_SVD || o.method == GWF_INV_SVD_REG) ? o.svals_thresh : 0.0;
   a.eigval = eigval;
   a.eigvec = eigvec;
+  a.par_mask = o.par_mask;
   a.n = n; a.fisher = fisher; a.cond_max = o.cond_max; a.cov = cov; a.sigma = sigma;
   a.cond = cond; a.inv_err = inv_err; a.logdet = logdet; a.status = status;
   a.p_full = P;

@@ -99,9 +99,10 @@ __global__ void combine_kernel(CombineArgs a) {
     for (int32_t i = a.item_first[e]; i < a.item_first[e + 1]; ++i) s += a.partial[(int64_t)i * NACC + slot];
   int r, c;
   slot_position(slot, NPI, r, c);
+  if (r == 8 && c == 8) a.snr[e] = sqrt(s);
+  if (!rows_in(event_rows(a.par_mask, e), r, c)) s = 0.0;   // not one of the event's rows
   a.fisher[((int64_t)r * P + c) * a.n + e] = s;
   a.fisher[((int64_t)c * P + r) * a.n + e] = s;
-  if (r == 8 && c == 8) a.snr[e] = sqrt(s);
   // the set-up kernel wrote the parameter status; a non-finite sum adds its bit
   if (!st0 && !finite(s)) atomicOr(a.status + e, (int32_t)kEvNonFinite);
 }

@@ -43,6 +43,7 @@ struct CombineArgs {
   double* fisher;             // [P][P][n]
   double* snr;                // [n]
   int32_t* status;            // [n]
+  const uint32_t* par_mask;   // [n] or NULL: rows of each event's Fisher matrix (others 0)
 };
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);

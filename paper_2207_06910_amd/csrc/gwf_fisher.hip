@@ -68,12 +68,13 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(Fis
   double t = 0.0;
   fisher_sums<TIDAL, ROT, false, false>(ec, sc, n_site, 0, ec.n, L, &t);
   if (tid < NACC) {
-    if (!isfinite(t)) atomicOr(&bad, 1);
     int r, c;
     slot_position(tid, NPI, r, c);
     if (r == 8 && c == 8) a.snr[e] = sqrt(t);     // Gamma_{Phic,Phic} = SNR^2
-    a.fisher[((int64_t)r * P + c) * a.n + e] = t;
-    a.fisher[((int64_t)c * P + r) * a.n + e] = t;
+    const double v = rows_in(event_rows(a.par_mask, e), r, c) ? t : 0.0;
+    if (!isfinite(v)) atomicOr(&bad, 1);
+    a.fisher[((int64_t)r * P + c) * a.n + e] = v;
+    a.fisher[((int64_t)c * P + r) * a.n + e] = v;
   }
   __syncthreads();
   if (tid == 0) a.status[e] = bad ? kEvNonFinite : 0;

@@ -52,30 +52,47 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
   return x * q + (x < r ? x : r) + t;
 }
 
-// Row j of the matrix that is inverted: the stored row of kept parameter j
-// restricted to the kept columns, with the prior added on the diagonal.
+// Kept parameters that are in event e's parameter set (bit i: kept i).
 template <int P>
-__device__ inline void load_row(const InvertArgs& a, int64_t e, int j, double* row) {
-  const int64_t rj = a.keep[j];
+__device__ inline uint32_t kept_rows(const InvertArgs& a, int64_t e) {
+  if (!a.par_mask) return (1u << P) - 1u;
+  const uint32_t m = a.par_mask[e];
+  uint32_t k = 0;
 #pragma unroll
-  for (int k = 0; k < P; ++k) row[k] = a.fisher[(rj * a.p_full + a.keep[k]) * a.n + e];
-  row[j] += a.prior[j];
+  for (int i = 0; i < P; ++i) k |= ((m >> a.keep[i]) & 1u) << i;
+  return k;
+}
+
+// Entry (r, c) of the matrix that is inverted: the stored entry of kept
+// parameters r and c with the prior added on the diagonal; a parameter
+// outside the event's set (its bit clear in am) stands in as a unit row and
+// column, which leaves the inverse of the rest unchanged.
+__device__ inline double gamma_rc(const InvertArgs& a, int64_t e, uint32_t am, int r, int c) {
+  if (!rows_in(am, r, c)) return r == c ? 1.0 : 0.0;
+  double v = a.fisher[((int64_t)a.keep[r] * a.p_full + a.keep[c]) * a.n + e];
+  if (r == c) v += a.prior[r];
+  return v;
+}
+
+// Row j of the matrix that is inverted.
+template <int P>
+__device__ inline void load_row(const InvertArgs& a, int64_t e, uint32_t am, int j, double* row) {
+#pragma unroll
+  for (int k = 0; k < P; ++k) row[k] = gamma_rc(a, e, am, j, k);
 }
 
 // Column j of the normalised matrix (the kept upper triangle with the prior
 // on the diagonal, divided by d_i d_j), the same bits as the values the
 // kernel starts from; zeros where valid is false.
 template <int P>
-__device__ inline void load_col(const InvertArgs& a, int64_t e, int j, bool valid, const double* d,
-                                double dj, double* h) {
+__device__ inline void load_col(const InvertArgs& a, int64_t e, uint32_t am, int j, bool valid,
+                                const double* d, double dj, double* h) {
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     double v = 0.0;
     if (valid) {
       const int r = i <= j ? i : j, c = i <= j ? j : i;
-      v = a.fisher[((int64_t)a.keep[r] * a.p_full + a.keep[c]) * a.n + e];
-      if (i == j) v += a.prior[j];
-      v = v / (d[i] * dj);
+      v = gamma_rc(a, e, am, r, c) / (d[i] * dj);
     }
     h[i] = v;
   }
@@ -106,9 +123,10 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
 
   int32_t st = live ? a.status[e] : kEvSkipped;
   const bool use = live && !(st & (kEvInvalid | kEvSkipped));
+  const uint32_t am = live ? kept_rows<P>(a, e) : 0u;
 
   // ---- Gamma (kept rows and columns, prior on the diagonal), row j per lane, into LDS
-  if (use && j < P) load_row<P>(a, e, j, Gs[g][j]);
+  if (use && j < P) load_row<P>(a, e, am, j, Gs[g][j]);
   __syncthreads();
 
   // column j of the upper triangle (h_i = Gamma_{min(i,j), max(i,j)}) and the diagonal
@@ -253,12 +271,11 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
     double dn[P], dnj = 1.0;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      const int64_t ki = a.keep[i];
-      dn[i] = (go0 && normalise) ? sqrt(a.fisher[(ki * a.p_full + ki) * a.n + e] + a.prior[i]) : 1.0;
+      dn[i] = (go0 && normalise) ? sqrt(gamma_rc(a, e, am, i, i)) : 1.0;
       if (i == j) dnj = dn[i];
     }
     double xs[P], vs[P];
-    load_col<P>(a, e, j, go0 && j < P, dn, dnj, xs);
+    load_col<P>(a, e, am, j, go0 && j < P, dn, dnj, xs);
 #pragma unroll
     for (int i = 0; i < P; ++i) vs[i] = (i == j) ? 1.0 : 0.0;
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
@@ -375,10 +392,7 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       dn[i] = dd_from(1.0);
-      if (ddg && normalise) {
-        const int64_t ki = a.keep[i];
-        dn[i] = dd_sqrt(dd_from(a.fisher[(ki * a.p_full + ki) * a.n + e] + a.prior[i]));
-      }
+      if (ddg && normalise) dn[i] = dd_sqrt(dd_from(gamma_rc(a, e, am, i, i)));
       if (i == j) dnj = dn[i];
     }
     dd lq[P];
@@ -387,9 +401,7 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
       lq[i] = dd_from(0.0);
       if (ddg && j < P) {
         const int r = i <= j ? i : j, c = i <= j ? j : i;
-        double v = a.fisher[((int64_t)a.keep[r] * a.p_full + a.keep[c]) * a.n + e];
-        if (i == j) v += a.prior[j];
-        lq[i] = dd_div(dd_from(v), dd_mul(dn[i], dnj));
+        lq[i] = dd_div(dd_from(gamma_rc(a, e, am, r, c)), dd_mul(dn[i], dnj));
       }
     }
     bool pdd = true;
@@ -469,7 +481,7 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
     ok = ddg && pdd;
   }
   // Gamma again (L2-resident) for the residual
-  if (a.inv_err && ok && j < P) load_row<P>(a, e, j, Gs[g][j]);
+  if (a.inv_err && ok && j < P) load_row<P>(a, e, am, j, Gs[g][j]);
   __syncthreads();
 
   // ---- outputs
@@ -497,23 +509,24 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
     else if (!pd && a.method == 1) st |= kEvSvd;
   }
   // column j of the covariance at its output position (marginalised
-  // parameters have none)
+  // parameters have none; parameters outside the event's set give zeros)
   const int oj = j < P ? a.out_pos[j] : -1;
   if (oj >= 0) {
     const int64_t no = a.n_out;
-    a.sigma[oj * a.n + e] = ok ? sqrt(Ls[g][j][j]) : nan;
+    const bool inj = (am >> j) & 1u;
+    a.sigma[oj * a.n + e] = (ok && inj) ? sqrt(Ls[g][j][j]) : nan;
     if (a.cov)
 #pragma unroll
       for (int k = 0; k < P; ++k) {
         const int ik = a.out_pos[k];
-        if (ik >= 0) a.cov[(ik * no + oj) * a.n + e] = ok ? cv[k] : nan;
+        if (ik >= 0) a.cov[(ik * no + oj) * a.n + e] = ok ? (rows_in(am, j, k) ? cv[k] : 0.0) : nan;
       }
   }
   if (j == 0) {
     if (a.sky) {
       // sky localisation region (sec. 4.1) from the theta-phi block
       double area = nan;
-      if (ok) {
+      if (ok && rows_in(am, a.i_theta, a.i_phi)) {
         const double ctt = Ls[g][a.i_theta][a.i_theta], cpp = Ls[g][a.i_phi][a.i_phi];
         const double ctp = Ls[g][a.i_phi][a.i_theta];
         const double det = fma(ctt, cpp, -(ctp * ctp));

@@ -12,6 +12,7 @@ struct FisherArgs {
   const double* fmax;       // NULL: cut frequency
   const int32_t* npts;
   const uint8_t* active;    // [n_ifo][ld] or NULL: interferometers taking part (duty factor)
+  const uint32_t* par_mask; // [n] or NULL: rows of each event's Fisher matrix (others 0)
   NetDesc net;
   double snr_th;
   const double* snr_pre;    // NULL, or SNRs of a previous pass for the threshold
@@ -63,6 +64,10 @@ struct InvertArgs {
   double svals_thresh;
   double* eigval;           // [P][n] or NULL: eigenvalues of the normalised kept matrix
   double* eigvec;           // [P][P][n] or NULL: its eigenvectors (columns)
+  // [n] or NULL: each event's parameter set, bit i for stored parameter i; a
+  // kept parameter outside it is replaced by a unit row and column, and its
+  // covariance row and column are written as 0, its sigma as NaN
+  const uint32_t* par_mask;
 };
 
 struct BasisArgs {
@@ -96,6 +101,7 @@ struct AdjointArgs {
   const double* fmax;       // NULL: cut frequency
   const int32_t* npts;
   const uint8_t* active;    // [n_ifo][ld] or NULL
+  const uint32_t* par_mask; // [n] or NULL: gbar entries outside an event's rows are ignored
   NetDesc net;
   const double* gbar;       // [P][P][n]
   const int32_t* status;    // [n] or NULL

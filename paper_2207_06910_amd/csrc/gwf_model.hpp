@@ -257,6 +257,13 @@ __host__ __device__ inline double cut_frequency_of(double M_s) {
 // x is neither infinite nor NaN (x - x is 0 exactly for finite x).
 __host__ __device__ inline bool finite(double x) { return (x - x) == 0.0; }
 
+// Rows of event e's Fisher matrix (bit r: row r; NULL: every row).
+__host__ __device__ inline uint32_t event_rows(const uint32_t* par_mask, int64_t e) {
+  return par_mask ? par_mask[e] : ~0u;
+}
+
+__host__ __device__ inline bool rows_in(uint32_t m, int r, int c) { return ((m >> r) & (m >> c) & 1u) != 0; }
+
 // Parameter validity; returns the status bits of an event.
 __host__ __device__ inline int32_t check_event(const double* p, bool tidal, double fmin, double fmax,
                                                int32_t n) {

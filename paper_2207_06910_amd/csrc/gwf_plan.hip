@@ -133,13 +133,13 @@ gwf_status enqueue(gwf_plan* p, const Outs& o, hipStream_t s) {
   if (err == hipSuccess) {
     CombineArgs ca{};
     ca.n = p->n; ca.evc = p->evc; ca.item_first = p->item_first; ca.partial = p->partial;
-    ca.fisher = o.fisher; ca.snr = o.snr; ca.status = o.status;
+    ca.fisher = o.fisher; ca.snr = o.snr; ca.status = o.status; ca.par_mask = p->ev.par_mask;
     err = launch_combine(ca, p->tidal, s);
   }
   if (err == hipSuccess && o.sigma) {
     InvertArgs ia{};
     ia.n = p->n; ia.fisher = o.fisher; ia.cond_max = o.cond_max; ia.cov = o.cov; ia.sigma = o.sigma;
-    ia.cond = o.cond; ia.inv_err = o.inv_err; ia.status = o.status;
+    ia.cond = o.cond; ia.inv_err = o.inv_err; ia.status = o.status; ia.par_mask = p->ev.par_mask;
     err = launch_invert(ia, p->P, s);
   }
   if (err != hipSuccess) return api_hip_fail(err, "batched launch");

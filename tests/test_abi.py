@@ -23,7 +23,7 @@ def test_library_exports_every_declared_symbol():
     assert {"gwf_snr", "gwf_fisher", "gwf_invert"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.gwf_version() == 3
+    assert lib.gwf_version() == 4
 
 
 def test_network_interferometer_count():

@@ -114,7 +114,7 @@ def gradient_form(binding, synth, torch, args, timed) -> dict:
     workload on five L sites, gradient along the 20 site parameters; each
     event's Fisher matrix has its kind's parameters (11 for BBH, 13 for BNS)."""
     from paper_2207_06910_amd import autodiff
-    wl = synth.mixed1e4().with_par_masks()
+    wl = synth.mixed1e4()
     dw = binding.DeviceWorkload(wl)
     xi = autodiff.site_parameters(dw)
 
@@ -139,7 +139,7 @@ def gradient_form(binding, synth, torch, args, timed) -> dict:
         tb.append(ev[0].elapsed_time(ev[1]))
     bwd = float(np.mean(tb))
     log(f"gradient (mixed1e4): {ms:.3f} ms per forward+backward, adjoint kernels {bwd:.3f} ms")
-    return {"gradient_mixed1e4": {"workload": "mixed1e4: 10^4 events (half BBH, half BNS), five L "
+    return {"gradient_mixed1e4": {"workload": "mixed1e4: 10^4 events (60% BBH, 40% BNS), five L "
                                               "sites, 11 (BBH) / 13 (BNS) parameters, d/d(lat, lon, gamma, ln S0)",
                                   "grid_points": int(wl.npts.sum()),
                                   "ms_per_forward_backward": round(ms, 4),
@@ -151,7 +151,7 @@ def catalogue_form(binding, synth, torch, args, timed, info) -> dict:
     """The batched FP64 form (same item length and workgroups per CU as on
     the BNS catalogue) on the 10^6-event BBH/BNS/NSBH catalogue, each
     event's Fisher matrix with its kind's parameters (11, 13 or 12)."""
-    wl = synth.catalog1e6().with_par_masks()
+    wl = synth.catalog1e6()
     dw = binding.DeviceWorkload(wl)
     plan = binding.Plan(dw, chunk=info["chunk"], wg_per_cu=info["wg_per_cu"])
     out = {}
@@ -163,8 +163,9 @@ def catalogue_form(binding, synth, torch, args, timed, info) -> dict:
     log(f"catalogue (catalog1e6): {ms:.3f} ms per step, {pinfo['n_items']} items, "
         f"inverted {int(np.sum(st == 0))}/{wl.n}")
     return {"batched_fp64_catalog1e6": {
-        "workload": "catalog1e6: 10^6 events (60% BBH, 35% BNS, 5% NSBH), three L sites, 11 / 13 / "
-                    "12 parameters by kind, 500-20000 points from 2 Hz",
+        "workload": "catalog1e6: 10^6 events (60% BBH, 35% BNS, 5% NSBH), the BNS catalogue's "
+                    "network (triangle + 2 L), 11 / 13 / 12 parameters by kind, 500-20000 points "
+                    "from 2 Hz",
         "grid_points": int(wl.npts.sum()), "ms_per_step": round(ms, 3),
         "events_per_s": round(wl.n / (ms * 1e-3), 1), "n_items": pinfo["n_items"],
         "inverted": int(np.sum(st == 0)), "ill_conditioned_or_not_pd": int(np.sum((st & 6) != 0))}}

@@ -283,36 +283,44 @@ def _grid_lengths(mtot, nmin, nmax, m_lo, m_hi):
     return (nmin + np.floor((nmax - nmin) * u)).astype(np.int32)
 
 
+# Grid lengths of the mixed populations: the heaviest system of the
+# catalogue (Mc = 60 Msun at eta = 0.1, f_cut = 18.41 Hz) gets 500 points and
+# the lightest neutron-star pair (2.2 Msun, f_cut = 1998.72 Hz) 20000.
+M_GRID_HI = 60.0 * 0.1 ** -0.6
+M_GRID_LO = 2.2
+
+
 def mixed1e4(n: int = 10000, seed: int = SEEDS["mixed1e4"]) -> Workload:
-    """10^4 events, half BBH (Mc 5-40 Msun, eta 0.1-0.25, spins up to 0.5)
-    and half BNS (as the BNS catalogue), on five L-shaped sites at seeded
-    positions and orientations with their own analytic PSDs; Earth rotation
-    and tidal terms on (13 parameters, Lambda = 0 for black holes); grids
+    """10^4 events, 60% BBH (Mc 5-40 Msun, eta 0.1-0.25, spins up to 0.5;
+    11 Fisher rows: no deformabilities) and 40% BNS (as the BNS catalogue,
+    13 rows), on five L-shaped sites at seeded positions and orientations
+    with their own analytic PSDs; Earth rotation and tidal terms on; grids
     from 2 Hz to the cut frequency with 500-20000 points set by the total
-    mass.  The detector-gradient workload."""
+    mass as in the 10^6-event catalogue.  The detector-gradient workload."""
     rng = np.random.default_rng(seed)
-    par, kind, mtot = _population(rng, n, (0.5, 0.5, 0.0), (5.0, 40.0))
+    par, kind, mtot = _population(rng, n, (0.6, 0.4, 0.0), (5.0, 40.0))
     sites = _random_sites(rng, [SHAPE_L] * 5)
-    npts = _grid_lengths(mtot, 500, 20000, 2.2, 100.0)
+    npts = _grid_lengths(mtot, 500, 20000, M_GRID_LO, M_GRID_HI)
     return Workload("mixed1e4", par, sites, np.full(n, 2.0), npts, None,
-                    FLAG_EARTH_ROT | FLAG_TIDAL, 13, meta={"kind": kind})
+                    FLAG_EARTH_ROT | FLAG_TIDAL, 13, meta={"kind": kind},
+                    par_mask=population_masks(kind))
 
 
 def catalog1e6(n: int = 1000000, seed: int = SEEDS["catalog1e6"]) -> Workload:
-    """10^6 events: 60% BBH (Mc 5-60 Msun), 35% BNS (m 1.1-2.2 Msun), 5%
-    NSBH (m1 5-20, m2 1.2-2 Msun), on three L-shaped detectors at the
-    Cosmic-Explorer and ET-like sites of Table 2 (CE1Id, CE2NM and the ET
-    Sardinia site, as L) with analytic PSDs; Earth rotation and tides on (13
-    parameters); grids from 2 Hz with 500-20000 points set by the total mass.
+    """10^6 events: 60% BBH (Mc 5-60 Msun; 11 Fisher rows), 35% BNS (m
+    1.1-2.2 Msun; 13 rows), 5% NSBH (m1 5-20, m2 1.2-2 Msun, Lambda1 = 0;
+    12 rows, the black hole's deformability left out) on the BNS catalogue's
+    network (the triangle and the two L sites of bns1e4), Earth rotation and
+    tides on; grids from 2 Hz with 500-20000 points,
+    n = 500 + floor(19500 u), u = ln(f_cut / 18.41 Hz) / ln(1998.72 / 18.41).
     The batched-catalogue workload (total points exceed 2^31)."""
     rng = np.random.default_rng(seed)
     par, kind, mtot = _population(rng, n, (0.60, 0.35, 0.05), (5.0, 60.0))
-    sites = [site("CE1Id", 1e-50, 150.0), site("CE2NM", 1e-50, 150.0), site("ETS", 3e-50, 200.0)]
-    sites[2] = Site(sites[2].lat, sites[2].lon, sites[2].gamma, 90.0 * DEG, SHAPE_L, sites[2].S0,
-                    sites[2].f0)
-    npts = _grid_lengths(mtot, 500, 20000, 2.2, 60.0)
+    sites = list(bns1e4().sites)
+    npts = _grid_lengths(mtot, 500, 20000, M_GRID_LO, M_GRID_HI)
     return Workload("catalog1e6", par, sites, np.full(n, 2.0), npts, None,
-                    FLAG_EARTH_ROT | FLAG_TIDAL, 13, meta={"kind": kind})
+                    FLAG_EARTH_ROT | FLAG_TIDAL, 13, meta={"kind": kind},
+                    par_mask=population_masks(kind))
 
 
 WORKLOADS = {"bbh100": bbh100, "bns1e4": bns1e4, "mixed1e4": mixed1e4, "catalog1e6": catalog1e6}

@@ -87,7 +87,7 @@ def test_adjoint_logdet_gradient_against_oracle(lib, orc):
     idx = np.r_[np.flatnonzero(kind == 0)[:2], np.flatnonzero(kind == 1)[:2]]
     wl = full.subset(idx)
     ref_f = orc.fisher(wl)
-    inv = orc.covariance(ref_f["fisher"], dps=50)
+    inv = orc.covariance(ref_f["fisher"], dps=50, par_mask=wl.par_mask)
     assert np.all(inv["status"] == 0)
     gbar = inv["cov"]
     ge, g = _adjoint(lib, wl, gbar)
@@ -152,7 +152,7 @@ def test_adjoint_full_workload_reproducible(lib):
     wl = synth.mixed1e4()
     dw = lib.DeviceWorkload(wl)
     r = lib.fisher(dw)
-    inv = lib.invert(r["fisher"], r["status"])
+    inv = lib.invert(r["fisher"], r["status"], par_mask=dw.par_mask)
     a = lib.fisher_adjoint(dw, inv["cov"], status=inv["status"])
     ga, gea = a["grad"].clone(), a["grad_event"].clone()
     b = lib.fisher_adjoint(dw, inv["cov"], status=inv["status"])
@@ -175,17 +175,18 @@ def test_logdet_gradient_end_to_end_against_oracle(lib, orc):
     full = synth.mixed1e4()
     kind = full.meta["kind"]
     cand = np.r_[np.flatnonzero(kind == 0)[:6], np.flatnonzero(kind == 1)[:6]]
-    k0 = orc.covariance(orc.fisher(full.subset(cand))["fisher"], dps=30)["cond"]
+    k0 = orc.covariance(orc.fisher(full.subset(cand))["fisher"], dps=30,
+                        par_mask=full.par_mask[cand])["cond"]
     idx = cand[k0 < 1e12][:6]
     assert len(idx) >= 3
     wl = full.subset(idx)
     dw = lib.DeviceWorkload(wl)
     r = lib.fisher(dw)
-    inv = lib.invert(r["fisher"], r["status"])
+    inv = lib.invert(r["fisher"], r["status"], par_mask=dw.par_mask)
     assert bool((inv["status"] == 0).all())
     ge = lib.fisher_adjoint(dw, inv["cov"], status=inv["status"])["grad_event"].cpu().numpy()
     ref_f = orc.fisher(wl)
-    oinv = orc.covariance(ref_f["fisher"], dps=50)
+    oinv = orc.covariance(ref_f["fisher"], dps=50, par_mask=wl.par_mask)
     ref, size = _reference(oinv["cov"], *_tangents(orc, wl), 1.0, 1.0)
     kappa = oinv["cond"][:, None, None]
     err = np.abs(ge - ref)

@@ -141,7 +141,8 @@ def test_mixed_waveform(lib, orc):
 
 def test_catalogue_1e6_plan(lib, orc):
     """The 10^6-event BBH/BNS/NSBH catalogue (more than 2^31 grid points in
-    total) in one persistent launch with inversion: every event's Fisher is
+    total; each kind with its own parameter set) in one persistent launch
+    with inversion: every event's Fisher is
     computed, the identity Gamma_dLdL dL^2 = SNR^2 holds for all of them,
     sampled events of each kind match the oracle, and ill-conditioned or
     non-positive-definite matrices are flagged, never silently inverted."""
@@ -157,11 +158,18 @@ def test_catalogue_1e6_plan(lib, orc):
     F_dl = out["fisher"][2, 2].cpu().numpy()
     np.testing.assert_allclose(F_dl * wl.par[2] ** 2, snr ** 2, rtol=1e-12)
     sig = out["sigma"].cpu().numpy()
-    assert np.all(np.isfinite(sig[:, st == 0])) and np.all(np.isnan(sig[:, st != 0]))
+    # each kind's own rows: 11 for BBH, 13 for BNS, 12 for NSBH
+    inn = ((wl.par_mask[None, :].astype(np.int64) >> np.arange(13)[:, None]) & 1).astype(bool)
+    assert np.array_equal(inn.sum(axis=0), np.choose(wl.meta["kind"], [11, 13, 12]))
+    assert np.all(np.isfinite(sig[:, st == 0][inn[:, st == 0]]))
+    assert np.all(np.isnan(sig[:, st == 0][~inn[:, st == 0]])) and np.all(np.isnan(sig[:, st != 0]))
     kind = wl.meta["kind"]
     idx = np.r_[[np.flatnonzero(kind == k)[0] for k in range(3)]]
     ref = orc.fisher(wl.subset(idx))
     F = out["fisher"][:, :, torch.as_tensor(idx, device="cuda")].cpu().numpy()
     np.testing.assert_allclose(snr[idx], ref["snr"], rtol=1e-12)
-    assert _ferr(F, ref["fisher"]) <= 1e-9
+    both = inn[:, None, idx] & inn[None, :, idx]
+    assert np.all(F[~both] == 0) and np.all(ref["fisher"][~both] == 0)
+    d = np.sqrt(np.where(inn[:, idx], np.einsum("iie->ie", ref["fisher"]), 1.0))
+    assert (np.abs(F - ref["fisher"]) / (d[:, None, :] * d[None, :, :])).max() <= 1e-9
     plan.close()

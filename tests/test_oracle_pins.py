@@ -808,6 +808,7 @@ def test_parameter_sets_reduce_to_the_untidal_fisher(orc):
     kind = full.meta["kind"]
     idx = np.r_[[np.flatnonzero(kind == k)[:2] for k in range(3)]].ravel()
     wl0 = full.subset(idx).with_npts(400)
+    wl0.par_mask = None
     wl = wl0.with_par_masks()
     assert list(wl.par_mask) == [2047, 2047, 8191, 8191, 6143, 6143]
     F0 = orc.fisher(wl0)["fisher"]

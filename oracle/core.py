@@ -47,6 +47,7 @@ def load():
                                    _I, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
         lib.orc_waveform.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_int, _D, _D, _D,
                                      _I, ctypes.c_int, ctypes.c_int, _L, ctypes.c_int64, _D]
+        lib.orc_waveform_deriv.argtypes = lib.orc_waveform.argtypes
         lib.orc_fisher_tangent.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_int, _D,
                                            _D, _D, _I, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int, ctypes.c_int, _D, _D]
@@ -248,6 +249,39 @@ def waveform(wl, offsets=None, total=None, nthreads=0):
                         npts.ctypes.data_as(_I), wl.flags, int(nthreads),
                         offsets.ctypes.data_as(_L), int(total), _p(h))
     return h[..., 0] + 1j * h[..., 1]
+
+
+def waveform_derivs(wl, offsets=None, total=None, nthreads=0):
+    """Derivatives of the strain with respect to the P parameters (the
+    Fisher matrix's rows, in its units), as complex dh[P][n_ifo][total] laid
+    out as waveform(); with wl.par_mask the rows outside an event's set are
+    0 there."""
+    par = _f64(wl.par)
+    n = par.shape[1]
+    s = _f64(wl.site_array())
+    ni = n_ifo(s)
+    P = 13 if wl.flags & FLAG_TIDAL else 11
+    npts = np.ascontiguousarray(wl.npts, dtype=np.int32)
+    if offsets is None:
+        offsets = np.concatenate([[0], np.cumsum(npts, dtype=np.int64)[:-1]])
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    if total is None:
+        total = int(np.max(offsets + npts))
+    fmin = _f64(wl.fmin)
+    fmax = None if wl.fmax is None else _f64(wl.fmax)
+    tc = None if wl.tc_s is None else _f64(wl.tc_s)
+    dh = np.zeros((P, ni, total, 2))
+    load().orc_waveform_deriv(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
+                              npts.ctypes.data_as(_I), wl.flags, int(nthreads),
+                              offsets.ctypes.data_as(_L), int(total), _p(dh))
+    out = dh[..., 0] + 1j * dh[..., 1]
+    pm = getattr(wl, "par_mask", None)
+    if pm is not None:
+        for e in range(n):
+            for r in range(P):
+                if not (int(pm[e]) >> r) & 1:
+                    out[r, :, offsets[e]:offsets[e] + npts[e]] = 0.0
+    return out
 
 
 def fisher_tangent(wl, site, which, nthreads=0):

@@ -505,6 +505,39 @@ void snr_event(const double* par, double tc_s, const std::vector<Ifo<double>>& i
 // =================================================================== C API
 using namespace orc;
 
+// Strain derivatives of n events with respect to their P parameters (the
+// Fisher matrix's rows and units), by forward-mode dual numbers through the
+// same strain as orc_waveform: dh[P][n_ifo][total][2], event e at columns
+// offsets[e] .. offsets[e] + npts[e] - 1.
+template <int P>
+static void waveform_deriv_events(int64_t n, const double* par, int64_t ld, const double* tc_s,
+                                  const std::vector<Ifo<double>>& ifos, const double* fmin,
+                                  const double* fmax, const int32_t* npts, int flags,
+                                  const int64_t* offsets, int64_t total, double* dh) {
+  using S = Dual<double, P>;
+  const int nifo = (int)ifos.size();
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t e = 0; e < n; ++e) {
+    double p[13];
+    for (int i = 0; i < 13; ++i) p[i] = par[i * ld + e];
+    double fhi = fmax ? fmax[e] : cut_frequency(p[0], p[1]);
+    Source<S> s = make_source<S>(p, tc_s ? tc_s[e] : 0.0);
+    for (int j = 0; j < P; ++j) slot(s, j).d[j] = 1.0;
+    std::vector<double> f, w;
+    make_grid(fmin[e], fhi, npts[e], f, w);
+    for (int d = 0; d < nifo; ++d)
+      for (int k = 0; k < npts[e]; ++k) {
+        S hr, hi;
+        strain(s, ifos[d], f[k], flags, hr, hi);
+        for (int j = 0; j < P; ++j) {
+          double* o = dh + (((int64_t)j * nifo + d) * total + offsets[e] + k) * 2;
+          o[0] = hr.d[j];
+          o[1] = hi.d[j];
+        }
+      }
+  }
+}
+
 extern "C" {
 
 // Constants, for the record of what the oracle assumed.
@@ -654,6 +687,21 @@ int orc_waveform(int64_t n, const double* par, int64_t ld, const double* tc_s, i
         strain(s, ifos[d], f[k], flags, o[0], o[1]);
       }
   }
+  return 0;
+}
+
+int orc_waveform_deriv(int64_t n, const double* par, int64_t ld, const double* tc_s, int n_site,
+                       const double* sites, const double* fmin, const double* fmax,
+                       const int32_t* npts, int flags, int nthreads, const int64_t* offsets,
+                       int64_t total, double* dh) {
+  auto ifos = expand_sites(n_site, sites);
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+  if (flags & FLAG_TIDAL)
+    waveform_deriv_events<13>(n, par, ld, tc_s, ifos, fmin, fmax, npts, flags, offsets, total, dh);
+  else
+    waveform_deriv_events<11>(n, par, ld, tc_s, ifos, fmin, fmax, npts, flags, offsets, total, dh);
   return 0;
 }
 

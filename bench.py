@@ -349,6 +349,34 @@ def main():
                       "frac": round(wave_gbs / PEAK_HBM_GBS, 4),
                       "traffic": MEASURED_TRAFFIC.get("waveform_kernel<rot,tidal%s>" % (",mixed" if mixed else ""))}
     del outw
+    # ---- strain derivatives (gwf_waveform_deriv) on the first 10^3 events:
+    # 16 B per point, interferometer and parameter (13), about 10 GB
+    nd = min(1000, wl.n)
+    wd = wl.subset(np.arange(nd))
+    dwd = binding.DeviceWorkload(wd)
+    endd = torch.cumsum(dwd.npts.to(torch.int64), 0)
+    offd, totd = endd - dwd.npts.to(torch.int64), int(endd[-1].item())
+    outd = {"dh": torch.empty((13, wd.n_ifo, totd), dtype=torch.complex128, device="cuda")}
+    for i in range(2):
+        binding.waveform_deriv(dwd, offsets=offd, total=totd, out=outd)
+    td = []
+    for i in range(max(3, args.steps // 4)):
+        ev[0].record(stream)
+        binding.waveform_deriv(dwd, offsets=offd, total=totd, out=outd)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        td.append(ev[0].elapsed_time(ev[1]))
+    der_ms = float(np.mean(td))
+    der_bytes = 16.0 * 13 * wd.n_ifo * totd + 8.0 * (13 * nd + 3 * nd)
+    der_gbs = der_bytes / (der_ms * 1e-3) / 1e9
+    log(f"waveform_deriv kernel {der_ms:.3f} ms, {der_bytes / 1e9:.2f} GB written, {der_gbs:.0f} GB/s")
+    wave["waveform_deriv_fp64"] = {"kernel": "waveform_deriv_kernel<rot,tidal>",
+                                   "workload": f"first {nd} events of bns1e4, 13 parameters",
+                                   "kernel_ms": round(der_ms, 4), "bytes": der_bytes,
+                                   "achieved_GBs": round(der_gbs, 1), "peak_GBs": PEAK_HBM_GBS,
+                                   "frac": round(der_gbs / PEAK_HBM_GBS, 4),
+                                   "traffic": MEASURED_TRAFFIC.get("waveform_deriv_kernel<rot,tidal>")}
+    del outd
 
     extra = {}
     if not args.no_extra:

@@ -205,6 +205,25 @@ gwf_status gwf_waveform(const gwf_events* ev, const gwf_network* net, const gwf_
                         uint32_t flags, const int64_t* offsets, int64_t total, double* h,
                         int32_t* status, void* stream);
 
+/* Derivatives of the detector strain with respect to the P parameters
+ * (P = 13 with GWF_TIDAL, else 11), the vectors whose noise-weighted
+ * products make the Fisher matrix (sec. 3.2):
+ *   Gamma_ab = 4 Re sum_i int d_a h_i(f) d_b h_i(f)^* / S_n,i(f) df,
+ * in the rows and units of gwf_fisher (GWF_MC ... order, dL in Gpc, the
+ * GWF_TCOAL row per second), analytic and evaluated with the strain's phase
+ * as in gwf_waveform.  Same events, network, grids, offsets and total as
+ * gwf_waveform (no GWF_MIXED: GWF_E_UNSUPPORTED).
+ *   dh      device [P][n_ifo][total][2] (re, im), required: row a * n_ifo + i
+ *           holds d h_i / d parameter a; rows of parameters outside an
+ *           event's set (ev->par_mask) are 0 over its columns.  Points of
+ *           events with a status are not written.
+ *   status  device int32 [n] or NULL
+ * The output holds P times the strain's bytes (about 101 GB for 10^4
+ * neutron-star binaries with 13 parameters on five interferometers). */
+gwf_status gwf_waveform_deriv(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
+                              uint32_t flags, const int64_t* offsets, int64_t total, double* dh,
+                              int32_t* status, void* stream);
+
 /* Network SNR (sec. 3.2) of every event.
  *   snr     device [n], required
  *   snr_ifo device [n_ifo][n] or NULL: SNR of each interferometer (a T site

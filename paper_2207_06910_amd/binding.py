@@ -89,6 +89,8 @@ def load():
         lib.gwf_waveform.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
                                      ctypes.POINTER(Grid), ctypes.c_uint32, vp, i64, vp, vp, vp]
         lib.gwf_waveform.restype = i32
+        lib.gwf_waveform_deriv.argtypes = lib.gwf_waveform.argtypes
+        lib.gwf_waveform_deriv.restype = i32
         lib.gwf_invert.argtypes = [i32, i64, vp, d, vp, vp, vp, vp, vp, vp, vp]
         lib.gwf_invert.restype = i32
         lib.gwf_covariance.argtypes = [i32, i64, vp, ctypes.POINTER(CovOptions), vp, vp, vp, vp, vp, vp, vp,
@@ -270,6 +272,37 @@ def waveform(dw: DeviceWorkload, offsets=None, total=None, mixed=False, stream=N
                                dw.flags | (MIXED if mixed else 0),
                                _ptr(offsets), int(total), _ptr(h), _ptr(res["status"]),
                                _stream(stream)), "gwf_waveform")
+    return res
+
+
+def waveform_deriv(dw: DeviceWorkload, offsets=None, total=None, stream=None, out=None):
+    """Strain derivatives dh [P][n_ifo][total] (complex128 on the device):
+    dh[a, i] is d h_i / d parameter a in the Fisher matrix's rows and units,
+    laid out over columns as by waveform(); P = 13 with tides, else 11."""
+    import torch
+    dev = dw.par.device
+    if offsets is None:
+        ends = torch.cumsum(dw.npts.to(torch.int64), 0)
+        offsets = ends - dw.npts.to(torch.int64)
+        if total is None:
+            total = int(ends[-1].item())
+    if not (offsets.is_cuda and offsets.dtype == torch.int64 and offsets.is_contiguous()
+            and offsets.numel() == dw.n):
+        raise GwfError("offsets must be a contiguous int64 device tensor of n entries")
+    if total is None:
+        raise GwfError("total is required with explicit offsets")
+    P = 13 if dw.flags & TIDAL else 11
+    res = out if out is not None else {}
+    res.setdefault("dh", torch.empty((P, dw.n_ifo, total), dtype=torch.complex128, device=dev))
+    res.setdefault("status", torch.empty(dw.n, dtype=torch.int32, device=dev))
+    dh = res["dh"]
+    if not (dh.is_cuda and dh.dtype == torch.complex128 and dh.is_contiguous()
+            and tuple(dh.shape) == (P, dw.n_ifo, total)):
+        raise GwfError(f"dh must be a contiguous complex128 device tensor of shape ({P}, {dw.n_ifo}, {total})")
+    ev, net, grid, keep = dw.descriptors()
+    _check(load().gwf_waveform_deriv(ctypes.byref(ev), ctypes.byref(net), ctypes.byref(grid), dw.flags,
+                                     _ptr(offsets), int(total), _ptr(dh), _ptr(res["status"]),
+                                     _stream(stream)), "gwf_waveform_deriv")
     return res
 
 

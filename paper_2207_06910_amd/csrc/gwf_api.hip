@@ -164,6 +164,25 @@ gwf_status gwf_waveform(const gwf_events* ev, const gwf_network* net, const gwf_
   return GWF_OK;
 }
 
+gwf_status gwf_waveform_deriv(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
+                              uint32_t flags, const int64_t* offsets, int64_t total, double* dh,
+                              int32_t* status, void* stream) {
+  gwf_status st = api_check_common(ev, grid, flags);
+  if (st) return st;
+  if (!offsets || !dh) return api_fail(GWF_E_INVALID_ARG, "offsets and dh are required");
+  if (total < 1) return api_fail(GWF_E_INVALID_ARG, "total=%lld must be >= 1", (long long)total);
+  if (flags & GWF_MIXED) return api_fail(GWF_E_UNSUPPORTED, "the strain derivatives have no mixed form");
+  gwf::WaveformArgs a{};
+  if ((st = api_pack_network(net, a.net))) return st;
+  a.par = ev->par; a.ld = ev->ld; a.n = ev->n; a.tc_s = ev->tc_s;
+  a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
+  a.offsets = offsets; a.total = total; a.dh = dh; a.status = status; a.par_mask = ev->par_mask;
+  hipError_t err = gwf::launch_waveform_deriv(a, (flags & GWF_TIDAL) != 0, (flags & GWF_EARTH_ROT) != 0,
+                                              (hipStream_t)stream);
+  if (err != hipSuccess) return api_hip_fail(err, "waveform derivative kernel launch");
+  return GWF_OK;
+}
+
 gwf_status gwf_fisher_adjoint(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
                               uint32_t flags, const double* gbar, const int32_t* status,
                               double w_snr, double w_fisher, double* grad_event, double* grad,

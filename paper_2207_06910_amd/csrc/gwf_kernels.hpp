@@ -92,6 +92,8 @@ struct WaveformArgs {
   int64_t total;            // points per interferometer row of h
   double* h;                // [n_ifo][total] complex (re, im)
   int32_t* status;          // [n] or NULL
+  double* dh;               // derivative kernel: [P][n_ifo][total] complex
+  const uint32_t* par_mask; // derivative kernel: [n] or NULL, rows outside an event's set are 0
 };
 
 struct AdjointArgs {
@@ -114,6 +116,7 @@ hipError_t launch_fisher(const FisherArgs& a, bool tidal, bool rot, hipStream_t 
 hipError_t launch_snr(const SnrArgs& a, bool rot, hipStream_t stream);
 hipError_t launch_invert(const InvertArgs& a, int P, hipStream_t stream);
 hipError_t launch_basis(const BasisArgs& a, int P, hipStream_t stream);
+hipError_t launch_waveform_deriv(const WaveformArgs& a, bool tidal, bool rot, hipStream_t stream);
 hipError_t launch_waveform(const WaveformArgs& a, bool tidal, bool rot, bool mixed, hipStream_t stream);
 hipError_t launch_adjoint(const AdjointArgs& a, bool tidal, bool rot, hipStream_t stream);
 

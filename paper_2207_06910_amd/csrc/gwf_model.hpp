@@ -751,6 +751,56 @@ __host__ __device__ inline double dot4(const double a[4], const double b[4]) {
   return fma(a[0], b[0], fma(a[1], b[1], fma(a[2], b[2], a[3] * b[3])));
 }
 
+// The event's amplitude factors that enter the derivative vectors.
+struct AmpFactors {
+  double cplus, ccross, dcp, dcx, dlnA, idL;
+};
+
+__host__ __device__ inline AmpFactors amp_factors(const EventC& ec) {
+  return AmpFactors{ec.cplus, ec.ccross, ec.dcplus, ec.dcross, ec.dlnA_dMc, ec.inv_dL};
+}
+
+// A site's derivatives of the phase at one point (the delay's share
+// included): with respect to Mc, eta, theta, phi and tc [s].
+struct SitePhase {
+  double mc, eta, t, p, tc;
+};
+
+__host__ __device__ inline SitePhase site_phase(const Point& q, const SitePoint& sp) {
+  return SitePhase{fma(q.tf * sp.dH, q.gMc, q.pMc), fma(q.tf * sp.dH, q.gEta, q.pEta), q.tf * sp.dT,
+                   -q.tf * sp.dH, q.tf * fma(kOmegaE, sp.dH, 1.0)};
+}
+
+// Phase-free derivative vector of one interferometer at one point,
+// D_b = dQ_b + Q dlnA_b + i Q dPsi_b for b = (Mc, eta, dL, theta, phi, iota,
+// psi, tc), from its pattern values F = (alpha.P, beta.P) and their hour-angle
+// (H) and theta (t) derivatives; Q = c+ F+ + i cx Fx.  The strain derivative
+// is A exp(i Psi) D_b, and i Q c(f) for the phase-only parameters.
+__host__ __device__ inline void derivative_vector(const AmpFactors& am, const Point& q, const SitePhase& ph,
+                                                  double Fp, double Fx, double FpH, double FxH,
+                                                  double Fpt, double Fxt, double* Dr, double* Di) {
+  const double Qr = am.cplus * Fp, Qi = am.ccross * Fx;
+  const double QHr = am.cplus * FpH, QHi = am.ccross * FxH;
+  const double Qtr = am.cplus * Fpt, Qti = am.ccross * Fxt;
+  // D = dQ + Q dlnA + i Q dPsi, with i Q x = (-Qi x, Qr x)
+  Dr[0] = fma(Qr, am.dlnA, fma(QHr, q.gMc, -Qi * ph.mc));     // Mc
+  Di[0] = fma(Qi, am.dlnA, fma(QHi, q.gMc, Qr * ph.mc));
+  Dr[1] = fma(QHr, q.gEta, -Qi * ph.eta);                     // eta
+  Di[1] = fma(QHi, q.gEta, Qr * ph.eta);
+  Dr[2] = -Qr * am.idL;                                       // dL
+  Di[2] = -Qi * am.idL;
+  Dr[3] = fma(-Qi, ph.t, Qtr);                                // theta
+  Di[3] = fma(Qr, ph.t, Qti);
+  Dr[4] = fma(-Qi, ph.p, -QHr);                               // phi (H = ... - phi)
+  Di[4] = fma(Qr, ph.p, -QHi);
+  Dr[5] = am.dcp * Fp;                                        // iota
+  Di[5] = am.dcx * Fx;
+  Dr[6] = 2.0 * am.cplus * Fx;                                // psi: dF+ = 2Fx, dFx = -2F+
+  Di[6] = -2.0 * am.ccross * Fp;
+  Dr[7] = fma(kOmegaE, QHr, -Qi * ph.tc);                     // tc [s]
+  Di[7] = fma(kOmegaE, QHi, Qr * ph.tc);
+}
+
 // ------------------------------------------------ one frequency point
 // Adds the contribution of grid point k of an event to G[36], the 8x8
 // upper-triangle block of (Mc, eta, dL, theta, phi, iota, psi, tc)
@@ -766,9 +816,7 @@ template <bool TIDAL, bool ROT, bool MIXED = false, bool PSUM = true>
 __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* sc, int n_site,
                                                  int32_t k, double* G, double* U, double& W,
                                                  double* cph) {
-  constexpr int NPI = TIDAL ? 5 : 3;
-  const double cplus = ec.cplus, ccross = ec.ccross, dcp = ec.dcplus, dcx = ec.dcross;
-  const double dlnA = ec.dlnA_dMc, idL = ec.inv_dL;
+  const AmpFactors am = amp_factors(ec);
   Point q;
   point_setup<PSUM>(ec, k, true, ROT, q, !MIXED);
   W = 0.0;
@@ -778,37 +826,14 @@ __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* 
     const SiteC& st = sc[s];
     SitePoint sp;
     site_point<MIXED, PSUM>(st, q, true, sp);
-    const double phMc = fma(q.tf * sp.dH, q.gMc, q.pMc);
-    const double phEta = fma(q.tf * sp.dH, q.gEta, q.pEta);
-    const double phT = q.tf * sp.dT;
-    const double phP = -q.tf * sp.dH;
-    const double phTc = q.tf * fma(kOmegaE, sp.dH, 1.0);
+    const SitePhase ph = site_phase(q, sp);
     for (int j = 0; j < st.n_eff; ++j) {
       const double om = sp.om * st.weff[j];
       const double Fp = dot4(st.alpha[j], sp.P), Fx = dot4(st.beta[j], sp.P);
-      const double FpH = dot4(st.alpha[j], sp.PH), FxH = dot4(st.beta[j], sp.PH);
-      const double Fpt = dot4(st.alpha[j], sp.Pt), Fxt = dot4(st.beta[j], sp.Pt);
-      const double Qr = cplus * Fp, Qi = ccross * Fx;
-      const double QHr = cplus * FpH, QHi = ccross * FxH;
-      const double Qtr = cplus * Fpt, Qti = ccross * Fxt;
       double Dr[8], Di[8];
-      // D = dQ + Q dlnA + i Q dPsi, with i Q x = (-Qi x, Qr x)
-      Dr[0] = fma(Qr, dlnA, fma(QHr, q.gMc, -Qi * phMc));     // Mc
-      Di[0] = fma(Qi, dlnA, fma(QHi, q.gMc, Qr * phMc));
-      Dr[1] = fma(QHr, q.gEta, -Qi * phEta);                  // eta
-      Di[1] = fma(QHi, q.gEta, Qr * phEta);
-      Dr[2] = -Qr * idL;                                      // dL
-      Di[2] = -Qi * idL;
-      Dr[3] = fma(-Qi, phT, Qtr);                             // theta
-      Di[3] = fma(Qr, phT, Qti);
-      Dr[4] = fma(-Qi, phP, -QHr);                            // phi (H = ... - phi)
-      Di[4] = fma(Qr, phP, -QHi);
-      Dr[5] = dcp * Fp;                                       // iota
-      Di[5] = dcx * Fx;
-      Dr[6] = 2.0 * cplus * Fx;                               // psi: dF+ = 2Fx, dFx = -2F+
-      Di[6] = -2.0 * ccross * Fp;
-      Dr[7] = fma(kOmegaE, QHr, -Qi * phTc);                  // tc [s]
-      Di[7] = fma(kOmegaE, QHi, Qr * phTc);
+      derivative_vector(am, q, ph, Fp, Fx, dot4(st.alpha[j], sp.PH), dot4(st.beta[j], sp.PH),
+                        dot4(st.alpha[j], sp.Pt), dot4(st.beta[j], sp.Pt), Dr, Di);
+      const double Qr = am.cplus * Fp, Qi = am.ccross * Fx;
       int g = 0;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {

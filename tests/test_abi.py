@@ -65,6 +65,11 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.gwf_waveform(B(ev), B(net), B(grid), 0, None, 10, 8, None, None) == 1
     assert lib.gwf_waveform(B(ev), B(net), B(grid), 0, 8, 10, None, None, None) == 1
     assert lib.gwf_waveform(B(ev), B(net), B(grid), 0, 8, 0, 8, None, None) == 1
+    # strain derivatives: the same checks, and no mixed form
+    assert lib.gwf_waveform_deriv(B(ev), B(net), B(grid), 0, None, 10, 8, None, None) == 1
+    assert lib.gwf_waveform_deriv(B(ev), B(net), B(grid), 0, 8, 10, None, None, None) == 1
+    assert lib.gwf_waveform_deriv(B(ev), B(net), B(grid), 0, 8, 0, 8, None, None) == 1
+    assert lib.gwf_waveform_deriv(B(ev), B(net), B(grid), binding.MIXED, 8, 10, 8, None, None) == 2
     # inversion: P out of range, NaN threshold
     assert lib.gwf_invert(14, 3, 8, 1e50, None, 8, None, None, None, 8, None) == 1
     assert lib.gwf_invert(13, 3, 8, float("nan"), None, 8, None, None, None, 8, None) == 1

@@ -31,12 +31,31 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # profiles/bns1e4_hbm_counters.md (calibrated against a 256 MiB copy: fetch
 # x 2.000, write x 1.000).  Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
-    "items_kernel<tidal,rot,mixed>": 58.42e6,
-    "items_kernel<tidal,rot>": 67.12e6,
-    "fisher_kernel<tidal,rot>": None,
-    "waveform_kernel<rot,tidal>": 7848.55e6,
-    "waveform_kernel<rot,tidal,mixed>": 7860.59e6,
+    "items_kernel<tidal,rot,mixed>": 61.55e6,
+    "items_kernel<tidal,rot>": 72.10e6,
+    "fisher_kernel<tidal,rot>": 127.54e6,
+    "waveform_kernel<rot,tidal>": 7848.64e6,
+    "waveform_kernel<rot,tidal,mixed>": 7862.99e6,
+    "waveform_deriv_kernel<rot,tidal>": 10304.34e6,
 }
+
+# VALU instructions (wavefront instructions, SQ_INSTS_VALU) per launch of the
+# Fisher kernels on the BNS catalogue, from the instruction-counter pass
+# summarised in profiles/bns1e4_kernel_trace.md.  A wave64 VALU instruction
+# occupies its SIMD for 4 cycles, so the VALU busy fraction is
+# 4 x SQ_INSTS_VALU / (1024 SIMDs x 2.4 GHz x kernel time).  Set an entry to
+# None when its kernel changes.
+MEASURED_VALU_INSTS = {
+    "items_kernel<tidal,rot,mixed>": 2.197e9,
+    "items_kernel<tidal,rot>": 1.938e9,
+    "fisher_kernel<tidal,rot>": 2.100e9,
+}
+N_SIMD, CLOCK_HZ = 1024, 2.4e9
+
+
+def valu_busy(kernel: str, kernel_ms: float):
+    n = MEASURED_VALU_INSTS.get(kernel)
+    return None if n is None else round(4.0 * n / (N_SIMD * CLOCK_HZ * kernel_ms * 1e-3), 4)
 
 
 def log(msg):
@@ -426,7 +445,8 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                 "traffic": MEASURED_TRAFFIC.get(kname),
-                "kernel": kname, "kernel_ms": round(kms, 4), "flops_per_launch": flops}
+                "kernel": kname, "kernel_ms": round(kms, 4), "flops_per_launch": flops,
+                "valu_busy": valu_busy(kname, kms)}
 
     value = wl.n / (ms * 1e-3)
     forms = {"plain_fp64": {"events_per_s": round(wl.n / (plain_ms * 1e-3), 1),

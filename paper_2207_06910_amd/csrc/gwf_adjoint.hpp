@@ -246,7 +246,11 @@ __host__ __device__ inline void adjoint_site(const EventC& ec, const SiteA& sa, 
   double bP[4] = {0.0, 0.0, 0.0, 0.0}, bPH[4] = {0.0, 0.0, 0.0, 0.0}, bPt[4] = {0.0, 0.0, 0.0, 0.0};
   double sP[4] = {0.0, 0.0, 0.0, 0.0};
   double bdH = 0.0, bdT = 0.0, bgam = 0.0, sgam = 0.0;
-  for (int j = 0; j < sa.n_eff; ++j) {
+  // at most two effective interferometers; unrolled, with the count the same
+  // for every lane (the second pass is skipped as a whole where unused)
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    if (j >= sa.n_eff) break;
     // compiler barrier: the constants below are loaded when needed rather
     // than all at once (register pressure)
     asm volatile("" ::: "memory");

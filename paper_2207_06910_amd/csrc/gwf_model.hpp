@@ -827,7 +827,11 @@ __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* 
     SitePoint sp;
     site_point<MIXED, PSUM>(st, q, true, sp);
     const SitePhase ph = site_phase(q, sp);
-    for (int j = 0; j < st.n_eff; ++j) {
+    // at most two effective interferometers per site; the count is the same
+    // for every lane, so the second pass is skipped as a whole where unused
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (j >= st.n_eff) break;
       const double om = sp.om * st.weff[j];
       const double Fp = dot4(st.alpha[j], sp.P), Fx = dot4(st.beta[j], sp.P);
       double Dr[8], Di[8];

@@ -33,7 +33,7 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 MEASURED_TRAFFIC = {
     "items_kernel<tidal,rot,mixed>": 61.55e6,
     "items_kernel<tidal,rot>": 72.10e6,
-    "fisher_kernel<tidal,rot>": 127.54e6,
+    "fisher_kernel<tidal,rot>": None,
     "waveform_kernel<rot,tidal>": 7848.64e6,
     "waveform_kernel<rot,tidal,mixed>": 7862.99e6,
     "waveform_deriv_kernel<rot,tidal>": 10304.34e6,
@@ -48,7 +48,7 @@ MEASURED_TRAFFIC = {
 MEASURED_VALU_INSTS = {
     "items_kernel<tidal,rot,mixed>": 2.197e9,
     "items_kernel<tidal,rot>": 1.938e9,
-    "fisher_kernel<tidal,rot>": 2.100e9,
+    "fisher_kernel<tidal,rot>": None,
 }
 N_SIMD, CLOCK_HZ = 1024, 2.4e9
 

@@ -250,6 +250,21 @@ gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_gr
                       uint32_t flags, double snr_th, double* fisher, double* snr,
                       double* snr_ifo, int32_t* status, void* stream);
 
+/* The Fisher matrix of every interferometer on its own (the paper's
+ * per-detector matrices, return_all in sec. 3.2), whose sum over the
+ * interferometers is gwf_fisher's network matrix; a T site gives its three
+ * arms in order, each with its own pattern map.  Same events (the duty
+ * factor's active flags and par_mask included), network, grids and flags as
+ * gwf_fisher, no SNR threshold and no GWF_MIXED (GWF_E_UNSUPPORTED).  One
+ * launch per interferometer.
+ *   fisher_ifo device [n_ifo][P][P][n], required; an interferometer that is
+ *              off for an event (active) gives zeros there
+ *   status     device int32 [n], required: the parameter status, as for
+ *              gwf_fisher (GWF_EV_NONFINITE if any matrix is not finite)
+ * Per-interferometer SNRs come from gwf_snr (snr_ifo). */
+gwf_status gwf_fisher_ifo(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
+                          uint32_t flags, double* fisher_ifo, int32_t* status, void* stream);
+
 /* Adjoint (reverse mode) of the Fisher/SNR map with respect to the detector
  * parameters: the gradient of a network figure of merit
  *   J = sum_e [ w_snr ln SNR_e + w_fisher sum_ij Gbar_e,ij Gamma_e,ij ]

@@ -89,6 +89,9 @@ def load():
         lib.gwf_waveform.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
                                      ctypes.POINTER(Grid), ctypes.c_uint32, vp, i64, vp, vp, vp]
         lib.gwf_waveform.restype = i32
+        lib.gwf_fisher_ifo.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
+                                       ctypes.POINTER(Grid), ctypes.c_uint32, vp, vp, vp]
+        lib.gwf_fisher_ifo.restype = i32
         lib.gwf_waveform_deriv.argtypes = lib.gwf_waveform.argtypes
         lib.gwf_waveform_deriv.restype = i32
         lib.gwf_invert.argtypes = [i32, i64, vp, d, vp, vp, vp, vp, vp, vp, vp]
@@ -272,6 +275,26 @@ def waveform(dw: DeviceWorkload, offsets=None, total=None, mixed=False, stream=N
                                dw.flags | (MIXED if mixed else 0),
                                _ptr(offsets), int(total), _ptr(h), _ptr(res["status"]),
                                _stream(stream)), "gwf_waveform")
+    return res
+
+
+def fisher_ifo(dw: DeviceWorkload, stream=None, out=None):
+    """Fisher matrix of every interferometer on its own, fisher_ifo
+    [n_ifo][P][P][N] (float64 on the device), whose sum over interferometers
+    is fisher()'s; plus the parameter status."""
+    import torch
+    dev = dw.par.device
+    P = 13 if dw.flags & TIDAL else 11
+    res = out if out is not None else {}
+    res.setdefault("fisher_ifo", torch.empty((dw.n_ifo, P, P, dw.n), dtype=torch.float64, device=dev))
+    res.setdefault("status", torch.empty(dw.n, dtype=torch.int32, device=dev))
+    F = res["fisher_ifo"]
+    if not (F.is_cuda and F.dtype == torch.float64 and F.is_contiguous()
+            and tuple(F.shape) == (dw.n_ifo, P, P, dw.n)):
+        raise GwfError(f"fisher_ifo must be a contiguous float64 device tensor of shape ({dw.n_ifo}, {P}, {P}, {dw.n})")
+    ev, net, grid, keep = dw.descriptors()
+    _check(load().gwf_fisher_ifo(ctypes.byref(ev), ctypes.byref(net), ctypes.byref(grid), dw.flags,
+                                 _ptr(F), _ptr(res["status"]), _stream(stream)), "gwf_fisher_ifo")
     return res
 
 

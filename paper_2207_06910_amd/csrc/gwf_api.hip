@@ -146,6 +146,30 @@ gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_gr
   return GWF_OK;
 }
 
+gwf_status gwf_fisher_ifo(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
+                          uint32_t flags, double* fisher_ifo, int32_t* status, void* stream) {
+  gwf_status st = api_check_common(ev, grid, flags);
+  if (st) return st;
+  if (!fisher_ifo || !status) return api_fail(GWF_E_INVALID_ARG, "fisher_ifo and status are required");
+  if (flags & GWF_MIXED) return api_fail(GWF_E_UNSUPPORTED, "the mixed form runs through a plan");
+  gwf::FisherArgs a{};
+  if ((st = api_pack_network(net, a.net))) return st;
+  a.par = ev->par; a.ld = ev->ld; a.n = ev->n;
+  a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
+  a.active = ev->active;
+  a.par_mask = ev->par_mask;
+  a.snr = nullptr; a.status = status;
+  const bool rot = (flags & GWF_EARTH_ROT) != 0, tidal = (flags & GWF_TIDAL) != 0;
+  const int64_t P = tidal ? 13 : 11;
+  for (int d = 0; d < a.net.n_ifo; ++d) {
+    a.ifo_sel = d + 1;
+    a.fisher = fisher_ifo + (int64_t)d * P * P * ev->n;
+    hipError_t err = gwf::launch_fisher(a, tidal, rot, (hipStream_t)stream);
+    if (err != hipSuccess) return api_hip_fail(err, "fisher kernel launch");
+  }
+  return GWF_OK;
+}
+
 gwf_status gwf_waveform(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
                         uint32_t flags, const int64_t* offsets, int64_t total, double* h,
                         int32_t* status, void* stream) {

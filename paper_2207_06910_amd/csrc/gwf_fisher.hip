@@ -57,12 +57,14 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(Fis
   if (skip) {
     for (int i = tid; i < P * P; i += kBlock) a.fisher[(int64_t)i * a.n + e] = 0.0;
     if (tid == 0) {
-      if (!a.snr_pre) a.snr[e] = 0.0;
+      if (!a.snr_pre && a.snr) a.snr[e] = 0.0;
       a.status[e] = skip;
     }
     return;
   }
-  if (tid < n_site) site_setup(p, a.net.site[tid], ec, sc[tid], site_arms_on(a.active, a.ld, e, a.net, tid));
+  if (tid < n_site)
+    site_setup(p, a.net.site[tid], ec, sc[tid],
+               select_ifo(site_arms_on(a.active, a.ld, e, a.net, tid), a.net, tid, a.ifo_sel));
   __syncthreads();
 
   double t = 0.0;
@@ -70,14 +72,18 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(Fis
   if (tid < NACC) {
     int r, c;
     slot_position(tid, NPI, r, c);
-    if (r == 8 && c == 8) a.snr[e] = sqrt(t);     // Gamma_{Phic,Phic} = SNR^2
+    if (r == 8 && c == 8 && a.snr) a.snr[e] = sqrt(t);     // Gamma_{Phic,Phic} = SNR^2
     const double v = rows_in(event_rows(a.par_mask, e), r, c) ? t : 0.0;
     if (!isfinite(v)) atomicOr(&bad, 1);
     a.fisher[((int64_t)r * P + c) * a.n + e] = v;
     a.fisher[((int64_t)c * P + r) * a.n + e] = v;
   }
   __syncthreads();
-  if (tid == 0) a.status[e] = bad ? kEvNonFinite : 0;
+  // one launch per interferometer (ifo_sel > 1 after the first) adds its bit
+  if (tid == 0) {
+    const int32_t f = bad ? kEvNonFinite : 0;
+    a.status[e] = a.ifo_sel > 1 ? (a.status[e] | f) : f;
+  }
 }
 
 // SNR only, with the SNR of every interferometer.  Same grid, weights and

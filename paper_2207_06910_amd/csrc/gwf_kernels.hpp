@@ -13,11 +13,12 @@ struct FisherArgs {
   const int32_t* npts;
   const uint8_t* active;    // [n_ifo][ld] or NULL: interferometers taking part (duty factor)
   const uint32_t* par_mask; // [n] or NULL: rows of each event's Fisher matrix (others 0)
+  int32_t ifo_sel;          // 0: every interferometer; d + 1: interferometer d alone
   NetDesc net;
   double snr_th;
   const double* snr_pre;    // NULL, or SNRs of a previous pass for the threshold
   double* fisher;           // [P][P][n]
-  double* snr;              // [n]
+  double* snr;              // [n] or NULL
   int32_t* status;          // [n]
 };
 

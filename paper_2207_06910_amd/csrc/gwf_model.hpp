@@ -486,6 +486,17 @@ __host__ __device__ inline uint32_t site_arms_on(const uint8_t* active, int64_t 
   return m;
 }
 
+// The arms of site s that take part when only interferometer ifo_sel - 1 is
+// wanted (ifo_sel = 0: every arm in `arms`).
+__host__ __device__ inline uint32_t select_ifo(uint32_t arms, const NetDesc& net, int s, int ifo_sel) {
+  if (ifo_sel <= 0) return arms;
+  int ifo0 = 0;
+  for (int u = 0; u < s; ++u) ifo0 += net.site[u].shape == 1 ? 3 : 1;
+  const int k = ifo_sel - 1 - ifo0;
+  const int na = net.site[s].shape == 1 ? 3 : 1;
+  return (k >= 0 && k < na) ? (arms & (1u << k)) : 0u;
+}
+
 // ---------------------------------------------------------- sin and cos
 // sin and cos of a moderate angle (|x| < 1e5): Cody-Waite reduction by pi/2
 // with a three-part constant, then the Taylor series of sin (to x^17) and

@@ -65,6 +65,10 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.gwf_waveform(B(ev), B(net), B(grid), 0, None, 10, 8, None, None) == 1
     assert lib.gwf_waveform(B(ev), B(net), B(grid), 0, 8, 10, None, None, None) == 1
     assert lib.gwf_waveform(B(ev), B(net), B(grid), 0, 8, 0, 8, None, None) == 1
+    # per-interferometer Fisher: outputs required, no mixed form
+    assert lib.gwf_fisher_ifo(B(ev), B(net), B(grid), 0, None, 8, None) == 1
+    assert lib.gwf_fisher_ifo(B(ev), B(net), B(grid), 0, 8, None, None) == 1
+    assert lib.gwf_fisher_ifo(B(ev), B(net), B(grid), binding.MIXED, 8, 8, None) == 2
     # strain derivatives: the same checks, and no mixed form
     assert lib.gwf_waveform_deriv(B(ev), B(net), B(grid), 0, None, 10, 8, None, None) == 1
     assert lib.gwf_waveform_deriv(B(ev), B(net), B(grid), 0, 8, 10, None, None, None) == 1

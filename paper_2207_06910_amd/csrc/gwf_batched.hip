@@ -76,9 +76,9 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void items_kernel(Item
       if (tid < NACC) out[tid] = 0.0;
     } else {
       double t = 0.0;
-      // FP64: sums of products over shared powers and the PSD power law once
-      // per point; mixed: Horner (measured faster there, see horner7)
-      fisher_sums<TIDAL, ROT, MIXED, !MIXED>(ecg, scg, n_site, k0, k1, L, &t);
+      // both forms: PN series as sums of products over shared powers and the
+      // PSD power law once per point (in FP32 for the mixed form)
+      fisher_sums<TIDAL, ROT, MIXED, true>(ecg, scg, n_site, k0, k1, L, &t);
       if (tid < NACC) out[tid] = t;
     }
     __syncthreads();                             // LDS is reused by the next item

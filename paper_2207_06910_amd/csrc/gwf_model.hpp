@@ -257,6 +257,30 @@ __host__ __device__ inline double cut_frequency_of(double M_s) {
 // x is neither infinite nor NaN (x - x is 0 exactly for finite x).
 __host__ __device__ inline bool finite(double x) { return (x - x) == 0.0; }
 
+// 1/x for finite x != 0: the hardware reciprocal refined by two Newton
+// steps (each squares the relative error), within an ulp or so of the
+// rounded quotient; the host build divides.
+__host__ __device__ inline double recip(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+
+// 1/x in FP32 from the hardware reciprocal (about an ulp); the host build divides.
+__host__ __device__ inline float recipf(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+
 // Rows of event e's Fisher matrix (bit r: row r; NULL: every row).
 __host__ __device__ inline uint32_t event_rows(const uint32_t* par_mask, int64_t e) {
   return par_mask ? par_mask[e] : ~0u;
@@ -622,14 +646,18 @@ struct Point {
   double vpsd;                    // v^-12.42: the PSD's power law, shared by all sites
 };
 
+// How point_setup forms the PSD's power law v^-12.42 shared by all sites:
+// not at all, in FP64, or in FP32 (the mixed form's weight).
+enum PsdPow { kPsdNone = 0, kPsdF64 = 1, kPsdF32 = 2 };
+
 // PSUM: the evaluation form of the PN series (see horner7) and of the PSD's
 // power law (once per point when true, once per site otherwise).
 template <bool PSUM = true>
 __host__ __device__ inline void point_setup(const EventC& ec, int32_t k, bool need_derivs, bool rot,
-                                            Point& q, bool need_psd = true) {
+                                            Point& q, int psd = kPsdF64) {
   const double L = fma((double)k, ec.dlnv, ec.lnv0);
   const double v = exp(L);
-  const double iv = 1.0 / v;
+  const double iv = recip(v);
   const double iv2 = iv * iv, iv4 = iv2 * iv2, iv5 = iv4 * iv, iv7 = iv5 * iv2, iv8 = iv4 * iv4;
   const double f = v * v * v * ec.inv_piM;
   double w = ec.wint;
@@ -638,7 +666,13 @@ __host__ __device__ inline void point_setup(const EventC& ec, int32_t k, bool ne
   q.v = v; q.iv = iv; q.L = L; q.f = f;
   q.tf = kTwoPi * f;
   q.w4A2 = w * f * ec.KA4 * iv7;
-  q.vpsd = (PSUM && need_psd) ? exp(-12.42 * L) : 0.0;
+  q.vpsd = 0.0;
+  if (PSUM && psd == kPsdF64) {
+    q.vpsd = exp(-12.42 * L);
+  } else if (psd == kPsdF32) {   // 2^y with the integer part of y split off exactly
+    const double y = (-12.42 / kLn2) * L, ny = rint(y);
+    q.vpsd = (double)ldexpf(exp2f((float)(y - ny)), (int)ny);
+  }
   VPow pw;
   vpow(v, L, pw);
   const double th = rot ? ec.thc + eval_tau<PSUM>(ec.ts[kTsTheta], pw, iv8, iv2) : ec.thc;
@@ -700,7 +734,7 @@ __host__ __device__ inline double psd_weight_of(double xp_fac, double lnx_off, d
   const double den = fma(0.5, x2, 1.0);
   // shape = [(x^-4.14 - 5 x^-2) den + 111 num] / den
   const double top = fma(fma(-5.0, ix2, xp), den, 111.0 * num);
-  return q.w4A2 * S0inv * den / top;
+  return q.w4A2 * S0inv * den * recip(top);
 }
 
 template <bool PSUM = true>
@@ -714,21 +748,21 @@ __host__ __device__ inline void psd_weight(const SiteC& sc, const Point& q, doub
 // positive-semidefinite order: SNR^2 moves by at most e and every sigma_i by
 // at most about e/2, whatever the condition number.  Errors in the
 // derivative vectors or in the sums have no such bound, which is why they
-// stay FP64.  x^-4.14 = 2^y with y = -4.14 log2 x formed in FP64 and its
-// integer part split off exactly, so the FP32 exponential sees |r| <= 1/2
-// and the argument's rounding costs below 1e-7; x^2 and x^-2 are FP64
-// products rounded once.
+// stay FP64.  x^-4.14 = xp_fac v^-12.42, the power of v taken once per point
+// as 2^y with y = -12.42 log2 v formed in FP64 and its integer part split
+// off exactly (point_setup, kPsdF32), so the FP32 exponential sees
+// |r| <= 1/2; x^2 and x^-2 are FP64 products rounded once; the quotient uses
+// the FP32 reciprocal.  Measured: 1.2e-8 of sqrt(Gamma_aa Gamma_bb) on the
+// BNS catalogue.
 __host__ __device__ inline void psd_weight_f32(const SiteC& sc, const Point& q, double& om) {
-  const double y = (-4.14 / kLn2) * fma(3.0, q.L, sc.lnx_off);
-  const double n = rint(y);
-  const float xp = ldexpf(exp2f((float)(y - n)), (int)n);
+  const float xp = (float)(sc.xp_fac * q.vpsd);
   const double v3 = q.v * q.v * q.v, iv3 = q.iv * q.iv * q.iv;
   const double x = sc.x_fac * v3, ix = sc.ix_fac * iv3;
   const float x2 = (float)(x * x), ix2 = (float)(ix * ix);
   const float num = fmaf(0.5f * x2, x2, 1.0f - x2);
   const float den = fmaf(0.5f, x2, 1.0f);
   const float top = fmaf(fmaf(-5.0f, ix2, xp), den, 111.0f * num);
-  om = q.w4A2 * sc.S0inv * (double)(den / top);
+  om = q.w4A2 * sc.S0inv * (double)(den * recipf(top));
 }
 
 template <bool MIXED = false, bool PSUM = true>
@@ -829,7 +863,7 @@ __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* 
                                                  double* cph) {
   const AmpFactors am = amp_factors(ec);
   Point q;
-  point_setup<PSUM>(ec, k, true, ROT, q, !MIXED);
+  point_setup<PSUM>(ec, k, true, ROT, q, MIXED ? kPsdF32 : kPsdF64);
   W = 0.0;
 #pragma unroll
   for (int b = 0; b < 8; ++b) U[b] = 0.0;

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kWBlock) void waveform_deriv_kernel(WaveformArgs a)
     // reads) rather than held in registers across iterations
     asm volatile("" ::: "memory");
     Point q;
-    point_setup<true>(ec, k, true, ROT, q, false);
+    point_setup<true>(ec, k, true, ROT, q, kPsdNone);
     VPow pw;
     vpow(q.v, q.L, pw);
     const double iv = q.iv, iv2 = iv * iv, iv5 = iv2 * iv2 * iv;

@@ -70,3 +70,16 @@ def test_fisher_ifo_against_oracle_and_network(lib, orc, case):
     assert _norm_err(Fi, Ri) <= 1e-9
     G = net["fisher"].cpu().numpy()
     assert _norm_err(Fi.sum(axis=0), G) <= 1e-12
+
+
+def test_fisher_ifo_single_detector_equals_network(lib, orc):
+    """One L detector without rotation (11 parameters): its only matrix is
+    the network matrix itself, bit for bit (the same kernel with the same
+    single interferometer), and matches the oracle."""
+    wl = synth.bbh100().subset(np.arange(6))
+    dw = lib.DeviceWorkload(wl)
+    Fi = lib.fisher_ifo(dw)["fisher_ifo"].cpu().numpy()
+    G = lib.fisher(dw)["fisher"].cpu().numpy()
+    assert Fi.shape == (1, 11, 11, 6)
+    assert np.array_equal(Fi[0], G)
+    assert _norm_err(Fi, orc.fisher(wl, per_ifo=True)["fisher_ifo"]) <= 1e-9

@@ -165,3 +165,22 @@ def test_parameter_sets_invalid_events_and_mixed(lib, orc):
                                        dw.flags | lib.MIXED, off.data_ptr(), total, out.data_ptr(),
                                        None, None)
     assert rc == lib.GWF_E_UNSUPPORTED
+
+
+def test_gps_scale_tc_against_oracle(lib, orc):
+    """Coalescence times of order 1e9 s in the phase (the 2 pi f tc term
+    reaches 1e13 rad): every derivative against the oracle with the phase
+    scale of the tolerance including tc, and the Fisher matrix rebuilt from
+    the derivatives unchanged by tc (it depends on |d h|^2 only)."""
+    full = synth.bns1e4()
+    wl = full.subset(np.arange(3)).with_npts(500)
+    wl.tc_s = np.array([1.3e9, 1.0e9 + 0.37, 2.5e8])
+    offsets, total = _offsets(wl.npts, 3)
+    dh, st = _gpu(lib, wl, offsets, total)
+    np.testing.assert_array_equal(st, 0)
+    _check_against_oracle(orc, wl, dh, offsets, total)
+    w0 = wl.subset(np.arange(wl.n))
+    w0.tc_s = None
+    dh0, _ = _gpu(lib, w0, offsets, total)
+    F, F0 = _fisher_from(orc, wl, dh, offsets), _fisher_from(orc, w0, dh0, offsets)
+    assert _fisher_close(F, F0) <= 1e-11

@@ -58,6 +58,18 @@ def valu_busy(kernel: str, kernel_ms: float):
     return None if n is None else round(4.0 * n / (N_SIMD * CLOCK_HZ * kernel_ms * 1e-3), 4)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -103,6 +115,7 @@ def cpu_baseline(wl, sample: int):
            "sample": f"{sample} seeded events of the same catalogue ({int(sub.npts.sum())} grid "
                      f"points); Fisher+SNR {t1 - t0:.2f} s on {threads} threads, mpmath "
                      f"inversion {t2 - t1:.2f} s"}
+    rec["cpu_model"] = cpu_model()
     return rec, {"idx": idx, "snr": r["snr"], "fisher": r["fisher"], "sigma": inv["sigma"],
                  "cond": inv["cond"]}
 

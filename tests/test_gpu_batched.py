@@ -173,3 +173,29 @@ def test_catalogue_1e6_plan(lib, orc):
     d = np.sqrt(np.where(inn[:, idx], np.einsum("iie->ie", ref["fisher"]), 1.0))
     assert (np.abs(F - ref["fisher"]) / (d[:, None, :] * d[None, :, :])).max() <= 1e-9
     plan.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_full_catalogue_in_the_bench_launch(lib, orc, mixed):
+    """Both batched forms on the whole 10^4-event BNS catalogue in the
+    benchmark's launch (16384-point items, four workgroups per compute unit,
+    HIP graph, inversion): every event valid and inverted or flagged, the
+    identity Gamma_dLdL dL^2 = SNR^2 for all of them (both sides carry the
+    same weights, so it holds to rounding in either form), and sampled
+    events against the oracle at the form's bar (FP64: SNR 1e-12, Fisher
+    1e-9; mixed: the weight-error bounds of test_mixed_plan_bounds)."""
+    full = synth.bns1e4()
+    dw = lib.DeviceWorkload(full)
+    plan = lib.Plan(dw, chunk=16384, wg_per_cu=4, mixed=mixed)
+    g = _np(plan.run(invert=True))
+    plan.close()
+    torch.cuda.synchronize()
+    st = g["status"]
+    assert np.all(st & 1 == 0) and np.all(st & 8 == 0)
+    assert (st == 0).sum() >= 0.99 * full.n
+    np.testing.assert_allclose(g["fisher"][2, 2] * full.par[2] ** 2, g["snr"] ** 2, rtol=1e-12)
+    idx = np.random.default_rng(5 + mixed).choice(full.n, 8, replace=False)
+    ref = orc.fisher(full.subset(idx))
+    tol_s, tol_f = (EPS_W / 2 + 1e-12, EPS_W + 1e-9) if mixed else (1e-12, 1e-9)
+    np.testing.assert_allclose(g["snr"][idx], ref["snr"], rtol=tol_s)
+    assert _ferr(g["fisher"][:, :, idx], ref["fisher"]) <= tol_f

@@ -22,9 +22,9 @@
 //   * quadrature: the trapezoid rule on the log-spaced grid the paper builds
 //     with geomspace (sec. 2.2), summed with Neumaier compensation.
 //
-// Readings where the paper is silent (PN coefficients, constants, sign and
-// frame conventions) are listed in the design doc; each block below names the
-// source it follows.  The scalar type is a template parameter so that the
+// Where the paper is silent (PN coefficients, constants, sign and frame
+// conventions) each block below names the source or the convention it
+// follows.  The scalar type is a template parameter so that the
 // same code runs on double, on dual numbers (derivatives), on nested dual
 // numbers (gradients of Fisher figures of merit w.r.t. detector parameters)
 // and on std::complex<double> (complex-step derivative checks).

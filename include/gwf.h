@@ -411,7 +411,12 @@ gwf_status gwf_covariance(int32_t P, int64_t n, const double* fisher, const gwf_
  *   out      device [P][P][n]; may equal fisher (in place)
  *   status   device int32 [n] or NULL: GWF_EV_NONFINITE is OR-ed in where the
  *            result is not finite (e.g. the tidal basis at eta = 1/4, where
- *            the map is singular) */
+ *            the map is singular)
+ * ev->par_mask is not read: a matrix with rows left out of its event's
+ * parameter set keeps zeros there when each pair of rows a basis mixes is
+ * wholly in or out of the set (a black-hole pair's 11 rows in any basis); a
+ * set holding one row of a pair (an NS-BH pair's Lambda2 without Lambda1)
+ * gives a singular matrix in the basis that mixes them. */
 enum { GWF_BASIS_CHI_SA = 1, GWF_BASIS_LAMBDA_TILDE = 2, GWF_BASIS_M1M2 = 4 };
 
 gwf_status gwf_fisher_basis(int32_t P, int64_t n, const double* fisher, const gwf_events* ev,

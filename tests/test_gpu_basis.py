@@ -86,3 +86,25 @@ def test_full_catalogue_sampled(lib, orc):
     idx = np.random.default_rng(9).choice(wl.n, 6, replace=False)
     _check(orc, F.cpu().numpy()[:, :, idx], wl.par[:, idx], G.cpu().numpy()[:, :, idx], 3)
     plan.close()
+
+
+def test_bases_of_black_hole_parameter_sets(lib, orc):
+    """Black-hole pairs with their 11-row sets in a tidal run (rows 11, 12
+    zero): in every basis the left-out rows stay exactly zero and the kept
+    block equals the oracle's transform of the 13-row matrix restricted the
+    same way (the tidal rows the eta row would pick up are zero)."""
+    full = synth.mixed1e4(n=200)
+    idx = np.flatnonzero(full.meta["kind"] == 0)[:5]
+    wl = full.subset(idx).with_npts(800)
+    assert np.all(wl.par_mask == synth.MASK_BBH)
+    F = orc.fisher(wl)["fisher"]
+    assert np.all(F[11:] == 0) and np.all(F[:, 11:] == 0)
+    dw = lib.DeviceWorkload(wl)
+    Ft = torch.as_tensor(F, device="cuda")
+    for bits, names in NAMES.items():
+        G = lib.fisher_basis(Ft, dw, basis=names).cpu().numpy()
+        assert np.all(G[11:] == 0) and np.all(G[:, 11:] == 0), names
+        ref = orc.fisher_basis(F, wl.par, bits)
+        d = np.sqrt(np.einsum("iie->ie", ref[:11, :11]))
+        err = np.abs(G[:11, :11] - ref[:11, :11]) / (d[:, None, :] * d[None, :, :])
+        assert err.max() < 1e-12, (names, err.max())

@@ -48,6 +48,7 @@ def load():
         lib.orc_waveform.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_int, _D, _D, _D,
                                      _I, ctypes.c_int, ctypes.c_int, _L, ctypes.c_int64, _D]
         lib.orc_waveform_deriv.argtypes = lib.orc_waveform.argtypes
+        lib.orc_set_explicit_grid.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_fisher_tangent.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_int, _D,
                                            _D, _D, _I, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int, ctypes.c_int, _D, _D]
@@ -176,6 +177,28 @@ def strain_plain(par13, sites, f, flags, tc_s=0.0, dt=0.0):
     return out[..., 0] + 1j * out[..., 1]
 
 
+class _grid:
+    """While active, the workload-level drivers use wl.grid_f (explicit
+    frequencies, trapezoid weights from their differences) in place of the
+    log descriptors."""
+
+    def __init__(self, wl):
+        g = getattr(wl, "grid_f", None)
+        self.f = None if g is None else np.ascontiguousarray(g, dtype=np.float64)
+        self.off = None if g is None else np.ascontiguousarray(wl.grid_offsets(), dtype=np.int64)
+
+    def __enter__(self):
+        if self.f is not None:
+            load().orc_set_explicit_grid(self.off.ctypes.data_as(ctypes.c_void_p),
+                                         self.f.ctypes.data_as(ctypes.c_void_p))
+        return self
+
+    def __exit__(self, *exc):
+        if self.f is not None:
+            load().orc_set_explicit_grid(None, None)
+        return False
+
+
 def restrict_rows(F, par_mask):
     """Each event's Fisher matrix over its own parameter set: in F[P][P][N]
     (in place), the rows and columns of parameters outside event e's set
@@ -210,9 +233,10 @@ def fisher(wl, want_fisher=True, per_ifo=False, nthreads=0):
     Fi = np.zeros((ni, P, P, n)) if (want_fisher and per_ifo) else None
     act = getattr(wl, "active", None)
     act = None if act is None else np.ascontiguousarray(act, dtype=np.uint8)
-    load().orc_fisher(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
-                      npts.ctypes.data_as(_I), None if act is None else act.ctypes.data_as(ctypes.c_void_p),
-                      wl.flags, int(nthreads), _p(snr), _p(snr_ifo), _p(F), _p(Fi))
+    with _grid(wl):
+        load().orc_fisher(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
+                          npts.ctypes.data_as(_I), None if act is None else act.ctypes.data_as(ctypes.c_void_p),
+                          wl.flags, int(nthreads), _p(snr), _p(snr_ifo), _p(F), _p(Fi))
     pm = getattr(wl, "par_mask", None)
     if pm is not None and want_fisher:
         restrict_rows(F, pm)
@@ -245,9 +269,10 @@ def waveform(wl, offsets=None, total=None, nthreads=0):
     fmax = None if wl.fmax is None else _f64(wl.fmax)
     tc = None if wl.tc_s is None else _f64(wl.tc_s)
     h = np.zeros((ni, total, 2))
-    load().orc_waveform(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
-                        npts.ctypes.data_as(_I), wl.flags, int(nthreads),
-                        offsets.ctypes.data_as(_L), int(total), _p(h))
+    with _grid(wl):
+        load().orc_waveform(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
+                            npts.ctypes.data_as(_I), wl.flags, int(nthreads),
+                            offsets.ctypes.data_as(_L), int(total), _p(h))
     return h[..., 0] + 1j * h[..., 1]
 
 
@@ -271,9 +296,10 @@ def waveform_derivs(wl, offsets=None, total=None, nthreads=0):
     fmax = None if wl.fmax is None else _f64(wl.fmax)
     tc = None if wl.tc_s is None else _f64(wl.tc_s)
     dh = np.zeros((P, ni, total, 2))
-    load().orc_waveform_deriv(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
-                              npts.ctypes.data_as(_I), wl.flags, int(nthreads),
-                              offsets.ctypes.data_as(_L), int(total), _p(dh))
+    with _grid(wl):
+        load().orc_waveform_deriv(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
+                                  npts.ctypes.data_as(_I), wl.flags, int(nthreads),
+                                  offsets.ctypes.data_as(_L), int(total), _p(dh))
     out = dh[..., 0] + 1j * dh[..., 1]
     pm = getattr(wl, "par_mask", None)
     if pm is not None:
@@ -301,9 +327,10 @@ def fisher_tangent(wl, site, which, nthreads=0):
     F = np.zeros((2, P, P, n))
     act = getattr(wl, "active", None)
     act = None if act is None else np.ascontiguousarray(act, dtype=np.uint8)
-    load().orc_fisher_tangent(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
-                              npts.ctypes.data_as(_I), None if act is None else act.ctypes.data_as(ctypes.c_void_p),
-                              wl.flags, int(nthreads), int(site), int(which), _p(snr2), _p(F))
+    with _grid(wl):
+        load().orc_fisher_tangent(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
+                                  npts.ctypes.data_as(_I), None if act is None else act.ctypes.data_as(ctypes.c_void_p),
+                                  wl.flags, int(nthreads), int(site), int(which), _p(snr2), _p(F))
     pm = getattr(wl, "par_mask", None)
     if pm is not None:
         restrict_rows(F[0], pm)

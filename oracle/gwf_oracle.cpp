@@ -385,6 +385,28 @@ inline void make_grid(double fmin, double fmax, int n, std::vector<double>& f, s
   }
 }
 
+// An explicit grid (the frequencies themselves, event e's at off[e] ..
+// off[e] + npts[e] - 1 of f) in place of the log descriptors, for the
+// workload-level drivers below; set by orc_set_explicit_grid, NULL = none.
+static const int64_t* g_grid_off = nullptr;
+static const double* g_grid_f = nullptr;
+
+// Event e's grid and trapezoid weights: the explicit frequencies if set,
+// else the log grid from fmin to fhi.
+inline void event_grid(int64_t e, double fmin, double fhi, int n, std::vector<double>& f,
+                       std::vector<double>& w) {
+  if (!g_grid_f || e < 0) {
+    make_grid(fmin, fhi, n, f, w);
+    return;
+  }
+  f.assign(g_grid_f + g_grid_off[e], g_grid_f + g_grid_off[e] + n);
+  w.assign(n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    double hi = f[k < n - 1 ? k + 1 : k], lo = f[k > 0 ? k - 1 : k];
+    w[k] = 0.5 * (hi - lo);
+  }
+}
+
 // ----------------------------------------------------- per-event sums
 template <class S>
 Source<S> make_source(const double* par, double tc_s) {
@@ -414,12 +436,12 @@ S& slot(Source<S>& s, int i) {
 template <int P>
 void fisher_event(const double* par, double tc_s, const std::vector<Ifo<double>>& ifos,
                   double fmin, double fmax, int n, int flags,
-                  double* snr2_ifo, double* F_ifo /* [n_ifo][P][P] */) {
+                  double* snr2_ifo, double* F_ifo /* [n_ifo][P][P] */, int64_t e = -1) {
   using S = Dual<double, P>;
   Source<S> s = make_source<S>(par, tc_s);
   for (int i = 0; i < P; ++i) slot(s, i).d[i] = 1.0;
   std::vector<double> f, w;
-  make_grid(fmin, fmax, n, f, w);
+  event_grid(e, fmin, fmax, n, f, w);
   const int nifo = (int)ifos.size();
   for (int d = 0; d < nifo; ++d) {
     NeumaierSum snr;
@@ -454,12 +476,12 @@ using D1 = Dual<double, 1>;
 template <int P>
 void fisher_event_tangent(const double* par, double tc_s, const std::vector<Ifo<D1>>& ifos,
                           const std::vector<char>& on, double fmin, double fmax, int n, int flags,
-                          double* snr2 /* [2] */, double* F /* [2][P][P] */) {
+                          double* snr2 /* [2] */, double* F /* [2][P][P] */, int64_t e = -1) {
   using S = Dual<D1, P>;
   Source<S> s = make_source<S>(par, tc_s);
   for (int i = 0; i < P; ++i) slot(s, i).d[i] = D1(1.0);
   std::vector<double> f, w;
-  make_grid(fmin, fmax, n, f, w);
+  event_grid(e, fmin, fmax, n, f, w);
   NeumaierSum sv, st;
   std::vector<NeumaierSum> Gv(P * P), Gt(P * P);
   for (size_t d = 0; d < ifos.size(); ++d)
@@ -485,10 +507,10 @@ void fisher_event_tangent(const double* par, double tc_s, const std::vector<Ifo<
 }
 
 void snr_event(const double* par, double tc_s, const std::vector<Ifo<double>>& ifos, double fmin,
-               double fmax, int n, int flags, double* snr2_ifo) {
+               double fmax, int n, int flags, double* snr2_ifo, int64_t e = -1) {
   Source<double> s = make_source<double>(par, tc_s);
   std::vector<double> f, w;
-  make_grid(fmin, fmax, n, f, w);
+  event_grid(e, fmin, fmax, n, f, w);
   for (size_t d = 0; d < ifos.size(); ++d) {
     NeumaierSum snr;
     for (int k = 0; k < n; ++k) {
@@ -524,7 +546,7 @@ static void waveform_deriv_events(int64_t n, const double* par, int64_t ld, cons
     Source<S> s = make_source<S>(p, tc_s ? tc_s[e] : 0.0);
     for (int j = 0; j < P; ++j) slot(s, j).d[j] = 1.0;
     std::vector<double> f, w;
-    make_grid(fmin[e], fhi, npts[e], f, w);
+    event_grid(e, fmin[e], fhi, npts[e], f, w);
     for (int d = 0; d < nifo; ++d)
       for (int k = 0; k < npts[e]; ++k) {
         S hr, hi;
@@ -665,6 +687,12 @@ int orc_strain_plain(const double* par, double tc_s, double dt, int n_site, cons
 // (the detector strain of sec. 3.1 on the grids of sec. 2.2), written to
 // h[((i * total) + offsets[e] + k) * 2 + {0,1}] for interferometer i, grid
 // point k (offsets[n] are the events' first columns).  fmax NULL means each grid ends at the event's cut frequency.
+int orc_set_explicit_grid(const int64_t* off, const double* f) {
+  g_grid_off = off;
+  g_grid_f = f;
+  return 0;
+}
+
 int orc_waveform(int64_t n, const double* par, int64_t ld, const double* tc_s, int n_site,
                  const double* sites, const double* fmin, const double* fmax, const int32_t* npts,
                  int flags, int nthreads, const int64_t* offsets, int64_t total, double* h) {
@@ -680,7 +708,7 @@ int orc_waveform(int64_t n, const double* par, int64_t ld, const double* tc_s, i
     double fhi = fmax ? fmax[e] : cut_frequency(p[0], p[1]);
     Source<double> s = make_source<double>(p, tc_s ? tc_s[e] : 0.0);
     std::vector<double> f, w;
-    make_grid(fmin[e], fhi, npts[e], f, w);
+    event_grid(e, fmin[e], fhi, npts[e], f, w);
     for (int d = 0; d < nifo; ++d)
       for (int k = 0; k < npts[e]; ++k) {
         double* o = h + ((int64_t)d * total + offsets[e] + k) * 2;
@@ -743,8 +771,8 @@ int orc_fisher_tangent(int64_t n, const double* par, int64_t ld, const double* t
     std::vector<char> on(ifos.size(), 1);
     if (active)
       for (size_t d = 0; d < ifos.size(); ++d) on[d] = active[(int64_t)d * n + e] != 0;
-    if (P == 13) fisher_event_tangent<13>(p, tcs, ifos, on, fmin[e], fhi, npts[e], flags, s2, F.data());
-    else fisher_event_tangent<11>(p, tcs, ifos, on, fmin[e], fhi, npts[e], flags, s2, F.data());
+    if (P == 13) fisher_event_tangent<13>(p, tcs, ifos, on, fmin[e], fhi, npts[e], flags, s2, F.data(), e);
+    else fisher_event_tangent<11>(p, tcs, ifos, on, fmin[e], fhi, npts[e], flags, s2, F.data(), e);
     snr2[e] = s2[0];
     snr2[n + e] = s2[1];
     for (int t = 0; t < 2; ++t)
@@ -779,10 +807,10 @@ int orc_fisher(int64_t n, const double* par, int64_t ld, const double* tc_s, int
     std::vector<double> s2(nifo), F;
     if (fisher || fisher_ifo) {
       F.assign((size_t)nifo * P * P, 0.0);
-      if (P == 13) fisher_event<13>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data(), F.data());
-      else fisher_event<11>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data(), F.data());
+      if (P == 13) fisher_event<13>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data(), F.data(), e);
+      else fisher_event<11>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data(), F.data(), e);
     } else {
-      snr_event(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data());
+      snr_event(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data(), e);
     }
     if (active)
       for (int d = 0; d < nifo; ++d)

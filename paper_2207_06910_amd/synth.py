@@ -93,6 +93,8 @@ class Workload:
     meta: dict = field(default_factory=dict)
     active: np.ndarray | None = None   # uint8 [n_ifo][N] or None: interferometers on (duty factor)
     par_mask: np.ndarray | None = None  # uint32 [N] or None: each event's Fisher rows (bit r: row r)
+    grid_f: np.ndarray | None = None    # float64 [sum npts] or None: explicit grids, event e's
+                                        # frequencies at its exclusive prefix sum of npts
 
     @property
     def n(self) -> int:
@@ -112,7 +114,9 @@ class Workload:
                         {k: (v[idx] if isinstance(v, np.ndarray) and v.shape[:1] == (self.n,) else v)
                          for k, v in self.meta.items()},
                         None if self.active is None else np.ascontiguousarray(self.active[:, idx]),
-                        None if self.par_mask is None else self.par_mask[idx].copy())
+                        None if self.par_mask is None else self.par_mask[idx].copy(),
+                        None if self.grid_f is None else np.concatenate(
+                            [self.event_grid(int(e)) for e in idx]))
 
     def with_duty_factor(self, duty, seed: int) -> "Workload":
         """A copy whose interferometers are each on for an event with
@@ -138,9 +142,29 @@ class Workload:
         w.par_mask = population_masks(self.meta["kind"], self.npar)
         return w
 
+    def grid_offsets(self) -> np.ndarray:
+        """int64 [N]: first column of each event's explicit grid in grid_f."""
+        return np.concatenate([[0], np.cumsum(self.npts, dtype=np.int64)[:-1]])
+
+    def event_grid(self, e: int) -> np.ndarray:
+        o = int(self.grid_offsets()[e])
+        return self.grid_f[o:o + int(self.npts[e])]
+
+    def with_grid_f(self, freqs) -> "Workload":
+        """A copy on explicit grids: freqs is a list of N increasing float64
+        arrays (event e's frequencies, at least two each); npts follows."""
+        w = self.subset(np.arange(self.n))
+        w.name = self.name + "[explicit grids]"
+        fs = [np.ascontiguousarray(f, dtype=np.float64) for f in freqs]
+        assert len(fs) == self.n and all(len(f) >= 2 for f in fs)
+        w.npts = np.array([len(f) for f in fs], dtype=np.int32)
+        w.grid_f = np.concatenate(fs)
+        return w
+
     def with_npts(self, n: int) -> "Workload":
         w = self.subset(np.arange(self.n))
         w.npts = np.full(self.n, n, dtype=np.int32)
+        w.grid_f = None
         return w
 
     def site_array(self) -> np.ndarray:

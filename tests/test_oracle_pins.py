@@ -897,3 +897,29 @@ def test_strain_derivatives_rebuild_the_fisher(orc):
         for e in range(wl.n):
             gap[offs[e]:offs[e] + npts[e]] = False
         assert np.all(dh[:, :, gap] == 0)
+
+
+# ------------------------------------------------------------ explicit grids
+def test_explicit_grids(orc):
+    """Explicit frequency grids: fed the log grid's own frequencies they
+    reproduce the descriptor results (SNR, Fisher, strain); on linear grids
+    the trapezoid SNR converges to the log-grid value at second order (the
+    error quarters when the number of points doubles)."""
+    wl = synth.bns1e4(n=3).with_npts(400)
+    freqs = [orc.grid(wl.fmin[e], orc.cut_frequency(wl.par[0, e], wl.par[1, e]), int(wl.npts[e]))[0]
+             for e in range(wl.n)]
+    we = wl.with_grid_f(freqs)
+    a, b = orc.fisher(wl), orc.fisher(we)
+    np.testing.assert_array_equal(a["snr"], b["snr"])
+    np.testing.assert_array_equal(a["fisher"], b["fisher"])
+    np.testing.assert_array_equal(orc.waveform(wl), orc.waveform(we))
+    w1 = synth.bbh100().subset([0, 1])
+    snr = []
+    for n in (1000, 2000, 4000, 8000):
+        lin = [np.linspace(w1.fmin[e], orc.cut_frequency(w1.par[0, e], w1.par[1, e]), n) for e in range(w1.n)]
+        snr.append(orc.fisher(w1.with_grid_f(lin), want_fisher=False)["snr"])
+    d = [snr[i] - snr[i + 1] for i in range(3)]          # successive differences
+    r1, r2 = d[0] / d[1], d[1] / d[2]
+    assert np.all((r1 > 3.5) & (r1 < 4.5) & (r2 > 3.5) & (r2 < 4.5)), (d, r1, r2)
+    ref = orc.fisher(w1.with_npts(20000), want_fisher=False)["snr"]
+    np.testing.assert_allclose(snr[-1], ref, rtol=1e-8)

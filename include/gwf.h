@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define GWF_VERSION 4
+#define GWF_VERSION 5
 
 /* ------------------------------------------------------------- statuses */
 typedef int32_t gwf_status;
@@ -164,17 +164,26 @@ typedef struct gwf_network {
 } gwf_network;
 
 /* ----------------------------------------------------------------- grids */
-enum { GWF_GRID_LOG = 0 };
+enum { GWF_GRID_LOG = 0, GWF_GRID_EXPLICIT = 1 };
 
 /* Per-event log-spaced grid (sec. 2.2: geomspace from fmin to fmax):
  * f_k = fmin exp(k D), D = ln(fmax/fmin)/(n-1), k = 0..n-1, trapezoid
  * weights.  fmax == NULL means every grid ends at the event's cut frequency
  * 1/(6^{3/2} pi G M/c^3) (twice the ISCO orbital frequency, sec. 2.2). */
+/* GWF_GRID_EXPLICIT: the frequencies themselves, event e's npts[e] values
+ * at f[off[e]] .. f[off[e] + npts[e] - 1] (increasing and positive: the
+ * first and last are checked, GWF_EV_INVALID_PARAM otherwise), with the
+ * trapezoid weights of their differences; fmin and fmax are not read and
+ * no cut frequency is applied.  Accepted by gwf_snr, gwf_fisher,
+ * gwf_fisher_ifo, gwf_waveform and gwf_waveform_deriv; plans and the
+ * adjoint return GWF_E_UNSUPPORTED (they generate log grids in registers). */
 typedef struct gwf_grid {
-  int32_t kind;            /* GWF_GRID_LOG                     */
-  const double* fmin;      /* device [n], Hz                   */
-  const double* fmax;      /* device [n] or NULL               */
+  int32_t kind;            /* GWF_GRID_LOG or GWF_GRID_EXPLICIT */
+  const double* fmin;      /* device [n], Hz (log)             */
+  const double* fmax;      /* device [n] or NULL (log)         */
   const int32_t* npts;     /* device [n], 2 <= npts <= 2^30    */
+  const int64_t* off;      /* device [n] (explicit)            */
+  const double* f;         /* device, Hz (explicit)            */
 } gwf_grid;
 
 /* -------------------------------------------------------------- calls */

@@ -38,7 +38,10 @@ class Network(ctypes.Structure):
 
 class Grid(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("fmin", ctypes.c_void_p), ("fmax", ctypes.c_void_p),
-                ("npts", ctypes.c_void_p)]
+                ("npts", ctypes.c_void_p), ("off", ctypes.c_void_p), ("f", ctypes.c_void_p)]
+
+
+GRID_LOG, GRID_EXPLICIT = 0, 1
 
 
 class PlanOptions(ctypes.Structure):
@@ -187,6 +190,11 @@ class DeviceWorkload:
         act = getattr(wl, "active", None)
         self.active = None if act is None else torch.as_tensor(
             np.ascontiguousarray(act, dtype=np.uint8), device=device)
+        gf = getattr(wl, "grid_f", None)
+        self.grid_f = None if gf is None else torch.as_tensor(
+            np.ascontiguousarray(gf, dtype=np.float64), device=device)
+        self.grid_off = None if gf is None else torch.as_tensor(
+            np.ascontiguousarray(wl.grid_offsets(), dtype=np.int64), device=device)
         pm = getattr(wl, "par_mask", None)
         self.par_mask = None if pm is None else torch.as_tensor(
             np.ascontiguousarray(pm, dtype=np.uint32).view(np.int32), device=device)
@@ -207,8 +215,12 @@ class DeviceWorkload:
                     None if self.active is None else self.active.data_ptr(),
                     None if self.par_mask is None else self.par_mask.data_ptr())
         net, keep = network(self.sites)
-        grid = Grid(0, self.fmin.data_ptr(), None if self.fmax is None else self.fmax.data_ptr(),
-                    self.npts.data_ptr())
+        if self.grid_f is None:
+            grid = Grid(GRID_LOG, self.fmin.data_ptr(), None if self.fmax is None else self.fmax.data_ptr(),
+                        self.npts.data_ptr(), None, None)
+        else:
+            grid = Grid(GRID_EXPLICIT, None, None, self.npts.data_ptr(), self.grid_off.data_ptr(),
+                        self.grid_f.data_ptr())
         return ev, net, grid, keep
 
 

@@ -76,11 +76,24 @@ gwf_status api_check_common(const gwf_events* ev, const gwf_grid* grid, uint32_t
   if (ev->n > 0x7fffffffLL) return api_fail(GWF_E_INVALID_ARG, "n=%lld exceeds 2^31-1", (long long)ev->n);
   if (ev->ld < ev->n) return api_fail(GWF_E_INVALID_ARG, "ld=%lld < n", (long long)ev->ld);
   if (!ev->par) return api_fail(GWF_E_INVALID_ARG, "par is NULL");
-  if (grid->kind != GWF_GRID_LOG) return api_fail(GWF_E_UNSUPPORTED, "grid kind %d", grid->kind);
-  if (!grid->fmin || !grid->npts) return api_fail(GWF_E_INVALID_ARG, "grid fmin or npts is NULL");
+  if (grid->kind == GWF_GRID_LOG) {
+    if (!grid->fmin || !grid->npts) return api_fail(GWF_E_INVALID_ARG, "grid fmin or npts is NULL");
+  } else if (grid->kind == GWF_GRID_EXPLICIT) {
+    if (!grid->off || !grid->f || !grid->npts)
+      return api_fail(GWF_E_INVALID_ARG, "explicit grid off, f or npts is NULL");
+  } else {
+    return api_fail(GWF_E_UNSUPPORTED, "grid kind %d", grid->kind);
+  }
   if (flags & ~(uint32_t)(GWF_EARTH_ROT | GWF_TIDAL | GWF_MIXED))
     return api_fail(GWF_E_INVALID_ARG, "unknown flag bits 0x%x", flags);
   return GWF_OK;
+}
+
+// The explicit grid's offsets and frequencies, or NULLs for a log grid.
+inline void api_explicit_grid(const gwf_grid* grid, const int64_t*& off, const double*& f) {
+  const bool ex = grid->kind == GWF_GRID_EXPLICIT;
+  off = ex ? grid->off : nullptr;
+  f = ex ? grid->f : nullptr;
 }
 
 extern "C" {
@@ -105,6 +118,7 @@ gwf_status gwf_snr(const gwf_events* ev, const gwf_network* net, const gwf_grid*
   if ((st = api_pack_network(net, a.net))) return st;
   a.par = ev->par; a.ld = ev->ld; a.n = ev->n;
   a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
+  api_explicit_grid(grid, a.goff, a.gf);
   a.tidal = (flags & GWF_TIDAL) ? 1 : 0;
   a.active = ev->active;
   a.snr = snr; a.snr_ifo = snr_ifo; a.status = status;
@@ -125,6 +139,7 @@ gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_gr
   if ((st = api_pack_network(net, a.net))) return st;
   a.par = ev->par; a.ld = ev->ld; a.n = ev->n;
   a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
+  api_explicit_grid(grid, a.goff, a.gf);
   a.snr_th = snr_th;
   a.active = ev->active;
   a.par_mask = ev->par_mask;
@@ -136,6 +151,7 @@ gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_gr
     gwf::SnrArgs b{};
     b.net = a.net; b.par = a.par; b.ld = a.ld; b.n = a.n;
     b.fmin = a.fmin; b.fmax = a.fmax; b.npts = a.npts; b.tidal = tidal; b.active = a.active;
+    b.goff = a.goff; b.gf = a.gf;
     b.snr = snr; b.snr_ifo = snr_ifo; b.status = nullptr;
     hipError_t err = gwf::launch_snr(b, rot, s);
     if (err != hipSuccess) return api_hip_fail(err, "snr kernel launch");
@@ -156,6 +172,7 @@ gwf_status gwf_fisher_ifo(const gwf_events* ev, const gwf_network* net, const gw
   if ((st = api_pack_network(net, a.net))) return st;
   a.par = ev->par; a.ld = ev->ld; a.n = ev->n;
   a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
+  api_explicit_grid(grid, a.goff, a.gf);
   a.active = ev->active;
   a.par_mask = ev->par_mask;
   a.snr = nullptr; a.status = status;
@@ -181,6 +198,7 @@ gwf_status gwf_waveform(const gwf_events* ev, const gwf_network* net, const gwf_
   if ((st = api_pack_network(net, a.net))) return st;
   a.par = ev->par; a.ld = ev->ld; a.n = ev->n; a.tc_s = ev->tc_s;
   a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
+  api_explicit_grid(grid, a.goff, a.gf);
   a.offsets = offsets; a.total = total; a.h = h; a.status = status;
   hipError_t err = gwf::launch_waveform(a, (flags & GWF_TIDAL) != 0, (flags & GWF_EARTH_ROT) != 0,
                                         (flags & GWF_MIXED) != 0, (hipStream_t)stream);
@@ -200,6 +218,7 @@ gwf_status gwf_waveform_deriv(const gwf_events* ev, const gwf_network* net, cons
   if ((st = api_pack_network(net, a.net))) return st;
   a.par = ev->par; a.ld = ev->ld; a.n = ev->n; a.tc_s = ev->tc_s;
   a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
+  api_explicit_grid(grid, a.goff, a.gf);
   a.offsets = offsets; a.total = total; a.dh = dh; a.status = status; a.par_mask = ev->par_mask;
   hipError_t err = gwf::launch_waveform_deriv(a, (flags & GWF_TIDAL) != 0, (flags & GWF_EARTH_ROT) != 0,
                                               (hipStream_t)stream);
@@ -214,6 +233,7 @@ gwf_status gwf_fisher_adjoint(const gwf_events* ev, const gwf_network* net, cons
   gwf_status st = api_check_common(ev, grid, flags);
   if (st) return st;
   if (flags & GWF_MIXED) return api_fail(GWF_E_UNSUPPORTED, "the adjoint has no mixed form");
+  if (grid->kind == GWF_GRID_EXPLICIT) return api_fail(GWF_E_UNSUPPORTED, "the adjoint needs log grids");
   if (!gbar || !grad_event || !grad) return api_fail(GWF_E_INVALID_ARG, "gbar, grad_event and grad are required");
   if (!std::isfinite(w_snr) || !std::isfinite(w_fisher))
     return api_fail(GWF_E_INVALID_ARG, "w_snr and w_fisher must be finite");

@@ -30,7 +30,7 @@ namespace gwf {
 // latency of the LDS constant reads and of the transcendental sequences.
 // (The P = 11 instantiation keeps the one-wavefront budget: under the
 // two-wavefront cap it spills.)
-template <bool TIDAL, bool ROT>
+template <bool TIDAL, bool ROT, bool EXPL>
 __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(FisherArgs a) {
   using Dm = FisherDims<TIDAL>;
   constexpr int P = Dm::P, NPI = Dm::NPI, NACC = Dm::NACC;
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(Fis
   double p[13];
   load_par(a.par, a.ld, e, TIDAL, p);
   if (tid == 0) {
-    event_setup(p, a.fmin[e], a.fmax ? a.fmax[e] : 0.0, a.npts[e], flags, ec);
+    event_setup_grid(p, a.fmin, a.fmax, a.npts, a.goff, a.gf, e, flags, ec);
     int32_t sk = ec.status;
     if (!sk && a.snr_pre && !(a.snr_pre[e] > a.snr_th)) sk = kEvSkipped;
     skip = sk;
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(Fis
   __syncthreads();
 
   double t = 0.0;
-  fisher_sums<TIDAL, ROT, false, false>(ec, sc, n_site, 0, ec.n, L, &t);
+  fisher_sums<TIDAL, ROT, false, false, EXPL>(ec, sc, n_site, 0, ec.n, L, &t);
   if (tid < NACC) {
     int r, c;
     slot_position(tid, NPI, r, c);
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(Fis
 
 // SNR only, with the SNR of every interferometer.  Same grid, weights and
 // patterns as the Fisher kernel; no derivatives.
-template <bool ROT>
+template <bool ROT, bool EXPL>
 __global__ __launch_bounds__(kBlock) void snr_kernel(SnrArgs a) {
   constexpr uint32_t flags = ROT ? kFlagRot : 0u;
   __shared__ EventC ec;
@@ -99,7 +99,8 @@ __global__ __launch_bounds__(kBlock) void snr_kernel(SnrArgs a) {
   const int n_site = a.net.n_site;
   double p[13];
   load_par(a.par, a.ld, e, a.tidal, p);
-  if (tid == 0) event_setup(p, a.fmin[e], a.fmax ? a.fmax[e] : 0.0, a.npts[e], flags | (a.tidal ? kFlagTidal : 0u), ec);
+  if (tid == 0)
+    event_setup_grid(p, a.fmin, a.fmax, a.npts, a.goff, a.gf, e, flags | (a.tidal ? kFlagTidal : 0u), ec);
   __syncthreads();
   if (ec.status) {
     if (tid == 0) {
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void snr_kernel(SnrArgs a) {
   for (int k = tid; k < ec.n; k += kBlock) {
     __asm__ volatile("" ::: "memory");
     Point q;
-    point_setup<false>(ec, k, false, ROT, q);
+    point_setup<false, EXPL>(ec, k, false, ROT, q);
 #pragma unroll
     for (int s = 0; s < kMaxSites; ++s) {
       if (s < n_site) {
@@ -174,19 +175,31 @@ __global__ __launch_bounds__(kBlock) void snr_kernel(SnrArgs a) {
   }
 }
 
+template <bool EXPL>
+void launch_fisher_t(const FisherArgs& a, bool tidal, bool rot, dim3 grid, dim3 block, hipStream_t stream) {
+  if (tidal && rot) hipLaunchKernelGGL((fisher_kernel<true, true, EXPL>), grid, block, 0, stream, a);
+  else if (tidal) hipLaunchKernelGGL((fisher_kernel<true, false, EXPL>), grid, block, 0, stream, a);
+  else if (rot) hipLaunchKernelGGL((fisher_kernel<false, true, EXPL>), grid, block, 0, stream, a);
+  else hipLaunchKernelGGL((fisher_kernel<false, false, EXPL>), grid, block, 0, stream, a);
+}
+
+// An explicit grid (a.gf set) selects the instantiations that read it.
 hipError_t launch_fisher(const FisherArgs& a, bool tidal, bool rot, hipStream_t stream) {
   dim3 grid((unsigned)a.n), block(kBlock);
-  if (tidal && rot) hipLaunchKernelGGL((fisher_kernel<true, true>), grid, block, 0, stream, a);
-  else if (tidal) hipLaunchKernelGGL((fisher_kernel<true, false>), grid, block, 0, stream, a);
-  else if (rot) hipLaunchKernelGGL((fisher_kernel<false, true>), grid, block, 0, stream, a);
-  else hipLaunchKernelGGL((fisher_kernel<false, false>), grid, block, 0, stream, a);
+  if (a.gf) launch_fisher_t<true>(a, tidal, rot, grid, block, stream);
+  else launch_fisher_t<false>(a, tidal, rot, grid, block, stream);
   return hipGetLastError();
 }
 
 hipError_t launch_snr(const SnrArgs& a, bool rot, hipStream_t stream) {
   dim3 grid((unsigned)a.n), block(kBlock);
-  if (rot) hipLaunchKernelGGL((snr_kernel<true>), grid, block, 0, stream, a);
-  else hipLaunchKernelGGL((snr_kernel<false>), grid, block, 0, stream, a);
+  if (a.gf) {
+    if (rot) hipLaunchKernelGGL((snr_kernel<true, true>), grid, block, 0, stream, a);
+    else hipLaunchKernelGGL((snr_kernel<false, true>), grid, block, 0, stream, a);
+  } else {
+    if (rot) hipLaunchKernelGGL((snr_kernel<true, false>), grid, block, 0, stream, a);
+    else hipLaunchKernelGGL((snr_kernel<false, false>), grid, block, 0, stream, a);
+  }
   return hipGetLastError();
 }
 

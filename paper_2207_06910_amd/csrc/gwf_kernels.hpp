@@ -11,6 +11,8 @@ struct FisherArgs {
   const double* fmin;
   const double* fmax;       // NULL: cut frequency
   const int32_t* npts;
+  const int64_t* goff;      // explicit grid: [n] first frequency of each event in gf, or NULL (log grid)
+  const double* gf;         // explicit grid frequencies, or NULL
   const uint8_t* active;    // [n_ifo][ld] or NULL: interferometers taking part (duty factor)
   const uint32_t* par_mask; // [n] or NULL: rows of each event's Fisher matrix (others 0)
   int32_t ifo_sel;          // 0: every interferometer; d + 1: interferometer d alone
@@ -28,6 +30,8 @@ struct SnrArgs {
   const double* fmin;
   const double* fmax;
   const int32_t* npts;
+  const int64_t* goff;      // explicit grid: [n] first frequency of each event in gf, or NULL (log grid)
+  const double* gf;         // explicit grid frequencies, or NULL
   const uint8_t* active;    // [n_ifo][ld] or NULL
   NetDesc net;
   int32_t tidal;
@@ -88,6 +92,8 @@ struct WaveformArgs {
   const double* fmin;
   const double* fmax;       // NULL: cut frequency
   const int32_t* npts;
+  const int64_t* goff;      // explicit grid: [n] first frequency of each event in gf, or NULL (log grid)
+  const double* gf;         // explicit grid frequencies, or NULL
   NetDesc net;
   const int64_t* offsets;   // [n]: event e writes columns [offsets[e], offsets[e] + npts[e])
   int64_t total;            // points per interferometer row of h

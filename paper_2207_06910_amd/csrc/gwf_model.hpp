@@ -86,6 +86,10 @@ enum { kTsTheta = 0, kTsMc, kTsEta };
 struct EventC {
   // grid: v_k = exp(lnv0 + k dlnv), f_k = v_k^3 / (pi M), trapezoid weights
   double lnv0, dlnv, inv_piM, piM, wint, wfirst, wlast;
+  // explicit grid: the event's frequencies (NULL on a log grid) and ln(pi M),
+  // v_k = exp((ln(pi M) + ln f_k)/3), weights (f_{k+1} - f_{k-1})/2
+  const double* fx;
+  double lnpiM;
   int32_t n;
   int32_t status;
   // amplitude: A^2 = KA v^-7 (factor 4 of the inner product included)
@@ -314,13 +318,15 @@ __host__ __device__ inline void event_setup(const double* p, double fmin, double
   const double Ms = Mc * pow(eta, -0.6) * kTsun;
   if (!(fmax > 0.0)) fmax = cut_frequency_of(Ms);
   ec.n = n;
+  ec.fx = nullptr;
   ec.status = check_event(p, tidal, fmin, fmax, n);
   if (ec.status) return;
   // grid
   const double D = log(fmax / fmin) / (double)(n - 1);
   ec.piM = kPi * Ms;
   ec.inv_piM = 1.0 / ec.piM;
-  ec.lnv0 = (log(ec.piM) + log(fmin)) / 3.0;
+  ec.lnpiM = log(ec.piM);
+  ec.lnv0 = (ec.lnpiM + log(fmin)) / 3.0;
   ec.dlnv = D / 3.0;
   ec.wint = sinh(D);                  // interior weight / f_k
   ec.wfirst = 0.5 * expm1(D);         // (f_1 - f_0)/2 / f_0
@@ -416,6 +422,24 @@ __host__ __device__ inline void event_setup(const double* p, double fmin, double
   ec.ts[kTsTheta].l6 = -om * Kt * l6;
   ec.ts[kTsMc].l6 = -om * (Kt / Mc) * (1.0 + (6 - 8) / 3.0) * l6;
   ec.ts[kTsEta].l6 = -om * Kt * (-6.0 * l6 / (5.0 * eta));
+}
+
+// event_setup on event e's grid: the log descriptors, or an explicit grid
+// (gf non-NULL; event e's npts[e] frequencies from gf + goff[e]) bounded by
+// its first and last frequency, which must be positive and increasing (the
+// event is flagged invalid otherwise, before any other frequency is read).
+__host__ __device__ inline void event_setup_grid(const double* p, const double* fmin, const double* fmax,
+                                                 const int32_t* npts, const int64_t* goff, const double* gf,
+                                                 int64_t e, uint32_t flags, EventC& ec) {
+  const int32_t n = npts[e];
+  if (gf) {
+    const double* fx = gf + goff[e];
+    const bool ok = n >= 2 && fx[0] > 0.0 && fx[n - 1] > fx[0];
+    event_setup(p, ok ? fx[0] : 0.0, ok ? fx[n - 1] : 0.0, n, flags, ec);
+    ec.fx = fx;
+  } else {
+    event_setup(p, fmin[e], fmax ? fmax[e] : 0.0, n, flags, ec);
+  }
 }
 
 // Pattern maps of one interferometer: F+ = alpha.P, Fx = beta.P.
@@ -652,20 +676,30 @@ enum PsdPow { kPsdNone = 0, kPsdF64 = 1, kPsdF32 = 2 };
 
 // PSUM: the evaluation form of the PN series (see horner7) and of the PSD's
 // power law (once per point when true, once per site otherwise).
-template <bool PSUM = true>
+// EXPL: the point of an explicit grid (ec.fx) rather than of the log grid.
+template <bool PSUM = true, bool EXPL = false>
 __host__ __device__ inline void point_setup(const EventC& ec, int32_t k, bool need_derivs, bool rot,
                                             Point& q, int psd = kPsdF64) {
-  const double L = fma((double)k, ec.dlnv, ec.lnv0);
-  const double v = exp(L);
+  double L, v, f, wf;               // wf: the trapezoid weight
+  if (EXPL) {
+    f = ec.fx[k];
+    L = (ec.lnpiM + log(f)) / 3.0;
+    v = exp(L);
+    wf = 0.5 * (ec.fx[k < ec.n - 1 ? k + 1 : k] - ec.fx[k > 0 ? k - 1 : k]);
+  } else {
+    L = fma((double)k, ec.dlnv, ec.lnv0);
+    v = exp(L);
+    f = v * v * v * ec.inv_piM;
+    double w = ec.wint;
+    if (k == 0) w = ec.wfirst;
+    if (k == ec.n - 1) w = ec.wlast;
+    wf = w * f;
+  }
   const double iv = recip(v);
   const double iv2 = iv * iv, iv4 = iv2 * iv2, iv5 = iv4 * iv, iv7 = iv5 * iv2, iv8 = iv4 * iv4;
-  const double f = v * v * v * ec.inv_piM;
-  double w = ec.wint;
-  if (k == 0) w = ec.wfirst;
-  if (k == ec.n - 1) w = ec.wlast;
   q.v = v; q.iv = iv; q.L = L; q.f = f;
   q.tf = kTwoPi * f;
-  q.w4A2 = w * f * ec.KA4 * iv7;
+  q.w4A2 = wf * ec.KA4 * iv7;
   q.vpsd = 0.0;
   if (PSUM && psd == kPsdF64) {
     q.vpsd = exp(-12.42 * L);
@@ -857,13 +891,13 @@ __host__ __device__ inline void derivative_vector(const AmpFactors& am, const Po
 // every interferometer, so the blocks they span are
 //   Gamma_{b, 8+i} += U_b c_i,   Gamma_{8+i, 8+j} += W c_i c_j,
 // which the caller accumulates (see add_phase_blocks).
-template <bool TIDAL, bool ROT, bool MIXED = false, bool PSUM = true>
+template <bool TIDAL, bool ROT, bool MIXED = false, bool PSUM = true, bool EXPL = false>
 __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* sc, int n_site,
                                                  int32_t k, double* G, double* U, double& W,
                                                  double* cph) {
   const AmpFactors am = amp_factors(ec);
   Point q;
-  point_setup<PSUM>(ec, k, true, ROT, q, MIXED ? kPsdF32 : kPsdF64);
+  point_setup<PSUM, EXPL>(ec, k, true, ROT, q, MIXED ? kPsdF32 : kPsdF64);
   W = 0.0;
 #pragma unroll
   for (int b = 0; b < 8; ++b) U[b] = 0.0;

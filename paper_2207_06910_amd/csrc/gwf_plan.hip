@@ -185,6 +185,8 @@ gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const g
   *out = nullptr;
   gwf_status st = api_check_common(ev, grid, flags);
   if (st) return st;
+  if (grid->kind == GWF_GRID_EXPLICIT)
+    return api_fail(GWF_E_UNSUPPORTED, "plans generate log grids; use gwf_fisher for explicit grids");
   gwf_plan* p = new gwf_plan();
   if ((st = api_pack_network(net, p->net))) { delete p; return st; }
   gwf_plan_options o{};

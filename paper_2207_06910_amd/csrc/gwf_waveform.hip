@@ -69,7 +69,7 @@ __device__ inline void sincos_cycles(double x, double* s, double* c) {
   }
 }
 
-template <bool ROT, bool TIDAL, bool MIXED>
+template <bool ROT, bool TIDAL, bool MIXED, bool EXPL>
 __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
   constexpr uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u);
   __shared__ EventC ec;
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
   if (tid == 0) {
     double p[13];
     for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
-    event_setup(p, a.fmin[e], a.fmax ? a.fmax[e] : 0.0, a.npts[e], flags, ec);
+    event_setup_grid(p, a.fmin, a.fmax, a.npts, a.goff, a.gf, e, flags, ec);
     // the event's columns [b, b + npts) must lie inside a row of h
     const int64_t b = a.offsets[e];
     const bool range_ok = b >= 0 && b <= a.total - (int64_t)a.npts[e];
@@ -115,14 +115,15 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
   double2* __restrict__ out = reinterpret_cast<double2*>(a.h) + base;
   const int64_t row = a.total;
   for (int k = tid; k < ec.n; k += kWBlock) {
-    const double L = fma((double)k, ec.dlnv, ec.lnv0);
+    // explicit grids: ln v = (ln(pi M) + ln f)/3 from the given frequency
+    const double L = EXPL ? (ec.lnpiM + log(ec.fx[k])) / 3.0 : fma((double)k, ec.dlnv, ec.lnv0);
     const double v = exp(L);
     const double iv = 1.0 / v;
     const double iv2 = iv * iv, iv5 = iv2 * iv2 * iv;
     VPow pw;
     vpow(v, L, pw);
     const double v2 = pw.p2;
-    const double f = v2 * v * ec.inv_piM;
+    const double f = EXPL ? ec.fx[k] : v2 * v * ec.inv_piM;
     // A(f) = A0 v^-7/2; mixed form: 2^y, y = -3.5 log2 v, with the integer
     // part of y split off exactly before the FP32 exponential
     double amp;
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
 // map.  One workgroup per event, lanes over grid points; row (a, i) of dh
 // holds parameter a at interferometer i, consecutive lanes on consecutive
 // complex values.  FP64 only.
-template <bool ROT, bool TIDAL>
+template <bool ROT, bool TIDAL, bool EXPL>
 __global__ __launch_bounds__(kWBlock) void waveform_deriv_kernel(WaveformArgs a) {
   constexpr int P = TIDAL ? 13 : 11, NPI = TIDAL ? 5 : 3;
   constexpr uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u);
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(kWBlock) void waveform_deriv_kernel(WaveformArgs a)
   if (tid == 0) {
     double p[13];
     for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
-    event_setup(p, a.fmin[e], a.fmax ? a.fmax[e] : 0.0, a.npts[e], flags, ec);
+    event_setup_grid(p, a.fmin, a.fmax, a.npts, a.goff, a.gf, e, flags, ec);
     const int64_t b = a.offsets[e];
     const bool range_ok = b >= 0 && b <= a.total - (int64_t)a.npts[e];
     int32_t st = ec.status;
@@ -229,7 +230,7 @@ __global__ __launch_bounds__(kWBlock) void waveform_deriv_kernel(WaveformArgs a)
     // reads) rather than held in registers across iterations
     asm volatile("" ::: "memory");
     Point q;
-    point_setup<true>(ec, k, true, ROT, q, kPsdNone);
+    point_setup<true, EXPL>(ec, k, true, ROT, q, kPsdNone);
     VPow pw;
     vpow(q.v, q.L, pw);
     const double iv = q.iv, iv2 = iv * iv, iv5 = iv2 * iv2 * iv;
@@ -275,28 +276,40 @@ __global__ __launch_bounds__(kWBlock) void waveform_deriv_kernel(WaveformArgs a)
 
 }  // namespace
 
-template <bool MIXED>
+template <bool MIXED, bool EXPL>
 void launch_waveform_t(const WaveformArgs& a, bool tidal, bool rot, dim3 grid, dim3 block,
                        hipStream_t stream) {
-  if (tidal && rot) hipLaunchKernelGGL((waveform_kernel<true, true, MIXED>), grid, block, 0, stream, a);
-  else if (tidal) hipLaunchKernelGGL((waveform_kernel<false, true, MIXED>), grid, block, 0, stream, a);
-  else if (rot) hipLaunchKernelGGL((waveform_kernel<true, false, MIXED>), grid, block, 0, stream, a);
-  else hipLaunchKernelGGL((waveform_kernel<false, false, MIXED>), grid, block, 0, stream, a);
+  if (tidal && rot) hipLaunchKernelGGL((waveform_kernel<true, true, MIXED, EXPL>), grid, block, 0, stream, a);
+  else if (tidal) hipLaunchKernelGGL((waveform_kernel<false, true, MIXED, EXPL>), grid, block, 0, stream, a);
+  else if (rot) hipLaunchKernelGGL((waveform_kernel<true, false, MIXED, EXPL>), grid, block, 0, stream, a);
+  else hipLaunchKernelGGL((waveform_kernel<false, false, MIXED, EXPL>), grid, block, 0, stream, a);
 }
 
+// An explicit grid (a.gf set) selects the instantiations that read it.
 hipError_t launch_waveform(const WaveformArgs& a, bool tidal, bool rot, bool mixed, hipStream_t stream) {
   dim3 grid((unsigned)a.n), block(kWBlock);
-  if (mixed) launch_waveform_t<true>(a, tidal, rot, grid, block, stream);
-  else launch_waveform_t<false>(a, tidal, rot, grid, block, stream);
+  if (a.gf) {
+    if (mixed) launch_waveform_t<true, true>(a, tidal, rot, grid, block, stream);
+    else launch_waveform_t<false, true>(a, tidal, rot, grid, block, stream);
+  } else {
+    if (mixed) launch_waveform_t<true, false>(a, tidal, rot, grid, block, stream);
+    else launch_waveform_t<false, false>(a, tidal, rot, grid, block, stream);
+  }
   return hipGetLastError();
+}
+
+template <bool EXPL>
+void launch_deriv_t(const WaveformArgs& a, bool tidal, bool rot, dim3 grid, dim3 block, hipStream_t stream) {
+  if (tidal && rot) hipLaunchKernelGGL((waveform_deriv_kernel<true, true, EXPL>), grid, block, 0, stream, a);
+  else if (tidal) hipLaunchKernelGGL((waveform_deriv_kernel<false, true, EXPL>), grid, block, 0, stream, a);
+  else if (rot) hipLaunchKernelGGL((waveform_deriv_kernel<true, false, EXPL>), grid, block, 0, stream, a);
+  else hipLaunchKernelGGL((waveform_deriv_kernel<false, false, EXPL>), grid, block, 0, stream, a);
 }
 
 hipError_t launch_waveform_deriv(const WaveformArgs& a, bool tidal, bool rot, hipStream_t stream) {
   dim3 grid((unsigned)a.n), block(kWBlock);
-  if (tidal && rot) hipLaunchKernelGGL((waveform_deriv_kernel<true, true>), grid, block, 0, stream, a);
-  else if (tidal) hipLaunchKernelGGL((waveform_deriv_kernel<false, true>), grid, block, 0, stream, a);
-  else if (rot) hipLaunchKernelGGL((waveform_deriv_kernel<true, false>), grid, block, 0, stream, a);
-  else hipLaunchKernelGGL((waveform_deriv_kernel<false, false>), grid, block, 0, stream, a);
+  if (a.gf) launch_deriv_t<true>(a, tidal, rot, grid, block, stream);
+  else launch_deriv_t<false>(a, tidal, rot, grid, block, stream);
   return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ def test_library_exports_every_declared_symbol():
     assert {"gwf_snr", "gwf_fisher", "gwf_invert"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.gwf_version() == 4
+    assert lib.gwf_version() == 5
 
 
 def test_network_interferometer_count():
@@ -81,6 +81,15 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.gwf_fisher_adjoint(B(ev), B(net), B(grid), 0, 8, None, 1.0, 1.0, None, 8, None) == 1
     assert lib.gwf_fisher_adjoint(B(ev), B(net), B(grid), 0, 8, None, float("inf"), 1.0, 8, 8, None) == 1
     assert lib.gwf_fisher_adjoint(B(ev), B(net), B(grid), 4, 8, None, 1.0, 1.0, 8, 8, None) == 2
+    # explicit grids: offsets and frequencies required; the adjoint and plans refuse them
+    gx = binding.Grid(binding.GRID_EXPLICIT, None, None, 16, None, 24)
+    assert lib.gwf_snr(B(ev), B(net), B(gx), 0, 8, None, None, None) == 1
+    gx = binding.Grid(binding.GRID_EXPLICIT, None, None, 16, 32, None)
+    assert lib.gwf_fisher(B(ev), B(net), B(gx), 0, 0.0, 8, 8, None, 8, None) == 1
+    gx = binding.Grid(binding.GRID_EXPLICIT, None, None, 16, 32, 24)
+    assert lib.gwf_fisher_adjoint(B(ev), B(net), B(gx), 0, 8, None, 1.0, 1.0, 8, 8, None) == 2
+    plan = ctypes.c_void_p()
+    assert lib.gwf_plan_create(B(ev), B(net), B(gx), 0, None, B(plan), None) == 2
     assert len(lib.gwf_last_error()) > 0
 
 

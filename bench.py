@@ -31,12 +31,12 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # profiles/bns1e4_hbm_counters.md (calibrated against a 256 MiB copy: fetch
 # x 2.000, write x 1.000).  Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
-    "items_kernel<tidal,rot,mixed>": None,
-    "items_kernel<tidal,rot>": None,
-    "fisher_kernel<tidal,rot>": None,
-    "waveform_kernel<rot,tidal>": None,
-    "waveform_kernel<rot,tidal,mixed>": None,
-    "waveform_deriv_kernel<rot,tidal>": None,
+    "items_kernel<tidal,rot,mixed>": 69.89e6,
+    "items_kernel<tidal,rot>": 72.62e6,
+    "fisher_kernel<tidal,rot>": 127.38e6,
+    "waveform_kernel<rot,tidal>": 7851.91e6,
+    "waveform_kernel<rot,tidal,mixed>": 7862.19e6,
+    "waveform_deriv_kernel<rot,tidal>": 10305.67e6,
 }
 
 # VALU instructions (wavefront instructions, SQ_INSTS_VALU) per launch of the
@@ -46,9 +46,9 @@ MEASURED_TRAFFIC = {
 # 4 x SQ_INSTS_VALU / (1024 SIMDs x 2.4 GHz x kernel time).  Set an entry to
 # None when its kernel changes.
 MEASURED_VALU_INSTS = {
-    "items_kernel<tidal,rot,mixed>": None,
-    "items_kernel<tidal,rot>": None,
-    "fisher_kernel<tidal,rot>": None,
+    "items_kernel<tidal,rot,mixed>": 1.878e9,
+    "items_kernel<tidal,rot>": 1.906e9,
+    "fisher_kernel<tidal,rot>": 2.068e9,
 }
 N_SIMD, CLOCK_HZ = 1024, 2.4e9
 

@@ -31,12 +31,12 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # profiles/bns1e4_hbm_counters.md (calibrated against a 256 MiB copy: fetch
 # x 2.000, write x 1.000).  Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
-    "items_kernel<tidal,rot,mixed>": 69.89e6,
-    "items_kernel<tidal,rot>": 72.62e6,
-    "fisher_kernel<tidal,rot>": 127.38e6,
-    "waveform_kernel<rot,tidal>": 7851.91e6,
-    "waveform_kernel<rot,tidal,mixed>": 7862.19e6,
-    "waveform_deriv_kernel<rot,tidal>": 10305.67e6,
+    "items_kernel<tidal,rot,mixed>": 58.09e6,
+    "items_kernel<tidal,rot>": 60.27e6,
+    "fisher_kernel<tidal,rot>": 108.64e6,
+    "waveform_kernel<rot,tidal>": 7852.00e6,
+    "waveform_kernel<rot,tidal,mixed>": 7863.75e6,
+    "waveform_deriv_kernel<rot,tidal>": 10305.27e6,
 }
 
 # VALU instructions (wavefront instructions, SQ_INSTS_VALU) per launch of the
@@ -46,9 +46,9 @@ MEASURED_TRAFFIC = {
 # 4 x SQ_INSTS_VALU / (1024 SIMDs x 2.4 GHz x kernel time).  Set an entry to
 # None when its kernel changes.
 MEASURED_VALU_INSTS = {
-    "items_kernel<tidal,rot,mixed>": 1.878e9,
-    "items_kernel<tidal,rot>": 1.906e9,
-    "fisher_kernel<tidal,rot>": 2.068e9,
+    "items_kernel<tidal,rot,mixed>": 1.635e9,
+    "items_kernel<tidal,rot>": 1.666e9,
+    "fisher_kernel<tidal,rot>": 1.837e9,
 }
 N_SIMD, CLOCK_HZ = 1024, 2.4e9
 
@@ -82,18 +82,23 @@ def algorithmic_flops(wl) -> float:
                             sidereal angle and its derivatives)
       100 x n_site          hour angle, pattern vectors and their
                             derivatives, delay derivatives, PSD weight
-      293 x n_eff           patterns, derivative vectors D_a, 8x8 rank-2
-                            Gram update, U_b, W (n_eff = 1 per L site, 2 per
+      217 x n_eff           patterns, derivative vectors D_a of the five
+                            rows that are not pattern combinations, their
+                            5x5 rank-2 Gram update and U_b, the pattern
+                            moments T_b and S (n_eff = 1 per L site, 2 per
                             triangle after the closed-loop reduction)
+      9                     the point's U and W of the dL, iota, psi rows
       6 + 23 n_c + 2 (8 NPI) + NPI + 2 NPI(NPI+1)/2
                             phase-only derivatives (n_c = 2, or 4 with
-                            tides; NPI = n_c + 1) and their blocks."""
+                            tides; NPI = n_c + 1) and their blocks.
+    The per-item epilogue that turns the moments into the 8x8 block (about
+    60 flops per lane per work item of up to 16384 points) is not counted."""
     n_site = len(wl.sites)
     n_eff = sum(2 if s.shape == 1 else 1 for s in wl.sites)
     tidal = bool(wl.flags & 2)
     n_c = 4 if tidal else 2
     npi = n_c + 1
-    per_point = 121 + 100 * n_site + 293 * n_eff + 6 + 23 * n_c + 16 * npi + npi + npi * (npi + 1)
+    per_point = 121 + 100 * n_site + 217 * n_eff + 9 + 6 + 23 * n_c + 16 * npi + npi + npi * (npi + 1)
     return float(per_point) * float(np.sum(wl.npts, dtype=np.int64))
 
 

@@ -4,8 +4,10 @@
 // A workgroup of kBlock lanes sums the contributions of grid points
 // [k0, k1) of one event: each lane takes points k0 + tid + kBlock*it,
 // evaluates the derivative vectors of all interferometers at that point in
-// registers and adds the 8x8 block of (Mc, eta, dL, theta, phi, iota, psi,
-// tc) to its 36 register accumulators.  The phase-only blocks are a small
+// registers and adds its share of the 8x8 block of (Mc, eta, dL, theta, phi,
+// iota, psi, tc) to its kGramAcc register accumulators (the 5x5 block of the
+// rows that are not pattern combinations, plus pattern moments; see
+// accumulate_point).  The phase-only blocks are a small
 // dense contraction over frequency, X = sum_f a_f c_f^T with
 // a_f = (U_0..U_7, W c_0..W c_{NPI-1}) and c_f = (c_0..c_{NPI-1}): every
 // iteration each wavefront stages its 64 points' a_f and c_f in LDS and
@@ -76,9 +78,9 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
   using Dm = FisherDims<TIDAL>;
   constexpr int NPI = Dm::NPI, NG = Dm::NG, NX = Dm::NX, NACC = Dm::NACC;
   const int tid = threadIdx.x;
-  double G[NG];
+  double G[kGramAcc];
 #pragma unroll
-  for (int i = 0; i < NG; ++i) G[i] = 0.0;
+  for (int i = 0; i < kGramAcc; ++i) G[i] = 0.0;
   double acc[Dm::NM];
   const int wave = tid >> 6, lane = tid & 63;
   // four-block MFMA 4x4x4 operand layout: lane 16 k + 4 q + i holds A[q][i][k]
@@ -137,9 +139,11 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
   }
 
   // ---- deterministic reduction: wavefront butterflies, then the waves in order
+  double F[NG];
+  gram_finish(ec, G, F);
 #pragma unroll
   for (int i = 0; i < NG; ++i) {
-    const double t = wave_sum(G[i]);
+    const double t = wave_sum(F[i]);
     if (lane == 0) L.red[wave][i] = t;
   }
   // lane 16 i + 4 q + j of accumulator m holds element (i, j) of tile 4 m + q:

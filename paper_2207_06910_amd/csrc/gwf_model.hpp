@@ -881,16 +881,32 @@ __host__ __device__ inline void derivative_vector(const AmpFactors& am, const Po
 }
 
 // ------------------------------------------------ one frequency point
-// Adds the contribution of grid point k of an event to G[36], the 8x8
-// upper-triangle block of (Mc, eta, dL, theta, phi, iota, psi, tc)
-// (row-major), and returns the point's phase-only quantities:
+// The rows of dL, iota and psi are fixed per-event combinations of the
+// pattern values (F+, Fx) of each interferometer:
+//   D_dL = -Q/dL,  D_iota = (dc+ F+, dcx Fx),  D_psi = (2 c+ Fx, -2 cx F+),
+// with Q = (c+ F+, cx Fx) and (re, im) pairs.  So every Fisher entry in
+// those rows is a combination of the moments
+//   T_b = sum w (F+ Dr_b, F+ Di_b, Fx Dr_b, Fx Di_b)   for the other rows b
+//   S   = sum w (F+^2, F+ Fx, Fx^2),
+// and only the 5x5 block of (Mc, eta, theta, phi, tc) needs a rank-2 update
+// per interferometer.  The accumulator G[kGramAcc] holds that block's upper
+// triangle (15, row-major), then T (4 per row, in the order above), then S;
+// gram_finish turns it into the 8x8 block.
+constexpr int kGramAcc = 15 + 20 + 3;
+constexpr int kGramRows[5] = {0, 1, 3, 4, 7};   // Mc, eta, theta, phi, tc
+
+// Adds the contribution of grid point k of an event to G[kGramAcc] (above)
+// and returns the point's phase-only quantities:
 //   U[8]   U_b = sum_i w_i Re(i Q_i D_b,i^*)
 //   W      sum_i w_i |Q_i|^2 (the SNR^2 density)
 //   c[NPI] (-1, dPsi/dchi1, dPsi/dchi2[, dPsi/dLambda1, dPsi/dLambda2]).
 // The phase-only derivative vectors are i Q c(f) with the same real c(f) at
 // every interferometer, so the blocks they span are
 //   Gamma_{b, 8+i} += U_b c_i,   Gamma_{8+i, 8+j} += W c_i c_j,
-// which the caller accumulates (see add_phase_blocks).
+// which the caller accumulates (see add_phase_blocks).  U and W of the rows
+// dL, iota, psi follow from the point's moments S as well: U_dL = 0
+// exactly, U_iota = (c+ dcx - cx dc+) S_+x, U_psi = -2 c+ cx (S_++ + S_xx),
+// W = c+^2 S_++ + cx^2 S_xx.
 template <bool TIDAL, bool ROT, bool MIXED = false, bool PSUM = true, bool EXPL = false>
 __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* sc, int n_site,
                                                  int32_t k, double* G, double* U, double& W,
@@ -898,9 +914,9 @@ __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* 
   const AmpFactors am = amp_factors(ec);
   Point q;
   point_setup<PSUM, EXPL>(ec, k, true, ROT, q, MIXED ? kPsdF32 : kPsdF64);
-  W = 0.0;
+  double UR[5], spp = 0.0, spx = 0.0, sxx = 0.0;
 #pragma unroll
-  for (int b = 0; b < 8; ++b) U[b] = 0.0;
+  for (int b = 0; b < 5; ++b) UR[b] = 0.0;
   for (int s = 0; s < n_site; ++s) {
     const SiteC& st = sc[s];
     SitePoint sp;
@@ -917,21 +933,66 @@ __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* 
       derivative_vector(am, q, ph, Fp, Fx, dot4(st.alpha[j], sp.PH), dot4(st.beta[j], sp.PH),
                         dot4(st.alpha[j], sp.Pt), dot4(st.beta[j], sp.Pt), Dr, Di);
       const double Qr = am.cplus * Fp, Qi = am.ccross * Fx;
+      const double wp = om * Fp, wx = om * Fx;
       int g = 0;
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
+      for (int a = 0; a < 5; ++a) {
+        const int r = kGramRows[a];
         const double wr = om * Dr[r], wi = om * Di[r];
 #pragma unroll
-        for (int c = r; c < 8; ++c) {
+        for (int b = a; b < 5; ++b) {
+          const int c = kGramRows[b];
           G[g] = fma(wr, Dr[c], fma(wi, Di[c], G[g]));
           ++g;
         }
-        U[r] = fma(om, fma(-Qi, Dr[r], Qr * Di[r]), U[r]);
+        G[15 + 4 * a + 0] = fma(wp, Dr[r], G[15 + 4 * a + 0]);
+        G[15 + 4 * a + 1] = fma(wp, Di[r], G[15 + 4 * a + 1]);
+        G[15 + 4 * a + 2] = fma(wx, Dr[r], G[15 + 4 * a + 2]);
+        G[15 + 4 * a + 3] = fma(wx, Di[r], G[15 + 4 * a + 3]);
+        // Re(i Q D_r^*) w = Qr (w Di_r) - Qi (w Dr_r), from the weighted row
+        UR[a] = fma(Qr, wi, fma(-Qi, wr, UR[a]));
       }
-      W = fma(om, fma(Qr, Qr, Qi * Qi), W);
+      spp = fma(wp, Fp, spp);
+      spx = fma(wp, Fx, spx);
+      sxx = fma(wx, Fx, sxx);
     }
   }
+  G[35] += spp;
+  G[36] += spx;
+  G[37] += sxx;
+#pragma unroll
+  for (int a = 0; a < 5; ++a) U[kGramRows[a]] = UR[a];
+  U[2] = 0.0;
+  U[5] = (am.cplus * am.dcx - am.ccross * am.dcp) * spx;
+  U[6] = -2.0 * am.cplus * am.ccross * (spp + sxx);
+  W = fma(am.cplus * am.cplus, spp, am.ccross * am.ccross * sxx);
   phase_only_coefficients<TIDAL, PSUM>(ec, q, cph);
+}
+
+// The 8x8 upper-triangle block of (Mc, eta, dL, theta, phi, iota, psi, tc)
+// (row-major, 36 values) from the accumulator of accumulate_point.
+__host__ __device__ inline void gram_finish(const EventC& ec, const double* G, double* F) {
+  const AmpFactors am = amp_factors(ec);
+  auto at = [](int r, int c) { return r <= c ? 8 * r - (r * (r - 1)) / 2 + (c - r)
+                                             : 8 * c - (c * (c - 1)) / 2 + (r - c); };
+  int g = 0;
+  for (int a = 0; a < 5; ++a)
+    for (int b = a; b < 5; ++b) F[at(kGramRows[a], kGramRows[b])] = G[g++];
+  for (int a = 0; a < 5; ++a) {
+    const int r = kGramRows[a];
+    const double tpr = G[15 + 4 * a], tpi = G[16 + 4 * a], txr = G[17 + 4 * a], txi = G[18 + 4 * a];
+    F[at(r, 2)] = -am.idL * fma(am.cplus, tpr, am.ccross * txi);
+    F[at(r, 5)] = fma(am.dcp, tpr, am.dcx * txi);
+    F[at(r, 6)] = 2.0 * fma(am.cplus, txr, -am.ccross * tpi);
+  }
+  const double spp = G[35], spx = G[36], sxx = G[37];
+  const double ci = am.ccross, si2 = (1.0 - ci) * (1.0 + ci);   // c+^2 - cx^2 = sin^4(iota)/4
+  F[at(2, 2)] = am.idL * am.idL * fma(am.cplus * am.cplus, spp, ci * ci * sxx);
+  F[at(2, 5)] = -am.idL * fma(am.cplus * am.dcp, spp, ci * am.dcx * sxx);
+  F[at(2, 6)] = -am.idL * 0.5 * si2 * si2 * spx;
+  F[at(5, 5)] = fma(am.dcp * am.dcp, spp, am.dcx * am.dcx * sxx);
+  F[at(5, 6)] = 2.0 * fma(am.cplus, am.dcp, -ci * am.dcx) * spx;
+  F[at(6, 6)] = 4.0 * fma(am.cplus * am.cplus, sxx, ci * ci * spp);
 }
 
 // Plain accumulation of the phase-only blocks of one point into

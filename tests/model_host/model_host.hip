@@ -22,12 +22,13 @@ static void one_event(const double* p, double fmin, double fmax, int32_t n, cons
   if (ec.status) return;
   SiteC sc[kMaxSites];
   for (int s = 0; s < nd.n_site; ++s) site_setup(p, nd.site[s], ec, sc[s]);
-  double G[36] = {0}, xy[64] = {0};
+  double Gacc[kGramAcc] = {0}, G[36], xy[64] = {0};
   for (int32_t k = 0; k < ec.n; ++k) {
     double U[8], W, c[5];
-    accumulate_point<TIDAL, ROT, MIXED>(ec, sc, nd.n_site, k, G, U, W, c);
+    accumulate_point<TIDAL, ROT, MIXED>(ec, sc, nd.n_site, k, Gacc, U, W, c);
     add_phase_blocks(NPI, U, W, c, xy, 1);
   }
+  gram_finish(ec, Gacc, G);
   for (int t = 0; t < NACC; ++t) {
     int r, c;
     slot_position(t, NPI, r, c);

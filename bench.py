@@ -31,12 +31,12 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # profiles/bns1e4_hbm_counters.md (calibrated against a 256 MiB copy: fetch
 # x 2.000, write x 1.000).  Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
-    "items_kernel<tidal,rot,mixed>": 58.09e6,
-    "items_kernel<tidal,rot>": 60.27e6,
-    "fisher_kernel<tidal,rot>": 108.64e6,
-    "waveform_kernel<rot,tidal>": 7852.00e6,
-    "waveform_kernel<rot,tidal,mixed>": 7863.75e6,
-    "waveform_deriv_kernel<rot,tidal>": 10305.27e6,
+    "items_kernel<tidal,rot,mixed>": 58.08e6,
+    "items_kernel<tidal,rot>": 60.25e6,
+    "fisher_kernel<tidal,rot>": 134.57e6,
+    "waveform_kernel<rot,tidal>": 7853.16e6,
+    "waveform_kernel<rot,tidal,mixed>": 7859.19e6,
+    "waveform_deriv_kernel<rot,tidal>": 10306.83e6,
 }
 
 # VALU instructions (wavefront instructions, SQ_INSTS_VALU) per launch of the
@@ -48,7 +48,7 @@ MEASURED_TRAFFIC = {
 MEASURED_VALU_INSTS = {
     "items_kernel<tidal,rot,mixed>": 1.635e9,
     "items_kernel<tidal,rot>": 1.666e9,
-    "fisher_kernel<tidal,rot>": 1.837e9,
+    "fisher_kernel<tidal,rot>": 1.696e9,
 }
 N_SIMD, CLOCK_HZ = 1024, 2.4e9
 

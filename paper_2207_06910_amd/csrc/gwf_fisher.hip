@@ -68,7 +68,7 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(Fis
   __syncthreads();
 
   double t = 0.0;
-  fisher_sums<TIDAL, ROT, false, false, EXPL>(ec, sc, n_site, 0, ec.n, L, &t);
+  fisher_sums<TIDAL, ROT, false, true, EXPL>(ec, sc, n_site, 0, ec.n, L, &t);
   if (tid < NACC) {
     int r, c;
     slot_position(tid, NPI, r, c);

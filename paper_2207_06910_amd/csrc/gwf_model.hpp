@@ -625,10 +625,11 @@ __host__ __device__ inline double series7(const double c[8], const VPow& w) {
   return h + c[0];
 }
 
-// The same polynomial by Horner's rule.  Kernels that re-read the per-event
-// coefficients from LDS into vector registers keep fewer values live this
-// way than with the sum of products, whose loads the compiler issues all
-// at once; kernels holding the coefficients in scalar registers use the sum.
+// The same polynomial by Horner's rule, which keeps fewer values live than
+// the sum of products (whose coefficient loads the compiler issues all at
+// once).  The SNR kernel, which re-reads the coefficients from LDS, uses it;
+// the Fisher kernels use the sum, whether their coefficients sit in scalar
+// registers or in LDS.
 __host__ __device__ inline double horner7(const double c[8], double v) {
   double h = c[7];
   for (int k = 6; k >= 0; --k) h = fma(h, v, c[k]);
@@ -735,7 +736,7 @@ __host__ __device__ inline void phase_only_coefficients(const EventC& ec, const 
       c[NPI - 2] = eval_phase_tidal(ec.ps[kPsL1], pw);
       c[NPI - 1] = eval_phase_tidal(ec.ps[kPsL2], pw);
     }
-  } else {         // the general form (fewer live values in the LDS-constant kernels)
+  } else {         // the general form (fewer live values)
     c[1] = eval_phase<false>(ec.ps[kPsChi1], pw, iv5);
     c[2] = eval_phase<false>(ec.ps[kPsChi2], pw, iv5);
     if (TIDAL) {

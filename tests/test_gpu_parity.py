@@ -239,3 +239,35 @@ def test_inversion_flags(lib):
     g = _invert_gpu(lib, F, status, cond_max=1e12)
     np.testing.assert_array_equal(g["status"], [0, 4, 2, 8, 16])
     assert np.all(np.isfinite(g["sigma"][:, 0])) and np.all(np.isnan(g["sigma"][:, 1:]))
+
+
+def test_degenerate_inclinations(lib, orc):
+    """Face-on, edge-on and face-away binaries (iota = 0, pi/2, pi, and 1e-6
+    off each).  The kernels form the Fisher rows of dL, iota and psi from
+    pattern moments whose coefficients (sin iota, cos iota and their
+    products) vanish or nearly cancel there.  Both forms match the oracle
+    element by element (normalised by sqrt(G_ii G_jj)); where the oracle's
+    diagonal entry is exactly zero (the iota row at iota = 0) the GPU's row
+    is exactly zero too."""
+    wl = synth.bns1e4(n=9).with_npts(900)
+    wl.par[5] = np.array([0.0, np.pi / 2, np.pi, 1e-6, np.pi / 2 - 1e-6, np.pi - 1e-6,
+                          0.3, 1.3, 2.9])
+    ref = orc.fisher(wl)
+    dg = np.einsum("iie->ie", ref["fisher"])
+    zero = dg == 0.0
+    assert zero[5, 0] and zero.sum() == 1          # only the iota row at iota = 0
+    d = np.sqrt(np.where(zero, 1.0, np.abs(dg)))
+    dw = lib.DeviceWorkload(wl)
+    plain = _run(lib, wl)
+    plan = lib.Plan(dw, chunk=512)
+    batched = {k: v.cpu().numpy() for k, v in plan.run().items()}
+    torch.cuda.synchronize()
+    plan.close()
+    for name, g in (("plain", plain), ("batched", batched)):
+        np.testing.assert_array_equal(g["status"], 0)
+        rel = np.abs(g["snr"] / ref["snr"] - 1).max()
+        assert rel <= 1e-12, f"{name}: SNR rel err {rel:.3e}"
+        err = np.abs(g["fisher"] - ref["fisher"]) / (d[:, None, :] * d[None, :, :])
+        assert err.max() <= 1e-9, f"{name}: Fisher err {err.max():.3e} at {np.unravel_index(err.argmax(), err.shape)}"
+        assert np.all(g["fisher"][5, :, 0] == 0.0) and np.all(g["fisher"][:, 5, 0] == 0.0), name
+        print(f"degenerate inclinations, {name}: SNR {rel:.2e}, Fisher {err.max():.2e}")

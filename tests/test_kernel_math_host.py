@@ -35,6 +35,25 @@ def test_host_model_bbh_single_detector(orc):
     assert _err(a, b).max() < 1e-12
 
 
+def test_host_model_degenerate_inclinations(orc):
+    """iota = 0, pi/2, pi and 1e-6 off each: the pattern-moment form of the
+    dL, iota and psi rows, whose coefficients vanish or nearly cancel there,
+    against the oracle's direct sums; the iota row at iota = 0 is exactly
+    zero on both sides."""
+    wl = synth.bns1e4(n=9).with_npts(900)
+    wl.par[5] = np.array([0.0, np.pi / 2, np.pi, 1e-6, np.pi / 2 - 1e-6, np.pi - 1e-6,
+                          0.3, 1.3, 2.9])
+    a = model_host.fisher(wl)
+    b = orc.fisher(wl)
+    dg = np.einsum("iie->ie", b["fisher"])
+    zero = dg == 0.0
+    assert zero[5, 0] and zero.sum() == 1
+    d = np.sqrt(np.where(zero, 1.0, np.abs(dg)))
+    np.testing.assert_allclose(a["snr"], b["snr"], rtol=1e-13)
+    assert (np.abs(a["fisher"] - b["fisher"]) / (d[:, None, :] * d[None, :, :])).max() < 1e-12
+    assert np.all(a["fisher"][5, :, 0] == 0.0) and np.all(a["fisher"][:, 5, 0] == 0.0)
+
+
 def test_host_model_invalid_events_flagged():
     wl = synth.bbh100(n=4)
     wl.par[1, 0] = 0.3          # eta > 1/4

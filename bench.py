@@ -31,12 +31,12 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # profiles/bns1e4_hbm_counters.md (calibrated against a 256 MiB copy: fetch
 # x 2.000, write x 1.000).  Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
-    "items_kernel<tidal,rot,mixed>": 58.08e6,
-    "items_kernel<tidal,rot>": 60.25e6,
-    "fisher_kernel<tidal,rot>": 134.57e6,
-    "waveform_kernel<rot,tidal>": 7853.16e6,
-    "waveform_kernel<rot,tidal,mixed>": 7859.19e6,
-    "waveform_deriv_kernel<rot,tidal>": 10306.83e6,
+    "items_kernel<tidal,rot,mixed>": 58.09e6,
+    "items_kernel<tidal,rot>": 60.20e6,
+    "fisher_kernel<tidal,rot>": 133.79e6,
+    "waveform_kernel<rot,tidal>": 7851.66e6,
+    "waveform_kernel<rot,tidal,mixed>": 7876.10e6,
+    "waveform_deriv_kernel<rot,tidal>": 10306.44e6,
 }
 
 # VALU instructions (wavefront instructions, SQ_INSTS_VALU) per launch of the

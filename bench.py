@@ -114,35 +114,111 @@ def cpu_baseline(wl, sample: int):
     t0 = time.perf_counter()
     r = oracle.fisher(sub, nthreads=threads)
     t1 = time.perf_counter()
-    inv = oracle.covariance(r["fisher"], dps=30)
+    inv = oracle.covariance(r["fisher"], dps=30, method="cho_svd")
     t2 = time.perf_counter()
     rec = {"value": sample / (t2 - t0), "unit": "events/s", "cores": threads, "kind": "oracle",
            "sample": f"{sample} seeded events of the same catalogue ({int(sub.npts.sum())} grid "
                      f"points); Fisher+SNR {t1 - t0:.2f} s on {threads} threads, mpmath "
-                     f"inversion {t2 - t1:.2f} s"}
+                     f"inversion (Cholesky, SVD where it fails) {t2 - t1:.2f} s"}
     rec["cpu_model"] = cpu_model()
+    # not timed: the well-conditioned 9-parameter block of the same matrices
+    keep = [k for k in range(r["fisher"].shape[0]) if k not in BLOCK_FIXED]
+    F9 = np.ascontiguousarray(r["fisher"][np.ix_(keep, keep)])
+    inv9 = oracle.covariance(F9, dps=30)
     return rec, {"idx": idx, "snr": r["snr"], "fisher": r["fisher"], "sigma": inv["sigma"],
-                 "cond": inv["cond"]}
+                 "cond": inv["cond"], "sigma9": inv9["sigma"], "cond9": inv9["cond"]}
+
+
+U64 = 2.0 ** -53
+# the 9-parameter block of the well-conditioned comparison: spins and
+# deformabilities held fixed (rows chi1z, chi2z, Lambda1, Lambda2 removed)
+BLOCK_FIXED = (9, 10, 11, 12)
+KAPPA_WELL = 1e5            # sigma parity <= 1e-9 asserted at or below this kappa
+KAPPA_MIXED = 1e12          # the mixed form's sigma bar applies below this kappa
+
+
+def _round(x, d=3):
+    return None if x is None or not np.isfinite(x) else float(f"{x:.{d}g}")
 
 
 def error_report(res, ref) -> dict:
-    """Errors of one form's outputs against the oracle on the sampled events:
-    SNR relative error, Fisher elements normalised by sqrt(G_ii G_jj), and
-    sigma_i relative error (all events, and those with condition number
-    below 1e13, where FP64 rounding in the sums alone moves sigma by less
-    than 1e-3)."""
+    """Errors of one form's outputs against the oracle on the sampled events.
+
+    SNR relative error; Fisher elements normalised by sqrt(G_ii G_jj), as the
+    maximum and per element (upper triangle, row-major); sigma_i relative
+    error of the full matrices per parameter and per decade of the condition
+    number kappa, with the events whose sigma is NaN on the GPU but finite in
+    the oracle counted apart (never skipped); the first-order bound
+    |dsigma_i/sigma_i| <= (P/2) kappa eps_e + 1e3 kappa u per event, eps_e the
+    event's largest normalised Fisher error (dC = -C dGamma C, with
+    lambda_min of the unit-diagonal matrix >= 1/kappa); and the sigmas of the
+    9-parameter block with spins and deformabilities fixed (kappa 1e3-1e8),
+    where the Fisher error alone decides the sigma error."""
     i = ref["idx"]
+    P = ref["fisher"].shape[0]
     snr = np.abs(res["snr"][i] / ref["snr"] - 1)
     F = res["fisher"][:, :, i]
     d = np.sqrt(np.abs(np.einsum("iie->ie", ref["fisher"])))
     ferr = np.abs(F - ref["fisher"]) / (d[:, None, :] * d[None, :, :])
-    sg = np.abs(res["sigma"][:, i] / ref["sigma"] - 1)
-    ok = ref["cond"] < 1e13
-    good = np.isfinite(sg)
-    return {"snr_max_rel": float(snr.max()), "fisher_max_norm": float(ferr.max()),
-            "sigma_frac_within_1e-3": float(np.mean(good & (sg <= 1e-3))),
-            "sigma_max_rel_kappa_lt_1e13": float(np.nanmax(sg[:, ok])) if ok.any() else None,
-            "events_kappa_lt_1e13": int(ok.sum()), "events": int(len(i))}
+    eps = ferr.max(axis=(0, 1))
+    sg_g, sg_r = res["sigma"][:, i], ref["sigma"]
+    both = np.isfinite(sg_g) & np.isfinite(sg_r)
+    nan_gpu = np.isfinite(sg_r) & ~np.isfinite(sg_g)
+    sg = np.where(both, np.abs(sg_g / np.where(both, sg_r, 1.0) - 1), np.nan)
+    kap = ref["cond"]
+    ev_err = np.nanmax(np.where(both, sg, -1.0), axis=0)       # per event, -1 if none
+    bound = 0.5 * P * kap * eps + 1e3 * kap * U64
+    in_bound = (ev_err <= bound) & ~nan_gpu.any(axis=0)
+    decades = []
+    for lo in range(9, 17):
+        m = (kap >= 10.0 ** lo) & (kap < 10.0 ** (lo + 1))
+        if not m.any():
+            continue
+        e = ev_err[m]
+        decades.append({"kappa": f"1e{lo}-1e{lo + 1}", "events": int(m.sum()),
+                        "max_rel": _round(float(e.max())), "median_rel": _round(float(np.median(e))),
+                        "nan_events": int(nan_gpu[:, m].any(axis=0).sum())})
+    mixed_sel = kap < KAPPA_MIXED
+    sub = ev_err[mixed_sel]
+    iu = np.triu_indices(P)
+    out = {"snr_max_rel": float(snr.max()), "fisher_max_norm": float(ferr.max()),
+           "fisher_max_norm_per_element_upper": [_round(float(x), 2) for x in ferr.max(axis=2)[iu]],
+           "sigma_max_rel_per_param": [_round(float(np.nanmax(sg[k]))) for k in range(P)],
+           "sigma_by_kappa": decades,
+           "sigma_nan_events": int(nan_gpu.any(axis=0).sum()),
+           "sigma_within_first_order_bound": float(np.mean(in_bound)),
+           f"sigma_max_rel_kappa_lt_{KAPPA_MIXED:.0e}": _round(float(sub.max())) if sub.size else None,
+           f"sigma_nan_kappa_lt_{KAPPA_MIXED:.0e}": int(nan_gpu[:, mixed_sel].any(axis=0).sum()),
+           f"events_kappa_lt_{KAPPA_MIXED:.0e}": int(mixed_sel.sum()),
+           "events": int(len(i))}
+    if "sigma9" in res and "sigma9" in ref:
+        s9g, s9r, k9 = res["sigma9"][:, i], ref["sigma9"], ref["cond9"]
+        e9 = np.abs(s9g / s9r - 1).max(axis=0)
+        e9 = np.where(np.isfinite(e9), e9, np.inf)
+        well = k9 <= KAPPA_WELL
+        out["block9"] = {"fixed": "chi1z, chi2z, Lambda1, Lambda2",
+                         "kappa_min": _round(float(k9.min())), "kappa_max": _round(float(k9.max())),
+                         f"sigma_max_rel_kappa_le_{KAPPA_WELL:.0e}": _round(float(e9[well].max())) if well.any() else None,
+                         f"events_kappa_le_{KAPPA_WELL:.0e}": int(well.sum()),
+                         "sigma_max_rel_all": _round(float(e9.max()))}
+    return out
+
+
+def passes(name, e) -> bool:
+    """The accuracy bar of a form on the sampled events.  FP64 forms: SNR
+    1e-12, Fisher 1e-9 (normalised), no NaN sigma where the oracle has one,
+    every sigma within the first-order bound of its event, and the
+    well-conditioned block's sigmas within 1e-9.  Mixed form: SNR 5e-7,
+    Fisher 1e-6 and sigma 1e-3 on every event with kappa < 1e12 (where the
+    FP64 forms' own error stays far below 1e-3), a NaN counting as a miss."""
+    if name == "batched_mixed":
+        m = e[f"sigma_max_rel_kappa_lt_{KAPPA_MIXED:.0e}"]
+        return (e["snr_max_rel"] <= 5e-7 and e["fisher_max_norm"] <= 1e-6 and m is not None and m <= 1e-3
+                and e[f"sigma_nan_kappa_lt_{KAPPA_MIXED:.0e}"] == 0)
+    b9 = e.get("block9", {})
+    w = b9.get(f"sigma_max_rel_kappa_le_{KAPPA_WELL:.0e}")
+    return (e["snr_max_rel"] <= 1e-12 and e["fisher_max_norm"] <= 1e-9 and e["sigma_nan_events"] == 0
+            and e["sigma_within_first_order_bound"] == 1.0 and (w is None or w <= 1e-9))
 
 
 def gradient_form(binding, synth, torch, args, timed) -> dict:
@@ -208,6 +284,29 @@ def catalogue_form(binding, synth, torch, args, timed, info) -> dict:
         "inverted": int(np.sum(st == 0)), "ill_conditioned_or_not_pd": int(np.sum((st & 6) != 0))}}
 
 
+def bbh100_form(binding, synth, torch, args, timed) -> dict:
+    """The small configuration: 100 BBH events, one L interferometer at the
+    H1 site, no Earth rotation, 1000-point grids, 11 parameters; the same
+    step (SNR and Fisher, then the inversion with the SVD fallback)."""
+    wl = synth.bbh100()
+    dw = binding.DeviceWorkload(wl)
+    o1, o2 = {}, {}
+
+    def step():
+        r = binding.fisher(dw, out=o1)
+        binding.covariance(r["fisher"], r["status"], method="cho_svd", out=o2)
+
+    for i in range(3):
+        step()
+    ms = timed(step, max(5, args.steps))
+    st = o2["status"].cpu().numpy()
+    log(f"bbh100: {ms:.4f} ms per step, inverted {int(np.sum((st & ~32) == 0))}/{wl.n}")
+    return {"plain_fp64_bbh100": {"workload": "bbh100: 100 BBH, one L interferometer (H1 site), no "
+                                              "rotation, 1000 points from 10 Hz, 11 parameters",
+                                  "ms_per_step": round(ms, 4), "events_per_s": round(wl.n / (ms * 1e-3), 1),
+                                  "inverted": int(np.sum((st & ~32) == 0))}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,9 +342,13 @@ def main():
             "status": torch.empty(wl.n, dtype=torch.int32, device="cuda")}
     outi = {}
 
+    # the paper's default inversion (sec. 4.1): Cholesky, an SVD where it fails
+    def invert(F, status, out):
+        return binding.covariance(F, status, method="cho_svd", out=out)
+
     def step():
         binding.fisher(dw, out=outf)
-        binding.invert(outf["fisher"], outf["status"], out=outi)
+        invert(outf["fisher"], outf["status"], outi)
 
     def timed(fn, steps):
         torch.cuda.synchronize()
@@ -269,7 +372,7 @@ def main():
         ev[0].record(stream)
         binding.fisher(dw, out=outf)
         ev[1].record(stream)
-        binding.invert(outf["fisher"], outf["status"], out=outi)
+        invert(outf["fisher"], outf["status"], outi)
         ev[2].record(stream)
         ev[2].synchronize()
         tf.append(ev[0].elapsed_time(ev[1]))
@@ -277,22 +380,28 @@ def main():
     fisher_ms = float(np.mean(tf))
     invert_ms = float(np.mean(ti))
     st = outf["status"].cpu().numpy()
+    sti = outi["status"].cpu().numpy()
     log(f"plain fisher kernel {fisher_ms:.3f} ms, invert kernel {invert_ms:.3f} ms, "
-        f"status ok {int(np.sum(st == 0))}/{wl.n}")
+        f"Fisher status ok {int(np.sum(st == 0))}/{wl.n}, inverted {int(np.sum((sti & ~32) == 0))}/{wl.n} "
+        f"({int(np.sum(sti == 32))} by SVD after a failed Cholesky)")
+
+    def block9(F, status):
+        r9 = binding.covariance(F, status, fixed=BLOCK_FIXED, method="cho")
+        return r9["sigma"].cpu().numpy()
 
     plain_res = {"snr": outf["snr"].cpu().numpy(), "fisher": outf["fisher"].cpu().numpy(),
-                 "sigma": outi["sigma"].cpu().numpy()}
+                 "sigma": outi["sigma"].cpu().numpy(), "sigma9": block9(outf["fisher"], outf["status"])}
 
     # ---- batched forms: work items, persistent workgroups, one HIP graph per step
     def batched(mixed, chunk, wg):
-        plan = binding.Plan(dw, chunk=chunk, wg_per_cu=wg, mixed=mixed)   # 0: autotuned
+        plan = binding.Plan(dw, chunk=chunk, wg_per_cu=wg, mixed=mixed, inv_method="cho_svd")   # 0: autotuned
         info = plan.info()
         outb = {}
         for i in range(args.warmup):
             plan.run(invert=True, out=outb)
         ms = timed(lambda: plan.run(invert=True, out=outb), args.steps)
         prof = binding.Plan(dw, chunk=info["chunk"], wg_per_cu=info["wg_per_cu"], use_graph=False,
-                            profile=True, mixed=mixed)
+                            profile=True, mixed=mixed, inv_method="cho_svd")
         items = []
         outp = {}
         for i in range(args.steps):
@@ -300,12 +409,13 @@ def main():
             items.append(prof.info()["items_ms"])
         prof.close()
         res = {k: outb[k].cpu().numpy() for k in ("snr", "fisher", "sigma", "status")}
+        res["sigma9"] = block9(outb["fisher"], torch.zeros_like(outb["status"]))
         plan.close()
         sb = res["status"]
         tag = "mixed" if mixed else "FP64"
         log(f"batched {tag}: chunk {info['chunk']}, {info['wg_per_cu']} WG/CU, {info['n_items']} "
             f"items, {ms:.3f} ms/step, items kernel {float(np.mean(items)):.3f} ms, inverted "
-            f"{int(np.sum(sb == 0))}/{wl.n} (Cholesky failed on {int(np.sum((sb & 2) != 0))})")
+            f"{int(np.sum((sb & ~32) == 0))}/{wl.n} ({int(np.sum(sb == 32))} by SVD after a failed Cholesky)")
         return ms, float(np.mean(items)), info, res
 
     batched_ms, items_ms, info, batched_res = batched(False, args.chunk, args.wg_per_cu)
@@ -415,7 +525,7 @@ def main():
                                    "traffic": MEASURED_TRAFFIC.get("waveform_deriv_kernel<rot,tidal>")}
     del outd
 
-    extra = {}
+    extra = bbh100_form(binding, synth, torch, args, timed)
     if not args.no_extra:
         extra.update(gradient_form(binding, synth, torch, args, timed))
         extra.update(catalogue_form(binding, synth, torch, args, timed, info))
@@ -441,30 +551,33 @@ def main():
         log(f"copy calibration: 3 x {args.copy_calibration} MiB")
 
     # the reported form: the fastest one that meets its accuracy bar on the
-    # sampled events (FP64 forms: SNR 1e-12, Fisher 1e-9; mixed form: SNR
-    # 5e-7, Fisher 1e-6, sigma 1e-3 where kappa < 1e13); without the oracle
-    # sample only the FP64 forms are eligible
-    def passes(name):
-        if name not in errs:
-            return name != "batched_mixed"
-        e = errs[name]
-        if name == "batched_mixed":
-            return (e["snr_max_rel"] <= 5e-7 and e["fisher_max_norm"] <= 1e-6 and
-                    (e["sigma_max_rel_kappa_lt_1e13"] or 0.0) <= 1e-3)
-        return e["snr_max_rel"] <= 1e-12 and e["fisher_max_norm"] <= 1e-9
+    # sampled events (passes()); without the oracle sample only the FP64
+    # forms are eligible
+    def eligible(name):
+        return passes(name, errs[name]) if name in errs else name != "batched_mixed"
 
     cands = [("plain_fp64", plain_ms, "fisher_kernel<tidal,rot>", fisher_ms),
              ("batched_fp64", batched_ms, "items_kernel<tidal,rot>", items_ms),
              ("batched_mixed", mixed_ms, "items_kernel<tidal,rot,mixed>", mitems_ms)]
-    eligible = [c for c in cands if passes(c[0])]
-    form, ms, kname, kms = min(eligible, key=lambda c: c[1])
+    ok = [c for c in cands if eligible(c[0])]
+    if not ok:
+        log("no form met its accuracy bar; reporting the plain FP64 form")
+        ok = cands[:1]
+    form, ms, kname, kms = min(ok, key=lambda c: c[1])
     flops = algorithmic_flops(wl)
-    achieved = flops / (kms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+
+    def roofline_of(kname, kms):
+        achieved = flops / (kms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                 "traffic": MEASURED_TRAFFIC.get(kname),
                 "kernel": kname, "kernel_ms": round(kms, 4), "flops_per_launch": flops,
                 "valu_busy": valu_busy(kname, kms)}
+    roofline = roofline_of(kname, kms)
+    # the fastest form at the paper's precision, beside the headline
+    f64 = min([c for c in ok if c[0] != "batched_mixed"] or cands[:2], key=lambda c: c[1])
+    fp64_line = {"form": f64[0], "value": round(wl.n / (f64[1] * 1e-3), 1), "unit": "events/s",
+                 "ms_per_step": round(f64[1], 4), "roofline": roofline_of(f64[2], f64[3])}
 
     value = wl.n / (ms * 1e-3)
     forms = {"plain_fp64": {"events_per_s": round(wl.n / (plain_ms * 1e-3), 1),
@@ -495,6 +608,7 @@ def main():
                    "events": wl.n, "grid_points": int(wl.npts.sum()), "form": form},
         "forms": forms,
         "roofline": roofline,
+        "fp64": fp64_line,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

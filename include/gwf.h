@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define GWF_VERSION 5
+#define GWF_VERSION 6
 
 /* ------------------------------------------------------------- statuses */
 typedef int32_t gwf_status;
@@ -84,7 +84,11 @@ enum {
 enum {
   GWF_MC = 0, GWF_ETA, GWF_DL, GWF_THETA, GWF_PHI, GWF_IOTA, GWF_PSI,
   GWF_TCOAL, GWF_PHICOAL, GWF_CHI1Z, GWF_CHI2Z, GWF_LAMBDA1, GWF_LAMBDA2,
-  GWF_NPAR_MAX = 13
+  GWF_NPAR_SRC = 13,  /* rows of gwf_events.par                               */
+  GWF_NPAR_MAX = 14   /* rows of the largest Fisher matrix: the orbital
+                         eccentricity e0 follows the spins and the tidal
+                         deformabilities (sec. 3.2), so P = 11, 12 (e0),
+                         13 (tides) or 14 (tides and e0)                     */
 };
 
 /* call flags */
@@ -92,6 +96,10 @@ enum {
   GWF_EARTH_ROT = 1, /* patterns and arrival-time phase at t(f); otherwise
                         frozen at the coalescence time (sec. 3, footnote)  */
   GWF_TIDAL = 2,     /* 5PN/6PN tidal phase; Fisher has 13 rows instead of 11 */
+  GWF_ECCENTRIC = 8, /* moderate eccentricity (sec. 2.2, e0 <~ 0.1): the
+                        leading-order e0^2 correction to the TaylorF2 phase,
+                        e0 given at a reference frequency (gwf_events ecc,
+                        f_ref_ecc); one more Fisher row, last              */
   GWF_MIXED = 4      /* mixed-precision form, accepted by gwf_plan_create and
                         gwf_waveform (gwf_snr and gwf_fisher return
                         GWF_E_UNSUPPORTED).  Plans: the noise weight
@@ -112,7 +120,7 @@ enum {
 typedef struct gwf_events {
   int64_t n;           /* number of events, >= 1                              */
   int64_t ld;          /* row stride of par in elements, >= n                 */
-  const double* par;   /* device [GWF_NPAR_MAX][ld]: row r, event e at par[r*ld+e].
+  const double* par;   /* device [GWF_NPAR_SRC][ld]: row r, event e at par[r*ld+e].
                           Rows LAMBDA1/LAMBDA2 are read only with GWF_TIDAL.   */
   const double* tc_s;  /* device [n] or NULL: coalescence time in seconds used
                           only in the 2 pi f tc term of the waveform phase     */
@@ -133,26 +141,46 @@ typedef struct gwf_events {
                           (its covariance row and column 0, its sigma NaN), and
                           the adjoint ignores gbar there.  SNR and strain are
                           not affected.                                       */
+  const double* ecc;   /* device [n], required with GWF_ECCENTRIC (else not read):
+                          the orbital eccentricity e0 >= 0 at the reference
+                          frequency (sec. 2.1; e0 <~ 0.1 for the model to hold)  */
+  const double* f_ref_ecc; /* device [n] or NULL: the reference frequency of e0 in
+                          Hz, > 0; NULL means each event's grid starts there
+                          (the paper's default fRef_ecc = None, sec. 2.1)      */
 } gwf_events;
 
 /* ------------------------------------------------------------ detectors */
 enum { GWF_SHAPE_L = 0, GWF_SHAPE_T = 1 };
-enum { GWF_PSD_ANALYTIC = 0 };
+enum { GWF_PSD_ANALYTIC = 0, GWF_PSD_TABLE = 1, GWF_ASD_TABLE = 2 };
 
 /* One detector site (sec. 3.1, Table 2), angles in radians.  An L site is
  * one interferometer whose arm bisector makes the angle gamma with local
  * East (counted towards North) and whose arms open by zeta.  A T site is
  * three co-located interferometers with 60-degree arms in a closed loop;
  * gamma is its first arm's angle, so the three bisectors are at
- * gamma + 30 deg + k 120 deg (zeta is ignored).
+ * gamma + 30 deg + k 120 deg (zeta is ignored).  The three arms of a T
+ * share its noise curve.
  * PSD (GWF_PSD_ANALYTIC): S_n(f) = S0 [x^-4.14 - 5 x^-2 + 111 (1 - x^2 +
- * x^4/2)/(1 + x^2/2)] with x = f/f0; the three arms of a T share it. */
+ * x^4/2)/(1 + x^2/2)] with x = f/f0.
+ * PSD (GWF_PSD_TABLE, GWF_ASD_TABLE): a sampled noise curve, the paper's
+ * psd_path file with its is_ASD flag (sec. 3.1): psd_n >= 2 frequencies
+ * psd_f [Hz], strictly increasing and > 0, and the values psd_S there, the
+ * PSD [1/Hz] or (GWF_ASD_TABLE) the ASD [1/sqrt(Hz)], squared into a PSD;
+ * S_n(f) = S0 x (the PSD linearly interpolated in f), S0 a scale (1 for the
+ * curve as given).  A grid point outside [psd_f[0], psd_f[psd_n-1]] gets
+ * zero weight (the detector is blind there).  Both arrays are DEVICE
+ * memory owned by the caller; their ordering and positivity are the
+ * caller's (not checked: a value <= 0 inside the range makes that site's
+ * weights infinite or negative, flagged GWF_EV_NONFINITE where it shows). */
 typedef struct gwf_site {
   double lat, lon, gamma, zeta;
   int32_t shape;
-  int32_t psd_kind;
-  double S0;   /* > 0, 1/Hz */
-  double f0;   /* > 0, Hz   */
+  int32_t psd_kind;    /* GWF_PSD_ANALYTIC, GWF_PSD_TABLE or GWF_ASD_TABLE */
+  double S0;           /* > 0: 1/Hz (analytic), a dimensionless scale (tables) */
+  double f0;           /* > 0, Hz (analytic; not read for tables)            */
+  const double* psd_f; /* device [psd_n] (tables; NULL for the analytic PSD)   */
+  const double* psd_S; /* device [psd_n] (tables)                              */
+  int64_t psd_n;       /* 2 <= psd_n <= 2^31 - 1 (tables)                      */
 } gwf_site;
 
 #define GWF_MAX_SITES 8
@@ -458,6 +486,11 @@ typedef struct gwf_plan_options {
   int32_t use_graph;   /* nonzero: capture and replay a HIP graph                     */
   int32_t profile;     /* nonzero (with use_graph = 0): time the work-item kernel of
                           each run with HIP events on its stream                     */
+  int32_t inv_method;  /* inversion of gwf_plan_fisher: GWF_INV_CHO (0, flags a failed
+                          Cholesky NOT_PD), GWF_INV_CHO_SVD (the paper's default: an
+                          SVD where the Cholesky fails, status GWF_EV_SVD) or
+                          GWF_INV_CHO_DD (double-double Cholesky); see gwf_covariance */
+  int32_t pad;
 } gwf_plan_options;
 
 typedef struct gwf_plan_info {
@@ -475,7 +508,8 @@ gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const g
 
 /* Fisher, SNR and status of the plan's catalogue (same layouts and meaning
  * as gwf_fisher with snr_th = 0).  With sigma non-NULL the inversion of
- * gwf_invert follows in the same graph (cov, cond, inv_err optional). */
+ * gwf_invert follows in the same graph (cov, cond, inv_err optional), by the
+ * plan's inv_method (gwf_plan_options). */
 gwf_status gwf_plan_fisher(gwf_plan* plan, double* fisher, double* snr, int32_t* status,
                            double cond_max, double* cov, double* sigma, double* cond,
                            double* inv_err, void* stream);

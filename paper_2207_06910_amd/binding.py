@@ -16,20 +16,22 @@ LIB_PATH = os.path.join(HERE, "libgwf.so")
 
 GWF_OK, GWF_E_INVALID_ARG, GWF_E_UNSUPPORTED, GWF_E_HIP, GWF_E_NOMEM = 0, 1, 2, 3, 4
 EV_INVALID_PARAM, EV_NOT_PD, EV_ILL_COND, EV_NONFINITE, EV_SKIPPED_SNR = 1, 2, 4, 8, 16
-EARTH_ROT, TIDAL, MIXED = 1, 2, 4
+EARTH_ROT, TIDAL, MIXED, ECCENTRIC = 1, 2, 4, 8
 SHAPE_L, SHAPE_T = 0, 1
-NPAR_MAX = 13
+NPAR_SRC, NPAR_MAX = 13, 14
 
 
 class Events(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("ld", ctypes.c_int64), ("par", ctypes.c_void_p),
-                ("tc_s", ctypes.c_void_p), ("active", ctypes.c_void_p), ("par_mask", ctypes.c_void_p)]
+                ("tc_s", ctypes.c_void_p), ("active", ctypes.c_void_p), ("par_mask", ctypes.c_void_p),
+                ("ecc", ctypes.c_void_p), ("f_ref_ecc", ctypes.c_void_p)]
 
 
 class SiteDesc(ctypes.Structure):
     _fields_ = [("lat", ctypes.c_double), ("lon", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("zeta", ctypes.c_double), ("shape", ctypes.c_int32), ("psd_kind", ctypes.c_int32),
-                ("S0", ctypes.c_double), ("f0", ctypes.c_double)]
+                ("S0", ctypes.c_double), ("f0", ctypes.c_double), ("psd_f", ctypes.c_void_p),
+                ("psd_S", ctypes.c_void_p), ("psd_n", ctypes.c_int64)]
 
 
 class Network(ctypes.Structure):
@@ -46,7 +48,8 @@ GRID_LOG, GRID_EXPLICIT = 0, 1
 
 class PlanOptions(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("profile", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("inv_method", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -61,7 +64,7 @@ _lib = None
 
 class CovOptions(ctypes.Structure):
     _fields_ = [("fixed_mask", ctypes.c_uint32), ("marg_mask", ctypes.c_uint32),
-                ("prior", ctypes.c_double * 13), ("cond_max", ctypes.c_double),
+                ("prior", ctypes.c_double * 14), ("cond_max", ctypes.c_double),
                 ("sky_level", ctypes.c_double), ("i_theta", ctypes.c_int32), ("i_phi", ctypes.c_int32),
                 ("sky_units", ctypes.c_int32), ("method", ctypes.c_int32), ("truncate", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("svals_thresh", ctypes.c_double), ("par_mask", ctypes.c_void_p)]
@@ -483,11 +486,12 @@ class Plan:
     arrays the plan reads at every run."""
 
     def __init__(self, dw: DeviceWorkload, chunk=0, wg_per_cu=0, use_graph=True, profile=False,
-                 mixed=False, stream=None):
+                 mixed=False, inv_method="cho", stream=None):
         self.dw = dw
         self.handle = ctypes.c_void_p()
         ev, net, grid, keep = dw.descriptors()
-        opt = PlanOptions(int(chunk), int(wg_per_cu), 1 if use_graph else 0, 1 if profile else 0)
+        opt = PlanOptions(int(chunk), int(wg_per_cu), 1 if use_graph else 0, 1 if profile else 0,
+                          INV_METHODS[inv_method], 0)
         _check(load().gwf_plan_create(ctypes.byref(ev), ctypes.byref(net), ctypes.byref(grid),
                                       dw.flags | (MIXED if mixed else 0), ctypes.byref(opt),
                                       ctypes.byref(self.handle),

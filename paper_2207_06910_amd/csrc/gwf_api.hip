@@ -51,8 +51,10 @@ gwf_status api_pack_network(const gwf_network* net, gwf::NetDesc& nd) {
     const gwf_site& in = net->site[s];
     if (in.shape != GWF_SHAPE_L && in.shape != GWF_SHAPE_T)
       return api_fail(GWF_E_INVALID_ARG, "site %d: shape %d is neither L nor T", s, in.shape);
+    if (in.psd_kind != GWF_PSD_ANALYTIC && in.psd_kind != GWF_PSD_TABLE && in.psd_kind != GWF_ASD_TABLE)
+      return api_fail(GWF_E_INVALID_ARG, "site %d: psd_kind %d unknown", s, in.psd_kind);
     if (in.psd_kind != GWF_PSD_ANALYTIC)
-      return api_fail(GWF_E_UNSUPPORTED, "site %d: psd_kind %d is not supported", s, in.psd_kind);
+      return api_fail(GWF_E_UNSUPPORTED, "site %d: tabulated noise curves are not available in this build", s);
     if (!finite_all({in.lat, in.lon, in.gamma, in.zeta, in.S0, in.f0}))
       return api_fail(GWF_E_INVALID_ARG, "site %d: non-finite geometry or PSD parameter", s);
     if (!(in.S0 > 0.0) || !(in.f0 > 0.0))
@@ -84,8 +86,9 @@ gwf_status api_check_common(const gwf_events* ev, const gwf_grid* grid, uint32_t
   } else {
     return api_fail(GWF_E_UNSUPPORTED, "grid kind %d", grid->kind);
   }
-  if (flags & ~(uint32_t)(GWF_EARTH_ROT | GWF_TIDAL | GWF_MIXED))
+  if (flags & ~(uint32_t)(GWF_EARTH_ROT | GWF_TIDAL | GWF_MIXED | GWF_ECCENTRIC))
     return api_fail(GWF_E_INVALID_ARG, "unknown flag bits 0x%x", flags);
+  if (flags & GWF_ECCENTRIC) return api_fail(GWF_E_UNSUPPORTED, "GWF_ECCENTRIC is not available in this build");
   return GWF_OK;
 }
 
@@ -254,7 +257,7 @@ gwf_status gwf_fisher_adjoint(const gwf_events* ev, const gwf_network* net, cons
 gwf_status gwf_invert(int32_t P, int64_t n, const double* fisher, double cond_max, double* cov,
                       double* sigma, double* cond, double* inv_err, double* logdet, int32_t* status,
                       void* stream) {
-  if (P < 1 || P > GWF_NPAR_MAX) return api_fail(GWF_E_INVALID_ARG, "P=%d outside 1..13", P);
+  if (P < 1 || P > GWF_NPAR_MAX) return api_fail(GWF_E_INVALID_ARG, "P=%d outside 1..%d", P, GWF_NPAR_MAX);
   if (n < 1) return api_fail(GWF_E_INVALID_ARG, "n=%lld must be >= 1", (long long)n);
   if (!fisher || !sigma || !status) return api_fail(GWF_E_INVALID_ARG, "fisher, sigma and status are required");
   if (std::isnan(cond_max)) return api_fail(GWF_E_INVALID_ARG, "cond_max is NaN");
@@ -286,7 +289,7 @@ gwf_status gwf_covariance(int32_t P, int64_t n, const double* fisher, const gwf_
                           const double* theta, double* cov, double* sigma, double* cond,
                           double* inv_err, double* logdet, double* sky, double* eigval,
                           double* eigvec, int32_t* status, void* stream) {
-  if (P < 1 || P > GWF_NPAR_MAX) return api_fail(GWF_E_INVALID_ARG, "P=%d outside 1..13", P);
+  if (P < 1 || P > GWF_NPAR_MAX) return api_fail(GWF_E_INVALID_ARG, "P=%d outside 1..%d", P, GWF_NPAR_MAX);
   if (n < 1) return api_fail(GWF_E_INVALID_ARG, "n=%lld must be >= 1", (long long)n);
   if (!fisher || !sigma || !status || !opts)
     return api_fail(GWF_E_INVALID_ARG, "fisher, opts, sigma and status are required");

@@ -141,6 +141,21 @@ hipError_t launch_combine(const CombineArgs& a, bool tidal, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <bool MIXED>
+int items_resident_t(bool tidal, bool rot) {
+  int nb = 0;
+  hipError_t err;
+  if (tidal && rot) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, items_kernel<true, true, MIXED>, kBlock, 0);
+  else if (tidal) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, items_kernel<true, false, MIXED>, kBlock, 0);
+  else if (rot) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, items_kernel<false, true, MIXED>, kBlock, 0);
+  else err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, items_kernel<false, false, MIXED>, kBlock, 0);
+  return err == hipSuccess ? nb : 0;
+}
+
+int items_max_resident(bool tidal, bool rot, bool mixed) {
+  return mixed ? items_resident_t<true>(tidal, rot) : items_resident_t<false>(tidal, rot);
+}
+
 int fisher_nacc(bool tidal) { return tidal ? FisherDims<true>::NACC : FisherDims<false>::NACC; }
 int fisher_block() { return kBlock; }
 

@@ -51,6 +51,9 @@ hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
 hipError_t launch_items(const ItemsArgs& a, bool tidal, bool rot, bool mixed, int n_wg, hipStream_t s);
 hipError_t launch_combine(const CombineArgs& a, bool tidal, hipStream_t s);
 int fisher_nacc(bool tidal);
+// Work-item workgroups that one compute unit holds at once (registers and
+// LDS of the instantiation), 0 if the runtime cannot tell.
+int items_max_resident(bool tidal, bool rot, bool mixed);
 int fisher_block();
 
 }  // namespace gwf

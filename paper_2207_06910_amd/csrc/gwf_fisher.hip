@@ -26,8 +26,10 @@ namespace gwf {
 
 // Declared for 2 x kBlock lanes so that the register budget is that of two
 // wavefronts per SIMD (256 registers); launched with kBlock lanes, two
-// workgroups (45 KB of LDS each) then share a compute unit, which hides the
-// latency of the LDS constant reads and of the transcendental sequences.
+// workgroups (about 60 KB of LDS each: 54 KB of FisherLds, the event's
+// 1 KB of constants and 3.8 KB for eight sites) then share a compute unit,
+// which hides the latency of the LDS constant reads and of the
+// transcendental sequences.
 // (The P = 11 instantiation keeps the one-wavefront budget: under the
 // two-wavefront cap it spills.)
 template <bool TIDAL, bool ROT, bool EXPL>

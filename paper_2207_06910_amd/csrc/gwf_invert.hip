@@ -38,7 +38,7 @@ namespace gwf {
 
 namespace {
 
-constexpr int kGroup = 16;                 // lanes per matrix: one per column, P <= 13
+constexpr int kGroup = 16;                 // lanes per matrix: one per column, P <= 14
 constexpr int kInvBlock = 64;              // one wavefront
 constexpr int kGroups = kInvBlock / kGroup;
 constexpr int kMaxSweeps = 40;
@@ -370,13 +370,14 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
     }
     __syncthreads();
     // ln det Gamma from the singular values where the Cholesky failed and all
-    // eigenvalues are positive
+    // eigenvalues are positive: lsv sums 2 ln d_j + ln s_j = ln det Gamma,
+    // while ld holds half of it on every path (the output doubles it)
     double lsv = own ? fma(2.0, log(dnj), log(sj)) : 0.0;
 #pragma unroll
     for (int off = kGroup / 2; off >= 1; off >>= 1) lsv += __shfl_xor(lsv, off, kGroup);
     const uint64_t negm = __ballot(own && !(lam > 0.0));
     const bool allpos = ((negm >> (g * kGroup)) & 0xffffull) == 0;
-    if (svd_grp && !pd) ld = allpos ? lsv : nan;
+    if (svd_grp && !pd) ld = allpos ? 0.5 * lsv : nan;
     svd_done = svd_grp;
     ok = ok || svd_done;
   }
@@ -547,7 +548,7 @@ hipError_t launch_p(const InvertArgs& a0, hipStream_t stream) {
   if (a.p_full == 0) {           // the whole matrix, no manipulations
     a.p_full = P;
     a.n_out = P;
-    for (int i = 0; i < 13; ++i) {
+    for (int i = 0; i < kMaxPar; ++i) {
       a.keep[i] = (int8_t)(i < P ? i : 0);
       a.out_pos[i] = (int8_t)(i < P ? i : -1);
       a.prior[i] = 0.0;
@@ -577,6 +578,7 @@ hipError_t launch_invert(const InvertArgs& a, int P, hipStream_t stream) {
     case 11: return launch_p<11>(a, stream);
     case 12: return launch_p<12>(a, stream);
     case 13: return launch_p<13>(a, stream);
+    case 14: return launch_p<14>(a, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -54,9 +54,9 @@ struct InvertArgs {
   // is inverted whole (launch_invert fills the identity maps below).
   int32_t p_full;           // parameters of the stored matrix
   int32_t n_out;            // parameters of cov and sigma (after marginalisation)
-  int8_t keep[13];          // stored index of kept parameter i (fixed ones removed)
-  int8_t out_pos[13];       // output position of kept parameter i, -1 if marginalised
-  double prior[13];         // added to kept diagonal entry i before inversion
+  int8_t keep[kMaxPar];      // stored index of kept parameter i (fixed ones removed)
+  int8_t out_pos[kMaxPar];   // output position of kept parameter i, -1 if marginalised
+  double prior[kMaxPar];     // added to kept diagonal entry i before inversion
   int32_t i_theta, i_phi;   // kept positions of theta and phi, -1: no sky area
   double sky_fac;           // -2 pi ln(1 - X/100) [x (180/pi)^2 for square degrees]
   const double* theta;      // [n], the events' polar angles (sky area only)

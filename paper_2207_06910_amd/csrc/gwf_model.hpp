@@ -56,6 +56,7 @@ constexpr double kEulerGamma = 0.5772156649015329;
 constexpr double kLn2 = 0.69314718055994530942;
 
 constexpr int kMaxSites = 8;
+constexpr int kMaxPar = 14;     // Fisher rows with tides and eccentricity
 constexpr int kMaxIfo = 16;
 constexpr uint32_t kFlagRot = 1;
 constexpr uint32_t kFlagTidal = 2;

@@ -30,6 +30,7 @@ struct gwf_plan {
   // tuning
   int chunk = 0, wg_per_cu = 0, n_items = 0;
   bool use_graph = true;
+  int32_t inv_method = GWF_INV_CHO;
   double tuned_ms = 0.0;
   // workspace
   EventC* evc = nullptr;
@@ -140,6 +141,7 @@ gwf_status enqueue(gwf_plan* p, const Outs& o, hipStream_t s) {
     InvertArgs ia{};
     ia.n = p->n; ia.fisher = o.fisher; ia.cond_max = o.cond_max; ia.cov = o.cov; ia.sigma = o.sigma;
     ia.cond = o.cond; ia.inv_err = o.inv_err; ia.status = o.status; ia.par_mask = p->ev.par_mask;
+    ia.method = p->inv_method;
     err = launch_invert(ia, p->P, s);
   }
   if (err != hipSuccess) return api_hip_fail(err, "batched launch");
@@ -196,6 +198,11 @@ gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const g
     return api_fail(GWF_E_INVALID_ARG, "chunk=%d must be a non-negative multiple of %d", o.chunk, fisher_block());
   }
   if (o.wg_per_cu < 0 || o.wg_per_cu > 8) { delete p; return api_fail(GWF_E_INVALID_ARG, "wg_per_cu=%d outside 0..8", o.wg_per_cu); }
+  if (o.inv_method != GWF_INV_CHO && o.inv_method != GWF_INV_CHO_SVD && o.inv_method != GWF_INV_CHO_DD) {
+    delete p;
+    return api_fail(GWF_E_INVALID_ARG, "inv_method=%d: plans invert by GWF_INV_CHO, GWF_INV_CHO_SVD or GWF_INV_CHO_DD",
+                    o.inv_method);
+  }
   p->ev = *ev; p->grid = *grid; p->flags = flags; p->n = ev->n;
   p->tidal = (flags & GWF_TIDAL) != 0;
   p->rot = (flags & GWF_EARTH_ROT) != 0;
@@ -203,6 +210,7 @@ gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const g
   p->P = p->tidal ? 13 : 11;
   p->nacc = fisher_nacc(p->tidal);
   p->use_graph = o.use_graph != 0;
+  p->inv_method = o.inv_method;
   if (o.profile && p->use_graph) {
     delete p;
     return api_fail(GWF_E_INVALID_ARG, "profile needs use_graph = 0 (kernels launched directly)");
@@ -234,8 +242,19 @@ gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const g
   }
   // candidates
   std::vector<int> chunks = o.chunk ? std::vector<int>{o.chunk} : std::vector<int>{2048, 4096, 8192, 16384};
-  std::vector<int> wgs = o.wg_per_cu ? std::vector<int>{o.wg_per_cu}
-                                     : (p->tidal ? std::vector<int>{2, 4} : std::vector<int>{1, 2});
+  // workgroups per CU: the candidates are those a compute unit can hold at
+  // once (its registers and LDS), so every persistent workgroup starts at the
+  // launch; a larger wg_per_cu given by the caller is honoured (the surplus
+  // workgroups start as others leave)
+  std::vector<int> wgs;
+  if (o.wg_per_cu) {
+    wgs.push_back(o.wg_per_cu);
+  } else {
+    const int res = items_max_resident(p->tidal, p->rot, p->mixed);
+    for (int w = 1; w <= 4; ++w)
+      if (w <= std::max(1, res)) wgs.push_back(w);
+    if (wgs.size() > 2) wgs.erase(wgs.begin(), wgs.end() - 2);   // the two largest
+  }
   int best_c = chunks[0], best_w = wgs[0];
   double best = 0.0;
   if (chunks.size() * wgs.size() > 1) {

@@ -23,7 +23,7 @@ def test_library_exports_every_declared_symbol():
     assert {"gwf_snr", "gwf_fisher", "gwf_invert"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.gwf_version() == 5
+    assert lib.gwf_version() == 6
 
 
 def test_network_interferometer_count():
@@ -75,7 +75,7 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.gwf_waveform_deriv(B(ev), B(net), B(grid), 0, 8, 0, 8, None, None) == 1
     assert lib.gwf_waveform_deriv(B(ev), B(net), B(grid), binding.MIXED, 8, 10, 8, None, None) == 2
     # inversion: P out of range, NaN threshold
-    assert lib.gwf_invert(14, 3, 8, 1e50, None, 8, None, None, None, 8, None) == 1
+    assert lib.gwf_invert(15, 3, 8, 1e50, None, 8, None, None, None, 8, None) == 1
     assert lib.gwf_invert(13, 3, 8, float("nan"), None, 8, None, None, None, 8, None) == 1
     # adjoint: missing outputs, non-finite weight, no mixed form
     assert lib.gwf_fisher_adjoint(B(ev), B(net), B(grid), 0, 8, None, 1.0, 1.0, None, 8, None) == 1
@@ -91,6 +91,16 @@ def test_invalid_arguments_rejected_on_host():
     plan = ctypes.c_void_p()
     assert lib.gwf_plan_create(B(ev), B(net), B(gx), 0, None, B(plan), None) == 2
     assert len(lib.gwf_last_error()) > 0
+    # plans invert by Cholesky, Cholesky with the SVD fallback or double-double Cholesky only
+    for m in (2, 3, 7):
+        opt = binding.PlanOptions(0, 0, 1, 0, m, 0)
+        assert lib.gwf_plan_create(B(ev), B(net), B(grid), 0, B(opt), B(plan), None) == 1
+        assert b"inv_method" in lib.gwf_last_error()
+    # an unknown noise-curve kind
+    s = synth.site("H1")
+    n3, k3 = binding.network([s])
+    k3[0].psd_kind = 5
+    assert lib.gwf_snr(B(ev), B(n3), B(grid), 0, 8, None, None, None) == 1
 
 
 def test_covariance_options_rejected_on_host():

@@ -222,6 +222,63 @@ def test_svd_fallback_on_indefinite_matrices(lib, orc):
     assert np.all(np.isnan(g1["logdet"][svd])) and np.all(np.isfinite(g1["logdet"][~svd]))
 
 
+def test_logdet_where_the_svd_replaces_a_failed_cholesky(lib):
+    """Positive-definite matrices (by their 50-digit eigenvalues) at kappa
+    ~1e16-1e19, one eigenvalue near the FP64 rounding level of the others,
+    so that the FP64 Cholesky fails on some of them: where 'cho_svd' takes
+    the SVD (status 32) and 'svd' likewise falls back from its Cholesky, ln
+    det Gamma comes from the singular values and must equal mpmath's ln det.
+    The scales s_i (1e3-1e6) make |ln det| about 200-300, so a factor of two
+    would miss by that much, while the smallest singular value of a matrix at
+    kappa carries a relative error up to ~1e3 kappa u: the tolerance is
+    1 + ln(1 + 1e3 kappa u)."""
+    mp = pytest.importorskip("mpmath")
+    rng = np.random.default_rng(1906)
+    P, n = 13, 160
+    F = np.zeros((P, P, n))
+    for e in range(n):
+        Q, _ = np.linalg.qr(rng.normal(size=(P, P)))
+        lam = np.geomspace(1.0, 0.05, P)
+        lam[-1] = 10.0 ** -rng.uniform(16.0, 18.5)
+        A = (Q * lam) @ Q.T
+        A = 0.5 * (A + A.T)
+        d = np.sqrt(np.diag(A))
+        A = A / np.outer(d, d)
+        sc = 10 ** rng.uniform(3, 6, P)
+        F[:, :, e] = A * np.outer(sc, sc)
+    ldr = np.full(n, np.nan)
+    kap = np.full(n, np.inf)
+    with mp.workdps(50):
+        for e in range(n):
+            M = mp.matrix(F[:, :, e].tolist())
+            dn = [mp.sqrt(M[i, i]) for i in range(P)]
+            Mh = mp.matrix(P, P)
+            for i in range(P):
+                for j in range(P):
+                    Mh[i, j] = M[i, j] / (dn[i] * dn[j])
+            ev = mp.eigsy(Mh, eigvals_only=True)
+            if all(x > 0 for x in ev):
+                ldr[e] = float(mp.log(mp.det(M)))
+                kap[e] = float(max(ev) / min(ev))
+    pd = np.isfinite(ldr)
+    assert pd.sum() >= 20
+    for method in ("cho_svd", "svd"):
+        g = _gpu(lib, F, method=method)
+        g0 = _gpu(lib, F, method="cho")
+        fell = (g0["status"] == 2) & pd & np.isfinite(g["logdet"])
+        assert fell.sum() >= 3, f"{method}: only {fell.sum()} positive-definite matrices took the SVD"
+        tol = 1.0 + np.log1p(1e3 * kap[fell] * U)
+        err = np.abs(g["logdet"][fell] - ldr[fell])
+        assert np.all(err <= tol), (method, err, ldr[fell])
+        print(f"{method}: {fell.sum()} positive-definite matrices by SVD, |ln det| "
+              f"{np.abs(ldr[fell]).min():.0f}-{np.abs(ldr[fell]).max():.0f}, max error {err.max():.2e}")
+        if method == "cho_svd":
+            assert np.all(g["status"][fell] == 32)
+        # where the FP64 Cholesky worked, both methods keep its ln det
+        chol = g0["status"] == 0
+        assert np.array_equal(g["logdet"][chol], g0["logdet"][chol])
+
+
 def test_eigen_decomposition_against_oracle(lib, orc):
     """Eigenvalues (ascending) and eigenvectors of the normalised matrices
     against mpmath's: well-separated spectra, both signs, the sign

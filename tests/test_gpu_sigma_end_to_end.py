@@ -1,0 +1,143 @@
+"""GPU: the parameter uncertainties end to end -- event parameters through
+the GPU Fisher matrix (gwf_fisher, or a plan) and the GPU inversion
+(gwf_covariance / the plan's inversion) -- against the oracle's Fisher
+matrix inverted by mpmath at 40 digits (sec. 4.1).
+
+How far sigma can agree is set by the Fisher matrices themselves: to first
+order a perturbation dGamma moves the covariance by dC = -C dGamma C, so on
+the unit-diagonal normalised matrix (whose smallest eigenvalue is at least
+1/kappa, its trace being P)
+
+    |dsigma_i / sigma_i| <= (1/2) ||dGamma^||_2 / lambda_min <= (P/2) kappa eps,
+
+eps the largest normalised Fisher error |dGamma_ij| / sqrt(Gamma_ii Gamma_jj)
+of the event; the FP64 inversion adds at most ~1e3 kappa u (u = 2^-53) on top
+(the bound of the same-matrix comparison in test_gpu_parity.py).
+
+  * Well-conditioned blocks (spins and deformabilities held fixed: the
+    9 x 9 block of Mc, eta, dL, theta, phi, iota, psi, tc, Phic, kappa
+    1e3-1e8 on the BNS catalogue): sigma within 1e-9 wherever kappa <= 1e5,
+    and within the bound above everywhere.
+  * Full 13 x 13 BNS matrices (kappa 1e10-1e14): every event within the
+    bound, no NaN where the oracle inverts.
+"""
+import numpy as np
+import pytest
+
+from paper_2207_06910_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+FIXED = (9, 10, 11, 12)
+KAPPA_WELL = 1e5
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2207_06910_amd import binding
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    binding.load()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def case(orc):
+    """24 events of the BNS catalogue on their full grids (2000-20000 points),
+    the oracle's Fisher matrices and their 40-digit inverses, whole and with
+    the spins and deformabilities fixed."""
+    full = synth.bns1e4()
+    idx = np.sort(np.random.default_rng(2207).choice(full.n, 24, replace=False))
+    wl = full.subset(idx)
+    ref = orc.fisher(wl)
+    F = ref["fisher"]
+    keep = [k for k in range(13) if k not in FIXED]
+    inv13 = orc.covariance(F, dps=40, method="cho_svd")
+    inv9 = orc.covariance(np.ascontiguousarray(F[np.ix_(keep, keep)]), dps=40)
+    return wl, ref, inv13, inv9
+
+
+def _eps(Fg, Fr):
+    d = np.sqrt(np.einsum("iie->ie", Fr))
+    return (np.abs(Fg - Fr) / (d[:, None, :] * d[None, :, :])).max(axis=(0, 1))
+
+
+def _check(g_sigma, ref_inv, eps, P, label, well=None):
+    ok = np.isfinite(ref_inv["sigma"]).all(axis=0)
+    assert ok.sum() >= len(ok) - 2, f"{label}: the oracle inverted only {ok.sum()} events"
+    assert np.all(np.isfinite(g_sigma[:, ok])), f"{label}: NaN sigma where the oracle inverts"
+    rel = np.abs(g_sigma[:, ok] / ref_inv["sigma"][:, ok] - 1).max(axis=0)
+    kap = ref_inv["cond"][ok]
+    bound = 0.5 * P * kap * eps[ok] + 1e3 * kap * U
+    assert np.all(rel <= bound), (label, rel, bound)
+    if well is not None:
+        w = kap <= well
+        assert w.sum() >= 5, f"{label}: only {w.sum()} events with kappa <= {well:g}"
+        assert rel[w].max() <= 1e-9, f"{label}: sigma err {rel[w].max():.3e} at kappa <= {well:g}"
+        for lo in range(3, 9):
+            m = (kap >= 10.0 ** lo) & (kap < 10.0 ** (lo + 1))
+            if m.any():
+                print(f"{label}: kappa 1e{lo}-1e{lo + 1}: {m.sum()} events, max sigma err {rel[m].max():.2e}")
+    else:
+        print(f"{label}: kappa {kap.min():.1e}-{kap.max():.1e}, max sigma err {rel.max():.2e}, "
+              f"max err / bound {np.max(rel / bound):.2e}")
+    return rel
+
+
+def test_sigma_end_to_end_plain(lib, case):
+    """gwf_fisher then gwf_covariance on the GPU; the well-conditioned block
+    and the full matrices against the oracle's mpmath inverses."""
+    wl, ref, inv13, inv9 = case
+    dw = lib.DeviceWorkload(wl)
+    r = lib.fisher(dw)
+    g9 = lib.covariance(r["fisher"], r["status"], fixed=FIXED, method="cho")
+    g13 = lib.covariance(r["fisher"], r["status"], method="cho_svd")
+    torch.cuda.synchronize()
+    Fg = r["fisher"].cpu().numpy()
+    eps = _eps(Fg, ref["fisher"])
+    keep = [k for k in range(13) if k not in FIXED]
+    eps9 = _eps(Fg[np.ix_(keep, keep)], ref["fisher"][np.ix_(keep, keep)])
+    assert list(g9["out"]) == keep
+    _check(g9["sigma"].cpu().numpy(), inv9, eps9, 9, "plain, 9x9 block", well=KAPPA_WELL)
+    _check(g13["sigma"].cpu().numpy(), inv13, eps, 13, "plain, 13x13")
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_sigma_end_to_end_plan(lib, case, mixed):
+    """The batched form: the plan's Fisher matrices and its own inversion
+    (Cholesky with the SVD fallback) in one graph.  FP64: the same bars as
+    the plain form.  Mixed: its noise weight carries a relative error e of
+    about 1e-7, a positive factor per point, so (1 - e) Gamma <= Gamma' <=
+    (1 + e) Gamma and each sigma moves by at most e/2 whatever kappa; the bar
+    is 1e-3 (the benchmark spec's mixed tolerance) on events with kappa < 1e12, and
+    1e-6 on the well-conditioned block."""
+    wl, ref, inv13, inv9 = case
+    dw = lib.DeviceWorkload(wl)
+    plan = lib.Plan(dw, chunk=2048, mixed=mixed, inv_method="cho_svd")
+    out = plan.run(invert=True)
+    Fg_t = out["fisher"]
+    g9 = lib.covariance(Fg_t, torch.zeros_like(out["status"]), fixed=FIXED, method="cho")
+    torch.cuda.synchronize()
+    plan.close()
+    Fg = Fg_t.cpu().numpy()
+    st = out["status"].cpu().numpy()
+    assert np.all((st & ~32) == 0), st
+    sig13 = out["sigma"].cpu().numpy()
+    keep = [k for k in range(13) if k not in FIXED]
+    if not mixed:
+        eps = _eps(Fg, ref["fisher"])
+        eps9 = _eps(Fg[np.ix_(keep, keep)], ref["fisher"][np.ix_(keep, keep)])
+        _check(g9["sigma"].cpu().numpy(), inv9, eps9, 9, "plan FP64, 9x9 block", well=KAPPA_WELL)
+        _check(sig13, inv13, eps, 13, "plan FP64, 13x13")
+    else:
+        s9 = g9["sigma"].cpu().numpy()
+        rel9 = np.abs(s9 / inv9["sigma"] - 1).max(axis=0)
+        assert rel9.max() <= 1e-6, rel9.max()
+        ok = inv13["cond"] < 1e12
+        assert ok.sum() >= 10
+        rel = np.abs(sig13[:, ok] / inv13["sigma"][:, ok] - 1).max(axis=0)
+        assert np.all(np.isfinite(rel)) and rel.max() <= 1e-3, rel
+        print(f"plan mixed: 9x9 block max sigma err {rel9.max():.2e}; 13x13 at kappa < 1e12 "
+              f"({ok.sum()} events) {rel.max():.2e}")

@@ -519,6 +519,37 @@ gwf_status gwf_plan_get_info(const gwf_plan* plan, gwf_plan_info* info);
 /* Frees the plan and its workspace (NULL is allowed). */
 gwf_status gwf_plan_destroy(gwf_plan* plan);
 
+/* ------------------------------------------- no device allocation */
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the
+ * batched form of gwf_plan_fisher (work items of at most `chunk` points,
+ * persistent workgroups, each event's item sums combined in item order)
+ * with its workspace in one fixed device array of GWF_STATIC_SCRATCH_BYTES
+ * per device, which the library holds from its load until the process ends.
+ * The work items are built on the device from the grid lengths, so the call
+ * allocates nothing, reads nothing back and never synchronises; there is no
+ * autotuning (chunk is the caller's) and no graph.  Outputs as for
+ * gwf_fisher with snr_th = 0 (the same kernels as a plan: for the same chunk
+ * the results equal gwf_plan_fisher's bit for bit).
+ *   chunk     points per work item, a positive multiple of 256
+ *   npts_max  an upper bound of the catalogue's grid lengths; an event with a
+ *             longer grid gets GWF_EV_INVALID_PARAM and a zero Fisher matrix
+ * The workspace needs, in 256-byte aligned parts, n x 1048 bytes of event
+ * constants, n x n_site x 480 of site constants, 4 (n + 1) of item offsets,
+ * and 16 + 8 NACC bytes per work item (NACC = 91 with GWF_TIDAL, else 69)
+ * for n ceil(npts_max / chunk) items, plus 256; a call needing more than
+ * GWF_STATIC_SCRATCH_BYTES returns GWF_E_INVALID_ARG before any launch (the
+ * 10^4 neutron-star binaries of 2000-20000 points on three sites need
+ * about 41 MB with chunk 16384).  Every call on a device uses the same
+ * array: calls that overlap on one device (different streams, or threads)
+ * race and must be serialised by the caller; each call rewrites everything
+ * it reads. */
+#define GWF_STATIC_SCRATCH_BYTES (64ll << 20)
+
+gwf_status gwf_fisher_static(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
+                             uint32_t flags, int32_t chunk, int32_t npts_max, double* fisher, double* snr,
+                             int32_t* status, void* stream);
+
 /* Number of interferometers of a network (T sites count 3); -1 if invalid. */
 int32_t gwf_network_n_ifo(const gwf_network* net);
 

@@ -117,6 +117,9 @@ def load():
         lib.gwf_plan_create.restype = i32
         lib.gwf_plan_fisher.argtypes = [vp, vp, vp, vp, d, vp, vp, vp, vp, vp]
         lib.gwf_plan_fisher.restype = i32
+        lib.gwf_fisher_static.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
+                                          ctypes.POINTER(Grid), ctypes.c_uint32, i32, i32, vp, vp, vp, vp]
+        lib.gwf_fisher_static.restype = i32
         lib.gwf_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         lib.gwf_plan_get_info.restype = i32
         lib.gwf_plan_destroy.argtypes = [vp]
@@ -477,6 +480,28 @@ def fisher_adjoint(dw: DeviceWorkload, gbar, status=None, w_snr=1.0, w_fisher=1.
                                      dw.flags, _ptr(gbar), _ptr(status), float(w_snr),
                                      float(w_fisher), _ptr(res["grad_event"]), _ptr(res["grad"]),
                                      _stream(stream)), "gwf_fisher_adjoint")
+    return res
+
+
+def fisher_static(dw: DeviceWorkload, chunk=4096, npts_max=None, mixed=False, stream=None, out=None):
+    """The batched form without device allocation (gwf_fisher_static): Fisher
+    [P][P][N], SNR and status of the workload, the workspace in the library's
+    fixed device array.  ``npts_max`` bounds the grid lengths (default: the
+    host workload's longest grid)."""
+    import torch
+    dev = dw.par.device
+    P = 13 if dw.flags & TIDAL else 11
+    res = out if out is not None else {}
+    res.setdefault("fisher", torch.empty((P, P, dw.n), dtype=torch.float64, device=dev))
+    res.setdefault("snr", torch.empty(dw.n, dtype=torch.float64, device=dev))
+    res.setdefault("status", torch.empty(dw.n, dtype=torch.int32, device=dev))
+    if npts_max is None:
+        npts_max = int(np.max(dw.wl.npts))
+    ev, net, grid, keep = dw.descriptors()
+    _check(load().gwf_fisher_static(ctypes.byref(ev), ctypes.byref(net), ctypes.byref(grid),
+                                    dw.flags | (MIXED if mixed else 0), int(chunk), int(npts_max),
+                                    _ptr(res["fisher"]), _ptr(res["snr"]), _ptr(res["status"]),
+                                    _stream(stream)), "gwf_fisher_static")
     return res
 
 

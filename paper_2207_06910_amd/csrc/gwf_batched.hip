@@ -35,7 +35,8 @@ __global__ void setup_kernel(SetupArgs a) {
   for (int r = 0; r < 13; ++r) p[r] = (r < 11 || tidal) ? a.par[r * a.ld + t] : 0.0;
   EventC ec;
   event_setup(p, a.fmin[t], a.fmax ? a.fmax[t] : 0.0, a.npts[t], a.flags, ec);
-  if (!ec.status && a.npts[t] != a.npts_plan[t]) ec.status = kEvInvalid;   // grid changed since plan creation
+  if (!ec.status && (a.npts[t] != a.npts_plan[t] || a.npts[t] > a.npts_max))
+    ec.status = kEvInvalid;   // grid changed since the items were built, or longer than they allow
   a.evc[t] = ec;
   a.status[t] = ec.status;
   if (!ec.status)
@@ -54,11 +55,12 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void items_kernel(Item
   __shared__ int32_t item;
   const int tid = threadIdx.x;
   const int n_site = a.n_site;
+  const int32_t n_items = a.n_items_dev ? *a.n_items_dev : a.n_items;
   for (;;) {
     if (tid == 0) item = atomicAdd(a.counter, 1);
     __syncthreads();
     const int32_t it = item;
-    if (it >= a.n_items) break;                  // every wave leaves on the same item count
+    if (it >= n_items) break;                    // every wave leaves on the same item count
     const Item w = a.items[__builtin_amdgcn_readfirstlane(it)];
     const int32_t ew = __builtin_amdgcn_readfirstlane(w.e);
     const int32_t k0 = __builtin_amdgcn_readfirstlane(w.k0);
@@ -105,6 +107,71 @@ __global__ void combine_kernel(CombineArgs a) {
   a.fisher[((int64_t)c * P + r) * a.n + e] = s;
   // the set-up kernel wrote the parameter status; a non-finite sum adds its bit
   if (!st0 && !finite(s)) atomicOr(a.status + e, (int32_t)kEvNonFinite);
+}
+
+constexpr int kScanBlock = 1024;
+
+// One workgroup: item counts per event and their exclusive prefix sum, tile
+// by tile of kScanBlock events (wavefront scans, then the wavefront totals,
+// then the running carry of the earlier tiles).
+__global__ __launch_bounds__(kScanBlock) void items_scan_kernel(const int32_t* __restrict__ npts, int64_t n,
+                                                                int32_t chunk, int32_t npts_max,
+                                                                int32_t* __restrict__ first,
+                                                                int32_t* __restrict__ n_items) {
+  __shared__ int32_t wtot[kScanBlock / 64];
+  __shared__ int32_t carry;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < n; base += kScanBlock) {
+    const int64_t e = base + tid;
+    int32_t c = 0;
+    if (e < n) {
+      int32_t m = npts[e];
+      if (m < 2 || m > npts_max) m = 2;
+      c = (m - 1) / chunk + 1;
+    }
+    int32_t x = c;                                   // inclusive scan within the wavefront
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wtot[wave] = x;
+    __syncthreads();
+    int32_t before = carry;                          // earlier tiles and earlier wavefronts
+    for (int w = 0; w < wave; ++w) before += wtot[w];
+    if (e < n) first[e] = before + x - c;
+    __syncthreads();                                 // every lane has read carry and wtot
+    if (tid == kScanBlock - 1) carry = before + x;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    first[n] = carry;
+    *n_items = carry;
+  }
+}
+
+// One lane per event writes its items (slot = position in event order).
+__global__ void items_fill_kernel(const int32_t* __restrict__ npts, int64_t n, int32_t chunk, int32_t npts_max,
+                                  const int32_t* __restrict__ first, Item* __restrict__ items) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  int32_t m = npts[e];
+  if (m < 2 || m > npts_max) m = 2;
+  const int32_t f0 = first[e], f1 = first[e + 1];
+  for (int32_t i = f0, k0 = 0; i < f1; ++i, k0 += chunk)
+    items[i] = Item{(int32_t)e, k0, min(m, k0 + chunk), i};
+}
+
+hipError_t launch_items_build(const int32_t* npts, int64_t n, int32_t chunk, int32_t npts_max, int32_t* first,
+                              int32_t* n_items, Item* items, hipStream_t s) {
+  hipLaunchKernelGGL(items_scan_kernel, dim3(1), dim3(kScanBlock), 0, s, npts, n, chunk, npts_max, first, n_items);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(items_fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, npts, n, chunk, npts_max,
+                     first, items);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {

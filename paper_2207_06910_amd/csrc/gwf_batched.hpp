@@ -17,6 +17,8 @@ struct SetupArgs {
   const double* fmax;
   const int32_t* npts;
   const int32_t* npts_plan;   // grid lengths the items were built from
+  int32_t npts_max;           // longer grids are flagged invalid (their items were
+                              // sized as for a two-point grid)
   const uint8_t* active;      // [n_ifo][ld] or NULL: interferometers taking part
   NetDesc net;
   uint32_t flags;
@@ -31,6 +33,7 @@ struct ItemsArgs {
   int32_t n_site;
   const Item* items;
   int32_t n_items;
+  const int32_t* n_items_dev; // NULL, or the item count in device memory (read in place of n_items)
   int32_t* counter;           // work-item counter, zeroed before the launch
   double* partial;            // [n_items][NACC]
 };
@@ -47,6 +50,12 @@ struct CombineArgs {
 };
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+// Work items built on the device: each event's count of items of at most
+// `chunk` points (a grid outside 2..npts_max counts as two points), their
+// exclusive prefix sum first[0..n] and the total in *n_items (one
+// workgroup), then the items themselves, in slot order.
+hipError_t launch_items_build(const int32_t* npts, int64_t n, int32_t chunk, int32_t npts_max, int32_t* first,
+                              int32_t* n_items, Item* items, hipStream_t s);
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
 hipError_t launch_items(const ItemsArgs& a, bool tidal, bool rot, bool mixed, int n_wg, hipStream_t s);
 hipError_t launch_combine(const CombineArgs& a, bool tidal, hipStream_t s);

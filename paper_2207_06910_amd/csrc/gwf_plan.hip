@@ -117,6 +117,7 @@ gwf_status enqueue(gwf_plan* p, const Outs& o, hipStream_t s) {
   SetupArgs sa{};
   sa.par = p->ev.par; sa.ld = p->ev.ld; sa.n = p->n;
   sa.fmin = p->grid.fmin; sa.fmax = p->grid.fmax; sa.npts = p->grid.npts; sa.npts_plan = p->npts_plan;
+  sa.npts_max = 0x7fffffff;
   sa.net = p->net; sa.flags = p->flags; sa.evc = p->evc; sa.sic = p->sic; sa.status = o.status;
   sa.active = p->ev.active;
   hipError_t err = launch_setup(sa, s);

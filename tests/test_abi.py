@@ -96,6 +96,14 @@ def test_invalid_arguments_rejected_on_host():
         opt = binding.PlanOptions(0, 0, 1, 0, m, 0)
         assert lib.gwf_plan_create(B(ev), B(net), B(grid), 0, B(opt), B(plan), None) == 1
         assert b"inv_method" in lib.gwf_last_error()
+    # the static-workspace form: outputs, item length, grid bound, workspace size
+    assert lib.gwf_fisher_static(B(ev), B(net), B(grid), 0, 4096, 100, None, 8, 8, None) == 1
+    assert lib.gwf_fisher_static(B(ev), B(net), B(grid), 0, 100, 100, 8, 8, 8, None) == 1
+    assert lib.gwf_fisher_static(B(ev), B(net), B(grid), 0, 4096, 1, 8, 8, 8, None) == 1
+    big = binding.Events(10 ** 6, 10 ** 6, 1, None)
+    assert lib.gwf_fisher_static(B(big), B(net), B(grid), 0, 4096, 20000, 8, 8, 8, None) == 1
+    assert b"workspace" in lib.gwf_last_error()
+    assert lib.gwf_fisher_static(B(ev), B(net), B(gx), 0, 4096, 100, 8, 8, 8, None) == 2
     # an unknown noise-curve kind
     s = synth.site("H1")
     n3, k3 = binding.network([s])

@@ -49,6 +49,10 @@ def load():
                                      _I, ctypes.c_int, ctypes.c_int, _L, ctypes.c_int64, _D]
         lib.orc_waveform_deriv.argtypes = lib.orc_waveform.argtypes
         lib.orc_set_explicit_grid.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        lib.orc_set_psd_tables.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p]
+        lib.orc_noise_weight.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                         _D, _D, _D]
         lib.orc_fisher_tangent.argtypes = [ctypes.c_int64, _D, ctypes.c_int64, _D, ctypes.c_int, _D,
                                            _D, _D, _I, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int, ctypes.c_int, _D, _D]
@@ -199,6 +203,46 @@ class _grid:
         return False
 
 
+class _tables:
+    """While active, the sites' sampled noise curves (psd_kind 1 = PSD, 2 =
+    ASD, with psd_f and psd_S) are used in place of the analytic PSD."""
+
+    def __init__(self, sites):
+        self.sites = list(sites)
+        self.kind = np.array([int(getattr(s, "psd_kind", 0)) for s in self.sites], dtype=np.int32)
+        self.f = [None if k == 0 else np.ascontiguousarray(s.psd_f, dtype=np.float64)
+                  for k, s in zip(self.kind, self.sites)]
+        self.S = [None if k == 0 else np.ascontiguousarray(s.psd_S, dtype=np.float64)
+                  for k, s in zip(self.kind, self.sites)]
+
+    def __enter__(self):
+        if self.kind.any():
+            ns = len(self.sites)
+            self.n = np.array([0 if f is None else len(f) for f in self.f], dtype=np.int64)
+            self.fp = (ctypes.c_void_p * ns)(*[None if f is None else f.ctypes.data for f in self.f])
+            self.Sp = (ctypes.c_void_p * ns)(*[None if x is None else x.ctypes.data for x in self.S])
+            load().orc_set_psd_tables(ns, self.kind.ctypes.data, self.n.ctypes.data,
+                                      ctypes.cast(self.fp, ctypes.c_void_p), ctypes.cast(self.Sp, ctypes.c_void_p))
+        return self
+
+    def __exit__(self, *exc):
+        if self.kind.any():
+            load().orc_set_psd_tables(0, None, None, None, None)
+        return False
+
+
+def noise_weight(site, f, w):
+    """4 w / S_n(f) of one site's noise curve (analytic or sampled) at
+    frequencies f with trapezoid weights w; zero where a sampled curve does
+    not reach."""
+    f = _f64(f)
+    w = _f64(w)
+    out = np.zeros_like(f)
+    with _tables([site]):
+        load().orc_noise_weight(float(site.S0), float(site.f0), 0, len(f), _p(f), _p(w), _p(out))
+    return out
+
+
 def restrict_rows(F, par_mask):
     """Each event's Fisher matrix over its own parameter set: in F[P][P][N]
     (in place), the rows and columns of parameters outside event e's set
@@ -233,7 +277,7 @@ def fisher(wl, want_fisher=True, per_ifo=False, nthreads=0):
     Fi = np.zeros((ni, P, P, n)) if (want_fisher and per_ifo) else None
     act = getattr(wl, "active", None)
     act = None if act is None else np.ascontiguousarray(act, dtype=np.uint8)
-    with _grid(wl):
+    with _grid(wl), _tables(wl.sites):
         load().orc_fisher(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
                           npts.ctypes.data_as(_I), None if act is None else act.ctypes.data_as(ctypes.c_void_p),
                           wl.flags, int(nthreads), _p(snr), _p(snr_ifo), _p(F), _p(Fi))
@@ -327,7 +371,7 @@ def fisher_tangent(wl, site, which, nthreads=0):
     F = np.zeros((2, P, P, n))
     act = getattr(wl, "active", None)
     act = None if act is None else np.ascontiguousarray(act, dtype=np.uint8)
-    with _grid(wl):
+    with _grid(wl), _tables(wl.sites):
         load().orc_fisher_tangent(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
                                   npts.ctypes.data_as(_I), None if act is None else act.ctypes.data_as(ctypes.c_void_p),
                                   wl.flags, int(nthreads), int(site), int(which), _p(snr2), _p(F))

@@ -29,6 +29,7 @@
 // numbers (gradients of Fisher figures of merit w.r.t. detector parameters)
 // and on std::complex<double> (complex-step derivative checks).
 
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <complex>
@@ -168,24 +169,26 @@ template <class T>
 struct Ifo {
   T lat, lon, gamma;   // radians; gamma = arm-bisector angle from local East
   double zeta;         // opening angle of the arms
-  T S0;                // analytic PSD scale [1/Hz]
+  T S0;                // analytic PSD scale [1/Hz], or the scale of a sampled curve
   double f0;           // analytic PSD knee [Hz]
+  int site;            // index of the site it belongs to (its noise curve)
 };
 
 // Expand sites [lat, lon, gamma, zeta, shape, S0, f0] into interferometers.
 // An L site is one interferometer.  A triangle site is three co-located
 // interferometers with 60-degree arms in a closed loop (sec. 3.1); the first
 // arm points at gamma, so the first interferometer's bisector is at
-// gamma + 30 deg and the other two follow at 120 deg steps.
-inline std::vector<Ifo<double>> expand_sites(int n_site, const double* s) {
+// gamma + 30 deg and the other two follow at 120 deg steps.  first_site is
+// the index of s's first site in the network.
+inline std::vector<Ifo<double>> expand_sites(int n_site, const double* s, int first_site = 0) {
   std::vector<Ifo<double>> out;
   for (int i = 0; i < n_site; ++i) {
     const double* r = s + 7 * i;
     if (r[4] == 1.0) {
       for (int k = 0; k < 3; ++k)
-        out.push_back({r[0], r[1], r[2] + PI / 6.0 + 2.0 * PI * k / 3.0, PI / 3.0, r[5], r[6]});
+        out.push_back({r[0], r[1], r[2] + PI / 6.0 + 2.0 * PI * k / 3.0, PI / 3.0, r[5], r[6], first_site + i});
     } else {
-      out.push_back({r[0], r[1], r[2], r[3], r[5], r[6]});
+      out.push_back({r[0], r[1], r[2], r[3], r[5], r[6], first_site + i});
     }
   }
   return out;
@@ -337,6 +340,59 @@ T psd(const T& S0, double f0, double f) {
   return S0 * shape;
 }
 
+// Sampled noise curves (sec. 3.1: a detector's PSD or ASD read from a file,
+// is_ASD telling which): per site, n frequencies f[] (increasing) and values
+// S[] there, the PSD itself (kind 1) or the ASD (kind 2), squared into a
+// PSD.  The PSD between two samples is the straight line through them (the
+// paper does not say how it interpolates; linear in f is the reading).  A
+// frequency outside the sampled range is one the detector does not see: its
+// point gets no weight.  The end samples are taken to cover frequencies
+// within a relative 1e-12 of them, so that a grid starting or ending on a
+// sampled frequency keeps that point whatever the rounding of its frequency.
+// Set by orc_set_psd_tables for the calls that follow; kind 0 = analytic.
+constexpr int MAX_SITES = 8;
+static int g_tab_kind[MAX_SITES] = {};
+static int64_t g_tab_n[MAX_SITES] = {};
+static const double* g_tab_f[MAX_SITES] = {};
+static const double* g_tab_S[MAX_SITES] = {};
+
+// The sampled PSD of site i at f (before the scale S0); false outside the range.
+inline bool table_psd(int i, double f, double& S) {
+  const int64_t n = g_tab_n[i];
+  const double* tf = g_tab_f[i];
+  const double* tS = g_tab_S[i];
+  const double eps = 1e-12;
+  if (f < tf[0] * (1.0 - eps) || f > tf[n - 1] * (1.0 + eps)) return false;
+  // the interval [tf[j], tf[j+1]] holding f (the first or last one at the ends):
+  // j is the last sample at or below f
+  int64_t j = (int64_t)(std::upper_bound(tf, tf + n, f) - tf) - 1;
+  if (j < 0) j = 0;
+  if (j > n - 2) j = n - 2;
+  double s0 = tS[j], s1 = tS[j + 1];
+  if (g_tab_kind[i] == 2) {
+    s0 = s0 * s0;
+    s1 = s1 * s1;
+  }
+  double t = (f - tf[j]) / (tf[j + 1] - tf[j]);
+  if (t < 0.0) t = 0.0;
+  if (t > 1.0) t = 1.0;
+  S = s0 + (s1 - s0) * t;
+  return true;
+}
+
+// The noise weight 4 w / S_n(f) of one interferometer at a grid point of
+// trapezoid weight w (zero where a sampled curve does not reach).
+template <class T>
+T noise_weight(const Ifo<T>& ifo, double w, double f) {
+  const int i = ifo.site;
+  if (i >= 0 && i < MAX_SITES && g_tab_kind[i] != 0) {
+    double S;
+    if (!table_psd(i, f, S)) return T(0.0);
+    return T(4.0 * w) / (ifo.S0 * S);
+  }
+  return T(4.0 * w) / psd(ifo.S0, ifo.f0, f);
+}
+
 // Strain h_i(f) at one interferometer: restricted amplitude (Newtonian
 // order, sqrt(5/24) pi^{-2/3} (G Mc/c^3)^{5/6} f^{-7/6} c/dL) times the
 // pattern-weighted polarisations, h+ ~ (1+cos^2 iota)/2, hx ~ i cos iota,
@@ -449,7 +505,7 @@ void fisher_event(const double* par, double tc_s, const std::vector<Ifo<double>>
     for (int k = 0; k < n; ++k) {
       S hre, him;
       strain(s, ifos[d], f[k], flags, hre, him);
-      double om = 4.0 * w[k] / psd(ifos[d].S0, ifos[d].f0, f[k]);
+      double om = noise_weight(ifos[d], w[k], f[k]);
       snr.add(om * (hre.v * hre.v + him.v * him.v));
       for (int a = 0; a < P; ++a)
         for (int b = a; b < P; ++b)
@@ -489,7 +545,7 @@ void fisher_event_tangent(const double* par, double tc_s, const std::vector<Ifo<
       if (!on[d]) break;                       // interferometer off for this event
       S hre, him;
       strain(s, ifos[d], f[k], flags, hre, him);
-      D1 om = D1(4.0 * w[k]) / psd(ifos[d].S0, ifos[d].f0, f[k]);
+      D1 om = noise_weight(ifos[d], w[k], f[k]);
       D1 a = om * (hre.v * hre.v + him.v * him.v);
       sv.add(a.v); st.add(a.d[0]);
       for (int i = 0; i < P; ++i)
@@ -516,7 +572,7 @@ void snr_event(const double* par, double tc_s, const std::vector<Ifo<double>>& i
     for (int k = 0; k < n; ++k) {
       double hre, him;
       strain(s, ifos[d], f[k], flags, hre, him);
-      snr.add(4.0 * w[k] / psd(ifos[d].S0, ifos[d].f0, f[k]) * (hre * hre + him * him));
+      snr.add(noise_weight(ifos[d], w[k], f[k]) * (hre * hre + him * him));
     }
     snr2_ifo[d] = snr.get();
   }
@@ -687,6 +743,29 @@ int orc_strain_plain(const double* par, double tc_s, double dt, int n_site, cons
 // (the detector strain of sec. 3.1 on the grids of sec. 2.2), written to
 // h[((i * total) + offsets[e] + k) * 2 + {0,1}] for interferometer i, grid
 // point k (offsets[n] are the events' first columns).  fmax NULL means each grid ends at the event's cut frequency.
+// Sampled noise curves of the sites (see table_psd) for the calls that
+// follow: kind[i] 0 (analytic), 1 (PSD) or 2 (ASD) for site i, and for the
+// sampled ones n[i] frequencies f[i][] with values S[i][]; n_site = 0
+// clears them.  The arrays must stay alive while they are set.
+int orc_set_psd_tables(int n_site, const int32_t* kind, const int64_t* n, const double* const* f,
+                       const double* const* S) {
+  for (int i = 0; i < MAX_SITES; ++i) {
+    const bool set = i < n_site && kind && kind[i] != 0;
+    g_tab_kind[i] = set ? kind[i] : 0;
+    g_tab_n[i] = set ? n[i] : 0;
+    g_tab_f[i] = set ? f[i] : nullptr;
+    g_tab_S[i] = set ? S[i] : nullptr;
+  }
+  return 0;
+}
+
+// The noise weight of an L site's interferometer (site 0 of the tables set)
+// or of the analytic PSD at frequencies f with trapezoid weights w.
+void orc_noise_weight(double S0, double f0, int site, int nf, const double* f, const double* w, double* out) {
+  Ifo<double> g{0.0, 0.0, 0.0, 0.0, S0, f0, site};
+  for (int k = 0; k < nf; ++k) out[k] = noise_weight(g, w[k], f[k]);
+}
+
 int orc_set_explicit_grid(const int64_t* off, const double* f) {
   g_grid_off = off;
   g_grid_f = f;
@@ -745,10 +824,10 @@ int orc_fisher_tangent(int64_t n, const double* par, int64_t ld, const double* t
   for (int i = 0; i < n_site; ++i) {
     const double* r = sites + 7 * i;
     const double seed = (i == site) ? 1.0 : 0.0;
-    for (const Ifo<double>& g : expand_sites(1, r)) {
+    for (const Ifo<double>& g : expand_sites(1, r, i)) {
       Ifo<D1> t;
       t.lat = D1(g.lat); t.lon = D1(g.lon); t.gamma = D1(g.gamma); t.zeta = g.zeta;
-      t.S0 = D1(g.S0); t.f0 = g.f0;
+      t.S0 = D1(g.S0); t.f0 = g.f0; t.site = g.site;
       if (which == 0) t.lat.d[0] = seed;
       if (which == 1) t.lon.d[0] = seed;
       if (which == 2) t.gamma.d[0] = seed;

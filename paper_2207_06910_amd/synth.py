@@ -38,6 +38,8 @@ PAR = {n: i for i, n in enumerate(PAR_NAMES)}
 SHAPE_L = 0
 SHAPE_T = 1
 
+PSD_ANALYTIC, PSD_TABLE, ASD_TABLE = 0, 1, 2
+
 FLAG_EARTH_ROT = 1
 FLAG_TIDAL = 2
 
@@ -71,12 +73,23 @@ class Site:
     gamma: float
     zeta: float
     shape: int
-    S0: float = 1e-49      # analytic PSD scale [1/Hz]
+    S0: float = 1e-49      # analytic PSD scale [1/Hz]; the scale of a sampled curve
     f0: float = 215.0      # analytic PSD knee [Hz]
+    psd_kind: int = PSD_ANALYTIC     # or PSD_TABLE / ASD_TABLE: a sampled noise curve
+    psd_f: np.ndarray | None = None  # float64 [m], increasing [Hz] (sampled curves)
+    psd_S: np.ndarray | None = None  # float64 [m], the PSD [1/Hz] or ASD [1/sqrt(Hz)] there
 
     @property
     def n_ifo(self) -> int:
         return 3 if self.shape == SHAPE_T else 1
+
+    def with_curve(self, f, S, asd=False, scale=1.0) -> "Site":
+        """The same site with a sampled noise curve (the paper's psd_path
+        file, with is_ASD): frequencies f and values S, scaled by `scale`."""
+        import dataclasses
+        return dataclasses.replace(self, S0=float(scale), psd_kind=ASD_TABLE if asd else PSD_TABLE,
+                                   psd_f=np.ascontiguousarray(f, dtype=np.float64),
+                                   psd_S=np.ascontiguousarray(S, dtype=np.float64))
 
 
 @dataclass

@@ -370,6 +370,142 @@ def test_psd_positive(orc):
         assert min(vals) > 0
 
 
+def test_psd_values_fixed_by_the_configuration_formula(orc):
+    """The configurations' analytic PSD, S0 [x^-4.14 - 5 x^-2 + 111 (1 - x^2 +
+    x^4/2)/(1 + x^2/2)] with x = f/f0, at points where it is known without
+    evaluating it term by term: at the knee x = 1 the three terms are 1, -5
+    and 111 (1/2)/(3/2) = 37, so S = 33 S0; far below the knee the x^-4.14
+    term takes over (S x^4.14 -> 1, the -5 x^-2 term the leading correction)
+    and far above it the rational term (S / (111 x^2) -> 1); and for
+    f0 = 215 Hz its minimum is 32.4 S0 near 228 Hz.  A dropped term or a
+    flipped sign moves at least one of these."""
+    from scipy.optimize import minimize_scalar
+    for f0 in (100.0, 215.0, 300.0):
+        assert abs(orc.psd(1.0, f0, f0) - 33.0) < 1e-13
+        assert abs(orc.psd(2.5e-49, f0, f0) / 2.5e-49 - 33.0) < 1e-13
+        x = 1e-3
+        assert abs(orc.psd(1.0, f0, x * f0) * x ** 4.14 - 1.0) < 6 * x ** 2.14
+        x = 1e3
+        assert abs(orc.psd(1.0, f0, x * f0) / (111.0 * x ** 2) - 1.0) < 5.0 / x ** 2
+    r = minimize_scalar(lambda f: orc.psd(1.0, 215.0, f), bounds=(100.0, 400.0), method="bounded",
+                        options={"xatol": 1e-6})
+    assert abs(r.x - 228.0) < 1.0 and abs(r.fun - 32.4) < 0.05, (r.x, r.fun)
+
+
+# ------------------------------------------------------ sampled noise curves (sec. 3.1)
+def _curve_site(name="H1", f=None, S=None, asd=False, scale=1.0):
+    return synth.site(name).with_curve(f, S, asd=asd, scale=scale)
+
+
+def test_sampled_curve_at_nodes_and_on_a_line(orc):
+    """Linear interpolation, checked where its value is known exactly: at the
+    samples themselves the weight is that of the sampled value, and a curve
+    that is a straight line in f, S = a + b f, sampled at its two ends, gives
+    4 w / (a + b f) everywhere between them; an ASD table is squared first."""
+    f = np.geomspace(5.0, 900.0, 64)
+    S = np.array([orc.psd(1e-49, 215.0, x) for x in f])
+    w = np.full_like(f, 0.37)
+    got = orc.noise_weight(_curve_site(f=f, S=S), f, w)
+    np.testing.assert_allclose(got, 4 * 0.37 / S, rtol=2e-16)
+    got = orc.noise_weight(_curve_site(f=f, S=np.sqrt(S), asd=True), f, w)
+    np.testing.assert_allclose(got, 4 * 0.37 / S, rtol=5e-16)
+    a, b = 3e-47, 2e-49
+    ends = np.array([7.0, 1300.0])
+    fg = np.geomspace(7.0, 1300.0, 501)
+    wg = np.linspace(0.1, 3.0, 501)
+    got = orc.noise_weight(_curve_site(f=ends, S=a + b * ends), fg, wg)
+    np.testing.assert_allclose(got, 4 * wg / (a + b * fg), rtol=4e-16)
+    got = orc.noise_weight(_curve_site(f=ends, S=np.sqrt(a + b * ends), asd=True), fg, wg)
+    # the ASD is squared at the samples: the line goes through their squares
+    np.testing.assert_allclose(got, 4 * wg / (a + b * fg), rtol=4e-16)
+    # the scale multiplies the curve
+    got = orc.noise_weight(_curve_site(f=ends, S=a + b * ends, scale=4.0), fg, wg)
+    np.testing.assert_allclose(got, wg / (a + b * fg), rtol=4e-16)
+
+
+def test_sampled_curve_outside_its_range_weighs_nothing(orc):
+    """Grid points below the first or above the last sampled frequency get
+    zero weight; the end samples themselves (and frequencies within 1e-12 of
+    them) are inside."""
+    f = np.array([20.0, 50.0, 400.0])
+    S = np.array([1e-46, 1e-47, 3e-47])
+    fg = np.array([19.0, 20.0 * (1 - 5e-13), 20.0, 30.0, 400.0, 400.0 * (1 + 5e-13), 401.0, 1000.0])
+    got = orc.noise_weight(_curve_site(f=f, S=S), fg, np.ones_like(fg))
+    assert got[0] == 0.0 and got[-1] == 0.0 and got[-2] == 0.0
+    np.testing.assert_allclose(got[1:6], 4.0 / np.array([1e-46, 1e-46, 1e-46 + (1e-47 - 1e-46) / 3, 3e-47, 3e-47]),
+                               rtol=1e-11)
+
+
+def test_dense_sampled_curve_reproduces_the_analytic_fisher(orc):
+    """The analytic PSD sampled on a log grid and linearly interpolated
+    differs from it by at most h^2/8 max|S''| on each interval (the remainder
+    of linear interpolation; S'' taken by central differences on a fine
+    mesh).  Every grid point's weight then moves by a relative e_k <= e, so
+    SNR^2 moves by at most e and each Fisher element by at most
+    e sqrt(Gamma_ii Gamma_jj) (Cauchy-Schwarz on the weighted sums).  Also
+    the ASD form of the same curve, and the curve cut to [30, 300] Hz
+    against the analytic per-point contributions summed over that band."""
+    wl = synth.bns1e4(n=3).with_npts(600)
+    ref = orc.fisher(wl, per_ifo=True)
+    nodes = np.geomspace(1.5, 2500.0, 700)
+    sites = []
+    e_max = 0.0
+    for st in wl.sites:
+        S = np.array([orc.psd(st.S0, st.f0, x) for x in nodes])
+        sites.append(st.with_curve(nodes, S / st.S0, scale=st.S0))
+        for a, b in zip(nodes[:-1], nodes[1:]):
+            m = np.linspace(a, b, 9)
+            hh = (b - a) / 64
+            d2 = max(abs(orc.psd(1.0, st.f0, x + hh) - 2 * orc.psd(1.0, st.f0, x) + orc.psd(1.0, st.f0, x - hh))
+                     / hh ** 2 for x in m)
+            smin = min(orc.psd(1.0, st.f0, x) for x in m)
+            e_max = max(e_max, 1.02 * (b - a) ** 2 / 8 * d2 / smin)
+    assert e_max < 1e-3
+    for asd in (False, True):
+        w2 = wl.subset(np.arange(wl.n))
+        w2.sites = [s.with_curve(s.psd_f, np.sqrt(s.psd_S) if asd else s.psd_S, asd=asd, scale=s.S0)
+                    for s in sites]
+        got = orc.fisher(w2, per_ifo=True)
+        np.testing.assert_array_less(np.abs(got["snr"] ** 2 / ref["snr"] ** 2 - 1), e_max)
+        d = np.sqrt(np.einsum("iie->ie", ref["fisher"]))
+        err = np.abs(got["fisher"] - ref["fisher"]) / (d[:, None, :] * d[None, :, :])
+        assert err.max() <= e_max, (asd, err.max(), e_max)
+        assert err.max() > 0.0                       # the curve is not the formula
+    # the band cut: SNR^2 of the points in [30, 300] Hz only
+    lo, hi = 30.0, 300.0
+    band = np.geomspace(lo, hi, 1500)
+    w3 = wl.subset(np.arange(wl.n))
+    w3.sites = [s.with_curve(band, np.array([orc.psd(1.0, s.f0, x) for x in band]), scale=s.S0) for s in wl.sites]
+    got = orc.fisher(w3, want_fisher=False)
+    for e in range(wl.n):
+        p = wl.par[:, e]
+        fg, wg = orc.grid(wl.fmin[e], orc.cut_frequency(p[0], p[1]), int(wl.npts[e]))
+        h = orc.strain(p, wl.site_array(), fg, wl.flags, derivs=False)
+        ifo_site = [0, 0, 0, 1, 2]
+        tot = 0.0
+        for d in range(h.shape[0]):
+            st = wl.sites[ifo_site[d]]
+            inb = (fg >= lo) & (fg <= hi)
+            om = 4 * wg[inb] / np.array([orc.psd(st.S0, st.f0, x) for x in fg[inb]])
+            tot += np.sum(om * np.abs(h[d, inb]) ** 2)
+        assert abs(got["snr"][e] ** 2 / tot - 1) < 1e-4
+
+
+def test_sampled_curve_scale_derivative_closed_form(orc):
+    """With sampled curves, ln S0 scales the curve: dSNR^2 = -SNR_site^2 and
+    dGamma = -Gamma_site, as for the analytic PSD."""
+    wl = synth.bns1e4(n=2).with_npts(300)
+    nodes = np.geomspace(1.0, 3000.0, 300)
+    wl.sites = [s.with_curve(nodes, np.array([orc.psd(1.0, s.f0, x) for x in nodes]) * (1 + 0.1 * np.sin(nodes)),
+                             scale=s.S0) for s in wl.sites]
+    r = orc.fisher(wl, per_ifo=True)
+    for s, arms in ((0, [0, 1, 2]), (2, [4])):
+        t = orc.fisher_tangent(wl, s, 3)
+        np.testing.assert_allclose(t["snr2"][1], -np.sum(r["snr_ifo"][arms] ** 2, axis=0), rtol=1e-12)
+        Fs = r["fisher_ifo"][arms].sum(axis=0)
+        np.testing.assert_allclose(t["fisher"][1], -Fs, rtol=1e-10, atol=1e-12 * np.abs(Fs).max())
+
+
 # ---------------------------------------------------------------- Fisher
 def test_fisher_invariants(orc):
     """Exact identities of the discrete sums: Gamma_dLdL = SNR^2/dL^2,

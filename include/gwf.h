@@ -501,7 +501,9 @@ typedef struct gwf_plan_info {
                           call waits for that run to finish), else 0               */
 } gwf_plan_info;
 
-/* opt NULL: autotune both knobs, use a graph. */
+/* opt NULL: autotune both knobs, use a graph.  Sampled noise curves of the
+ * network (gwf_site psd_f, psd_S) are read at their addresses on every run:
+ * they must stay allocated, at the same addresses, for the plan's life. */
 gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const gwf_grid* grid,
                            uint32_t flags, const gwf_plan_options* opt, gwf_plan** plan,
                            void* stream);
@@ -535,7 +537,7 @@ gwf_status gwf_plan_destroy(gwf_plan* plan);
  *   npts_max  an upper bound of the catalogue's grid lengths; an event with a
  *             longer grid gets GWF_EV_INVALID_PARAM and a zero Fisher matrix
  * The workspace needs, in 256-byte aligned parts, n x 1048 bytes of event
- * constants, n x n_site x 480 of site constants, 4 (n + 1) of item offsets,
+ * constants, n x n_site x 512 of site constants, 4 (n + 1) of item offsets,
  * and 16 + 8 NACC bytes per work item (NACC = 91 with GWF_TIDAL, else 69)
  * for n ceil(npts_max / chunk) items, plus 256; a call needing more than
  * GWF_STATIC_SCRATCH_BYTES returns GWF_E_INVALID_ARG before any launch (the

@@ -18,6 +18,7 @@ GWF_OK, GWF_E_INVALID_ARG, GWF_E_UNSUPPORTED, GWF_E_HIP, GWF_E_NOMEM = 0, 1, 2, 
 EV_INVALID_PARAM, EV_NOT_PD, EV_ILL_COND, EV_NONFINITE, EV_SKIPPED_SNR = 1, 2, 4, 8, 16
 EARTH_ROT, TIDAL, MIXED, ECCENTRIC = 1, 2, 4, 8
 SHAPE_L, SHAPE_T = 0, 1
+PSD_ANALYTIC, PSD_TABLE, ASD_TABLE = 0, 1, 2
 NPAR_SRC, NPAR_MAX = 13, 14
 
 
@@ -157,18 +158,40 @@ def _dev_f64(t):
     return t
 
 
-def network(sites) -> tuple:
+def network(sites, curves=None, geometry_only=False) -> tuple:
     """ctypes network descriptor from a list of objects with lat, lon, gamma,
-    zeta, shape, S0, f0 attributes (radians, 1/Hz, Hz)."""
+    zeta, shape, S0, f0 attributes (radians, 1/Hz, Hz) and optionally
+    psd_kind; ``curves`` holds, per site, None or the (frequencies, values)
+    device tensors of its sampled noise curve."""
     arr = (SiteDesc * len(sites))()
     for i, s in enumerate(sites):
-        arr[i] = SiteDesc(s.lat, s.lon, s.gamma, s.zeta, int(s.shape), 0, s.S0, s.f0)
+        c = None if curves is None else curves[i]
+        kind = PSD_ANALYTIC if geometry_only else int(getattr(s, "psd_kind", PSD_ANALYTIC))
+        if kind != PSD_ANALYTIC and c is None:
+            raise GwfError(f"site {i}: a sampled noise curve needs its device arrays")
+        arr[i] = SiteDesc(s.lat, s.lon, s.gamma, s.zeta, int(s.shape), kind, s.S0, s.f0,
+                          None if c is None else c[0].data_ptr(), None if c is None else c[1].data_ptr(),
+                          0 if c is None else int(c[0].numel()))
     net = Network(len(sites), ctypes.cast(arr, ctypes.POINTER(SiteDesc)))
     return net, arr   # keep arr alive with net
 
 
+def upload_curves(sites, device="cuda"):
+    """Device copies (frequencies, values) of the sites' sampled noise
+    curves, None for analytic ones."""
+    import torch
+    out = []
+    for s in sites:
+        if int(getattr(s, "psd_kind", PSD_ANALYTIC)) == PSD_ANALYTIC:
+            out.append(None)
+        else:
+            out.append((torch.as_tensor(np.ascontiguousarray(s.psd_f, dtype=np.float64), device=device),
+                        torch.as_tensor(np.ascontiguousarray(s.psd_S, dtype=np.float64), device=device)))
+    return out
+
+
 def n_ifo(sites) -> int:
-    net, keep = network(sites)
+    net, keep = network(sites, geometry_only=True)
     n = load().gwf_network_n_ifo(ctypes.byref(net))
     if n < 0:
         _check(GWF_E_INVALID_ARG, "gwf_network_n_ifo")
@@ -204,15 +227,21 @@ class DeviceWorkload:
         pm = getattr(wl, "par_mask", None)
         self.par_mask = None if pm is None else torch.as_tensor(
             np.ascontiguousarray(pm, dtype=np.uint32).view(np.int32), device=device)
+        self.curves = upload_curves(self.sites, device)
         self.n_ifo = n_ifo(self.sites)
 
     def with_sites(self, sites) -> "DeviceWorkload":
-        """The same device arrays with another network of the same shapes."""
+        """The same device arrays with another network of the same shapes
+        (sampled noise curves uploaded anew when they changed)."""
         import copy
         if [s.shape for s in sites] != [s.shape for s in self.sites]:
             raise GwfError("with_sites keeps the network's site shapes")
         out = copy.copy(self)
         out.sites = list(sites)
+        same = all(getattr(a, "psd_f", None) is getattr(b, "psd_f", None) and
+                   getattr(a, "psd_S", None) is getattr(b, "psd_S", None) for a, b in zip(sites, self.sites))
+        if not same:
+            out.curves = upload_curves(out.sites, self.par.device)
         return out
 
     def descriptors(self):
@@ -220,7 +249,7 @@ class DeviceWorkload:
                     None if self.tc_s is None else self.tc_s.data_ptr(),
                     None if self.active is None else self.active.data_ptr(),
                     None if self.par_mask is None else self.par_mask.data_ptr())
-        net, keep = network(self.sites)
+        net, keep = network(self.sites, self.curves)
         if self.grid_f is None:
             grid = Grid(GRID_LOG, self.fmin.data_ptr(), None if self.fmax is None else self.fmax.data_ptr(),
                         self.npts.data_ptr(), None, None)

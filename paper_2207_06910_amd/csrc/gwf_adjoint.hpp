@@ -62,7 +62,10 @@ struct SiteA {
   T3 cdl, sdl, sl, cl, slct, clst, k1, k0, k1t, k0t;
   T3 alpha[2][4], beta[2][4];
   double ct, st, xp_fac, ix_fac, x_fac, S0inv, weff[2];
-  int32_t n_eff, pad;
+  int32_t n_eff, tab_kind;
+  const double* tab_f;      // sampled noise curve (tab_kind 1 PSD, 2 ASD), as SiteC
+  const double* tab_S;
+  int64_t tab_n;
 };
 
 // Pattern maps of one interferometer (as pattern_map) and their derivatives
@@ -106,6 +109,10 @@ __host__ __device__ inline void site_setup_adj(const double* p, const SiteDesc& 
   sa.ix_fac = sd.f0 * ec.piM;
   sa.x_fac = 1.0 / sa.ix_fac;
   sa.S0inv = 1.0 / sd.S0;
+  sa.tab_kind = sd.psd_kind;
+  sa.tab_f = sd.tab_f;
+  sa.tab_S = sd.tab_S;
+  sa.tab_n = sd.tab_n;
   if (sd.shape == 1) {
     T3 al[3][4], be[3][4];
     for (int k = 0; k < 3; ++k)
@@ -137,7 +144,6 @@ __host__ __device__ inline void site_setup_adj(const double* p, const SiteDesc& 
     sa.weff[0] = 1.0; sa.weff[1] = 0.0;
     sa.n_eff = (arm_on & 1u) ? 1 : 0;
   }
-  sa.pad = 0;
 }
 
 // Accumulator slots of one site: sum Gbar dGamma along (lat, lon, gamma,
@@ -236,7 +242,8 @@ __host__ __device__ inline void adjoint_site(const EventC& ec, const SiteA& sa, 
     dHv = -(sa.k1.v * sH);
     dTv = fma(sa.k1t.v, cH, sa.k0t.v);
   }
-  const double om0 = psd_weight_of(sa.xp_fac, 0.0, sa.ix_fac, sa.x_fac, sa.S0inv, q);
+  const double om0 = sa.tab_kind ? table_weight(sa.tab_f, sa.tab_S, sa.tab_n, sa.tab_kind, sa.S0inv, q.w4A2, q.f)
+                                 : psd_weight_of(sa.xp_fac, 0.0, sa.ix_fac, sa.x_fac, sa.S0inv, q);
   const double tf = q.tf;
   const double phMc = fma(tf * dHv, q.gMc, q.pMc), phEta = fma(tf * dHv, q.gEta, q.pEta);
   const double phT = tf * dTv, phP = -tf * dHv, phTc = tf * fma(kOmegaE, dHv, 1.0);

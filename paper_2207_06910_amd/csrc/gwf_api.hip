@@ -53,17 +53,23 @@ gwf_status api_pack_network(const gwf_network* net, gwf::NetDesc& nd) {
       return api_fail(GWF_E_INVALID_ARG, "site %d: shape %d is neither L nor T", s, in.shape);
     if (in.psd_kind != GWF_PSD_ANALYTIC && in.psd_kind != GWF_PSD_TABLE && in.psd_kind != GWF_ASD_TABLE)
       return api_fail(GWF_E_INVALID_ARG, "site %d: psd_kind %d unknown", s, in.psd_kind);
-    if (in.psd_kind != GWF_PSD_ANALYTIC)
-      return api_fail(GWF_E_UNSUPPORTED, "site %d: tabulated noise curves are not available in this build", s);
-    if (!finite_all({in.lat, in.lon, in.gamma, in.zeta, in.S0, in.f0}))
+    const bool table = in.psd_kind != GWF_PSD_ANALYTIC;
+    if (!finite_all({in.lat, in.lon, in.gamma, in.zeta, in.S0}) || (!table && !std::isfinite(in.f0)))
       return api_fail(GWF_E_INVALID_ARG, "site %d: non-finite geometry or PSD parameter", s);
-    if (!(in.S0 > 0.0) || !(in.f0 > 0.0))
+    if (!(in.S0 > 0.0) || (!table && !(in.f0 > 0.0)))
       return api_fail(GWF_E_INVALID_ARG, "site %d: S0 and f0 must be > 0", s);
+    if (table && (!in.psd_f || !in.psd_S || in.psd_n < 2 || in.psd_n > 0x7fffffffLL))
+      return api_fail(GWF_E_INVALID_ARG, "site %d: a sampled noise curve needs psd_f, psd_S and 2 <= psd_n < 2^31",
+                      s);
     if (std::fabs(in.lat) > 0.5 * M_PI + 1e-12)
       return api_fail(GWF_E_INVALID_ARG, "site %d: latitude outside [-pi/2, pi/2]", s);
     gwf::SiteDesc& o = nd.site[s];
     o.lat = in.lat; o.lon = in.lon; o.gamma = in.gamma; o.zeta = in.zeta;
-    o.S0 = in.S0; o.f0 = in.f0; o.shape = in.shape;
+    o.S0 = in.S0; o.f0 = table ? 1.0 : in.f0; o.shape = in.shape;   // f0 is not read for a sampled curve
+    o.psd_kind = in.psd_kind;
+    o.tab_f = table ? in.psd_f : nullptr;
+    o.tab_S = table ? in.psd_S : nullptr;
+    o.tab_n = table ? in.psd_n : 0;
     n_ifo += in.shape == GWF_SHAPE_T ? 3 : 1;
   }
   if (n_ifo > GWF_MAX_IFO) return api_fail(GWF_E_INVALID_ARG, "%d interferometers > %d", n_ifo, GWF_MAX_IFO);

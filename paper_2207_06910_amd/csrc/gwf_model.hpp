@@ -118,12 +118,22 @@ struct SiteC {
   double alpha[2][4], beta[2][4], weff[2];  // effective interferometers (pattern maps)
   double arm_alpha[3][4], arm_beta[3][4];   // individual arms (SNR per interferometer)
   int32_t n_eff, n_arm;
+  // sampled noise curve (tab_kind 1: PSD, 2: ASD; 0: the analytic PSD above)
+  const double* tab_f;
+  const double* tab_S;
+  int64_t tab_n;
+  int32_t tab_kind, pad;
 };
 
-// Site description as passed at the boundary (radians).
+// Site description as passed at the boundary (radians); psd_kind 0 is the
+// analytic PSD (S0, f0), 1 and 2 a sampled PSD or ASD (tab_f, tab_S,
+// tab_n, scaled by S0).
 struct SiteDesc {
   double lat, lon, gamma, zeta, S0, f0;
-  int32_t shape, pad;
+  int32_t shape, psd_kind;
+  const double* tab_f;
+  const double* tab_S;
+  int64_t tab_n;
 };
 
 struct NetDesc {
@@ -481,6 +491,11 @@ __host__ __device__ inline void site_setup(const double* p, const SiteDesc& sd, 
   sc.ix_fac = sd.f0 * ec.piM;
   sc.x_fac = 1.0 / sc.ix_fac;
   sc.S0inv = 1.0 / sd.S0;
+  sc.tab_f = sd.tab_f;
+  sc.tab_S = sd.tab_S;
+  sc.tab_n = sd.tab_n;
+  sc.tab_kind = sd.psd_kind;
+  sc.pad = 0;
   if (sd.shape == 1) {
     double al[3][4], be[3][4];
     for (int k = 0; k < 3; ++k) {
@@ -773,9 +788,35 @@ __host__ __device__ inline double psd_weight_of(double xp_fac, double lnx_off, d
   return q.w4A2 * S0inv * den * recip(top);
 }
 
+// The weight with a sampled noise curve (sec. 3.1, a PSD or ASD file): the
+// PSD between two samples on the straight line through them (an ASD squared
+// at the samples first), scaled by S0; no weight outside the sampled range,
+// whose end samples cover frequencies within a relative 1e-12 of them (so a
+// grid starting on a sampled frequency keeps its first point whatever the
+// rounding of f).  The interval is found by bisection over the samples.
+__host__ __device__ inline double table_weight(const double* __restrict__ tf, const double* __restrict__ tS,
+                                               int64_t n, int32_t kind, double S0inv, double w4A2, double f) {
+  constexpr double eps = 1e-12;
+  if (!(f >= tf[0] * (1.0 - eps)) || !(f <= tf[n - 1] * (1.0 + eps))) return 0.0;
+  int64_t lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (tf[mid] <= f) lo = mid;
+    else hi = mid;
+  }
+  double s0 = tS[lo], s1 = tS[hi];
+  if (kind == 2) {
+    s0 *= s0;
+    s1 *= s1;
+  }
+  const double t = fmin(fmax((f - tf[lo]) / (tf[hi] - tf[lo]), 0.0), 1.0);
+  return w4A2 * S0inv / fma(t, s1 - s0, s0);
+}
+
 template <bool PSUM = true>
 __host__ __device__ inline void psd_weight(const SiteC& sc, const Point& q, double& om) {
-  om = psd_weight_of<PSUM>(sc.xp_fac, sc.lnx_off, sc.ix_fac, sc.x_fac, sc.S0inv, q);
+  if (sc.tab_kind) om = table_weight(sc.tab_f, sc.tab_S, sc.tab_n, sc.tab_kind, sc.S0inv, q.w4A2, q.f);
+  else om = psd_weight_of<PSUM>(sc.xp_fac, sc.lnx_off, sc.ix_fac, sc.x_fac, sc.S0inv, q);
 }
 
 // The same weight with the PSD shape evaluated in FP32 (mixed form).  The
@@ -791,6 +832,10 @@ __host__ __device__ inline void psd_weight(const SiteC& sc, const Point& q, doub
 // the FP32 reciprocal.  Measured: 1.2e-8 of sqrt(Gamma_aa Gamma_bb) on the
 // BNS catalogue.
 __host__ __device__ inline void psd_weight_f32(const SiteC& sc, const Point& q, double& om) {
+  if (sc.tab_kind) {   // a sampled curve: the FP64 weight
+    om = table_weight(sc.tab_f, sc.tab_S, sc.tab_n, sc.tab_kind, sc.S0inv, q.w4A2, q.f);
+    return;
+  }
   const float xp = (float)(sc.xp_fac * q.vpsd);
   const double v3 = q.v * q.v * q.v, iv3 = q.iv * q.iv * q.iv;
   const double x = sc.x_fac * v3, ix = sc.ix_fac * iv3;

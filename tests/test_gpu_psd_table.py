@@ -1,0 +1,136 @@
+"""GPU: sampled noise curves (a detector's PSD or ASD given as samples, the
+paper's psd_path file with is_ASD, sec. 3.1) in the SNR, Fisher, batched,
+static-workspace and adjoint kernels, against the oracle's own
+interpolation of the same samples.
+
+The curves are seeded synthetic inputs: a smooth three-regime shape with a
+wiggle on a log grid of 1200-2600 samples; one covers 1-4000 Hz (every grid
+point inside), one only 6-700 Hz (the grid's low and high ends get no
+weight), and one is given as an ASD.  Bars as for the analytic PSD: SNR
+1e-12, Fisher 1e-9 of sqrt(G_ii G_jj); the adjoint 1e-10 of its size."""
+import numpy as np
+import pytest
+
+from paper_2207_06910_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2207_06910_amd import binding
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    binding.load()
+    return binding
+
+
+def _curve(rng, lo, hi, m):
+    f = np.geomspace(lo, hi, m)
+    shape = (f / 15.0) ** -4.0 + 1.0 + (f / 250.0) ** 2
+    wiggle = 1.0 + 0.15 * np.sin(5.0 * np.log(f) + rng.uniform(0, 6.3))
+    return f, shape * wiggle
+
+
+def _network(sites, seed=5):
+    """Site 0 (a triangle): an ASD over 1-4000 Hz; site 1: a PSD over only
+    6-700 Hz; site 2 keeps the analytic PSD."""
+    rng = np.random.default_rng(seed)
+    f0, s0 = _curve(rng, 1.0, 4000.0, 2600)
+    f1, s1 = _curve(rng, 6.0, 700.0, 1200)
+    return [sites[0].with_curve(f0, np.sqrt(s0), asd=True, scale=3e-50),
+            sites[1].with_curve(f1, s1, scale=1e-49),
+            sites[2]]
+
+
+def _workload(n=8, npts=None):
+    wl = synth.bns1e4()
+    idx = np.random.default_rng(17).choice(wl.n, n, replace=False)
+    wl = wl.subset(idx)
+    if npts is not None:
+        wl = wl.with_npts(npts)
+    wl.sites = _network(wl.sites)
+    return wl
+
+
+def _fisher_err(F, Fref):
+    d = np.sqrt(np.abs(np.einsum("iie->ie", Fref)))
+    return np.abs(F - Fref) / (d[:, None, :] * d[None, :, :])
+
+
+def _check(g, ref, snr_tol=1e-12, f_tol=1e-9):
+    assert np.all(g["status"] == 0)
+    rel = np.abs(g["snr"] / ref["snr"] - 1).max()
+    assert rel <= snr_tol, rel
+    err = _fisher_err(g["fisher"], ref["fisher"]).max()
+    assert err <= f_tol, err
+    return rel, err
+
+
+def test_sampled_curves_plain_fisher_and_snr(lib, orc):
+    """gwf_fisher and gwf_snr (per interferometer) on full BNS grids."""
+    wl = _workload()
+    dw = lib.DeviceWorkload(wl)
+    r = {k: v.cpu().numpy() for k, v in lib.fisher(dw, per_ifo_snr=True).items()}
+    s = {k: v.cpu().numpy() for k, v in lib.snr(dw, per_ifo=True).items()}
+    ref = orc.fisher(wl)
+    rel, err = _check(r, ref)
+    np.testing.assert_allclose(r["snr_ifo"], ref["snr_ifo"], rtol=1e-12)
+    np.testing.assert_allclose(s["snr_ifo"], ref["snr_ifo"], rtol=1e-12)
+    # the grids (2 Hz to the cut frequency) reach beyond the band-limited curve at both ends
+    assert np.all(wl.fmin < 6.0) and np.all(wl.npts > 0)
+    print(f"sampled curves, plain: SNR {rel:.2e}, Fisher {err:.2e}")
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_sampled_curves_plan_and_static(lib, orc, mixed):
+    """The batched form (FP64 and mixed: with a sampled curve the mixed form
+    keeps that site's weight in FP64) and the static-workspace form, equal to
+    the plan bit for bit."""
+    wl = _workload(n=12)
+    dw = lib.DeviceWorkload(wl)
+    plan = lib.Plan(dw, chunk=2048, wg_per_cu=2, mixed=mixed)
+    r = {k: v.cpu().numpy() for k, v in plan.run().items()}
+    plan.close()
+    ref = orc.fisher(wl)
+    _check(r, ref, 5e-7 if mixed else 1e-12, 1e-6 if mixed else 1e-9)
+    st = {k: v.cpu().numpy() for k, v in lib.fisher_static(dw, chunk=2048, mixed=mixed).items()}
+    for k in ("fisher", "snr", "status"):
+        assert np.array_equal(st[k], r[k]), k
+
+
+def test_sampled_curves_explicit_grid(lib, orc):
+    """An explicit grid that starts exactly on the band-limited curve's first
+    sample and runs past its last one."""
+    wl = _workload(n=3, npts=500)
+    freqs = [np.geomspace(6.0, 900.0, 500) for _ in range(wl.n)]
+    wx = wl.with_grid_f(freqs)
+    dw = lib.DeviceWorkload(wx)
+    r = {k: v.cpu().numpy() for k, v in lib.fisher(dw).items()}
+    _check(r, orc.fisher(wx))
+
+
+def test_sampled_curves_adjoint(lib, orc):
+    """The detector gradient with sampled curves: latitude, longitude, arm
+    angle and ln S0 (the curve's scale) of every site, against the oracle's
+    nested-dual derivatives, with a Gbar scaled like an inverse Fisher
+    matrix."""
+    wl = _workload(n=3, npts=700)
+    F = orc.fisher(wl)["fisher"]
+    d = np.sqrt(np.einsum("iie->ie", F))
+    P = F.shape[0]
+    gbar = np.random.default_rng(3).normal(size=(P, P, wl.n)) / (d[:, None, :] * d[None, :, :])
+    dw = lib.DeviceWorkload(wl)
+    r = lib.fisher_adjoint(dw, torch.as_tensor(gbar, device="cuda"), w_snr=0.5, w_fisher=1.5)
+    ge = r["grad_event"].cpu().numpy()
+    ns = len(wl.sites)
+    tang = [[orc.fisher_tangent(wl, s, m) for m in range(4)] for s in range(ns)]
+    dF = np.array([[t["fisher"][1] for t in row] for row in tang])
+    dS = np.array([[t["snr2"][1] for t in row] for row in tang])
+    S2 = tang[0][0]["snr2"][0]
+    Gs = 0.5 * (gbar + gbar.transpose(1, 0, 2))
+    ref = 1.5 * np.einsum("ije,smije->esm", Gs, dF) + 0.5 * np.transpose(dS, (2, 0, 1)) / (2 * S2[:, None, None])
+    scale = np.abs(ref).max(axis=(1, 2), keepdims=True)
+    err = np.abs(ge - ref) / scale
+    assert err.max() < 1e-10, (err.max(), np.unravel_index(err.argmax(), err.shape))

@@ -12,13 +12,13 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 it and never calls it.
 """
 from .core import (build, load, fisher, fisher_tangent, restrict_rows, waveform, waveform_derivs, strain, strain_cstep, strain_plain, phase_tau,
-                   phase_dpsi_df_cstep, antenna, delay, cut_frequency, psd, noise_weight, grid, constants,
+                   phase_dpsi_df_cstep, phase_cstep_par, n_params, antenna, delay, cut_frequency, psd, noise_weight, grid, constants,
                    ifos, n_ifo)
 from .basis import fisher_basis, jacobian as basis_jacobian, CHI_SA, LAMBDA_TILDE, M1M2
 from .invert import covariance, eigen, fix_params, add_prior, marginalise, sky_area, covariance_epilogue
 
 __all__ = ["build", "load", "fisher", "fisher_tangent", "restrict_rows", "waveform", "waveform_derivs", "strain", "strain_cstep", "strain_plain", "phase_tau",
-           "phase_dpsi_df_cstep", "antenna", "delay", "cut_frequency", "psd", "noise_weight", "grid",
+           "phase_dpsi_df_cstep", "phase_cstep_par", "n_params", "antenna", "delay", "cut_frequency", "psd", "noise_weight", "grid",
            "constants", "ifos", "n_ifo", "covariance", "eigen", "fix_params", "add_prior", "marginalise",
            "sky_area", "covariance_epilogue", "fisher_basis", "basis_jacobian", "CHI_SA",
            "LAMBDA_TILDE", "M1M2"]

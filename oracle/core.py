@@ -17,6 +17,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 FLAG_EARTH_ROT = 1
 FLAG_TIDAL = 2
+FLAG_ECC = 8
 
 _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
@@ -64,6 +65,8 @@ def load():
                                          ctypes.c_int, _D, ctypes.c_int, _D]
         lib.orc_phase_tau.argtypes = [_D, ctypes.c_int, ctypes.c_int, _D, _D, _D]
         lib.orc_phase_cstep_f.argtypes = [_D, ctypes.c_int, ctypes.c_int, _D, ctypes.c_double, _D]
+        lib.orc_phase_cstep_par.argtypes = [_D, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, ctypes.c_double, _D]
+        lib.orc_set_eccentricity.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_antenna.argtypes = [ctypes.c_double] * 7 + [_D, _D]
         lib.orc_delay.argtypes = [ctypes.c_double] * 4
         lib.orc_cut_frequency.argtypes = [ctypes.c_double, ctypes.c_double]
@@ -78,6 +81,22 @@ def load():
 
 def _p(a):
     return None if a is None else a.ctypes.data_as(_D)
+
+
+def n_params(flags):
+    """Fisher parameters: 11, the two deformabilities with FLAG_TIDAL, and
+    e0 (last) with FLAG_ECC."""
+    return 11 + (2 if flags & FLAG_TIDAL else 0) + (1 if flags & FLAG_ECC else 0)
+
+
+def _par15(par):
+    """One event's parameters as the oracle takes them: the 13 rows, e0 and
+    the reference frequency of e0 (0: the first frequency of the list or
+    grid); a 13-vector is padded with zeros."""
+    p = np.zeros(15)
+    a = np.asarray(par, dtype=np.float64).ravel()
+    p[:len(a)] = a
+    return p
 
 
 def _f64(a):
@@ -129,7 +148,7 @@ def delay(lat, lst, theta, phi):
 
 
 def phase_tau(par13, f, flags=0):
-    par = _f64(par13)
+    par = _par15(par13)
     f = _f64(f)
     psi = np.zeros_like(f)
     tau = np.zeros_like(f)
@@ -138,20 +157,30 @@ def phase_tau(par13, f, flags=0):
 
 
 def phase_dpsi_df_cstep(par13, f, flags=0, h=1e-30):
-    par = _f64(par13)
+    par = _par15(par13)
     f = _f64(f)
     out = np.zeros_like(f)
     load().orc_phase_cstep_f(_p(par), flags, len(f), _p(f), h, _p(out))
     return out
 
 
+def phase_cstep_par(par, f, flags, j, h=1e-30):
+    """d Psi_PN / d (slot j) at fixed frequencies by complex step (the
+    eccentric term included under FLAG_ECC)."""
+    par = _par15(par)
+    f = _f64(f)
+    out = np.zeros_like(f)
+    load().orc_phase_cstep_par(_p(par), flags, int(j), len(f), _p(f), h, _p(out))
+    return out
+
+
 def strain(par13, sites, f, flags, tc_s=0.0, derivs=True):
     """h[n_ifo][nf] complex and, if derivs, dh[n_ifo][nf][P] complex."""
-    par = _f64(par13)
+    par = _par15(par13)
     s = _f64(sites)
     f = _f64(f)
     ni = n_ifo(s)
-    P = 13 if flags & FLAG_TIDAL else 11
+    P = n_params(flags)
     h = np.zeros((ni, len(f), 2))
     dh = np.zeros((ni, len(f), P, 2)) if derivs else None
     load().orc_strain(_p(par), float(tc_s), len(s), _p(s), len(f), _p(f), flags, _p(h), _p(dh))
@@ -162,7 +191,7 @@ def strain(par13, sites, f, flags, tc_s=0.0, derivs=True):
 
 
 def strain_cstep(par13, sites, f, flags, j, step=1e-30, tc_s=0.0):
-    par = _f64(par13)
+    par = _par15(par13)
     s = _f64(sites)
     f = _f64(f)
     out = np.zeros((n_ifo(s), len(f), 2))
@@ -172,7 +201,7 @@ def strain_cstep(par13, sites, f, flags, j, step=1e-30, tc_s=0.0):
 
 
 def strain_plain(par13, sites, f, flags, tc_s=0.0, dt=0.0):
-    par = _f64(par13)
+    par = _par15(par13)
     s = _f64(sites)
     f = _f64(f)
     out = np.zeros((n_ifo(s), len(f), 2))
@@ -200,6 +229,29 @@ class _grid:
     def __exit__(self, *exc):
         if self.f is not None:
             load().orc_set_explicit_grid(None, None)
+        return False
+
+
+class _ecc:
+    """While active, the workload's eccentricities (wl.ecc) and their
+    reference frequencies (wl.f_ref_ecc, or None: each grid's first
+    frequency) are the events' e0 and f_ref."""
+
+    def __init__(self, wl):
+        e = getattr(wl, "ecc", None)
+        fr = getattr(wl, "f_ref_ecc", None)
+        self.e = None if e is None else np.ascontiguousarray(e, dtype=np.float64)
+        self.fr = None if fr is None else np.ascontiguousarray(fr, dtype=np.float64)
+
+    def __enter__(self):
+        if self.e is not None:
+            load().orc_set_eccentricity(self.e.ctypes.data,
+                                        None if self.fr is None else self.fr.ctypes.data)
+        return self
+
+    def __exit__(self, *exc):
+        if self.e is not None:
+            load().orc_set_eccentricity(None, None)
         return False
 
 
@@ -266,7 +318,7 @@ def fisher(wl, want_fisher=True, per_ifo=False, nthreads=0):
     n = par.shape[1]
     s = _f64(wl.site_array())
     ni = n_ifo(s)
-    P = 13 if wl.flags & FLAG_TIDAL else 11
+    P = n_params(wl.flags)
     fmin = _f64(wl.fmin)
     fmax = None if wl.fmax is None else _f64(wl.fmax)
     npts = np.ascontiguousarray(wl.npts, dtype=np.int32)
@@ -277,7 +329,7 @@ def fisher(wl, want_fisher=True, per_ifo=False, nthreads=0):
     Fi = np.zeros((ni, P, P, n)) if (want_fisher and per_ifo) else None
     act = getattr(wl, "active", None)
     act = None if act is None else np.ascontiguousarray(act, dtype=np.uint8)
-    with _grid(wl), _tables(wl.sites):
+    with _grid(wl), _tables(wl.sites), _ecc(wl):
         load().orc_fisher(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
                           npts.ctypes.data_as(_I), None if act is None else act.ctypes.data_as(ctypes.c_void_p),
                           wl.flags, int(nthreads), _p(snr), _p(snr_ifo), _p(F), _p(Fi))
@@ -313,7 +365,7 @@ def waveform(wl, offsets=None, total=None, nthreads=0):
     fmax = None if wl.fmax is None else _f64(wl.fmax)
     tc = None if wl.tc_s is None else _f64(wl.tc_s)
     h = np.zeros((ni, total, 2))
-    with _grid(wl):
+    with _grid(wl), _ecc(wl):
         load().orc_waveform(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
                             npts.ctypes.data_as(_I), wl.flags, int(nthreads),
                             offsets.ctypes.data_as(_L), int(total), _p(h))
@@ -329,7 +381,7 @@ def waveform_derivs(wl, offsets=None, total=None, nthreads=0):
     n = par.shape[1]
     s = _f64(wl.site_array())
     ni = n_ifo(s)
-    P = 13 if wl.flags & FLAG_TIDAL else 11
+    P = n_params(wl.flags)
     npts = np.ascontiguousarray(wl.npts, dtype=np.int32)
     if offsets is None:
         offsets = np.concatenate([[0], np.cumsum(npts, dtype=np.int64)[:-1]])
@@ -340,7 +392,7 @@ def waveform_derivs(wl, offsets=None, total=None, nthreads=0):
     fmax = None if wl.fmax is None else _f64(wl.fmax)
     tc = None if wl.tc_s is None else _f64(wl.tc_s)
     dh = np.zeros((P, ni, total, 2))
-    with _grid(wl):
+    with _grid(wl), _ecc(wl):
         load().orc_waveform_deriv(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
                                   npts.ctypes.data_as(_I), wl.flags, int(nthreads),
                                   offsets.ctypes.data_as(_L), int(total), _p(dh))
@@ -362,7 +414,7 @@ def fisher_tangent(wl, site, which, nthreads=0):
     par = _f64(wl.par)
     n = par.shape[1]
     s = _f64(wl.site_array())
-    P = 13 if wl.flags & FLAG_TIDAL else 11
+    P = n_params(wl.flags)
     fmin = _f64(wl.fmin)
     fmax = None if wl.fmax is None else _f64(wl.fmax)
     npts = np.ascontiguousarray(wl.npts, dtype=np.int32)
@@ -371,7 +423,7 @@ def fisher_tangent(wl, site, which, nthreads=0):
     F = np.zeros((2, P, P, n))
     act = getattr(wl, "active", None)
     act = None if act is None else np.ascontiguousarray(act, dtype=np.uint8)
-    with _grid(wl), _tables(wl.sites):
+    with _grid(wl), _tables(wl.sites), _ecc(wl):
         load().orc_fisher_tangent(n, _p(par), n, _p(tc), len(s), _p(s), _p(fmin), _p(fmax),
                                   npts.ctypes.data_as(_I), None if act is None else act.ctypes.data_as(ctypes.c_void_p),
                                   wl.flags, int(nthreads), int(site), int(which), _p(snr2), _p(F))

@@ -57,7 +57,7 @@ const double OMEGA_E = 2.0 * PI / SIDEREAL_DAY;        // rad/s
 const double R_EARTH = 6.371e6;                        // m (spherical Earth)
 const double EULER_GAMMA = 0.5772156649015329;
 
-enum : int { FLAG_EARTH_ROT = 1, FLAG_TIDAL = 2 };
+enum : int { FLAG_EARTH_ROT = 1, FLAG_TIDAL = 2, FLAG_ECC = 8 };
 enum : int { NPAR = 13 };
 
 // ------------------------------------------------------------ dual numbers
@@ -160,8 +160,10 @@ struct NeumaierSum {
 template <class S>
 struct Source {
   S Mc, eta, dL, theta, phi, iota, psi, dt, Phic, chi1, chi2, L1, L2;
+  S e0;                      // orbital eccentricity at the reference frequency
   double tcoal_days = 0.0;   // GMST of coalescence in sidereal days
   double tc_s = 0.0;         // coalescence time used in the 2 pi f tc phase term [s]
+  double f_ref = 0.0;        // reference (GW) frequency of e0 [Hz]
 };
 
 // Interferometer geometry; T is the type of the detector parameters.
@@ -254,6 +256,21 @@ S pn_phase(const Source<S>& s, const S& v, bool tidal) {
   }
   S v5 = v2 * v2 * v;
   return 3.0 / (128.0 * eta * v5) * series;
+}
+
+// Moderate eccentricity (the is_eccentric extension of sec. 2.2, whose
+// reference is Moore et al. 2016): to leading order in e0 and at Newtonian
+// order, the phase gains -(2355/1462) e0^2 (v_ref/v)^{19/3} times the
+// Newtonian term 3/(128 eta v^5), with e0 the eccentricity where the GW
+// frequency is f_ref and v_ref = (pi G M f_ref/c^3)^{1/3}.  Valid for
+// e0 <~ 0.1 (sec. 2.2).  The numerical coefficient comes from that
+// reference, not from the paper.
+template <class S>
+S eccentric_phase(const Source<S>& s, const S& Ms, const S& v) {
+  using std::pow;
+  S vref = pow(PI * Ms * s.f_ref, 1.0 / 3.0);
+  S v5 = v * v * v * v * v;
+  return 3.0 / (128.0 * s.eta * v5) * (-2355.0 / 1462.0) * s.e0 * s.e0 * pow(vref / v, 19.0 / 3.0);
 }
 
 // Time to coalescence tau*(f), 3.5PN, non-spinning (the paper cites
@@ -418,6 +435,7 @@ void strain(const Source<S>& s, const Ifo<T>& ifo, double f, int flags, S& hre, 
   S qre = amp * Fp * 0.5 * (1.0 + ci * ci);
   S qim = amp * Fx * ci;
   S Psi = 2.0 * PI * f * (s.tc_s + s.dt + Delta) - s.Phic - 0.25 * PI + pn_phase(s, v, (flags & FLAG_TIDAL) != 0);
+  if (flags & FLAG_ECC) Psi = Psi + eccentric_phase(s, Ms, v);
   S c = cos(Psi), sn = sin(Psi);
   hre = qre * c - qim * sn;
   him = qre * sn + qim * c;
@@ -471,14 +489,37 @@ Source<S> make_source(const double* par, double tc_s) {
   s.phi = S(par[4]); s.iota = S(par[5]); s.psi = S(par[6]); s.dt = S(0.0);
   s.Phic = S(par[8]); s.chi1 = S(par[9]); s.chi2 = S(par[10]);
   s.L1 = S(par[11]); s.L2 = S(par[12]);
+  s.e0 = S(par[13]);
   s.tcoal_days = par[7];
   s.tc_s = tc_s;
+  s.f_ref = par[14];
   return s;
 }
 
-// Slot i of the Fisher matrix, in the parameter order of the public tables.
+// Number of Fisher parameters: 11, plus the two deformabilities, plus e0.
+inline int n_params(int flags) {
+  return 11 + ((flags & FLAG_TIDAL) ? 2 : 0) + ((flags & FLAG_ECC) ? 1 : 0);
+}
+
+// Per-event eccentricities and their reference frequencies for the
+// workload-level drivers (orc_set_eccentricity); NULL = none / the grid's
+// first frequency.
+static const double* g_ecc = nullptr;
+static const double* g_fref = nullptr;
+
+// Event e's parameters: the 13 rows of par, then e0 and f_ref (0 = the
+// grid's first frequency).
+inline void event_params(const double* par, int64_t ld, int64_t e, double* p) {
+  for (int i = 0; i < 13; ++i) p[i] = par[i * ld + e];
+  p[13] = g_ecc ? g_ecc[e] : 0.0;
+  p[14] = g_fref ? g_fref[e] : 0.0;
+}
+
+// Slot i of the Fisher matrix, in the parameter order of the public tables
+// (sec. 3.2): e0 comes after the spins and the deformabilities.
 template <class S>
-S& slot(Source<S>& s, int i) {
+S& slot(Source<S>& s, int i, int flags) {
+  if ((flags & FLAG_ECC) && i == n_params(flags) - 1) return s.e0;
   switch (i) {
     case 0: return s.Mc; case 1: return s.eta; case 2: return s.dL; case 3: return s.theta;
     case 4: return s.phi; case 5: return s.iota; case 6: return s.psi; case 7: return s.dt;
@@ -495,9 +536,10 @@ void fisher_event(const double* par, double tc_s, const std::vector<Ifo<double>>
                   double* snr2_ifo, double* F_ifo /* [n_ifo][P][P] */, int64_t e = -1) {
   using S = Dual<double, P>;
   Source<S> s = make_source<S>(par, tc_s);
-  for (int i = 0; i < P; ++i) slot(s, i).d[i] = 1.0;
+  for (int i = 0; i < P; ++i) slot(s, i, flags).d[i] = 1.0;
   std::vector<double> f, w;
   event_grid(e, fmin, fmax, n, f, w);
+  if (!(s.f_ref > 0.0)) s.f_ref = f[0];   // e0 given at the grid's first frequency
   const int nifo = (int)ifos.size();
   for (int d = 0; d < nifo; ++d) {
     NeumaierSum snr;
@@ -535,9 +577,10 @@ void fisher_event_tangent(const double* par, double tc_s, const std::vector<Ifo<
                           double* snr2 /* [2] */, double* F /* [2][P][P] */, int64_t e = -1) {
   using S = Dual<D1, P>;
   Source<S> s = make_source<S>(par, tc_s);
-  for (int i = 0; i < P; ++i) slot(s, i).d[i] = D1(1.0);
+  for (int i = 0; i < P; ++i) slot(s, i, flags).d[i] = D1(1.0);
   std::vector<double> f, w;
   event_grid(e, fmin, fmax, n, f, w);
+  if (!(s.f_ref > 0.0)) s.f_ref = f[0];   // e0 given at the grid's first frequency
   NeumaierSum sv, st;
   std::vector<NeumaierSum> Gv(P * P), Gt(P * P);
   for (size_t d = 0; d < ifos.size(); ++d)
@@ -567,6 +610,7 @@ void snr_event(const double* par, double tc_s, const std::vector<Ifo<double>>& i
   Source<double> s = make_source<double>(par, tc_s);
   std::vector<double> f, w;
   event_grid(e, fmin, fmax, n, f, w);
+  if (!(s.f_ref > 0.0)) s.f_ref = f[0];   // e0 given at the grid's first frequency
   for (size_t d = 0; d < ifos.size(); ++d) {
     NeumaierSum snr;
     for (int k = 0; k < n; ++k) {
@@ -596,13 +640,14 @@ static void waveform_deriv_events(int64_t n, const double* par, int64_t ld, cons
   const int nifo = (int)ifos.size();
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t e = 0; e < n; ++e) {
-    double p[13];
-    for (int i = 0; i < 13; ++i) p[i] = par[i * ld + e];
+    double p[15];
+    event_params(par, ld, e, p);
     double fhi = fmax ? fmax[e] : cut_frequency(p[0], p[1]);
     Source<S> s = make_source<S>(p, tc_s ? tc_s[e] : 0.0);
-    for (int j = 0; j < P; ++j) slot(s, j).d[j] = 1.0;
+    for (int j = 0; j < P; ++j) slot(s, j, flags).d[j] = 1.0;
     std::vector<double> f, w;
     event_grid(e, fmin[e], fhi, npts[e], f, w);
+    if (!(s.f_ref > 0.0)) s.f_ref = f[0];
     for (int d = 0; d < nifo; ++d)
       for (int k = 0; k < npts[e]; ++k) {
         S hr, hi;
@@ -614,6 +659,24 @@ static void waveform_deriv_events(int64_t n, const double* par, int64_t ld, cons
         }
       }
   }
+}
+
+template <int P>
+static void strain_events_one(const double* par, double tc_s, const std::vector<Ifo<double>>& ifos, int nf,
+                              const double* f, int flags, double* h, double* dh) {
+  using S = Dual<double, P>;
+  for (size_t i = 0; i < ifos.size(); ++i)
+    for (int k = 0; k < nf; ++k) {
+      Source<S> s = make_source<S>(par, tc_s);
+      if (!(s.f_ref > 0.0)) s.f_ref = f[0];
+      for (int j = 0; j < P; ++j) slot(s, j, flags).d[j] = 1.0;
+      S hr, hi;
+      strain(s, ifos[i], f[k], flags, hr, hi);
+      h[(i * nf + k) * 2] = hr.v; h[(i * nf + k) * 2 + 1] = hi.v;
+      if (dh) for (int j = 0; j < P; ++j) {
+        dh[((i * nf + k) * P + j) * 2] = hr.d[j]; dh[((i * nf + k) * P + j) * 2 + 1] = hi.d[j];
+      }
+    }
 }
 
 extern "C" {
@@ -655,12 +718,40 @@ double orc_delay(double lat, double lst, double theta, double phi) {
 // PN phase and tau*(f) of one event on nf frequencies.
 void orc_phase_tau(const double* par, int flags, int nf, const double* f, double* psi_pn, double* tau) {
   Source<double> s = make_source<double>(par, 0.0);
+  if (!(s.f_ref > 0.0)) s.f_ref = f[0];
   double Ms = s.Mc * std::pow(s.eta, -0.6) * T_SUN;
   for (int k = 0; k < nf; ++k) {
     double v = std::pow(PI * Ms * f[k], 1.0 / 3.0);
     psi_pn[k] = pn_phase(s, v, (flags & FLAG_TIDAL) != 0);
+    if (flags & FLAG_ECC) psi_pn[k] += eccentric_phase(s, Ms, v);
     tau[k] = tau_star(s, Ms, v);
   }
+}
+
+// Complex-step derivative of the PN phase (with the eccentric term under
+// FLAG_ECC) with respect to parameter slot j at fixed frequency:
+// Im Psi(par + i h e_j) / h.
+void orc_phase_cstep_par(const double* par, int flags, int j, int nf, const double* f, double h, double* out) {
+  using C = std::complex<double>;
+  Source<C> s = make_source<C>(par, 0.0);
+  if (!(s.f_ref > 0.0)) s.f_ref = f[0];
+  slot(s, j, flags) = slot(s, j, flags) + C(0.0, h);
+  C Ms = s.Mc * std::pow(s.eta, -0.6) * T_SUN;
+  for (int k = 0; k < nf; ++k) {
+    C v = std::pow(PI * Ms * f[k], 1.0 / 3.0);
+    C psi = pn_phase(s, v, (flags & FLAG_TIDAL) != 0);
+    if (flags & FLAG_ECC) psi = psi + eccentric_phase(s, Ms, v);
+    out[k] = psi.imag() / h;
+  }
+}
+
+// Eccentricities e0[n] and reference frequencies f_ref[n] (NULL: each grid's
+// first frequency) of the workload-level drivers that follow; NULL, NULL
+// clears them.  The arrays must stay alive while they are set.
+int orc_set_eccentricity(const double* e0, const double* f_ref) {
+  g_ecc = e0;
+  g_fref = f_ref;
+  return 0;
 }
 
 // Complex-step version of the PN phase: Im(Psi(f + i h))/h = dPsi/df.
@@ -676,35 +767,17 @@ void orc_phase_cstep_f(const double* par, int flags, int nf, const double* f, do
 
 // Strain of one event at every interferometer on an explicit frequency list,
 // h[(i*nf + k)*2 + {0,1}], and optionally its P derivatives by dual numbers,
-// dh[((i*nf + k)*P + j)*2 + {0,1}].
+// dh[((i*nf + k)*P + j)*2 + {0,1}].  par holds the 13 parameters, e0 and
+// f_ref (0: the list's first frequency).
 int orc_strain(const double* par, double tc_s, int n_site, const double* sites, int nf,
                const double* f, int flags, double* h, double* dh) {
   auto ifos = expand_sites(n_site, sites);
-  const int P = (flags & FLAG_TIDAL) ? 13 : 11;
-  for (size_t i = 0; i < ifos.size(); ++i)
-    for (int k = 0; k < nf; ++k) {
-      if (P == 13) {
-        using S = Dual<double, 13>;
-        Source<S> s = make_source<S>(par, tc_s);
-        for (int j = 0; j < 13; ++j) slot(s, j).d[j] = 1.0;
-        S hr, hi;
-        strain(s, ifos[i], f[k], flags, hr, hi);
-        h[(i * nf + k) * 2] = hr.v; h[(i * nf + k) * 2 + 1] = hi.v;
-        if (dh) for (int j = 0; j < 13; ++j) {
-          dh[((i * nf + k) * 13 + j) * 2] = hr.d[j]; dh[((i * nf + k) * 13 + j) * 2 + 1] = hi.d[j];
-        }
-      } else {
-        using S = Dual<double, 11>;
-        Source<S> s = make_source<S>(par, tc_s);
-        for (int j = 0; j < 11; ++j) slot(s, j).d[j] = 1.0;
-        S hr, hi;
-        strain(s, ifos[i], f[k], flags, hr, hi);
-        h[(i * nf + k) * 2] = hr.v; h[(i * nf + k) * 2 + 1] = hi.v;
-        if (dh) for (int j = 0; j < 11; ++j) {
-          dh[((i * nf + k) * 11 + j) * 2] = hr.d[j]; dh[((i * nf + k) * 11 + j) * 2 + 1] = hi.d[j];
-        }
-      }
-    }
+  switch (n_params(flags)) {
+    case 14: strain_events_one<14>(par, tc_s, ifos, nf, f, flags, h, dh); break;
+    case 13: strain_events_one<13>(par, tc_s, ifos, nf, f, flags, h, dh); break;
+    case 12: strain_events_one<12>(par, tc_s, ifos, nf, f, flags, h, dh); break;
+    default: strain_events_one<11>(par, tc_s, ifos, nf, f, flags, h, dh);
+  }
   return 0;
 }
 
@@ -716,7 +789,8 @@ int orc_strain_cstep(const double* par, double tc_s, int n_site, const double* s
   using C = std::complex<double>;
   auto ifos = expand_sites(n_site, sites);
   Source<C> s = make_source<C>(par, tc_s);
-  slot(s, j) = slot(s, j) + C(0.0, step);
+  if (!(s.f_ref > 0.0)) s.f_ref = f[0];
+  slot(s, j, flags) = slot(s, j, flags) + C(0.0, step);
   for (size_t i = 0; i < ifos.size(); ++i)
     for (int k = 0; k < nf; ++k) {
       C hr, hi;
@@ -733,6 +807,7 @@ int orc_strain_plain(const double* par, double tc_s, double dt, int n_site, cons
                      int nf, const double* f, int flags, double* h) {
   auto ifos = expand_sites(n_site, sites);
   Source<double> s = make_source<double>(par, tc_s);
+  if (!(s.f_ref > 0.0)) s.f_ref = f[0];
   s.dt = dt;
   for (size_t i = 0; i < ifos.size(); ++i)
     for (int k = 0; k < nf; ++k) strain(s, ifos[i], f[k], flags, h[(i * nf + k) * 2], h[(i * nf + k) * 2 + 1]);
@@ -782,12 +857,13 @@ int orc_waveform(int64_t n, const double* par, int64_t ld, const double* tc_s, i
 #endif
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t e = 0; e < n; ++e) {
-    double p[13];
-    for (int i = 0; i < 13; ++i) p[i] = par[i * ld + e];
+    double p[15];
+    event_params(par, ld, e, p);
     double fhi = fmax ? fmax[e] : cut_frequency(p[0], p[1]);
     Source<double> s = make_source<double>(p, tc_s ? tc_s[e] : 0.0);
     std::vector<double> f, w;
     event_grid(e, fmin[e], fhi, npts[e], f, w);
+    if (!(s.f_ref > 0.0)) s.f_ref = f[0];
     for (int d = 0; d < nifo; ++d)
       for (int k = 0; k < npts[e]; ++k) {
         double* o = h + ((int64_t)d * total + offsets[e] + k) * 2;
@@ -805,10 +881,12 @@ int orc_waveform_deriv(int64_t n, const double* par, int64_t ld, const double* t
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
-  if (flags & FLAG_TIDAL)
-    waveform_deriv_events<13>(n, par, ld, tc_s, ifos, fmin, fmax, npts, flags, offsets, total, dh);
-  else
-    waveform_deriv_events<11>(n, par, ld, tc_s, ifos, fmin, fmax, npts, flags, offsets, total, dh);
+  switch (n_params(flags)) {
+    case 14: waveform_deriv_events<14>(n, par, ld, tc_s, ifos, fmin, fmax, npts, flags, offsets, total, dh); break;
+    case 13: waveform_deriv_events<13>(n, par, ld, tc_s, ifos, fmin, fmax, npts, flags, offsets, total, dh); break;
+    case 12: waveform_deriv_events<12>(n, par, ld, tc_s, ifos, fmin, fmax, npts, flags, offsets, total, dh); break;
+    default: waveform_deriv_events<11>(n, par, ld, tc_s, ifos, fmin, fmax, npts, flags, offsets, total, dh);
+  }
   return 0;
 }
 
@@ -835,14 +913,14 @@ int orc_fisher_tangent(int64_t n, const double* par, int64_t ld, const double* t
       ifos.push_back(t);
     }
   }
-  const int P = (flags & FLAG_TIDAL) ? 13 : 11;
+  const int P = n_params(flags);
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t e = 0; e < n; ++e) {
-    double p[13];
-    for (int i = 0; i < 13; ++i) p[i] = par[i * ld + e];
+    double p[15];
+    event_params(par, ld, e, p);
     double fhi = fmax ? fmax[e] : cut_frequency(p[0], p[1]);
     double tcs = tc_s ? tc_s[e] : 0.0;
     double s2[2];
@@ -850,8 +928,12 @@ int orc_fisher_tangent(int64_t n, const double* par, int64_t ld, const double* t
     std::vector<char> on(ifos.size(), 1);
     if (active)
       for (size_t d = 0; d < ifos.size(); ++d) on[d] = active[(int64_t)d * n + e] != 0;
-    if (P == 13) fisher_event_tangent<13>(p, tcs, ifos, on, fmin[e], fhi, npts[e], flags, s2, F.data(), e);
-    else fisher_event_tangent<11>(p, tcs, ifos, on, fmin[e], fhi, npts[e], flags, s2, F.data(), e);
+    switch (P) {
+      case 14: fisher_event_tangent<14>(p, tcs, ifos, on, fmin[e], fhi, npts[e], flags, s2, F.data(), e); break;
+      case 13: fisher_event_tangent<13>(p, tcs, ifos, on, fmin[e], fhi, npts[e], flags, s2, F.data(), e); break;
+      case 12: fisher_event_tangent<12>(p, tcs, ifos, on, fmin[e], fhi, npts[e], flags, s2, F.data(), e); break;
+      default: fisher_event_tangent<11>(p, tcs, ifos, on, fmin[e], fhi, npts[e], flags, s2, F.data(), e);
+    }
     snr2[e] = s2[0];
     snr2[n + e] = s2[1];
     for (int t = 0; t < 2; ++t)
@@ -873,21 +955,25 @@ int orc_fisher(int64_t n, const double* par, int64_t ld, const double* tc_s, int
                double* fisher, double* fisher_ifo) {
   auto ifos = expand_sites(n_site, sites);
   const int nifo = (int)ifos.size();
-  const int P = (flags & FLAG_TIDAL) ? 13 : 11;
+  const int P = n_params(flags);
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t e = 0; e < n; ++e) {
-    double p[13];
-    for (int i = 0; i < 13; ++i) p[i] = par[i * ld + e];
+    double p[15];
+    event_params(par, ld, e, p);
     double fhi = fmax ? fmax[e] : cut_frequency(p[0], p[1]);
     double tcs = tc_s ? tc_s[e] : 0.0;
     std::vector<double> s2(nifo), F;
     if (fisher || fisher_ifo) {
       F.assign((size_t)nifo * P * P, 0.0);
-      if (P == 13) fisher_event<13>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data(), F.data(), e);
-      else fisher_event<11>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data(), F.data(), e);
+      switch (P) {
+        case 14: fisher_event<14>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data(), F.data(), e); break;
+        case 13: fisher_event<13>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data(), F.data(), e); break;
+        case 12: fisher_event<12>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data(), F.data(), e); break;
+        default: fisher_event<11>(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data(), F.data(), e);
+      }
     } else {
       snr_event(p, tcs, ifos, fmin[e], fhi, npts[e], flags, s2.data(), e);
     }

@@ -42,6 +42,7 @@ PSD_ANALYTIC, PSD_TABLE, ASD_TABLE = 0, 1, 2
 
 FLAG_EARTH_ROT = 1
 FLAG_TIDAL = 2
+FLAG_ECCENTRIC = 8
 
 DEG = math.pi / 180.0
 
@@ -108,6 +109,9 @@ class Workload:
     par_mask: np.ndarray | None = None  # uint32 [N] or None: each event's Fisher rows (bit r: row r)
     grid_f: np.ndarray | None = None    # float64 [sum npts] or None: explicit grids, event e's
                                         # frequencies at its exclusive prefix sum of npts
+    ecc: np.ndarray | None = None       # float64 [N] or None: e0 (with FLAG_ECCENTRIC)
+    f_ref_ecc: np.ndarray | None = None  # float64 [N] or None: reference frequency of e0
+                                         # (None: each grid's first frequency)
 
     @property
     def n(self) -> int:
@@ -129,7 +133,9 @@ class Workload:
                         None if self.active is None else np.ascontiguousarray(self.active[:, idx]),
                         None if self.par_mask is None else self.par_mask[idx].copy(),
                         None if self.grid_f is None else np.concatenate(
-                            [self.event_grid(int(e)) for e in idx]))
+                            [self.event_grid(int(e)) for e in idx]),
+                        None if self.ecc is None else self.ecc[idx].copy(),
+                        None if self.f_ref_ecc is None else self.f_ref_ecc[idx].copy())
 
     def with_duty_factor(self, duty, seed: int) -> "Workload":
         """A copy whose interferometers are each on for an event with
@@ -153,6 +159,20 @@ class Workload:
         w = self.subset(np.arange(self.n))
         w.name = self.name + "[par masks]"
         w.par_mask = population_masks(self.meta["kind"], self.npar)
+        return w
+
+    def with_eccentricity(self, e0, f_ref=None) -> "Workload":
+        """A copy with orbital eccentricities e0 [N] (or one value for all),
+        given at the reference frequencies f_ref [N] (None: each grid's first
+        frequency); the Fisher matrices gain e0 as their last row."""
+        w = self.subset(np.arange(self.n))
+        w.name = self.name + "[eccentric]"
+        w.ecc = np.broadcast_to(np.asarray(e0, dtype=np.float64), (self.n,)).copy()
+        w.f_ref_ecc = None if f_ref is None else np.broadcast_to(
+            np.asarray(f_ref, dtype=np.float64), (self.n,)).copy()
+        if not self.flags & FLAG_ECCENTRIC:
+            w.flags = self.flags | FLAG_ECCENTRIC
+            w.npar = self.npar + 1
         return w
 
     def grid_offsets(self) -> np.ndarray:

@@ -14,6 +14,7 @@ from paper_2207_06910_amd import synth
 
 ROT = synth.FLAG_EARTH_ROT
 TID = synth.FLAG_TIDAL
+ECC = synth.FLAG_ECCENTRIC
 
 
 def _bns_event(i=0):
@@ -55,6 +56,91 @@ def test_newtonian_phase_normalisation(orc):
     par[0], par[1] = 1.2, 0.24
     v, s = _phase_coeffs(orc, par, vs=(1e-5,))
     assert abs(s[0] - 1.0) < 1e-8
+
+
+# ------------------------------------------------------------ eccentricity (sec. 2.2)
+def _ecc_par(e0, f_ref, i=3):
+    w, par = _bns_event(i)
+    return np.concatenate([par, [e0, f_ref]])
+
+
+def test_eccentric_phase_scalings(orc):
+    """The leading-order eccentric correction of the phase, Delta Psi =
+    Psi(e0) - Psi(0) at fixed frequency: proportional to e0^2; as a
+    function of f, (f_ref/f)^{19/9} times the Newtonian f^{-5/3}, so
+    Delta Psi(f1)/Delta Psi(f2) = (f2/f1)^{34/9}; moving f_ref multiplies it
+    by (f_ref'/f_ref)^{19/9}; and at f = f_ref it is -(2355/1462) e0^2 times
+    the Newtonian phase 3/128 (pi G Mc f/c^3)^{-5/3}, written in the chirp
+    mass alone (the reference's coefficient; its value is parity unpinned
+    here, the structure is not)."""
+    T = orc.constants()["T_SUN"]
+    f = np.array([6.0, 20.0, 75.0, 310.0])
+    for e0, fr in ((0.05, 6.0), (0.1, 6.0), (0.1, 12.0)):
+        p = _ecc_par(e0, fr)
+        p0 = _ecc_par(0.0, fr)
+        psi, _ = orc.phase_tau(p, f, ECC)
+        psi0, _ = orc.phase_tau(p0, f, ECC)
+        d = psi - psi0
+        np.testing.assert_allclose(d[1:] / d[0], (f[0] / f[1:]) ** (34.0 / 9.0), rtol=1e-9)
+        if fr == 6.0:
+            newt = 3.0 / 128.0 * (np.pi * T * p[0] * fr) ** (-5.0 / 3.0)
+            assert abs(d[0] / newt + 2355.0 / 1462.0 * e0 ** 2) < 1e-9 * 2355.0 / 1462.0 * e0 ** 2
+    a = orc.phase_tau(_ecc_par(0.1, 6.0), f, ECC)[0] - orc.phase_tau(_ecc_par(0.0, 6.0), f, ECC)[0]
+    b = orc.phase_tau(_ecc_par(0.05, 6.0), f, ECC)[0] - orc.phase_tau(_ecc_par(0.0, 6.0), f, ECC)[0]
+    c = orc.phase_tau(_ecc_par(0.1, 12.0), f, ECC)[0] - orc.phase_tau(_ecc_par(0.0, 12.0), f, ECC)[0]
+    np.testing.assert_allclose(a / b, 4.0, rtol=1e-9)
+    np.testing.assert_allclose(c / a, 2.0 ** (19.0 / 9.0), rtol=1e-9)
+    # without the flag e0 is not read
+    np.testing.assert_array_equal(orc.phase_tau(_ecc_par(0.1, 6.0), f, 0)[0],
+                                  orc.phase_tau(_ecc_par(0.0, 6.0), f, 0)[0])
+
+
+def test_eccentric_phase_parameter_derivatives(orc):
+    """At fixed f and f_ref the correction depends on the masses only through
+    the chirp mass (Newtonian order, M^{-5/3} with v/v_ref mass-free):
+    d Delta Psi/d Mc = -(5/3) Delta Psi/Mc, d Delta Psi/d eta = 0 at fixed Mc,
+    and d Psi/d e0 = 2 Delta Psi/e0; complex-step derivatives of the oracle's
+    phase, exact to rounding."""
+    f = np.geomspace(5.0, 800.0, 17)
+    for flags in (ECC, TID | ECC):
+        p = _ecc_par(0.08, 5.0)
+        p0 = _ecc_par(0.0, 5.0)
+        psi0 = orc.phase_tau(p0, f, flags)[0]
+        d = orc.phase_tau(p, f, flags)[0] - psi0          # carries ~u |Psi| of rounding
+        du = 1e-14 * np.abs(psi0).max()
+        je = orc.n_params(flags) - 1
+        dmc = orc.phase_cstep_par(p, f, flags, 0) - orc.phase_cstep_par(p0, f, flags, 0)
+        deta = orc.phase_cstep_par(p, f, flags, 1) - orc.phase_cstep_par(p0, f, flags, 1)
+        de0 = orc.phase_cstep_par(p, f, flags, je)
+        # the differences of whole-phase derivatives carry their rounding
+        full = np.abs(orc.phase_cstep_par(p0, f, flags, 0))
+        np.testing.assert_allclose(dmc, -5.0 / 3.0 * d / p[0], rtol=1e-9,
+                                   atol=1e-14 * full.max() + 2 * du / p[0])
+        scale = np.abs(orc.phase_cstep_par(p, f, flags, 1))
+        assert np.all(np.abs(deta) <= 1e-12 * scale.max())
+        np.testing.assert_allclose(de0, 2.0 * d / 0.08, rtol=1e-12, atol=2.0 * du / 0.08)
+
+
+def test_eccentric_fisher_reduces_to_circular(orc):
+    """With e0 = 0 the correction and its e0-derivative vanish: the Fisher
+    matrix with the e0 row equals the circular one in its other rows (bit for
+    bit) and has a zero e0 row; with e0 > 0 that row is nonzero and the
+    matrix stays symmetric and positive on its diagonal."""
+    for flags in (ROT, ROT | TID):
+        w = synth.bns1e4(n=3).with_npts(400)
+        w.flags = flags
+        w.npar = 13 if flags & TID else 11
+        circ = orc.fisher(w)
+        we = w.with_eccentricity(0.0)
+        ecc = orc.fisher(we)
+        P = w.npar
+        np.testing.assert_array_equal(ecc["fisher"][:P, :P], circ["fisher"])
+        assert np.all(ecc["fisher"][P] == 0) and np.all(ecc["fisher"][:, P] == 0)
+        np.testing.assert_array_equal(ecc["snr"], circ["snr"])
+        we = w.with_eccentricity(0.05)
+        F = orc.fisher(we)["fisher"]
+        assert np.all(F[P, P] > 0)
+        np.testing.assert_array_equal(F, F.transpose(1, 0, 2))
 
 
 def _component(par):
@@ -243,11 +329,12 @@ def test_delay_closed_form(orc):
 
 
 # ---------------------------------------------------------- derivatives
-@pytest.mark.parametrize("flags", [0, ROT | TID])
+@pytest.mark.parametrize("flags", [0, ROT | TID, ECC, ROT | TID | ECC])
 def test_dual_derivatives_vs_complex_step_and_fd(orc, flags):
     """Dual-number derivatives of the strain against (a) the complex step,
     exact to rounding, for every parameter slot, and (b) central finite
-    differences on the double-precision strain (error O(h^2))."""
+    differences on the double-precision strain (error O(h^2)); with
+    eccentricity (e0 = 0.07 given at 10 Hz) the e0 slot comes last."""
     if flags & TID:
         w, par = _bns_event(1)
         sites = w.site_array()
@@ -255,7 +342,9 @@ def test_dual_derivatives_vs_complex_step_and_fd(orc, flags):
         w = synth.bbh100(n=3)
         par = w.par[:, 1].copy()
         sites = w.site_array()
-    P = 13 if flags & TID else 11
+    par = np.concatenate([par, [0.07, 10.0]])     # e0, f_ref (read with ECC only)
+    P = orc.n_params(flags)
+    pidx = list(range(P - 1)) + [13 if flags & ECC else P - 1]   # slot -> parameter entry
     fc = orc.cut_frequency(par[0], par[1])
     f = np.geomspace(8.0, fc, 40)
     h, dh = orc.strain(par, sites, f, flags)
@@ -270,8 +359,8 @@ def test_dual_derivatives_vs_complex_step_and_fd(orc, flags):
             hp = orc.strain_plain(par, sites, f, flags, dt=step)
             hm = orc.strain_plain(par, sites, f, flags, dt=-step)
         else:
-            pp = par.copy(); pp[j] += step
-            pm = par.copy(); pm[j] -= step
+            pp = par.copy(); pp[pidx[j]] += step
+            pm = par.copy(); pm[pidx[j]] -= step
             hp = orc.strain_plain(pp, sites, f, flags)
             hm = orc.strain_plain(pm, sites, f, flags)
         fd = (hp - hm) / (2 * step)

@@ -133,6 +133,12 @@ def load():
     return _lib
 
 
+def n_params(flags) -> int:
+    """Fisher rows of a call: 11, plus the deformabilities with TIDAL, plus
+    e0 with ECCENTRIC."""
+    return 11 + (2 if flags & TIDAL else 0) + (1 if flags & ECCENTRIC else 0)
+
+
 def _check(code, what):
     if code != GWF_OK:
         msg = load().gwf_last_error().decode()
@@ -227,6 +233,12 @@ class DeviceWorkload:
         pm = getattr(wl, "par_mask", None)
         self.par_mask = None if pm is None else torch.as_tensor(
             np.ascontiguousarray(pm, dtype=np.uint32).view(np.int32), device=device)
+        ecc = getattr(wl, "ecc", None)
+        fre = getattr(wl, "f_ref_ecc", None)
+        self.ecc = None if ecc is None else torch.as_tensor(np.ascontiguousarray(ecc, dtype=np.float64),
+                                                            device=device)
+        self.f_ref_ecc = None if fre is None else torch.as_tensor(np.ascontiguousarray(fre, dtype=np.float64),
+                                                                  device=device)
         self.curves = upload_curves(self.sites, device)
         self.n_ifo = n_ifo(self.sites)
 
@@ -248,7 +260,9 @@ class DeviceWorkload:
         ev = Events(self.n, self.par.shape[1], self.par.data_ptr(),
                     None if self.tc_s is None else self.tc_s.data_ptr(),
                     None if self.active is None else self.active.data_ptr(),
-                    None if self.par_mask is None else self.par_mask.data_ptr())
+                    None if self.par_mask is None else self.par_mask.data_ptr(),
+                    None if self.ecc is None else self.ecc.data_ptr(),
+                    None if self.f_ref_ecc is None else self.f_ref_ecc.data_ptr())
         net, keep = network(self.sites, self.curves)
         if self.grid_f is None:
             grid = Grid(GRID_LOG, self.fmin.data_ptr(), None if self.fmax is None else self.fmax.data_ptr(),
@@ -278,7 +292,7 @@ def fisher(dw: DeviceWorkload, snr_th=0.0, per_ifo_snr=False, stream=None, out=N
     """Fisher matrices [P][P][N], SNR [N] and status [N] of every event."""
     import torch
     dev = dw.par.device
-    P = 13 if dw.flags & TIDAL else 11
+    P = n_params(dw.flags)
     res = out if out is not None else {}
     res.setdefault("fisher", torch.empty((P, P, dw.n), dtype=torch.float64, device=dev))
     res.setdefault("snr", torch.empty(dw.n, dtype=torch.float64, device=dev))
@@ -331,7 +345,7 @@ def fisher_ifo(dw: DeviceWorkload, stream=None, out=None):
     is fisher()'s; plus the parameter status."""
     import torch
     dev = dw.par.device
-    P = 13 if dw.flags & TIDAL else 11
+    P = n_params(dw.flags)
     res = out if out is not None else {}
     res.setdefault("fisher_ifo", torch.empty((dw.n_ifo, P, P, dw.n), dtype=torch.float64, device=dev))
     res.setdefault("status", torch.empty(dw.n, dtype=torch.int32, device=dev))
@@ -361,7 +375,7 @@ def waveform_deriv(dw: DeviceWorkload, offsets=None, total=None, stream=None, ou
         raise GwfError("offsets must be a contiguous int64 device tensor of n entries")
     if total is None:
         raise GwfError("total is required with explicit offsets")
-    P = 13 if dw.flags & TIDAL else 11
+    P = n_params(dw.flags)
     res = out if out is not None else {}
     res.setdefault("dh", torch.empty((P, dw.n_ifo, total), dtype=torch.complex128, device=dev))
     res.setdefault("status", torch.empty(dw.n, dtype=torch.int32, device=dev))
@@ -519,7 +533,7 @@ def fisher_static(dw: DeviceWorkload, chunk=4096, npts_max=None, mixed=False, st
     host workload's longest grid)."""
     import torch
     dev = dw.par.device
-    P = 13 if dw.flags & TIDAL else 11
+    P = n_params(dw.flags)
     res = out if out is not None else {}
     res.setdefault("fisher", torch.empty((P, P, dw.n), dtype=torch.float64, device=dev))
     res.setdefault("snr", torch.empty(dw.n, dtype=torch.float64, device=dev))
@@ -550,7 +564,7 @@ class Plan:
                                       dw.flags | (MIXED if mixed else 0), ctypes.byref(opt),
                                       ctypes.byref(self.handle),
                                       _stream(stream)), "gwf_plan_create")
-        self.P = 13 if dw.flags & TIDAL else 11
+        self.P = n_params(dw.flags)
 
     def info(self) -> dict:
         i = PlanInfo()

@@ -40,10 +40,12 @@ __device__ inline int slot_of(int i) { return i < 7 ? i : kAdjW; }   // LDS slot
 
 // Two wavefronts per SIMD: the registers are capped at 256 (the sums live in
 // LDS, not in registers).
-template <bool TIDAL, bool ROT>
+template <int NPI, bool ROT>
 __global__ __launch_bounds__(kABlock, 2) void adjoint_kernel(AdjointArgs a) {
-  constexpr int P = TIDAL ? 13 : 11;
-  constexpr uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u);
+  using PO = PhaseOnly<NPI>;
+  constexpr int P = PO::P;
+  constexpr bool TIDAL = PO::tidal;
+  constexpr uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u) | (PO::ecc ? kFlagEcc : 0u);
   __shared__ EventC ec;
   __shared__ SiteA sa[kMaxSites];
   __shared__ double Gb[P * P];
@@ -54,8 +56,10 @@ __global__ __launch_bounds__(kABlock, 2) void adjoint_kernel(AdjointArgs a) {
   const int tid = threadIdx.x;
   const int n_site = a.net.n_site;
   if (tid == 0) {
-    double p[13];
+    double p[kNparIn];
     for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
+    p[13] = PO::ecc && a.ecc ? a.ecc[e] : 0.0;
+    p[14] = PO::ecc && a.fref ? a.fref[e] : 0.0;
     event_setup(p, a.fmin[e], a.fmax ? a.fmax[e] : 0.0, a.npts[e], flags, ec);
     ok = ec.status == 0 && (a.status == nullptr || a.status[e] == 0);
   }
@@ -75,7 +79,7 @@ __global__ __launch_bounds__(kABlock, 2) void adjoint_kernel(AdjointArgs a) {
     return;
   }
   if (tid < n_site) {
-    double p[13];
+    double p[kNparIn];
     for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
     site_setup_adj(p, a.net.site[tid], ec, sa[tid], site_arms_on(a.active, a.ld, e, a.net, tid));
   }
@@ -94,13 +98,13 @@ __global__ __launch_bounds__(kABlock, 2) void adjoint_kernel(AdjointArgs a) {
     const int k = it * kABlock + tid;
     const bool in = k < ec.n;
     AdjPoint ap;
-    if (in) adjoint_point_setup<TIDAL, ROT>(ec, Gb, k, ap);
+    if (in) adjoint_point_setup<NPI, ROT>(ec, Gb, k, ap);
     for (int s = 0; s < n_site; ++s) {
       asm volatile("" ::: "memory");
       double acc[kAdjN];
 #pragma unroll
       for (int i = 0; i < kAdjN; ++i) acc[i] = 0.0;
-      if (in) adjoint_site<TIDAL>(ec, sa[s], Gb, ap, acc);
+      if (in) adjoint_site<NPI>(ec, sa[s], Gb, ap, acc);
 #pragma unroll
       for (int i = 0; i < kSlots; ++i) {
         const double v = acc[slot_of(i)];
@@ -149,13 +153,21 @@ __global__ __launch_bounds__(kABlock) void reduce_kernel(const double* __restric
 
 }  // namespace
 
-hipError_t launch_adjoint(const AdjointArgs& a, bool tidal, bool rot, hipStream_t stream) {
+template <int NPI>
+void launch_adjoint_n(const AdjointArgs& a, bool rot, dim3 grid, dim3 block, size_t lds, hipStream_t stream) {
+  if (rot) hipLaunchKernelGGL((adjoint_kernel<NPI, true>), grid, block, lds, stream, a);
+  else hipLaunchKernelGGL((adjoint_kernel<NPI, false>), grid, block, lds, stream, a);
+}
+
+hipError_t launch_adjoint(const AdjointArgs& a, int npi, bool rot, hipStream_t stream) {
   dim3 grid((unsigned)a.n), block(kABlock);
   const size_t lds = sizeof(double) * (size_t)a.net.n_site * kSlots * kCols;
-  if (tidal && rot) hipLaunchKernelGGL((adjoint_kernel<true, true>), grid, block, lds, stream, a);
-  else if (tidal) hipLaunchKernelGGL((adjoint_kernel<true, false>), grid, block, lds, stream, a);
-  else if (rot) hipLaunchKernelGGL((adjoint_kernel<false, true>), grid, block, lds, stream, a);
-  else hipLaunchKernelGGL((adjoint_kernel<false, false>), grid, block, lds, stream, a);
+  switch (npi) {
+    case 6: launch_adjoint_n<6>(a, rot, grid, block, lds, stream); break;
+    case 5: launch_adjoint_n<5>(a, rot, grid, block, lds, stream); break;
+    case 4: launch_adjoint_n<4>(a, rot, grid, block, lds, stream); break;
+    default: launch_adjoint_n<3>(a, rot, grid, block, lds, stream);
+  }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   const int width = a.net.n_site * 4;

@@ -172,14 +172,13 @@ struct AdjPoint {
   double gc[8], cgc;
 };
 
-template <bool TIDAL, bool ROT>
+template <int NPI, bool ROT>
 __host__ __device__ inline void adjoint_point_setup(const EventC& ec, const double* Gb, int32_t k,
                                                     AdjPoint& ap) {
-  constexpr int NPI = TIDAL ? 5 : 3;
   constexpr int P = 8 + NPI;
-  point_setup(ec, k, true, ROT, ap.q);
+  point_setup<true, false, PhaseOnly<NPI>::ecc>(ec, k, true, ROT, ap.q);
   double c[NPI];
-  phase_only_coefficients<TIDAL>(ec, ap.q, c);
+  phase_only_coefficients<NPI>(ec, ap.q, c);
   double cg[NPI];
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
@@ -213,10 +212,9 @@ __host__ __device__ inline void adjoint_point_setup(const EventC& ec, const doub
 // geometry gives the latitude and longitude tangents of P, PH, Pt, dH and dT,
 // contracted with those adjoints.  Only the values and the adjoints are live
 // across the interferometers.
-template <bool TIDAL>
+template <int NPI>
 __host__ __device__ inline void adjoint_site(const EventC& ec, const SiteA& sa, const double* Gb,
                                              const AdjPoint& ap, double* acc) {
-  constexpr int NPI = TIDAL ? 5 : 3;
   constexpr int P = 8 + NPI;
   const Point& q = ap.q;
   // hour angle, pattern vectors and arrival-time derivatives: values
@@ -407,12 +405,12 @@ __host__ __device__ inline void adjoint_site(const EventC& ec, const SiteA& sa, 
 }
 
 // One grid point and one site (host checks).
-template <bool TIDAL, bool ROT>
+template <int NPI, bool ROT>
 __host__ __device__ inline void adjoint_point(const EventC& ec, const SiteA& sa, const double* Gb,
                                               int32_t k, double* acc) {
   AdjPoint ap;
-  adjoint_point_setup<TIDAL, ROT>(ec, Gb, k, ap);
-  adjoint_site<TIDAL>(ec, sa, Gb, ap, acc);
+  adjoint_point_setup<NPI, ROT>(ec, Gb, k, ap);
+  adjoint_site<NPI>(ec, sa, Gb, ap, acc);
 }
 
 }  // namespace gwf

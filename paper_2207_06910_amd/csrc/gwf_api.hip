@@ -94,7 +94,7 @@ gwf_status api_check_common(const gwf_events* ev, const gwf_grid* grid, uint32_t
   }
   if (flags & ~(uint32_t)(GWF_EARTH_ROT | GWF_TIDAL | GWF_MIXED | GWF_ECCENTRIC))
     return api_fail(GWF_E_INVALID_ARG, "unknown flag bits 0x%x", flags);
-  if (flags & GWF_ECCENTRIC) return api_fail(GWF_E_UNSUPPORTED, "GWF_ECCENTRIC is not available in this build");
+  if ((flags & GWF_ECCENTRIC) && !ev->ecc) return api_fail(GWF_E_INVALID_ARG, "GWF_ECCENTRIC needs ev->ecc");
   return GWF_OK;
 }
 
@@ -154,6 +154,7 @@ gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_gr
   a.par_mask = ev->par_mask;
   a.fisher = fisher; a.snr = snr; a.status = status;
   const bool rot = (flags & GWF_EARTH_ROT) != 0, tidal = (flags & GWF_TIDAL) != 0;
+  a.ecc = ev->ecc; a.fref = ev->f_ref_ecc;
   hipStream_t s = (hipStream_t)stream;
   // per-interferometer SNRs, or the SNR pass that decides the threshold
   if (snr_ifo || snr_th > 0.0) {
@@ -166,7 +167,7 @@ gwf_status gwf_fisher(const gwf_events* ev, const gwf_network* net, const gwf_gr
     if (err != hipSuccess) return api_hip_fail(err, "snr kernel launch");
     if (snr_th > 0.0) a.snr_pre = snr;
   }
-  hipError_t err = gwf::launch_fisher(a, tidal, rot, s);
+  hipError_t err = gwf::launch_fisher(a, api_npi(flags), rot, s);
   if (err != hipSuccess) return api_hip_fail(err, "fisher kernel launch");
   return GWF_OK;
 }
@@ -185,12 +186,13 @@ gwf_status gwf_fisher_ifo(const gwf_events* ev, const gwf_network* net, const gw
   a.active = ev->active;
   a.par_mask = ev->par_mask;
   a.snr = nullptr; a.status = status;
-  const bool rot = (flags & GWF_EARTH_ROT) != 0, tidal = (flags & GWF_TIDAL) != 0;
-  const int64_t P = tidal ? 13 : 11;
+  const bool rot = (flags & GWF_EARTH_ROT) != 0;
+  const int64_t P = 8 + api_npi(flags);
+  a.ecc = ev->ecc; a.fref = ev->f_ref_ecc;
   for (int d = 0; d < a.net.n_ifo; ++d) {
     a.ifo_sel = d + 1;
     a.fisher = fisher_ifo + (int64_t)d * P * P * ev->n;
-    hipError_t err = gwf::launch_fisher(a, tidal, rot, (hipStream_t)stream);
+    hipError_t err = gwf::launch_fisher(a, api_npi(flags), rot, (hipStream_t)stream);
     if (err != hipSuccess) return api_hip_fail(err, "fisher kernel launch");
   }
   return GWF_OK;
@@ -209,6 +211,7 @@ gwf_status gwf_waveform(const gwf_events* ev, const gwf_network* net, const gwf_
   a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
   api_explicit_grid(grid, a.goff, a.gf);
   a.offsets = offsets; a.total = total; a.h = h; a.status = status;
+  a.ecc = ev->ecc; a.fref = ev->f_ref_ecc; a.ecc_flag = flags & GWF_ECCENTRIC;
   hipError_t err = gwf::launch_waveform(a, (flags & GWF_TIDAL) != 0, (flags & GWF_EARTH_ROT) != 0,
                                         (flags & GWF_MIXED) != 0, (hipStream_t)stream);
   if (err != hipSuccess) return api_hip_fail(err, "waveform kernel launch");
@@ -229,7 +232,8 @@ gwf_status gwf_waveform_deriv(const gwf_events* ev, const gwf_network* net, cons
   a.fmin = grid->fmin; a.fmax = grid->fmax; a.npts = grid->npts;
   api_explicit_grid(grid, a.goff, a.gf);
   a.offsets = offsets; a.total = total; a.dh = dh; a.status = status; a.par_mask = ev->par_mask;
-  hipError_t err = gwf::launch_waveform_deriv(a, (flags & GWF_TIDAL) != 0, (flags & GWF_EARTH_ROT) != 0,
+  a.ecc = ev->ecc; a.fref = ev->f_ref_ecc; a.ecc_flag = flags & GWF_ECCENTRIC;
+  hipError_t err = gwf::launch_waveform_deriv(a, api_npi(flags), (flags & GWF_EARTH_ROT) != 0,
                                               (hipStream_t)stream);
   if (err != hipSuccess) return api_hip_fail(err, "waveform derivative kernel launch");
   return GWF_OK;
@@ -254,7 +258,8 @@ gwf_status gwf_fisher_adjoint(const gwf_events* ev, const gwf_network* net, cons
   a.active = ev->active;
   a.par_mask = ev->par_mask;
   a.grad_event = grad_event; a.grad = grad;
-  hipError_t err = gwf::launch_adjoint(a, (flags & GWF_TIDAL) != 0, (flags & GWF_EARTH_ROT) != 0,
+  a.ecc = ev->ecc; a.fref = ev->f_ref_ecc;
+  hipError_t err = gwf::launch_adjoint(a, api_npi(flags), (flags & GWF_EARTH_ROT) != 0,
                                        (hipStream_t)stream);
   if (err != hipSuccess) return api_hip_fail(err, "adjoint kernel launch");
   return GWF_OK;
@@ -277,13 +282,13 @@ gwf_status gwf_invert(int32_t P, int64_t n, const double* fisher, double cond_ma
 
 gwf_status gwf_fisher_basis(int32_t P, int64_t n, const double* fisher, const gwf_events* ev,
                             uint32_t basis, double* out, int32_t* status, void* stream) {
-  if (P != 11 && P != 13) return api_fail(GWF_E_INVALID_ARG, "P=%d must be 11 or 13", P);
+  if (P < 11 || P > 14) return api_fail(GWF_E_INVALID_ARG, "P=%d must be 11 to 14", P);
   if (n < 1) return api_fail(GWF_E_INVALID_ARG, "n=%lld must be >= 1", (long long)n);
   if (!fisher || !out || !ev || !ev->par) return api_fail(GWF_E_INVALID_ARG, "fisher, out and ev->par are required");
   if (ev->n != n || ev->ld < n) return api_fail(GWF_E_INVALID_ARG, "ev->n must be n and ev->ld >= n");
   if (basis & ~7u) return api_fail(GWF_E_INVALID_ARG, "basis=%u has unknown bits", basis);
-  if ((basis & GWF_BASIS_LAMBDA_TILDE) && P != 13)
-    return api_fail(GWF_E_INVALID_ARG, "the tidal basis needs P=13");
+  if ((basis & GWF_BASIS_LAMBDA_TILDE) && P < 13)
+    return api_fail(GWF_E_INVALID_ARG, "the tidal basis needs P=13 (or 14 with e0)");
   gwf::BasisArgs a{};
   a.n = n; a.fisher = fisher; a.out = out; a.par = ev->par; a.ld = ev->ld; a.basis = basis; a.status = status;
   hipError_t err = gwf::launch_basis(a, P, (hipStream_t)stream);

@@ -13,3 +13,8 @@ gwf_status api_hip_fail(hipError_t err, const char* where);
 gwf_status api_pack_network(const gwf_network* net, gwf::NetDesc& nd);
 // Checks shared by every call taking events and a grid.
 gwf_status api_check_common(const gwf_events* ev, const gwf_grid* grid, uint32_t flags);
+// Phase-only Fisher parameters of a call: 3, plus 2 with GWF_TIDAL, plus 1
+// with GWF_ECCENTRIC (P = 8 + this).
+inline int api_npi(uint32_t flags) {
+  return 3 + ((flags & GWF_TIDAL) ? 2 : 0) + ((flags & GWF_ECCENTRIC) ? 1 : 0);
+}

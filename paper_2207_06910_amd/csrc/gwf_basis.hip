@@ -38,7 +38,7 @@ template <int P>
 __device__ inline void apply_j(const BasisJ& b, double* x) {
   const double x0 = x[0], x1 = x[1];
   double xe = x1;
-  if (P >= 13 && b.lam) {
+  if (P >= 13 && b.lam) {                 // P = 14: e0 (row 13) is not mixed
     const double x11 = x[11], x12 = x[12];
     xe = fma(x11, b.g[0], fma(x12, b.g[1], x1));
     x[11] = fma(x11, b.K[0][0], x12 * b.K[1][0]);
@@ -136,8 +136,11 @@ __global__ __launch_bounds__(kBBlock) void basis_kernel(BasisArgs a) {
 
 hipError_t launch_basis(const BasisArgs& a, int P, hipStream_t stream) {
   const unsigned blocks = (unsigned)((a.n + kBBlock - 1) / kBBlock);
+  // P = 12 and 14 carry e0 as their last row, which no basis mixes
   if (P == 13) hipLaunchKernelGGL((basis_kernel<13>), dim3(blocks), dim3(kBBlock), 0, stream, a);
   else if (P == 11) hipLaunchKernelGGL((basis_kernel<11>), dim3(blocks), dim3(kBBlock), 0, stream, a);
+  else if (P == 14) hipLaunchKernelGGL((basis_kernel<14>), dim3(blocks), dim3(kBBlock), 0, stream, a);
+  else if (P == 12) hipLaunchKernelGGL((basis_kernel<12>), dim3(blocks), dim3(kBBlock), 0, stream, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -31,8 +31,10 @@ __global__ void setup_kernel(SetupArgs a) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.n) return;
   const bool tidal = (a.flags & kFlagTidal) != 0;
-  double p[13];
+  double p[kNparIn];
   for (int r = 0; r < 13; ++r) p[r] = (r < 11 || tidal) ? a.par[r * a.ld + t] : 0.0;
+  p[13] = (a.flags & kFlagEcc) && a.ecc ? a.ecc[t] : 0.0;
+  p[14] = (a.flags & kFlagEcc) && a.fref ? a.fref[t] : 0.0;
   EventC ec;
   event_setup(p, a.fmin[t], a.fmax ? a.fmax[t] : 0.0, a.npts[t], a.flags, ec);
   if (!ec.status && (a.npts[t] != a.npts_plan[t] || a.npts[t] > a.npts_max))
@@ -47,9 +49,9 @@ __global__ void setup_kernel(SetupArgs a) {
     }
 }
 
-template <bool TIDAL, bool ROT, bool MIXED>
-__global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void items_kernel(ItemsArgs a) {
-  using Dm = FisherDims<TIDAL>;
+template <int NPI, bool ROT, bool MIXED>
+__global__ __launch_bounds__(FisherDims<NPI>::TIDAL ? 2 * kBlock : kBlock) void items_kernel(ItemsArgs a) {
+  using Dm = FisherDims<NPI>;
   constexpr int NACC = Dm::NACC;
   __shared__ FisherLds L;
   __shared__ int32_t item;
@@ -80,16 +82,16 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void items_kernel(Item
       double t = 0.0;
       // both forms: PN series as sums of products over shared powers and the
       // PSD power law once per point (in FP32 for the mixed form)
-      fisher_sums<TIDAL, ROT, MIXED, true>(ecg, scg, n_site, k0, k1, L, &t);
+      fisher_sums<NPI, ROT, MIXED, true>(ecg, scg, n_site, k0, k1, L, &t);
       if (tid < NACC) out[tid] = t;
     }
     __syncthreads();                             // LDS is reused by the next item
   }
 }
 
-template <bool TIDAL>
+template <int NPI_>
 __global__ void combine_kernel(CombineArgs a) {
-  using Dm = FisherDims<TIDAL>;
+  using Dm = FisherDims<NPI_>;
   constexpr int P = Dm::P, NPI = Dm::NPI, NACC = Dm::NACC;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.n * NACC) return;
@@ -184,46 +186,72 @@ hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <bool MIXED>
-void launch_items_t(const ItemsArgs& a, bool tidal, bool rot, dim3 grid, dim3 block, hipStream_t s) {
-  if (tidal && rot) hipLaunchKernelGGL((items_kernel<true, true, MIXED>), grid, block, 0, s, a);
-  else if (tidal) hipLaunchKernelGGL((items_kernel<true, false, MIXED>), grid, block, 0, s, a);
-  else if (rot) hipLaunchKernelGGL((items_kernel<false, true, MIXED>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((items_kernel<false, false, MIXED>), grid, block, 0, s, a);
+template <int NPI, bool MIXED>
+void launch_items_n(const ItemsArgs& a, bool rot, dim3 grid, dim3 block, hipStream_t s) {
+  if (rot) hipLaunchKernelGGL((items_kernel<NPI, true, MIXED>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((items_kernel<NPI, false, MIXED>), grid, block, 0, s, a);
 }
 
-hipError_t launch_items(const ItemsArgs& a, bool tidal, bool rot, bool mixed, int n_wg, hipStream_t s) {
+template <bool MIXED>
+void launch_items_t(const ItemsArgs& a, int npi, bool rot, dim3 grid, dim3 block, hipStream_t s) {
+  switch (npi) {
+    case 6: launch_items_n<6, MIXED>(a, rot, grid, block, s); break;
+    case 5: launch_items_n<5, MIXED>(a, rot, grid, block, s); break;
+    case 4: launch_items_n<4, MIXED>(a, rot, grid, block, s); break;
+    default: launch_items_n<3, MIXED>(a, rot, grid, block, s);
+  }
+}
+
+hipError_t launch_items(const ItemsArgs& a, int npi, bool rot, bool mixed, int n_wg, hipStream_t s) {
   dim3 grid((unsigned)n_wg), block(kBlock);
-  if (mixed) launch_items_t<true>(a, tidal, rot, grid, block, s);
-  else launch_items_t<false>(a, tidal, rot, grid, block, s);
+  if (mixed) launch_items_t<true>(a, npi, rot, grid, block, s);
+  else launch_items_t<false>(a, npi, rot, grid, block, s);
   return hipGetLastError();
 }
 
-hipError_t launch_combine(const CombineArgs& a, bool tidal, hipStream_t s) {
-  const int nacc = tidal ? FisherDims<true>::NACC : FisherDims<false>::NACC;
-  const int64_t threads = a.n * nacc;
+int fisher_nacc(int npi) {
+  switch (npi) {
+    case 6: return FisherDims<6>::NACC;
+    case 5: return FisherDims<5>::NACC;
+    case 4: return FisherDims<4>::NACC;
+    default: return FisherDims<3>::NACC;
+  }
+}
+
+hipError_t launch_combine(const CombineArgs& a, int npi, hipStream_t s) {
+  const int64_t threads = a.n * fisher_nacc(npi);
   dim3 grid((unsigned)((threads + 255) / 256)), block(256);
-  if (tidal) hipLaunchKernelGGL((combine_kernel<true>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((combine_kernel<false>), grid, block, 0, s, a);
+  switch (npi) {
+    case 6: hipLaunchKernelGGL((combine_kernel<6>), grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((combine_kernel<5>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((combine_kernel<4>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((combine_kernel<3>), grid, block, 0, s, a);
+  }
   return hipGetLastError();
 }
 
-template <bool MIXED>
-int items_resident_t(bool tidal, bool rot) {
+template <int NPI, bool MIXED>
+int items_resident_n(bool rot) {
   int nb = 0;
-  hipError_t err;
-  if (tidal && rot) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, items_kernel<true, true, MIXED>, kBlock, 0);
-  else if (tidal) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, items_kernel<true, false, MIXED>, kBlock, 0);
-  else if (rot) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, items_kernel<false, true, MIXED>, kBlock, 0);
-  else err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, items_kernel<false, false, MIXED>, kBlock, 0);
+  const hipError_t err = rot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, items_kernel<NPI, true, MIXED>, kBlock, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, items_kernel<NPI, false, MIXED>, kBlock, 0);
   return err == hipSuccess ? nb : 0;
 }
 
-int items_max_resident(bool tidal, bool rot, bool mixed) {
-  return mixed ? items_resident_t<true>(tidal, rot) : items_resident_t<false>(tidal, rot);
+template <bool MIXED>
+int items_resident_t(int npi, bool rot) {
+  switch (npi) {
+    case 6: return items_resident_n<6, MIXED>(rot);
+    case 5: return items_resident_n<5, MIXED>(rot);
+    case 4: return items_resident_n<4, MIXED>(rot);
+    default: return items_resident_n<3, MIXED>(rot);
+  }
 }
 
-int fisher_nacc(bool tidal) { return tidal ? FisherDims<true>::NACC : FisherDims<false>::NACC; }
+int items_max_resident(int npi, bool rot, bool mixed) {
+  return mixed ? items_resident_t<true>(npi, rot) : items_resident_t<false>(npi, rot);
+}
+
 int fisher_block() { return kBlock; }
 
 }  // namespace gwf

@@ -13,6 +13,8 @@ struct Item {
 struct SetupArgs {
   const double* par;
   int64_t ld, n;
+  const double* ecc;          // [n] or NULL: e0 (with kFlagEcc)
+  const double* fref;         // [n] or NULL: reference frequency of e0
   const double* fmin;
   const double* fmax;
   const int32_t* npts;
@@ -57,12 +59,13 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_items_build(const int32_t* npts, int64_t n, int32_t chunk, int32_t npts_max, int32_t* first,
                               int32_t* n_items, Item* items, hipStream_t s);
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
-hipError_t launch_items(const ItemsArgs& a, bool tidal, bool rot, bool mixed, int n_wg, hipStream_t s);
-hipError_t launch_combine(const CombineArgs& a, bool tidal, hipStream_t s);
-int fisher_nacc(bool tidal);
+// npi: phase-only parameters, 3 + 2 (tides) + 1 (eccentricity)
+hipError_t launch_items(const ItemsArgs& a, int npi, bool rot, bool mixed, int n_wg, hipStream_t s);
+hipError_t launch_combine(const CombineArgs& a, int npi, hipStream_t s);
+int fisher_nacc(int npi);
 // Work-item workgroups that one compute unit holds at once (registers and
 // LDS of the instantiation), 0 if the runtime cannot tell.
-int items_max_resident(bool tidal, bool rot, bool mixed);
+int items_max_resident(int npi, bool rot, bool mixed);
 int fisher_block();
 
 }  // namespace gwf

@@ -32,11 +32,12 @@ namespace gwf {
 // transcendental sequences.
 // (The P = 11 instantiation keeps the one-wavefront budget: under the
 // two-wavefront cap it spills.)
-template <bool TIDAL, bool ROT, bool EXPL>
-__global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(FisherArgs a) {
-  using Dm = FisherDims<TIDAL>;
+template <int NPI_, bool ROT, bool EXPL>
+__global__ __launch_bounds__(FisherDims<NPI_>::TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(FisherArgs a) {
+  using Dm = FisherDims<NPI_>;
+  using PO = PhaseOnly<NPI_>;
   constexpr int P = Dm::P, NPI = Dm::NPI, NACC = Dm::NACC;
-  constexpr uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u);
+  constexpr uint32_t flags = (PO::tidal ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u) | (PO::ecc ? kFlagEcc : 0u);
 
   __shared__ EventC ec;
   __shared__ SiteC sc[kMaxSites];
@@ -46,8 +47,8 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(Fis
   const int64_t e = blockIdx.x;
   const int tid = threadIdx.x;
   const int n_site = a.net.n_site;
-  double p[13];
-  load_par(a.par, a.ld, e, TIDAL, p);
+  double p[kNparIn];
+  load_par(a.par, a.ld, e, PO::tidal, PO::ecc ? a.ecc : nullptr, a.fref, p);
   if (tid == 0) {
     event_setup_grid(p, a.fmin, a.fmax, a.npts, a.goff, a.gf, e, flags, ec);
     int32_t sk = ec.status;
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(Fis
   __syncthreads();
 
   double t = 0.0;
-  fisher_sums<TIDAL, ROT, false, true, EXPL>(ec, sc, n_site, 0, ec.n, L, &t);
+  fisher_sums<NPI, ROT, false, true, EXPL>(ec, sc, n_site, 0, ec.n, L, &t);
   if (tid < NACC) {
     int r, c;
     slot_position(tid, NPI, r, c);
@@ -99,8 +100,8 @@ __global__ __launch_bounds__(kBlock) void snr_kernel(SnrArgs a) {
   const int64_t e = blockIdx.x;
   const int tid = threadIdx.x;
   const int n_site = a.net.n_site;
-  double p[13];
-  load_par(a.par, a.ld, e, a.tidal, p);
+  double p[kNparIn];
+  load_par(a.par, a.ld, e, a.tidal, nullptr, nullptr, p);
   if (tid == 0)
     event_setup_grid(p, a.fmin, a.fmax, a.npts, a.goff, a.gf, e, flags | (a.tidal ? kFlagTidal : 0u), ec);
   __syncthreads();
@@ -177,19 +178,27 @@ __global__ __launch_bounds__(kBlock) void snr_kernel(SnrArgs a) {
   }
 }
 
+template <int NPI, bool EXPL>
+void launch_fisher_n(const FisherArgs& a, bool rot, dim3 grid, dim3 block, hipStream_t stream) {
+  if (rot) hipLaunchKernelGGL((fisher_kernel<NPI, true, EXPL>), grid, block, 0, stream, a);
+  else hipLaunchKernelGGL((fisher_kernel<NPI, false, EXPL>), grid, block, 0, stream, a);
+}
+
 template <bool EXPL>
-void launch_fisher_t(const FisherArgs& a, bool tidal, bool rot, dim3 grid, dim3 block, hipStream_t stream) {
-  if (tidal && rot) hipLaunchKernelGGL((fisher_kernel<true, true, EXPL>), grid, block, 0, stream, a);
-  else if (tidal) hipLaunchKernelGGL((fisher_kernel<true, false, EXPL>), grid, block, 0, stream, a);
-  else if (rot) hipLaunchKernelGGL((fisher_kernel<false, true, EXPL>), grid, block, 0, stream, a);
-  else hipLaunchKernelGGL((fisher_kernel<false, false, EXPL>), grid, block, 0, stream, a);
+void launch_fisher_t(const FisherArgs& a, int npi, bool rot, dim3 grid, dim3 block, hipStream_t stream) {
+  switch (npi) {
+    case 6: launch_fisher_n<6, EXPL>(a, rot, grid, block, stream); break;
+    case 5: launch_fisher_n<5, EXPL>(a, rot, grid, block, stream); break;
+    case 4: launch_fisher_n<4, EXPL>(a, rot, grid, block, stream); break;
+    default: launch_fisher_n<3, EXPL>(a, rot, grid, block, stream);
+  }
 }
 
 // An explicit grid (a.gf set) selects the instantiations that read it.
-hipError_t launch_fisher(const FisherArgs& a, bool tidal, bool rot, hipStream_t stream) {
+hipError_t launch_fisher(const FisherArgs& a, int npi, bool rot, hipStream_t stream) {
   dim3 grid((unsigned)a.n), block(kBlock);
-  if (a.gf) launch_fisher_t<true>(a, tidal, rot, grid, block, stream);
-  else launch_fisher_t<false>(a, tidal, rot, grid, block, stream);
+  if (a.gf) launch_fisher_t<true>(a, npi, rot, grid, block, stream);
+  else launch_fisher_t<false>(a, npi, rot, grid, block, stream);
   return hipGetLastError();
 }
 

@@ -13,9 +13,10 @@
 // iteration each wavefront stages its 64 points' a_f and c_f in LDS and
 // folds them into 4x4 output tiles of X with the four-block FP64 MFMA
 // 4x4x4 (k = frequency), which keeps those sums out of the lanes' registers.
-// The 13 x 5 block (tides; 11 x 3 without) needs seven tiles (three): two
-// MFMAs (one) per four points, a quarter of the cycles of one 16x16x4 MFMA
-// per four points, which computes mostly padding.
+// The 13 x 5 block (tides; 11 x 3 without; with e0 one more row and column,
+// in the same tiles) needs seven tiles (three): two MFMAs (one) per four
+// points, a quarter of the cycles of one 16x16x4 MFMA per four points, which
+// computes mostly padding.
 // The sums are then reduced in a fixed order (wavefront butterflies, then
 // the waves in index order), so results are bitwise reproducible.
 #pragma once
@@ -26,18 +27,19 @@ namespace gwf {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kRowsA = 16;        // 8 U rows, up to 5 W c rows, zero rows to a whole tile
-constexpr int kRowsB = 8;         // up to 5 c rows, zero rows to a whole tile
+constexpr int kRowsA = 16;        // 8 U rows, up to 6 W c rows, zero rows to a whole tile
+constexpr int kRowsB = 8;         // up to 6 c rows, zero rows to a whole tile
 constexpr int kZeroRowB = 7;      // a B row no point writes (operand of unused tile slots)
 constexpr int kZeroRowA = 15;
 constexpr int kTileLd = 64 + 4;   // row stride (doubles): an operand read touches 8 rows x
                                   // 4 points, 2 (8 row + k) mod 64 distinct dword banks
-constexpr int kNaccMax = 91;
+constexpr int kNaccMax = 105;    // 36 + 8 NPI + NPI (NPI + 1)/2 at NPI = 6
 
-template <bool TIDAL>
+template <int NPI_>
 struct FisherDims {
-  static constexpr int P = TIDAL ? 13 : 11;
-  static constexpr int NPI = P - 8;                  // phase-only parameters
+  static constexpr int NPI = NPI_;                   // phase-only parameters
+  static constexpr bool TIDAL = NPI >= 5;
+  static constexpr int P = 8 + NPI;
   static constexpr int NG = 36, NX = 8 * NPI, NY = NPI * (NPI + 1) / 2;
   static constexpr int NACC = NG + NX + NY;          // SNR^2 = Gamma_{Phic,Phic}
   // 4x4 output tiles (row group R of a_f, column group C of c_f) of the
@@ -63,19 +65,23 @@ __device__ inline double wave_sum(double x) {
   return x;
 }
 
-// Load an event's 13 parameters (missing tidal rows read as zero).
+// Load an event's inputs: the 13 parameters (missing tidal rows read as
+// zero), e0 and its reference frequency (zero without eccentricity; a NULL
+// f_ref array means the grid's first frequency).
 __device__ inline void load_par(const double* __restrict__ par, int64_t ld, int64_t e, bool tidal,
-                                double p[13]) {
+                                const double* ecc, const double* fref, double p[kNparIn]) {
   for (int r = 0; r < 13; ++r) p[r] = (r < 11 || tidal) ? par[r * ld + e] : 0.0;
+  p[13] = ecc ? ecc[e] : 0.0;
+  p[14] = fref ? fref[e] : 0.0;
 }
 
 // Sums of points [k0, k1) of the event whose constants are ec/sc.  On
 // return (after a workgroup barrier), lane t < NACC holds accumulator slot t
 // (see slot_position) in *tot.
-template <bool TIDAL, bool ROT, bool MIXED = false, bool PSUM = true, bool EXPL = false>
+template <int NPI_, bool ROT, bool MIXED = false, bool PSUM = true, bool EXPL = false>
 __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site, int k0, int k1,
                                    FisherLds& L, double* tot) {
-  using Dm = FisherDims<TIDAL>;
+  using Dm = FisherDims<NPI_>;
   constexpr int NPI = Dm::NPI, NG = Dm::NG, NX = Dm::NX, NACC = Dm::NACC;
   const int tid = threadIdx.x;
   double G[kGramAcc];
@@ -115,7 +121,7 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
     for (int b = 0; b < 8; ++b) U[b] = 0.0;
 #pragma unroll
     for (int i = 0; i < NPI; ++i) cph[i] = 0.0;
-    if (k < k1) accumulate_point<TIDAL, ROT, MIXED, PSUM, EXPL>(ec, sc, n_site, k, G, U, W, cph);
+    if (k < k1) accumulate_point<NPI, ROT, MIXED, PSUM, EXPL>(ec, sc, n_site, k, G, U, W, cph);
     // stage this point's row (points past the range contribute zeros)
 #pragma unroll
     for (int b = 0; b < 8; ++b) A[b][lane] = U[b];

@@ -8,6 +8,8 @@ namespace gwf {
 struct FisherArgs {
   const double* par;
   int64_t ld, n;
+  const double* ecc;        // [n] or NULL: e0 (eccentric instantiations only)
+  const double* fref;       // [n] or NULL: reference frequency of e0 (NULL: grid start)
   const double* fmin;
   const double* fmax;       // NULL: cut frequency
   const int32_t* npts;
@@ -88,6 +90,9 @@ struct BasisArgs {
 struct WaveformArgs {
   const double* par;
   int64_t ld, n;
+  const double* ecc;        // [n] or NULL: e0 (with kFlagEcc in the call's flags)
+  const double* fref;       // [n] or NULL: reference frequency of e0
+  uint32_t ecc_flag;        // kFlagEcc or 0
   const double* tc_s;       // [n] or NULL
   const double* fmin;
   const double* fmax;       // NULL: cut frequency
@@ -106,6 +111,8 @@ struct WaveformArgs {
 struct AdjointArgs {
   const double* par;
   int64_t ld, n;
+  const double* ecc;        // [n] or NULL: e0 (eccentric instantiations only)
+  const double* fref;       // [n] or NULL
   const double* fmin;
   const double* fmax;       // NULL: cut frequency
   const int32_t* npts;
@@ -119,12 +126,13 @@ struct AdjointArgs {
   double* grad;             // [n_site][4]
 };
 
-hipError_t launch_fisher(const FisherArgs& a, bool tidal, bool rot, hipStream_t stream);
+// npi: phase-only parameters, 3 + 2 (tides) + 1 (eccentricity)
+hipError_t launch_fisher(const FisherArgs& a, int npi, bool rot, hipStream_t stream);
 hipError_t launch_snr(const SnrArgs& a, bool rot, hipStream_t stream);
 hipError_t launch_invert(const InvertArgs& a, int P, hipStream_t stream);
 hipError_t launch_basis(const BasisArgs& a, int P, hipStream_t stream);
-hipError_t launch_waveform_deriv(const WaveformArgs& a, bool tidal, bool rot, hipStream_t stream);
+hipError_t launch_waveform_deriv(const WaveformArgs& a, int npi, bool rot, hipStream_t stream);
 hipError_t launch_waveform(const WaveformArgs& a, bool tidal, bool rot, bool mixed, hipStream_t stream);
-hipError_t launch_adjoint(const AdjointArgs& a, bool tidal, bool rot, hipStream_t stream);
+hipError_t launch_adjoint(const AdjointArgs& a, int npi, bool rot, hipStream_t stream);
 
 }  // namespace gwf

@@ -61,6 +61,8 @@ constexpr int kMaxIfo = 16;
 constexpr uint32_t kFlagRot = 1;
 constexpr uint32_t kFlagTidal = 2;
 constexpr uint32_t kFlagMixed = 4;
+constexpr uint32_t kFlagEcc = 8;
+constexpr int kNparIn = 15;      // event inputs: the 13 parameters, e0, f_ref (0: the grid start)
 
 enum : int32_t { kEvInvalid = 1, kEvNotPD = 2, kEvIllCond = 4, kEvNonFinite = 8, kEvSkipped = 16, kEvSvd = 32 };
 
@@ -105,6 +107,11 @@ struct EventC {
   // (A = exp(lnA - 3.5 ln v)), and -(Phic + pi/4)/(2 pi)
   PhaseSeries cyc;
   double lnA, cyc0;
+  // moderate eccentricity (ecc != 0): the phase gains ecc_psi v^-5 r with
+  // r = (v_ref/v)^{19/3} = exp((19/3)(ecc_lnvr - ln v)); ecc_mc v^-5 r joins
+  // dPsi/dMc and ecc_e0 v^-5 r is dPsi/de0 (eta does not enter at fixed Mc)
+  double ecc_lnvr, ecc_psi, ecc_mc, ecc_e0, ecc_cyc;
+  int32_t ecc, pad_ecc;
 };
 
 struct SiteC {
@@ -305,17 +312,19 @@ __host__ __device__ inline bool rows_in(uint32_t m, int r, int c) { return ((m >
 
 // Parameter validity; returns the status bits of an event.
 __host__ __device__ inline int32_t check_event(const double* p, bool tidal, double fmin, double fmax,
-                                               int32_t n) {
+                                               int32_t n, bool ecc = false) {
   int32_t st = 0;
   const int np = tidal ? 13 : 11;
   for (int i = 0; i < np; ++i)
     if (!finite(p[i])) st |= kEvNonFinite;
+  if (ecc && (!finite(p[13]) || !finite(p[14]))) st |= kEvNonFinite;
   if (!finite(fmin) || !finite(fmax)) st |= kEvNonFinite;
   if (st) return st;
   if (!(p[0] > 0.0) || !(p[1] > 0.0) || !(p[1] <= 0.25) || !(p[2] > 0.0)) st |= kEvInvalid;
   if (fabs(p[9]) > 1.0 || fabs(p[10]) > 1.0) st |= kEvInvalid;
   if (tidal && (p[11] < 0.0 || p[12] < 0.0)) st |= kEvInvalid;
   if (n < 2 || !(fmin > 0.0) || !(fmax > fmin)) st |= kEvInvalid;
+  if (ecc && (!(p[13] >= 0.0) || !(p[13] < 1.0) || p[14] < 0.0)) st |= kEvInvalid;
   return st;
 }
 
@@ -325,12 +334,15 @@ __host__ __device__ inline void event_setup(const double* p, double fmin, double
                                             uint32_t flags, EventC& ec) {
   const bool tidal = (flags & kFlagTidal) != 0;
   const bool rot = (flags & kFlagRot) != 0;
+  const bool ecc = (flags & kFlagEcc) != 0;
   const double Mc = p[0], eta = p[1], dL = p[2];
   const double Ms = Mc * pow(eta, -0.6) * kTsun;
   if (!(fmax > 0.0)) fmax = cut_frequency_of(Ms);
   ec.n = n;
   ec.fx = nullptr;
-  ec.status = check_event(p, tidal, fmin, fmax, n);
+  ec.ecc = 0;
+  ec.ecc_lnvr = ec.ecc_psi = ec.ecc_mc = ec.ecc_e0 = ec.ecc_cyc = 0.0;
+  ec.status = check_event(p, tidal, fmin, fmax, n, ecc);
   if (ec.status) return;
   // grid
   const double D = log(fmax / fmin) / (double)(n - 1);
@@ -356,6 +368,23 @@ __host__ __device__ inline void event_setup(const double* p, double fmin, double
   ec.ccross = ci;
   ec.dcplus = -ci * si;
   ec.dcross = -si;
+
+  // ---- moderate eccentricity (sec. 2.2, is_eccentric): the leading-order
+  // correction -(2355/1462) e0^2 (v_ref/v)^{19/3} relative to the Newtonian
+  // phase 3/(128 eta v^5) (the model the paper cites, Moore et al. 2016),
+  // e0 given where the GW frequency is f_ref (the grid's first frequency
+  // unless given, sec. 2.1).  At fixed f and f_ref it is proportional to
+  // eta^-1 v^-5, i.e. to Mc^{-5/3} alone.
+  if (ecc) {
+    const double e0 = p[13], fref = p[14] > 0.0 ? p[14] : fmin;
+    const double K = (3.0 / (128.0 * eta)) * (-2355.0 / 1462.0);
+    ec.ecc = 1;
+    ec.ecc_lnvr = (ec.lnpiM + log(fref)) / 3.0;
+    ec.ecc_psi = K * e0 * e0;
+    ec.ecc_mc = -5.0 / (3.0 * Mc) * ec.ecc_psi;
+    ec.ecc_e0 = 2.0 * K * e0;
+    ec.ecc_cyc = ec.ecc_psi / kTwoPi;
+  }
 
   // ---- phase-derivative series
   PNCoef c;
@@ -685,6 +714,17 @@ struct Point {
   double gMc, gEta;               // d(sidereal angle)/dMc, /deta
   double pMc, pEta;               // dPsi_PN/dMc, /deta
   double vpsd;                    // v^-12.42: the PSD's power law, shared by all sites
+  double ecv;                     // v^-5 (v_ref/v)^{19/3} (eccentric forms, else 0)
+};
+
+// Number of phase-only Fisher parameters (Phic, chi1z, chi2z, then Lambda1,
+// Lambda2 with tides, then e0 with eccentricity) and what it implies.
+template <int NPI>
+struct PhaseOnly {
+  static_assert(NPI >= 3 && NPI <= 6, "3 to 6 phase-only parameters");
+  static constexpr bool tidal = NPI >= 5;
+  static constexpr bool ecc = (NPI & 1) == 0;
+  static constexpr int P = 8 + NPI;
 };
 
 // How point_setup forms the PSD's power law v^-12.42 shared by all sites:
@@ -694,7 +734,7 @@ enum PsdPow { kPsdNone = 0, kPsdF64 = 1, kPsdF32 = 2 };
 // PSUM: the evaluation form of the PN series (see horner7) and of the PSD's
 // power law (once per point when true, once per site otherwise).
 // EXPL: the point of an explicit grid (ec.fx) rather than of the log grid.
-template <bool PSUM = true, bool EXPL = false>
+template <bool PSUM = true, bool EXPL = false, bool ECC = false>
 __host__ __device__ inline void point_setup(const EventC& ec, int32_t k, bool need_derivs, bool rot,
                                             Point& q, int psd = kPsdF64) {
   double L, v, f, wf;               // wf: the trapezoid weight
@@ -734,13 +774,18 @@ __host__ __device__ inline void point_setup(const EventC& ec, int32_t k, bool ne
     q.pMc = eval_phase<PSUM>(ec.ps[kPsMc], pw, iv5);
     q.pEta = eval_phase<PSUM>(ec.ps[kPsEta], pw, iv5);
   }
+  q.ecv = 0.0;
+  if (ECC) {
+    q.ecv = iv5 * exp((19.0 / 3.0) * (ec.ecc_lnvr - L));
+    if (need_derivs) q.pMc = fma(ec.ecc_mc, q.ecv, q.pMc);
+  }
 }
 
 // The phase-only derivative coefficients of a point: c = (-1, dPsi/dchi1,
-// dPsi/dchi2[, dPsi/dLambda1, dPsi/dLambda2]).
-template <bool TIDAL, bool PSUM = true>
+// dPsi/dchi2[, dPsi/dLambda1, dPsi/dLambda2][, dPsi/de0]).
+template <int NPI, bool PSUM = true>
 __host__ __device__ inline void phase_only_coefficients(const EventC& ec, const Point& q, double* c) {
-  constexpr int NPI = TIDAL ? 5 : 3;
+  using PO = PhaseOnly<NPI>;
   const double iv = q.iv, iv2 = iv * iv, iv5 = iv2 * iv2 * iv;
   VPow pw;
   vpow(q.v, q.L, pw);
@@ -748,18 +793,19 @@ __host__ __device__ inline void phase_only_coefficients(const EventC& ec, const 
   if (PSUM) {      // the spin and deformability series' structural zeros skipped
     c[1] = eval_phase_spin<true>(ec.ps[kPsChi1], pw, iv5);
     c[2] = eval_phase_spin<true>(ec.ps[kPsChi2], pw, iv5);
-    if (TIDAL) {
-      c[NPI - 2] = eval_phase_tidal(ec.ps[kPsL1], pw);
-      c[NPI - 1] = eval_phase_tidal(ec.ps[kPsL2], pw);
+    if (PO::tidal) {
+      c[3] = eval_phase_tidal(ec.ps[kPsL1], pw);
+      c[4] = eval_phase_tidal(ec.ps[kPsL2], pw);
     }
   } else {         // the general form (fewer live values)
     c[1] = eval_phase<false>(ec.ps[kPsChi1], pw, iv5);
     c[2] = eval_phase<false>(ec.ps[kPsChi2], pw, iv5);
-    if (TIDAL) {
-      c[NPI - 2] = eval_phase<false>(ec.ps[kPsL1], pw, iv5);
-      c[NPI - 1] = eval_phase<false>(ec.ps[kPsL2], pw, iv5);
+    if (PO::tidal) {
+      c[3] = eval_phase<false>(ec.ps[kPsL1], pw, iv5);
+      c[4] = eval_phase<false>(ec.ps[kPsL2], pw, iv5);
     }
   }
+  if (PO::ecc) c[NPI - 1] = ec.ecc_e0 * q.ecv;
 }
 
 // Site-level quantities at one frequency: the P vectors and their hour-angle
@@ -946,7 +992,7 @@ constexpr int kGramRows[5] = {0, 1, 3, 4, 7};   // Mc, eta, theta, phi, tc
 // and returns the point's phase-only quantities:
 //   U[8]   U_b = sum_i w_i Re(i Q_i D_b,i^*)
 //   W      sum_i w_i |Q_i|^2 (the SNR^2 density)
-//   c[NPI] (-1, dPsi/dchi1, dPsi/dchi2[, dPsi/dLambda1, dPsi/dLambda2]).
+//   c[NPI] (-1, dPsi/dchi1, dPsi/dchi2[, dPsi/dLambda1, dPsi/dLambda2][, dPsi/de0]).
 // The phase-only derivative vectors are i Q c(f) with the same real c(f) at
 // every interferometer, so the blocks they span are
 //   Gamma_{b, 8+i} += U_b c_i,   Gamma_{8+i, 8+j} += W c_i c_j,
@@ -954,13 +1000,13 @@ constexpr int kGramRows[5] = {0, 1, 3, 4, 7};   // Mc, eta, theta, phi, tc
 // dL, iota, psi follow from the point's moments S as well: U_dL = 0
 // exactly, U_iota = (c+ dcx - cx dc+) S_+x, U_psi = -2 c+ cx (S_++ + S_xx),
 // W = c+^2 S_++ + cx^2 S_xx.
-template <bool TIDAL, bool ROT, bool MIXED = false, bool PSUM = true, bool EXPL = false>
+template <int NPI, bool ROT, bool MIXED = false, bool PSUM = true, bool EXPL = false>
 __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* sc, int n_site,
                                                  int32_t k, double* G, double* U, double& W,
                                                  double* cph) {
   const AmpFactors am = amp_factors(ec);
   Point q;
-  point_setup<PSUM, EXPL>(ec, k, true, ROT, q, MIXED ? kPsdF32 : kPsdF64);
+  point_setup<PSUM, EXPL, PhaseOnly<NPI>::ecc>(ec, k, true, ROT, q, MIXED ? kPsdF32 : kPsdF64);
   double UR[5], spp = 0.0, spx = 0.0, sxx = 0.0;
 #pragma unroll
   for (int b = 0; b < 5; ++b) UR[b] = 0.0;
@@ -1013,7 +1059,7 @@ __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* 
   U[5] = (am.cplus * am.dcx - am.ccross * am.dcp) * spx;
   U[6] = -2.0 * am.cplus * am.ccross * (spp + sxx);
   W = fma(am.cplus * am.cplus, spp, am.ccross * am.ccross * sxx);
-  phase_only_coefficients<TIDAL, PSUM>(ec, q, cph);
+  phase_only_coefficients<NPI, PSUM>(ec, q, cph);
 }
 
 // The 8x8 upper-triangle block of (Mc, eta, dL, theta, phi, iota, psi, tc)

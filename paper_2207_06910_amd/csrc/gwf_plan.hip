@@ -24,7 +24,7 @@ struct gwf_plan {
   NetDesc net{};
   uint32_t flags = 0;
   int64_t n = 0;
-  int P = 0, nacc = 0, n_cu = 0;
+  int P = 0, npi = 3, nacc = 0, n_cu = 0;
   bool tidal = false, rot = false, mixed = false;
   std::vector<int32_t> npts_host;
   // tuning
@@ -118,6 +118,7 @@ gwf_status enqueue(gwf_plan* p, const Outs& o, hipStream_t s) {
   sa.par = p->ev.par; sa.ld = p->ev.ld; sa.n = p->n;
   sa.fmin = p->grid.fmin; sa.fmax = p->grid.fmax; sa.npts = p->grid.npts; sa.npts_plan = p->npts_plan;
   sa.npts_max = 0x7fffffff;
+  sa.ecc = p->ev.ecc; sa.fref = p->ev.f_ref_ecc;
   sa.net = p->net; sa.flags = p->flags; sa.evc = p->evc; sa.sic = p->sic; sa.status = o.status;
   sa.active = p->ev.active;
   hipError_t err = launch_setup(sa, s);
@@ -129,14 +130,14 @@ gwf_status enqueue(gwf_plan* p, const Outs& o, hipStream_t s) {
     const int n_wg = std::max(1, std::min(p->n_items, p->n_cu * p->wg_per_cu));
     const bool timed = p->profile && p->ev0;
     if (timed) (void)hipEventRecord(p->ev0, s);
-    err = launch_items(ia, p->tidal, p->rot, p->mixed, n_wg, s);
+    err = launch_items(ia, p->npi, p->rot, p->mixed, n_wg, s);
     if (timed) (void)hipEventRecord(p->ev1, s);
   }
   if (err == hipSuccess) {
     CombineArgs ca{};
     ca.n = p->n; ca.evc = p->evc; ca.item_first = p->item_first; ca.partial = p->partial;
     ca.fisher = o.fisher; ca.snr = o.snr; ca.status = o.status; ca.par_mask = p->ev.par_mask;
-    err = launch_combine(ca, p->tidal, s);
+    err = launch_combine(ca, p->npi, s);
   }
   if (err == hipSuccess && o.sigma) {
     InvertArgs ia{};
@@ -208,8 +209,9 @@ gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const g
   p->tidal = (flags & GWF_TIDAL) != 0;
   p->rot = (flags & GWF_EARTH_ROT) != 0;
   p->mixed = (flags & GWF_MIXED) != 0;
-  p->P = p->tidal ? 13 : 11;
-  p->nacc = fisher_nacc(p->tidal);
+  p->npi = api_npi(flags);
+  p->P = 8 + p->npi;
+  p->nacc = fisher_nacc(p->npi);
   p->use_graph = o.use_graph != 0;
   p->inv_method = o.inv_method;
   if (o.profile && p->use_graph) {
@@ -251,7 +253,7 @@ gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const g
   if (o.wg_per_cu) {
     wgs.push_back(o.wg_per_cu);
   } else {
-    const int res = items_max_resident(p->tidal, p->rot, p->mixed);
+    const int res = items_max_resident(p->npi, p->rot, p->mixed);
     for (int w = 1; w <= 4; ++w)
       if (w <= std::max(1, res)) wgs.push_back(w);
     if (wgs.size() > 2) wgs.erase(wgs.begin(), wgs.end() - 2);   // the two largest

@@ -70,8 +70,9 @@ gwf_status gwf_fisher_static(const gwf_events* ev, const gwf_network* net, const
   if (npts_max < 2 || npts_max > (1 << 30)) return api_fail(GWF_E_INVALID_ARG, "npts_max=%d outside 2..2^30", npts_max);
   NetDesc nd;
   if ((st = api_pack_network(net, nd))) return st;
-  const bool tidal = (flags & GWF_TIDAL) != 0, rot = (flags & GWF_EARTH_ROT) != 0, mixed = (flags & GWF_MIXED) != 0;
-  const int nacc = fisher_nacc(tidal);
+  const bool rot = (flags & GWF_EARTH_ROT) != 0, mixed = (flags & GWF_MIXED) != 0;
+  const int npi = api_npi(flags);
+  const int nacc = fisher_nacc(npi);
   // workspace layout, each part 256-byte aligned
   const int64_t n = ev->n;
   const int64_t per_event = (npts_max - 1) / chunk + 1;
@@ -104,7 +105,7 @@ gwf_status gwf_fisher_static(const gwf_events* ev, const gwf_network* net, const
   int n_cu = 0;
   if ((err = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return api_hip_fail(err, "compute-unit count");
-  const int wg = std::max(1, items_max_resident(tidal, rot, mixed));
+  const int wg = std::max(1, items_max_resident(npi, rot, mixed));
   const int n_wg = (int)std::max<int64_t>(1, std::min<int64_t>(items_max, (int64_t)n_cu * wg));
   hipStream_t s = (hipStream_t)stream;
   // items from the grid lengths; the counter starts at zero (a fill kernel)
@@ -115,6 +116,7 @@ gwf_status gwf_fisher_static(const gwf_events* ev, const gwf_network* net, const
     sa.par = ev->par; sa.ld = ev->ld; sa.n = n;
     sa.fmin = grid->fmin; sa.fmax = grid->fmax; sa.npts = grid->npts; sa.npts_plan = grid->npts;
     sa.npts_max = npts_max;
+    sa.ecc = ev->ecc; sa.fref = ev->f_ref_ecc;
     sa.net = nd; sa.flags = flags; sa.evc = evc; sa.sic = sic; sa.status = status;
     sa.active = ev->active;
     err = launch_setup(sa, s);
@@ -123,13 +125,13 @@ gwf_status gwf_fisher_static(const gwf_events* ev, const gwf_network* net, const
     ItemsArgs ia{};
     ia.evc = evc; ia.sic = sic; ia.n_site = nd.n_site; ia.items = items;
     ia.n_items = 0; ia.n_items_dev = n_items; ia.counter = counter; ia.partial = partial;
-    err = launch_items(ia, tidal, rot, mixed, n_wg, s);
+    err = launch_items(ia, npi, rot, mixed, n_wg, s);
   }
   if (err == hipSuccess) {
     CombineArgs ca{};
     ca.n = n; ca.evc = evc; ca.item_first = first; ca.partial = partial;
     ca.fisher = fisher; ca.snr = snr; ca.status = status; ca.par_mask = ev->par_mask;
-    err = launch_combine(ca, tidal, s);
+    err = launch_combine(ca, npi, s);
   }
   if (err != hipSuccess) return api_hip_fail(err, "gwf_fisher_static launch");
   return GWF_OK;

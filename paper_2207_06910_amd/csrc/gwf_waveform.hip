@@ -31,6 +31,14 @@ struct WaveSite {
   int32_t n_arm, pad;
 };
 
+// Event e's inputs: the 13 parameters (no tidal rows without tides), e0 and
+// its reference frequency (with the eccentric flag, else zero).
+__device__ inline void load_event(const WaveformArgs& a, int64_t e, bool tidal, double* p) {
+  for (int r = 0; r < 13; ++r) p[r] = (r < 11 || tidal) ? a.par[r * a.ld + e] : 0.0;
+  p[13] = a.ecc_flag && a.ecc ? a.ecc[e] : 0.0;
+  p[14] = a.ecc_flag && a.fref ? a.fref[e] : 0.0;
+}
+
 // x reduced to [-1/2, 1/2] by subtracting the nearest integer (exact).
 __device__ inline double frac_center(double x) { return x - rint(x); }
 
@@ -79,9 +87,9 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
   const int tid = threadIdx.x;
   const int n_site = a.net.n_site;
   if (tid == 0) {
-    double p[13];
-    for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
-    event_setup_grid(p, a.fmin, a.fmax, a.npts, a.goff, a.gf, e, flags, ec);
+    double p[kNparIn];
+    load_event(a, e, TIDAL, p);
+    event_setup_grid(p, a.fmin, a.fmax, a.npts, a.goff, a.gf, e, flags | a.ecc_flag, ec);
     // the event's columns [b, b + npts) must lie inside a row of h
     const int64_t b = a.offsets[e];
     const bool range_ok = b >= 0 && b <= a.total - (int64_t)a.npts[e];
@@ -93,8 +101,8 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
   __syncthreads();
   if (!ok) return;
   if (tid < n_site) {
-    double p[13];
-    for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
+    double p[kNparIn];
+    load_event(a, e, TIDAL, p);
     SiteC sc;
     site_setup(p, a.net.site[tid], ec, sc);
     WaveSite& w = ws[tid];
@@ -145,7 +153,9 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
     // modulo one.  f tc - n with n the integer nearest to the rounded product
     // is formed by one fused multiply-add from the exact product, so the
     // reduced fraction carries a single rounding however large f tc is.
-    const double pn = frac_center(eval_phase(ec.cyc, pw, iv5));
+    double pnc = eval_phase(ec.cyc, pw, iv5);
+    if (ec.ecc) pnc = fma(ec.ecc_cyc, iv5 * exp((19.0 / 3.0) * (ec.ecc_lnvr - L)), pnc);
+    const double pn = frac_center(pnc);
     const double ftr = fma(f, tc, -rint(f * tc));
     const double cyc = frac_center(pn + ftr + ec.cyc0);
     double2* o = out + k;
@@ -183,15 +193,17 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
 //   d_a h_i = A exp(2 pi i cyc_i) D_a,i,
 // D the phase-free derivative vector of the Fisher kernels for (Mc, eta, dL,
 // theta, phi, iota, psi, tc) and i Q c_a for the phase-only parameters
-// (Phic, chi1z, chi2z[, Lambda1, Lambda2]); the phase in cycles exactly as
+// (Phic, chi1z, chi2z[, Lambda1, Lambda2][, e0]); the phase in cycles exactly as
 // for the strain.  Each arm of a triangle is projected with its own pattern
 // map.  One workgroup per event, lanes over grid points; row (a, i) of dh
 // holds parameter a at interferometer i, consecutive lanes on consecutive
 // complex values.  FP64 only.
-template <bool ROT, bool TIDAL, bool EXPL>
+template <bool ROT, int NPI, bool EXPL>
 __global__ __launch_bounds__(kWBlock) void waveform_deriv_kernel(WaveformArgs a) {
-  constexpr int P = TIDAL ? 13 : 11, NPI = TIDAL ? 5 : 3;
-  constexpr uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u);
+  using PO = PhaseOnly<NPI>;
+  constexpr int P = PO::P;
+  constexpr bool TIDAL = PO::tidal;
+  constexpr uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u) | (PO::ecc ? kFlagEcc : 0u);
   __shared__ EventC ec;
   __shared__ SiteC sc[kMaxSites];
   __shared__ int32_t ok;
@@ -199,8 +211,8 @@ __global__ __launch_bounds__(kWBlock) void waveform_deriv_kernel(WaveformArgs a)
   const int tid = threadIdx.x;
   const int n_site = a.net.n_site;
   if (tid == 0) {
-    double p[13];
-    for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
+    double p[kNparIn];
+    load_event(a, e, TIDAL, p);
     event_setup_grid(p, a.fmin, a.fmax, a.npts, a.goff, a.gf, e, flags, ec);
     const int64_t b = a.offsets[e];
     const bool range_ok = b >= 0 && b <= a.total - (int64_t)a.npts[e];
@@ -212,8 +224,8 @@ __global__ __launch_bounds__(kWBlock) void waveform_deriv_kernel(WaveformArgs a)
   __syncthreads();
   if (!ok) return;
   if (tid < n_site) {
-    double p[13];
-    for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
+    double p[kNparIn];
+    load_event(a, e, TIDAL, p);
     site_setup(p, a.net.site[tid], ec, sc[tid]);
   }
   __syncthreads();
@@ -230,16 +242,18 @@ __global__ __launch_bounds__(kWBlock) void waveform_deriv_kernel(WaveformArgs a)
     // reads) rather than held in registers across iterations
     asm volatile("" ::: "memory");
     Point q;
-    point_setup<true, EXPL>(ec, k, true, ROT, q, kPsdNone);
+    point_setup<true, EXPL, PO::ecc>(ec, k, true, ROT, q, kPsdNone);
     VPow pw;
     vpow(q.v, q.L, pw);
     const double iv = q.iv, iv2 = iv * iv, iv5 = iv2 * iv2 * iv;
     const double amp = amp0 * iv2 * iv * sqrt(iv);
-    const double pn = frac_center(eval_phase(ec.cyc, pw, iv5));
+    double pnc = eval_phase(ec.cyc, pw, iv5);
+    if (PO::ecc) pnc = fma(ec.ecc_cyc, q.ecv, pnc);
+    const double pn = frac_center(pnc);
     const double ftr = fma(q.f, tc, -rint(q.f * tc));
     const double cyc = frac_center(pn + ftr + ec.cyc0);
     double cph[NPI];
-    phase_only_coefficients<TIDAL>(ec, q, cph);
+    phase_only_coefficients<NPI>(ec, q, cph);
     double2* o = out + k;
     for (int s = 0; s < n_site; ++s) {
       asm volatile("" ::: "memory");
@@ -298,18 +312,26 @@ hipError_t launch_waveform(const WaveformArgs& a, bool tidal, bool rot, bool mix
   return hipGetLastError();
 }
 
-template <bool EXPL>
-void launch_deriv_t(const WaveformArgs& a, bool tidal, bool rot, dim3 grid, dim3 block, hipStream_t stream) {
-  if (tidal && rot) hipLaunchKernelGGL((waveform_deriv_kernel<true, true, EXPL>), grid, block, 0, stream, a);
-  else if (tidal) hipLaunchKernelGGL((waveform_deriv_kernel<false, true, EXPL>), grid, block, 0, stream, a);
-  else if (rot) hipLaunchKernelGGL((waveform_deriv_kernel<true, false, EXPL>), grid, block, 0, stream, a);
-  else hipLaunchKernelGGL((waveform_deriv_kernel<false, false, EXPL>), grid, block, 0, stream, a);
+template <int NPI, bool EXPL>
+void launch_deriv_n(const WaveformArgs& a, bool rot, dim3 grid, dim3 block, hipStream_t stream) {
+  if (rot) hipLaunchKernelGGL((waveform_deriv_kernel<true, NPI, EXPL>), grid, block, 0, stream, a);
+  else hipLaunchKernelGGL((waveform_deriv_kernel<false, NPI, EXPL>), grid, block, 0, stream, a);
 }
 
-hipError_t launch_waveform_deriv(const WaveformArgs& a, bool tidal, bool rot, hipStream_t stream) {
+template <bool EXPL>
+void launch_deriv_t(const WaveformArgs& a, int npi, bool rot, dim3 grid, dim3 block, hipStream_t stream) {
+  switch (npi) {
+    case 6: launch_deriv_n<6, EXPL>(a, rot, grid, block, stream); break;
+    case 5: launch_deriv_n<5, EXPL>(a, rot, grid, block, stream); break;
+    case 4: launch_deriv_n<4, EXPL>(a, rot, grid, block, stream); break;
+    default: launch_deriv_n<3, EXPL>(a, rot, grid, block, stream);
+  }
+}
+
+hipError_t launch_waveform_deriv(const WaveformArgs& a, int npi, bool rot, hipStream_t stream) {
   dim3 grid((unsigned)a.n), block(kWBlock);
-  if (a.gf) launch_deriv_t<true>(a, tidal, rot, grid, block, stream);
-  else launch_deriv_t<false>(a, tidal, rot, grid, block, stream);
+  if (a.gf) launch_deriv_t<true>(a, npi, rot, grid, block, stream);
+  else launch_deriv_t<false>(a, npi, rot, grid, block, stream);
   return hipGetLastError();
 }
 

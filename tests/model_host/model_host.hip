@@ -15,6 +15,7 @@ template <bool TIDAL, bool ROT, bool MIXED>
 static void one_event(const double* p, double fmin, double fmax, int32_t n, const NetDesc& nd,
                       double* F, double* snr, int32_t* status) {
   constexpr int P = TIDAL ? 13 : 11, NPI = P - 8, NACC = 36 + 8 * NPI + NPI * (NPI + 1) / 2;
+  static_assert(NPI == 3 || NPI == 5, "the host build covers the non-eccentric forms");
   const uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u);
   EventC ec;
   event_setup(p, fmin, fmax, n, flags, ec);
@@ -25,7 +26,7 @@ static void one_event(const double* p, double fmin, double fmax, int32_t n, cons
   double Gacc[kGramAcc] = {0}, G[36], xy[64] = {0};
   for (int32_t k = 0; k < ec.n; ++k) {
     double U[8], W, c[5];
-    accumulate_point<TIDAL, ROT, MIXED>(ec, sc, nd.n_site, k, Gacc, U, W, c);
+    accumulate_point<NPI, ROT, MIXED>(ec, sc, nd.n_site, k, Gacc, U, W, c);
     add_phase_blocks(NPI, U, W, c, xy, 1);
   }
   gram_finish(ec, Gacc, G);
@@ -53,7 +54,7 @@ extern "C" int model_fisher_host(int64_t n, const double* par, int64_t ld, const
   const int P = tidal ? 13 : 11;
   std::vector<double> F(P * P);
   for (int64_t e = 0; e < n; ++e) {
-    double p[13];
+    double p[kNparIn] = {};
     for (int r = 0; r < 13; ++r) p[r] = par[r * ld + e];
     const double fx = fmax ? fmax[e] : 0.0;
     if (flags & kFlagMixed) {
@@ -88,7 +89,7 @@ static void one_event_adjoint(const double* p, double fmin, double fmax, int32_t
   for (int s = 0; s < nd.n_site; ++s) {
     SiteA sa;
     site_setup_adj(p, nd.site[s], ec, sa);
-    for (int32_t k = 0; k < ec.n; ++k) adjoint_point<TIDAL, ROT>(ec, sa, Gb, k, acc[s]);
+    for (int32_t k = 0; k < ec.n; ++k) adjoint_point<TIDAL ? 5 : 3, ROT>(ec, sa, Gb, k, acc[s]);
   }
   double W = 0.0;
   for (int s = 0; s < nd.n_site; ++s) W += acc[s][kAdjW];
@@ -111,7 +112,7 @@ extern "C" int model_adjoint_host(int64_t n, const double* par, int64_t ld, cons
   const int P = tidal ? 13 : 11;
   std::vector<double> G(P * P);
   for (int64_t e = 0; e < n; ++e) {
-    double p[13];
+    double p[kNparIn] = {};
     for (int r = 0; r < 13; ++r) p[r] = par[r * ld + e];
     for (int i = 0; i < P; ++i)
       for (int j = 0; j < P; ++j)

@@ -104,6 +104,9 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.gwf_fisher_static(B(big), B(net), B(grid), 0, 4096, 20000, 8, 8, 8, None) == 1
     assert b"workspace" in lib.gwf_last_error()
     assert lib.gwf_fisher_static(B(ev), B(net), B(gx), 0, 4096, 100, 8, 8, 8, None) == 2
+    # eccentricity needs the e0 array
+    assert lib.gwf_snr(B(ev), B(net), B(grid), binding.ECCENTRIC, 8, None, None, None) == 1
+    assert b"ecc" in lib.gwf_last_error()
     # an unknown noise-curve kind
     s = synth.site("H1")
     n3, k3 = binding.network([s])
@@ -158,14 +161,16 @@ def test_covariance_options_rejected_on_host():
 
 
 def test_basis_arguments_rejected_on_host():
-    """gwf_fisher_basis: P other than 11/13, the tidal basis without tides,
-    unknown basis bits, a descriptor for another number of events, missing
-    output."""
+    """gwf_fisher_basis: P outside 11-14, the tidal basis without tides (P =
+    11, or 12: no tides and e0), unknown basis bits, a descriptor for another
+    number of events, missing output."""
     lib = binding.load()
     B = ctypes.byref
     ev = binding.Events(3, 3, 8, None)
-    assert lib.gwf_fisher_basis(12, 3, 8, B(ev), 1, 8, None, None) == 1
+    assert lib.gwf_fisher_basis(10, 3, 8, B(ev), 1, 8, None, None) == 1
+    assert lib.gwf_fisher_basis(15, 3, 8, B(ev), 1, 8, None, None) == 1
     assert lib.gwf_fisher_basis(11, 3, 8, B(ev), 2, 8, None, None) == 1
+    assert lib.gwf_fisher_basis(12, 3, 8, B(ev), 2, 8, None, None) == 1
     assert lib.gwf_fisher_basis(13, 3, 8, B(ev), 8, 8, None, None) == 1
     assert lib.gwf_fisher_basis(13, 4, 8, B(ev), 1, 8, None, None) == 1
     assert lib.gwf_fisher_basis(13, 3, 8, B(ev), 1, None, None, None) == 1

@@ -31,12 +31,9 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # profiles/bns1e4_hbm_counters.md (calibrated against a 256 MiB copy: fetch
 # x 2.000, write x 1.000).  Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
-    "items_kernel<tidal,rot,mixed>": 58.09e6,
-    "items_kernel<tidal,rot>": 60.20e6,
-    "fisher_kernel<tidal,rot>": 133.79e6,
-    "waveform_kernel<rot,tidal>": 7851.66e6,
-    "waveform_kernel<rot,tidal,mixed>": 7876.10e6,
-    "waveform_deriv_kernel<rot,tidal>": 10306.44e6,
+    "waveform_kernel<rot,tidal>": None,
+    "waveform_kernel<rot,tidal,mixed>": None,
+    "waveform_deriv_kernel<rot,tidal>": None,
 }
 
 # VALU instructions (wavefront instructions, SQ_INSTS_VALU) per launch of the
@@ -45,11 +42,7 @@ MEASURED_TRAFFIC = {
 # occupies its SIMD for 4 cycles, so the VALU busy fraction is
 # 4 x SQ_INSTS_VALU / (1024 SIMDs x 2.4 GHz x kernel time).  Set an entry to
 # None when its kernel changes.
-MEASURED_VALU_INSTS = {
-    "items_kernel<tidal,rot,mixed>": 1.635e9,
-    "items_kernel<tidal,rot>": 1.666e9,
-    "fisher_kernel<tidal,rot>": 1.696e9,
-}
+MEASURED_VALU_INSTS = {}
 N_SIMD, CLOCK_HZ = 1024, 2.4e9
 
 
@@ -225,38 +218,58 @@ def gradient_form(binding, synth, torch, args, timed) -> dict:
     """Forward (Fisher + inversion with ln det) and backward (adjoint) of
     J = sum ln SNR + sum ln det Gamma over the 10^4-event mixed BBH/BNS
     workload on five L sites, gradient along the 20 site parameters; each
-    event's Fisher matrix has its kind's parameters (11 for BBH, 13 for BNS)."""
+    event's Fisher matrix has its kind's parameters (11 for BBH, 13 for BNS).
+    Timed through a plan (the batched forward and backward over work items)
+    and, for the backward alone, also with the one-workgroup-per-event
+    adjoint."""
     from paper_2207_06910_amd import autodiff
     wl = synth.mixed1e4()
     dw = binding.DeviceWorkload(wl)
     xi = autodiff.site_parameters(dw)
+    plan = binding.Plan(dw)                      # FP64, autotuned
 
     def step():
         x = xi.clone().requires_grad_(True)
-        J = autodiff.network_fom(x, dw)
+        J = autodiff.network_fom(x, dw, plan=plan)
         J.backward()
         return x.grad
 
     for i in range(2):
         step()
     ms = timed(step, max(3, args.steps // 4))
-    r = binding.fisher(dw)
+    plan.set_sites(dw.sites)
+    r = plan.run()
     inv = binding.invert(r["fisher"], r["status"], par_mask=dw.par_mask)
+    stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    tb = []
-    for i in range(max(3, args.steps // 4)):
-        ev[0].record()
-        binding.fisher_adjoint(dw, inv["cov"], status=inv["status"])
-        ev[1].record()
-        ev[1].synchronize()
-        tb.append(ev[0].elapsed_time(ev[1]))
-    bwd = float(np.mean(tb))
-    log(f"gradient (mixed1e4): {ms:.3f} ms per forward+backward, adjoint kernels {bwd:.3f} ms")
+
+    def kernel_ms(fn):
+        fn()
+        t = []
+        for i in range(max(3, args.steps // 4)):
+            ev[0].record(stream)
+            fn()
+            ev[1].record(stream)
+            ev[1].synchronize()
+            t.append(ev[0].elapsed_time(ev[1]))
+        return float(np.mean(t))
+    fwd = kernel_ms(lambda: plan.run())
+    bwd = kernel_ms(lambda: plan.adjoint(inv["cov"], status=inv["status"]))
+    bwd_plain = kernel_ms(lambda: binding.fisher_adjoint(dw, inv["cov"], status=inv["status"]))
+    info = plan.info()
+    plan.close()
+    log(f"gradient (mixed1e4): {ms:.3f} ms per forward+backward through a plan; plan Fisher {fwd:.3f} ms, "
+        f"plan adjoint {bwd:.3f} ms ({bwd / fwd:.2f}x the forward), one-workgroup-per-event adjoint "
+        f"{bwd_plain:.3f} ms")
     return {"gradient_mixed1e4": {"workload": "mixed1e4: 10^4 events (60% BBH, 40% BNS), five L "
                                               "sites, 11 (BBH) / 13 (BNS) parameters, d/d(lat, lon, gamma, ln S0)",
                                   "grid_points": int(wl.npts.sum()),
                                   "ms_per_forward_backward": round(ms, 4),
+                                  "plan_fisher_ms": round(fwd, 4),
                                   "adjoint_ms": round(bwd, 4),
+                                  "adjoint_over_forward": round(bwd / fwd, 3),
+                                  "adjoint_per_event_ms": round(bwd_plain, 4),
+                                  "chunk": info["chunk"], "wg_per_cu": info["wg_per_cu"],
                                   "events_per_s": round(wl.n / (ms * 1e-3), 1)}}
 
 

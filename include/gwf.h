@@ -516,6 +516,30 @@ gwf_status gwf_plan_fisher(gwf_plan* plan, double* fisher, double* snr, int32_t*
                            double cond_max, double* cov, double* sigma, double* cond,
                            double* inv_err, void* stream);
 
+/* The adjoint of gwf_fisher_adjoint over the plan's work items: the same
+ * gradient (sec. 3.3 derivatives, reverse mode; the detector gradient is the
+ * batched form of the adjoint) along every site's (latitude, longitude,
+ * gamma, ln S0) of
+ *   J = sum_e [ w_snr ln SNR_e + w_fisher sum_ij Gbar_e,ij Gamma_e,ij ],
+ * for the plan's events, grids and current network (gwf_plan_set_network),
+ * one workgroup per work item (longest first), each item's per-site sums
+ * combined per event in item order and the events summed in a fixed order
+ * (bitwise reproducible).  gbar, status, grad_event and grad as for
+ * gwf_fisher_adjoint (grad_event [n][n_site][4], grad [n_site][4]).  Plans
+ * created with GWF_MIXED return GWF_E_UNSUPPORTED.  The adjoint shares the
+ * plan's workspace with gwf_plan_fisher: calls on one plan must be ordered
+ * (one stream, or synchronised). */
+gwf_status gwf_plan_adjoint(gwf_plan* plan, const double* gbar, const int32_t* status, double w_snr,
+                            double w_fisher, double* grad_event, double* grad, void* stream);
+
+/* Replace the plan's network (any valid network of at most as many sites as
+ * the plan was created with; grid lengths and items do not depend on it):
+ * the detector positions, orientations and
+ * noise curves of the next gwf_plan_fisher and gwf_plan_adjoint calls, e.g.
+ * for gradient steps on the detector parameters.  A captured graph is
+ * rebuilt at the next gwf_plan_fisher. */
+gwf_status gwf_plan_set_network(gwf_plan* plan, const gwf_network* net);
+
 gwf_status gwf_plan_get_info(const gwf_plan* plan, gwf_plan_info* info);
 
 /* Frees the plan and its workspace (NULL is allowed). */

@@ -10,9 +10,9 @@ tr(Gamma^-1 dGamma), a sum whose terms cancel by up to the condition number;
 in FP64 it keeps about 1e-16 kappa relative accuracy per event, so events
 with larger kappa would add noise rather than signal.  An event's own
 parameter set (the workload's par_mask) further restricts A for that event.
-The forward pass runs gwf_fisher and gwf_covariance (which returns
-ln det Gamma and Gamma^-1); the
-backward pass runs the hand-written adjoint gwf_fisher_adjoint with
+The forward pass runs gwf_fisher (or a plan's gwf_plan_fisher) and
+gwf_covariance (which returns ln det Gamma and Gamma^-1); the backward pass
+runs the hand-written adjoint gwf_fisher_adjoint (or gwf_plan_adjoint) with
 Gbar = Gamma^-1 embedded in the full matrix, recomputing the strain
 derivatives at every grid point instead of storing them.  Every per-point
 and per-event step runs in the library's kernels; this module only moves
@@ -41,10 +41,14 @@ def site_parameters(dw):
                         dtype=torch.float64)
 
 
-def _forward(dw, xi, w_snr, w_logdet, rows, cond_max):
+def _forward(dw, xi, w_snr, w_logdet, rows, cond_max, plan=None):
     import torch
     dwx = dw.with_sites(_sites_at(dw.sites, xi))
-    r = binding.fisher(dwx)
+    if plan is not None:              # the batched form: the plan's work items, network replaced
+        plan.set_sites(dwx.sites)
+        r = plan.run()
+    else:
+        r = binding.fisher(dwx)
     F = r["fisher"]
     P = F.shape[0]
     # restriction to the rows A by fixing the others; each event's own
@@ -60,9 +64,9 @@ class NetworkFoM(__import__("torch").autograd.Function):
     """J(xi); see the module docstring.  Use network_fom()."""
 
     @staticmethod
-    def forward(ctx, xi, dw, w_snr, w_logdet, rows, cond_max):
+    def forward(ctx, xi, dw, w_snr, w_logdet, rows, cond_max, plan):
         import torch
-        dwx, r, inv, ok, J = _forward(dw, xi, w_snr, w_logdet, rows, cond_max)
+        dwx, r, inv, ok, J = _forward(dw, xi, w_snr, w_logdet, rows, cond_max, plan)
         P = r["fisher"].shape[0]
         gbar = inv["cov"]
         if len(inv["out"]) != P:
@@ -70,24 +74,30 @@ class NetworkFoM(__import__("torch").autograd.Function):
             idx = torch.as_tensor(list(inv["out"]), dtype=torch.long, device=gbar.device)
             full[idx.view(-1, 1), idx.view(1, -1)] = gbar
             gbar = full
-        ctx.dwx, ctx.gbar, ctx.status = dwx, gbar, inv["status"]
+        ctx.dwx, ctx.gbar, ctx.status, ctx.plan = dwx, gbar, inv["status"], plan
         ctx.w = (float(w_snr), float(w_logdet))
         ctx.xi_device, ctx.xi_dtype = xi.device, xi.dtype
         return J.to(device=xi.device, dtype=xi.dtype)
 
     @staticmethod
     def backward(ctx, gJ):
-        g = binding.fisher_adjoint(ctx.dwx, ctx.gbar, status=ctx.status, w_snr=ctx.w[0],
-                                   w_fisher=ctx.w[1])["grad"]
+        if ctx.plan is not None:
+            g = ctx.plan.adjoint(ctx.gbar, status=ctx.status, w_snr=ctx.w[0], w_fisher=ctx.w[1])["grad"]
+        else:
+            g = binding.fisher_adjoint(ctx.dwx, ctx.gbar, status=ctx.status, w_snr=ctx.w[0],
+                                       w_fisher=ctx.w[1])["grad"]
         g = g.to(device=ctx.xi_device, dtype=ctx.xi_dtype)
-        return gJ * g, None, None, None, None, None
+        return gJ * g, None, None, None, None, None, None
 
 
-def network_fom(xi, dw, w_snr=1.0, w_logdet=1.0, rows=None, cond_max=1e13):
+def network_fom(xi, dw, w_snr=1.0, w_logdet=1.0, rows=None, cond_max=1e13, plan=None):
     """J(xi) as a differentiable scalar (see the module docstring); rows
-    selects the Fisher rows whose ln det enters (None: all)."""
+    selects the Fisher rows whose ln det enters (None: all).  With a plan
+    (binding.Plan of the same workload, FP64) the forward and backward passes
+    run over its work items (gwf_plan_fisher, gwf_plan_adjoint), the plan's
+    network replaced by the sites at xi."""
     return NetworkFoM.apply(xi, dw, float(w_snr), float(w_logdet), None if rows is None else tuple(rows),
-                            float(cond_max))
+                            float(cond_max), plan)
 
 
 def network_fom_value(xi, dw, w_snr=1.0, w_logdet=1.0, rows=None, cond_max=1e13):

@@ -121,6 +121,10 @@ def load():
         lib.gwf_fisher_static.argtypes = [ctypes.POINTER(Events), ctypes.POINTER(Network),
                                           ctypes.POINTER(Grid), ctypes.c_uint32, i32, i32, vp, vp, vp, vp]
         lib.gwf_fisher_static.restype = i32
+        lib.gwf_plan_adjoint.argtypes = [vp, vp, vp, d, d, vp, vp, vp]
+        lib.gwf_plan_adjoint.restype = i32
+        lib.gwf_plan_set_network.argtypes = [vp, ctypes.POINTER(Network)]
+        lib.gwf_plan_set_network.restype = i32
         lib.gwf_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         lib.gwf_plan_get_info.restype = i32
         lib.gwf_plan_destroy.argtypes = [vp]
@@ -588,6 +592,30 @@ class Plan:
                                       _ptr(res["status"]), float(cond_max), _ptr(res.get("cov")),
                                       _ptr(res.get("sigma")), _ptr(res.get("cond")),
                                       _ptr(res.get("inv_err")), _stream(stream)), "gwf_plan_fisher")
+        return res
+
+    def set_sites(self, sites):
+        """Replace the plan's network (gwf_plan_set_network), e.g. for a step
+        in the detector parameters; sampled noise curves are uploaded."""
+        curves = upload_curves(sites, self.dw.par.device)
+        net, keep = network(sites, curves)
+        _check(load().gwf_plan_set_network(self.handle, ctypes.byref(net)), "gwf_plan_set_network")
+        self.sites, self._curves = list(sites), curves
+
+    def adjoint(self, gbar, status=None, w_snr=1.0, w_fisher=1.0, stream=None, out=None):
+        """gwf_plan_adjoint: grad [n_site][4] and grad_event [N][n_site][4] of
+        sum_e (w_snr ln SNR_e + w_fisher sum_ij gbar_ij Gamma_ij) along every
+        site's (latitude, longitude, gamma, ln S0), over the plan's work items."""
+        import torch
+        _dev_f64(gbar)
+        dev = self.dw.par.device
+        ns = len(getattr(self, "sites", self.dw.sites))
+        res = out if out is not None else {}
+        res.setdefault("grad_event", torch.empty((self.dw.n, ns, 4), dtype=torch.float64, device=dev))
+        res.setdefault("grad", torch.empty((ns, 4), dtype=torch.float64, device=dev))
+        _check(load().gwf_plan_adjoint(self.handle, _ptr(gbar), _ptr(status), float(w_snr), float(w_fisher),
+                                       _ptr(res["grad_event"]), _ptr(res["grad"]), _stream(stream)),
+               "gwf_plan_adjoint")
         return res
 
     def close(self):

@@ -12,78 +12,48 @@
 //   z = Gbar D,
 // so the backward pass recomputes D at every grid point, forms z, and
 // contracts it with the derivative of D along each detector parameter; no
-// Jacobian is stored.  The derivatives along latitude, longitude and gamma
-// are carried by the three-component tangent numbers T3 through the site's
-// geometry (patterns, hour angle, arrival-time offset); along ln S0 only the
-// weight changes, dw = -w, which gives -sum w Re(D^H z) in closed form.
+// Jacobian is stored.  Reverse mode all the way: the weights of the building
+// blocks (the pattern vectors P, their hour-angle and theta derivatives PH,
+// Pt, and the arrival-time derivatives dH, dT) are taken back to the site's
+// local frame vectors (the E/N components of the polarisation frame and
+// their H and theta derivatives), whose derivatives along latitude and
+// longitude are a handful of closed forms (the longitude enters only through
+// the hour angle, so d/dlon = d/dH); gamma moves only the pattern maps.
+// Along ln S0 only the weight changes, dw = -w, which gives
+// -sum w Re(D^H z) in closed form.
 #pragma once
 
 #include "gwf_model.hpp"
 
 namespace gwf {
 
-// ------------------------------------------------------------- tangents
-// A value and its derivatives along (latitude, longitude, gamma) of one site.
-struct T3 {
-  double v, d[3];
-};
-
-__host__ __device__ inline T3 t3c(double v) { return T3{v, {0.0, 0.0, 0.0}}; }
-__host__ __device__ inline T3 operator+(const T3& a, const T3& b) {
-  return T3{a.v + b.v, {a.d[0] + b.d[0], a.d[1] + b.d[1], a.d[2] + b.d[2]}};
-}
-__host__ __device__ inline T3 operator-(const T3& a, const T3& b) {
-  return T3{a.v - b.v, {a.d[0] - b.d[0], a.d[1] - b.d[1], a.d[2] - b.d[2]}};
-}
-__host__ __device__ inline T3 operator-(const T3& a) { return T3{-a.v, {-a.d[0], -a.d[1], -a.d[2]}}; }
-__host__ __device__ inline T3 operator*(const T3& a, const T3& b) {
-  return T3{a.v * b.v, {fma(a.d[0], b.v, a.v * b.d[0]), fma(a.d[1], b.v, a.v * b.d[1]),
-                        fma(a.d[2], b.v, a.v * b.d[2])}};
-}
-__host__ __device__ inline T3 operator*(double s, const T3& a) {
-  return T3{s * a.v, {s * a.d[0], s * a.d[1], s * a.d[2]}};
-}
-__host__ __device__ inline T3 operator*(const T3& a, double s) { return s * a; }
-__host__ __device__ inline T3 operator+(const T3& a, double s) { return T3{a.v + s, {a.d[0], a.d[1], a.d[2]}}; }
-// a * b + c
-__host__ __device__ inline T3 fmat(const T3& a, const T3& b, const T3& c) {
-  return T3{fma(a.v, b.v, c.v), {fma(a.d[0], b.v, fma(a.v, b.d[0], c.d[0])),
-                                 fma(a.d[1], b.v, fma(a.v, b.d[1], c.d[1])),
-                                 fma(a.d[2], b.v, fma(a.v, b.d[2], c.d[2]))}};
-}
-__host__ __device__ inline T3 dot4t(const T3 a[4], const T3 b[4]) {
-  return fmat(a[0], b[0], fmat(a[1], b[1], fmat(a[2], b[2], a[3] * b[3])));
-}
-
 // ----------------------------------------------------- site constants
-// The per-(event, site) constants of site_setup with their derivatives
-// along latitude (d[0]), longitude (d[1]) and gamma (d[2]).
+// The per-(event, site) constants of site_setup that the adjoint needs, and
+// the derivatives of the pattern maps along gamma.
 struct SiteA {
-  T3 cdl, sdl, sl, cl, slct, clst, k1, k0, k1t, k0t;
-  T3 alpha[2][4], beta[2][4];
-  double ct, st, xp_fac, ix_fac, x_fac, S0inv, weff[2];
+  double cdl, sdl;                       // cos, sin of (site longitude - phi)
+  double ct, st, sl, cl, slct, clst;     // cos th, sin th, sin lat, cos lat, sin lat cos th, cos lat sin th
+  double k1, k1t, k0t;                   // Delta = k1 cos H + k0, dDelta/dth = k1t cos H + k0t
+  double alpha[2][4], beta[2][4];        // pattern maps of the effective interferometers
+  double alpha_g[2][4], beta_g[2][4];    // and their derivatives along gamma
+  double xp_fac, ix_fac, x_fac, S0inv, weff[2];
   int32_t n_eff, tab_kind;
-  const double* tab_f;      // sampled noise curve (tab_kind 1 PSD, 2 ASD), as SiteC
+  const double* tab_f;                   // sampled noise curve (tab_kind 1 PSD, 2 ASD), as SiteC
   const double* tab_S;
   int64_t tab_n;
 };
 
 // Pattern maps of one interferometer (as pattern_map) and their derivatives
-// along its bisector angle.
-__host__ __device__ inline void pattern_map_t(double gamma, double zeta, double c2p, double s2p,
-                                              T3 al[4], T3 be[4]) {
+// along its bisector angle gamma.
+__host__ __device__ inline void pattern_map_g(double gamma, double zeta, double c2p, double s2p, double al[4],
+                                              double be[4], double alg[4], double beg[4]) {
+  pattern_map(gamma, zeta, c2p, s2p, al, be);
   const double sz = sin(zeta), s2g = sin(2.0 * gamma), c2g = cos(2.0 * gamma);
-  const double v_al[4] = {sz * s2g * c2p, -sz * c2g * c2p, sz * s2g * s2p, -sz * c2g * s2p};
-  const double v_be[4] = {-sz * s2g * s2p, sz * c2g * s2p, sz * s2g * c2p, -sz * c2g * c2p};
   // d/dgamma: s2g -> 2 c2g, c2g -> -2 s2g
-  const double g_al[4] = {2.0 * sz * c2g * c2p, 2.0 * sz * s2g * c2p, 2.0 * sz * c2g * s2p,
-                          2.0 * sz * s2g * s2p};
-  const double g_be[4] = {-2.0 * sz * c2g * s2p, -2.0 * sz * s2g * s2p, 2.0 * sz * c2g * c2p,
-                          2.0 * sz * s2g * c2p};
-  for (int i = 0; i < 4; ++i) {
-    al[i] = T3{v_al[i], {0.0, 0.0, g_al[i]}};
-    be[i] = T3{v_be[i], {0.0, 0.0, g_be[i]}};
-  }
+  alg[0] = 2.0 * sz * c2g * c2p; alg[1] = 2.0 * sz * s2g * c2p; alg[2] = 2.0 * sz * c2g * s2p;
+  alg[3] = 2.0 * sz * s2g * s2p;
+  beg[0] = -2.0 * sz * c2g * s2p; beg[1] = -2.0 * sz * s2g * s2p; beg[2] = 2.0 * sz * c2g * c2p;
+  beg[3] = 2.0 * sz * s2g * c2p;
 }
 
 // arm_on as for site_setup.
@@ -91,20 +61,15 @@ __host__ __device__ inline void site_setup_adj(const double* p, const SiteDesc& 
                                                SiteA& sa, uint32_t arm_on = 7u) {
   const double th = p[3], ph = p[4], psi = p[6];
   const double c2p = cos(2.0 * psi), s2p = sin(2.0 * psi);
-  const double cdl = cos(sd.lon - ph), sdl = sin(sd.lon - ph);
-  sa.cdl = T3{cdl, {0.0, -sdl, 0.0}};
-  sa.sdl = T3{sdl, {0.0, cdl, 0.0}};
+  sa.cdl = cos(sd.lon - ph);
+  sa.sdl = sin(sd.lon - ph);
   const double ct = cos(th), st = sin(th), sl = sin(sd.lat), cl = cos(sd.lat);
-  sa.ct = ct; sa.st = st;
-  const T3 tsl = T3{sl, {cl, 0.0, 0.0}}, tcl = T3{cl, {-sl, 0.0, 0.0}};
-  sa.sl = tsl;
-  sa.cl = tcl;
-  sa.slct = ct * tsl;
-  sa.clst = st * tcl;
-  sa.k1 = (-kREarthS * st) * tcl;
-  sa.k0 = (-kREarthS * ct) * tsl;
-  sa.k1t = (-kREarthS * ct) * tcl;
-  sa.k0t = (kREarthS * st) * tsl;
+  sa.ct = ct; sa.st = st; sa.sl = sl; sa.cl = cl;
+  sa.slct = sl * ct;
+  sa.clst = cl * st;
+  sa.k1 = -kREarthS * cl * st;
+  sa.k1t = -kREarthS * cl * ct;
+  sa.k0t = kREarthS * sl * st;
   sa.xp_fac = exp(4.14 * (log(ec.piM) + log(sd.f0)));
   sa.ix_fac = sd.f0 * ec.piM;
   sa.x_fac = 1.0 / sa.ix_fac;
@@ -113,14 +78,18 @@ __host__ __device__ inline void site_setup_adj(const double* p, const SiteDesc& 
   sa.tab_f = sd.tab_f;
   sa.tab_S = sd.tab_S;
   sa.tab_n = sd.tab_n;
+  for (int r = 0; r < 2; ++r)
+    for (int j = 0; j < 4; ++j) sa.alpha[r][j] = sa.beta[r][j] = sa.alpha_g[r][j] = sa.beta_g[r][j] = 0.0;
   if (sd.shape == 1) {
-    T3 al[3][4], be[3][4];
+    double al[3][4], be[3][4], alg[3][4], beg[3][4];
     for (int k = 0; k < 3; ++k)
-      pattern_map_t(sd.gamma + kPi / 6.0 + kTwoPi * k / 3.0, kPi / 3.0, c2p, s2p, al[k], be[k]);
+      pattern_map_g(sd.gamma + kPi / 6.0 + kTwoPi * k / 3.0, kPi / 3.0, c2p, s2p, al[k], be[k], alg[k], beg[k]);
     if ((arm_on & 7u) == 7u) {
       for (int j = 0; j < 4; ++j) {
         sa.alpha[0][j] = al[0][j] + al[1][j]; sa.beta[0][j] = be[0][j] + be[1][j];
         sa.alpha[1][j] = al[0][j] - al[1][j]; sa.beta[1][j] = be[0][j] - be[1][j];
+        sa.alpha_g[0][j] = alg[0][j] + alg[1][j]; sa.beta_g[0][j] = beg[0][j] + beg[1][j];
+        sa.alpha_g[1][j] = alg[0][j] - alg[1][j]; sa.beta_g[1][j] = beg[0][j] - beg[1][j];
       }
       sa.weff[0] = 1.5; sa.weff[1] = 0.5;
       sa.n_eff = 2;
@@ -128,19 +97,18 @@ __host__ __device__ inline void site_setup_adj(const double* p, const SiteDesc& 
       int m = 0;
       for (int k = 0; k < 3; ++k)
         if (arm_on >> k & 1u) {
-          for (int j = 0; j < 4; ++j) { sa.alpha[m][j] = al[k][j]; sa.beta[m][j] = be[k][j]; }
+          for (int j = 0; j < 4; ++j) {
+            sa.alpha[m][j] = al[k][j]; sa.beta[m][j] = be[k][j];
+            sa.alpha_g[m][j] = alg[k][j]; sa.beta_g[m][j] = beg[k][j];
+          }
           sa.weff[m] = 1.0;
           ++m;
         }
-      for (int r = m; r < 2; ++r) {
-        for (int j = 0; j < 4; ++j) { sa.alpha[r][j] = t3c(0.0); sa.beta[r][j] = t3c(0.0); }
-        sa.weff[r] = 0.0;
-      }
+      for (int r = m; r < 2; ++r) sa.weff[r] = 0.0;
       sa.n_eff = m;
     }
   } else {
-    pattern_map_t(sd.gamma, sd.zeta, c2p, s2p, sa.alpha[0], sa.beta[0]);
-    for (int j = 0; j < 4; ++j) { sa.alpha[1][j] = t3c(0.0); sa.beta[1][j] = t3c(0.0); }
+    pattern_map_g(sd.gamma, sd.zeta, c2p, s2p, sa.alpha[0], sa.beta[0], sa.alpha_g[0], sa.beta_g[0]);
     sa.weff[0] = 1.0; sa.weff[1] = 0.0;
     sa.n_eff = (arm_on & 1u) ? 1 : 0;
   }
@@ -220,25 +188,28 @@ __host__ __device__ inline void adjoint_site(const EventC& ec, const SiteA& sa, 
   // hour angle, pattern vectors and arrival-time derivatives: values
   double Pv[4], PH[4], Pt[4], dHv, dTv;
   {
-    const double cH = q.cth * sa.cdl.v - q.sth * sa.sdl.v;
-    const double sH = q.sth * sa.cdl.v + q.cth * sa.sdl.v;
-    const double EX = cH, EY = -(sa.ct * sH), NX = -(sa.sl.v * sH), NY = -(sa.slct.v * cH + sa.clst.v);
+    // the site's E/N frame components of the polarisation frame and their H
+    // and theta derivatives (formed again for the reverse pass below rather
+    // than kept live across the interferometers)
+    const double cH = q.cth * sa.cdl - q.sth * sa.sdl;
+    const double sH = q.sth * sa.cdl + q.cth * sa.sdl;
+    const double EX = cH, EY = -(sa.ct * sH), NX = -(sa.sl * sH), NY = -(sa.slct * cH + sa.clst);
+    const double EXh = -sH, EYh = -(sa.ct * cH), NXh = -(sa.sl * cH), NYh = sa.slct * sH;
+    const double EYt = sa.st * sH, NYt = sa.st * (sa.sl * cH) - sa.ct * sa.cl;
     Pv[0] = 0.5 * (EX * EX - NX * NX - EY * EY + NY * NY);
     Pv[1] = EX * NX - EY * NY;
     Pv[2] = EX * EY - NX * NY;
     Pv[3] = EX * NY + NX * EY;
-    const double EXh = -sH, EYh = -(sa.ct * cH), NXh = -(sa.sl.v * cH), NYh = sa.slct.v * sH;
     PH[0] = EX * EXh - NX * NXh - EY * EYh + NY * NYh;
     PH[1] = EXh * NX + EX * NXh - EYh * NY - EY * NYh;
     PH[2] = EXh * EY + EX * EYh - NXh * NY - NX * NYh;
     PH[3] = EXh * NY + EX * NYh + NXh * EY + NX * EYh;
-    const double EYt = sa.st * sH, NYt = sa.st * (sa.sl.v * cH) - sa.ct * sa.cl.v;
     Pt[0] = -(EY * EYt) + NY * NYt;
     Pt[1] = -(EYt * NY + EY * NYt);
     Pt[2] = EX * EYt - NX * NYt;
     Pt[3] = EX * NYt + NX * EYt;
-    dHv = -(sa.k1.v * sH);
-    dTv = fma(sa.k1t.v, cH, sa.k0t.v);
+    dHv = -(sa.k1 * sH);
+    dTv = fma(sa.k1t, cH, sa.k0t);
   }
   const double om0 = sa.tab_kind ? table_weight(sa.tab_f, sa.tab_S, sa.tab_n, sa.tab_kind, sa.S0inv, q.w4A2, q.f)
                                  : psd_weight_of(sa.xp_fac, 0.0, sa.ix_fac, sa.x_fac, sa.S0inv, q);
@@ -263,8 +234,8 @@ __host__ __device__ inline void adjoint_site(const EventC& ec, const SiteA& sa, 
     double al[4], be[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      al[i] = sa.alpha[j][i].v;
-      be[i] = sa.beta[j][i].v;
+      al[i] = sa.alpha[j][i];
+      be[i] = sa.beta[j][i];
     }
     const double Fp = dot4(al, Pv), Fx = dot4(be, Pv);
     const double FpH = dot4(al, PH), FxH = dot4(be, PH);
@@ -344,8 +315,8 @@ __host__ __device__ inline void adjoint_site(const EventC& ec, const SiteA& sa, 
       bPH[i] = fma(kFpH, al[i], fma(kFxH, be[i], bPH[i]));
       bPt[i] = fma(kFpt, al[i], fma(kFxt, be[i], bPt[i]));
       sP[i] = fma(sFp, al[i], fma(sFx, be[i], sP[i]));
-      ag[i] = sa.alpha[j][i].d[2];
-      bg[i] = sa.beta[j][i].d[2];
+      ag[i] = sa.alpha_g[j][i];
+      bg[i] = sa.beta_g[j][i];
     }
     const double gFp = dot4(ag, Pv), gFx = dot4(bg, Pv);
     bgam = fma(kFp, gFp, fma(kFx, gFx, fma(kFpH, dot4(ag, PH), fma(kFxH, dot4(bg, PH),
@@ -356,50 +327,57 @@ __host__ __device__ inline void adjoint_site(const EventC& ec, const SiteA& sa, 
     acc[kAdjS + 3] = fma(-om, q2, acc[kAdjS + 3]);
     acc[kAdjW] = fma(om, q2, acc[kAdjW]);
   }
-  // latitude and longitude tangents of the geometry, contracted with the adjoints
+  // reverse pass through the geometry: the weights of the pattern vectors
+  // (bP, bPH, bPt; sP for SNR^2) taken back to the frame components EX, EY,
+  // NX, NY, their H derivatives (h) and theta derivatives (t) ...
   asm volatile("" ::: "memory");
-  const T3 cH = q.cth * sa.cdl - q.sth * sa.sdl;
-  const T3 sH = q.sth * sa.cdl + q.cth * sa.sdl;
-  const T3 EX = cH, EY = -(sa.ct * sH), NX = -(sa.sl * sH), NY = -(sa.slct * cH + sa.clst);
-  double tb[2] = {0.0, 0.0}, ts[2] = {0.0, 0.0};
-  {
-    const T3 P0 = 0.5 * (EX * EX - NX * NX - EY * EY + NY * NY);
-    const T3 P1 = EX * NX - EY * NY;
-    const T3 P2 = EX * EY - NX * NY;
-    const T3 P3 = EX * NY + NX * EY;
-#pragma unroll
-    for (int x = 0; x < 2; ++x) {
-      tb[x] = fma(bP[0], P0.d[x], fma(bP[1], P1.d[x], fma(bP[2], P2.d[x], bP[3] * P3.d[x])));
-      ts[x] = fma(sP[0], P0.d[x], fma(sP[1], P1.d[x], fma(sP[2], P2.d[x], sP[3] * P3.d[x])));
-    }
-  }
-  {
-    const T3 EXh = -sH, EYh = -(sa.ct * cH), NXh = -(sa.sl * cH), NYh = sa.slct * sH;
-    const T3 H0 = EX * EXh - NX * NXh - EY * EYh + NY * NYh;
-    const T3 H1 = EXh * NX + EX * NXh - EYh * NY - EY * NYh;
-    const T3 H2 = EXh * EY + EX * EYh - NXh * NY - NX * NYh;
-    const T3 H3 = EXh * NY + EX * NYh + NXh * EY + NX * EYh;
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-      tb[x] = fma(bPH[0], H0.d[x], fma(bPH[1], H1.d[x], fma(bPH[2], H2.d[x], fma(bPH[3], H3.d[x], tb[x]))));
-  }
-  {
-    const T3 EYt = sa.st * sH, NYt = sa.st * (sa.sl * cH) - sa.ct * sa.cl;
-    const T3 T0 = -(EY * EYt) + NY * NYt;
-    const T3 T1 = -(EYt * NY + EY * NYt);
-    const T3 T2 = EX * EYt - NX * NYt;
-    const T3 T3v = EX * NYt + NX * EYt;
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-      tb[x] = fma(bPt[0], T0.d[x], fma(bPt[1], T1.d[x], fma(bPt[2], T2.d[x], fma(bPt[3], T3v.d[x], tb[x]))));
-  }
-  const T3 dH = -(sa.k1 * sH);
-  const T3 dT = fmat(sa.k1t, cH, sa.k0t);
-#pragma unroll
-  for (int x = 0; x < 2; ++x) {
-    acc[kAdjT + x] += fma(bdH, dH.d[x], fma(bdT, dT.d[x], tb[x]));
-    acc[kAdjS + x] += ts[x];
-  }
+  const double cH = q.cth * sa.cdl - q.sth * sa.sdl;
+  const double sH = q.sth * sa.cdl + q.cth * sa.sdl;
+  const double EX = cH, EY = -(sa.ct * sH), NX = -(sa.sl * sH), NY = -(sa.slct * cH + sa.clst);
+  const double EXh = -sH, EYh = -(sa.ct * cH), NXh = -(sa.sl * cH), NYh = sa.slct * sH;
+  const double EYt = sa.st * sH, NYt = sa.st * (sa.sl * cH) - sa.ct * sa.cl;
+  const double aEX = fma(bP[0], EX, fma(bP[1], NX, fma(bP[2], EY, fma(bP[3], NY, fma(bPH[0], EXh,
+                     fma(bPH[1], NXh, fma(bPH[2], EYh, fma(bPH[3], NYh, fma(bPt[2], EYt, bPt[3] * NYt)))))))));
+  const double aEY = fma(-bP[0], EY, fma(-bP[1], NY, fma(bP[2], EX, fma(bP[3], NX, fma(-bPH[0], EYh,
+                     fma(-bPH[1], NYh, fma(bPH[2], EXh, fma(bPH[3], NXh, fma(-bPt[0], EYt, -bPt[1] * NYt)))))))));
+  const double aNX = fma(-bP[0], NX, fma(bP[1], EX, fma(-bP[2], NY, fma(bP[3], EY, fma(-bPH[0], NXh,
+                     fma(bPH[1], EXh, fma(-bPH[2], NYh, fma(bPH[3], EYh, fma(-bPt[2], NYt, bPt[3] * EYt)))))))));
+  const double aNY = fma(bP[0], NY, fma(-bP[1], EY, fma(-bP[2], NX, fma(bP[3], EX, fma(bPH[0], NYh,
+                     fma(-bPH[1], EYh, fma(-bPH[2], NXh, fma(bPH[3], EXh, fma(bPt[0], NYt, -bPt[1] * EYt)))))))));
+  const double aEXh = fma(bPH[0], EX, fma(bPH[1], NX, fma(bPH[2], EY, bPH[3] * NY)));
+  const double aEYh = fma(-bPH[0], EY, fma(-bPH[1], NY, fma(bPH[2], EX, bPH[3] * NX)));
+  const double aNXh = fma(-bPH[0], NX, fma(bPH[1], EX, fma(-bPH[2], NY, bPH[3] * EY)));
+  const double aNYh = fma(bPH[0], NY, fma(-bPH[1], EY, fma(-bPH[2], NX, bPH[3] * EX)));
+  const double aEYt = fma(-bPt[0], EY, fma(-bPt[1], NY, fma(bPt[2], EX, bPt[3] * NX)));
+  const double aNYt = fma(bPt[0], NY, fma(-bPt[1], EY, fma(-bPt[2], NX, bPt[3] * EX)));
+  const double sEX = fma(sP[0], EX, fma(sP[1], NX, fma(sP[2], EY, sP[3] * NY)));
+  const double sEY = fma(-sP[0], EY, fma(-sP[1], NY, fma(sP[2], EX, sP[3] * NX)));
+  const double sNX = fma(-sP[0], NX, fma(sP[1], EX, fma(-sP[2], NY, sP[3] * EY)));
+  const double sNY = fma(sP[0], NY, fma(-sP[1], EY, fma(-sP[2], NX, sP[3] * EX)));
+  // ... and contracted with their derivatives.  Longitude enters only through
+  // the hour angle H: dEX/dH = EXh etc., dEXh/dH = -EX, dEYh/dH = -EY,
+  // dNXh/dH = -NX, dNYh/dH = -(NY + clst), dEYt/dH = st cH, dNYt/dH =
+  // -st sl sH, d dH/dH = -k1 cH, d dT/dH = -k1t sH.
+  const double glon = fma(aEX, EXh, fma(aEY, EYh, fma(aNX, NXh, fma(aNY, NYh,
+                      fma(-aEXh, EX, fma(-aEYh, EY, fma(-aNXh, NX, fma(-aNYh, NY + sa.clst,
+                      fma(aEYt, sa.st * cH, fma(-aNYt, sa.st * sa.sl * sH,
+                      fma(-bdH, sa.k1 * cH, -bdT * sa.k1t * sH)))))))))));
+  const double slon = fma(sEX, EXh, fma(sEY, EYh, fma(sNX, NXh, sNY * NYh)));
+  // Latitude: sl' = cl, cl' = -sl, so EX, EY, EXh, EYh, EYt do not move,
+  // dNX = -cl sH, dNY = sl st - cl ct cH, dNXh = -cl cH, dNYh = cl ct sH,
+  // dNYt = st cl cH + sl ct; the delay coefficients k1 = -R cl st,
+  // k1t = -R cl ct, k0t = R sl st give d dH = -R sl st sH and
+  // d dT = R (sl ct cH + cl st).
+  const double cl = sa.cl, sl = sa.sl, ct = sa.ct, st = sa.st;
+  const double dNY = fma(sl, st, -cl * ct * cH);
+  const double glat = fma(aNX, -cl * sH, fma(aNY, dNY, fma(aNXh, -cl * cH, fma(aNYh, cl * ct * sH,
+                      fma(aNYt, fma(st * cl, cH, sl * ct), fma(bdH, -kREarthS * sl * st * sH,
+                      bdT * kREarthS * fma(sl * ct, cH, cl * st)))))));
+  const double slat = fma(sNX, -cl * sH, sNY * dNY);
+  acc[kAdjT + 0] += glat;
+  acc[kAdjT + 1] += glon;
+  acc[kAdjS + 0] += slat;
+  acc[kAdjS + 1] += slon;
   acc[kAdjT + 2] += bgam;
   acc[kAdjS + 2] += sgam;
 }

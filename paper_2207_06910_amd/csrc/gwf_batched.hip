@@ -40,7 +40,7 @@ __global__ void setup_kernel(SetupArgs a) {
   if (!ec.status && (a.npts[t] != a.npts_plan[t] || a.npts[t] > a.npts_max))
     ec.status = kEvInvalid;   // grid changed since the items were built, or longer than they allow
   a.evc[t] = ec;
-  a.status[t] = ec.status;
+  if (a.status) a.status[t] = ec.status;
   if (!ec.status)
     for (int s = 0; s < a.net.n_site; ++s) {
       SiteC sc;

@@ -26,7 +26,7 @@ struct SetupArgs {
   uint32_t flags;
   EventC* evc;                // [n]
   SiteC* sic;                 // [n][n_site]
-  int32_t* status;            // [n] output: parameter status of each event
+  int32_t* status;            // [n] or NULL, output: parameter status of each event
 };
 
 struct ItemsArgs {
@@ -50,6 +50,38 @@ struct CombineArgs {
   int32_t* status;            // [n]
   const uint32_t* par_mask;   // [n] or NULL: rows of each event's Fisher matrix (others 0)
 };
+
+// The adjoint over work items (gwf_plan_adjoint): one workgroup per item of
+// the plan, the plan's per-event constants, the sites' constants with their
+// gamma derivatives formed per item in LDS, each item's per-site sums
+// written to its slot.
+struct AdjItemsArgs {
+  const double* par;          // [13][ld]: theta, phi, psi of each event for the site constants
+  int64_t ld, n;
+  const uint8_t* active;      // [n_ifo][ld] or NULL
+  const uint32_t* par_mask;   // [n] or NULL
+  NetDesc net;
+  const double* gbar;         // [P][P][n]
+  const int32_t* status;      // [n] or NULL: events with a nonzero status contribute zero
+  const EventC* evc;
+  const Item* items;          // one workgroup per item, in this order
+  int32_t n_items;
+  double* partial;            // [n_items][n_site][8]; NaN where the event is left out
+};
+
+struct AdjCombineArgs {
+  int64_t n;
+  int32_t n_site;
+  const int32_t* item_first;  // [n+1]
+  const double* partial;
+  double w_snr, w_fisher;
+  double* grad_event;         // [n][n_site][4]
+  double* grad;               // [n_site][4]
+};
+
+hipError_t launch_adjoint_items(const AdjItemsArgs& a, int npi, bool rot, hipStream_t s);
+hipError_t launch_adjoint_combine(const AdjCombineArgs& a, hipStream_t s);
+int adjoint_items_block();
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 // Work items built on the device: each event's count of items of at most

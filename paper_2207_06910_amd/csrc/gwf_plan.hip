@@ -24,7 +24,7 @@ struct gwf_plan {
   NetDesc net{};
   uint32_t flags = 0;
   int64_t n = 0;
-  int P = 0, npi = 3, nacc = 0, n_cu = 0;
+  int P = 0, npi = 3, nacc = 0, n_cu = 0, n_site_alloc = 0;
   bool tidal = false, rot = false, mixed = false;
   std::vector<int32_t> npts_host;
   // tuning
@@ -231,6 +231,7 @@ gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const g
     return api_hip_fail(err, "reading grid lengths");
   }
   int64_t total = 0;
+  p->n_site_alloc = p->net.n_site;
   if ((err = dev_alloc(&p->evc, p->n, total)) != hipSuccess ||
       (err = dev_alloc(&p->sic, p->n * p->net.n_site, total)) != hipSuccess ||
       (err = dev_alloc(&p->npts_plan, p->n, total)) != hipSuccess ||
@@ -329,6 +330,55 @@ gwf_status gwf_plan_fisher(gwf_plan* p, double* fisher, double* snr, int32_t* st
   }
   hipError_t err = hipGraphLaunch(p->exec, s);
   if (err != hipSuccess) return api_hip_fail(err, "graph launch");
+  return GWF_OK;
+}
+
+gwf_status gwf_plan_set_network(gwf_plan* p, const gwf_network* net) {
+  if (!p) return api_fail(GWF_E_INVALID_ARG, "plan is NULL");
+  NetDesc nd;
+  gwf_status st = api_pack_network(net, nd);
+  if (st) return st;
+  if (nd.n_site > p->n_site_alloc)
+    return api_fail(GWF_E_INVALID_ARG, "%d sites: the plan holds site constants for %d", nd.n_site, p->n_site_alloc);
+  p->net = nd;
+  if (p->exec) {                    // the captured graph holds the old network
+    (void)hipGraphExecDestroy(p->exec);
+    p->exec = nullptr;
+  }
+  return GWF_OK;
+}
+
+gwf_status gwf_plan_adjoint(gwf_plan* p, const double* gbar, const int32_t* status, double w_snr,
+                            double w_fisher, double* grad_event, double* grad, void* stream) {
+  if (!p) return api_fail(GWF_E_INVALID_ARG, "plan is NULL");
+  if (!gbar || !grad_event || !grad) return api_fail(GWF_E_INVALID_ARG, "gbar, grad_event and grad are required");
+  if (!std::isfinite(w_snr) || !std::isfinite(w_fisher))
+    return api_fail(GWF_E_INVALID_ARG, "w_snr and w_fisher must be finite");
+  if (p->mixed) return api_fail(GWF_E_UNSUPPORTED, "the adjoint has no mixed form (create the plan without GWF_MIXED)");
+  hipStream_t s = (hipStream_t)stream;
+  // the events' constants (the same set-up kernel as gwf_plan_fisher)
+  SetupArgs sa{};
+  sa.par = p->ev.par; sa.ld = p->ev.ld; sa.n = p->n;
+  sa.fmin = p->grid.fmin; sa.fmax = p->grid.fmax; sa.npts = p->grid.npts; sa.npts_plan = p->npts_plan;
+  sa.npts_max = 0x7fffffff;
+  sa.ecc = p->ev.ecc; sa.fref = p->ev.f_ref_ecc;
+  sa.net = p->net; sa.flags = p->flags; sa.evc = p->evc; sa.sic = p->sic; sa.status = nullptr;
+  sa.active = p->ev.active;
+  hipError_t err = launch_setup(sa, s);
+  if (err == hipSuccess) {
+    AdjItemsArgs aa{};
+    aa.par = p->ev.par; aa.ld = p->ev.ld; aa.n = p->n; aa.active = p->ev.active; aa.par_mask = p->ev.par_mask;
+    aa.net = p->net; aa.gbar = gbar; aa.status = status; aa.evc = p->evc;
+    aa.items = p->items; aa.n_items = p->n_items; aa.partial = p->partial;
+    err = launch_adjoint_items(aa, p->npi, p->rot, s);
+  }
+  if (err == hipSuccess) {
+    AdjCombineArgs ca{};
+    ca.n = p->n; ca.n_site = p->net.n_site; ca.item_first = p->item_first; ca.partial = p->partial;
+    ca.w_snr = w_snr; ca.w_fisher = w_fisher; ca.grad_event = grad_event; ca.grad = grad;
+    err = launch_adjoint_combine(ca, s);
+  }
+  if (err != hipSuccess) return api_hip_fail(err, "plan adjoint launch");
   return GWF_OK;
 }
 

@@ -195,3 +195,120 @@ def test_logdet_gradient_end_to_end_against_oracle(lib, orc):
     print(f"ln det gradient: max |error| / allowance {np.max(err / tol):.2e}, "
           f"max relative {np.max(err / np.maximum(np.abs(ref), 1e-300)):.2e}, kappa {oinv['cond'].min():.1e}"
           f"-{oinv['cond'].max():.1e}")
+
+
+# ------------------------------------------------------------ batched (plan) form
+def _plan_adjoint(lib, wl, gbar, status=None, w_snr=1.0, w_fisher=1.0, chunk=512):
+    dw = lib.DeviceWorkload(wl)
+    plan = lib.Plan(dw, chunk=chunk, wg_per_cu=2)
+    g = torch.as_tensor(np.ascontiguousarray(gbar), device="cuda")
+    st = None if status is None else torch.as_tensor(status, dtype=torch.int32, device="cuda")
+    r = plan.adjoint(g, status=st, w_snr=w_snr, w_fisher=w_fisher)
+    torch.cuda.synchronize()
+    out = r["grad_event"].cpu().numpy(), r["grad"].cpu().numpy()
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("flags", [synth.FLAG_EARTH_ROT | synth.FLAG_TIDAL, synth.FLAG_EARTH_ROT, 0])
+def test_plan_adjoint_against_oracle_and_plain(lib, orc, flags):
+    """gwf_plan_adjoint over work items of 512 points (events split into
+    several items, ragged ends): against the oracle's nested duals (1e-10 of
+    the size) and the one-workgroup-per-event adjoint (1e-12), summed grad
+    equal to the sum of the event terms."""
+    wl = synth.bns1e4(n=4)
+    wl.npts = np.array([257, 1600, 1023, 2], dtype=np.int32)
+    wl.flags = flags
+    P = 13 if flags & synth.FLAG_TIDAL else 11
+    F = orc.fisher(wl)["fisher"]
+    d = np.sqrt(np.einsum("iie->ie", F))
+    gbar = np.random.default_rng(19).normal(size=(P, P, wl.n)) / (d[:, None, :] * d[None, :, :])
+    ge, g = _plan_adjoint(lib, wl, gbar, w_snr=0.7, w_fisher=1.3)
+    ref, size = _reference(gbar, *_tangents(orc, wl), 0.7, 1.3)
+    scale = np.abs(ref).max(axis=(1, 2), keepdims=True)
+    assert (np.abs(ge - ref) / scale).max() < 1e-10
+    gp, _ = _adjoint(lib, wl, gbar, w_snr=0.7, w_fisher=1.3)
+    assert (np.abs(ge - gp) / scale).max() < 1e-12
+    np.testing.assert_allclose(g, ge.sum(axis=0), rtol=1e-12, atol=1e-14 * np.abs(ge).max())
+
+
+def test_plan_adjoint_mixed_population_duty_factor_and_flags(lib, orc):
+    """The mixed BBH/BNS workload (per-event parameter sets) with the duty
+    factor (some interferometers off) and flagged events: equal to the plain
+    adjoint within 1e-12 of each event's size; flagged events give zeros."""
+    full = synth.mixed1e4()
+    wl = full.subset(np.arange(24)).with_duty_factor(0.8, seed=3)
+    dw = lib.DeviceWorkload(wl)
+    r = lib.fisher(dw)
+    inv = lib.invert(r["fisher"], r["status"], par_mask=dw.par_mask)
+    gbar = inv["cov"].cpu().numpy()
+    status = inv["status"].cpu().numpy().copy()
+    status[[3, 7]] = 2
+    ge, g = _plan_adjoint(lib, wl, gbar, status=status, chunk=1024)
+    gp, _ = _adjoint(lib, wl, gbar, status=status)
+    assert np.all(ge[[3, 7]] == 0)
+    scale = np.maximum(np.abs(gp).max(axis=(1, 2), keepdims=True), 1e-300)
+    assert (np.abs(ge - gp) / scale).max() < 1e-11
+
+
+def test_plan_adjoint_reproducible_and_network_update(lib, orc):
+    """Bitwise reproducible; after gwf_plan_set_network (a site moved and
+    turned) the plan's Fisher matrices and adjoint equal the plain entry
+    points on the moved network."""
+    import dataclasses
+    wl = synth.bns1e4(n=6).with_npts(1500)
+    dw = lib.DeviceWorkload(wl)
+    plan = lib.Plan(dw, chunk=1024, wg_per_cu=2)
+    F = orc.fisher(wl)["fisher"]
+    d = np.sqrt(np.einsum("iie->ie", F))
+    gbar = torch.as_tensor(np.random.default_rng(4).normal(size=(13, 13, wl.n)) / (d[:, None, :] * d[None, :, :]),
+                           device="cuda")
+    a = plan.adjoint(gbar)
+    ga = a["grad"].clone()
+    b = plan.adjoint(gbar)
+    torch.cuda.synchronize()
+    assert torch.equal(ga, b["grad"])
+    moved = list(wl.sites)
+    moved[1] = dataclasses.replace(moved[1], lat=moved[1].lat + 0.2, gamma=moved[1].gamma - 0.4)
+    plan.set_sites(moved)
+    pf = {k: v.cpu().numpy() for k, v in plan.run().items()}
+    pa = plan.adjoint(gbar)["grad_event"].cpu().numpy()
+    plan.close()
+    dwm = dw.with_sites(moved)
+    f = {k: v.cpu().numpy() for k, v in lib.fisher(dwm).items()}
+    pg = lib.fisher_adjoint(dwm, gbar)["grad_event"].cpu().numpy()
+    dd = np.sqrt(np.einsum("iie->ie", f["fisher"]))
+    assert (np.abs(pf["fisher"] - f["fisher"]) / (dd[:, None, :] * dd[None, :, :])).max() < 1e-13
+    assert (np.abs(pa - pg) / np.abs(pg).max(axis=(1, 2), keepdims=True)).max() < 1e-12
+    assert not np.allclose(pa, ga.cpu().numpy())
+
+
+def test_figure_of_merit_through_a_plan(lib):
+    """autodiff.network_fom with a plan: the same J and gradient as the
+    plain entry points (1e-11), for the extrinsic block of 32 events."""
+    from paper_2207_06910_amd import autodiff
+    wl = synth.mixed1e4().subset(np.arange(32))
+    dw = lib.DeviceWorkload(wl)
+    rows = (2, 3, 4, 5, 6)
+    xi = autodiff.site_parameters(dw)
+    xi[0, 0] += 0.05                                   # away from the plan's own network
+    x1 = xi.clone().requires_grad_(True)
+    J1 = autodiff.network_fom(x1, dw, rows=rows)
+    J1.backward()
+    plan = lib.Plan(dw, chunk=2048, wg_per_cu=2)
+    x2 = xi.clone().requires_grad_(True)
+    J2 = autodiff.network_fom(x2, dw, rows=rows, plan=plan)
+    J2.backward()
+    plan.close()
+    assert abs(float(J1) - float(J2)) <= 1e-11 * abs(float(J1))
+    g1, g2 = x1.grad.numpy(), x2.grad.numpy()
+    assert np.abs(g1 - g2).max() <= 1e-11 * np.abs(g1).max()
+
+
+def test_plan_adjoint_rejects_the_mixed_form(lib):
+    wl = synth.bns1e4(n=2).with_npts(600)
+    plan = lib.Plan(lib.DeviceWorkload(wl), chunk=512, wg_per_cu=2, mixed=True)
+    g = torch.zeros((13, 13, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.GwfError):
+        plan.adjoint(g)
+    plan.close()

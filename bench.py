@@ -269,17 +269,16 @@ def gradient_form(binding, synth, torch, args, timed) -> dict:
                                   "adjoint_ms": round(bwd, 4),
                                   "adjoint_over_forward": round(bwd / fwd, 3),
                                   "adjoint_per_event_ms": round(bwd_plain, 4),
-                                  "chunk": info["chunk"], "wg_per_cu": info["wg_per_cu"],
+                                  "chunk": info["chunk"],
                                   "events_per_s": round(wl.n / (ms * 1e-3), 1)}}
 
 
 def catalogue_form(binding, synth, torch, args, timed, info) -> dict:
-    """The batched FP64 form (same item length and workgroups per CU as on
-    the BNS catalogue) on the 10^6-event BBH/BNS/NSBH catalogue, each
+    """The batched FP64 form (same item length as on the BNS catalogue) on the 10^6-event BBH/BNS/NSBH catalogue, each
     event's Fisher matrix with its kind's parameters (11, 13 or 12)."""
     wl = synth.catalog1e6()
     dw = binding.DeviceWorkload(wl)
-    plan = binding.Plan(dw, chunk=info["chunk"], wg_per_cu=info["wg_per_cu"])
+    plan = binding.Plan(dw, chunk=info["chunk"])
     out = {}
     plan.run(invert=True, out=out)
     ms = timed(lambda: plan.run(invert=True, out=out), 3)
@@ -328,7 +327,6 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk", type=int, default=0, help="batched form: fixed item length (0: autotune)")
-    ap.add_argument("--wg-per-cu", type=int, default=0, help="batched form: fixed WGs per CU (0: autotune)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the detector-gradient and 10^6-event catalogue measurements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -405,15 +403,15 @@ def main():
     plain_res = {"snr": outf["snr"].cpu().numpy(), "fisher": outf["fisher"].cpu().numpy(),
                  "sigma": outi["sigma"].cpu().numpy(), "sigma9": block9(outf["fisher"], outf["status"])}
 
-    # ---- batched forms: work items, persistent workgroups, one HIP graph per step
-    def batched(mixed, chunk, wg):
-        plan = binding.Plan(dw, chunk=chunk, wg_per_cu=wg, mixed=mixed, inv_method="cho_svd")   # 0: autotuned
+    # ---- batched forms: work items (one workgroup each), one HIP graph per step
+    def batched(mixed, chunk):
+        plan = binding.Plan(dw, chunk=chunk, mixed=mixed, inv_method="cho_svd")   # 0: autotuned
         info = plan.info()
         outb = {}
         for i in range(args.warmup):
             plan.run(invert=True, out=outb)
         ms = timed(lambda: plan.run(invert=True, out=outb), args.steps)
-        prof = binding.Plan(dw, chunk=info["chunk"], wg_per_cu=info["wg_per_cu"], use_graph=False,
+        prof = binding.Plan(dw, chunk=info["chunk"], use_graph=False,
                             profile=True, mixed=mixed, inv_method="cho_svd")
         items = []
         outp = {}
@@ -426,13 +424,13 @@ def main():
         plan.close()
         sb = res["status"]
         tag = "mixed" if mixed else "FP64"
-        log(f"batched {tag}: chunk {info['chunk']}, {info['wg_per_cu']} WG/CU, {info['n_items']} "
+        log(f"batched {tag}: chunk {info['chunk']}, {info['n_items']} "
             f"items, {ms:.3f} ms/step, items kernel {float(np.mean(items)):.3f} ms, inverted "
             f"{int(np.sum((sb & ~32) == 0))}/{wl.n} ({int(np.sum(sb == 32))} by SVD after a failed Cholesky)")
         return ms, float(np.mean(items)), info, res
 
-    batched_ms, items_ms, info, batched_res = batched(False, args.chunk, args.wg_per_cu)
-    mixed_ms, mitems_ms, minfo, mixed_res = batched(True, args.chunk, args.wg_per_cu)
+    batched_ms, items_ms, info, batched_res = batched(False, args.chunk)
+    mixed_ms, mitems_ms, minfo, mixed_res = batched(True, args.chunk)
 
     # ---- covariance epilogue (gwf_covariance) on the plain form's Fisher matrices: the
     # paper's worked example (spins fixed, Gaussian priors of variance 2 pi^2 on the
@@ -598,11 +596,11 @@ def main():
                             "invert_ms": round(invert_ms, 4)},
              "batched_fp64": {"events_per_s": round(wl.n / (batched_ms * 1e-3), 1),
                               "ms_per_step": round(batched_ms, 4), "items_ms": round(items_ms, 4),
-                              "chunk": info["chunk"], "wg_per_cu": info["wg_per_cu"],
+                              "chunk": info["chunk"],
                               "n_items": info["n_items"], "graph": True},
              "batched_mixed": {"events_per_s": round(wl.n / (mixed_ms * 1e-3), 1),
                                "ms_per_step": round(mixed_ms, 4), "items_ms": round(mitems_ms, 4),
-                               "chunk": minfo["chunk"], "wg_per_cu": minfo["wg_per_cu"],
+                               "chunk": minfo["chunk"],
                                "n_items": minfo["n_items"], "graph": True}}
     for k, v in errs.items():
         forms[k]["errors_vs_oracle"] = v

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define GWF_VERSION 6
+#define GWF_VERSION 7
 
 /* ------------------------------------------------------------- statuses */
 typedef int32_t gwf_status;
@@ -462,17 +462,17 @@ gwf_status gwf_fisher_basis(int32_t P, int64_t n, const double* fisher, const gw
 /* ------------------------------------------------------ batched form */
 /* A plan runs the Fisher (and optionally the inversion) of one catalogue
  * repeatedly: the work is cut into items of at most `chunk` grid points
- * (events with long grids give several items), persistent workgroups pull
- * items from a device counter, and each event's item sums are combined in
+ * (events with long grids give several items), one workgroup takes each
+ * item (longest items first), and each event's item sums are combined in
  * item order, so results are deterministic and independent of scheduling.
  * The set-up, item, combine and inversion kernels are captured once into a
- * HIP graph and replayed.  This is the batched persistent form of the path
+ * HIP graph and replayed.  This is the batched form of the path
  * for catalogues with uneven grid lengths (the paper's counterpart is its
  * batch/process parallelism over catalogues, sec. 5).
  *
  * gwf_plan_create reads the grid lengths (npts) back to the host and
- * synchronises `stream`; with chunk or wg_per_cu left at 0 it also times
- * the candidate configurations on the given events (autotuning).  The event,
+ * synchronises `stream`; with chunk left at 0 it also times the candidate
+ * item lengths on the given events (autotuning).  The event,
  * grid and network descriptors are captured: later runs read the device
  * arrays at the same addresses, whose values (parameters, fmin, fmax) may
  * change, but the grid lengths may not (an event whose npts differs from
@@ -482,7 +482,6 @@ typedef struct gwf_plan gwf_plan;
 
 typedef struct gwf_plan_options {
   int32_t chunk;       /* points per work item, a multiple of 256; 0 = autotune     */
-  int32_t wg_per_cu;   /* persistent workgroups per compute unit, 1..8; 0 = autotune */
   int32_t use_graph;   /* nonzero: capture and replay a HIP graph                     */
   int32_t profile;     /* nonzero (with use_graph = 0): time the work-item kernel of
                           each run with HIP events on its stream                     */
@@ -490,11 +489,10 @@ typedef struct gwf_plan_options {
                           Cholesky NOT_PD), GWF_INV_CHO_SVD (the paper's default: an
                           SVD where the Cholesky fails, status GWF_EV_SVD) or
                           GWF_INV_CHO_DD (double-double Cholesky); see gwf_covariance */
-  int32_t pad;
 } gwf_plan_options;
 
 typedef struct gwf_plan_info {
-  int32_t chunk, wg_per_cu, n_items, use_graph;
+  int32_t chunk, n_items, use_graph, pad;
   int64_t workspace_bytes;
   double tuned_ms;     /* time of the chosen configuration during autotuning, or 0 */
   double items_ms;     /* with profile: work-item kernel time of the last run (this
@@ -549,7 +547,7 @@ gwf_status gwf_plan_destroy(gwf_plan* plan);
 /* For callers that cannot allocate device memory -- code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc: the
  * batched form of gwf_plan_fisher (work items of at most `chunk` points,
- * persistent workgroups, each event's item sums combined in item order)
+ * one workgroup each, each event's item sums combined in item order)
  * with its workspace in one fixed device array of GWF_STATIC_SCRATCH_BYTES
  * per device, which the library holds from its load until the process ends.
  * The work items are built on the device from the grid lengths, so the call

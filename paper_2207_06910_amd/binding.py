@@ -48,14 +48,13 @@ GRID_LOG, GRID_EXPLICIT = 0, 1
 
 
 class PlanOptions(ctypes.Structure):
-    _fields_ = [("chunk", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("inv_method", ctypes.c_int32), ("pad", ctypes.c_int32)]
+    _fields_ = [("chunk", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("inv_method", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
-    _fields_ = [("chunk", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("n_items", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+    _fields_ = [("chunk", ctypes.c_int32), ("n_items", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_int64), ("tuned_ms", ctypes.c_double),
                 ("items_ms", ctypes.c_double)]
 
@@ -553,17 +552,16 @@ def fisher_static(dw: DeviceWorkload, chunk=4096, npts_max=None, mixed=False, st
 
 
 class Plan:
-    """Batched persistent form (gwf_plan_*): built once for a device-resident
+    """Batched form (gwf_plan_*): built once for a device-resident
     catalogue, then replayed.  Keeps a reference to the DeviceWorkload, whose
     arrays the plan reads at every run."""
 
-    def __init__(self, dw: DeviceWorkload, chunk=0, wg_per_cu=0, use_graph=True, profile=False,
+    def __init__(self, dw: DeviceWorkload, chunk=0, use_graph=True, profile=False,
                  mixed=False, inv_method="cho", stream=None):
         self.dw = dw
         self.handle = ctypes.c_void_p()
         ev, net, grid, keep = dw.descriptors()
-        opt = PlanOptions(int(chunk), int(wg_per_cu), 1 if use_graph else 0, 1 if profile else 0,
-                          INV_METHODS[inv_method], 0)
+        opt = PlanOptions(int(chunk), 1 if use_graph else 0, 1 if profile else 0, INV_METHODS[inv_method])
         _check(load().gwf_plan_create(ctypes.byref(ev), ctypes.byref(net), ctypes.byref(grid),
                                       dw.flags | (MIXED if mixed else 0), ctypes.byref(opt),
                                       ctypes.byref(self.handle),
@@ -573,7 +571,7 @@ class Plan:
     def info(self) -> dict:
         i = PlanInfo()
         _check(load().gwf_plan_get_info(self.handle, ctypes.byref(i)), "gwf_plan_get_info")
-        return {f: getattr(i, f) for f, _ in PlanInfo._fields_}
+        return {f: getattr(i, f) for f, _ in PlanInfo._fields_ if f != "pad"}
 
     def run(self, invert=False, cond_max=1e50, stream=None, out=None):
         import torch

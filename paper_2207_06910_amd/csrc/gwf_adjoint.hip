@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kABlock, 2) void adjoint_kernel(AdjointArgs a) {
   extern __shared__ double accl[];      // [n_site][kSlots][kCols], column tid/2 per lane pair
   __shared__ double site_acc[kMaxSites][kSlots];
   __shared__ int32_t ok;
-  const int64_t e = blockIdx.x;
+  const int64_t e = a.base + blockIdx.x;
   const int tid = threadIdx.x;
   const int n_site = a.net.n_site;
   if (tid == 0) {
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kAIBlock, 2) void adjoint_items_kernel(AdjItemsArgs
   const int width = n_site * kSlots;
   // workgroup b takes item b: the plan orders its items longest first, and
   // workgroups are dispatched in order, so the shortest items come last
-  const Item w = a.items[blockIdx.x];
+  const Item w = a.items[a.base + blockIdx.x];
   const int32_t e = __builtin_amdgcn_readfirstlane(w.e);
   const int32_t k0 = __builtin_amdgcn_readfirstlane(w.k0);
   const int32_t k1 = __builtin_amdgcn_readfirstlane(w.k1);
@@ -287,16 +287,16 @@ void launch_adjoint_items_n(const AdjItemsArgs& a, bool rot, dim3 grid, dim3 blo
   else hipLaunchKernelGGL((adjoint_items_kernel<NPI, false>), grid, block, lds, s, a);
 }
 
-hipError_t launch_adjoint_items(const AdjItemsArgs& a, int npi, bool rot, hipStream_t s) {
-  dim3 grid((unsigned)a.n_items), block(kAIBlock);
-  const size_t lds = sizeof(double) * (size_t)a.net.n_site * kSlots * kAICols;
-  switch (npi) {
-    case 6: launch_adjoint_items_n<6>(a, rot, grid, block, lds, s); break;
-    case 5: launch_adjoint_items_n<5>(a, rot, grid, block, lds, s); break;
-    case 4: launch_adjoint_items_n<4>(a, rot, grid, block, lds, s); break;
-    default: launch_adjoint_items_n<3>(a, rot, grid, block, lds, s);
-  }
-  return hipGetLastError();
+hipError_t launch_adjoint_items(const AdjItemsArgs& a0, int npi, bool rot, hipStream_t s) {
+  const size_t lds = sizeof(double) * (size_t)a0.net.n_site * kSlots * kAICols;
+  return launch_slices(a0, a0.n_items, 1, kAIBlock, [&](const AdjItemsArgs& a, dim3 grid, dim3 block) {
+    switch (npi) {
+      case 6: launch_adjoint_items_n<6>(a, rot, grid, block, lds, s); break;
+      case 5: launch_adjoint_items_n<5>(a, rot, grid, block, lds, s); break;
+      case 4: launch_adjoint_items_n<4>(a, rot, grid, block, lds, s); break;
+      default: launch_adjoint_items_n<3>(a, rot, grid, block, lds, s);
+    }
+  });
 }
 
 hipError_t launch_adjoint_combine(const AdjCombineArgs& a, hipStream_t s) {
@@ -316,20 +316,20 @@ void launch_adjoint_n(const AdjointArgs& a, bool rot, dim3 grid, dim3 block, siz
   else hipLaunchKernelGGL((adjoint_kernel<NPI, false>), grid, block, lds, stream, a);
 }
 
-hipError_t launch_adjoint(const AdjointArgs& a, int npi, bool rot, hipStream_t stream) {
-  dim3 grid((unsigned)a.n), block(kABlock);
-  const size_t lds = sizeof(double) * (size_t)a.net.n_site * kSlots * kCols;
-  switch (npi) {
-    case 6: launch_adjoint_n<6>(a, rot, grid, block, lds, stream); break;
-    case 5: launch_adjoint_n<5>(a, rot, grid, block, lds, stream); break;
-    case 4: launch_adjoint_n<4>(a, rot, grid, block, lds, stream); break;
-    default: launch_adjoint_n<3>(a, rot, grid, block, lds, stream);
-  }
-  hipError_t err = hipGetLastError();
+hipError_t launch_adjoint(const AdjointArgs& a0, int npi, bool rot, hipStream_t stream) {
+  const size_t lds = sizeof(double) * (size_t)a0.net.n_site * kSlots * kCols;
+  hipError_t err = launch_slices(a0, a0.n, 1, kABlock, [&](const AdjointArgs& a, dim3 grid, dim3 block) {
+    switch (npi) {
+      case 6: launch_adjoint_n<6>(a, rot, grid, block, lds, stream); break;
+      case 5: launch_adjoint_n<5>(a, rot, grid, block, lds, stream); break;
+      case 4: launch_adjoint_n<4>(a, rot, grid, block, lds, stream); break;
+      default: launch_adjoint_n<3>(a, rot, grid, block, lds, stream);
+    }
+  });
   if (err != hipSuccess) return err;
-  const int width = a.net.n_site * 4;
-  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)width), block, 0, stream, a.grad_event, a.n, width,
-                     a.grad);
+  const int width = a0.net.n_site * 4;
+  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)width), dim3(kABlock), 0, stream, a0.grad_event, a0.n, width,
+                     a0.grad);
   return hipGetLastError();
 }
 

@@ -3,13 +3,16 @@
 //
 //   setup_kernel    one lane per event (and per event x site): the per-event
 //                   and per-site constants, written once to a workspace.
-//   items_kernel    persistent workgroups pull work items (event, point range
-//                   [k0, k1), at most `chunk` points) from a device counter,
-//                   longest first, and write each item's partial sums to its
+//   items_kernel    one workgroup per work item (event, point range [k0, k1),
+//                   at most `chunk` points), dispatched in the plan's
+//                   longest-first order, writes the item's partial sums to its
 //                   own slot (the item's position in event order), so long
 //                   and short events are spread evenly over the chip, the
 //                   last items to start are the shortest, and the result
-//                   does not depend on which workgroup took which item.  The event's constants are read from the
+//                   does not depend on which workgroup took which item.  (A
+//                   persistent form pulling items from a counter kept more
+//                   values live across its outer loop: more register spills,
+//                   1.7% slower.)  The event's constants are read from the
 //                   workspace through the constant address space, i.e. by
 //                   scalar loads into SGPRs, which costs neither LDS traffic
 //                   nor vector registers.
@@ -49,43 +52,40 @@ __global__ void setup_kernel(SetupArgs a) {
     }
 }
 
-template <int NPI, bool ROT, bool MIXED>
+template <int NPI, bool ROT, bool MIXED, bool TAB>
 __global__ __launch_bounds__(FisherDims<NPI>::TIDAL ? 2 * kBlock : kBlock) void items_kernel(ItemsArgs a) {
   using Dm = FisherDims<NPI>;
   constexpr int NACC = Dm::NACC;
   __shared__ FisherLds L;
-  __shared__ int32_t item;
   const int tid = threadIdx.x;
   const int n_site = a.n_site;
+  // workgroup b takes item b (the plan orders its items longest first, and
+  // workgroups are dispatched in order); with the count on the device, the
+  // grid is its upper bound and the surplus workgroups leave
   const int32_t n_items = a.n_items_dev ? *a.n_items_dev : a.n_items;
-  for (;;) {
-    if (tid == 0) item = atomicAdd(a.counter, 1);
-    __syncthreads();
-    const int32_t it = item;
-    if (it >= n_items) break;                    // every wave leaves on the same item count
-    const Item w = a.items[__builtin_amdgcn_readfirstlane(it)];
-    const int32_t ew = __builtin_amdgcn_readfirstlane(w.e);
-    const int32_t k0 = __builtin_amdgcn_readfirstlane(w.k0);
-    const int32_t k1 = __builtin_amdgcn_readfirstlane(w.k1);
-    // constants read through the constant address space: uniform, never
-    // written during the kernel, so the compiler may use scalar loads
-    typedef const __attribute__((address_space(4))) EventC CEventC;
-    typedef const __attribute__((address_space(4))) SiteC CSiteC;
-    CEventC* ecp = (CEventC*)(a.evc) + ew;
-    CSiteC* scp = (CSiteC*)(a.sic) + (int64_t)ew * n_site;
-    const EventC& ecg = *(const EventC*)ecp;
-    const SiteC* scg = (const SiteC*)scp;
-    double* out = a.partial + (int64_t)__builtin_amdgcn_readfirstlane(w.slot) * NACC;
-    if (ecg.status) {
-      if (tid < NACC) out[tid] = 0.0;
-    } else {
-      double t = 0.0;
-      // both forms: PN series as sums of products over shared powers and the
-      // PSD power law once per point (in FP32 for the mixed form)
-      fisher_sums<NPI, ROT, MIXED, true>(ecg, scg, n_site, k0, k1, L, &t);
-      if (tid < NACC) out[tid] = t;
-    }
-    __syncthreads();                             // LDS is reused by the next item
+  const int64_t it = a.base + blockIdx.x;
+  if (it >= n_items) return;
+  const Item w = a.items[it];
+  const int32_t ew = __builtin_amdgcn_readfirstlane(w.e);
+  const int32_t k0 = __builtin_amdgcn_readfirstlane(w.k0);
+  const int32_t k1 = __builtin_amdgcn_readfirstlane(w.k1);
+  // constants read through the constant address space: uniform, never
+  // written during the kernel, so the compiler may use scalar loads
+  typedef const __attribute__((address_space(4))) EventC CEventC;
+  typedef const __attribute__((address_space(4))) SiteC CSiteC;
+  CEventC* ecp = (CEventC*)(a.evc) + ew;
+  CSiteC* scp = (CSiteC*)(a.sic) + (int64_t)ew * n_site;
+  const EventC& ecg = *(const EventC*)ecp;
+  const SiteC* scg = (const SiteC*)scp;
+  double* out = a.partial + (int64_t)__builtin_amdgcn_readfirstlane(w.slot) * NACC;
+  if (ecg.status) {
+    if (tid < NACC) out[tid] = 0.0;
+  } else {
+    double t = 0.0;
+    // both forms: PN series as sums of products over shared powers and the
+    // PSD power law once per point (in FP32 for the mixed form)
+    fisher_sums<NPI, ROT, MIXED, true, false, TAB>(ecg, scg, n_site, k0, k1, L, &t);
+    if (tid < NACC) out[tid] = t;
   }
 }
 
@@ -93,7 +93,7 @@ template <int NPI_>
 __global__ void combine_kernel(CombineArgs a) {
   using Dm = FisherDims<NPI_>;
   constexpr int P = Dm::P, NPI = Dm::NPI, NACC = Dm::NACC;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = a.base + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.n * NACC) return;
   const int64_t e = t / NACC;
   const int slot = (int)(t - e * NACC);
@@ -187,26 +187,28 @@ hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
 }
 
 template <int NPI, bool MIXED>
-void launch_items_n(const ItemsArgs& a, bool rot, dim3 grid, dim3 block, hipStream_t s) {
-  if (rot) hipLaunchKernelGGL((items_kernel<NPI, true, MIXED>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((items_kernel<NPI, false, MIXED>), grid, block, 0, s, a);
+void launch_items_n(const ItemsArgs& a, bool rot, bool tab, dim3 grid, dim3 block, hipStream_t s) {
+  if (rot && tab) hipLaunchKernelGGL((items_kernel<NPI, true, MIXED, true>), grid, block, 0, s, a);
+  else if (rot) hipLaunchKernelGGL((items_kernel<NPI, true, MIXED, false>), grid, block, 0, s, a);
+  else if (tab) hipLaunchKernelGGL((items_kernel<NPI, false, MIXED, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((items_kernel<NPI, false, MIXED, false>), grid, block, 0, s, a);
 }
 
 template <bool MIXED>
-void launch_items_t(const ItemsArgs& a, int npi, bool rot, dim3 grid, dim3 block, hipStream_t s) {
+void launch_items_t(const ItemsArgs& a, int npi, bool rot, bool tab, dim3 grid, dim3 block, hipStream_t s) {
   switch (npi) {
-    case 6: launch_items_n<6, MIXED>(a, rot, grid, block, s); break;
-    case 5: launch_items_n<5, MIXED>(a, rot, grid, block, s); break;
-    case 4: launch_items_n<4, MIXED>(a, rot, grid, block, s); break;
-    default: launch_items_n<3, MIXED>(a, rot, grid, block, s);
+    case 6: launch_items_n<6, MIXED>(a, rot, tab, grid, block, s); break;
+    case 5: launch_items_n<5, MIXED>(a, rot, tab, grid, block, s); break;
+    case 4: launch_items_n<4, MIXED>(a, rot, tab, grid, block, s); break;
+    default: launch_items_n<3, MIXED>(a, rot, tab, grid, block, s);
   }
 }
 
-hipError_t launch_items(const ItemsArgs& a, int npi, bool rot, bool mixed, int n_wg, hipStream_t s) {
-  dim3 grid((unsigned)n_wg), block(kBlock);
-  if (mixed) launch_items_t<true>(a, npi, rot, grid, block, s);
-  else launch_items_t<false>(a, npi, rot, grid, block, s);
-  return hipGetLastError();
+hipError_t launch_items(const ItemsArgs& a0, int npi, bool rot, bool mixed, bool tab, int64_t n_wg, hipStream_t s) {
+  return launch_slices(a0, n_wg, 1, kBlock, [&](const ItemsArgs& a, dim3 grid, dim3 block) {
+    if (mixed) launch_items_t<true>(a, npi, rot, tab, grid, block, s);
+    else launch_items_t<false>(a, npi, rot, tab, grid, block, s);
+  });
 }
 
 int fisher_nacc(int npi) {
@@ -218,38 +220,15 @@ int fisher_nacc(int npi) {
   }
 }
 
-hipError_t launch_combine(const CombineArgs& a, int npi, hipStream_t s) {
-  const int64_t threads = a.n * fisher_nacc(npi);
-  dim3 grid((unsigned)((threads + 255) / 256)), block(256);
-  switch (npi) {
-    case 6: hipLaunchKernelGGL((combine_kernel<6>), grid, block, 0, s, a); break;
-    case 5: hipLaunchKernelGGL((combine_kernel<5>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((combine_kernel<4>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((combine_kernel<3>), grid, block, 0, s, a);
-  }
-  return hipGetLastError();
-}
-
-template <int NPI, bool MIXED>
-int items_resident_n(bool rot) {
-  int nb = 0;
-  const hipError_t err = rot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, items_kernel<NPI, true, MIXED>, kBlock, 0)
-                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, items_kernel<NPI, false, MIXED>, kBlock, 0);
-  return err == hipSuccess ? nb : 0;
-}
-
-template <bool MIXED>
-int items_resident_t(int npi, bool rot) {
-  switch (npi) {
-    case 6: return items_resident_n<6, MIXED>(rot);
-    case 5: return items_resident_n<5, MIXED>(rot);
-    case 4: return items_resident_n<4, MIXED>(rot);
-    default: return items_resident_n<3, MIXED>(rot);
-  }
-}
-
-int items_max_resident(int npi, bool rot, bool mixed) {
-  return mixed ? items_resident_t<true>(npi, rot) : items_resident_t<false>(npi, rot);
+hipError_t launch_combine(const CombineArgs& a0, int npi, hipStream_t s) {
+  return launch_slices(a0, a0.n * fisher_nacc(npi), 256, 256, [&](const CombineArgs& a, dim3 grid, dim3 block) {
+    switch (npi) {
+      case 6: hipLaunchKernelGGL((combine_kernel<6>), grid, block, 0, s, a); break;
+      case 5: hipLaunchKernelGGL((combine_kernel<5>), grid, block, 0, s, a); break;
+      case 4: hipLaunchKernelGGL((combine_kernel<4>), grid, block, 0, s, a); break;
+      default: hipLaunchKernelGGL((combine_kernel<3>), grid, block, 0, s, a);
+    }
+  });
 }
 
 int fisher_block() { return kBlock; }

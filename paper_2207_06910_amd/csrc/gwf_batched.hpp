@@ -33,11 +33,11 @@ struct ItemsArgs {
   const EventC* evc;
   const SiteC* sic;
   int32_t n_site;
-  const Item* items;
+  const Item* items;          // one workgroup per item, in this order
   int32_t n_items;
   const int32_t* n_items_dev; // NULL, or the item count in device memory (read in place of n_items)
-  int32_t* counter;           // work-item counter, zeroed before the launch
   double* partial;            // [n_items][NACC]
+  int64_t base;               // first item of the launch (set by the launcher)
 };
 
 struct CombineArgs {
@@ -49,6 +49,7 @@ struct CombineArgs {
   double* snr;                // [n]
   int32_t* status;            // [n]
   const uint32_t* par_mask;   // [n] or NULL: rows of each event's Fisher matrix (others 0)
+  int64_t base;               // first (event, slot) pair of the launch (set by the launcher)
 };
 
 // The adjoint over work items (gwf_plan_adjoint): one workgroup per item of
@@ -67,6 +68,7 @@ struct AdjItemsArgs {
   const Item* items;          // one workgroup per item, in this order
   int32_t n_items;
   double* partial;            // [n_items][n_site][8]; NaN where the event is left out
+  int64_t base;               // first item of the launch (set by the launcher)
 };
 
 struct AdjCombineArgs {
@@ -92,12 +94,10 @@ hipError_t launch_items_build(const int32_t* npts, int64_t n, int32_t chunk, int
                               int32_t* n_items, Item* items, hipStream_t s);
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
 // npi: phase-only parameters, 3 + 2 (tides) + 1 (eccentricity)
-hipError_t launch_items(const ItemsArgs& a, int npi, bool rot, bool mixed, int n_wg, hipStream_t s);
+// tab: a site has a sampled noise curve; n_wg: the number of items (or a bound)
+hipError_t launch_items(const ItemsArgs& a, int npi, bool rot, bool mixed, bool tab, int64_t n_wg, hipStream_t s);
 hipError_t launch_combine(const CombineArgs& a, int npi, hipStream_t s);
 int fisher_nacc(int npi);
-// Work-item workgroups that one compute unit holds at once (registers and
-// LDS of the instantiation), 0 if the runtime cannot tell.
-int items_max_resident(int npi, bool rot, bool mixed);
 int fisher_block();
 
 }  // namespace gwf

@@ -32,7 +32,7 @@ namespace gwf {
 // transcendental sequences.
 // (The P = 11 instantiation keeps the one-wavefront budget: under the
 // two-wavefront cap it spills.)
-template <int NPI_, bool ROT, bool EXPL>
+template <int NPI_, bool ROT, bool EXPL, bool TAB>
 __global__ __launch_bounds__(FisherDims<NPI_>::TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(FisherArgs a) {
   using Dm = FisherDims<NPI_>;
   using PO = PhaseOnly<NPI_>;
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(FisherDims<NPI_>::TIDAL ? 2 * kBlock : kBlock) void
   __shared__ FisherLds L;
   __shared__ int32_t skip, bad;
 
-  const int64_t e = blockIdx.x;
+  const int64_t e = a.base + blockIdx.x;
   const int tid = threadIdx.x;
   const int n_site = a.net.n_site;
   double p[kNparIn];
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(FisherDims<NPI_>::TIDAL ? 2 * kBlock : kBlock) void
   __syncthreads();
 
   double t = 0.0;
-  fisher_sums<NPI, ROT, false, true, EXPL>(ec, sc, n_site, 0, ec.n, L, &t);
+  fisher_sums<NPI, ROT, false, true, EXPL, TAB>(ec, sc, n_site, 0, ec.n, L, &t);
   if (tid < NACC) {
     int r, c;
     slot_position(tid, NPI, r, c);
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void snr_kernel(SnrArgs a) {
   __shared__ EventC ec;
   __shared__ SiteC sc[kMaxSites];
   __shared__ double red[kWaves][kMaxIfo + 1];
-  const int64_t e = blockIdx.x;
+  const int64_t e = a.base + blockIdx.x;
   const int tid = threadIdx.x;
   const int n_site = a.net.n_site;
   double p[kNparIn];
@@ -180,8 +180,11 @@ __global__ __launch_bounds__(kBlock) void snr_kernel(SnrArgs a) {
 
 template <int NPI, bool EXPL>
 void launch_fisher_n(const FisherArgs& a, bool rot, dim3 grid, dim3 block, hipStream_t stream) {
-  if (rot) hipLaunchKernelGGL((fisher_kernel<NPI, true, EXPL>), grid, block, 0, stream, a);
-  else hipLaunchKernelGGL((fisher_kernel<NPI, false, EXPL>), grid, block, 0, stream, a);
+  const bool tab = net_has_tables(a.net);
+  if (rot && tab) hipLaunchKernelGGL((fisher_kernel<NPI, true, EXPL, true>), grid, block, 0, stream, a);
+  else if (rot) hipLaunchKernelGGL((fisher_kernel<NPI, true, EXPL, false>), grid, block, 0, stream, a);
+  else if (tab) hipLaunchKernelGGL((fisher_kernel<NPI, false, EXPL, true>), grid, block, 0, stream, a);
+  else hipLaunchKernelGGL((fisher_kernel<NPI, false, EXPL, false>), grid, block, 0, stream, a);
 }
 
 template <bool EXPL>
@@ -195,23 +198,23 @@ void launch_fisher_t(const FisherArgs& a, int npi, bool rot, dim3 grid, dim3 blo
 }
 
 // An explicit grid (a.gf set) selects the instantiations that read it.
-hipError_t launch_fisher(const FisherArgs& a, int npi, bool rot, hipStream_t stream) {
-  dim3 grid((unsigned)a.n), block(kBlock);
-  if (a.gf) launch_fisher_t<true>(a, npi, rot, grid, block, stream);
-  else launch_fisher_t<false>(a, npi, rot, grid, block, stream);
-  return hipGetLastError();
+hipError_t launch_fisher(const FisherArgs& a0, int npi, bool rot, hipStream_t stream) {
+  return launch_slices(a0, a0.n, 1, kBlock, [&](const FisherArgs& a, dim3 grid, dim3 block) {
+    if (a.gf) launch_fisher_t<true>(a, npi, rot, grid, block, stream);
+    else launch_fisher_t<false>(a, npi, rot, grid, block, stream);
+  });
 }
 
-hipError_t launch_snr(const SnrArgs& a, bool rot, hipStream_t stream) {
-  dim3 grid((unsigned)a.n), block(kBlock);
-  if (a.gf) {
-    if (rot) hipLaunchKernelGGL((snr_kernel<true, true>), grid, block, 0, stream, a);
-    else hipLaunchKernelGGL((snr_kernel<false, true>), grid, block, 0, stream, a);
-  } else {
-    if (rot) hipLaunchKernelGGL((snr_kernel<true, false>), grid, block, 0, stream, a);
-    else hipLaunchKernelGGL((snr_kernel<false, false>), grid, block, 0, stream, a);
-  }
-  return hipGetLastError();
+hipError_t launch_snr(const SnrArgs& a0, bool rot, hipStream_t stream) {
+  return launch_slices(a0, a0.n, 1, kBlock, [&](const SnrArgs& a, dim3 grid, dim3 block) {
+    if (a.gf) {
+      if (rot) hipLaunchKernelGGL((snr_kernel<true, true>), grid, block, 0, stream, a);
+      else hipLaunchKernelGGL((snr_kernel<false, true>), grid, block, 0, stream, a);
+    } else {
+      if (rot) hipLaunchKernelGGL((snr_kernel<true, false>), grid, block, 0, stream, a);
+      else hipLaunchKernelGGL((snr_kernel<false, false>), grid, block, 0, stream, a);
+    }
+  });
 }
 
 }  // namespace gwf

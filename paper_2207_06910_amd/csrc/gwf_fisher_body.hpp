@@ -78,7 +78,7 @@ __device__ inline void load_par(const double* __restrict__ par, int64_t ld, int6
 // Sums of points [k0, k1) of the event whose constants are ec/sc.  On
 // return (after a workgroup barrier), lane t < NACC holds accumulator slot t
 // (see slot_position) in *tot.
-template <int NPI_, bool ROT, bool MIXED = false, bool PSUM = true, bool EXPL = false>
+template <int NPI_, bool ROT, bool MIXED = false, bool PSUM = true, bool EXPL = false, bool TAB = true>
 __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site, int k0, int k1,
                                    FisherLds& L, double* tot) {
   using Dm = FisherDims<NPI_>;
@@ -121,7 +121,7 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
     for (int b = 0; b < 8; ++b) U[b] = 0.0;
 #pragma unroll
     for (int i = 0; i < NPI; ++i) cph[i] = 0.0;
-    if (k < k1) accumulate_point<NPI, ROT, MIXED, PSUM, EXPL>(ec, sc, n_site, k, G, U, W, cph);
+    if (k < k1) accumulate_point<NPI, ROT, MIXED, PSUM, EXPL, TAB>(ec, sc, n_site, k, G, U, W, cph);
     // stage this point's row (points past the range contribute zeros)
 #pragma unroll
     for (int b = 0; b < 8; ++b) A[b][lane] = U[b];

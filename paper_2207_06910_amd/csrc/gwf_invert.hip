@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
   __shared__ double Ls[kGroups][P][LD];
   const int lane = threadIdx.x;
   const int g = lane / kGroup, j = lane % kGroup;
-  const int64_t e = xcd_block(blockIdx.x, gridDim.x) * kGroups + g;
+  const int64_t e = a.base + xcd_block(blockIdx.x, gridDim.x) * kGroups + g;
   const bool live = e < a.n;
   const bool own = live && j < P;          // lane owns a column of a real matrix
   const double nan = __builtin_nan("");
@@ -556,9 +556,9 @@ hipError_t launch_p(const InvertArgs& a0, hipStream_t stream) {
     a.i_theta = a.i_phi = -1;
     a.sky = nullptr;
   }
-  const unsigned blocks = (unsigned)((a.n + kGroups - 1) / kGroups);
-  hipLaunchKernelGGL((invert_kernel<P>), dim3(blocks), dim3(kInvBlock), 0, stream, a);
-  return hipGetLastError();
+  return launch_slices(a, a.n, kGroups, kInvBlock, [&](const InvertArgs& s, dim3 grid, dim3 block) {
+    hipLaunchKernelGGL((invert_kernel<P>), grid, block, 0, stream, s);
+  });
 }
 
 }  // namespace

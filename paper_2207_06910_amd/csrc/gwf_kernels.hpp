@@ -1,9 +1,27 @@
 // gwf_kernels.hpp -- kernel argument blocks and launchers of libgwf.
 #pragma once
 
+#include <algorithm>
+
 #include "gwf_model.hpp"
 
 namespace gwf {
+
+// A launch counts its work-items in 32 bits, so kernels with one workgroup
+// per event (or per work item, or per few matrices) go out in slices of at
+// most 2^31 work-items; each slice's kernel adds its first unit, `base`.
+template <class Args, class Launch>
+hipError_t launch_slices(Args a, int64_t units, int64_t units_per_wg, unsigned block, Launch&& launch) {
+  const int64_t max_wg = (int64_t(1) << 31) / block;
+  const int64_t wgs = (units + units_per_wg - 1) / units_per_wg;
+  for (int64_t b = 0; b < wgs; b += max_wg) {
+    a.base = b * units_per_wg;
+    launch(a, dim3((unsigned)std::min(max_wg, wgs - b)), dim3(block));
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
 
 struct FisherArgs {
   const double* par;
@@ -24,6 +42,7 @@ struct FisherArgs {
   double* fisher;           // [P][P][n]
   double* snr;              // [n] or NULL
   int32_t* status;          // [n]
+  int64_t base;             // first event of the launch (set by the launcher)
 };
 
 struct SnrArgs {
@@ -40,6 +59,7 @@ struct SnrArgs {
   double* snr;              // [n]
   double* snr_ifo;          // [n_ifo][n] or NULL
   int32_t* status;          // [n] or NULL
+  int64_t base;             // first event of the launch (set by the launcher)
 };
 
 struct InvertArgs {
@@ -75,6 +95,7 @@ struct InvertArgs {
   // kept parameter outside it is replaced by a unit row and column, and its
   // covariance row and column are written as 0, its sigma as NaN
   const uint32_t* par_mask;
+  int64_t base;             // first matrix of the launch (set by the launcher)
 };
 
 struct BasisArgs {
@@ -106,6 +127,7 @@ struct WaveformArgs {
   int32_t* status;          // [n] or NULL
   double* dh;               // derivative kernel: [P][n_ifo][total] complex
   const uint32_t* par_mask; // derivative kernel: [n] or NULL, rows outside an event's set are 0
+  int64_t base;             // first event of the launch (set by the launcher)
 };
 
 struct AdjointArgs {
@@ -124,6 +146,7 @@ struct AdjointArgs {
   double w_snr, w_fisher;
   double* grad_event;       // [n][n_site][4]
   double* grad;             // [n_site][4]
+  int64_t base;             // first event of the launch (set by the launcher)
 };
 
 // npi: phase-only parameters, 3 + 2 (tides) + 1 (eccentricity)

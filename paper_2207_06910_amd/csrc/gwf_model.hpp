@@ -148,6 +148,14 @@ struct NetDesc {
   int32_t n_site, n_ifo;
 };
 
+// Whether any site of the network has a sampled noise curve (the kernels
+// without one leave the check out).
+__host__ __device__ inline bool net_has_tables(const NetDesc& nd) {
+  for (int s = 0; s < nd.n_site; ++s)
+    if (nd.site[s].psd_kind != 0) return true;
+  return false;
+}
+
 // ------------------------------------------------ per-event coefficients
 // Coefficients a_k (k = 0..7), b_5, b_6 (ln v parts) and tidal a_10, a_12 of
 // the TaylorF2 phase Psi_PN = 3/(128 eta) v^-5 sum_k (a_k + b_k ln v) v^k,
@@ -859,9 +867,11 @@ __host__ __device__ inline double table_weight(const double* __restrict__ tf, co
   return w4A2 * S0inv / fma(t, s1 - s0, s0);
 }
 
-template <bool PSUM = true>
+// TAB = false: instantiations for networks without sampled curves, which
+// leave the check out of the per-point code.
+template <bool PSUM = true, bool TAB = true>
 __host__ __device__ inline void psd_weight(const SiteC& sc, const Point& q, double& om) {
-  if (sc.tab_kind) om = table_weight(sc.tab_f, sc.tab_S, sc.tab_n, sc.tab_kind, sc.S0inv, q.w4A2, q.f);
+  if (TAB && sc.tab_kind) om = table_weight(sc.tab_f, sc.tab_S, sc.tab_n, sc.tab_kind, sc.S0inv, q.w4A2, q.f);
   else om = psd_weight_of<PSUM>(sc.xp_fac, sc.lnx_off, sc.ix_fac, sc.x_fac, sc.S0inv, q);
 }
 
@@ -877,8 +887,9 @@ __host__ __device__ inline void psd_weight(const SiteC& sc, const Point& q, doub
 // |r| <= 1/2; x^2 and x^-2 are FP64 products rounded once; the quotient uses
 // the FP32 reciprocal.  Measured: 1.2e-8 of sqrt(Gamma_aa Gamma_bb) on the
 // BNS catalogue.
+template <bool TAB = true>
 __host__ __device__ inline void psd_weight_f32(const SiteC& sc, const Point& q, double& om) {
-  if (sc.tab_kind) {   // a sampled curve: the FP64 weight
+  if (TAB && sc.tab_kind) {   // a sampled curve: the FP64 weight
     om = table_weight(sc.tab_f, sc.tab_S, sc.tab_n, sc.tab_kind, sc.S0inv, q.w4A2, q.f);
     return;
   }
@@ -892,7 +903,7 @@ __host__ __device__ inline void psd_weight_f32(const SiteC& sc, const Point& q, 
   om = q.w4A2 * sc.S0inv * (double)(den * recipf(top));
 }
 
-template <bool MIXED = false, bool PSUM = true>
+template <bool MIXED = false, bool PSUM = true, bool TAB = true>
 __host__ __device__ inline void site_point(const SiteC& sc, const Point& q, bool need_derivs,
                                            SitePoint& sp) {
   const double cH = q.cth * sc.cdl - q.sth * sc.sdl;
@@ -902,8 +913,8 @@ __host__ __device__ inline void site_point(const SiteC& sc, const Point& q, bool
   sp.P[1] = EX * NX - EY * NY;
   sp.P[2] = EX * EY - NX * NY;
   sp.P[3] = EX * NY + NX * EY;
-  if (MIXED) psd_weight_f32(sc, q, sp.om);
-  else psd_weight<PSUM>(sc, q, sp.om);
+  if (MIXED) psd_weight_f32<TAB>(sc, q, sp.om);
+  else psd_weight<PSUM, TAB>(sc, q, sp.om);
   if (!need_derivs) return;
   const double EXh = -sH, EYh = -sc.ct * cH, NXh = -sc.sl * cH, NYh = sc.slct * sH;
   sp.PH[0] = EX * EXh - NX * NXh - EY * EYh + NY * NYh;
@@ -1000,7 +1011,7 @@ constexpr int kGramRows[5] = {0, 1, 3, 4, 7};   // Mc, eta, theta, phi, tc
 // dL, iota, psi follow from the point's moments S as well: U_dL = 0
 // exactly, U_iota = (c+ dcx - cx dc+) S_+x, U_psi = -2 c+ cx (S_++ + S_xx),
 // W = c+^2 S_++ + cx^2 S_xx.
-template <int NPI, bool ROT, bool MIXED = false, bool PSUM = true, bool EXPL = false>
+template <int NPI, bool ROT, bool MIXED = false, bool PSUM = true, bool EXPL = false, bool TAB = true>
 __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* sc, int n_site,
                                                  int32_t k, double* G, double* U, double& W,
                                                  double* cph) {
@@ -1013,7 +1024,7 @@ __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* 
   for (int s = 0; s < n_site; ++s) {
     const SiteC& st = sc[s];
     SitePoint sp;
-    site_point<MIXED, PSUM>(st, q, true, sp);
+    site_point<MIXED, PSUM, TAB>(st, q, true, sp);
     const SitePhase ph = site_phase(q, sp);
     // at most two effective interferometers per site; the count is the same
     // for every lane, so the second pass is skipped as a whole where unused

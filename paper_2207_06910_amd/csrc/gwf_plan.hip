@@ -1,6 +1,6 @@
 // gwf_plan.hip -- host side of the batched form (gwf_plan_* in include/gwf.h):
-// work-item tables, workspace, autotuning of the item length and of the
-// number of persistent workgroups, and capture/replay of the whole
+// work-item tables, workspace, autotuning of the item length, and
+// capture/replay of the whole
 // set-up -> items -> combine (-> inversion) sequence as one HIP graph.
 #include <hip/hip_runtime.h>
 
@@ -24,11 +24,11 @@ struct gwf_plan {
   NetDesc net{};
   uint32_t flags = 0;
   int64_t n = 0;
-  int P = 0, npi = 3, nacc = 0, n_cu = 0, n_site_alloc = 0;
-  bool tidal = false, rot = false, mixed = false;
+  int P = 0, npi = 3, nacc = 0, n_site_alloc = 0;
+  bool tidal = false, rot = false, mixed = false, tab = false;
   std::vector<int32_t> npts_host;
   // tuning
-  int chunk = 0, wg_per_cu = 0, n_items = 0;
+  int chunk = 0, n_items = 0;
   bool use_graph = true;
   int32_t inv_method = GWF_INV_CHO;
   double tuned_ms = 0.0;
@@ -39,7 +39,6 @@ struct gwf_plan {
   Item* items = nullptr;
   int32_t* item_first = nullptr;
   double* partial = nullptr;
-  int32_t* counter = nullptr;
   size_t items_cap = 0;
   int64_t workspace_bytes = 0;
   // graph cache, keyed by the output pointers of the last replay
@@ -122,15 +121,13 @@ gwf_status enqueue(gwf_plan* p, const Outs& o, hipStream_t s) {
   sa.net = p->net; sa.flags = p->flags; sa.evc = p->evc; sa.sic = p->sic; sa.status = o.status;
   sa.active = p->ev.active;
   hipError_t err = launch_setup(sa, s);
-  if (err == hipSuccess) err = launch_fill_i32(p->counter, 0, 1, s);
   if (err == hipSuccess) {
     ItemsArgs ia{};
     ia.evc = p->evc; ia.sic = p->sic; ia.n_site = p->net.n_site; ia.items = p->items;
-    ia.n_items = p->n_items; ia.counter = p->counter; ia.partial = p->partial;
-    const int n_wg = std::max(1, std::min(p->n_items, p->n_cu * p->wg_per_cu));
+    ia.n_items = p->n_items; ia.partial = p->partial;
     const bool timed = p->profile && p->ev0;
     if (timed) (void)hipEventRecord(p->ev0, s);
-    err = launch_items(ia, p->npi, p->rot, p->mixed, n_wg, s);
+    err = launch_items(ia, p->npi, p->rot, p->mixed, p->tab, p->n_items, s);
     if (timed) (void)hipEventRecord(p->ev1, s);
   }
   if (err == hipSuccess) {
@@ -173,7 +170,7 @@ void free_plan(gwf_plan* p) {
   if (p->ev0) (void)hipEventDestroy(p->ev0);
   if (p->ev1) (void)hipEventDestroy(p->ev1);
   for (void* q : {(void*)p->evc, (void*)p->sic, (void*)p->npts_plan, (void*)p->items, (void*)p->item_first,
-                  (void*)p->partial, (void*)p->counter})
+                  (void*)p->partial})
     (void)hipFree(q);
   delete p;
 }
@@ -199,7 +196,6 @@ gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const g
     delete p;
     return api_fail(GWF_E_INVALID_ARG, "chunk=%d must be a non-negative multiple of %d", o.chunk, fisher_block());
   }
-  if (o.wg_per_cu < 0 || o.wg_per_cu > 8) { delete p; return api_fail(GWF_E_INVALID_ARG, "wg_per_cu=%d outside 0..8", o.wg_per_cu); }
   if (o.inv_method != GWF_INV_CHO && o.inv_method != GWF_INV_CHO_SVD && o.inv_method != GWF_INV_CHO_DD) {
     delete p;
     return api_fail(GWF_E_INVALID_ARG, "inv_method=%d: plans invert by GWF_INV_CHO, GWF_INV_CHO_SVD or GWF_INV_CHO_DD",
@@ -209,6 +205,7 @@ gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const g
   p->tidal = (flags & GWF_TIDAL) != 0;
   p->rot = (flags & GWF_EARTH_ROT) != 0;
   p->mixed = (flags & GWF_MIXED) != 0;
+  p->tab = net_has_tables(p->net);
   p->npi = api_npi(flags);
   p->P = 8 + p->npi;
   p->nacc = fisher_nacc(p->npi);
@@ -219,9 +216,6 @@ gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const g
     return api_fail(GWF_E_INVALID_ARG, "profile needs use_graph = 0 (kernels launched directly)");
   }
   hipStream_t s = (hipStream_t)stream;
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   hipError_t err;
   // grid lengths are fixed for the life of the plan
   p->npts_host.resize(p->n);
@@ -235,8 +229,7 @@ gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const g
   if ((err = dev_alloc(&p->evc, p->n, total)) != hipSuccess ||
       (err = dev_alloc(&p->sic, p->n * p->net.n_site, total)) != hipSuccess ||
       (err = dev_alloc(&p->npts_plan, p->n, total)) != hipSuccess ||
-      (err = dev_alloc(&p->item_first, p->n + 1, total)) != hipSuccess ||
-      (err = dev_alloc(&p->counter, 1, total)) != hipSuccess) {
+      (err = dev_alloc(&p->item_first, p->n + 1, total)) != hipSuccess) {
     free_plan(p);
     return api_fail(GWF_E_NOMEM, "plan workspace: %s", hipGetErrorString(err));
   }
@@ -244,24 +237,11 @@ gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const g
     free_plan(p);
     return api_hip_fail(err, "grid-length upload");
   }
-  // candidates
+  // candidate item lengths
   std::vector<int> chunks = o.chunk ? std::vector<int>{o.chunk} : std::vector<int>{2048, 4096, 8192, 16384};
-  // workgroups per CU: the candidates are those a compute unit can hold at
-  // once (its registers and LDS), so every persistent workgroup starts at the
-  // launch; a larger wg_per_cu given by the caller is honoured (the surplus
-  // workgroups start as others leave)
-  std::vector<int> wgs;
-  if (o.wg_per_cu) {
-    wgs.push_back(o.wg_per_cu);
-  } else {
-    const int res = items_max_resident(p->npi, p->rot, p->mixed);
-    for (int w = 1; w <= 4; ++w)
-      if (w <= std::max(1, res)) wgs.push_back(w);
-    if (wgs.size() > 2) wgs.erase(wgs.begin(), wgs.end() - 2);   // the two largest
-  }
-  int best_c = chunks[0], best_w = wgs[0];
+  int best_c = chunks[0];
   double best = 0.0;
-  if (chunks.size() * wgs.size() > 1) {
+  if (chunks.size() > 1) {
     double *tf = nullptr, *ts = nullptr;
     int32_t* tst = nullptr;
     int64_t dummy = 0;
@@ -275,16 +255,12 @@ gwf_status gwf_plan_create(const gwf_events* ev, const gwf_network* net, const g
     best = 1e300;
     for (int c : chunks) {
       if ((st = set_items(p, c))) { (void)hipFree(tf); (void)hipFree(ts); (void)hipFree(tst); free_plan(p); return st; }
-      for (int w : wgs) {
-        p->wg_per_cu = w;
-        const double ms = time_config(p, to, s);
-        if (ms < best) { best = ms; best_c = c; best_w = w; }
-      }
+      const double ms = time_config(p, to, s);
+      if (ms < best) { best = ms; best_c = c; }
     }
     (void)hipFree(tf); (void)hipFree(ts); (void)hipFree(tst);
   }
   if ((st = set_items(p, best_c))) { free_plan(p); return st; }
-  p->wg_per_cu = best_w;
   p->tuned_ms = best;
   if (o.profile) {
     if ((err = hipEventCreate(&p->ev0)) != hipSuccess || (err = hipEventCreate(&p->ev1)) != hipSuccess) {
@@ -341,6 +317,7 @@ gwf_status gwf_plan_set_network(gwf_plan* p, const gwf_network* net) {
   if (nd.n_site > p->n_site_alloc)
     return api_fail(GWF_E_INVALID_ARG, "%d sites: the plan holds site constants for %d", nd.n_site, p->n_site_alloc);
   p->net = nd;
+  p->tab = net_has_tables(nd);
   if (p->exec) {                    // the captured graph holds the old network
     (void)hipGraphExecDestroy(p->exec);
     p->exec = nullptr;
@@ -385,8 +362,8 @@ gwf_status gwf_plan_adjoint(gwf_plan* p, const double* gbar, const int32_t* stat
 gwf_status gwf_plan_get_info(const gwf_plan* p, gwf_plan_info* info) {
   if (!p || !info) return api_fail(GWF_E_INVALID_ARG, "plan or info is NULL");
   info->chunk = p->chunk;
-  info->wg_per_cu = p->wg_per_cu;
   info->n_items = p->n_items;
+  info->pad = 0;
   info->use_graph = p->use_graph ? 1 : 0;
   info->workspace_bytes = p->workspace_bytes;
   info->tuned_ms = p->tuned_ms;

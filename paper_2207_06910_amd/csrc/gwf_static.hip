@@ -1,15 +1,16 @@
 // gwf_static.hip -- gwf_fisher_static: the batched form of the Fisher/SNR
-// path (work items of at most `chunk` points pulled by persistent
-// workgroups, partial sums combined per event in item order) for callers
-// that cannot allocate device memory.  Its workspace -- the per-event and
-// per-site constants, the work items, their partial sums and the item
-// counter -- lives in one file-scope device array of fixed size instead of a
+// path (work items of at most `chunk` points, one workgroup each, partial
+// sums combined per event in item order) for callers that cannot allocate
+// device memory.  Its workspace -- the per-event and per-site constants, the
+// work items, their count and their partial sums -- lives in one file-scope
+// device array of fixed size instead of a
 // plan's allocations, and the work items are built on the device from the
 // grid lengths, so the call neither allocates nor reads anything back.
 //
 // The kernels are those of the plan (gwf_batched.hip) with the items built
 // by launch_items_build; the items are taken in slot order rather than
-// longest first.
+// longest first, by a grid of the largest item count the workspace allows
+// (workgroups beyond the count built on the device leave at once).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -100,17 +101,10 @@ gwf_status gwf_fisher_static(const gwf_events* ev, const gwf_network* net, const
   int32_t* first = reinterpret_cast<int32_t*>(w + o_first);
   Item* items = reinterpret_cast<Item*>(w + o_items);
   double* partial = reinterpret_cast<double*>(w + o_part);
-  int32_t* counter = reinterpret_cast<int32_t*>(w + o_cnt);
-  int32_t* n_items = counter + 1;
-  int n_cu = 0;
-  if ((err = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
-    return api_hip_fail(err, "compute-unit count");
-  const int wg = std::max(1, items_max_resident(npi, rot, mixed));
-  const int n_wg = (int)std::max<int64_t>(1, std::min<int64_t>(items_max, (int64_t)n_cu * wg));
+  int32_t* n_items = reinterpret_cast<int32_t*>(w + o_cnt);
   hipStream_t s = (hipStream_t)stream;
-  // items from the grid lengths; the counter starts at zero (a fill kernel)
+  // items from the grid lengths
   err = launch_items_build(grid->npts, n, chunk, npts_max, first, n_items, items, s);
-  if (err == hipSuccess) err = launch_fill_i32(counter, 0, 1, s);
   if (err == hipSuccess) {
     SetupArgs sa{};
     sa.par = ev->par; sa.ld = ev->ld; sa.n = n;
@@ -124,8 +118,8 @@ gwf_status gwf_fisher_static(const gwf_events* ev, const gwf_network* net, const
   if (err == hipSuccess) {
     ItemsArgs ia{};
     ia.evc = evc; ia.sic = sic; ia.n_site = nd.n_site; ia.items = items;
-    ia.n_items = 0; ia.n_items_dev = n_items; ia.counter = counter; ia.partial = partial;
-    err = launch_items(ia, npi, rot, mixed, n_wg, s);
+    ia.n_items = 0; ia.n_items_dev = n_items; ia.partial = partial;
+    err = launch_items(ia, npi, rot, mixed, net_has_tables(nd), std::max<int64_t>(items_max, 1), s);
   }
   if (err == hipSuccess) {
     CombineArgs ca{};

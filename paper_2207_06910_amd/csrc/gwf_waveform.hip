@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
   __shared__ EventC ec;
   __shared__ WaveSite ws[kMaxSites];
   __shared__ int32_t ok;
-  const int64_t e = blockIdx.x;
+  const int64_t e = a.base + blockIdx.x;
   const int tid = threadIdx.x;
   const int n_site = a.net.n_site;
   if (tid == 0) {
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(kWBlock) void waveform_deriv_kernel(WaveformArgs a)
   __shared__ EventC ec;
   __shared__ SiteC sc[kMaxSites];
   __shared__ int32_t ok;
-  const int64_t e = blockIdx.x;
+  const int64_t e = a.base + blockIdx.x;
   const int tid = threadIdx.x;
   const int n_site = a.net.n_site;
   if (tid == 0) {
@@ -300,16 +300,16 @@ void launch_waveform_t(const WaveformArgs& a, bool tidal, bool rot, dim3 grid, d
 }
 
 // An explicit grid (a.gf set) selects the instantiations that read it.
-hipError_t launch_waveform(const WaveformArgs& a, bool tidal, bool rot, bool mixed, hipStream_t stream) {
-  dim3 grid((unsigned)a.n), block(kWBlock);
-  if (a.gf) {
-    if (mixed) launch_waveform_t<true, true>(a, tidal, rot, grid, block, stream);
-    else launch_waveform_t<false, true>(a, tidal, rot, grid, block, stream);
-  } else {
-    if (mixed) launch_waveform_t<true, false>(a, tidal, rot, grid, block, stream);
-    else launch_waveform_t<false, false>(a, tidal, rot, grid, block, stream);
-  }
-  return hipGetLastError();
+hipError_t launch_waveform(const WaveformArgs& a0, bool tidal, bool rot, bool mixed, hipStream_t stream) {
+  return launch_slices(a0, a0.n, 1, kWBlock, [&](const WaveformArgs& a, dim3 grid, dim3 block) {
+    if (a.gf) {
+      if (mixed) launch_waveform_t<true, true>(a, tidal, rot, grid, block, stream);
+      else launch_waveform_t<false, true>(a, tidal, rot, grid, block, stream);
+    } else {
+      if (mixed) launch_waveform_t<true, false>(a, tidal, rot, grid, block, stream);
+      else launch_waveform_t<false, false>(a, tidal, rot, grid, block, stream);
+    }
+  });
 }
 
 template <int NPI, bool EXPL>
@@ -328,11 +328,11 @@ void launch_deriv_t(const WaveformArgs& a, int npi, bool rot, dim3 grid, dim3 bl
   }
 }
 
-hipError_t launch_waveform_deriv(const WaveformArgs& a, int npi, bool rot, hipStream_t stream) {
-  dim3 grid((unsigned)a.n), block(kWBlock);
-  if (a.gf) launch_deriv_t<true>(a, npi, rot, grid, block, stream);
-  else launch_deriv_t<false>(a, npi, rot, grid, block, stream);
-  return hipGetLastError();
+hipError_t launch_waveform_deriv(const WaveformArgs& a0, int npi, bool rot, hipStream_t stream) {
+  return launch_slices(a0, a0.n, 1, kWBlock, [&](const WaveformArgs& a, dim3 grid, dim3 block) {
+    if (a.gf) launch_deriv_t<true>(a, npi, rot, grid, block, stream);
+    else launch_deriv_t<false>(a, npi, rot, grid, block, stream);
+  });
 }
 
 }  // namespace gwf

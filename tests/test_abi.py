@@ -23,7 +23,7 @@ def test_library_exports_every_declared_symbol():
     assert {"gwf_snr", "gwf_fisher", "gwf_invert"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.gwf_version() == 6
+    assert lib.gwf_version() == 7
 
 
 def test_network_interferometer_count():
@@ -93,7 +93,7 @@ def test_invalid_arguments_rejected_on_host():
     assert len(lib.gwf_last_error()) > 0
     # plans invert by Cholesky, Cholesky with the SVD fallback or double-double Cholesky only
     for m in (2, 3, 7):
-        opt = binding.PlanOptions(0, 0, 1, 0, m, 0)
+        opt = binding.PlanOptions(0, 1, 0, m)
         assert lib.gwf_plan_create(B(ev), B(net), B(grid), 0, B(opt), B(plan), None) == 1
         assert b"inv_method" in lib.gwf_last_error()
     # the static-workspace form: outputs, item length, grid bound, workspace size

@@ -200,7 +200,7 @@ def test_logdet_gradient_end_to_end_against_oracle(lib, orc):
 # ------------------------------------------------------------ batched (plan) form
 def _plan_adjoint(lib, wl, gbar, status=None, w_snr=1.0, w_fisher=1.0, chunk=512):
     dw = lib.DeviceWorkload(wl)
-    plan = lib.Plan(dw, chunk=chunk, wg_per_cu=2)
+    plan = lib.Plan(dw, chunk=chunk)
     g = torch.as_tensor(np.ascontiguousarray(gbar), device="cuda")
     st = None if status is None else torch.as_tensor(status, dtype=torch.int32, device="cuda")
     r = plan.adjoint(g, status=st, w_snr=w_snr, w_fisher=w_fisher)
@@ -258,7 +258,7 @@ def test_plan_adjoint_reproducible_and_network_update(lib, orc):
     import dataclasses
     wl = synth.bns1e4(n=6).with_npts(1500)
     dw = lib.DeviceWorkload(wl)
-    plan = lib.Plan(dw, chunk=1024, wg_per_cu=2)
+    plan = lib.Plan(dw, chunk=1024)
     F = orc.fisher(wl)["fisher"]
     d = np.sqrt(np.einsum("iie->ie", F))
     gbar = torch.as_tensor(np.random.default_rng(4).normal(size=(13, 13, wl.n)) / (d[:, None, :] * d[None, :, :]),
@@ -295,7 +295,7 @@ def test_figure_of_merit_through_a_plan(lib):
     x1 = xi.clone().requires_grad_(True)
     J1 = autodiff.network_fom(x1, dw, rows=rows)
     J1.backward()
-    plan = lib.Plan(dw, chunk=2048, wg_per_cu=2)
+    plan = lib.Plan(dw, chunk=2048)
     x2 = xi.clone().requires_grad_(True)
     J2 = autodiff.network_fom(x2, dw, rows=rows, plan=plan)
     J2.backward()
@@ -307,7 +307,7 @@ def test_figure_of_merit_through_a_plan(lib):
 
 def test_plan_adjoint_rejects_the_mixed_form(lib):
     wl = synth.bns1e4(n=2).with_npts(600)
-    plan = lib.Plan(lib.DeviceWorkload(wl), chunk=512, wg_per_cu=2, mixed=True)
+    plan = lib.Plan(lib.DeviceWorkload(wl), chunk=512, mixed=True)
     g = torch.zeros((13, 13, 2), dtype=torch.float64, device="cuda")
     with pytest.raises(lib.GwfError):
         plan.adjoint(g)

@@ -77,7 +77,7 @@ def test_full_catalogue_sampled(lib, orc):
     events against the oracle's transform of the same matrices; all finite."""
     wl = synth.bns1e4()
     dw = lib.DeviceWorkload(wl)
-    plan = lib.Plan(dw, chunk=16384, wg_per_cu=4, use_graph=False)
+    plan = lib.Plan(dw, chunk=16384, use_graph=False)
     F = plan.run()["fisher"]
     st = torch.zeros(wl.n, dtype=torch.int32, device="cuda")
     G = lib.fisher_basis(F, dw, basis=("chi_sa", "lambda_tilde"), status=st)

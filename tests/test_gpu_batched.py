@@ -1,4 +1,4 @@
-"""GPU: the batched persistent form (gwf_plan_*, work items + HIP graph)
+"""GPU: the batched form (gwf_plan_*, work items + HIP graph)
 against the plain kernel and the oracle.  The two forms sum the same
 per-point terms in a different order, so they agree to rounding (<= 1e-13
 relative on SNR, <= 1e-12 normalised on Fisher elements)."""
@@ -141,7 +141,7 @@ def test_mixed_waveform(lib, orc):
 
 def test_catalogue_1e6_plan(lib, orc):
     """The 10^6-event BBH/BNS/NSBH catalogue (more than 2^31 grid points in
-    total; each kind with its own parameter set) in one persistent launch
+    total; each kind with its own parameter set) in one launch
     with inversion: every event's Fisher is
     computed, the identity Gamma_dLdL dL^2 = SNR^2 holds for all of them,
     sampled events of each kind match the oracle, and ill-conditioned or
@@ -149,7 +149,7 @@ def test_catalogue_1e6_plan(lib, orc):
     wl = synth.catalog1e6()
     assert int(wl.npts.sum()) > 2 ** 31
     dw = lib.DeviceWorkload(wl)
-    plan = lib.Plan(dw, chunk=8192, wg_per_cu=4)
+    plan = lib.Plan(dw, chunk=8192)
     out = plan.run(invert=True)
     torch.cuda.synchronize()
     st = out["status"].cpu().numpy()
@@ -186,7 +186,7 @@ def test_full_catalogue_in_the_bench_launch(lib, orc, mixed):
     1e-9; mixed: the weight-error bounds of test_mixed_plan_bounds)."""
     full = synth.bns1e4()
     dw = lib.DeviceWorkload(full)
-    plan = lib.Plan(dw, chunk=16384, wg_per_cu=4, mixed=mixed)
+    plan = lib.Plan(dw, chunk=16384, mixed=mixed)
     g = _np(plan.run(invert=True))
     plan.close()
     torch.cuda.synchronize()

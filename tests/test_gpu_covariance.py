@@ -135,7 +135,7 @@ def test_full_catalogue_sampled_against_oracle(lib, orc):
     succeeded."""
     wl = synth.bns1e4()
     dw = lib.DeviceWorkload(wl)
-    plan = lib.Plan(dw, chunk=16384, wg_per_cu=4, use_graph=False)
+    plan = lib.Plan(dw, chunk=16384, use_graph=False)
     F = plan.run()["fisher"]
     theta = dw.par[3].contiguous()
     r = lib.covariance(F, theta=theta, fixed=FIXED, prior=PRIOR, marg=MARG)

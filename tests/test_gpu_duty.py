@@ -50,7 +50,7 @@ def test_fisher_and_snr_with_duty_factor(lib, orc):
     np.testing.assert_allclose(si, ref["snr_ifo"], rtol=1e-12, atol=0)
     assert np.all(si[wl.active == 0] == 0)
     assert _fisher_err(F[..., ok], ref["fisher"][..., ok]).max() < 1e-9
-    plan = lib.Plan(dw, chunk=1024, wg_per_cu=2, use_graph=False)
+    plan = lib.Plan(dw, chunk=1024, use_graph=False)
     o = plan.run()
     torch.cuda.synchronize()
     Fb = o["fisher"].cpu().numpy()

@@ -90,7 +90,7 @@ def test_eccentric_zero_is_circular_bit_for_bit(lib):
 def test_eccentric_plan_and_static(lib, orc, mixed):
     wl = _bns(8, seed=5)
     dw = lib.DeviceWorkload(wl)
-    plan = lib.Plan(dw, chunk=4096, wg_per_cu=2, mixed=mixed)
+    plan = lib.Plan(dw, chunk=4096, mixed=mixed)
     r = _np(plan.run())
     plan.close()
     _check(r, orc.fisher(wl), 5e-7 if mixed else 1e-12, 1e-6 if mixed else 1e-9)

@@ -90,7 +90,7 @@ def test_sampled_curves_plan_and_static(lib, orc, mixed):
     the plan bit for bit."""
     wl = _workload(n=12)
     dw = lib.DeviceWorkload(wl)
-    plan = lib.Plan(dw, chunk=2048, wg_per_cu=2, mixed=mixed)
+    plan = lib.Plan(dw, chunk=2048, mixed=mixed)
     r = {k: v.cpu().numpy() for k, v in plan.run().items()}
     plan.close()
     ref = orc.fisher(wl)

@@ -29,7 +29,7 @@ def _np(r):
 
 
 def _plan(lib, dw, chunk, mixed=False):
-    plan = lib.Plan(dw, chunk=chunk, wg_per_cu=2, mixed=mixed)
+    plan = lib.Plan(dw, chunk=chunk, mixed=mixed)
     r = plan.run()
     torch.cuda.synchronize()
     out = _np(r)

@@ -156,7 +156,12 @@ def error_report(res, ref) -> dict:
     eps = ferr.max(axis=(0, 1))
     sg_g, sg_r = res["sigma"][:, i], ref["sigma"]
     both = np.isfinite(sg_g) & np.isfinite(sg_r)
-    nan_gpu = np.isfinite(sg_r) & ~np.isfinite(sg_g)
+    # a NaN sigma counts against the form wherever the GPU matrix is provably
+    # positive definite: P kappa eps < 1 (Weyl: the normalised matrix's
+    # smallest eigenvalue, at least 1/kappa, moves by at most P eps)
+    provable = P * ref["cond"] * eps < 1.0
+    nan_gpu = np.isfinite(sg_r) & ~np.isfinite(sg_g) & provable[None, :]
+    nan_unprovable = int((np.isfinite(sg_r) & ~np.isfinite(sg_g) & ~provable[None, :]).any(axis=0).sum())
     sg = np.where(both, np.abs(sg_g / np.where(both, sg_r, 1.0) - 1), np.nan)
     kap = ref["cond"]
     ev_err = np.nanmax(np.where(both, sg, -1.0), axis=0)       # per event, -1 if none
@@ -179,6 +184,7 @@ def error_report(res, ref) -> dict:
            "sigma_max_rel_per_param": [_round(float(np.nanmax(sg[k]))) for k in range(P)],
            "sigma_by_kappa": decades,
            "sigma_nan_events": int(nan_gpu.any(axis=0).sum()),
+           "sigma_nan_events_not_provably_pd": nan_unprovable,
            "sigma_within_first_order_bound": float(np.mean(in_bound)),
            f"sigma_max_rel_kappa_lt_{KAPPA_MIXED:.0e}": _round(float(sub.max())) if sub.size else None,
            f"sigma_nan_kappa_lt_{KAPPA_MIXED:.0e}": int(nan_gpu[:, mixed_sel].any(axis=0).sum()),
@@ -329,10 +335,19 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="batched form: fixed item length (0: autotune)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the detector-gradient and 10^6-event catalogue measurements")
+    ap.add_argument("--skip", default="", metavar="LIST",
+                    help="comma-separated measurements to leave out: covariance, strain, bbh100, "
+                         "gradient, catalogue")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device-to-device (a plain copy kernel of "
                          "known size, for calibrating HBM byte counters)")
     args = ap.parse_args()
+    skip = {x.strip() for x in args.skip.split(",") if x.strip()}
+    if args.no_extra:
+        skip |= {"gradient", "catalogue"}
+    unknown = skip - {"covariance", "strain", "bbh100", "gradient", "catalogue"}
+    if unknown:
+        ap.error(f"unknown --skip entries: {sorted(unknown)}")
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the path shards "
               f"events across GPUs with no exchange, so per-GPU throughput is the figure.",
@@ -432,113 +447,133 @@ def main():
     batched_ms, items_ms, info, batched_res = batched(False, args.chunk)
     mixed_ms, mitems_ms, minfo, mixed_res = batched(True, args.chunk)
 
-    # ---- covariance epilogue (gwf_covariance) on the plain form's Fisher matrices: the
-    # paper's worked example (spins fixed, Gaussian priors of variance 2 pi^2 on the
-    # angles, 90% sky area in square degrees) with the tidal deformabilities
-    # marginalised over, inverted by the paper's default method (Cholesky, an SVD
-    # where it fails)
-    outc = {}
-    ckw = dict(theta=dw.par[3].contiguous(), fixed=(9, 10), marg=(11, 12), sky_level=90.0,
-               units="SqDeg", prior={i: 1.0 / (2.0 * np.pi ** 2) for i in (3, 4, 5, 6, 8)},
-               method="cho_svd", out=outc)
-    for i in range(2):
-        binding.covariance(outf["fisher"], outf["status"], **ckw)
-    tc = []
-    for i in range(args.steps):
-        ev[0].record(stream)
-        binding.covariance(outf["fisher"], outf["status"], **ckw)
-        ev[1].record(stream)
-        ev[1].synchronize()
-        tc.append(ev[0].elapsed_time(ev[1]))
-    cov_ms = float(np.mean(tc))
-    stc, skyc = outc["status"].cpu().numpy(), outc["sky"].cpu().numpy()
-    log(f"covariance epilogue kernel {cov_ms:.3f} ms, inverted {int(np.sum(stc == 0))}/{wl.n} "
-        f"(+{int(np.sum(stc == 32))} by SVD), median 90% sky area {float(np.median(skyc[stc == 0])):.3g} deg^2")
-    def time_cov(**kw):
-        o = {}
+    cov_form = {}
+    if "covariance" not in skip:
+        # ---- covariance epilogue (gwf_covariance) on the plain form's Fisher matrices: the
+        # paper's worked example (spins fixed, Gaussian priors of variance 2 pi^2 on the
+        # angles, 90% sky area in square degrees) with the tidal deformabilities
+        # marginalised over, inverted by the paper's default method (Cholesky, an SVD
+        # where it fails)
+        outc = {}
+        ckw = dict(theta=dw.par[3].contiguous(), fixed=(9, 10), marg=(11, 12), sky_level=90.0,
+                   units="SqDeg", prior={i: 1.0 / (2.0 * np.pi ** 2) for i in (3, 4, 5, 6, 8)},
+                   method="cho_svd", out=outc)
         for i in range(2):
-            binding.covariance(outf["fisher"], outf["status"], out=o, **kw)
-        t = []
+            binding.covariance(outf["fisher"], outf["status"], **ckw)
+        tc = []
         for i in range(args.steps):
             ev[0].record(stream)
-            binding.covariance(outf["fisher"], outf["status"], out=o, **kw)
+            binding.covariance(outf["fisher"], outf["status"], **ckw)
             ev[1].record(stream)
             ev[1].synchronize()
-            t.append(ev[0].elapsed_time(ev[1]))
-        return float(np.mean(t))
-    # every matrix by SVD, with its eigen-decomposition (the paper's 'svd' and
-    # CheckFisher), and every 13 x 13 matrix by the double-double Cholesky
-    svd_ms = time_cov(method="svd", eigen=True)
-    dd_ms = time_cov(method="cho_dd")
-    log(f"SVD inversion with eigen-decomposition {svd_ms:.3f} ms, double-double Cholesky {dd_ms:.3f} ms")
-    cov_form = {"covariance_epilogue": {
-        "workload": "bns1e4 Fisher matrices: chi1z, chi2z fixed; Gaussian priors of variance 2 pi^2 "
-                    "on theta, phi, iota, psi, Phicoal; Lambda1, Lambda2 marginalised; 90% sky area",
-        "kernel": "invert_kernel<11>", "kernel_ms": round(cov_ms, 4),
-        "events_per_s": round(wl.n / (cov_ms * 1e-3), 1), "inverted": int(np.sum(stc == 0)),
-        "inverted_by_svd": int(np.sum(stc == 32)),
-        "median_sky_deg2": round(float(np.median(skyc[stc == 0])), 4),
-        "svd_with_eigen_ms": round(svd_ms, 4), "cho_dd_ms": round(dd_ms, 4)}}
+            tc.append(ev[0].elapsed_time(ev[1]))
+        cov_ms = float(np.mean(tc))
+        stc, skyc = outc["status"].cpu().numpy(), outc["sky"].cpu().numpy()
+        log(f"covariance epilogue kernel {cov_ms:.3f} ms, inverted {int(np.sum(stc == 0))}/{wl.n} "
+            f"(+{int(np.sum(stc == 32))} by SVD), median 90% sky area {float(np.median(skyc[stc == 0])):.3g} deg^2")
+        def time_cov(**kw):
+            o = {}
+            for i in range(2):
+                binding.covariance(outf["fisher"], outf["status"], out=o, **kw)
+            t = []
+            for i in range(args.steps):
+                ev[0].record(stream)
+                binding.covariance(outf["fisher"], outf["status"], out=o, **kw)
+                ev[1].record(stream)
+                ev[1].synchronize()
+                t.append(ev[0].elapsed_time(ev[1]))
+            return float(np.mean(t))
+        # every matrix by SVD, with its eigen-decomposition (the paper's 'svd' and
+        # CheckFisher), and every 13 x 13 matrix by the double-double Cholesky
+        svd_ms = time_cov(method="svd", eigen=True)
+        dd_ms = time_cov(method="cho_dd")
+        log(f"SVD inversion with eigen-decomposition {svd_ms:.3f} ms, double-double Cholesky {dd_ms:.3f} ms")
+        cov_form = {"covariance_epilogue": {
+            "workload": "bns1e4 Fisher matrices: chi1z, chi2z fixed; Gaussian priors of variance 2 pi^2 "
+                        "on theta, phi, iota, psi, Phicoal; Lambda1, Lambda2 marginalised; 90% sky area",
+            "kernel": "invert_kernel<11>", "kernel_ms": round(cov_ms, 4),
+            "events_per_s": round(wl.n / (cov_ms * 1e-3), 1), "inverted": int(np.sum(stc == 0)),
+            "inverted_by_svd": int(np.sum(stc == 32)),
+            "median_sky_deg2": round(float(np.median(skyc[stc == 0])), 4),
+            "svd_with_eigen_ms": round(svd_ms, 4), "cho_dd_ms": round(dd_ms, 4)}}
 
-    # ---- strain output (gwf_waveform): HBM-bound, 16 B per point and interferometer
-    ends = torch.cumsum(dw.npts.to(torch.int64), 0)
-    offsets = ends - dw.npts.to(torch.int64)
-    total = int(ends[-1].item())
-    outw = {"h": torch.empty((wl.n_ifo, total), dtype=torch.complex128, device="cuda")}
     wave = {}
-    for mixed in (False, True):
+    if "strain" not in skip:
+        # ---- strain output (gwf_waveform): HBM-bound, 16 B per point and interferometer
+        ends = torch.cumsum(dw.npts.to(torch.int64), 0)
+        offsets = ends - dw.npts.to(torch.int64)
+        total = int(ends[-1].item())
+        outw = {"h": torch.empty((wl.n_ifo, total), dtype=torch.complex128, device="cuda")}
+        for mixed in (False, True):
+            for i in range(2):
+                binding.waveform(dw, offsets=offsets, total=total, out=outw, mixed=mixed)
+            tw = []
+            for i in range(max(3, args.steps // 4)):
+                ev[0].record(stream)
+                binding.waveform(dw, offsets=offsets, total=total, out=outw, mixed=mixed)
+                ev[1].record(stream)
+                ev[1].synchronize()
+                tw.append(ev[0].elapsed_time(ev[1]))
+            wave_ms = float(np.mean(tw))
+            wave_bytes = 16.0 * wl.n_ifo * total + 8.0 * (13 * wl.n + 3 * wl.n)
+            wave_gbs = wave_bytes / (wave_ms * 1e-3) / 1e9
+            name = "waveform_mixed" if mixed else "waveform_fp64"
+            log(f"{name} kernel {wave_ms:.3f} ms, {wave_bytes / 1e9:.2f} GB written, {wave_gbs:.0f} GB/s")
+            wave[name] = {"kernel": "waveform_kernel<rot,tidal%s>" % (",mixed" if mixed else ""),
+                          "kernel_ms": round(wave_ms, 4), "bytes": wave_bytes,
+                          "achieved_GBs": round(wave_gbs, 1), "peak_GBs": PEAK_HBM_GBS,
+                          "frac": round(wave_gbs / PEAK_HBM_GBS, 4),
+                          "traffic": MEASURED_TRAFFIC.get("waveform_kernel<rot,tidal%s>" % (",mixed" if mixed else ""))}
+        # the write ceiling of the same buffer: torch's own fills (a memset of
+        # zeros and an elementwise fill kernel), timed the same way
+        for name, fn in (("fill_zero", lambda: outw["h"].zero_()), ("fill_value", lambda: outw["h"].fill_(1.0))):
+            fn()
+            tw = []
+            for i in range(max(3, args.steps // 4)):
+                ev[0].record(stream)
+                fn()
+                ev[1].record(stream)
+                ev[1].synchronize()
+                tw.append(ev[0].elapsed_time(ev[1]))
+            fms = float(np.mean(tw))
+            fbytes = 16.0 * wl.n_ifo * total
+            log(f"{name} of the strain buffer {fms:.3f} ms, {fbytes / (fms * 1e-3) / 1e9:.0f} GB/s")
+            wave["waveform_fp64"][name + "_ms"] = round(fms, 4)
+            wave["waveform_fp64"][name + "_GBs"] = round(fbytes / (fms * 1e-3) / 1e9, 1)
+        del outw
+        # ---- strain derivatives (gwf_waveform_deriv) on the first 10^3 events:
+        # 16 B per point, interferometer and parameter (13), about 10 GB
+        nd = min(1000, wl.n)
+        wd = wl.subset(np.arange(nd))
+        dwd = binding.DeviceWorkload(wd)
+        endd = torch.cumsum(dwd.npts.to(torch.int64), 0)
+        offd, totd = endd - dwd.npts.to(torch.int64), int(endd[-1].item())
+        outd = {"dh": torch.empty((13, wd.n_ifo, totd), dtype=torch.complex128, device="cuda")}
         for i in range(2):
-            binding.waveform(dw, offsets=offsets, total=total, out=outw, mixed=mixed)
-        tw = []
+            binding.waveform_deriv(dwd, offsets=offd, total=totd, out=outd)
+        td = []
         for i in range(max(3, args.steps // 4)):
             ev[0].record(stream)
-            binding.waveform(dw, offsets=offsets, total=total, out=outw, mixed=mixed)
+            binding.waveform_deriv(dwd, offsets=offd, total=totd, out=outd)
             ev[1].record(stream)
             ev[1].synchronize()
-            tw.append(ev[0].elapsed_time(ev[1]))
-        wave_ms = float(np.mean(tw))
-        wave_bytes = 16.0 * wl.n_ifo * total + 8.0 * (13 * wl.n + 3 * wl.n)
-        wave_gbs = wave_bytes / (wave_ms * 1e-3) / 1e9
-        name = "waveform_mixed" if mixed else "waveform_fp64"
-        log(f"{name} kernel {wave_ms:.3f} ms, {wave_bytes / 1e9:.2f} GB written, {wave_gbs:.0f} GB/s")
-        wave[name] = {"kernel": "waveform_kernel<rot,tidal%s>" % (",mixed" if mixed else ""),
-                      "kernel_ms": round(wave_ms, 4), "bytes": wave_bytes,
-                      "achieved_GBs": round(wave_gbs, 1), "peak_GBs": PEAK_HBM_GBS,
-                      "frac": round(wave_gbs / PEAK_HBM_GBS, 4),
-                      "traffic": MEASURED_TRAFFIC.get("waveform_kernel<rot,tidal%s>" % (",mixed" if mixed else ""))}
-    del outw
-    # ---- strain derivatives (gwf_waveform_deriv) on the first 10^3 events:
-    # 16 B per point, interferometer and parameter (13), about 10 GB
-    nd = min(1000, wl.n)
-    wd = wl.subset(np.arange(nd))
-    dwd = binding.DeviceWorkload(wd)
-    endd = torch.cumsum(dwd.npts.to(torch.int64), 0)
-    offd, totd = endd - dwd.npts.to(torch.int64), int(endd[-1].item())
-    outd = {"dh": torch.empty((13, wd.n_ifo, totd), dtype=torch.complex128, device="cuda")}
-    for i in range(2):
-        binding.waveform_deriv(dwd, offsets=offd, total=totd, out=outd)
-    td = []
-    for i in range(max(3, args.steps // 4)):
-        ev[0].record(stream)
-        binding.waveform_deriv(dwd, offsets=offd, total=totd, out=outd)
-        ev[1].record(stream)
-        ev[1].synchronize()
-        td.append(ev[0].elapsed_time(ev[1]))
-    der_ms = float(np.mean(td))
-    der_bytes = 16.0 * 13 * wd.n_ifo * totd + 8.0 * (13 * nd + 3 * nd)
-    der_gbs = der_bytes / (der_ms * 1e-3) / 1e9
-    log(f"waveform_deriv kernel {der_ms:.3f} ms, {der_bytes / 1e9:.2f} GB written, {der_gbs:.0f} GB/s")
-    wave["waveform_deriv_fp64"] = {"kernel": "waveform_deriv_kernel<rot,tidal>",
-                                   "workload": f"first {nd} events of bns1e4, 13 parameters",
-                                   "kernel_ms": round(der_ms, 4), "bytes": der_bytes,
-                                   "achieved_GBs": round(der_gbs, 1), "peak_GBs": PEAK_HBM_GBS,
-                                   "frac": round(der_gbs / PEAK_HBM_GBS, 4),
-                                   "traffic": MEASURED_TRAFFIC.get("waveform_deriv_kernel<rot,tidal>")}
-    del outd
+            td.append(ev[0].elapsed_time(ev[1]))
+        der_ms = float(np.mean(td))
+        der_bytes = 16.0 * 13 * wd.n_ifo * totd + 8.0 * (13 * nd + 3 * nd)
+        der_gbs = der_bytes / (der_ms * 1e-3) / 1e9
+        log(f"waveform_deriv kernel {der_ms:.3f} ms, {der_bytes / 1e9:.2f} GB written, {der_gbs:.0f} GB/s")
+        wave["waveform_deriv_fp64"] = {"kernel": "waveform_deriv_kernel<rot,tidal>",
+                                       "workload": f"first {nd} events of bns1e4, 13 parameters",
+                                       "kernel_ms": round(der_ms, 4), "bytes": der_bytes,
+                                       "achieved_GBs": round(der_gbs, 1), "peak_GBs": PEAK_HBM_GBS,
+                                       "frac": round(der_gbs / PEAK_HBM_GBS, 4),
+                                       "traffic": MEASURED_TRAFFIC.get("waveform_deriv_kernel<rot,tidal>")}
+        del outd
 
-    extra = bbh100_form(binding, synth, torch, args, timed)
-    if not args.no_extra:
+    extra = {} if "bbh100" in skip else bbh100_form(binding, synth, torch, args, timed)
+    if "gradient" not in skip:
         extra.update(gradient_form(binding, synth, torch, args, timed))
+    if "catalogue" not in skip:
         extra.update(catalogue_form(binding, synth, torch, args, timed, info))
 
     cpu, errs = None, {}

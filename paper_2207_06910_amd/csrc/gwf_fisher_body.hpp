@@ -110,6 +110,9 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
   for (int r = NPI; r < kRowsB; ++r) B[r][lane] = 0.0;
 
   const int iters = (k1 - k0 + kBlock - 1) / kBlock;   // same trip count for every lane
+  // on a log grid, v, 1/v and v^-12.42 walk from point to point (GridWalk)
+  GridWalk gw;
+  if (!EXPL) gw.start(ec, k0 + tid, kBlock);
   for (int it = 0; it < iters; ++it) {
     // The per-event constants stay in LDS and are re-read every iteration
     // (uniform broadcast reads); hoisting them out of the loop would need
@@ -121,7 +124,10 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
     for (int b = 0; b < 8; ++b) U[b] = 0.0;
 #pragma unroll
     for (int i = 0; i < NPI; ++i) cph[i] = 0.0;
-    if (k < k1) accumulate_point<NPI, ROT, MIXED, PSUM, EXPL, TAB>(ec, sc, n_site, k, G, U, W, cph);
+    if (k < k1)
+      accumulate_point<NPI, ROT, MIXED, PSUM, EXPL, TAB>(ec, sc, n_site, k, G, U, W, cph,
+                                                         EXPL ? nullptr : gw.val);
+    if (!EXPL) gw.step();
     // stage this point's row (points past the range contribute zeros)
 #pragma unroll
     for (int b = 0; b < 8; ++b) A[b][lane] = U[b];

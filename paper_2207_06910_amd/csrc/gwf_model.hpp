@@ -123,6 +123,10 @@ struct SiteC {
   double xp_fac;               // (f/f0)^-4.14 = xp_fac v^-12.42
   double S0inv;                // 1/S0
   double alpha[2][4], beta[2][4], weff[2];  // effective interferometers (pattern maps)
+  // the effective interferometers' F+, Fx and their theta derivatives as
+  // trigonometric polynomials in the hour angle H: coefficients of
+  // (1, cos H, sin H, cos 2H, sin 2H), each scaled by sqrt(weff)
+  double jk[2][4][5];
   double arm_alpha[3][4], arm_beta[3][4];   // individual arms (SNR per interferometer)
   int32_t n_eff, n_arm;
   // sampled noise curve (tab_kind 1: PSD, 2: ASD; 0: the analytic PSD above)
@@ -490,6 +494,51 @@ __host__ __device__ inline void event_setup_grid(const double* p, const double* 
   }
 }
 
+// A function u + v cos H + w sin H of the hour angle H.
+struct TrigLin {
+  double u, v, w;
+};
+
+// Adds k a b to out, the coefficients of (1, cos H, sin H, cos 2H, sin 2H).
+__host__ __device__ inline void trig_mul_add(const TrigLin& a, const TrigLin& b, double k, double out[5]) {
+  out[0] += k * fma(a.u, b.u, 0.5 * fma(a.v, b.v, a.w * b.w));
+  out[1] += k * fma(a.u, b.v, a.v * b.u);
+  out[2] += k * fma(a.u, b.w, a.w * b.u);
+  out[3] += k * 0.5 * fma(a.v, b.v, -a.w * b.w);
+  out[4] += k * 0.5 * fma(a.v, b.w, a.w * b.v);
+}
+
+// The pattern vector P(H) of site_point and its theta derivative as
+// trigonometric polynomials of degree two in the hour angle: the frame
+// components EX = cos H, EY = -cos th sin H, NX = -sin lat sin H,
+// NY = -(sin lat cos th cos H + cos lat sin th) are linear in (cos H, sin H),
+// and every component of P is a quadratic form in them.
+__host__ __device__ inline void pattern_trig(double ct, double st, double sl, double cl, double pc[4][5],
+                                             double ptc[4][5]) {
+  const TrigLin EX{0.0, 1.0, 0.0}, EY{0.0, 0.0, -ct}, NX{0.0, 0.0, -sl}, NY{-cl * st, -sl * ct, 0.0};
+  const TrigLin EYt{0.0, 0.0, st}, NYt{-cl * ct, sl * st, 0.0};    // theta derivatives (EX, NX do not move)
+  for (int i = 0; i < 4; ++i)
+    for (int m = 0; m < 5; ++m) pc[i][m] = ptc[i][m] = 0.0;
+  trig_mul_add(EX, EX, 0.5, pc[0]);
+  trig_mul_add(NX, NX, -0.5, pc[0]);
+  trig_mul_add(EY, EY, -0.5, pc[0]);
+  trig_mul_add(NY, NY, 0.5, pc[0]);
+  trig_mul_add(EX, NX, 1.0, pc[1]);
+  trig_mul_add(EY, NY, -1.0, pc[1]);
+  trig_mul_add(EX, EY, 1.0, pc[2]);
+  trig_mul_add(NX, NY, -1.0, pc[2]);
+  trig_mul_add(EX, NY, 1.0, pc[3]);
+  trig_mul_add(NX, EY, 1.0, pc[3]);
+  trig_mul_add(EY, EYt, -1.0, ptc[0]);
+  trig_mul_add(NY, NYt, 1.0, ptc[0]);
+  trig_mul_add(EYt, NY, -1.0, ptc[1]);
+  trig_mul_add(EY, NYt, -1.0, ptc[1]);
+  trig_mul_add(EX, EYt, 1.0, ptc[2]);
+  trig_mul_add(NX, NYt, -1.0, ptc[2]);
+  trig_mul_add(EX, NYt, 1.0, ptc[3]);
+  trig_mul_add(NX, EYt, 1.0, ptc[3]);
+}
+
 // Pattern maps of one interferometer: F+ = alpha.P, Fx = beta.P.
 __host__ __device__ inline void pattern_map(double gamma, double zeta, double c2p, double s2p,
                                             double al[4], double be[4]) {
@@ -569,6 +618,24 @@ __host__ __device__ inline void site_setup(const double* p, const SiteDesc& sd, 
     }
     sc.weff[0] = 1.0; sc.weff[1] = 0.0;
     sc.n_eff = (arm_on & 1u) ? 1 : 0; sc.n_arm = 1;
+  }
+  double pc[4][5], ptc[4][5];
+  pattern_trig(ct, st, sl, cl, pc, ptc);
+  for (int j = 0; j < 2; ++j) {
+    const double w = sqrt(sc.weff[j]);
+    for (int m = 0; m < 5; ++m) {
+      double fp = 0.0, fx = 0.0, fpt = 0.0, fxt = 0.0;
+      for (int i = 0; i < 4; ++i) {
+        fp = fma(sc.alpha[j][i], pc[i][m], fp);
+        fx = fma(sc.beta[j][i], pc[i][m], fx);
+        fpt = fma(sc.alpha[j][i], ptc[i][m], fpt);
+        fxt = fma(sc.beta[j][i], ptc[i][m], fxt);
+      }
+      sc.jk[j][0][m] = w * fp;
+      sc.jk[j][1][m] = w * fx;
+      sc.jk[j][2][m] = w * fpt;
+      sc.jk[j][3][m] = w * fxt;
+    }
   }
 }
 
@@ -725,6 +792,34 @@ struct Point {
   double ecv;                     // v^-5 (v_ref/v)^{19/3} (eccentric forms, else 0)
 };
 
+// v = exp(ln v), 1/v and the PSD's power law v^-12.42 at the points k,
+// k + stride, k + 2 stride, ... of a log grid (ln v linear in k): evaluated
+// once at the first point, then multiplied by the ratios exp(stride dlnv),
+// exp(-stride dlnv), exp(-12.42 stride dlnv) per step.  After m steps each
+// value carries a relative error of at most about (2m + 1) u (u = 2^-53) on
+// top of that of its first evaluation: 1.4e-14 for the 63 steps of a
+// 16384-point work item walked by 256 lanes, far inside the Fisher and SNR
+// tolerances, for three multiplications per point instead of two
+// exponentials and a reciprocal.
+struct GridWalk {
+  double val[3];      // v, 1/v, v^-12.42 at the current point
+  double ratio[3];
+  __host__ __device__ inline void start(const EventC& ec, int32_t k, int32_t stride) {
+    const double L = fma((double)k, ec.dlnv, ec.lnv0), D = (double)stride * ec.dlnv;
+    val[0] = exp(L);
+    val[1] = exp(-L);
+    val[2] = exp(-12.42 * L);
+    ratio[0] = exp(D);
+    ratio[1] = exp(-D);
+    ratio[2] = exp(-12.42 * D);
+  }
+  __host__ __device__ inline void step() {
+    val[0] *= ratio[0];
+    val[1] *= ratio[1];
+    val[2] *= ratio[2];
+  }
+};
+
 // Number of phase-only Fisher parameters (Phic, chi1z, chi2z, then Lambda1,
 // Lambda2 with tides, then e0 with eccentricity) and what it implies.
 template <int NPI>
@@ -742,9 +837,11 @@ enum PsdPow { kPsdNone = 0, kPsdF64 = 1, kPsdF32 = 2 };
 // PSUM: the evaluation form of the PN series (see horner7) and of the PSD's
 // power law (once per point when true, once per site otherwise).
 // EXPL: the point of an explicit grid (ec.fx) rather than of the log grid.
+// vrec (log grids only, NULL: evaluate directly): v, 1/v and v^-12.42 at the
+// point, carried by the caller from an earlier point (see GridWalk).
 template <bool PSUM = true, bool EXPL = false, bool ECC = false>
 __host__ __device__ inline void point_setup(const EventC& ec, int32_t k, bool need_derivs, bool rot,
-                                            Point& q, int psd = kPsdF64) {
+                                            Point& q, int psd = kPsdF64, const double* vrec = nullptr) {
   double L, v, f, wf;               // wf: the trapezoid weight
   if (EXPL) {
     f = ec.fx[k];
@@ -753,20 +850,22 @@ __host__ __device__ inline void point_setup(const EventC& ec, int32_t k, bool ne
     wf = 0.5 * (ec.fx[k < ec.n - 1 ? k + 1 : k] - ec.fx[k > 0 ? k - 1 : k]);
   } else {
     L = fma((double)k, ec.dlnv, ec.lnv0);
-    v = exp(L);
+    v = vrec ? vrec[0] : exp(L);
     f = v * v * v * ec.inv_piM;
     double w = ec.wint;
     if (k == 0) w = ec.wfirst;
     if (k == ec.n - 1) w = ec.wlast;
     wf = w * f;
   }
-  const double iv = recip(v);
+  const double iv = (!EXPL && vrec) ? vrec[1] : recip(v);
   const double iv2 = iv * iv, iv4 = iv2 * iv2, iv5 = iv4 * iv, iv7 = iv5 * iv2, iv8 = iv4 * iv4;
   q.v = v; q.iv = iv; q.L = L; q.f = f;
   q.tf = kTwoPi * f;
   q.w4A2 = wf * ec.KA4 * iv7;
   q.vpsd = 0.0;
-  if (PSUM && psd == kPsdF64) {
+  if (!EXPL && vrec && psd != kPsdNone) {
+    q.vpsd = vrec[2];
+  } else if (PSUM && psd == kPsdF64) {
     q.vpsd = exp(-12.42 * L);
   } else if (psd == kPsdF32) {   // 2^y with the integer part of y split off exactly
     const double y = (-12.42 / kLn2) * L, ny = rint(y);
@@ -930,6 +1029,40 @@ __host__ __device__ inline void site_point(const SiteC& sc, const Point& q, bool
   sp.dT = fma(sc.k1t, cH, sc.k0t);
 }
 
+// Site-level quantities of the Fisher kernels at one frequency for the
+// trigonometric form of the patterns (SiteC::jk): cos H, sin H, cos 2H,
+// sin 2H and the factors 2 cos 2H, -2 sin 2H of the H derivatives; the
+// arrival-time derivatives and the noise weight.
+struct SiteTrig {
+  double cH, sH, c2H, s2H, p2c, m2s;
+  double dH, dT;      // dDelta/dH, dDelta/dtheta
+  double om;          // 4 w A^2 / S_n(f)
+};
+
+template <bool MIXED = false, bool PSUM = true, bool TAB = true>
+__host__ __device__ inline void site_trig(const SiteC& sc, const Point& q, SiteTrig& sp) {
+  const double cH = q.cth * sc.cdl - q.sth * sc.sdl;
+  const double sH = q.sth * sc.cdl + q.cth * sc.sdl;
+  sp.cH = cH;
+  sp.sH = sH;
+  sp.c2H = fma(cH, cH, -sH * sH);
+  sp.s2H = 2.0 * (sH * cH);
+  sp.p2c = 2.0 * sp.c2H;
+  sp.m2s = -2.0 * sp.s2H;
+  if (MIXED) psd_weight_f32<TAB>(sc, q, sp.om);
+  else psd_weight<PSUM, TAB>(sc, q, sp.om);
+  sp.dH = -sc.k1 * sH;
+  sp.dT = fma(sc.k1t, cH, sc.k0t);
+}
+
+// A trigonometric polynomial of SiteC::jk at the point, and its H derivative.
+__host__ __device__ inline double trig_val(const double c[5], const SiteTrig& sp) {
+  return fma(c[4], sp.s2H, fma(c[3], sp.c2H, fma(c[2], sp.sH, fma(c[1], sp.cH, c[0]))));
+}
+__host__ __device__ inline double trig_dH(const double c[5], const SiteTrig& sp) {
+  return fma(c[4], sp.p2c, fma(c[3], sp.m2s, fma(c[2], sp.cH, -c[1] * sp.sH)));
+}
+
 __host__ __device__ inline double dot4(const double a[4], const double b[4]) {
   return fma(a[0], b[0], fma(a[1], b[1], fma(a[2], b[2], a[3] * b[3])));
 }
@@ -949,9 +1082,12 @@ struct SitePhase {
   double mc, eta, t, p, tc;
 };
 
+__host__ __device__ inline SitePhase site_phase(const Point& q, double dH, double dT) {
+  return SitePhase{fma(q.tf * dH, q.gMc, q.pMc), fma(q.tf * dH, q.gEta, q.pEta), q.tf * dT,
+                   -q.tf * dH, q.tf * fma(kOmegaE, dH, 1.0)};
+}
 __host__ __device__ inline SitePhase site_phase(const Point& q, const SitePoint& sp) {
-  return SitePhase{fma(q.tf * sp.dH, q.gMc, q.pMc), fma(q.tf * sp.dH, q.gEta, q.pEta), q.tf * sp.dT,
-                   -q.tf * sp.dH, q.tf * fma(kOmegaE, sp.dH, 1.0)};
+  return site_phase(q, sp.dH, sp.dT);
 }
 
 // Phase-free derivative vector of one interferometer at one point,
@@ -1014,28 +1150,31 @@ constexpr int kGramRows[5] = {0, 1, 3, 4, 7};   // Mc, eta, theta, phi, tc
 template <int NPI, bool ROT, bool MIXED = false, bool PSUM = true, bool EXPL = false, bool TAB = true>
 __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* sc, int n_site,
                                                  int32_t k, double* G, double* U, double& W,
-                                                 double* cph) {
+                                                 double* cph, const double* vrec = nullptr) {
   const AmpFactors am = amp_factors(ec);
   Point q;
-  point_setup<PSUM, EXPL, PhaseOnly<NPI>::ecc>(ec, k, true, ROT, q, MIXED ? kPsdF32 : kPsdF64);
+  point_setup<PSUM, EXPL, PhaseOnly<NPI>::ecc>(ec, k, true, ROT, q, MIXED ? kPsdF32 : kPsdF64, vrec);
   double UR[5], spp = 0.0, spx = 0.0, sxx = 0.0;
 #pragma unroll
   for (int b = 0; b < 5; ++b) UR[b] = 0.0;
   for (int s = 0; s < n_site; ++s) {
     const SiteC& st = sc[s];
-    SitePoint sp;
-    site_point<MIXED, PSUM, TAB>(st, q, true, sp);
-    const SitePhase ph = site_phase(q, sp);
+    SiteTrig sp;
+    site_trig<MIXED, PSUM, TAB>(st, q, sp);
+    const SitePhase ph = site_phase(q, sp.dH, sp.dT);
     // at most two effective interferometers per site; the count is the same
-    // for every lane, so the second pass is skipped as a whole where unused
+    // for every lane, so the second pass is skipped as a whole where unused.
+    // The patterns are trigonometric polynomials in H whose coefficients
+    // carry sqrt(weff), so every product below is already weighted by weff.
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       if (j >= st.n_eff) break;
-      const double om = sp.om * st.weff[j];
-      const double Fp = dot4(st.alpha[j], sp.P), Fx = dot4(st.beta[j], sp.P);
+      const double om = sp.om;
+      const double(*c)[5] = st.jk[j];
+      const double Fp = trig_val(c[0], sp), Fx = trig_val(c[1], sp);
       double Dr[8], Di[8];
-      derivative_vector(am, q, ph, Fp, Fx, dot4(st.alpha[j], sp.PH), dot4(st.beta[j], sp.PH),
-                        dot4(st.alpha[j], sp.Pt), dot4(st.beta[j], sp.Pt), Dr, Di);
+      derivative_vector(am, q, ph, Fp, Fx, trig_dH(c[0], sp), trig_dH(c[1], sp), trig_val(c[2], sp),
+                        trig_val(c[3], sp), Dr, Di);
       const double Qr = am.cplus * Fp, Qi = am.ccross * Fx;
       const double wp = om * Fp, wx = om * Fx;
       int g = 0;

@@ -18,8 +18,16 @@ of the event; the FP64 inversion adds at most ~1e3 kappa u (u = 2^-53) on top
     9 x 9 block of Mc, eta, dL, theta, phi, iota, psi, tc, Phic, kappa
     1e3-1e8 on the BNS catalogue): sigma within 1e-9 wherever kappa <= 1e5,
     and within the bound above everywhere.
-  * Full 13 x 13 BNS matrices (kappa 1e10-1e14): every event within the
-    bound, no NaN where the oracle inverts.
+  * Full 13 x 13 BNS matrices (kappa 1e10-1e16): every event within the
+    bound, no NaN where the oracle inverts and the GPU matrix is provably
+    positive definite.  By Weyl's inequality the smallest eigenvalue of the
+    normalised matrix moves by at most ||dGamma^||_2 <= P eps, and it is at
+    least 1/kappa, so P kappa eps < 1 (the bound above below 1/2) keeps the
+    GPU matrix positive definite; past that the bound says nothing (it
+    exceeds 1/2) and an FP64 matrix an ulp-level perturbation away from
+    indefinite may legitimately have no Cholesky factor and an SVD inverse
+    with a NaN sigma (ln det undefined).  Such events are reported, not
+    asserted.
 """
 import numpy as np
 import pytest
@@ -67,6 +75,12 @@ def _eps(Fg, Fr):
 def _check(g_sigma, ref_inv, eps, P, label, well=None):
     ok = np.isfinite(ref_inv["sigma"]).all(axis=0)
     assert ok.sum() >= len(ok) - 2, f"{label}: the oracle inverted only {ok.sum()} events"
+    pd = ok & (P * ref_inv["cond"] * eps < 1.0)      # provably positive definite on the GPU too
+    for e in np.flatnonzero(ok & ~pd):
+        print(f"{label}: event {e} kappa {ref_inv['cond'][e]:.1e} eps {eps[e]:.1e}: P kappa eps >= 1, "
+              f"finite sigma on the GPU: {bool(np.all(np.isfinite(g_sigma[:, e])))}")
+    ok = pd
+    assert ok.sum() >= len(ok) - 2, f"{label}: only {ok.sum()} events with P kappa eps < 1"
     assert np.all(np.isfinite(g_sigma[:, ok])), f"{label}: NaN sigma where the oracle inverts"
     rel = np.abs(g_sigma[:, ok] / ref_inv["sigma"][:, ok] - 1).max(axis=0)
     kap = ref_inv["cond"][ok]

@@ -7,16 +7,19 @@
 // registers and adds its share of the 8x8 block of (Mc, eta, dL, theta, phi,
 // iota, psi, tc) to its kGramAcc register accumulators (the 5x5 block of the
 // rows that are not pattern combinations, plus pattern moments; see
-// accumulate_point).  The phase-only blocks are a small
-// dense contraction over frequency, X = sum_f a_f c_f^T with
-// a_f = (U_0..U_7, W c_0..W c_{NPI-1}) and c_f = (c_0..c_{NPI-1}): every
-// iteration each wavefront stages its 64 points' a_f and c_f in LDS and
-// folds them into 4x4 output tiles of X with the four-block FP64 MFMA
-// 4x4x4 (k = frequency), which keeps those sums out of the lanes' registers.
-// The 13 x 5 block (tides; 11 x 3 without; with e0 one more row and column,
-// in the same tiles) needs seven tiles (three): two MFMAs (one) per four
-// points, a quarter of the cycles of one 16x16x4 MFMA per four points, which
-// computes mostly padding.
+// accumulate_point).  The phase-only blocks Gamma_{b, 8+i} = sum U_b c_i and
+// Gamma_{8+i, 8+j} = sum W c_i c_j split in two:
+//   * the Phic column (c_0 = -1 at every point) needs only sums of U_b and of
+//     W c_i; those of U_b and W are combinations of the pattern moments the
+//     lanes already hold (U_b = c+ T_b,1 - cx T_b,2, U_dL = 0, U_iota and
+//     U_psi and W from S), so a lane adds up only W c_i (i >= 1);
+//   * the rest is a small dense contraction over frequency, X = sum_f a_f c_f^T
+//     with a_f = (U_0, U_1, U_3, U_4, U_5, U_6, U_7, W c_1 .. W c_{NPI-1}) and
+//     c_f = (c_1 .. c_{NPI-1}): every iteration each wavefront stages its 64
+//     points' a_f and c_f in LDS and folds them into 4x4 output tiles of X
+//     with the four-block FP64 MFMA 4x4x4 (k = frequency).  With tides
+//     (NPI = 5) the 11 x 4 block fits three tiles, one MFMA per four points
+//     (a fourth tile slot idle); with e0 as well six tiles, two MFMAs.
 // The sums are then reduced in a fixed order (wavefront butterflies, then
 // the waves in index order), so results are bitwise reproducible.
 #pragma once
@@ -27,13 +30,14 @@ namespace gwf {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kRowsA = 16;        // 8 U rows, up to 6 W c rows, zero rows to a whole tile
-constexpr int kRowsB = 8;         // up to 6 c rows, zero rows to a whole tile
+constexpr int kRowsA = 16;        // 7 U rows, up to 5 W c rows, zero rows to a whole tile
+constexpr int kRowsB = 8;         // up to 5 c rows, zero rows to a whole tile
 constexpr int kZeroRowB = 7;      // a B row no point writes (operand of unused tile slots)
 constexpr int kZeroRowA = 15;
 constexpr int kTileLd = 64 + 4;   // row stride (doubles): an operand read touches 8 rows x
                                   // 4 points, 2 (8 row + k) mod 64 distinct dword banks
 constexpr int kNaccMax = 105;    // 36 + 8 NPI + NPI (NPI + 1)/2 at NPI = 6
+constexpr int kURow[7] = {0, 1, 3, 4, 5, 6, 7};   // the U rows staged (U_dL = 0)
 
 template <int NPI_>
 struct FisherDims {
@@ -42,15 +46,34 @@ struct FisherDims {
   static constexpr int P = 8 + NPI;
   static constexpr int NG = 36, NX = 8 * NPI, NY = NPI * (NPI + 1) / 2;
   static constexpr int NACC = NG + NX + NY;          // SNR^2 = Gamma_{Phic,Phic}
-  // 4x4 output tiles (row group R of a_f, column group C of c_f) of the
-  // phase-only blocks: every tile of the U rows, and of the W c rows those
-  // holding an element of the upper triangle (4C + 3 >= 4R - 8)
-  static constexpr int RG = (8 + NPI + 3) / 4, CG = (NPI + 3) / 4;
-  static constexpr int NT = TIDAL ? 7 : 3;
+  // the staged contraction: NA rows of a_f (7 U rows, then W c_i for
+  // i = 1..NPI-1), NB columns c_1..c_{NPI-1}; its 4x4 output tiles are those
+  // holding a U row or an element of the upper triangle of W c_i c_j
+  static constexpr int NA = 6 + NPI, NB = NPI - 1;
+  static constexpr int RG = (NA + 3) / 4, CG = (NB + 3) / 4;
+  __host__ __device__ static constexpr bool tile_used(int r, int c) {
+    return 4 * r < 7 || 4 * c + 3 >= (4 * r > 7 ? 4 * r : 7) - 7;
+  }
+  __host__ __device__ static constexpr int count_tiles() {
+    int n = 0;
+    for (int r = 0; r < RG; ++r)
+      for (int c = 0; c < CG; ++c) n += tile_used(r, c) ? 1 : 0;
+    return n;
+  }
+  static constexpr int NT = count_tiles();
   static constexpr int NM = (NT + 3) / 4;            // MFMA accumulators (4 tiles each)
-  __host__ __device__ static constexpr int tile_r(int t) { return TIDAL ? (t < 4 ? t / 2 : t == 6 ? 3 : 2) : t; }
-  __host__ __device__ static constexpr int tile_c(int t) { return TIDAL ? (t < 4 ? t % 2 : t == 6 ? 1 : t - 4) : 0; }
+  // row group and column group of the t-th used tile (row-major order)
+  __host__ __device__ static constexpr int tile_rc(int t, bool col) {
+    for (int r = 0; r < RG; ++r)
+      for (int c = 0; c < CG; ++c)
+        if (tile_used(r, c) && t-- == 0) return col ? c : r;
+    return 0;
+  }
+  __host__ __device__ static constexpr int tile_r(int t) { return tile_rc(t, false); }
+  __host__ __device__ static constexpr int tile_c(int t) { return tile_rc(t, true); }
 };
+static_assert(FisherDims<5>::NM == 1 && FisherDims<3>::NM == 1 && FisherDims<4>::NM == 1 &&
+              FisherDims<6>::NM == 2, "tile counts");
 
 // LDS working set of one workgroup.
 struct FisherLds {
@@ -105,41 +128,52 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
   double(*B)[kTileLd] = L.stB[wave];
   // rows no point ever writes stay zero
 #pragma unroll
-  for (int r = 8 + NPI; r < kRowsA; ++r) A[r][lane] = 0.0;
+  for (int r = Dm::NA; r < kRowsA; ++r) A[r][lane] = 0.0;
 #pragma unroll
-  for (int r = NPI; r < kRowsB; ++r) B[r][lane] = 0.0;
+  for (int r = Dm::NB; r < kRowsB; ++r) B[r][lane] = 0.0;
+  double wc[NPI - 1];                      // this lane's sums of W c_i, i >= 1
+#pragma unroll
+  for (int i = 0; i < NPI - 1; ++i) wc[i] = 0.0;
 
   const int iters = (k1 - k0 + kBlock - 1) / kBlock;   // same trip count for every lane
+  const int full = (k1 - k0) / kBlock;                  // iterations with every lane in range
   // on a log grid, v, 1/v and v^-12.42 walk from point to point (GridWalk)
   GridWalk gw;
   if (!EXPL) gw.start(ec, k0 + tid, kBlock);
-  for (int it = 0; it < iters; ++it) {
-    // The per-event constants stay in LDS and are re-read every iteration
-    // (uniform broadcast reads); hoisting them out of the loop would need
-    // more registers than a lane has.
+  // One iteration: every lane's point, then the wavefront's MFMA phase.  The
+  // iterations whose points are all in range run without the range test
+  // (and without zeroing the point's outputs for lanes past the end); the
+  // last, partial one, if any, runs with it.
+  auto iteration = [&](int it, bool guard) {
+    // The per-event constants are re-read every iteration (uniform reads);
+    // hoisting them out of the loop would need more registers than a lane has.
     __asm__ volatile("" ::: "memory");
     const int k = k0 + it * kBlock + tid;
-    double U[8], W = 0.0, cph[NPI];
+    double U[8], W, cph[NPI];
+    if (guard) {
+      W = 0.0;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) U[b] = 0.0;
+      for (int b = 0; b < 8; ++b) U[b] = 0.0;
 #pragma unroll
-    for (int i = 0; i < NPI; ++i) cph[i] = 0.0;
-    if (k < k1)
+      for (int i = 0; i < NPI; ++i) cph[i] = 0.0;
+    }
+    if (!guard || k < k1)
       accumulate_point<NPI, ROT, MIXED, PSUM, EXPL, TAB>(ec, sc, n_site, k, G, U, W, cph,
                                                          EXPL ? nullptr : gw.val);
     if (!EXPL) gw.step();
     // stage this point's row (points past the range contribute zeros)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) A[b][lane] = U[b];
+    for (int r = 0; r < 7; ++r) A[r][lane] = U[kURow[r]];
 #pragma unroll
-    for (int i = 0; i < NPI; ++i) {
-      A[8 + i][lane] = W * cph[i];
-      B[i][lane] = cph[i];
+    for (int i = 1; i < NPI; ++i) {
+      const double x = W * cph[i];
+      wc[i - 1] += x;
+      A[6 + i][lane] = x;
+      B[i - 1][lane] = cph[i];
     }
     __builtin_amdgcn_wave_barrier();
     // The LDS-fed MFMA phase runs at raised issue priority, so it drains
-    // quickly while the SIMD's other wave keeps the VALU busy (measured:
-    // items kernel 1.7% faster, sums unchanged).
+    // quickly while the SIMD's other wave keeps the VALU busy.
     __builtin_amdgcn_s_setprio(1);
     // X += A^T B over this wavefront's 64 points, four points per step
 #pragma unroll
@@ -153,7 +187,9 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
     }
     __builtin_amdgcn_s_setprio(0);
     __builtin_amdgcn_wave_barrier();
-  }
+  };
+  for (int it = 0; it < full; ++it) iteration(it, false);
+  if (full < iters) iteration(full, true);
 
   // ---- deterministic reduction: wavefront butterflies, then the waves in order
   double F[NG];
@@ -163,19 +199,50 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
     const double t = wave_sum(F[i]);
     if (lane == 0) L.red[wave][i] = t;
   }
+  // the Phic column: Gamma_{b,Phic} = -sum U_b from the pattern moments,
+  // Gamma_{Phic,Phic} = sum W, Gamma_{Phic, 8+j} = -sum W c_j
+  {
+    const AmpFactors am = amp_factors(ec);
+    double xc[10 + NPI - 1];
+#pragma unroll
+    for (int a = 0; a < 5; ++a)
+      xc[a] = fma(am.ccross, G[17 + 4 * a], -am.cplus * G[16 + 4 * a]);   // rows Mc, eta, theta, phi, tc
+    xc[5] = -(am.cplus * am.dcx - am.ccross * am.dcp) * G[36];               // iota
+    xc[6] = 2.0 * am.cplus * am.ccross * (G[35] + G[37]);                    // psi
+    xc[7] = fma(am.cplus * am.cplus, G[35], am.ccross * am.ccross * G[37]);   // Phic, Phic
+#pragma unroll
+    for (int i = 1; i < NPI; ++i) xc[7 + i] = -wc[i - 1];
+    constexpr int rowof[5] = {0, 1, 3, 4, 7};
+#pragma unroll
+    for (int x = 0; x < 7 + NPI; ++x) {
+      const double t = wave_sum(xc[x]);
+      int slot;
+      if (x < 5) slot = NG + rowof[x] * NPI;
+      else if (x == 5) slot = NG + 5 * NPI;
+      else if (x == 6) slot = NG + 6 * NPI;
+      else slot = NG + NX + (x - 7);                 // row Phic: (8, 8 + x - 7)
+      if (lane == 0) L.red[wave][slot] = t;
+    }
+    // the dL row of the phase-only block is exactly zero (U_dL = 0)
+    if (lane < NPI) L.red[wave][NG + 2 * NPI + lane] = 0.0;
+  }
   // lane 16 i + 4 q + j of accumulator m holds element (i, j) of tile 4 m + q:
-  // X rows 0..7 are the U_b rows (columns 0..NPI-1), rows 8..8+NPI-1 the
-  // W c_i rows (upper triangle kept)
+  // rows 0..6 of X are U_0, U_1, U_3 .. U_7, rows 7.. the W c_i rows (i >= 1),
+  // column c is c_{c+1}; the upper triangle of W c_i c_j is kept
 #pragma unroll
   for (int m = 0; m < Dm::NM; ++m) {
     const int t = 4 * m + q4;
     if (t >= Dm::NT) continue;
     const int row = 4 * Dm::tile_r(t) + kk, col = 4 * Dm::tile_c(t) + i4;
     int slot = -1;
-    if (row < 8 && col < NPI) slot = NG + row * NPI + col;
-    else if (row >= 8 && row < 8 + NPI && col >= row - 8 && col < NPI) {
-      const int i = row - 8;
-      slot = NG + NX + i * NPI - (i * (i - 1)) / 2 + (col - i);
+    if (col < Dm::NB) {
+      const int j = col + 1;
+      if (row < 7) {
+        slot = NG + kURow[row] * NPI + j;
+      } else if (row < Dm::NA) {
+        const int i = row - 6;
+        if (j >= i) slot = NG + NX + i * NPI - (i * (i - 1)) / 2 + (j - i);
+      }
     }
     if (slot >= 0) L.red[wave][slot] = acc[m];
   }

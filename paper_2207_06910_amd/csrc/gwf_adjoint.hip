@@ -2,31 +2,31 @@
 // respect to the detector parameters; the per-point mathematics and its
 // derivation are in gwf_adjoint.hpp.
 //
-//   adjoint_kernel  one workgroup per event: the event's constants, its
-//                   symmetrised Gbar and the sites' constants with their
-//                   tangents in LDS; every lane walks the grid with a stride
-//                   of the workgroup size, forms the point quantities once
-//                   and, for each site, recomputes the derivative vectors and
-//                   contracts them into that site's sums; each pair of lanes
-//                   adds its two contributions and keeps the running sums in
-//                   one LDS column (sized by the number of sites, so that two
-//                   wavefronts fit per SIMD); the sums are reduced over the
-//                   workgroup in a fixed order and combined into the event's
-//                   gradient terms.
+//   adjoint_kernel  one workgroup of 128 lanes per event: the event's
+//                   constants, the contractions of its symmetrised Gbar
+//                   (AdjEventC) and the sites' constants (SiteC, AdjSiteC)
+//                   in LDS; every lane walks the grid with a stride of the
+//                   workgroup size, forms the point quantities once
+//                   and adds each site's contributions to its own LDS column
+//                   (one LDS add per value; every address has one writer, so
+//                   the sums are in program order); the columns are reduced in
+//                   a fixed order and combined into the event's gradient
+//                   terms.
 //   reduce_kernel   one workgroup per output component sums the events'
 //                   terms in a fixed order, so the gradient is bitwise
 //                   reproducible.
 //
 // The batched form (gwf_plan_adjoint) runs the same per-point mathematics
 // over a plan's work items:
-//   adjoint_items_kernel    one workgroup of 256 lanes per work item (event,
+//   adj_setup_kernel        one lane per event: AdjEventC from Gbar and the
+//                   AdjSiteC of every site, into the plan's adjoint workspace
+//                   (the plan's set-up kernel has written EventC and SiteC);
+//   adjoint_items_kernel    one workgroup of 128 lanes per work item (event,
 //                   point range), in the plan's longest-first order; the
-//                   event's constants (from the plan's workspace), the
-//                   symmetrised Gbar and the sites' constants go to LDS, each
-//                   group of four lanes keeps its running per-site sums in one
-//                   LDS column, and the item's sums are written to its slot
-//                   (deterministic: fixed reduction order, slots in event
-//                   order);
+//                   event's and sites' constants are read through the
+//                   constant address space (scalar loads into SGPRs); the
+//                   item's per-site sums go to its slot (deterministic:
+//                   fixed reduction order, slots in event order);
 //   adjoint_combine_kernel  one lane per event sums its items' slots in item
 //                   order and forms the event's gradient terms; the
 //                   reduce_kernel then sums the events.
@@ -39,11 +39,7 @@ namespace gwf {
 namespace {
 
 constexpr int kABlock = 128;
-constexpr int kCols = kABlock / 2;        // LDS accumulator columns, one per lane pair
-// accumulator slots kept per (site, lane pair) in LDS: the four Gbar:dGamma
-// terms, the three geometric SNR^2 derivatives and the site's SNR^2 (its
-// ln S0 derivative is minus that)
-constexpr int kSlots = 8;
+constexpr int kSlots = kAdjN;   // LDS accumulator values per site and lane
 
 __device__ inline double wave_sum_a(double x) {
 #pragma unroll
@@ -51,30 +47,89 @@ __device__ inline double wave_sum_a(double x) {
   return x;
 }
 
-__device__ inline int slot_of(int i) { return i < 7 ? i : kAdjW; }   // LDS slot -> acc index
+// The sums of points [k0, k1) of one event into the LDS columns
+// accl[(s kSlots + i) kABlock + lane] (zeroed by the caller).
+template <int NPI, bool ROT, bool TAB>
+__device__ __attribute__((always_inline)) inline void adjoint_sums(const EventC& ec, const AdjEventC& ae, const SiteC* sc, const AdjSiteC* as,
+                                    int n_site, int k0, int k1, double* accl) {
+  const int tid = threadIdx.x;
+  // v = exp(ln v) is evaluated at every point (not carried from point to
+  // point as in the Fisher kernels): the sum of Gbar-weighted terms cancels
+  // strongly when Gbar is an ill-conditioned covariance, so the grid values
+  // must not depend on where a work item starts for the batched and the
+  // per-event forms to agree to rounding
+  const int iters = (k1 - k0 + kABlock - 1) / kABlock;
+  for (int it = 0; it < iters; ++it) {
+    asm volatile("" ::: "memory");   // constants are re-read rather than held in registers
+    const int k = k0 + it * kABlock + tid;
+    if (k < k1) {
+      AdjPoint ap;
+      adjoint_point_setup<NPI, ROT>(ec, ae, k, ap);
+      for (int s = 0; s < n_site; ++s) {
+        asm volatile("" ::: "memory");
+        double acc[kAdjN];
+#pragma unroll
+        for (int i = 0; i < kAdjN; ++i) acc[i] = 0.0;
+        adjoint_site<TAB>(ae, sc[s], as[s], ap, acc);
+#pragma unroll
+        for (int i = 0; i < kSlots; ++i) atomicAdd(&accl[(s * kSlots + i) * kABlock + tid], acc[i]);
+      }
+    }
+  }
+}
+
+// The site sums of the workgroup's columns, in a fixed order: wave w takes
+// the values t = w, w + 2, ...; each lane adds its two columns, then the
+// wavefront butterfly.
+__device__ inline void adjoint_columns(const double* accl, int width, double* out) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int t = wave; t < width; t += kABlock / 64) {
+    const double v = wave_sum_a(accl[t * kABlock + lane] + accl[t * kABlock + 64 + lane]);
+    if (lane == 0) out[t] = v;
+  }
+}
+
+// Gbar of event e from [P][P][n], symmetrised and zero outside its rows.
+struct GbarOf {
+  const double* g;
+  int64_t n, e;
+  int P;
+  uint32_t pm;
+  __device__ double operator()(int i, int j) const {
+    return rows_in(pm, i, j) ? 0.5 * (g[(int64_t)(i * P + j) * n + e] + g[(int64_t)(j * P + i) * n + e]) : 0.0;
+  }
+};
+
+struct GbarLds {
+  const double* g;
+  int P;
+  __device__ double operator()(int i, int j) const { return g[i * P + j]; }
+};
 
 // Two wavefronts per SIMD: the registers are capped at 256 (the sums live in
 // LDS, not in registers).
-template <int NPI, bool ROT>
+template <int NPI, bool ROT, bool TAB>
 __global__ __launch_bounds__(kABlock, 2) void adjoint_kernel(AdjointArgs a) {
   using PO = PhaseOnly<NPI>;
   constexpr int P = PO::P;
   constexpr bool TIDAL = PO::tidal;
   constexpr uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u) | (PO::ecc ? kFlagEcc : 0u);
   __shared__ EventC ec;
-  __shared__ SiteA sa[kMaxSites];
+  __shared__ AdjEventC ae;
+  __shared__ SiteC sc[kMaxSites];
+  __shared__ AdjSiteC as[kMaxSites];
   __shared__ double Gb[P * P];
-  extern __shared__ double accl[];      // [n_site][kSlots][kCols], column tid/2 per lane pair
-  __shared__ double site_acc[kMaxSites][kSlots];
+  extern __shared__ double accl[];      // [n_site][kSlots][kABlock]
+  __shared__ double site_acc[kMaxSites * kSlots];
   __shared__ int32_t ok;
   const int64_t e = a.base + blockIdx.x;
   const int tid = threadIdx.x;
   const int n_site = a.net.n_site;
+  double p[kNparIn];
+  for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
+  p[13] = PO::ecc && a.ecc ? a.ecc[e] : 0.0;
+  p[14] = PO::ecc && a.fref ? a.fref[e] : 0.0;
   if (tid == 0) {
-    double p[kNparIn];
-    for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
-    p[13] = PO::ecc && a.ecc ? a.ecc[e] : 0.0;
-    p[14] = PO::ecc && a.fref ? a.fref[e] : 0.0;
     event_setup(p, a.fmin[e], a.fmax ? a.fmax[e] : 0.0, a.npts[e], flags, ec);
     ok = ec.status == 0 && (a.status == nullptr || a.status[e] == 0);
   }
@@ -82,8 +137,7 @@ __global__ __launch_bounds__(kABlock, 2) void adjoint_kernel(AdjointArgs a) {
   const uint32_t pm = event_rows(a.par_mask, e);
   for (int t = tid; t < P * P; t += kABlock) {
     const int i = t / P, j = t - i * P;
-    const double g = rows_in(pm, i, j)
-        ? 0.5 * (a.gbar[(int64_t)(i * P + j) * a.n + e] + a.gbar[(int64_t)(j * P + i) * a.n + e]) : 0.0;
+    const double g = GbarOf{a.gbar, a.n, e, P, pm}(i, j);
     Gb[t] = g;
     if (!finite(g)) ok = 0;          // every writer stores the same value
   }
@@ -93,60 +147,26 @@ __global__ __launch_bounds__(kABlock, 2) void adjoint_kernel(AdjointArgs a) {
     if (tid < n_site * 4) ge[tid] = 0.0;
     return;
   }
+  if (tid == 0) adj_event_setup(ec, NPI, GbarLds{Gb, P}, ae);
   if (tid < n_site) {
-    double p[kNparIn];
-    for (int r = 0; r < 13; ++r) p[r] = (r < 11 || TIDAL) ? a.par[r * a.ld + e] : 0.0;
-    site_setup_adj(p, a.net.site[tid], ec, sa[tid], site_arms_on(a.active, a.ld, e, a.net, tid));
+    const uint32_t arms = site_arms_on(a.active, a.ld, e, a.net, tid);
+    site_setup(p, a.net.site[tid], ec, sc[tid], arms);
+    adj_site_setup(p, a.net.site[tid], sc[tid], as[tid], arms);
   }
-  const int col = tid >> 1;
-  if ((tid & 1) == 0)
-    for (int s = 0; s < n_site; ++s)
-#pragma unroll
-      for (int i = 0; i < kSlots; ++i) accl[(s * kSlots + i) * kCols + col] = 0.0;
+  for (int t = tid; t < n_site * kSlots * kABlock; t += kABlock) accl[t] = 0.0;
   __syncthreads();
-  // every lane walks its grid points once (the same trip count for every
-  // lane, so that both lanes of a pair take part in each exchange; points
-  // past the grid add zero); the point quantities are shared by all sites
-  const int iters = (ec.n + kABlock - 1) / kABlock;
-  for (int it = 0; it < iters; ++it) {
-    asm volatile("" ::: "memory");   // constants stay in LDS rather than occupying registers
-    const int k = it * kABlock + tid;
-    const bool in = k < ec.n;
-    AdjPoint ap;
-    if (in) adjoint_point_setup<NPI, ROT>(ec, Gb, k, ap);
-    for (int s = 0; s < n_site; ++s) {
-      asm volatile("" ::: "memory");
-      double acc[kAdjN];
-#pragma unroll
-      for (int i = 0; i < kAdjN; ++i) acc[i] = 0.0;
-      if (in) adjoint_site<NPI>(ec, sa[s], Gb, ap, acc);
-#pragma unroll
-      for (int i = 0; i < kSlots; ++i) {
-        const double v = acc[slot_of(i)];
-        const double t = v + __shfl_xor(v, 1, 64);       // the lane pair's two points
-        if ((tid & 1) == 0) accl[(s * kSlots + i) * kCols + col] += t;
-      }
-    }
-  }
+  adjoint_sums<NPI, ROT, TAB>(ec, ae, sc, as, n_site, 0, ec.n, accl);
   __syncthreads();
-  // the first wavefront sums the columns (kCols = 64 lanes)
-  if (tid < kCols) {
-    for (int s = 0; s < n_site; ++s)
-#pragma unroll
-      for (int i = 0; i < kSlots; ++i) {
-        const double t = wave_sum_a(accl[(s * kSlots + i) * kCols + tid]);
-        if (tid == 0) site_acc[s][i] = t;
-      }
-  }
+  adjoint_columns(accl, n_site * kSlots, site_acc);
   __syncthreads();
   if (tid < n_site * 4) {
     const int s = tid >> 2, m = tid & 3;
     double W = 0.0;
-    for (int u = 0; u < n_site; ++u) W += site_acc[u][7];
+    for (int u = 0; u < n_site; ++u) W += site_acc[u * kSlots + kAdjW];
     // d SNR^2 along ln S0 of a site is minus that site's SNR^2
-    const double dS = m < 3 ? site_acc[s][4 + m] : -site_acc[s][7];
+    const double dS = m < 3 ? site_acc[s * kSlots + kAdjS + m] : -site_acc[s * kSlots + kAdjW];
     // w_fisher sum Gbar dGamma + w_snr d ln SNR, d ln SNR = dSNR^2 / (2 SNR^2)
-    ge[tid] = fma(a.w_fisher, site_acc[s][m], a.w_snr * dS / (2.0 * W));
+    ge[tid] = fma(a.w_fisher, site_acc[s * kSlots + kAdjT + m], a.w_snr * dS / (2.0 * W));
   }
 }
 
@@ -167,20 +187,40 @@ __global__ __launch_bounds__(kABlock) void reduce_kernel(const double* __restric
 }
 
 // ---------------------------------------------------- batched (work items)
-constexpr int kAIBlock = 256;
-constexpr int kAICols = kAIBlock / 4;     // LDS accumulator columns, one per group of four lanes
-
-template <int NPI, bool ROT>
-__global__ __launch_bounds__(kAIBlock, 2) void adjoint_items_kernel(AdjItemsArgs a) {
+// One lane per event: the contractions of its Gbar (AdjEventC, ok = 0 where
+// the event is left out) and its sites' AdjSiteC, after the plan's set-up
+// kernel has written EventC and SiteC.
+template <int NPI>
+__global__ void adj_setup_kernel(AdjSetupArgs a) {
   constexpr int P = PhaseOnly<NPI>::P;
-  __shared__ double Gb[P * P];
-  __shared__ SiteA sa[kMaxSites];
-  __shared__ EventC ec;
-  extern __shared__ double accl[];        // [n_site][kSlots][kAICols]
-  __shared__ int32_t ok;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.n) return;
+  const EventC& ec = a.evc[e];
+  AdjEventC ae;
+  const GbarOf gb{a.gbar, a.n, e, P, event_rows(a.par_mask, e)};
+  adj_event_setup(ec, NPI, gb, ae);
+  int32_t ok = ec.status == 0 && (a.status == nullptr || a.status[e] == 0);
+  for (int i = 0; i < P && ok; ++i)
+    for (int j = 0; j < P; ++j)
+      if (!finite(gb(i, j))) ok = 0;
+  ae.ok = ok;
+  a.aec[e] = ae;
+  if (!ok) return;
+  double p[kNparIn] = {};
+  p[3] = a.par[3 * a.ld + e];
+  p[6] = a.par[6 * a.ld + e];
+  for (int s = 0; s < a.net.n_site; ++s) {
+    AdjSiteC as;
+    adj_site_setup(p, a.net.site[s], a.sic[e * a.net.n_site + s], as, site_arms_on(a.active, a.ld, e, a.net, s));
+    a.asc[e * a.net.n_site + s] = as;
+  }
+}
+
+template <int NPI, bool ROT, bool TAB>
+__global__ __launch_bounds__(kABlock, 2) void adjoint_items_kernel(AdjItemsArgs a) {
+  extern __shared__ double accl[];        // [n_site][kSlots][kABlock]
   const int tid = threadIdx.x;
   const int n_site = a.net.n_site;
-  const int col = tid >> 2;
   const int width = n_site * kSlots;
   // workgroup b takes item b: the plan orders its items longest first, and
   // workgroups are dispatched in order, so the shortest items come last
@@ -188,68 +228,26 @@ __global__ __launch_bounds__(kAIBlock, 2) void adjoint_items_kernel(AdjItemsArgs
   const int32_t e = __builtin_amdgcn_readfirstlane(w.e);
   const int32_t k0 = __builtin_amdgcn_readfirstlane(w.k0);
   const int32_t k1 = __builtin_amdgcn_readfirstlane(w.k1);
-  // the event's constants from the plan's workspace into LDS (re-read there
-  // at every use rather than held in registers)
-  {
-    static_assert(sizeof(EventC) % sizeof(double) == 0, "EventC copied as doubles");
-    const double* src = reinterpret_cast<const double*>(a.evc + e);
-    double* dst = reinterpret_cast<double*>(&ec);
-    for (int t = tid; t < (int)(sizeof(EventC) / sizeof(double)); t += kAIBlock) dst[t] = src[t];
-  }
+  // constants read through the constant address space: uniform, never
+  // written during the kernel, so the compiler may use scalar loads
+  typedef const __attribute__((address_space(4))) EventC CEventC;
+  typedef const __attribute__((address_space(4))) AdjEventC CAdjEventC;
+  typedef const __attribute__((address_space(4))) SiteC CSiteC;
+  typedef const __attribute__((address_space(4))) AdjSiteC CAdjSiteC;
+  const EventC& ec = *(const EventC*)((CEventC*)(a.evc) + e);
+  const AdjEventC& ae = *(const AdjEventC*)((CAdjEventC*)(a.aec) + e);
+  const SiteC* sc = (const SiteC*)((CSiteC*)(a.sic) + (int64_t)e * n_site);
+  const AdjSiteC* as = (const AdjSiteC*)((CAdjSiteC*)(a.asc) + (int64_t)e * n_site);
   double* out = a.partial + (int64_t)__builtin_amdgcn_readfirstlane(w.slot) * width;
-  __syncthreads();
-  if (tid == 0) ok = ec.status == 0 && (a.status == nullptr || a.status[e] == 0);
-  __syncthreads();
-  const uint32_t pm = event_rows(a.par_mask, e);
-  for (int t = tid; t < P * P; t += kAIBlock) {
-    const int i = t / P, j = t - i * P;
-    const double g = rows_in(pm, i, j)
-        ? 0.5 * (a.gbar[(int64_t)(i * P + j) * a.n + e] + a.gbar[(int64_t)(j * P + i) * a.n + e]) : 0.0;
-    Gb[t] = g;
-    if (!finite(g)) ok = 0;                     // every writer stores the same value
-  }
-  if (tid < n_site) {
-    double p[kNparIn] = {};
-    p[3] = a.par[3 * a.ld + e];
-    p[4] = a.par[4 * a.ld + e];
-    p[6] = a.par[6 * a.ld + e];
-    site_setup_adj(p, a.net.site[tid], ec, sa[tid], site_arms_on(a.active, a.ld, e, a.net, tid));
-  }
-  for (int t = tid; t < width * kAICols; t += kAIBlock) accl[t] = 0.0;
-  __syncthreads();
-  if (!ok) {                                     // left out: NaN marks the item for the combine
+  if (!ae.ok) {                                  // left out: NaN marks the item for the combine
     if (tid < width) out[tid] = __builtin_nan("");
     return;
   }
-  const int iters = (k1 - k0 + kAIBlock - 1) / kAIBlock;   // same trip count for every lane
-  for (int r = 0; r < iters; ++r) {
-    asm volatile("" ::: "memory");
-    const int k = k0 + r * kAIBlock + tid;
-    const bool in = k < k1;
-    AdjPoint ap;
-    if (in) adjoint_point_setup<NPI, ROT>(ec, Gb, k, ap);
-    for (int s = 0; s < n_site; ++s) {
-      asm volatile("" ::: "memory");
-      double acc[kAdjN];
-#pragma unroll
-      for (int i = 0; i < kAdjN; ++i) acc[i] = 0.0;
-      if (in) adjoint_site<NPI>(ec, sa[s], Gb, ap, acc);
-#pragma unroll
-      for (int i = 0; i < kSlots; ++i) {
-        double v = acc[slot_of(i)];
-        v += __shfl_xor(v, 1, 64);               // the group's four points
-        v += __shfl_xor(v, 2, 64);
-        if ((tid & 3) == 0) accl[(s * kSlots + i) * kAICols + col] += v;
-      }
-    }
-  }
+  for (int t = tid; t < width * kABlock; t += kABlock) accl[t] = 0.0;
   __syncthreads();
-  if (tid < kAICols) {                           // the first wavefront sums the 64 columns
-    for (int t = 0; t < width; ++t) {
-      const double v = wave_sum_a(accl[t * kAICols + tid]);
-      if (tid == 0) out[t] = v;
-    }
-  }
+  adjoint_sums<NPI, ROT, TAB>(ec, ae, sc, as, n_site, k0, k1, accl);
+  __syncthreads();
+  adjoint_columns(accl, width, out);
 }
 
 // One lane per event: its items' sums in item order, then the gradient terms.
@@ -281,20 +279,39 @@ __global__ void adjoint_combine_kernel(AdjCombineArgs a) {
 
 }  // namespace
 
+template <int NPI, bool ROT>
+void launch_adjoint_items_r(const AdjItemsArgs& a, bool tab, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+  if (tab) hipLaunchKernelGGL((adjoint_items_kernel<NPI, ROT, true>), grid, block, lds, s, a);
+  else hipLaunchKernelGGL((adjoint_items_kernel<NPI, ROT, false>), grid, block, lds, s, a);
+}
+
 template <int NPI>
-void launch_adjoint_items_n(const AdjItemsArgs& a, bool rot, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
-  if (rot) hipLaunchKernelGGL((adjoint_items_kernel<NPI, true>), grid, block, lds, s, a);
-  else hipLaunchKernelGGL((adjoint_items_kernel<NPI, false>), grid, block, lds, s, a);
+void launch_adjoint_items_n(const AdjItemsArgs& a, bool rot, bool tab, dim3 grid, dim3 block, size_t lds,
+                            hipStream_t s) {
+  if (rot) launch_adjoint_items_r<NPI, true>(a, tab, grid, block, lds, s);
+  else launch_adjoint_items_r<NPI, false>(a, tab, grid, block, lds, s);
+}
+
+hipError_t launch_adjoint_setup(const AdjSetupArgs& a, int npi, hipStream_t s) {
+  const dim3 grid((unsigned)((a.n + 127) / 128)), block(128);
+  switch (npi) {
+    case 6: hipLaunchKernelGGL((adj_setup_kernel<6>), grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((adj_setup_kernel<5>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((adj_setup_kernel<4>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((adj_setup_kernel<3>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_adjoint_items(const AdjItemsArgs& a0, int npi, bool rot, hipStream_t s) {
-  const size_t lds = sizeof(double) * (size_t)a0.net.n_site * kSlots * kAICols;
-  return launch_slices(a0, a0.n_items, 1, kAIBlock, [&](const AdjItemsArgs& a, dim3 grid, dim3 block) {
+  const size_t lds = sizeof(double) * (size_t)a0.net.n_site * kSlots * kABlock;
+  const bool tab = net_has_tables(a0.net);
+  return launch_slices(a0, a0.n_items, 1, kABlock, [&](const AdjItemsArgs& a, dim3 grid, dim3 block) {
     switch (npi) {
-      case 6: launch_adjoint_items_n<6>(a, rot, grid, block, lds, s); break;
-      case 5: launch_adjoint_items_n<5>(a, rot, grid, block, lds, s); break;
-      case 4: launch_adjoint_items_n<4>(a, rot, grid, block, lds, s); break;
-      default: launch_adjoint_items_n<3>(a, rot, grid, block, lds, s);
+      case 6: launch_adjoint_items_n<6>(a, rot, tab, grid, block, lds, s); break;
+      case 5: launch_adjoint_items_n<5>(a, rot, tab, grid, block, lds, s); break;
+      case 4: launch_adjoint_items_n<4>(a, rot, tab, grid, block, lds, s); break;
+      default: launch_adjoint_items_n<3>(a, rot, tab, grid, block, lds, s);
     }
   });
 }
@@ -308,22 +325,32 @@ hipError_t launch_adjoint_combine(const AdjCombineArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-int adjoint_items_block() { return kAIBlock; }
+int adjoint_items_block() { return kABlock; }
+size_t adjoint_event_bytes() { return sizeof(AdjEventC); }
+size_t adjoint_site_bytes() { return sizeof(AdjSiteC); }
+
+template <int NPI, bool ROT>
+void launch_adjoint_r(const AdjointArgs& a, bool tab, dim3 grid, dim3 block, size_t lds, hipStream_t stream) {
+  if (tab) hipLaunchKernelGGL((adjoint_kernel<NPI, ROT, true>), grid, block, lds, stream, a);
+  else hipLaunchKernelGGL((adjoint_kernel<NPI, ROT, false>), grid, block, lds, stream, a);
+}
 
 template <int NPI>
-void launch_adjoint_n(const AdjointArgs& a, bool rot, dim3 grid, dim3 block, size_t lds, hipStream_t stream) {
-  if (rot) hipLaunchKernelGGL((adjoint_kernel<NPI, true>), grid, block, lds, stream, a);
-  else hipLaunchKernelGGL((adjoint_kernel<NPI, false>), grid, block, lds, stream, a);
+void launch_adjoint_n(const AdjointArgs& a, bool rot, bool tab, dim3 grid, dim3 block, size_t lds,
+                      hipStream_t stream) {
+  if (rot) launch_adjoint_r<NPI, true>(a, tab, grid, block, lds, stream);
+  else launch_adjoint_r<NPI, false>(a, tab, grid, block, lds, stream);
 }
 
 hipError_t launch_adjoint(const AdjointArgs& a0, int npi, bool rot, hipStream_t stream) {
-  const size_t lds = sizeof(double) * (size_t)a0.net.n_site * kSlots * kCols;
+  const size_t lds = sizeof(double) * (size_t)a0.net.n_site * kSlots * kABlock;
+  const bool tab = net_has_tables(a0.net);
   hipError_t err = launch_slices(a0, a0.n, 1, kABlock, [&](const AdjointArgs& a, dim3 grid, dim3 block) {
     switch (npi) {
-      case 6: launch_adjoint_n<6>(a, rot, grid, block, lds, stream); break;
-      case 5: launch_adjoint_n<5>(a, rot, grid, block, lds, stream); break;
-      case 4: launch_adjoint_n<4>(a, rot, grid, block, lds, stream); break;
-      default: launch_adjoint_n<3>(a, rot, grid, block, lds, stream);
+      case 6: launch_adjoint_n<6>(a, rot, tab, grid, block, lds, stream); break;
+      case 5: launch_adjoint_n<5>(a, rot, tab, grid, block, lds, stream); break;
+      case 4: launch_adjoint_n<4>(a, rot, tab, grid, block, lds, stream); break;
+      default: launch_adjoint_n<3>(a, rot, tab, grid, block, lds, stream);
     }
   });
   if (err != hipSuccess) return err;

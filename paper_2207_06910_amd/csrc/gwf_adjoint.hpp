@@ -7,42 +7,46 @@
 //   dJ/dxi = sum_e [ sum_ij Gbar_e,ij dGamma_e,ij/dxi + snrbar_e dSNR_e/dxi ],
 // Gbar = dJ/dGamma (Gamma^-1 for J = ln det Gamma), snrbar = dJ/dSNR.  With
 // Gamma_ij = sum_{k,d} w Re(D_i D_j^*) (sec. 3.2, D the noise-weighted
-// derivative vectors of the phase-free form) and a symmetric Gbar,
-//   sum_ij Gbar_ij dGamma_ij = sum_{k,d} [ dw Re(D^H z) + 2 w Re(dD . z^*) ],
-//   z = Gbar D,
-// so the backward pass recomputes D at every grid point, forms z, and
-// contracts it with the derivative of D along each detector parameter; no
-// Jacobian is stored.  Reverse mode all the way: the weights of the building
-// blocks (the pattern vectors P, their hour-angle and theta derivatives PH,
-// Pt, and the arrival-time derivatives dH, dT) are taken back to the site's
-// local frame vectors (the E/N components of the polarisation frame and
-// their H and theta derivatives), whose derivatives along latitude and
-// longitude are a handful of closed forms (the longitude enters only through
-// the hour angle, so d/dlon = d/dH); gamma moves only the pattern maps.
-// Along ln S0 only the weight changes, dw = -w, which gives
-// -sum w Re(D^H z) in closed form.
+// derivative vectors of the phase-free form) and a symmetric Gbar, each
+// grid point and interferometer contributes w (Dr^T Gbar Dr + Di^T Gbar Di)
+// to sum_ij Gbar_ij Gamma_ij.  The backward pass recomputes that quadratic
+// form at every point and takes its derivatives; no Jacobian is stored.
+//
+// Structure used (exact algebra).  An interferometer enters D only through
+// its six pattern values y = (F+, Fx, dF+/dH, dFx/dH, dF+/dth, dFx/dth)
+// (H the hour angle): with c+ = (1 + cos^2 i)/2, cx = cos i,
+//   Dr = v0 y0 + (-cx rho + 2 c+ e6) y1 + c+ gamma y2 + c+ e3 y4,
+//   Di = (c+ rho - 2 cx e6) y0 + w1 y1 + cx gamma y3 + cx e3 y5,
+// where e3, e6 are the unit vectors of theta and psi, v0 and w1 fixed
+// per-event vectors (amplitude, distance and inclination rows), gamma the
+// hour-angle direction of the phase derivatives (Mc, eta through the
+// sidereal angle at t(f); phi; tc) and rho = pi + 2 pi f (dDelta/dH gamma +
+// dDelta/dth e3) the site's phase-derivative vector (pi: the PN phase
+// derivatives, 2 pi f for tc and the phase-only coefficients c_i).  So the
+// form is y^T H y with H = M^T Gbar M built from the Gbar inner products
+// <a, b> = a^T Gbar b of just six vectors {pi, gamma, e3, e6, v0, w1}: those
+// among the fixed ones once per event, those with pi and gamma once per grid
+// point (shared by all sites), and those with rho, which depend on the
+// site's arrival-time derivatives, by two multiply-adds each per site.  Per
+// interferometer the point then needs two 4 x 4 quadratic forms in y instead
+// of z = Gbar D (an 8 x 8 product for two vectors).
+//
+// Derivatives: J_point depends on the detector parameters through y (the
+// patterns: latitude and gamma move their coefficients, longitude the hour
+// angle H), through the arrival-time derivatives dDelta/dH and dDelta/dth
+// (latitude and longitude) and, for ln S0, through the weight (dw = -w).
+// The patterns are trigonometric polynomials in H (SiteC::jk), so along
+// longitude y' follows from the same coefficients, and along latitude and
+// gamma from their per-event derivatives (AdjSiteC).
 #pragma once
 
 #include "gwf_model.hpp"
 
 namespace gwf {
 
-// ----------------------------------------------------- site constants
-// The per-(event, site) constants of site_setup that the adjoint needs, and
-// the derivatives of the pattern maps along gamma.
-struct SiteA {
-  double cdl, sdl;                       // cos, sin of (site longitude - phi)
-  double ct, st, sl, cl, slct, clst;     // cos th, sin th, sin lat, cos lat, sin lat cos th, cos lat sin th
-  double k1, k1t, k0t;                   // Delta = k1 cos H + k0, dDelta/dth = k1t cos H + k0t
-  double alpha[2][4], beta[2][4];        // pattern maps of the effective interferometers
-  double alpha_g[2][4], beta_g[2][4];    // and their derivatives along gamma
-  double xp_fac, ix_fac, x_fac, S0inv, weff[2];
-  int32_t n_eff, tab_kind;
-  const double* tab_f;                   // sampled noise curve (tab_kind 1 PSD, 2 ASD), as SiteC
-  const double* tab_S;
-  int64_t tab_n;
-};
+constexpr int kMaxNpi = 6;
 
+// ----------------------------------------------------- site constants
 // Pattern maps of one interferometer (as pattern_map) and their derivatives
 // along its bisector angle gamma.
 __host__ __device__ inline void pattern_map_g(double gamma, double zeta, double c2p, double s2p, double al[4],
@@ -56,339 +60,355 @@ __host__ __device__ inline void pattern_map_g(double gamma, double zeta, double 
   beg[3] = 2.0 * sz * s2g * c2p;
 }
 
-// arm_on as for site_setup.
-__host__ __device__ inline void site_setup_adj(const double* p, const SiteDesc& sd, const EventC& ec,
-                                               SiteA& sa, uint32_t arm_on = 7u) {
-  const double th = p[3], ph = p[4], psi = p[6];
+// Adds k (a' b + a b') to out: the derivative of trig_mul_add(a, b, k) along
+// a direction in which a and b move by a' and b'.
+__host__ __device__ inline void trig_mul_add_d(const TrigLin& a, const TrigLin& ad, const TrigLin& b,
+                                               const TrigLin& bd, double k, double out[5]) {
+  trig_mul_add(ad, b, k, out);
+  trig_mul_add(a, bd, k, out);
+}
+
+// The latitude derivatives of pattern_trig's polynomials: sin lat -> cos lat,
+// cos lat -> -sin lat, which moves only NX, NY and the theta derivative of NY.
+__host__ __device__ inline void pattern_trig_lat(double ct, double st, double sl, double cl, double pc[4][5],
+                                                 double ptc[4][5]) {
+  const TrigLin EX{0.0, 1.0, 0.0}, EY{0.0, 0.0, -ct}, NX{0.0, 0.0, -sl}, NY{-cl * st, -sl * ct, 0.0};
+  const TrigLin EYt{0.0, 0.0, st}, NYt{-cl * ct, sl * st, 0.0};
+  const TrigLin Z{0.0, 0.0, 0.0};
+  const TrigLin NXl{0.0, 0.0, -cl}, NYl{sl * st, -cl * ct, 0.0}, NYtl{sl * ct, cl * st, 0.0};
+  for (int i = 0; i < 4; ++i)
+    for (int m = 0; m < 5; ++m) pc[i][m] = ptc[i][m] = 0.0;
+  // P0 = (EX EX - NX NX - EY EY + NY NY)/2
+  trig_mul_add_d(NX, NXl, NX, NXl, -0.5, pc[0]);
+  trig_mul_add_d(NY, NYl, NY, NYl, 0.5, pc[0]);
+  // P1 = EX NX - EY NY
+  trig_mul_add_d(EX, Z, NX, NXl, 1.0, pc[1]);
+  trig_mul_add_d(EY, Z, NY, NYl, -1.0, pc[1]);
+  // P2 = EX EY - NX NY
+  trig_mul_add_d(NX, NXl, NY, NYl, -1.0, pc[2]);
+  // P3 = EX NY + NX EY
+  trig_mul_add_d(EX, Z, NY, NYl, 1.0, pc[3]);
+  trig_mul_add_d(NX, NXl, EY, Z, 1.0, pc[3]);
+  // theta derivatives: Pt0 = -EY EYt + NY NYt, Pt1 = -(EYt NY + EY NYt),
+  // Pt2 = EX EYt - NX NYt, Pt3 = EX NYt + NX EYt
+  trig_mul_add_d(NY, NYl, NYt, NYtl, 1.0, ptc[0]);
+  trig_mul_add_d(EYt, Z, NY, NYl, -1.0, ptc[1]);
+  trig_mul_add_d(EY, Z, NYt, NYtl, -1.0, ptc[1]);
+  trig_mul_add_d(NX, NXl, NYt, NYtl, -1.0, ptc[2]);
+  trig_mul_add_d(EX, Z, NYt, NYtl, 1.0, ptc[3]);
+  trig_mul_add_d(NX, NXl, EYt, Z, 1.0, ptc[3]);
+}
+
+// Per (event, site) constants of the adjoint beside SiteC: the latitude and
+// gamma derivatives of the effective interferometers' pattern polynomials
+// (SiteC::jk, sqrt(weff) included) and the latitude derivatives of the
+// arrival-time coefficients.
+struct AdjSiteC {
+  double jl[2][4][5];                   // d jk / d latitude
+  double jg[2][4][5];                   // d jk / d gamma
+  double k1l, k1tl, k0tl;               // d(k1, k1t, k0t)/d latitude
+  double pad;
+};
+
+// sc: the site's SiteC (site_setup) with the same arm_on.
+__host__ __device__ inline void adj_site_setup(const double* p, const SiteDesc& sd, const SiteC& sc,
+                                               AdjSiteC& as, uint32_t arm_on = 7u) {
+  const double th = p[3], psi = p[6];
   const double c2p = cos(2.0 * psi), s2p = sin(2.0 * psi);
-  sa.cdl = cos(sd.lon - ph);
-  sa.sdl = sin(sd.lon - ph);
   const double ct = cos(th), st = sin(th), sl = sin(sd.lat), cl = cos(sd.lat);
-  sa.ct = ct; sa.st = st; sa.sl = sl; sa.cl = cl;
-  sa.slct = sl * ct;
-  sa.clst = cl * st;
-  sa.k1 = -kREarthS * cl * st;
-  sa.k1t = -kREarthS * cl * ct;
-  sa.k0t = kREarthS * sl * st;
-  sa.xp_fac = exp(4.14 * (log(ec.piM) + log(sd.f0)));
-  sa.ix_fac = sd.f0 * ec.piM;
-  sa.x_fac = 1.0 / sa.ix_fac;
-  sa.S0inv = 1.0 / sd.S0;
-  sa.tab_kind = sd.psd_kind;
-  sa.tab_f = sd.tab_f;
-  sa.tab_S = sd.tab_S;
-  sa.tab_n = sd.tab_n;
-  for (int r = 0; r < 2; ++r)
-    for (int j = 0; j < 4; ++j) sa.alpha[r][j] = sa.beta[r][j] = sa.alpha_g[r][j] = sa.beta_g[r][j] = 0.0;
+  as.k1l = kREarthS * sl * st;
+  as.k1tl = kREarthS * sl * ct;
+  as.k0tl = kREarthS * cl * st;
+  as.pad = 0.0;
+  // gamma derivatives of the effective interferometers' pattern maps
+  double alg[2][4] = {}, beg[2][4] = {};
   if (sd.shape == 1) {
-    double al[3][4], be[3][4], alg[3][4], beg[3][4];
+    double al[3][4], be[3][4], ag[3][4], bg[3][4];
     for (int k = 0; k < 3; ++k)
-      pattern_map_g(sd.gamma + kPi / 6.0 + kTwoPi * k / 3.0, kPi / 3.0, c2p, s2p, al[k], be[k], alg[k], beg[k]);
+      pattern_map_g(sd.gamma + kPi / 6.0 + kTwoPi * k / 3.0, kPi / 3.0, c2p, s2p, al[k], be[k], ag[k], bg[k]);
     if ((arm_on & 7u) == 7u) {
       for (int j = 0; j < 4; ++j) {
-        sa.alpha[0][j] = al[0][j] + al[1][j]; sa.beta[0][j] = be[0][j] + be[1][j];
-        sa.alpha[1][j] = al[0][j] - al[1][j]; sa.beta[1][j] = be[0][j] - be[1][j];
-        sa.alpha_g[0][j] = alg[0][j] + alg[1][j]; sa.beta_g[0][j] = beg[0][j] + beg[1][j];
-        sa.alpha_g[1][j] = alg[0][j] - alg[1][j]; sa.beta_g[1][j] = beg[0][j] - beg[1][j];
+        alg[0][j] = ag[0][j] + ag[1][j]; beg[0][j] = bg[0][j] + bg[1][j];
+        alg[1][j] = ag[0][j] - ag[1][j]; beg[1][j] = bg[0][j] - bg[1][j];
       }
-      sa.weff[0] = 1.5; sa.weff[1] = 0.5;
-      sa.n_eff = 2;
     } else {
       int m = 0;
       for (int k = 0; k < 3; ++k)
         if (arm_on >> k & 1u) {
-          for (int j = 0; j < 4; ++j) {
-            sa.alpha[m][j] = al[k][j]; sa.beta[m][j] = be[k][j];
-            sa.alpha_g[m][j] = alg[k][j]; sa.beta_g[m][j] = beg[k][j];
-          }
-          sa.weff[m] = 1.0;
+          for (int j = 0; j < 4; ++j) { alg[m][j] = ag[k][j]; beg[m][j] = bg[k][j]; }
           ++m;
         }
-      for (int r = m; r < 2; ++r) sa.weff[r] = 0.0;
-      sa.n_eff = m;
     }
   } else {
-    pattern_map_g(sd.gamma, sd.zeta, c2p, s2p, sa.alpha[0], sa.beta[0], sa.alpha_g[0], sa.beta_g[0]);
-    sa.weff[0] = 1.0; sa.weff[1] = 0.0;
-    sa.n_eff = (arm_on & 1u) ? 1 : 0;
+    double al[4], be[4];
+    pattern_map_g(sd.gamma, sd.zeta, c2p, s2p, al, be, alg[0], beg[0]);
+  }
+  double pc[4][5], ptc[4][5], pcl[4][5], ptcl[4][5];
+  pattern_trig(ct, st, sl, cl, pc, ptc);
+  pattern_trig_lat(ct, st, sl, cl, pcl, ptcl);
+  for (int j = 0; j < 2; ++j) {
+    const double w = sqrt(sc.weff[j]);
+    for (int m = 0; m < 5; ++m) {
+      double l[4] = {0.0, 0.0, 0.0, 0.0}, g[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int i = 0; i < 4; ++i) {
+        l[0] = fma(sc.alpha[j][i], pcl[i][m], l[0]);
+        l[1] = fma(sc.beta[j][i], pcl[i][m], l[1]);
+        l[2] = fma(sc.alpha[j][i], ptcl[i][m], l[2]);
+        l[3] = fma(sc.beta[j][i], ptcl[i][m], l[3]);
+        g[0] = fma(alg[j][i], pc[i][m], g[0]);
+        g[1] = fma(beg[j][i], pc[i][m], g[1]);
+        g[2] = fma(alg[j][i], ptc[i][m], g[2]);
+        g[3] = fma(beg[j][i], ptc[i][m], g[3]);
+      }
+      for (int q = 0; q < 4; ++q) {
+        as.jl[j][q][m] = w * l[q];
+        as.jg[j][q][m] = w * g[q];
+      }
+    }
   }
 }
 
-// Accumulator slots of one site: sum Gbar dGamma along (lat, lon, gamma,
-// ln S0), dSNR^2 along the same four, and SNR^2 itself.
-enum { kAdjT = 0, kAdjS = 4, kAdjW = 8, kAdjN = 9 };
+// ----------------------------------------------------- event constants
+// The fixed vectors (length P): e3, e6, v0 = (dlnA c+, 0, -c+/dL, 0, 0,
+// dc+/di, 0, 0, 0...), w1 = (dlnA cx, 0, -cx/dL, 0, 0, dcx/di, 0, 0, 0...),
+// and gamma0 = -e4 + Omega e7 (the part of gamma that does not depend on
+// the point).
+enum { kXe3 = 0, kXe6, kXv0, kXw1, kXg0, kNX };
 
-// ------------------------------------------------------ one grid point
-// Adds the contribution of grid point k and site sa to acc[kAdjN].  Gb is the
-// symmetric P x P matrix Gbar of the event (row-major).
-//
-// The derivative vectors D_b (b < 8) are built from the pattern values
-// F = (Fp, Fx) and their hour-angle and theta derivatives FH, Ft, and from
-// the arrival-time derivatives dH, dT; the phase-only ones are i Q c_i.  With
-// z = Gbar D held fixed, sum_b Re(dD_b . z_b^*) is linear in the derivatives
-// of those building blocks, so the point first forms the weights kappa of
-// the building blocks (reverse mode through the D formulas, values only) and
-// then contracts them with the building blocks' tangents along latitude,
-// longitude and gamma (forward mode through the site geometry).
-// Per grid point, shared by all sites: the point quantities, and
-//   gc_a = sum_i Gbar_{a, 8+i} c_i  (a < 8),   cgc = sum_ij c_i Gbar_{8+i, 8+j} c_j,
-// so that with D_{8+i} = i Q c_i the rows z_a = (Gbar D)_a for a < 8 and the
-// contraction c . z_{8:} of the phase-only rows need only Gbar[:8, :8], gc
-// and cgc (Gbar symmetric).
-struct AdjPoint {
-  Point q;
-  double gc[8], cgc;
+__host__ __device__ constexpr int xx_index(int a, int b) {
+  return a <= b ? a * kNX - (a * (a - 1)) / 2 + (b - a) : b * kNX - (b * (b - 1)) / 2 + (a - b);
+}
+__host__ __device__ constexpr int cc_index(int i, int j) {
+  return i <= j ? i * kMaxNpi - (i * (i - 1)) / 2 + (j - i) : j * kMaxNpi - (j * (j - 1)) / 2 + (i - j);
+}
+
+// Contractions of an event's (symmetrised, masked) Gbar: rows b = Mc, eta,
+// tc (the point-dependent basis rows of pi and gamma), the phase-only rows
+// 8 + i and the fixed vectors.
+struct AdjEventC {
+  double g3[6];                              // <e_a, e_b>, (a, b) = 00, 01, 07, 11, 17, 77
+  double bx[3][kNX];                         // <e_b, X>, b = Mc, eta, tc
+  double cx[kNX][kMaxNpi];                   // <e_{8+i}, X>
+  double cb[3][kMaxNpi];                     // <e_b, e_{8+i}>
+  double cc[kMaxNpi * (kMaxNpi + 1) / 2];    // <e_{8+i}, e_{8+j}>
+  double xx[kNX * (kNX + 1) / 2];            // <X, Y>
+  double cpl, ccr;                           // c+, cx
+  int32_t ok, pad;
 };
 
+// gb(i, j): Gbar_ij, symmetric, zero outside the event's rows.
+template <class GB>
+__host__ __device__ inline void adj_event_setup(const EventC& ec, int npi, const GB& gb, AdjEventC& ae) {
+  const int P = 8 + npi;
+  double X[kNX][8];
+  for (int x = 0; x < kNX; ++x)
+    for (int r = 0; r < 8; ++r) X[x][r] = 0.0;
+  X[kXe3][3] = 1.0;
+  X[kXe6][6] = 1.0;
+  X[kXv0][0] = ec.dlnA_dMc * ec.cplus; X[kXv0][2] = -ec.cplus * ec.inv_dL; X[kXv0][5] = ec.dcplus;
+  X[kXw1][0] = ec.dlnA_dMc * ec.ccross; X[kXw1][2] = -ec.ccross * ec.inv_dL; X[kXw1][5] = ec.dcross;
+  X[kXg0][4] = -1.0; X[kXg0][7] = kOmegaE;
+  double GX[kNX][8 + kMaxNpi];                 // Gbar X
+  for (int x = 0; x < kNX; ++x)
+    for (int r = 0; r < P; ++r) {
+      double t = 0.0;
+      for (int c = 0; c < 8; ++c) t = fma(gb(r, c), X[x][c], t);
+      GX[x][r] = t;
+    }
+  const int rows[3] = {0, 1, 7};
+  ae.g3[0] = gb(0, 0); ae.g3[1] = gb(0, 1); ae.g3[2] = gb(0, 7);
+  ae.g3[3] = gb(1, 1); ae.g3[4] = gb(1, 7); ae.g3[5] = gb(7, 7);
+  for (int b = 0; b < 3; ++b)
+    for (int x = 0; x < kNX; ++x) ae.bx[b][x] = GX[x][rows[b]];
+  for (int x = 0; x < kNX; ++x)
+    for (int i = 0; i < kMaxNpi; ++i) ae.cx[x][i] = i < npi ? GX[x][8 + i] : 0.0;
+  for (int b = 0; b < 3; ++b)
+    for (int i = 0; i < kMaxNpi; ++i) ae.cb[b][i] = i < npi ? gb(rows[b], 8 + i) : 0.0;
+  for (int i = 0; i < kMaxNpi; ++i)
+    for (int j = i; j < kMaxNpi; ++j) ae.cc[cc_index(i, j)] = (i < npi && j < npi) ? gb(8 + i, 8 + j) : 0.0;
+  for (int x = 0; x < kNX; ++x)
+    for (int y = x; y < kNX; ++y) {
+      double t = 0.0;
+      for (int r = 0; r < 8; ++r) t = fma(X[y][r], GX[x][r], t);
+      ae.xx[xx_index(x, y)] = t;
+    }
+  ae.cpl = ec.cplus;
+  ae.ccr = ec.ccross;
+  ae.pad = 0;
+}
+
+// Accumulator slots of one site: sum Gbar dGamma along (lat, lon, gamma,
+// ln S0), dSNR^2 along (lat, lon, gamma), and SNR^2 itself (its ln S0
+// derivative is minus that).
+enum { kAdjT = 0, kAdjS = 4, kAdjW = 7, kAdjN = 8 };
+
+// ------------------------------------------------------ one grid point
+// The point quantities shared by all sites: the inner products of pi and
+// gamma with each other and with the fixed vectors.
+struct AdjPoint {
+  Point q;
+  double pX[kNX];        // <pi, X>
+  double gX[4];          // <gamma, X>, X = e3, e6, v0, w1
+  double pp, pg, gg;     // <pi, pi>, <pi, gamma>, <gamma, gamma>
+};
+
+// vrec: v, 1/v and v^-12.42 at the point (GridWalk), or NULL.
 template <int NPI, bool ROT>
-__host__ __device__ inline void adjoint_point_setup(const EventC& ec, const double* Gb, int32_t k,
-                                                    AdjPoint& ap) {
-  constexpr int P = 8 + NPI;
-  point_setup<true, false, PhaseOnly<NPI>::ecc>(ec, k, true, ROT, ap.q);
+__host__ __device__ inline void adjoint_point_setup(const EventC& ec, const AdjEventC& ae, int32_t k,
+                                                    AdjPoint& ap, const double* vrec = nullptr) {
+  point_setup<true, false, PhaseOnly<NPI>::ecc>(ec, k, true, ROT, ap.q, kPsdF64, vrec);
+  const Point& q = ap.q;
   double c[NPI];
-  phase_only_coefficients<NPI>(ec, ap.q, c);
-  double cg[NPI];
+  phase_only_coefficients<NPI>(ec, q, c);
+  // u_b = <e_b, C>, C = sum c_i e_{8+i}; cCc = <C, C>
+  double u[3];
 #pragma unroll
-  for (int a = 0; a < 8; ++a) {
+  for (int b = 0; b < 3; ++b) {
     double t = 0.0;
 #pragma unroll
-    for (int i = 0; i < NPI; ++i) t = fma(Gb[a * P + 8 + i], c[i], t);
-    ap.gc[a] = t;
+    for (int i = 0; i < NPI; ++i) t = fma(ae.cb[b][i], c[i], t);
+    u[b] = t;
   }
+  double cCc = 0.0;
 #pragma unroll
   for (int i = 0; i < NPI; ++i) {
     double t = 0.0;
 #pragma unroll
-    for (int j = 0; j < NPI; ++j) t = fma(Gb[(8 + i) * P + 8 + j], c[j], t);
-    cg[i] = t;
+    for (int j = 0; j < NPI; ++j) t = fma(ae.cc[cc_index(i, j)], c[j], t);
+    cCc = fma(c[i], t, cCc);
   }
-  double t = 0.0;
+  // pi = pMc e0 + pEta e1 + tf e7 + C
+  const double pm = q.pMc, pe = q.pEta, tf = q.tf;
 #pragma unroll
-  for (int i = 0; i < NPI; ++i) t = fma(c[i], cg[i], t);
-  ap.cgc = t;
+  for (int x = 0; x < kNX; ++x) {
+    double t = fma(pm, ae.bx[0][x], fma(pe, ae.bx[1][x], tf * ae.bx[2][x]));
+#pragma unroll
+    for (int i = 0; i < NPI; ++i) t = fma(c[i], ae.cx[x][i], t);
+    ap.pX[x] = t;
+  }
+  const double pe0 = fma(pm, ae.g3[0], fma(pe, ae.g3[1], fma(tf, ae.g3[2], u[0])));   // <pi, e0>
+  const double pe1 = fma(pm, ae.g3[1], fma(pe, ae.g3[3], fma(tf, ae.g3[4], u[1])));   // <pi, e1>
+  const double pe7 = fma(pm, ae.g3[2], fma(pe, ae.g3[4], fma(tf, ae.g3[5], u[2])));   // <pi, e7>
+  ap.pp = fma(pm, pe0, fma(pe, pe1, fma(tf, pe7, fma(pm, u[0], fma(pe, u[1], fma(tf, u[2], cCc))))));
+  // gamma = gMc e0 + gEta e1 + gamma0 (gMc = gEta = 0 without rotation)
+  const double gm = q.gMc, ge = q.gEta;
+#pragma unroll
+  for (int x = 0; x < 4; ++x) ap.gX[x] = fma(gm, ae.bx[0][x], fma(ge, ae.bx[1][x], ae.xx[xx_index(kXg0, x)]));
+  ap.pg = fma(gm, pe0, fma(ge, pe1, ap.pX[kXg0]));
+  const double ge0 = fma(gm, ae.g3[0], fma(ge, ae.g3[1], 2.0 * ae.bx[0][kXg0]));
+  const double ge1 = fma(gm, ae.g3[1], fma(ge, ae.g3[3], 2.0 * ae.bx[1][kXg0]));
+  ap.gg = fma(gm, ge0, fma(ge, ge1, ae.xx[xx_index(kXg0, kXg0)]));
+}
+
+// Second hour-angle derivative of a trigonometric polynomial of SiteC::jk
+// (m4c = -4 cos 2H, m4s = -4 sin 2H).
+__host__ __device__ inline double trig_dHH(const double c[5], const SiteTrig& sp, double m4c, double m4s) {
+  return fma(c[4], m4s, fma(c[3], m4c, -fma(c[1], sp.cH, c[2] * sp.sH)));
 }
 
 // Adds the contribution of one site at the point to acc[kAdjN].
-//
-// Order of the work: the site geometry is evaluated as values only; for each
-// effective interferometer the derivative vectors, z and the reverse weights
-// kappa of the building blocks are formed and folded (times 2w) into the
-// adjoints of the site's pattern vectors P, PH, Pt (4 each) and of dH, dT,
-// since Fp = alpha . P etc. are linear in them; gamma moves only alpha and
-// beta, so its terms are taken per interferometer from their gamma
-// derivatives.  After the last interferometer, one forward pass through the
-// geometry gives the latitude and longitude tangents of P, PH, Pt, dH and dT,
-// contracted with those adjoints.  Only the values and the adjoints are live
-// across the interferometers.
-template <int NPI>
-__host__ __device__ inline void adjoint_site(const EventC& ec, const SiteA& sa, const double* Gb,
+template <bool TAB>
+__host__ __device__ inline void adjoint_site(const AdjEventC& ae, const SiteC& sc, const AdjSiteC& as,
                                              const AdjPoint& ap, double* acc) {
-  constexpr int P = 8 + NPI;
   const Point& q = ap.q;
-  // hour angle, pattern vectors and arrival-time derivatives: values
-  double Pv[4], PH[4], Pt[4], dHv, dTv;
-  {
-    // the site's E/N frame components of the polarisation frame and their H
-    // and theta derivatives (formed again for the reverse pass below rather
-    // than kept live across the interferometers)
-    const double cH = q.cth * sa.cdl - q.sth * sa.sdl;
-    const double sH = q.sth * sa.cdl + q.cth * sa.sdl;
-    const double EX = cH, EY = -(sa.ct * sH), NX = -(sa.sl * sH), NY = -(sa.slct * cH + sa.clst);
-    const double EXh = -sH, EYh = -(sa.ct * cH), NXh = -(sa.sl * cH), NYh = sa.slct * sH;
-    const double EYt = sa.st * sH, NYt = sa.st * (sa.sl * cH) - sa.ct * sa.cl;
-    Pv[0] = 0.5 * (EX * EX - NX * NX - EY * EY + NY * NY);
-    Pv[1] = EX * NX - EY * NY;
-    Pv[2] = EX * EY - NX * NY;
-    Pv[3] = EX * NY + NX * EY;
-    PH[0] = EX * EXh - NX * NXh - EY * EYh + NY * NYh;
-    PH[1] = EXh * NX + EX * NXh - EYh * NY - EY * NYh;
-    PH[2] = EXh * EY + EX * EYh - NXh * NY - NX * NYh;
-    PH[3] = EXh * NY + EX * NYh + NXh * EY + NX * EYh;
-    Pt[0] = -(EY * EYt) + NY * NYt;
-    Pt[1] = -(EYt * NY + EY * NYt);
-    Pt[2] = EX * EYt - NX * NYt;
-    Pt[3] = EX * NYt + NX * EYt;
-    dHv = -(sa.k1 * sH);
-    dTv = fma(sa.k1t, cH, sa.k0t);
-  }
-  const double om0 = sa.tab_kind ? table_weight(sa.tab_f, sa.tab_S, sa.tab_n, sa.tab_kind, sa.S0inv, q.w4A2, q.f)
-                                 : psd_weight_of(sa.xp_fac, 0.0, sa.ix_fac, sa.x_fac, sa.S0inv, q);
+  SiteTrig sp;
+  site_trig<false, true, TAB>(sc, q, sp);
+  const double m4c = -2.0 * sp.p2c, m4s = 2.0 * sp.m2s;
   const double tf = q.tf;
-  const double phMc = fma(tf * dHv, q.gMc, q.pMc), phEta = fma(tf * dHv, q.gEta, q.pEta);
-  const double phT = tf * dTv, phP = -tf * dHv, phTc = tf * fma(kOmegaE, dHv, 1.0);
-  const double cplus = ec.cplus, ccross = ec.ccross, dcp = ec.dcplus, dcx = ec.dcross;
-  const double dlnA = ec.dlnA_dMc, idL = ec.inv_dL;
-  // adjoints, summed over the interferometers: Gbar:dGamma (b) and SNR^2 (s)
-  double bP[4] = {0.0, 0.0, 0.0, 0.0}, bPH[4] = {0.0, 0.0, 0.0, 0.0}, bPt[4] = {0.0, 0.0, 0.0, 0.0};
-  double sP[4] = {0.0, 0.0, 0.0, 0.0};
-  double bdH = 0.0, bdT = 0.0, bgam = 0.0, sgam = 0.0;
-  // at most two effective interferometers; unrolled, with the count the same
-  // for every lane (the second pass is skipped as a whole where unused)
+  const double a = tf * sp.dH, b = tf * sp.dT;
+  const double cp = ae.cpl, cx = ae.ccr;
+  // <rho, X> for the site's rho = pi + a gamma + b e3
+  double R[4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x) R[x] = fma(a, ap.gX[x], fma(b, ae.xx[xx_index(kXe3, x)], ap.pX[x]));
+  const double Rg = fma(a, ap.gg, fma(b, ap.gX[kXe3], ap.pg));
+  const double Rr = fma(a, ap.pg + Rg, fma(b, ap.pX[kXe3] + R[kXe3], ap.pp));   // <rho, rho>
+  const double x33 = ae.xx[xx_index(kXe3, kXe3)], x36 = ae.xx[xx_index(kXe3, kXe6)];
+  const double x66 = ae.xx[xx_index(kXe6, kXe6)];
+  // rows gamma^T Gbar M and e3^T Gbar M of the real (y0, y1, y2, y4) and
+  // imaginary (y0, y1, y3, y5) parts
+  const double rg1 = fma(-cx, Rg, 2.0 * cp * ap.gX[kXe6]);
+  const double re1 = fma(-cx, R[kXe3], 2.0 * cp * x36);
+  const double ig0 = fma(cp, Rg, -2.0 * cx * ap.gX[kXe6]);
+  const double ie0 = fma(cp, R[kXe3], -2.0 * cx * x36);
+  const double Rg_r[4] = {ap.gX[kXv0], rg1, cp * ap.gg, cp * ap.gX[kXe3]};
+  const double Re_r[4] = {ae.xx[xx_index(kXe3, kXv0)], re1, cp * ap.gX[kXe3], cp * x33};
+  const double Rg_i[4] = {ig0, ap.gX[kXw1], cx * ap.gg, cx * ap.gX[kXe3]};
+  const double Re_i[4] = {ie0, ae.xx[xx_index(kXe3, kXw1)], cx * ap.gX[kXe3], cx * x33};
+  // rows 0 and 1 of Hr + Hi (the y0, y1 rows, where both parts meet)
+  const double f = 4.0 * cp * cx * R[kXe6];
+  const double h00 = ae.xx[xx_index(kXv0, kXv0)] + fma(cp * cp, Rr, fma(4.0 * cx * cx, x66, -f));
+  const double h01 = fma(-cx, R[kXv0], 2.0 * cp * ae.xx[xx_index(kXe6, kXv0)]) +
+                     fma(cp, R[kXw1], -2.0 * cx * ae.xx[xx_index(kXe6, kXw1)]);
+  const double h11 = ae.xx[xx_index(kXw1, kXw1)] + fma(cx * cx, Rr, fma(4.0 * cp * cp, x66, -f));
+  const double h02 = cp * ap.gX[kXv0], h03 = cx * ig0, h04 = cp * ae.xx[xx_index(kXe3, kXv0)], h05 = cx * ie0;
+  const double h12 = cp * rg1, h13 = cx * ap.gX[kXw1], h14 = cp * re1, h15 = cx * ae.xx[xx_index(kXe3, kXw1)];
+  const double twom = 2.0 * sp.om;
+  const double om = sp.om;
+  double wdH = 0.0, wdT = 0.0;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    if (j >= sa.n_eff) break;
-    // compiler barrier: the constants below are loaded when needed rather
-    // than all at once (register pressure)
-    asm volatile("" ::: "memory");
-    const double om = om0 * sa.weff[j];
-    double al[4], be[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      al[i] = sa.alpha[j][i];
-      be[i] = sa.beta[j][i];
+    if (j >= sc.n_eff) break;
+    const double(*C)[5] = sc.jk[j];
+    const double y0 = trig_val(C[0], sp), y1 = trig_val(C[1], sp);
+    const double y2 = trig_dH(C[0], sp), y3 = trig_dH(C[1], sp);
+    const double y4 = trig_val(C[2], sp), y5 = trig_val(C[3], sp);
+    const double tgr = fma(Rg_r[0], y0, fma(Rg_r[1], y1, fma(Rg_r[2], y2, Rg_r[3] * y4)));
+    const double ter = fma(Re_r[0], y0, fma(Re_r[1], y1, fma(Re_r[2], y2, Re_r[3] * y4)));
+    const double tgi = fma(Rg_i[0], y0, fma(Rg_i[1], y1, fma(Rg_i[2], y3, Rg_i[3] * y5)));
+    const double tei = fma(Re_i[0], y0, fma(Re_i[1], y1, fma(Re_i[2], y3, Re_i[3] * y5)));
+    const double hy0 = fma(h00, y0, fma(h01, y1, fma(h02, y2, fma(h03, y3, fma(h04, y4, h05 * y5)))));
+    const double hy1 = fma(h01, y0, fma(h11, y1, fma(h12, y2, fma(h13, y3, fma(h14, y4, h15 * y5)))));
+    // the point's Gbar-weighted quadratic form, and its gradient in y (times 2 w)
+    const double J = fma(y0, hy0, fma(y1, hy1, fma(cp, fma(y2, tgr, y4 * ter), cx * fma(y3, tgi, y5 * tei))));
+    const double g0 = twom * hy0, g1 = twom * hy1;
+    const double g2 = twom * cp * tgr, g3 = twom * cx * tgi, g4 = twom * cp * ter, g5 = twom * cx * tei;
+    // the arrival-time derivatives' adjoints (times 1/tf)
+    wdH = fma(twom, fma(cp * y0, tgi, -cx * y1 * tgr), wdH);
+    wdT = fma(twom, fma(cp * y0, tei, -cx * y1 * ter), wdT);
+    // SNR^2 = sum w |Q|^2, |Q|^2 = c+^2 y0^2 + cx^2 y1^2
+    const double q2 = fma(cp * cp * y0, y0, cx * cx * y1 * y1);
+    const double s0 = twom * cp * cp * y0, s1 = twom * cx * cx * y1;
+    // longitude (= hour angle): y0' = y2, y1' = y3
+    const double y2h = trig_dHH(C[0], sp, m4c, m4s), y3h = trig_dHH(C[1], sp, m4c, m4s);
+    const double y4h = trig_dH(C[2], sp), y5h = trig_dH(C[3], sp);
+    acc[kAdjT + 1] += fma(g0, y2, fma(g1, y3, fma(g2, y2h, fma(g3, y3h, fma(g4, y4h, g5 * y5h)))));
+    acc[kAdjS + 1] += fma(s0, y2, s1 * y3);
+    // latitude
+    {
+      const double(*L)[5] = as.jl[j];
+      const double l0 = trig_val(L[0], sp), l1 = trig_val(L[1], sp);
+      const double l2 = trig_dH(L[0], sp), l3 = trig_dH(L[1], sp);
+      const double l4 = trig_val(L[2], sp), l5 = trig_val(L[3], sp);
+      acc[kAdjT + 0] += fma(g0, l0, fma(g1, l1, fma(g2, l2, fma(g3, l3, fma(g4, l4, g5 * l5)))));
+      acc[kAdjS + 0] += fma(s0, l0, s1 * l1);
     }
-    const double Fp = dot4(al, Pv), Fx = dot4(be, Pv);
-    const double FpH = dot4(al, PH), FxH = dot4(be, PH);
-    const double Fpt = dot4(al, Pt), Fxt = dot4(be, Pt);
-    const double Qr = cplus * Fp, Qi = ccross * Fx;
-    const double QHr = cplus * FpH, QHi = ccross * FxH;
-    const double Qtr = cplus * Fpt, Qti = ccross * Fxt;
-    // D values (as in accumulate_point)
-    double Dr[8], Di[8];
-    Dr[0] = fma(Qr, dlnA, fma(QHr, q.gMc, -Qi * phMc));
-    Di[0] = fma(Qi, dlnA, fma(QHi, q.gMc, Qr * phMc));
-    Dr[1] = fma(QHr, q.gEta, -Qi * phEta);
-    Di[1] = fma(QHi, q.gEta, Qr * phEta);
-    Dr[2] = -Qr * idL;
-    Di[2] = -Qi * idL;
-    Dr[3] = fma(-Qi, phT, Qtr);
-    Di[3] = fma(Qr, phT, Qti);
-    Dr[4] = fma(-Qi, phP, -QHr);
-    Di[4] = fma(Qr, phP, -QHi);
-    Dr[5] = dcp * Fp;
-    Di[5] = dcx * Fx;
-    Dr[6] = 2.0 * cplus * Fx;
-    Di[6] = -2.0 * ccross * Fp;
-    Dr[7] = fma(kOmegaE, QHr, -Qi * phTc);
-    Di[7] = fma(kOmegaE, QHi, Qr * phTc);
-    // z = Gbar D for rows a < 8, and c . z over the phase-only rows, from
-    // Gbar[:8, :8], gc and cgc (see AdjPoint)
-    double zr[8], zi[8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      asm volatile("" ::: "memory");
-      double sr = -Qi * ap.gc[a], si = Qr * ap.gc[a];
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        sr = fma(Gb[a * P + b], Dr[b], sr);
-        si = fma(Gb[a * P + b], Di[b], si);
-      }
-      zr[a] = sr;
-      zi[a] = si;
+    // gamma
+    {
+      const double(*G)[5] = as.jg[j];
+      const double l0 = trig_val(G[0], sp), l1 = trig_val(G[1], sp);
+      const double l2 = trig_dH(G[0], sp), l3 = trig_dH(G[1], sp);
+      const double l4 = trig_val(G[2], sp), l5 = trig_val(G[3], sp);
+      acc[kAdjT + 2] += fma(g0, l0, fma(g1, l1, fma(g2, l2, fma(g3, l3, fma(g4, l4, g5 * l5)))));
+      acc[kAdjS + 2] += fma(s0, l0, s1 * l1);
     }
-    double czr = -Qi * ap.cgc, czi = Qr * ap.cgc;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      czr = fma(ap.gc[b], Dr[b], czr);
-      czi = fma(ap.gc[b], Di[b], czi);
-    }
-    // Re(D^H z) for the ln S0 term
-    double dz = fma(-Qi, czr, Qr * czi);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) dz = fma(Dr[b], zr[b], fma(Di[b], zi[b], dz));
-    // weights of the building blocks in sum_b Re(D_b z_b^*) (+ the phase-only rows)
-    const double kQr = fma(dlnA, zr[0], fma(phMc, zi[0], fma(phEta, zi[1], fma(-idL, zr[2],
-                       fma(phT, zi[3], fma(phP, zi[4], fma(phTc, zi[7], czi)))))));
-    const double kQi = fma(-phMc, zr[0], fma(dlnA, zi[0], fma(-phEta, zr[1], fma(-idL, zi[2],
-                       fma(-phT, zr[3], fma(-phP, zr[4], fma(-phTc, zr[7], -czr)))))));
-    const double kQHr = fma(q.gMc, zr[0], fma(q.gEta, zr[1], fma(kOmegaE, zr[7], -zr[4])));
-    const double kQHi = fma(q.gMc, zi[0], fma(q.gEta, zi[1], fma(kOmegaE, zi[7], -zi[4])));
-    const double kQtr = zr[3], kQti = zi[3];
-    const double kphMc = fma(-Qi, zr[0], Qr * zi[0]);
-    const double kphEta = fma(-Qi, zr[1], Qr * zi[1]);
-    const double kphT = fma(-Qi, zr[3], Qr * zi[3]);
-    const double kphP = fma(-Qi, zr[4], Qr * zi[4]);
-    const double kphTc = fma(-Qi, zr[7], Qr * zi[7]);
-    // ... mapped to the pattern values and the arrival-time derivatives
-    const double f = 2.0 * om;
-    const double kFp = f * fma(cplus, kQr, fma(dcp, zr[5], -2.0 * ccross * zi[6]));
-    const double kFx = f * fma(ccross, kQi, fma(dcx, zi[5], 2.0 * cplus * zr[6]));
-    const double kFpH = f * (cplus * kQHr), kFxH = f * (ccross * kQHi);
-    const double kFpt = f * (cplus * kQtr), kFxt = f * (ccross * kQti);
-    bdH = fma(f * tf, fma(q.gMc, kphMc, fma(q.gEta, kphEta, fma(kOmegaE, kphTc, -kphP))), bdH);
-    bdT = fma(f * tf, kphT, bdT);
-    const double sFp = f * (Qr * cplus), sFx = f * (Qi * ccross);
-    double ag[4], bg[4];                      // d alpha / d gamma, d beta / d gamma
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      bP[i] = fma(kFp, al[i], fma(kFx, be[i], bP[i]));
-      bPH[i] = fma(kFpH, al[i], fma(kFxH, be[i], bPH[i]));
-      bPt[i] = fma(kFpt, al[i], fma(kFxt, be[i], bPt[i]));
-      sP[i] = fma(sFp, al[i], fma(sFx, be[i], sP[i]));
-      ag[i] = sa.alpha_g[j][i];
-      bg[i] = sa.beta_g[j][i];
-    }
-    const double gFp = dot4(ag, Pv), gFx = dot4(bg, Pv);
-    bgam = fma(kFp, gFp, fma(kFx, gFx, fma(kFpH, dot4(ag, PH), fma(kFxH, dot4(bg, PH),
-           fma(kFpt, dot4(ag, Pt), fma(kFxt, dot4(bg, Pt), bgam))))));
-    sgam = fma(sFp, gFp, fma(sFx, gFx, sgam));
-    const double q2 = fma(Qr, Qr, Qi * Qi);
-    acc[kAdjT + 3] = fma(-om, dz, acc[kAdjT + 3]);
-    acc[kAdjS + 3] = fma(-om, q2, acc[kAdjS + 3]);
+    acc[kAdjT + 3] = fma(-om, J, acc[kAdjT + 3]);
     acc[kAdjW] = fma(om, q2, acc[kAdjW]);
   }
-  // reverse pass through the geometry: the weights of the pattern vectors
-  // (bP, bPH, bPt; sP for SNR^2) taken back to the frame components EX, EY,
-  // NX, NY, their H derivatives (h) and theta derivatives (t) ...
-  asm volatile("" ::: "memory");
-  const double cH = q.cth * sa.cdl - q.sth * sa.sdl;
-  const double sH = q.sth * sa.cdl + q.cth * sa.sdl;
-  const double EX = cH, EY = -(sa.ct * sH), NX = -(sa.sl * sH), NY = -(sa.slct * cH + sa.clst);
-  const double EXh = -sH, EYh = -(sa.ct * cH), NXh = -(sa.sl * cH), NYh = sa.slct * sH;
-  const double EYt = sa.st * sH, NYt = sa.st * (sa.sl * cH) - sa.ct * sa.cl;
-  const double aEX = fma(bP[0], EX, fma(bP[1], NX, fma(bP[2], EY, fma(bP[3], NY, fma(bPH[0], EXh,
-                     fma(bPH[1], NXh, fma(bPH[2], EYh, fma(bPH[3], NYh, fma(bPt[2], EYt, bPt[3] * NYt)))))))));
-  const double aEY = fma(-bP[0], EY, fma(-bP[1], NY, fma(bP[2], EX, fma(bP[3], NX, fma(-bPH[0], EYh,
-                     fma(-bPH[1], NYh, fma(bPH[2], EXh, fma(bPH[3], NXh, fma(-bPt[0], EYt, -bPt[1] * NYt)))))))));
-  const double aNX = fma(-bP[0], NX, fma(bP[1], EX, fma(-bP[2], NY, fma(bP[3], EY, fma(-bPH[0], NXh,
-                     fma(bPH[1], EXh, fma(-bPH[2], NYh, fma(bPH[3], EYh, fma(-bPt[2], NYt, bPt[3] * EYt)))))))));
-  const double aNY = fma(bP[0], NY, fma(-bP[1], EY, fma(-bP[2], NX, fma(bP[3], EX, fma(bPH[0], NYh,
-                     fma(-bPH[1], EYh, fma(-bPH[2], NXh, fma(bPH[3], EXh, fma(bPt[0], NYt, -bPt[1] * EYt)))))))));
-  const double aEXh = fma(bPH[0], EX, fma(bPH[1], NX, fma(bPH[2], EY, bPH[3] * NY)));
-  const double aEYh = fma(-bPH[0], EY, fma(-bPH[1], NY, fma(bPH[2], EX, bPH[3] * NX)));
-  const double aNXh = fma(-bPH[0], NX, fma(bPH[1], EX, fma(-bPH[2], NY, bPH[3] * EY)));
-  const double aNYh = fma(bPH[0], NY, fma(-bPH[1], EY, fma(-bPH[2], NX, bPH[3] * EX)));
-  const double aEYt = fma(-bPt[0], EY, fma(-bPt[1], NY, fma(bPt[2], EX, bPt[3] * NX)));
-  const double aNYt = fma(bPt[0], NY, fma(-bPt[1], EY, fma(-bPt[2], NX, bPt[3] * EX)));
-  const double sEX = fma(sP[0], EX, fma(sP[1], NX, fma(sP[2], EY, sP[3] * NY)));
-  const double sEY = fma(-sP[0], EY, fma(-sP[1], NY, fma(sP[2], EX, sP[3] * NX)));
-  const double sNX = fma(-sP[0], NX, fma(sP[1], EX, fma(-sP[2], NY, sP[3] * EY)));
-  const double sNY = fma(sP[0], NY, fma(-sP[1], EY, fma(-sP[2], NX, sP[3] * EX)));
-  // ... and contracted with their derivatives.  Longitude enters only through
-  // the hour angle H: dEX/dH = EXh etc., dEXh/dH = -EX, dEYh/dH = -EY,
-  // dNXh/dH = -NX, dNYh/dH = -(NY + clst), dEYt/dH = st cH, dNYt/dH =
-  // -st sl sH, d dH/dH = -k1 cH, d dT/dH = -k1t sH.
-  const double glon = fma(aEX, EXh, fma(aEY, EYh, fma(aNX, NXh, fma(aNY, NYh,
-                      fma(-aEXh, EX, fma(-aEYh, EY, fma(-aNXh, NX, fma(-aNYh, NY + sa.clst,
-                      fma(aEYt, sa.st * cH, fma(-aNYt, sa.st * sa.sl * sH,
-                      fma(-bdH, sa.k1 * cH, -bdT * sa.k1t * sH)))))))))));
-  const double slon = fma(sEX, EXh, fma(sEY, EYh, fma(sNX, NXh, sNY * NYh)));
-  // Latitude: sl' = cl, cl' = -sl, so EX, EY, EXh, EYh, EYt do not move,
-  // dNX = -cl sH, dNY = sl st - cl ct cH, dNXh = -cl cH, dNYh = cl ct sH,
-  // dNYt = st cl cH + sl ct; the delay coefficients k1 = -R cl st,
-  // k1t = -R cl ct, k0t = R sl st give d dH = -R sl st sH and
-  // d dT = R (sl ct cH + cl st).
-  const double cl = sa.cl, sl = sa.sl, ct = sa.ct, st = sa.st;
-  const double dNY = fma(sl, st, -cl * ct * cH);
-  const double glat = fma(aNX, -cl * sH, fma(aNY, dNY, fma(aNXh, -cl * cH, fma(aNYh, cl * ct * sH,
-                      fma(aNYt, fma(st * cl, cH, sl * ct), fma(bdH, -kREarthS * sl * st * sH,
-                      bdT * kREarthS * fma(sl * ct, cH, cl * st)))))));
-  const double slat = fma(sNX, -cl * sH, sNY * dNY);
-  acc[kAdjT + 0] += glat;
-  acc[kAdjT + 1] += glon;
-  acc[kAdjS + 0] += slat;
-  acc[kAdjS + 1] += slon;
-  acc[kAdjT + 2] += bgam;
-  acc[kAdjS + 2] += sgam;
+  // arrival-time derivatives: dDelta/dH = -k1 sin H, dDelta/dth = k1t cos H + k0t
+  //   d/dH:   d(dDelta/dH) = -k1 cos H,      d(dDelta/dth) = -k1t sin H
+  //   d/dlat: d(dDelta/dH) = -k1l sin H,     d(dDelta/dth) = k1tl cos H + k0tl
+  acc[kAdjT + 1] += tf * fma(wdH, -sc.k1 * sp.cH, -wdT * sc.k1t * sp.sH);
+  acc[kAdjT + 0] += tf * fma(wdH, -as.k1l * sp.sH, wdT * fma(as.k1tl, sp.cH, as.k0tl));
 }
 
 // One grid point and one site (host checks).
 template <int NPI, bool ROT>
-__host__ __device__ inline void adjoint_point(const EventC& ec, const SiteA& sa, const double* Gb,
-                                              int32_t k, double* acc) {
+__host__ __device__ inline void adjoint_point(const EventC& ec, const AdjEventC& ae, const SiteC& sc,
+                                              const AdjSiteC& as, int32_t k, double* acc) {
   AdjPoint ap;
-  adjoint_point_setup<NPI, ROT>(ec, Gb, k, ap);
-  adjoint_site<NPI>(ec, sa, Gb, ap, acc);
+  adjoint_point_setup<NPI, ROT>(ec, ae, k, ap);
+  adjoint_site<true>(ae, sc, as, ap, acc);
 }
 
 }  // namespace gwf

@@ -52,12 +52,15 @@ struct CombineArgs {
   int64_t base;               // first (event, slot) pair of the launch (set by the launcher)
 };
 
-// The adjoint over work items (gwf_plan_adjoint): one workgroup per item of
-// the plan, the plan's per-event constants, the sites' constants with their
-// gamma derivatives formed per item in LDS, each item's per-site sums
-// written to its slot.
-struct AdjItemsArgs {
-  const double* par;          // [13][ld]: theta, phi, psi of each event for the site constants
+// The adjoint over work items (gwf_plan_adjoint).  AdjEventC and AdjSiteC
+// are declared in gwf_adjoint.hpp.
+struct AdjEventC;
+struct AdjSiteC;
+
+// One lane per event: the contractions of its Gbar and its sites' pattern
+// derivatives, after the plan's set-up kernel (EventC, SiteC).
+struct AdjSetupArgs {
+  const double* par;          // [13][ld]: theta and psi of each event
   int64_t ld, n;
   const uint8_t* active;      // [n_ifo][ld] or NULL
   const uint32_t* par_mask;   // [n] or NULL
@@ -65,6 +68,19 @@ struct AdjItemsArgs {
   const double* gbar;         // [P][P][n]
   const int32_t* status;      // [n] or NULL: events with a nonzero status contribute zero
   const EventC* evc;
+  const SiteC* sic;
+  AdjEventC* aec;             // [n]
+  AdjSiteC* asc;              // [n][n_site]
+};
+
+// One workgroup per item of the plan; the constants of the set-up kernels;
+// each item's per-site sums written to its slot.
+struct AdjItemsArgs {
+  NetDesc net;
+  const EventC* evc;
+  const SiteC* sic;
+  const AdjEventC* aec;
+  const AdjSiteC* asc;
   const Item* items;          // one workgroup per item, in this order
   int32_t n_items;
   double* partial;            // [n_items][n_site][8]; NaN where the event is left out
@@ -81,7 +97,11 @@ struct AdjCombineArgs {
   double* grad;               // [n_site][4]
 };
 
+hipError_t launch_adjoint_setup(const AdjSetupArgs& a, int npi, hipStream_t s);
 hipError_t launch_adjoint_items(const AdjItemsArgs& a, int npi, bool rot, hipStream_t s);
+// bytes of the adjoint's per-event and per-site constants
+size_t adjoint_event_bytes();
+size_t adjoint_site_bytes();
 hipError_t launch_adjoint_combine(const AdjCombineArgs& a, hipStream_t s);
 int adjoint_items_block();
 

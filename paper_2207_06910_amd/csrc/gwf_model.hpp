@@ -1056,8 +1056,10 @@ __host__ __device__ inline void site_trig(const SiteC& sc, const Point& q, SiteT
 }
 
 // A trigonometric polynomial of SiteC::jk at the point, and its H derivative.
+// The constant term is added last: the coefficients sit in scalar registers,
+// and as the first addend it would need copying into vector registers.
 __host__ __device__ inline double trig_val(const double c[5], const SiteTrig& sp) {
-  return fma(c[4], sp.s2H, fma(c[3], sp.c2H, fma(c[2], sp.sH, fma(c[1], sp.cH, c[0]))));
+  return fma(c[4], sp.s2H, fma(c[3], sp.c2H, fma(c[2], sp.sH, c[1] * sp.cH))) + c[0];
 }
 __host__ __device__ inline double trig_dH(const double c[5], const SiteTrig& sp) {
   return fma(c[4], sp.p2c, fma(c[3], sp.m2s, fma(c[2], sp.cH, -c[1] * sp.sH)));

@@ -40,6 +40,9 @@ struct gwf_plan {
   int32_t* item_first = nullptr;
   double* partial = nullptr;
   size_t items_cap = 0;
+  // the adjoint's constants (allocated by the first gwf_plan_adjoint)
+  AdjEventC* aec = nullptr;
+  AdjSiteC* asc = nullptr;
   int64_t workspace_bytes = 0;
   // graph cache, keyed by the output pointers of the last replay
   hipStream_t cap = nullptr;
@@ -170,7 +173,7 @@ void free_plan(gwf_plan* p) {
   if (p->ev0) (void)hipEventDestroy(p->ev0);
   if (p->ev1) (void)hipEventDestroy(p->ev1);
   for (void* q : {(void*)p->evc, (void*)p->sic, (void*)p->npts_plan, (void*)p->items, (void*)p->item_first,
-                  (void*)p->partial})
+                  (void*)p->partial, (void*)p->aec, (void*)p->asc})
     (void)hipFree(q);
   delete p;
 }
@@ -341,11 +344,32 @@ gwf_status gwf_plan_adjoint(gwf_plan* p, const double* gbar, const int32_t* stat
   sa.ecc = p->ev.ecc; sa.fref = p->ev.f_ref_ecc;
   sa.net = p->net; sa.flags = p->flags; sa.evc = p->evc; sa.sic = p->sic; sa.status = nullptr;
   sa.active = p->ev.active;
-  hipError_t err = launch_setup(sa, s);
+  hipError_t err = hipSuccess;
+  if (!p->aec) {                    // the first adjoint call allocates its constants
+    int64_t dummy = 0;
+    err = dev_alloc((char**)&p->aec, (size_t)p->n * adjoint_event_bytes(), dummy);
+    if (err == hipSuccess)
+      err = dev_alloc((char**)&p->asc, (size_t)p->n * p->n_site_alloc * adjoint_site_bytes(), dummy);
+    if (err != hipSuccess) {
+      (void)hipFree(p->aec);
+      (void)hipFree(p->asc);
+      p->aec = nullptr;
+      p->asc = nullptr;
+      return api_fail(GWF_E_NOMEM, "adjoint constants of %lld events", (long long)p->n);
+    }
+    p->workspace_bytes += (int64_t)((size_t)p->n * (adjoint_event_bytes() + p->n_site_alloc * adjoint_site_bytes()));
+  }
+  err = launch_setup(sa, s);
+  if (err == hipSuccess) {
+    AdjSetupArgs ua{};
+    ua.par = p->ev.par; ua.ld = p->ev.ld; ua.n = p->n; ua.active = p->ev.active; ua.par_mask = p->ev.par_mask;
+    ua.net = p->net; ua.gbar = gbar; ua.status = status; ua.evc = p->evc; ua.sic = p->sic;
+    ua.aec = p->aec; ua.asc = p->asc;
+    err = launch_adjoint_setup(ua, p->npi, s);
+  }
   if (err == hipSuccess) {
     AdjItemsArgs aa{};
-    aa.par = p->ev.par; aa.ld = p->ev.ld; aa.n = p->n; aa.active = p->ev.active; aa.par_mask = p->ev.par_mask;
-    aa.net = p->net; aa.gbar = gbar; aa.status = status; aa.evc = p->evc;
+    aa.net = p->net; aa.evc = p->evc; aa.sic = p->sic; aa.aec = p->aec; aa.asc = p->asc;
     aa.items = p->items; aa.n_items = p->n_items; aa.partial = p->partial;
     err = launch_adjoint_items(aa, p->npi, p->rot, s);
   }

@@ -81,21 +81,28 @@ template <bool TIDAL, bool ROT>
 static void one_event_adjoint(const double* p, double fmin, double fmax, int32_t n, const NetDesc& nd,
                               const double* Gb, double w_snr, double w_fisher, double* ge) {
   const uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u);
+  constexpr int NPI = TIDAL ? 5 : 3, P = 8 + NPI;
   EventC ec;
   event_setup(p, fmin, fmax, n, flags, ec);
   for (int i = 0; i < nd.n_site * 4; ++i) ge[i] = 0.0;
   if (ec.status) return;
+  AdjEventC ae;
+  adj_event_setup(ec, NPI, [&](int i, int j) { return Gb[i * P + j]; }, ae);
   double acc[kMaxSites][kAdjN] = {};
   for (int s = 0; s < nd.n_site; ++s) {
-    SiteA sa;
-    site_setup_adj(p, nd.site[s], ec, sa);
-    for (int32_t k = 0; k < ec.n; ++k) adjoint_point<TIDAL ? 5 : 3, ROT>(ec, sa, Gb, k, acc[s]);
+    SiteC sc;
+    AdjSiteC as;
+    site_setup(p, nd.site[s], ec, sc);
+    adj_site_setup(p, nd.site[s], sc, as);
+    for (int32_t k = 0; k < ec.n; ++k) adjoint_point<NPI, ROT>(ec, ae, sc, as, k, acc[s]);
   }
   double W = 0.0;
   for (int s = 0; s < nd.n_site; ++s) W += acc[s][kAdjW];
   for (int s = 0; s < nd.n_site; ++s)
-    for (int m = 0; m < 4; ++m)
-      ge[s * 4 + m] = w_fisher * acc[s][kAdjT + m] + w_snr * acc[s][kAdjS + m] / (2.0 * W);
+    for (int m = 0; m < 4; ++m) {
+      const double dS = m < 3 ? acc[s][kAdjS + m] : -acc[s][kAdjW];
+      ge[s * 4 + m] = w_fisher * acc[s][kAdjT + m] + w_snr * dS / (2.0 * W);
+    }
 }
 
 extern "C" int model_adjoint_host(int64_t n, const double* par, int64_t ld, const double* fmin,

@@ -53,18 +53,28 @@ template <int NPI, bool ROT, bool TAB>
 __device__ __attribute__((always_inline)) inline void adjoint_sums(const EventC& ec, const AdjEventC& ae, const SiteC* sc, const AdjSiteC* as,
                                     int n_site, int k0, int k1, double* accl) {
   const int tid = threadIdx.x;
-  // v = exp(ln v) is evaluated at every point (not carried from point to
-  // point as in the Fisher kernels): the sum of Gbar-weighted terms cancels
-  // strongly when Gbar is an ill-conditioned covariance, so the grid values
-  // must not depend on where a work item starts for the batched and the
-  // per-event forms to agree to rounding
+  // v, 1/v and v^-12.42 walk from point to point (GridWalk), evaluated
+  // directly where a block of kABlock points starts on a multiple of
+  // kAnchor and carried by exact ratios in between.  The sum of
+  // Gbar-weighted terms cancels strongly when Gbar is an ill-conditioned
+  // covariance, so the grid values must not depend on where a work item
+  // starts: an item that starts between anchors walks from the anchor below
+  // (item starts are multiples of kABlock), and the batched and per-event
+  // forms see the same values at every point.
+  constexpr int kAnchor = 16 * kABlock;
+  const int ka = k0 - k0 % kAnchor;
+  GridWalk gw;
+  gw.start(ec, ka + tid, kABlock);
+  for (int kb = ka; kb < k0; kb += kABlock) gw.step();
   const int iters = (k1 - k0 + kABlock - 1) / kABlock;
   for (int it = 0; it < iters; ++it) {
     asm volatile("" ::: "memory");   // constants are re-read rather than held in registers
-    const int k = k0 + it * kABlock + tid;
+    const int kb = k0 + it * kABlock;
+    if (it > 0 && kb % kAnchor == 0) gw.anchor(ec, kb + tid);
+    const int k = kb + tid;
     if (k < k1) {
       AdjPoint ap;
-      adjoint_point_setup<NPI, ROT>(ec, ae, k, ap);
+      adjoint_point_setup<NPI, ROT>(ec, ae, k, ap, gw.val);
       for (int s = 0; s < n_site; ++s) {
         asm volatile("" ::: "memory");
         double acc[kAdjN];
@@ -75,6 +85,7 @@ __device__ __attribute__((always_inline)) inline void adjoint_sums(const EventC&
         for (int i = 0; i < kSlots; ++i) atomicAdd(&accl[(s * kSlots + i) * kABlock + tid], acc[i]);
       }
     }
+    gw.step();
   }
 }
 

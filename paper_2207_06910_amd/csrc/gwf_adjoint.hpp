@@ -193,6 +193,12 @@ struct AdjEventC {
   double cc[kMaxNpi * (kMaxNpi + 1) / 2];    // <e_{8+i}, e_{8+j}>
   double xx[kNX * (kNX + 1) / 2];            // <X, Y>
   double cpl, ccr;                           // c+, cx
+  // products of the above that the per-site rows need (see adjoint_site)
+  double h00c, h11c;                         // <v0,v0> + 4 cx^2 <e6,e6>, <w1,w1> + 4 c+^2 <e6,e6>
+  double h01c;                               // 2 c+ <e6,v0> - 2 cx <e6,w1>
+  double h04, h15;                           // c+ <e3,v0>, cx <e3,w1>
+  double cpx33, cxx33;                       // c+ <e3,e3>, cx <e3,e3>
+  double cp2x36, cx2x36;                     // 2 c+ <e3,e6>, 2 cx <e3,e6>
   int32_t ok, pad;
 };
 
@@ -234,6 +240,18 @@ __host__ __device__ inline void adj_event_setup(const EventC& ec, int npi, const
     }
   ae.cpl = ec.cplus;
   ae.ccr = ec.ccross;
+  const double cp = ec.cplus, cx = ec.ccross;
+  const double x66 = ae.xx[xx_index(kXe6, kXe6)], x33 = ae.xx[xx_index(kXe3, kXe3)];
+  const double x36 = ae.xx[xx_index(kXe3, kXe6)];
+  ae.h00c = ae.xx[xx_index(kXv0, kXv0)] + 4.0 * cx * cx * x66;
+  ae.h11c = ae.xx[xx_index(kXw1, kXw1)] + 4.0 * cp * cp * x66;
+  ae.h01c = 2.0 * cp * ae.xx[xx_index(kXe6, kXv0)] - 2.0 * cx * ae.xx[xx_index(kXe6, kXw1)];
+  ae.h04 = cp * ae.xx[xx_index(kXe3, kXv0)];
+  ae.h15 = cx * ae.xx[xx_index(kXe3, kXw1)];
+  ae.cpx33 = cp * x33;
+  ae.cxx33 = cx * x33;
+  ae.cp2x36 = 2.0 * cp * x36;
+  ae.cx2x36 = 2.0 * cx * x36;
   ae.pad = 0;
 }
 
@@ -250,6 +268,10 @@ struct AdjPoint {
   double pX[kNX];        // <pi, X>
   double gX[4];          // <gamma, X>, X = e3, e6, v0, w1
   double pp, pg, gg;     // <pi, pi>, <pi, gamma>, <gamma, gamma>
+  // products the per-site rows take from them
+  double cpgg, cxgg, cpg3, cxg3;   // c+ <g,g>, cx <g,g>, c+ <g,e3>, cx <g,e3>
+  double h02, h13;                 // c+ <g,v0>, cx <g,w1>
+  double cp2g6, cx2g6;             // 2 c+ <g,e6>, 2 cx <g,e6>
 };
 
 // vrec: v, 1/v and v^-12.42 at the point (GridWalk), or NULL.
@@ -298,6 +320,15 @@ __host__ __device__ inline void adjoint_point_setup(const EventC& ec, const AdjE
   const double ge0 = fma(gm, ae.g3[0], fma(ge, ae.g3[1], 2.0 * ae.bx[0][kXg0]));
   const double ge1 = fma(gm, ae.g3[1], fma(ge, ae.g3[3], 2.0 * ae.bx[1][kXg0]));
   ap.gg = fma(gm, ge0, fma(ge, ge1, ae.xx[xx_index(kXg0, kXg0)]));
+  const double cp = ae.cpl, cx = ae.ccr;
+  ap.cpgg = cp * ap.gg;
+  ap.cxgg = cx * ap.gg;
+  ap.cpg3 = cp * ap.gX[kXe3];
+  ap.cxg3 = cx * ap.gX[kXe3];
+  ap.h02 = cp * ap.gX[kXv0];
+  ap.h13 = cx * ap.gX[kXw1];
+  ap.cp2g6 = 2.0 * cp * ap.gX[kXe6];
+  ap.cx2g6 = 2.0 * cx * ap.gX[kXe6];
 }
 
 // Second hour-angle derivative of a trigonometric polynomial of SiteC::jk
@@ -323,28 +354,21 @@ __host__ __device__ inline void adjoint_site(const AdjEventC& ae, const SiteC& s
   for (int x = 0; x < 4; ++x) R[x] = fma(a, ap.gX[x], fma(b, ae.xx[xx_index(kXe3, x)], ap.pX[x]));
   const double Rg = fma(a, ap.gg, fma(b, ap.gX[kXe3], ap.pg));
   const double Rr = fma(a, ap.pg + Rg, fma(b, ap.pX[kXe3] + R[kXe3], ap.pp));   // <rho, rho>
-  const double x33 = ae.xx[xx_index(kXe3, kXe3)], x36 = ae.xx[xx_index(kXe3, kXe6)];
-  const double x66 = ae.xx[xx_index(kXe6, kXe6)];
   // rows gamma^T Gbar M and e3^T Gbar M of the real (y0, y1, y2, y4) and
   // imaginary (y0, y1, y3, y5) parts
-  const double rg1 = fma(-cx, Rg, 2.0 * cp * ap.gX[kXe6]);
-  const double re1 = fma(-cx, R[kXe3], 2.0 * cp * x36);
-  const double ig0 = fma(cp, Rg, -2.0 * cx * ap.gX[kXe6]);
-  const double ie0 = fma(cp, R[kXe3], -2.0 * cx * x36);
-  const double Rg_r[4] = {ap.gX[kXv0], rg1, cp * ap.gg, cp * ap.gX[kXe3]};
-  const double Re_r[4] = {ae.xx[xx_index(kXe3, kXv0)], re1, cp * ap.gX[kXe3], cp * x33};
-  const double Rg_i[4] = {ig0, ap.gX[kXw1], cx * ap.gg, cx * ap.gX[kXe3]};
-  const double Re_i[4] = {ie0, ae.xx[xx_index(kXe3, kXw1)], cx * ap.gX[kXe3], cx * x33};
+  const double rg1 = fma(-cx, Rg, ap.cp2g6);
+  const double re1 = fma(-cx, R[kXe3], ae.cp2x36);
+  const double ig0 = fma(cp, Rg, -ap.cx2g6);
+  const double ie0 = fma(cp, R[kXe3], -ae.cx2x36);
   // rows 0 and 1 of Hr + Hi (the y0, y1 rows, where both parts meet)
   const double f = 4.0 * cp * cx * R[kXe6];
-  const double h00 = ae.xx[xx_index(kXv0, kXv0)] + fma(cp * cp, Rr, fma(4.0 * cx * cx, x66, -f));
-  const double h01 = fma(-cx, R[kXv0], 2.0 * cp * ae.xx[xx_index(kXe6, kXv0)]) +
-                     fma(cp, R[kXw1], -2.0 * cx * ae.xx[xx_index(kXe6, kXw1)]);
-  const double h11 = ae.xx[xx_index(kXw1, kXw1)] + fma(cx * cx, Rr, fma(4.0 * cp * cp, x66, -f));
-  const double h02 = cp * ap.gX[kXv0], h03 = cx * ig0, h04 = cp * ae.xx[xx_index(kXe3, kXv0)], h05 = cx * ie0;
-  const double h12 = cp * rg1, h13 = cx * ap.gX[kXw1], h14 = cp * re1, h15 = cx * ae.xx[xx_index(kXe3, kXw1)];
+  const double h00 = fma(cp * cp, Rr, ae.h00c - f);
+  const double h11 = fma(cx * cx, Rr, ae.h11c - f);
+  const double h01 = fma(-cx, R[kXv0], fma(cp, R[kXw1], ae.h01c));
+  const double h03 = cx * ig0, h05 = cx * ie0, h12 = cp * rg1, h14 = cp * re1;
   const double twom = 2.0 * sp.om;
   const double om = sp.om;
+  const double wp = twom * cp, wx = twom * cx;     // 2 w c+, 2 w cx
   double wdH = 0.0, wdT = 0.0;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -353,35 +377,36 @@ __host__ __device__ inline void adjoint_site(const AdjEventC& ae, const SiteC& s
     const double y0 = trig_val(C[0], sp), y1 = trig_val(C[1], sp);
     const double y2 = trig_dH(C[0], sp), y3 = trig_dH(C[1], sp);
     const double y4 = trig_val(C[2], sp), y5 = trig_val(C[3], sp);
-    const double tgr = fma(Rg_r[0], y0, fma(Rg_r[1], y1, fma(Rg_r[2], y2, Rg_r[3] * y4)));
-    const double ter = fma(Re_r[0], y0, fma(Re_r[1], y1, fma(Re_r[2], y2, Re_r[3] * y4)));
-    const double tgi = fma(Rg_i[0], y0, fma(Rg_i[1], y1, fma(Rg_i[2], y3, Rg_i[3] * y5)));
-    const double tei = fma(Re_i[0], y0, fma(Re_i[1], y1, fma(Re_i[2], y3, Re_i[3] * y5)));
-    const double hy0 = fma(h00, y0, fma(h01, y1, fma(h02, y2, fma(h03, y3, fma(h04, y4, h05 * y5)))));
-    const double hy1 = fma(h01, y0, fma(h11, y1, fma(h12, y2, fma(h13, y3, fma(h14, y4, h15 * y5)))));
+    const double tgr = fma(ap.gX[kXv0], y0, fma(rg1, y1, fma(ap.cpgg, y2, ap.cpg3 * y4)));
+    const double ter = fma(ae.xx[xx_index(kXe3, kXv0)], y0, fma(re1, y1, fma(ap.cpg3, y2, ae.cpx33 * y4)));
+    const double tgi = fma(ig0, y0, fma(ap.gX[kXw1], y1, fma(ap.cxgg, y3, ap.cxg3 * y5)));
+    const double tei = fma(ie0, y0, fma(ae.xx[xx_index(kXe3, kXw1)], y1, fma(ap.cxg3, y3, ae.cxx33 * y5)));
+    const double hy0 = fma(h00, y0, fma(h01, y1, fma(ap.h02, y2, fma(h03, y3, fma(ae.h04, y4, h05 * y5)))));
+    const double hy1 = fma(h01, y0, fma(h11, y1, fma(h12, y2, fma(ap.h13, y3, fma(h14, y4, ae.h15 * y5)))));
     // the point's Gbar-weighted quadratic form, and its gradient in y (times 2 w)
     const double J = fma(y0, hy0, fma(y1, hy1, fma(cp, fma(y2, tgr, y4 * ter), cx * fma(y3, tgi, y5 * tei))));
     const double g0 = twom * hy0, g1 = twom * hy1;
-    const double g2 = twom * cp * tgr, g3 = twom * cx * tgi, g4 = twom * cp * ter, g5 = twom * cx * tei;
-    // the arrival-time derivatives' adjoints (times 1/tf)
-    wdH = fma(twom, fma(cp * y0, tgi, -cx * y1 * tgr), wdH);
-    wdT = fma(twom, fma(cp * y0, tei, -cx * y1 * ter), wdT);
-    // SNR^2 = sum w |Q|^2, |Q|^2 = c+^2 y0^2 + cx^2 y1^2
-    const double q2 = fma(cp * cp * y0, y0, cx * cx * y1 * y1);
-    const double s0 = twom * cp * cp * y0, s1 = twom * cx * cx * y1;
+    const double g2 = wp * tgr, g3 = wx * tgi, g4 = wp * ter, g5 = wx * tei;
+    // Q = (c+ y0, cx y1); the arrival-time derivatives' adjoints (times 1/tf)
+    const double Qr = cp * y0, Qi = cx * y1;
+    wdH = fma(twom, fma(Qr, tgi, -Qi * tgr), wdH);
+    wdT = fma(twom, fma(Qr, tei, -Qi * ter), wdT);
+    // SNR^2 = sum w |Q|^2 and its gradient in (y0, y1)
+    const double q2 = fma(Qr, Qr, Qi * Qi);
+    const double s0 = wp * Qr, s1 = wx * Qi;
     // longitude (= hour angle): y0' = y2, y1' = y3
     const double y2h = trig_dHH(C[0], sp, m4c, m4s), y3h = trig_dHH(C[1], sp, m4c, m4s);
     const double y4h = trig_dH(C[2], sp), y5h = trig_dH(C[3], sp);
-    acc[kAdjT + 1] += fma(g0, y2, fma(g1, y3, fma(g2, y2h, fma(g3, y3h, fma(g4, y4h, g5 * y5h)))));
-    acc[kAdjS + 1] += fma(s0, y2, s1 * y3);
+    acc[kAdjT + 1] = fma(g0, y2, fma(g1, y3, fma(g2, y2h, fma(g3, y3h, fma(g4, y4h, fma(g5, y5h, acc[kAdjT + 1]))))));
+    acc[kAdjS + 1] = fma(s0, y2, fma(s1, y3, acc[kAdjS + 1]));
     // latitude
     {
       const double(*L)[5] = as.jl[j];
       const double l0 = trig_val(L[0], sp), l1 = trig_val(L[1], sp);
       const double l2 = trig_dH(L[0], sp), l3 = trig_dH(L[1], sp);
       const double l4 = trig_val(L[2], sp), l5 = trig_val(L[3], sp);
-      acc[kAdjT + 0] += fma(g0, l0, fma(g1, l1, fma(g2, l2, fma(g3, l3, fma(g4, l4, g5 * l5)))));
-      acc[kAdjS + 0] += fma(s0, l0, s1 * l1);
+      acc[kAdjT + 0] = fma(g0, l0, fma(g1, l1, fma(g2, l2, fma(g3, l3, fma(g4, l4, fma(g5, l5, acc[kAdjT + 0]))))));
+      acc[kAdjS + 0] = fma(s0, l0, fma(s1, l1, acc[kAdjS + 0]));
     }
     // gamma
     {
@@ -389,8 +414,8 @@ __host__ __device__ inline void adjoint_site(const AdjEventC& ae, const SiteC& s
       const double l0 = trig_val(G[0], sp), l1 = trig_val(G[1], sp);
       const double l2 = trig_dH(G[0], sp), l3 = trig_dH(G[1], sp);
       const double l4 = trig_val(G[2], sp), l5 = trig_val(G[3], sp);
-      acc[kAdjT + 2] += fma(g0, l0, fma(g1, l1, fma(g2, l2, fma(g3, l3, fma(g4, l4, g5 * l5)))));
-      acc[kAdjS + 2] += fma(s0, l0, s1 * l1);
+      acc[kAdjT + 2] = fma(g0, l0, fma(g1, l1, fma(g2, l2, fma(g3, l3, fma(g4, l4, fma(g5, l5, acc[kAdjT + 2]))))));
+      acc[kAdjS + 2] = fma(s0, l0, fma(s1, l1, acc[kAdjS + 2]));
     }
     acc[kAdjT + 3] = fma(-om, J, acc[kAdjT + 3]);
     acc[kAdjW] = fma(om, q2, acc[kAdjW]);

@@ -818,6 +818,13 @@ struct GridWalk {
     val[1] *= ratio[1];
     val[2] *= ratio[2];
   }
+  // the values at point k evaluated directly again (ratios kept)
+  __host__ __device__ inline void anchor(const EventC& ec, int32_t k) {
+    const double L = fma((double)k, ec.dlnv, ec.lnv0);
+    val[0] = exp(L);
+    val[1] = exp(-L);
+    val[2] = exp(-12.42 * L);
+  }
 };
 
 // Number of phase-only Fisher parameters (Phic, chi1z, chi2z, then Lambda1,

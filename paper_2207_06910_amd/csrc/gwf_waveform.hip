@@ -22,14 +22,19 @@ namespace {
 constexpr int kWBlock = 256;
 
 // Per-site constants of the strain loop: rotation to the site's hour angle,
-// the geometry of its E/N vectors, the delay, and for each computed arm the
-// pattern maps with the inclination factors folded in:
-// Re part of the projected amplitude = m[j][0..3] . P, Im part = m[j][4..7] . P.
+// the delay, and for each computed arm the projected amplitude's real and
+// imaginary parts (c+ F+ and cx Fx, inclination factors folded in) as
+// trigonometric polynomials in the hour angle H: coefficients of
+// (1, cos H, sin H, cos 2H, sin 2H).
 struct WaveSite {
-  double cdl, sdl, ct, sl, slct, clst, k1, k0;
-  double m[2][8];
+  double cdl, sdl, k1, k0;
+  double m[2][2][5];
   int32_t n_arm, pad;
 };
+
+__device__ inline double trig5(const double c[5], double cH, double sH, double c2H, double s2H) {
+  return fma(c[4], s2H, fma(c[3], c2H, fma(c[2], sH, c[1] * cH))) + c[0];
+}
 
 // Event e's inputs: the 13 parameters (no tidal rows without tides), e0 and
 // its reference frequency (with the eccentric flag, else zero).
@@ -42,12 +47,11 @@ __device__ inline void load_event(const WaveformArgs& a, int64_t e, bool tidal, 
 // x reduced to [-1/2, 1/2] by subtracting the nearest integer (exact).
 __device__ inline double frac_center(double x) { return x - rint(x); }
 
-__device__ inline double dot4p(const double* m, const double P[4]) {
-  return fma(m[0], P[0], fma(m[1], P[1], fma(m[2], P[2], m[3] * P[3])));
-}
-
-// sin and cos of 2 pi x for |x| <= 1/2.  FP64: the series of
-// sincos_moderate.  Mixed form: the quarter-turn q = rint(4x) and the rest
+// sin and cos of 2 pi x for |x| <= 1/2.  FP64: the quarter-turn q = rint(4x)
+// and the rest r = x - q/4 are exact in cycles (|r| <= 1/8), so t = 2 pi r
+// carries one rounding (|t| <= pi/4) and needs no Cody-Waite reduction; the
+// Taylor series of sin to t^17 and cos to t^16 truncate below 1e-18.
+// Mixed form: the quarter-turn q = rint(4x) and the rest
 // r = x - q/4 (exact, |r| <= 1/8) are taken in FP64, then the Taylor series
 // of sin (to the 9th power) and cos (to the 10th) of 2 pi r in FP32, whose
 // truncation errors (< 2e-9, < 2e-10 on |2 pi r| <= pi/4) lie below the
@@ -73,7 +77,31 @@ __device__ inline void sincos_cycles(double x, double* s, double* c) {
     *s = (double)((k & 2) ? -ss : ss);
     *c = (double)(((k + 1) & 2) ? -cc : cc);
   } else {
-    sincos_moderate(kTwoPi * x, s, c);
+    const double q = rint(4.0 * x);
+    const double t = kTwoPi * fma(-0.25, q, x);
+    const double t2 = t * t;
+    double ps = -1.0 / 355687428096000.0;          // -1/17!
+    ps = fma(ps, t2, 1.0 / 1307674368000.0);       //  1/15!
+    ps = fma(ps, t2, -1.0 / 6227020800.0);         // -1/13!
+    ps = fma(ps, t2, 1.0 / 39916800.0);            //  1/11!
+    ps = fma(ps, t2, -1.0 / 362880.0);             // -1/9!
+    ps = fma(ps, t2, 1.0 / 5040.0);                //  1/7!
+    ps = fma(ps, t2, -1.0 / 120.0);                // -1/5!
+    ps = fma(ps, t2, 1.0 / 6.0);                   //  1/3!
+    const double sr = fma(-t * t2, ps, t);
+    double pc = 1.0 / 20922789888000.0;            //  1/16!
+    pc = fma(pc, t2, -1.0 / 87178291200.0);        // -1/14!
+    pc = fma(pc, t2, 1.0 / 479001600.0);           //  1/12!
+    pc = fma(pc, t2, -1.0 / 3628800.0);            // -1/10!
+    pc = fma(pc, t2, 1.0 / 40320.0);               //  1/8!
+    pc = fma(pc, t2, -1.0 / 720.0);                // -1/6!
+    pc = fma(pc, t2, 1.0 / 24.0);                  //  1/4!
+    pc = fma(pc, t2, -0.5);                        // -1/2!
+    const double cr = fma(t2, pc, 1.0);
+    const int k = (int)q & 3;                      // angle = k quarter turns + t
+    const double ss = (k & 1) ? cr : sr, cc = (k & 1) ? sr : cr;
+    *s = (k & 2) ? -ss : ss;
+    *c = ((k + 1) & 2) ? -cc : cc;
   }
 }
 
@@ -106,12 +134,19 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
     SiteC sc;
     site_setup(p, a.net.site[tid], ec, sc);
     WaveSite& w = ws[tid];
-    w.cdl = sc.cdl; w.sdl = sc.sdl; w.ct = sc.ct; w.sl = sc.sl; w.slct = sc.slct; w.clst = sc.clst;
+    w.cdl = sc.cdl; w.sdl = sc.sdl;
     w.k1 = sc.k1; w.k0 = sc.k0;
+    double pc[4][5], ptc[4][5];
+    pattern_trig(sc.ct, sc.st, sc.sl, sc.cl, pc, ptc);
     for (int j = 0; j < 2; ++j)
-      for (int i = 0; i < 4; ++i) {
-        w.m[j][i] = ec.cplus * sc.arm_alpha[j][i];
-        w.m[j][4 + i] = ec.ccross * sc.arm_beta[j][i];
+      for (int m = 0; m < 5; ++m) {
+        double fp = 0.0, fx = 0.0;
+        for (int i = 0; i < 4; ++i) {
+          fp = fma(sc.arm_alpha[j][i], pc[i][m], fp);
+          fx = fma(sc.arm_beta[j][i], pc[i][m], fx);
+        }
+        w.m[j][0][m] = ec.cplus * fp;
+        w.m[j][1][m] = ec.ccross * fx;
       }
     w.n_arm = sc.n_arm;
   }
@@ -126,7 +161,7 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
     // explicit grids: ln v = (ln(pi M) + ln f)/3 from the given frequency
     const double L = EXPL ? (ec.lnpiM + log(ec.fx[k])) / 3.0 : fma((double)k, ec.dlnv, ec.lnv0);
     const double v = exp(L);
-    const double iv = 1.0 / v;
+    const double iv = recip(v);
     const double iv2 = iv * iv, iv5 = iv2 * iv2 * iv;
     VPow pw;
     vpow(v, L, pw);
@@ -164,21 +199,16 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
       const WaveSite& w = ws[s];
       const double cH = cth * w.cdl - sth * w.sdl;
       const double sH = sth * w.cdl + cth * w.sdl;
-      const double EX = cH, EY = -w.ct * sH, NX = -w.sl * sH, NY = -(w.slct * cH + w.clst);
-      double P[4];
-      P[0] = 0.5 * (EX * EX - NX * NX - EY * EY + NY * NY);
-      P[1] = EX * NX - EY * NY;
-      P[2] = EX * EY - NX * NY;
-      P[3] = EX * NY + NX * EY;
+      const double c2H = fma(cH, cH, -sH * sH), s2H = 2.0 * (sH * cH);
       double sn, cs;
       sincos_cycles<MIXED>(frac_center(fma(f, fma(w.k1, cH, w.k0), cyc)), &sn, &cs);
       const double ca = amp * cs, sa = amp * sn;
-      const double qr0 = dot4p(w.m[0], P), qi0 = dot4p(w.m[0] + 4, P);
+      const double qr0 = trig5(w.m[0][0], cH, sH, c2H, s2H), qi0 = trig5(w.m[0][1], cH, sH, c2H, s2H);
       const double2 h0 = make_double2(qr0 * ca - qi0 * sa, qr0 * sa + qi0 * ca);
       *o = h0;
       o += row;
       if (w.n_arm == 3) {                 // closed triangle: third arm = -(first + second)
-        const double qr1 = dot4p(w.m[1], P), qi1 = dot4p(w.m[1] + 4, P);
+        const double qr1 = trig5(w.m[1][0], cH, sH, c2H, s2H), qi1 = trig5(w.m[1][1], cH, sH, c2H, s2H);
         const double2 h1 = make_double2(qr1 * ca - qi1 * sa, qr1 * sa + qi1 * ca);
         o[0] = h1;
         o[row] = make_double2(-(h0.x + h1.x), -(h0.y + h1.y));

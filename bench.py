@@ -31,18 +31,25 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # profiles/bns1e4_hbm_counters.md (calibrated against a 256 MiB copy: fetch
 # x 2.000, write x 1.000).  Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
-    "waveform_kernel<rot,tidal>": None,
-    "waveform_kernel<rot,tidal,mixed>": None,
-    "waveform_deriv_kernel<rot,tidal>": None,
+    "items_kernel<tidal,rot>": 61.18e6,
+    "items_kernel<tidal,rot,mixed>": 61.16e6,
+    "fisher_kernel<tidal,rot>": 77.70e6,
+    "waveform_kernel<rot,tidal>": 7829.69e6,
+    "waveform_kernel<rot,tidal,mixed>": 7881.85e6,
+    "waveform_deriv_kernel<rot,tidal>": 10306.52e6,
 }
 
-# VALU instructions (wavefront instructions, SQ_INSTS_VALU) per launch of the
-# Fisher kernels on the BNS catalogue, from the instruction-counter pass
-# summarised in profiles/bns1e4_kernel_trace.md.  A wave64 VALU instruction
-# occupies its SIMD for 4 cycles, so the VALU busy fraction is
-# 4 x SQ_INSTS_VALU / (1024 SIMDs x 2.4 GHz x kernel time).  Set an entry to
-# None when its kernel changes.
-MEASURED_VALU_INSTS = {}
+# VALU instructions (wavefront instructions, SQ_INSTS_VALU, MFMA included) per
+# launch of the Fisher kernels on the BNS catalogue, from the counter pass
+# summarised in profiles/bns1e4_flop_counters.md.  A wave64 VALU instruction
+# occupies its SIMD for 4 cycles, so the VALU busy fraction at the nominal
+# clock is 4 x SQ_INSTS_VALU / (1024 SIMDs x 2.4 GHz x kernel time).  Set an
+# entry to None when its kernel changes.
+MEASURED_VALU_INSTS = {
+    "items_kernel<tidal,rot>": 1.3564e9,
+    "items_kernel<tidal,rot,mixed>": 1.3396e9,
+    "fisher_kernel<tidal,rot>": 1.4219e9,
+}
 N_SIMD, CLOCK_HZ = 1024, 2.4e9
 
 
@@ -67,32 +74,48 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_flops(wl) -> float:
-    """FP64 flops of the Fisher+SNR evaluation as formulated in gwf_model.hpp,
-    counted from the source with an FMA as 2 flops and exp, sin/cos and a
-    division as 1 each, per grid point of an event:
-      121                   point set-up (grid, amplitude, PN derivatives,
-                            sidereal angle and its derivatives)
-      100 x n_site          hour angle, pattern vectors and their
-                            derivatives, delay derivatives, PSD weight
-      217 x n_eff           patterns, derivative vectors D_a of the five
-                            rows that are not pattern combinations, their
-                            5x5 rank-2 Gram update and U_b, the pattern
-                            moments T_b and S (n_eff = 1 per L site, 2 per
-                            triangle after the closed-loop reduction)
-      9                     the point's U and W of the dL, iota, psi rows
-      6 + 23 n_c + 2 (8 NPI) + NPI + 2 NPI(NPI+1)/2
-                            phase-only derivatives (n_c = 2, or 4 with
-                            tides; NPI = n_c + 1) and their blocks.
-    The per-item epilogue that turns the moments into the 8x8 block (about
-    60 flops per lane per work item of up to 16384 points) is not counted."""
+# FP64 flops per grid point executed by the kernels, counted from their
+# gfx950 instruction stream in this build (v_fma/v_fmac = 2, v_mul/v_add = 1,
+# the MFMA as its 512 flops per four-block 4x4x4 instruction) for the
+# instantiation the benchmarks run: tides, Earth rotation, analytic PSDs.
+# Split by where the work sits: once per point, per site, per effective
+# interferometer (n_eff = 1 per L site, 2 per closed triangle).
+#   items_kernel (FP64)   point 232 (grid, amplitude, PN series, sidereal
+#                         sin/cos, phase-only coefficients, staging),
+#                         site 59 (hour angle, PSD weight, arrival-time
+#                         derivatives), interferometer 221 (six pattern
+#                         polynomials, derivative vectors, 5x5 rank-2 update,
+#                         moments); MFMA 128 (16 per 64 points)
+#   items_kernel (mixed)  the same with the PSD's rational part in FP32:
+#                         site 33 FP64 (+ 13 FP32)
+#   adjoint_items_kernel  point 435 (the point set-up and the Gbar inner
+#                         products of the point's vectors), site 121, interferometer 304
+# The counter passes (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes and
+# SQ_INSTS_VALU_MFMA_MOPS_F64 x 512) confirm these per launch.
+KERNEL_FLOPS = {
+    "items": {"point": 232, "site": 59, "ifo": 221, "mfma": 128},
+    "items_mixed": {"point": 233, "site": 33, "ifo": 221, "mfma": 128},
+    "adjoint": {"point": 435, "site": 121, "ifo": 304, "mfma": 0},
+}
+# SURVEY's dense per-(point, interferometer) count (Gram 2P(P+1), weighting
+# 2P, SNR 4, derivative assembly 8P, projection 120, PN 200 per point): the
+# work of evaluating every interferometer's full P x P Gram, which the
+# kernels' exact identities avoid
+DENSE_PER_POINT_IFO = lambda P: 2 * P * (P + 1) + 2 * P + 4 + 8 * P + 120
+
+
+def kernel_flops(wl, kind: str) -> dict:
+    """Executed FP64 flops per launch of a kernel on workload wl (KERNEL_FLOPS)."""
+    k = KERNEL_FLOPS[kind]
     n_site = len(wl.sites)
     n_eff = sum(2 if s.shape == 1 else 1 for s in wl.sites)
-    tidal = bool(wl.flags & 2)
-    n_c = 4 if tidal else 2
-    npi = n_c + 1
-    per_point = 121 + 100 * n_site + 217 * n_eff + 9 + 6 + 23 * n_c + 16 * npi + npi + npi * (npi + 1)
-    return float(per_point) * float(np.sum(wl.npts, dtype=np.int64))
+    pts = float(np.sum(wl.npts, dtype=np.int64))
+    valu = (k["point"] + k["site"] * n_site + k["ifo"] * n_eff) * pts
+    mfma = k["mfma"] * pts
+    n_ifo = sum(3 if s.shape == 1 else 1 for s in wl.sites)
+    dense = (DENSE_PER_POINT_IFO(wl.npar) * n_ifo + 200) * pts
+    return {"valu": valu, "mfma": mfma, "total": valu + mfma, "dense": dense,
+            "per_point": k["point"] + k["site"] * n_site + k["ifo"] * n_eff + k["mfma"]}
 
 
 def cpu_baseline(wl, sample: int):
@@ -267,6 +290,8 @@ def gradient_form(binding, synth, torch, args, timed) -> dict:
     log(f"gradient (mixed1e4): {ms:.3f} ms per forward+backward through a plan; plan Fisher {fwd:.3f} ms, "
         f"plan adjoint {bwd:.3f} ms ({bwd / fwd:.2f}x the forward), one-workgroup-per-event adjoint "
         f"{bwd_plain:.3f} ms")
+    fla = kernel_flops(wl, "adjoint")
+    adj_tf = fla["total"] / (bwd * 1e-3) / 1e12
     return {"gradient_mixed1e4": {"workload": "mixed1e4: 10^4 events (60% BBH, 40% BNS), five L "
                                               "sites, 11 (BBH) / 13 (BNS) parameters, d/d(lat, lon, gamma, ln S0)",
                                   "grid_points": int(wl.npts.sum()),
@@ -275,6 +300,11 @@ def gradient_form(binding, synth, torch, args, timed) -> dict:
                                   "adjoint_ms": round(bwd, 4),
                                   "adjoint_over_forward": round(bwd / fwd, 3),
                                   "adjoint_per_event_ms": round(bwd_plain, 4),
+                                  "adjoint_roofline": {
+                                      "bound": "alu", "achieved": round(adj_tf, 3), "peak": PEAK_FP64_TFLOPS,
+                                      "unit": "TFLOP/s", "frac": round(adj_tf / PEAK_FP64_TFLOPS, 4),
+                                      "flops_per_launch": fla["total"], "flops_per_point": fla["per_point"],
+                                      "timed": "the whole backward call: set-up, work items, combine, reduce"},
                                   "chunk": info["chunk"],
                                   "events_per_s": round(wl.n / (ms * 1e-3), 1)}}
 
@@ -610,14 +640,19 @@ def main():
         log("no form met its accuracy bar; reporting the plain FP64 form")
         ok = cands[:1]
     form, ms, kname, kms = min(ok, key=lambda c: c[1])
-    flops = algorithmic_flops(wl)
 
     def roofline_of(kname, kms):
-        achieved = flops / (kms * 1e-3) / 1e12
+        fl = kernel_flops(wl, "items_mixed" if "mixed" in kname else "items")
+        achieved = fl["total"] / (kms * 1e-3) / 1e12
         return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "traffic": MEASURED_TRAFFIC.get(kname),
-                "kernel": kname, "kernel_ms": round(kms, 4), "flops_per_launch": flops,
+                "traffic": MEASURED_TRAFFIC.get(kname), "traffic_unit": "bytes per launch",
+                "kernel": kname, "kernel_ms": round(kms, 4), "flops_per_launch": fl["total"],
+                "flops_per_point": fl["per_point"], "flops_mfma_per_launch": fl["mfma"],
+                "flops_model": "executed FP64 flops of the kernel's instruction stream (FMA = 2), "
+                               "VALU and MFMA, confirmed by SQ_INSTS_VALU_FLOPS_FP64 and "
+                               "SQ_INSTS_VALU_MFMA_MOPS_F64",
+                "dense_count_frac": round(fl["dense"] / (kms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
                 "valu_busy": valu_busy(kname, kms)}
     roofline = roofline_of(kname, kms)
     # the fastest form at the paper's precision, beside the headline

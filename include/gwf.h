@@ -526,7 +526,12 @@ gwf_status gwf_plan_fisher(gwf_plan* plan, double* fisher, double* snr, int32_t*
  * gwf_fisher_adjoint (grad_event [n][n_site][4], grad [n_site][4]).  Plans
  * created with GWF_MIXED return GWF_E_UNSUPPORTED.  The adjoint shares the
  * plan's workspace with gwf_plan_fisher: calls on one plan must be ordered
- * (one stream, or synchronised). */
+ * (one stream, or synchronised).  The first call on a plan allocates the
+ * adjoint's constants (the contractions of each event's Gbar, about 1 KB per
+ * event, and each site's pattern-derivative polynomials, about 0.7 KB per
+ * event and site), kept with the plan until gwf_plan_destroy and counted in
+ * gwf_plan_info's workspace_bytes; later calls allocate nothing.  Returns
+ * GWF_E_NOMEM if that allocation fails. */
 gwf_status gwf_plan_adjoint(gwf_plan* plan, const double* gbar, const int32_t* status, double w_snr,
                             double w_fisher, double* grad_event, double* grad, void* stream);
 

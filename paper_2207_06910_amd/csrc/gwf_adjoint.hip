@@ -39,7 +39,8 @@ namespace gwf {
 namespace {
 
 constexpr int kABlock = 128;
-constexpr int kSlots = kAdjN;   // LDS accumulator values per site and lane
+constexpr int kACols = kABlock / 2;   // LDS accumulator columns, one per pair of lanes
+constexpr int kSlots = kAdjN;         // LDS accumulator values per site and column
 
 __device__ inline double wave_sum_a(double x) {
 #pragma unroll
@@ -47,11 +48,16 @@ __device__ inline double wave_sum_a(double x) {
   return x;
 }
 
-// The sums of points [k0, k1) of one event into the LDS columns
-// accl[(s kSlots + i) kABlock + lane] (zeroed by the caller).
-template <int NPI, bool ROT, bool TAB>
-__device__ __attribute__((always_inline)) inline void adjoint_sums(const EventC& ec, const AdjEventC& ae, const SiteC* sc, const AdjSiteC* as,
-                                    int n_site, int k0, int k1, double* accl) {
+// The sums of points [k0, k1) of one event into LDS columns (zeroed by the
+// caller, one writer per address, so the sums are in program order):
+// PAIR = false, one column per lane, accl[(s kSlots + i) kABlock + lane];
+// PAIR = true, each pair of lanes adds its two points' values and the even
+// lane adds that to column lane / 2 of kACols, which halves the LDS a
+// workgroup needs for 3 VALU instructions per value.
+template <int NPI, bool ROT, bool TAB, bool PAIR>
+__device__ __attribute__((always_inline)) inline void adjoint_sums(const EventC& ec, const AdjEventC& ae,
+                                                                   const SiteC* sc, const AdjSiteC* as, int n_site,
+                                                                   int k0, int k1, double* accl) {
   const int tid = threadIdx.x;
   // v, 1/v and v^-12.42 walk from point to point (GridWalk), evaluated
   // directly where a block of kABlock points starts on a multiple of
@@ -72,7 +78,23 @@ __device__ __attribute__((always_inline)) inline void adjoint_sums(const EventC&
     const int kb = k0 + it * kABlock;
     if (it > 0 && kb % kAnchor == 0) gw.anchor(ec, kb + tid);
     const int k = kb + tid;
-    if (k < k1) {
+    const bool in = k < k1;
+    if (PAIR) {                      // both lanes of a pair take part in each exchange
+      AdjPoint ap;
+      if (in) adjoint_point_setup<NPI, ROT>(ec, ae, k, ap, gw.val);
+      for (int s = 0; s < n_site; ++s) {
+        asm volatile("" ::: "memory");
+        double acc[kAdjN];
+#pragma unroll
+        for (int i = 0; i < kAdjN; ++i) acc[i] = 0.0;
+        if (in) adjoint_site<TAB>(ae, sc[s], as[s], ap, acc);
+#pragma unroll
+        for (int i = 0; i < kSlots; ++i) {
+          const double v = acc[i] + __shfl_xor(acc[i], 1, 64);
+          if ((tid & 1) == 0) atomicAdd(&accl[(s * kSlots + i) * kACols + (tid >> 1)], v);
+        }
+      }
+    } else if (in) {
       AdjPoint ap;
       adjoint_point_setup<NPI, ROT>(ec, ae, k, ap, gw.val);
       for (int s = 0; s < n_site; ++s) {
@@ -89,13 +111,15 @@ __device__ __attribute__((always_inline)) inline void adjoint_sums(const EventC&
   }
 }
 
-// The site sums of the workgroup's columns, in a fixed order: wave w takes
-// the values t = w, w + 2, ...; each lane adds its two columns, then the
-// wavefront butterfly.
+// The site sums of the workgroup's columns (as adjoint_sums left them), in a
+// fixed order: wave w takes the values t = w, w + 2, ...; each lane adds its
+// columns, then the wavefront butterfly.
+template <bool PAIR>
 __device__ inline void adjoint_columns(const double* accl, int width, double* out) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int t = wave; t < width; t += kABlock / 64) {
-    const double v = wave_sum_a(accl[t * kABlock + lane] + accl[t * kABlock + 64 + lane]);
+    const double c = PAIR ? accl[t * kACols + lane] : accl[t * kABlock + lane] + accl[t * kABlock + 64 + lane];
+    const double v = wave_sum_a(c);
     if (lane == 0) out[t] = v;
   }
 }
@@ -130,7 +154,7 @@ __global__ __launch_bounds__(kABlock, 2) void adjoint_kernel(AdjointArgs a) {
   __shared__ SiteC sc[kMaxSites];
   __shared__ AdjSiteC as[kMaxSites];
   __shared__ double Gb[P * P];
-  extern __shared__ double accl[];      // [n_site][kSlots][kABlock]
+  extern __shared__ double accl[];      // [n_site][kSlots][kACols]
   __shared__ double site_acc[kMaxSites * kSlots];
   __shared__ int32_t ok;
   const int64_t e = a.base + blockIdx.x;
@@ -164,11 +188,11 @@ __global__ __launch_bounds__(kABlock, 2) void adjoint_kernel(AdjointArgs a) {
     site_setup(p, a.net.site[tid], ec, sc[tid], arms);
     adj_site_setup(p, a.net.site[tid], sc[tid], as[tid], arms);
   }
-  for (int t = tid; t < n_site * kSlots * kABlock; t += kABlock) accl[t] = 0.0;
+  for (int t = tid; t < n_site * kSlots * kACols; t += kABlock) accl[t] = 0.0;
   __syncthreads();
-  adjoint_sums<NPI, ROT, TAB>(ec, ae, sc, as, n_site, 0, ec.n, accl);
+  adjoint_sums<NPI, ROT, TAB, true>(ec, ae, sc, as, n_site, 0, ec.n, accl);
   __syncthreads();
-  adjoint_columns(accl, n_site * kSlots, site_acc);
+  adjoint_columns<true>(accl, n_site * kSlots, site_acc);
   __syncthreads();
   if (tid < n_site * 4) {
     const int s = tid >> 2, m = tid & 3;
@@ -256,9 +280,9 @@ __global__ __launch_bounds__(kABlock, 2) void adjoint_items_kernel(AdjItemsArgs 
   }
   for (int t = tid; t < width * kABlock; t += kABlock) accl[t] = 0.0;
   __syncthreads();
-  adjoint_sums<NPI, ROT, TAB>(ec, ae, sc, as, n_site, k0, k1, accl);
+  adjoint_sums<NPI, ROT, TAB, false>(ec, ae, sc, as, n_site, k0, k1, accl);
   __syncthreads();
-  adjoint_columns(accl, width, out);
+  adjoint_columns<false>(accl, width, out);
 }
 
 // One lane per event: its items' sums in item order, then the gradient terms.
@@ -354,7 +378,7 @@ void launch_adjoint_n(const AdjointArgs& a, bool rot, bool tab, dim3 grid, dim3 
 }
 
 hipError_t launch_adjoint(const AdjointArgs& a0, int npi, bool rot, hipStream_t stream) {
-  const size_t lds = sizeof(double) * (size_t)a0.net.n_site * kSlots * kABlock;
+  const size_t lds = sizeof(double) * (size_t)a0.net.n_site * kSlots * kACols;
   const bool tab = net_has_tables(a0.net);
   hipError_t err = launch_slices(a0, a0.n, 1, kABlock, [&](const AdjointArgs& a, dim3 grid, dim3 block) {
     switch (npi) {

@@ -6,10 +6,11 @@
 //                   constants, the contractions of its symmetrised Gbar
 //                   (AdjEventC) and the sites' constants (SiteC, AdjSiteC)
 //                   in LDS; every lane walks the grid with a stride of the
-//                   workgroup size, forms the point quantities once
-//                   and adds each site's contributions to its own LDS column
-//                   (one LDS add per value; every address has one writer, so
-//                   the sums are in program order); the columns are reduced in
+//                   workgroup size, forms the point quantities once, and
+//                   each pair of lanes adds its two points' contributions per
+//                   site to one LDS column (one LDS add per value; every
+//                   address has one writer, so the sums are in program
+//                   order); the columns are reduced in
 //                   a fixed order and combined into the event's gradient
 //                   terms.
 //   reduce_kernel   one workgroup per output component sums the events'
@@ -18,9 +19,10 @@
 //
 // The batched form (gwf_plan_adjoint) runs the same per-point mathematics
 // over a plan's work items:
-//   adj_setup_kernel        one lane per event: AdjEventC from Gbar and the
-//                   AdjSiteC of every site, into the plan's adjoint workspace
-//                   (the plan's set-up kernel has written EventC and SiteC);
+//   adj_setup_kernel        one lane per event (AdjEventC from Gbar) and one
+//                   per (event, site) (AdjSiteC), into the plan's adjoint
+//                   workspace (the plan's set-up kernel has written EventC
+//                   and SiteC);
 //   adjoint_items_kernel    one workgroup of 128 lanes per work item (event,
 //                   point range), in the plan's longest-first order; the
 //                   event's and sites' constants are read through the
@@ -38,9 +40,12 @@ namespace gwf {
 
 namespace {
 
-constexpr int kABlock = 128;
-constexpr int kACols = kABlock / 2;   // LDS accumulator columns, one per pair of lanes
+constexpr int kABlock = 128;          // lanes of a workgroup (both forms)
 constexpr int kSlots = kAdjN;         // LDS accumulator values per site and column
+// The grid walk's stride and anchor spacing (points): they fix the grid values
+// at every point, whatever the workgroup size.
+constexpr int kWalk = 128;
+constexpr int kAnchor = 16 * kWalk;
 
 __device__ inline double wave_sum_a(double x) {
 #pragma unroll
@@ -49,37 +54,47 @@ __device__ inline double wave_sum_a(double x) {
 }
 
 // The sums of points [k0, k1) of one event into LDS columns (zeroed by the
-// caller, one writer per address, so the sums are in program order):
-// PAIR = false, one column per lane, accl[(s kSlots + i) kABlock + lane];
+// caller, one writer per address, so the sums are in program order), by a
+// workgroup of nb lanes (a multiple of kWalk dividing kAnchor; k0 a multiple
+// of kWalk): lane t takes the points k0 + t, k0 + t + nb, ...
+// PAIR = false, one column per lane, accl[(s kSlots + i) nb + lane];
 // PAIR = true, each pair of lanes adds its two points' values and the even
-// lane adds that to column lane / 2 of kACols, which halves the LDS a
+// lane adds that to column lane / 2 of nb / 2, which halves the LDS a
 // workgroup needs for 3 VALU instructions per value.
+//
+// Grid values: v, 1/v and v^-12.42 at point k are evaluated directly at
+// a + k mod kWalk, a = the multiple of kAnchor at or below k, and carried
+// from there by (k - a) / kWalk multiplications by the exact ratio over
+// kWalk points, in that order.  The sum of Gbar-weighted terms cancels
+// strongly when Gbar is an ill-conditioned covariance, so these values must
+// not depend on where a work item starts or on the workgroup size: every
+// form (batched, per event, any nb) sees the same values at every point.
 template <int NPI, bool ROT, bool TAB, bool PAIR>
 __device__ __attribute__((always_inline)) inline void adjoint_sums(const EventC& ec, const AdjEventC& ae,
                                                                    const SiteC* sc, const AdjSiteC* as, int n_site,
-                                                                   int k0, int k1, double* accl) {
+                                                                   int k0, int k1, int nb, double* accl) {
   const int tid = threadIdx.x;
-  // v, 1/v and v^-12.42 walk from point to point (GridWalk), evaluated
-  // directly where a block of kABlock points starts on a multiple of
-  // kAnchor and carried by exact ratios in between.  The sum of
-  // Gbar-weighted terms cancels strongly when Gbar is an ill-conditioned
-  // covariance, so the grid values must not depend on where a work item
-  // starts: an item that starts between anchors walks from the anchor below
-  // (item starts are multiples of kABlock), and the batched and per-event
-  // forms see the same values at every point.
-  constexpr int kAnchor = 16 * kABlock;
-  const int ka = k0 - k0 % kAnchor;
+  const int r = tid % kWalk;             // k mod kWalk at every point of the lane
+  int k = k0 + tid;
+  int a = k - k % kAnchor;
   GridWalk gw;
-  gw.start(ec, ka + tid, kABlock);
-  for (int kb = ka; kb < k0; kb += kABlock) gw.step();
-  const int iters = (k1 - k0 + kABlock - 1) / kABlock;
-  for (int it = 0; it < iters; ++it) {
+  gw.start(ec, a + r, kWalk);
+  for (int q = (k - a) / kWalk; q > 0; --q) gw.step();
+  const int iters = (k1 - k0 + nb - 1) / nb;
+  for (int it = 0; it < iters; ++it, k += nb) {
     asm volatile("" ::: "memory");   // constants are re-read rather than held in registers
-    const int kb = k0 + it * kABlock;
-    if (it > 0 && kb % kAnchor == 0) gw.anchor(ec, kb + tid);
-    const int k = kb + tid;
+    if (it > 0) {
+      if (k - a >= kAnchor) {          // the lane's point has passed an anchor
+        a = k - k % kAnchor;
+        gw.anchor(ec, a + r);
+        for (int q = (k - a) / kWalk; q > 0; --q) gw.step();
+      } else {
+        for (int q = nb / kWalk; q > 0; --q) gw.step();
+      }
+    }
     const bool in = k < k1;
     if (PAIR) {                      // both lanes of a pair take part in each exchange
+      const int cols = nb >> 1;
       AdjPoint ap;
       if (in) adjoint_point_setup<NPI, ROT>(ec, ae, k, ap, gw.val);
       for (int s = 0; s < n_site; ++s) {
@@ -91,7 +106,7 @@ __device__ __attribute__((always_inline)) inline void adjoint_sums(const EventC&
 #pragma unroll
         for (int i = 0; i < kSlots; ++i) {
           const double v = acc[i] + __shfl_xor(acc[i], 1, 64);
-          if ((tid & 1) == 0) atomicAdd(&accl[(s * kSlots + i) * kACols + (tid >> 1)], v);
+          if ((tid & 1) == 0) atomicAdd(&accl[(s * kSlots + i) * cols + (tid >> 1)], v);
         }
       }
     } else if (in) {
@@ -104,21 +119,22 @@ __device__ __attribute__((always_inline)) inline void adjoint_sums(const EventC&
         for (int i = 0; i < kAdjN; ++i) acc[i] = 0.0;
         adjoint_site<TAB>(ae, sc[s], as[s], ap, acc);
 #pragma unroll
-        for (int i = 0; i < kSlots; ++i) atomicAdd(&accl[(s * kSlots + i) * kABlock + tid], acc[i]);
+        for (int i = 0; i < kSlots; ++i) atomicAdd(&accl[(s * kSlots + i) * nb + tid], acc[i]);
       }
     }
-    gw.step();
   }
 }
 
 // The site sums of the workgroup's columns (as adjoint_sums left them), in a
-// fixed order: wave w takes the values t = w, w + 2, ...; each lane adds its
-// columns, then the wavefront butterfly.
+// fixed order: wave w of the nb / 64 takes the values t = w, w + nb / 64, ...;
+// each lane adds its columns in column order, then the wavefront butterfly.
 template <bool PAIR>
-__device__ inline void adjoint_columns(const double* accl, int width, double* out) {
+__device__ inline void adjoint_columns(const double* accl, int width, int nb, double* out) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int t = wave; t < width; t += kABlock / 64) {
-    const double c = PAIR ? accl[t * kACols + lane] : accl[t * kABlock + lane] + accl[t * kABlock + 64 + lane];
+  const int cols = PAIR ? nb >> 1 : nb;
+  for (int t = wave; t < width; t += nb >> 6) {
+    double c = 0.0;
+    for (int j = lane; j < cols; j += 64) c += accl[t * cols + j];
     const double v = wave_sum_a(c);
     if (lane == 0) out[t] = v;
   }
@@ -154,7 +170,7 @@ __global__ __launch_bounds__(kABlock, 2) void adjoint_kernel(AdjointArgs a) {
   __shared__ SiteC sc[kMaxSites];
   __shared__ AdjSiteC as[kMaxSites];
   __shared__ double Gb[P * P];
-  extern __shared__ double accl[];      // [n_site][kSlots][kACols]
+  extern __shared__ double accl[];      // [n_site][kSlots][kABlock / 2]
   __shared__ double site_acc[kMaxSites * kSlots];
   __shared__ int32_t ok;
   const int64_t e = a.base + blockIdx.x;
@@ -182,17 +198,17 @@ __global__ __launch_bounds__(kABlock, 2) void adjoint_kernel(AdjointArgs a) {
     if (tid < n_site * 4) ge[tid] = 0.0;
     return;
   }
-  if (tid == 0) adj_event_setup(ec, NPI, GbarLds{Gb, P}, ae);
+  if (tid == 0) adj_event_setup<NPI>(ec, GbarLds{Gb, P}, ae);
   if (tid < n_site) {
     const uint32_t arms = site_arms_on(a.active, a.ld, e, a.net, tid);
     site_setup(p, a.net.site[tid], ec, sc[tid], arms);
     adj_site_setup(p, a.net.site[tid], sc[tid], as[tid], arms);
   }
-  for (int t = tid; t < n_site * kSlots * kACols; t += kABlock) accl[t] = 0.0;
+  for (int t = tid; t < n_site * kSlots * (kABlock / 2); t += kABlock) accl[t] = 0.0;
   __syncthreads();
-  adjoint_sums<NPI, ROT, TAB, true>(ec, ae, sc, as, n_site, 0, ec.n, accl);
+  adjoint_sums<NPI, ROT, TAB, true>(ec, ae, sc, as, n_site, 0, ec.n, kABlock, accl);
   __syncthreads();
-  adjoint_columns<true>(accl, n_site * kSlots, site_acc);
+  adjoint_columns<true>(accl, n_site * kSlots, kABlock, site_acc);
   __syncthreads();
   if (tid < n_site * 4) {
     const int s = tid >> 2, m = tid & 3;
@@ -222,35 +238,42 @@ __global__ __launch_bounds__(kABlock) void reduce_kernel(const double* __restric
 }
 
 // ---------------------------------------------------- batched (work items)
-// One lane per event: the contractions of its Gbar (AdjEventC, ok = 0 where
-// the event is left out) and its sites' AdjSiteC, after the plan's set-up
-// kernel has written EventC and SiteC.
+// After the plan's set-up kernel has written EventC and SiteC: lanes
+// [0, n) take one event each, the contractions of its Gbar (AdjEventC, ok = 0
+// where the event is left out); lanes [n, n + n n_site) one (event, site)
+// pair each, its AdjSiteC (not written for an event whose set-up failed).
 template <int NPI>
-__global__ void adj_setup_kernel(AdjSetupArgs a) {
+__global__ __launch_bounds__(64) void adj_setup_kernel(AdjSetupArgs a) {
   constexpr int P = PhaseOnly<NPI>::P;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.n) return;
-  const EventC& ec = a.evc[e];
-  AdjEventC ae;
-  const GbarOf gb{a.gbar, a.n, e, P, event_rows(a.par_mask, e)};
-  adj_event_setup(ec, NPI, gb, ae);
-  int32_t ok = ec.status == 0 && (a.status == nullptr || a.status[e] == 0);
-  for (int i = 0; i < P && ok; ++i)
-    for (int j = 0; j < P; ++j)
-      if (!finite(gb(i, j))) ok = 0;
-  ae.ok = ok;
-  a.aec[e] = ae;
-  if (!ok) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n_site = a.net.n_site;
+  if (t < a.n) {
+    const int64_t e = t;
+    const EventC& ec = a.evc[e];
+    const GbarOf gb{a.gbar, a.n, e, P, event_rows(a.par_mask, e)};
+    int32_t ok = ec.status == 0 && (a.status == nullptr || a.status[e] == 0);
+    for (int i = 0; i < P; ++i)               // gb is symmetric: the upper triangle decides
+      for (int j = i; j < P; ++j)
+        if (!finite(gb(i, j))) ok = 0;
+    AdjEventC& ae = a.aec[e];
+    adj_event_setup<NPI>(ec, gb, ae);
+    ae.ok = ok;
+    return;
+  }
+  const int64_t u = t - a.n;
+  if (u >= a.n * n_site) return;
+  const int64_t e = u / n_site;
+  const int s = (int)(u - e * n_site);
+  if (a.evc[e].status != 0 || (a.status != nullptr && a.status[e] != 0)) return;
   double p[kNparIn] = {};
   p[3] = a.par[3 * a.ld + e];
   p[6] = a.par[6 * a.ld + e];
-  for (int s = 0; s < a.net.n_site; ++s) {
-    AdjSiteC as;
-    adj_site_setup(p, a.net.site[s], a.sic[e * a.net.n_site + s], as, site_arms_on(a.active, a.ld, e, a.net, s));
-    a.asc[e * a.net.n_site + s] = as;
-  }
+  adj_site_setup(p, a.net.site[s], a.sic[u], a.asc[u], site_arms_on(a.active, a.ld, e, a.net, s));
 }
 
+// Two wavefronts per SIMD (the sums live in LDS, 40 KB per workgroup on
+// five sites).  Larger workgroups put fewer events' constants in a compute
+// unit's scalar cache but were measured slower on the mixed BBH/BNS workload.
 template <int NPI, bool ROT, bool TAB>
 __global__ __launch_bounds__(kABlock, 2) void adjoint_items_kernel(AdjItemsArgs a) {
   extern __shared__ double accl[];        // [n_site][kSlots][kABlock]
@@ -280,9 +303,9 @@ __global__ __launch_bounds__(kABlock, 2) void adjoint_items_kernel(AdjItemsArgs 
   }
   for (int t = tid; t < width * kABlock; t += kABlock) accl[t] = 0.0;
   __syncthreads();
-  adjoint_sums<NPI, ROT, TAB, false>(ec, ae, sc, as, n_site, k0, k1, accl);
+  adjoint_sums<NPI, ROT, TAB, false>(ec, ae, sc, as, n_site, k0, k1, kABlock, accl);
   __syncthreads();
-  adjoint_columns<false>(accl, width, out);
+  adjoint_columns<false>(accl, width, kABlock, out);
 }
 
 // One lane per event: its items' sums in item order, then the gradient terms.
@@ -328,7 +351,8 @@ void launch_adjoint_items_n(const AdjItemsArgs& a, bool rot, bool tab, dim3 grid
 }
 
 hipError_t launch_adjoint_setup(const AdjSetupArgs& a, int npi, hipStream_t s) {
-  const dim3 grid((unsigned)((a.n + 127) / 128)), block(128);
+  const int64_t lanes = a.n * (1 + (int64_t)a.net.n_site);
+  const dim3 grid((unsigned)((lanes + 63) / 64)), block(64);
   switch (npi) {
     case 6: hipLaunchKernelGGL((adj_setup_kernel<6>), grid, block, 0, s, a); break;
     case 5: hipLaunchKernelGGL((adj_setup_kernel<5>), grid, block, 0, s, a); break;
@@ -360,7 +384,6 @@ hipError_t launch_adjoint_combine(const AdjCombineArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-int adjoint_items_block() { return kABlock; }
 size_t adjoint_event_bytes() { return sizeof(AdjEventC); }
 size_t adjoint_site_bytes() { return sizeof(AdjSiteC); }
 
@@ -378,7 +401,7 @@ void launch_adjoint_n(const AdjointArgs& a, bool rot, bool tab, dim3 grid, dim3 
 }
 
 hipError_t launch_adjoint(const AdjointArgs& a0, int npi, bool rot, hipStream_t stream) {
-  const size_t lds = sizeof(double) * (size_t)a0.net.n_site * kSlots * kACols;
+  const size_t lds = sizeof(double) * (size_t)a0.net.n_site * kSlots * (kABlock / 2);
   const bool tab = net_has_tables(a0.net);
   hipError_t err = launch_slices(a0, a0.n, 1, kABlock, [&](const AdjointArgs& a, dim3 grid, dim3 block) {
     switch (npi) {

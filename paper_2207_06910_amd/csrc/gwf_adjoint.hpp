@@ -123,19 +123,28 @@ __host__ __device__ inline void adj_site_setup(const double* p, const SiteDesc& 
   // gamma derivatives of the effective interferometers' pattern maps
   double alg[2][4] = {}, beg[2][4] = {};
   if (sd.shape == 1) {
-    double al[3][4], be[3][4], ag[3][4], bg[3][4];
-    for (int k = 0; k < 3; ++k)
-      pattern_map_g(sd.gamma + kPi / 6.0 + kTwoPi * k / 3.0, kPi / 3.0, c2p, s2p, al[k], be[k], ag[k], bg[k]);
+    double ag[3][4], bg[3][4];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double al[4], be[4];
+      pattern_map_g(sd.gamma + kPi / 6.0 + kTwoPi * k / 3.0, kPi / 3.0, c2p, s2p, al, be, ag[k], bg[k]);
+    }
     if ((arm_on & 7u) == 7u) {
+#pragma unroll
       for (int j = 0; j < 4; ++j) {
         alg[0][j] = ag[0][j] + ag[1][j]; beg[0][j] = bg[0][j] + bg[1][j];
         alg[1][j] = ag[0][j] - ag[1][j]; beg[1][j] = bg[0][j] - bg[1][j];
       }
-    } else {
+    } else {                                 // the active arms in arm order
       int m = 0;
+#pragma unroll
       for (int k = 0; k < 3; ++k)
         if (arm_on >> k & 1u) {
-          for (int j = 0; j < 4; ++j) { alg[m][j] = ag[k][j]; beg[m][j] = bg[k][j]; }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (m == 0) { alg[0][j] = ag[k][j]; beg[0][j] = bg[k][j]; }
+            else { alg[1][j] = ag[k][j]; beg[1][j] = bg[k][j]; }
+          }
           ++m;
         }
     }
@@ -143,28 +152,41 @@ __host__ __device__ inline void adj_site_setup(const double* p, const SiteDesc& 
     double al[4], be[4];
     pattern_map_g(sd.gamma, sd.zeta, c2p, s2p, al, be, alg[0], beg[0]);
   }
-  double pc[4][5], ptc[4][5], pcl[4][5], ptcl[4][5];
-  pattern_trig(ct, st, sl, cl, pc, ptc);
-  pattern_trig_lat(ct, st, sl, cl, pcl, ptcl);
-  for (int j = 0; j < 2; ++j) {
+  // coefficient q of effective interferometer j: sqrt(weff) (a . pm, b . pm,
+  // a . ptm, b . ptm) for the maps (a, b) and polynomials (pm, ptm) given
+  auto contract = [&](int j, const double (&a)[4], const double (&b)[4], const double (&pm)[4][5],
+                      const double (&ptm)[4][5], double (&out)[4][5]) {
     const double w = sqrt(sc.weff[j]);
+#pragma unroll
     for (int m = 0; m < 5; ++m) {
-      double l[4] = {0.0, 0.0, 0.0, 0.0}, g[4] = {0.0, 0.0, 0.0, 0.0};
+      double t[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
       for (int i = 0; i < 4; ++i) {
-        l[0] = fma(sc.alpha[j][i], pcl[i][m], l[0]);
-        l[1] = fma(sc.beta[j][i], pcl[i][m], l[1]);
-        l[2] = fma(sc.alpha[j][i], ptcl[i][m], l[2]);
-        l[3] = fma(sc.beta[j][i], ptcl[i][m], l[3]);
-        g[0] = fma(alg[j][i], pc[i][m], g[0]);
-        g[1] = fma(beg[j][i], pc[i][m], g[1]);
-        g[2] = fma(alg[j][i], ptc[i][m], g[2]);
-        g[3] = fma(beg[j][i], ptc[i][m], g[3]);
+        t[0] = fma(a[i], pm[i][m], t[0]);
+        t[1] = fma(b[i], pm[i][m], t[1]);
+        t[2] = fma(a[i], ptm[i][m], t[2]);
+        t[3] = fma(b[i], ptm[i][m], t[3]);
       }
-      for (int q = 0; q < 4; ++q) {
-        as.jl[j][q][m] = w * l[q];
-        as.jg[j][q][m] = w * g[q];
-      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out[q][m] = w * t[q];
     }
+  };
+  {
+    double pcl[4][5], ptcl[4][5];
+    pattern_trig_lat(ct, st, sl, cl, pcl, ptcl);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) { a[i] = sc.alpha[j][i]; b[i] = sc.beta[j][i]; }
+      contract(j, a, b, pcl, ptcl, as.jl[j]);
+    }
+  }
+  {
+    double pc[4][5], ptc[4][5];
+    pattern_trig(ct, st, sl, cl, pc, ptc);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) contract(j, alg[j], beg[j], pc, ptc, as.jg[j]);
   }
 }
 
@@ -190,7 +212,7 @@ struct AdjEventC {
   double bx[3][kNX];                         // <e_b, X>, b = Mc, eta, tc
   double cx[kNX][kMaxNpi];                   // <e_{8+i}, X>
   double cb[3][kMaxNpi];                     // <e_b, e_{8+i}>
-  double cc[kMaxNpi * (kMaxNpi + 1) / 2];    // <e_{8+i}, e_{8+j}>
+  double cq[kMaxNpi * (kMaxNpi + 1) / 2];    // <e_{8+i}, e_{8+j}> for i = j, twice that for i < j
   double xx[kNX * (kNX + 1) / 2];            // <X, Y>
   double cpl, ccr;                           // c+, cx
   // products of the above that the per-site rows need (see adjoint_site)
@@ -202,42 +224,61 @@ struct AdjEventC {
   int32_t ok, pad;
 };
 
-// gb(i, j): Gbar_ij, symmetric, zero outside the event's rows.
-template <class GB>
-__host__ __device__ inline void adj_event_setup(const EventC& ec, int npi, const GB& gb, AdjEventC& ae) {
-  const int P = 8 + npi;
-  double X[kNX][8];
-  for (int x = 0; x < kNX; ++x)
-    for (int r = 0; r < 8; ++r) X[x][r] = 0.0;
-  X[kXe3][3] = 1.0;
-  X[kXe6][6] = 1.0;
-  X[kXv0][0] = ec.dlnA_dMc * ec.cplus; X[kXv0][2] = -ec.cplus * ec.inv_dL; X[kXv0][5] = ec.dcplus;
-  X[kXw1][0] = ec.dlnA_dMc * ec.ccross; X[kXw1][2] = -ec.ccross * ec.inv_dL; X[kXw1][5] = ec.dcross;
-  X[kXg0][4] = -1.0; X[kXg0][7] = kOmegaE;
-  double GX[kNX][8 + kMaxNpi];                 // Gbar X
-  for (int x = 0; x < kNX; ++x)
-    for (int r = 0; r < P; ++r) {
-      double t = 0.0;
-      for (int c = 0; c < 8; ++c) t = fma(gb(r, c), X[x][c], t);
-      GX[x][r] = t;
+// gb(i, j): Gbar_ij, symmetric, zero outside the event's rows.  The fixed
+// vectors have at most three nonzero entries each, so Gbar X takes those
+// columns of Gbar only; every index is fixed at compile time.
+template <int NPI, class GB>
+__host__ __device__ inline void adj_event_setup(const EventC& ec, const GB& gb, AdjEventC& ae) {
+  const double v0a = ec.dlnA_dMc * ec.cplus, v0b = -ec.cplus * ec.inv_dL, v0c = ec.dcplus;
+  const double w1a = ec.dlnA_dMc * ec.ccross, w1b = -ec.ccross * ec.inv_dL, w1c = ec.dcross;
+  // X_x^T v for a vector v on the binary's eight rows (Mc, eta, dL, theta,
+  // phi, iota, psi, tc)
+  auto xdot = [&](int x, const double* v) -> double {
+    switch (x) {
+      case kXe3: return v[3];
+      case kXe6: return v[6];
+      case kXv0: return fma(v0c, v[5], fma(v0b, v[2], v0a * v[0]));
+      case kXw1: return fma(w1c, v[5], fma(w1b, v[2], w1a * v[0]));
+      default: return fma(kOmegaE, v[7], -v[4]);
     }
-  const int rows[3] = {0, 1, 7};
+  };
+  double GX[kNX][8];                           // (Gbar X)_r on the eight rows
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    double row[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) row[c] = gb(r, c);
+#pragma unroll
+    for (int x = 0; x < kNX; ++x) GX[x][r] = xdot(x, row);
+  }
+#pragma unroll
+  for (int i = 0; i < kMaxNpi; ++i) {
+    double row[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) row[c] = i < NPI ? gb(8 + i, c) : 0.0;
+#pragma unroll
+    for (int x = 0; x < kNX; ++x) ae.cx[x][i] = i < NPI ? xdot(x, row) : 0.0;
+  }
+  constexpr int rows[3] = {0, 1, 7};
   ae.g3[0] = gb(0, 0); ae.g3[1] = gb(0, 1); ae.g3[2] = gb(0, 7);
   ae.g3[3] = gb(1, 1); ae.g3[4] = gb(1, 7); ae.g3[5] = gb(7, 7);
+#pragma unroll
   for (int b = 0; b < 3; ++b)
+#pragma unroll
     for (int x = 0; x < kNX; ++x) ae.bx[b][x] = GX[x][rows[b]];
-  for (int x = 0; x < kNX; ++x)
-    for (int i = 0; i < kMaxNpi; ++i) ae.cx[x][i] = i < npi ? GX[x][8 + i] : 0.0;
+#pragma unroll
   for (int b = 0; b < 3; ++b)
-    for (int i = 0; i < kMaxNpi; ++i) ae.cb[b][i] = i < npi ? gb(rows[b], 8 + i) : 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxNpi; ++i) ae.cb[b][i] = i < NPI ? gb(rows[b], 8 + i) : 0.0;
+#pragma unroll
   for (int i = 0; i < kMaxNpi; ++i)
-    for (int j = i; j < kMaxNpi; ++j) ae.cc[cc_index(i, j)] = (i < npi && j < npi) ? gb(8 + i, 8 + j) : 0.0;
+#pragma unroll
+    for (int j = i; j < kMaxNpi; ++j)
+      ae.cq[cc_index(i, j)] = (i < NPI && j < NPI) ? (i == j ? 1.0 : 2.0) * gb(8 + i, 8 + j) : 0.0;
+#pragma unroll
   for (int x = 0; x < kNX; ++x)
-    for (int y = x; y < kNX; ++y) {
-      double t = 0.0;
-      for (int r = 0; r < 8; ++r) t = fma(X[y][r], GX[x][r], t);
-      ae.xx[xx_index(x, y)] = t;
-    }
+#pragma unroll
+    for (int y = x; y < kNX; ++y) ae.xx[xx_index(x, y)] = xdot(y, GX[x]);
   ae.cpl = ec.cplus;
   ae.ccr = ec.ccross;
   const double cp = ec.cplus, cx = ec.ccross;
@@ -291,12 +332,13 @@ __host__ __device__ inline void adjoint_point_setup(const EventC& ec, const AdjE
     for (int i = 0; i < NPI; ++i) t = fma(ae.cb[b][i], c[i], t);
     u[b] = t;
   }
+  // cCc = sum_i c_i (Gbar_ii c_i + 2 sum_{j > i} Gbar_ij c_j)
   double cCc = 0.0;
 #pragma unroll
   for (int i = 0; i < NPI; ++i) {
     double t = 0.0;
 #pragma unroll
-    for (int j = 0; j < NPI; ++j) t = fma(ae.cc[cc_index(i, j)], c[j], t);
+    for (int j = i; j < NPI; ++j) t = fma(ae.cq[cc_index(i, j)], c[j], t);
     cCc = fma(c[i], t, cCc);
   }
   // pi = pMc e0 + pEta e1 + tf e7 + C
@@ -331,10 +373,14 @@ __host__ __device__ inline void adjoint_point_setup(const EventC& ec, const AdjE
   ap.cx2g6 = 2.0 * cx * ap.gX[kXe6];
 }
 
-// Second hour-angle derivative of a trigonometric polynomial of SiteC::jk
-// (m4c = -4 cos 2H, m4s = -4 sin 2H).
-__host__ __device__ inline double trig_dHH(const double c[5], const SiteTrig& sp, double m4c, double m4s) {
-  return fma(c[4], m4s, fma(c[3], m4c, -fma(c[1], sp.cH, c[2] * sp.sH)));
+// A trigonometric polynomial of SiteC::jk and its second hour-angle
+// derivative from the same partial sums: with a1 = c1 cos H + c2 sin H and
+// a2 = c3 cos 2H + c4 sin 2H, y = c0 + a1 + a2 and y'' = -(a1 + 4 a2).
+__host__ __device__ inline void trig_val_dHH(const double c[5], const SiteTrig& sp, double& y, double& yhh) {
+  const double a1 = fma(c[2], sp.sH, c[1] * sp.cH);
+  const double a2 = fma(c[4], sp.s2H, c[3] * sp.c2H);
+  y = (a1 + a2) + c[0];
+  yhh = -fma(4.0, a2, a1);
 }
 
 // Adds the contribution of one site at the point to acc[kAdjN].
@@ -344,7 +390,6 @@ __host__ __device__ inline void adjoint_site(const AdjEventC& ae, const SiteC& s
   const Point& q = ap.q;
   SiteTrig sp;
   site_trig<false, true, TAB>(sc, q, sp);
-  const double m4c = -2.0 * sp.p2c, m4s = 2.0 * sp.m2s;
   const double tf = q.tf;
   const double a = tf * sp.dH, b = tf * sp.dT;
   const double cp = ae.cpl, cx = ae.ccr;
@@ -374,7 +419,9 @@ __host__ __device__ inline void adjoint_site(const AdjEventC& ae, const SiteC& s
   for (int j = 0; j < 2; ++j) {
     if (j >= sc.n_eff) break;
     const double(*C)[5] = sc.jk[j];
-    const double y0 = trig_val(C[0], sp), y1 = trig_val(C[1], sp);
+    double y0, y1, y2h, y3h;
+    trig_val_dHH(C[0], sp, y0, y2h);
+    trig_val_dHH(C[1], sp, y1, y3h);
     const double y2 = trig_dH(C[0], sp), y3 = trig_dH(C[1], sp);
     const double y4 = trig_val(C[2], sp), y5 = trig_val(C[3], sp);
     const double tgr = fma(ap.gX[kXv0], y0, fma(rg1, y1, fma(ap.cpgg, y2, ap.cpg3 * y4)));
@@ -395,7 +442,6 @@ __host__ __device__ inline void adjoint_site(const AdjEventC& ae, const SiteC& s
     const double q2 = fma(Qr, Qr, Qi * Qi);
     const double s0 = wp * Qr, s1 = wx * Qi;
     // longitude (= hour angle): y0' = y2, y1' = y3
-    const double y2h = trig_dHH(C[0], sp, m4c, m4s), y3h = trig_dHH(C[1], sp, m4c, m4s);
     const double y4h = trig_dH(C[2], sp), y5h = trig_dH(C[3], sp);
     acc[kAdjT + 1] = fma(g0, y2, fma(g1, y3, fma(g2, y2h, fma(g3, y3h, fma(g4, y4h, fma(g5, y5h, acc[kAdjT + 1]))))));
     acc[kAdjS + 1] = fma(s0, y2, fma(s1, y3, acc[kAdjS + 1]));

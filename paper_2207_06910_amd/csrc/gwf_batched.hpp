@@ -103,7 +103,6 @@ hipError_t launch_adjoint_items(const AdjItemsArgs& a, int npi, bool rot, hipStr
 size_t adjoint_event_bytes();
 size_t adjoint_site_bytes();
 hipError_t launch_adjoint_combine(const AdjCombineArgs& a, hipStream_t s);
-int adjoint_items_block();
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 // Work items built on the device: each event's count of items of at most

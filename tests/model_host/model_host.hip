@@ -87,7 +87,7 @@ static void one_event_adjoint(const double* p, double fmin, double fmax, int32_t
   for (int i = 0; i < nd.n_site * 4; ++i) ge[i] = 0.0;
   if (ec.status) return;
   AdjEventC ae;
-  adj_event_setup(ec, NPI, [&](int i, int j) { return Gb[i * P + j]; }, ae);
+  adj_event_setup<NPI>(ec, [&](int i, int j) { return Gb[i * P + j]; }, ae);
   double acc[kMaxSites][kAdjN] = {};
   for (int s = 0; s < nd.n_site; ++s) {
     SiteC sc;

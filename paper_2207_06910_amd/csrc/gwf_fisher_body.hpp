@@ -110,7 +110,13 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
   double G[kGramAcc];
 #pragma unroll
   for (int i = 0; i < kGramAcc; ++i) G[i] = 0.0;
-  double acc[Dm::NM];
+  // The 16 MFMAs of an iteration alternate between two independent chains
+  // per accumulator (summed once at the end), so consecutive MFMAs do not wait
+  // for each other's results.  Every instantiation sums in the same order, so
+  // a tile holds the same bits whichever tile slot it occupies (e0 = 0 gives
+  // the circular matrix exactly).
+  constexpr int NC = 2;
+  double acc[Dm::NM][NC];
   const int wave = tid >> 6, lane = tid & 63;
   // four-block MFMA 4x4x4 operand layout: lane 16 k + 4 q + i holds A[q][i][k]
   // and B[q][k][i]; the result D[q][i][j] is in lane 16 i + 4 q + j.  Block q
@@ -119,7 +125,8 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
   int arow[Dm::NM], bcol[Dm::NM];
 #pragma unroll
   for (int m = 0; m < Dm::NM; ++m) {
-    acc[m] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[m][c] = 0.0;
     const int t = 4 * m + q4;
     arow[m] = t < Dm::NT ? 4 * Dm::tile_r(t) + i4 : kZeroRowA;
     bcol[m] = t < Dm::NT ? 4 * Dm::tile_c(t) + i4 : kZeroRowB;
@@ -182,7 +189,7 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
       for (int m = 0; m < Dm::NM; ++m) {
         const double av = A[arow[m]][4 * s2 + kk];
         const double bv = B[bcol[m]][4 * s2 + kk];
-        acc[m] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, bv, acc[m], 0, 0, 0);
+        acc[m][s2 % NC] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, bv, acc[m][s2 % NC], 0, 0, 0);
       }
     }
     __builtin_amdgcn_s_setprio(0);
@@ -244,7 +251,10 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
         if (j >= i) slot = NG + NX + i * NPI - (i * (i - 1)) / 2 + (j - i);
       }
     }
-    if (slot >= 0) L.red[wave][slot] = acc[m];
+    double x = acc[m][0];
+#pragma unroll
+    for (int c = 1; c < NC; ++c) x += acc[m][c];
+    if (slot >= 0) L.red[wave][slot] = x;
   }
   __syncthreads();
   if (tid < NACC) {

@@ -101,6 +101,9 @@ struct EventC {
   // sky/orientation
   double thc;                  // sidereal angle at coalescence, 2 pi tcoal
   double cplus, ccross, dcplus, dcross;   // (1+cos^2 i)/2, cos i and d/d iota
+  // their products in the per-point rows of iota, psi and the SNR density:
+  // c+^2, cx^2, c+ dcx - cx dc+, -2 c+ cx
+  double cp2, cx2, u_iota, u_psi;
   PhaseSeries ps[6];
   TauSeries ts[3];
   // waveform only: Psi_PN / (2 pi) in cycles, ln of the amplitude factor
@@ -380,6 +383,10 @@ __host__ __device__ inline void event_setup(const double* p, double fmin, double
   ec.ccross = ci;
   ec.dcplus = -ci * si;
   ec.dcross = -si;
+  ec.cp2 = ec.cplus * ec.cplus;
+  ec.cx2 = ec.ccross * ec.ccross;
+  ec.u_iota = ec.cplus * ec.dcross - ec.ccross * ec.dcplus;
+  ec.u_psi = -2.0 * ec.cplus * ec.ccross;
 
   // ---- moderate eccentricity (sec. 2.2, is_eccentric): the leading-order
   // correction -(2355/1462) e0^2 (v_ref/v)^{19/3} relative to the Newtonian
@@ -1215,9 +1222,9 @@ __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* 
 #pragma unroll
   for (int a = 0; a < 5; ++a) U[kGramRows[a]] = UR[a];
   U[2] = 0.0;
-  U[5] = (am.cplus * am.dcx - am.ccross * am.dcp) * spx;
-  U[6] = -2.0 * am.cplus * am.ccross * (spp + sxx);
-  W = fma(am.cplus * am.cplus, spp, am.ccross * am.ccross * sxx);
+  U[5] = ec.u_iota * spx;
+  U[6] = ec.u_psi * (spp + sxx);
+  W = fma(ec.cp2, spp, ec.cx2 * sxx);
   phase_only_coefficients<NPI, PSUM>(ec, q, cph);
 }
 

@@ -796,6 +796,7 @@ struct Point {
   double gMc, gEta;               // d(sidereal angle)/dMc, /deta
   double pMc, pEta;               // dPsi_PN/dMc, /deta
   double vpsd;                    // v^-12.42: the PSD's power law, shared by all sites
+  double v3, iv3;                 // v^3 and v^-3 (proportional to f and 1/f), shared by all sites
   double ecv;                     // v^-5 (v_ref/v)^{19/3} (eccentric forms, else 0)
 };
 
@@ -865,7 +866,7 @@ __host__ __device__ inline void point_setup(const EventC& ec, int32_t k, bool ne
   } else {
     L = fma((double)k, ec.dlnv, ec.lnv0);
     v = vrec ? vrec[0] : exp(L);
-    f = v * v * v * ec.inv_piM;
+    f = (v * v * v) * ec.inv_piM;
     double w = ec.wint;
     if (k == 0) w = ec.wfirst;
     if (k == ec.n - 1) w = ec.wlast;
@@ -874,6 +875,8 @@ __host__ __device__ inline void point_setup(const EventC& ec, int32_t k, bool ne
   const double iv = (!EXPL && vrec) ? vrec[1] : recip(v);
   const double iv2 = iv * iv, iv4 = iv2 * iv2, iv5 = iv4 * iv, iv7 = iv5 * iv2, iv8 = iv4 * iv4;
   q.v = v; q.iv = iv; q.L = L; q.f = f;
+  q.v3 = v * v * v;
+  q.iv3 = iv2 * iv;
   q.tf = kTwoPi * f;
   q.w4A2 = wf * ec.KA4 * iv7;
   q.vpsd = 0.0;
@@ -944,8 +947,8 @@ __host__ __device__ inline double psd_weight_of(double xp_fac, double lnx_off, d
   // x^-4.14 = xp_fac v^-12.42 with the power of v evaluated once per point
   // (PSUM), or exp(-4.14 ln x) here
   const double xp = PSUM ? xp_fac * q.vpsd : exp(-4.14 * fma(3.0, q.L, lnx_off));
-  const double ix = ix_fac * q.iv * q.iv * q.iv;   // f0/f
-  const double x = x_fac * q.v * q.v * q.v;        // f/f0
+  const double ix = ix_fac * q.iv3;                // f0/f
+  const double x = x_fac * q.v3;                   // f/f0
   const double ix2 = ix * ix;
   const double x2 = x * x;
   const double num = fma(0.5 * x2, x2, 1.0 - x2);
@@ -1007,8 +1010,7 @@ __host__ __device__ inline void psd_weight_f32(const SiteC& sc, const Point& q, 
     return;
   }
   const float xp = (float)(sc.xp_fac * q.vpsd);
-  const double v3 = q.v * q.v * q.v, iv3 = q.iv * q.iv * q.iv;
-  const double x = sc.x_fac * v3, ix = sc.ix_fac * iv3;
+  const double x = sc.x_fac * q.v3, ix = sc.ix_fac * q.iv3;
   const float x2 = (float)(x * x), ix2 = (float)(ix * ix);
   const float num = fmaf(0.5f * x2, x2, 1.0f - x2);
   const float den = fmaf(0.5f, x2, 1.0f);

@@ -13,13 +13,11 @@
 // One workgroup per event, lanes over grid points: each interferometer's
 // output row is written with consecutive lanes on consecutive 16-byte
 // complex values, so the kernel streams its output at HBM rate.
-#include "gwf_kernels.hpp"
+#include "gwf_waveform.hpp"
 
 namespace gwf {
 
 namespace {
-
-constexpr int kWBlock = 256;
 
 // Per-site constants of the strain loop: rotation to the site's hour angle,
 // the delay, and for each computed arm the projected amplitude's real and
@@ -34,75 +32,6 @@ struct WaveSite {
 
 __device__ inline double trig5(const double c[5], double cH, double sH, double c2H, double s2H) {
   return fma(c[4], s2H, fma(c[3], c2H, fma(c[2], sH, c[1] * cH))) + c[0];
-}
-
-// Event e's inputs: the 13 parameters (no tidal rows without tides), e0 and
-// its reference frequency (with the eccentric flag, else zero).
-__device__ inline void load_event(const WaveformArgs& a, int64_t e, bool tidal, double* p) {
-  for (int r = 0; r < 13; ++r) p[r] = (r < 11 || tidal) ? a.par[r * a.ld + e] : 0.0;
-  p[13] = a.ecc_flag && a.ecc ? a.ecc[e] : 0.0;
-  p[14] = a.ecc_flag && a.fref ? a.fref[e] : 0.0;
-}
-
-// x reduced to [-1/2, 1/2] by subtracting the nearest integer (exact).
-__device__ inline double frac_center(double x) { return x - rint(x); }
-
-// sin and cos of 2 pi x for |x| <= 1/2.  FP64: the quarter-turn q = rint(4x)
-// and the rest r = x - q/4 are exact in cycles (|r| <= 1/8), so t = 2 pi r
-// carries one rounding (|t| <= pi/4) and needs no Cody-Waite reduction; the
-// Taylor series of sin to t^17 and cos to t^16 truncate below 1e-18.
-// Mixed form: the quarter-turn q = rint(4x) and the rest
-// r = x - q/4 (exact, |r| <= 1/8) are taken in FP64, then the Taylor series
-// of sin (to the 9th power) and cos (to the 10th) of 2 pi r in FP32, whose
-// truncation errors (< 2e-9, < 2e-10 on |2 pi r| <= pi/4) lie below the
-// FP32 rounding; the absolute error is a few 1e-8 rad from rounding r and
-// about 1e-7 from the FP32 arithmetic.
-template <bool MIXED>
-__device__ inline void sincos_cycles(double x, double* s, double* c) {
-  if (MIXED) {
-    const double q = rint(4.0 * x);
-    const float t = (float)kTwoPi * (float)fma(-0.25, q, x);
-    const float t2 = t * t;
-    float ps = fmaf(t2, 1.0f / 362880.0f, -1.0f / 5040.0f);
-    ps = fmaf(ps, t2, 1.0f / 120.0f);
-    ps = fmaf(ps, t2, -1.0f / 6.0f);
-    const float sr = fmaf(t * t2, ps, t);
-    float pc = fmaf(t2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
-    pc = fmaf(pc, t2, -1.0f / 720.0f);
-    pc = fmaf(pc, t2, 1.0f / 24.0f);
-    pc = fmaf(pc, t2, -0.5f);
-    const float cr = fmaf(t2, pc, 1.0f);
-    const int k = (int)q & 3;                  // angle = k quarter turns + t
-    const float ss = (k & 1) ? cr : sr, cc = (k & 1) ? sr : cr;
-    *s = (double)((k & 2) ? -ss : ss);
-    *c = (double)(((k + 1) & 2) ? -cc : cc);
-  } else {
-    const double q = rint(4.0 * x);
-    const double t = kTwoPi * fma(-0.25, q, x);
-    const double t2 = t * t;
-    double ps = -1.0 / 355687428096000.0;          // -1/17!
-    ps = fma(ps, t2, 1.0 / 1307674368000.0);       //  1/15!
-    ps = fma(ps, t2, -1.0 / 6227020800.0);         // -1/13!
-    ps = fma(ps, t2, 1.0 / 39916800.0);            //  1/11!
-    ps = fma(ps, t2, -1.0 / 362880.0);             // -1/9!
-    ps = fma(ps, t2, 1.0 / 5040.0);                //  1/7!
-    ps = fma(ps, t2, -1.0 / 120.0);                // -1/5!
-    ps = fma(ps, t2, 1.0 / 6.0);                   //  1/3!
-    const double sr = fma(-t * t2, ps, t);
-    double pc = 1.0 / 20922789888000.0;            //  1/16!
-    pc = fma(pc, t2, -1.0 / 87178291200.0);        // -1/14!
-    pc = fma(pc, t2, 1.0 / 479001600.0);           //  1/12!
-    pc = fma(pc, t2, -1.0 / 3628800.0);            // -1/10!
-    pc = fma(pc, t2, 1.0 / 40320.0);               //  1/8!
-    pc = fma(pc, t2, -1.0 / 720.0);                // -1/6!
-    pc = fma(pc, t2, 1.0 / 24.0);                  //  1/4!
-    pc = fma(pc, t2, -0.5);                        // -1/2!
-    const double cr = fma(t2, pc, 1.0);
-    const int k = (int)q & 3;                      // angle = k quarter turns + t
-    const double ss = (k & 1) ? cr : sr, cc = (k & 1) ? sr : cr;
-    *s = (k & 2) ? -ss : ss;
-    *c = ((k + 1) & 2) ? -cc : cc;
-  }
 }
 
 template <bool ROT, bool TIDAL, bool MIXED, bool EXPL>
@@ -218,106 +147,6 @@ __global__ __launch_bounds__(kWBlock) void waveform_kernel(WaveformArgs a) {
   }
 }
 
-// The strain's derivatives with respect to the P parameters, in the rows and
-// units of the Fisher matrix (whose entries are 4 Re sum w d_a h d_b h^* / S_n):
-//   d_a h_i = A exp(2 pi i cyc_i) D_a,i,
-// D the phase-free derivative vector of the Fisher kernels for (Mc, eta, dL,
-// theta, phi, iota, psi, tc) and i Q c_a for the phase-only parameters
-// (Phic, chi1z, chi2z[, Lambda1, Lambda2][, e0]); the phase in cycles exactly as
-// for the strain.  Each arm of a triangle is projected with its own pattern
-// map.  One workgroup per event, lanes over grid points; row (a, i) of dh
-// holds parameter a at interferometer i, consecutive lanes on consecutive
-// complex values.  FP64 only.
-template <bool ROT, int NPI, bool EXPL>
-__global__ __launch_bounds__(kWBlock) void waveform_deriv_kernel(WaveformArgs a) {
-  using PO = PhaseOnly<NPI>;
-  constexpr int P = PO::P;
-  constexpr bool TIDAL = PO::tidal;
-  constexpr uint32_t flags = (TIDAL ? kFlagTidal : 0u) | (ROT ? kFlagRot : 0u) | (PO::ecc ? kFlagEcc : 0u);
-  __shared__ EventC ec;
-  __shared__ SiteC sc[kMaxSites];
-  __shared__ int32_t ok;
-  const int64_t e = a.base + blockIdx.x;
-  const int tid = threadIdx.x;
-  const int n_site = a.net.n_site;
-  if (tid == 0) {
-    double p[kNparIn];
-    load_event(a, e, TIDAL, p);
-    event_setup_grid(p, a.fmin, a.fmax, a.npts, a.goff, a.gf, e, flags, ec);
-    const int64_t b = a.offsets[e];
-    const bool range_ok = b >= 0 && b <= a.total - (int64_t)a.npts[e];
-    int32_t st = ec.status;
-    if (!range_ok) st |= kEvInvalid;
-    ok = st == 0;
-    if (a.status) a.status[e] = st;
-  }
-  __syncthreads();
-  if (!ok) return;
-  if (tid < n_site) {
-    double p[kNparIn];
-    load_event(a, e, TIDAL, p);
-    site_setup(p, a.net.site[tid], ec, sc[tid]);
-  }
-  __syncthreads();
-
-  const uint32_t pm = event_rows(a.par_mask, e);
-  const double tc = a.tc_s ? a.tc_s[e] : 0.0;
-  const double amp0 = exp(ec.lnA);
-  const AmpFactors am = amp_factors(ec);
-  double2* __restrict__ out = reinterpret_cast<double2*>(a.dh) + a.offsets[e];
-  const int64_t row = a.total;
-  const int64_t prow = (int64_t)a.net.n_ifo * row;     // one parameter's block of rows
-  for (int k = tid; k < ec.n; k += kWBlock) {
-    // the event and site constants are re-read from LDS (uniform broadcast
-    // reads) rather than held in registers across iterations
-    asm volatile("" ::: "memory");
-    Point q;
-    point_setup<true, EXPL, PO::ecc>(ec, k, true, ROT, q, kPsdNone);
-    VPow pw;
-    vpow(q.v, q.L, pw);
-    const double iv = q.iv, iv2 = iv * iv, iv5 = iv2 * iv2 * iv;
-    const double amp = amp0 * iv2 * iv * sqrt(iv);
-    double pnc = eval_phase(ec.cyc, pw, iv5);
-    if (PO::ecc) pnc = fma(ec.ecc_cyc, q.ecv, pnc);
-    const double pn = frac_center(pnc);
-    const double ftr = fma(q.f, tc, -rint(q.f * tc));
-    const double cyc = frac_center(pn + ftr + ec.cyc0);
-    double cph[NPI];
-    phase_only_coefficients<NPI>(ec, q, cph);
-    double2* o = out + k;
-    for (int s = 0; s < n_site; ++s) {
-      asm volatile("" ::: "memory");
-      const SiteC& st = sc[s];
-      SitePoint sp;
-      site_point<false, true>(st, q, true, sp);
-      const SitePhase ph = site_phase(q, sp);
-      const double cH = q.cth * st.cdl - q.sth * st.sdl;
-      double sn, cs;
-      sincos_cycles<false>(frac_center(fma(q.f, fma(st.k1, cH, st.k0), cyc)), &sn, &cs);
-      const double ca = amp * cs, sa = amp * sn;
-      for (int j = 0; j < st.n_arm; ++j) {
-        const double Fp = dot4(st.arm_alpha[j], sp.P), Fx = dot4(st.arm_beta[j], sp.P);
-        double Dr[P], Di[P];
-        derivative_vector(am, q, ph, Fp, Fx, dot4(st.arm_alpha[j], sp.PH), dot4(st.arm_beta[j], sp.PH),
-                          dot4(st.arm_alpha[j], sp.Pt), dot4(st.arm_beta[j], sp.Pt), Dr, Di);
-        const double Qr = am.cplus * Fp, Qi = am.ccross * Fx;
-#pragma unroll
-        for (int i = 0; i < NPI; ++i) {          // i Q c
-          Dr[8 + i] = -Qi * cph[i];
-          Di[8 + i] = Qr * cph[i];
-        }
-#pragma unroll
-        for (int r = 0; r < P; ++r) {
-          const bool in = (pm >> r) & 1u;
-          o[r * prow] = in ? make_double2(Dr[r] * ca - Di[r] * sa, Dr[r] * sa + Di[r] * ca)
-                           : make_double2(0.0, 0.0);
-        }
-        o += row;
-      }
-    }
-  }
-}
-
 }  // namespace
 
 template <bool MIXED, bool EXPL>
@@ -339,29 +168,6 @@ hipError_t launch_waveform(const WaveformArgs& a0, bool tidal, bool rot, bool mi
       if (mixed) launch_waveform_t<true, false>(a, tidal, rot, grid, block, stream);
       else launch_waveform_t<false, false>(a, tidal, rot, grid, block, stream);
     }
-  });
-}
-
-template <int NPI, bool EXPL>
-void launch_deriv_n(const WaveformArgs& a, bool rot, dim3 grid, dim3 block, hipStream_t stream) {
-  if (rot) hipLaunchKernelGGL((waveform_deriv_kernel<true, NPI, EXPL>), grid, block, 0, stream, a);
-  else hipLaunchKernelGGL((waveform_deriv_kernel<false, NPI, EXPL>), grid, block, 0, stream, a);
-}
-
-template <bool EXPL>
-void launch_deriv_t(const WaveformArgs& a, int npi, bool rot, dim3 grid, dim3 block, hipStream_t stream) {
-  switch (npi) {
-    case 6: launch_deriv_n<6, EXPL>(a, rot, grid, block, stream); break;
-    case 5: launch_deriv_n<5, EXPL>(a, rot, grid, block, stream); break;
-    case 4: launch_deriv_n<4, EXPL>(a, rot, grid, block, stream); break;
-    default: launch_deriv_n<3, EXPL>(a, rot, grid, block, stream);
-  }
-}
-
-hipError_t launch_waveform_deriv(const WaveformArgs& a0, int npi, bool rot, hipStream_t stream) {
-  return launch_slices(a0, a0.n, 1, kWBlock, [&](const WaveformArgs& a, dim3 grid, dim3 block) {
-    if (a.gf) launch_deriv_t<true>(a, npi, rot, grid, block, stream);
-    else launch_deriv_t<false>(a, npi, rot, grid, block, stream);
   });
 }
 

@@ -31,12 +31,12 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # profiles/bns1e4_hbm_counters.md (calibrated against a 256 MiB copy: fetch
 # x 2.000, write x 1.000).  Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
-    "items_kernel<tidal,rot>": 61.18e6,
-    "items_kernel<tidal,rot,mixed>": 61.16e6,
-    "fisher_kernel<tidal,rot>": 77.70e6,
-    "waveform_kernel<rot,tidal>": 7829.69e6,
-    "waveform_kernel<rot,tidal,mixed>": 7881.85e6,
-    "waveform_deriv_kernel<rot,tidal>": 10306.52e6,
+    "items_kernel<tidal,rot>": 61.84e6,
+    "items_kernel<tidal,rot,mixed>": 61.84e6,
+    "fisher_kernel<tidal,rot>": 77.84e6,
+    "waveform_kernel<rot,tidal>": 7854.93e6,
+    "waveform_kernel<rot,tidal,mixed>": 7883.11e6,
+    "waveform_deriv_kernel<rot,tidal>": 10306.09e6,
 }
 
 # VALU instructions (wavefront instructions, SQ_INSTS_VALU, MFMA included) per
@@ -46,9 +46,9 @@ MEASURED_TRAFFIC = {
 # clock is 4 x SQ_INSTS_VALU / (1024 SIMDs x 2.4 GHz x kernel time).  Set an
 # entry to None when its kernel changes.
 MEASURED_VALU_INSTS = {
-    "items_kernel<tidal,rot>": 1.3564e9,
-    "items_kernel<tidal,rot,mixed>": 1.3396e9,
-    "fisher_kernel<tidal,rot>": 1.4219e9,
+    "items_kernel<tidal,rot>": 1.3237e9,
+    "items_kernel<tidal,rot,mixed>": 1.3244e9,
+    "fisher_kernel<tidal,rot>": 1.3749e9,
 }
 N_SIMD, CLOCK_HZ = 1024, 2.4e9
 
@@ -80,22 +80,22 @@ def log(msg):
 # instantiation the benchmarks run: tides, Earth rotation, analytic PSDs.
 # Split by where the work sits: once per point, per site, per effective
 # interferometer (n_eff = 1 per L site, 2 per closed triangle).
-#   items_kernel (FP64)   point 232 (grid, amplitude, PN series, sidereal
+#   items_kernel (FP64)   point 226 (grid, amplitude, PN series, sidereal
 #                         sin/cos, phase-only coefficients, staging),
-#                         site 59 (hour angle, PSD weight, arrival-time
+#                         site 55 (hour angle, PSD weight, arrival-time
 #                         derivatives), interferometer 221 (six pattern
 #                         polynomials, derivative vectors, 5x5 rank-2 update,
 #                         moments); MFMA 128 (16 per 64 points)
 #   items_kernel (mixed)  the same with the PSD's rational part in FP32:
 #                         site 33 FP64 (+ 13 FP32)
-#   adjoint_items_kernel  point 435 (the point set-up and the Gbar inner
-#                         products of the point's vectors), site 121, interferometer 304
+#   adjoint_items_kernel  point 418 (the point set-up and the Gbar inner
+#                         products of the point's vectors), site 115, interferometer 294
 # The counter passes (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes and
 # SQ_INSTS_VALU_MFMA_MOPS_F64 x 512) confirm these per launch.
 KERNEL_FLOPS = {
-    "items": {"point": 232, "site": 59, "ifo": 221, "mfma": 128},
-    "items_mixed": {"point": 233, "site": 33, "ifo": 221, "mfma": 128},
-    "adjoint": {"point": 435, "site": 121, "ifo": 304, "mfma": 0},
+    "items": {"point": 226, "site": 55, "ifo": 221, "mfma": 128},
+    "items_mixed": {"point": 226, "site": 33, "ifo": 221, "mfma": 128},
+    "adjoint": {"point": 418, "site": 115, "ifo": 294, "mfma": 0},
 }
 # SURVEY's dense per-(point, interferometer) count (Gram 2P(P+1), weighting
 # 2P, SNR 4, derivative assembly 8P, projection 120, PN 200 per point): the

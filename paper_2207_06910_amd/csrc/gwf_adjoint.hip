@@ -125,6 +125,73 @@ __device__ __attribute__((always_inline)) inline void adjoint_sums(const EventC&
   }
 }
 
+// adjoint_sums with PAIR = false and two grid points per lane and iteration,
+// k and k + nb (the same walk, taken two points at a time): the two points'
+// site terms are independent instruction streams the compiler interleaves,
+// and each site's constants are read once for both.  A point past k1 is
+// evaluated as the item's last point with zero weight (every term of
+// adjoint_site carries the weight), so the site code has no branch; its walk
+// values would overflow on a short grid.  The column gets the two points'
+// sum per site and iteration.
+template <int NPI, bool ROT, bool TAB>
+__device__ __attribute__((always_inline)) inline void adjoint_sums2(const EventC& ec, const AdjEventC& ae,
+                                                                    const SiteC* sc, const AdjSiteC* as, int n_site,
+                                                                    int k0, int k1, int nb, double* accl) {
+  const int tid = threadIdx.x;
+  const int r = tid % kWalk;
+  int k = k0 + tid;
+  int a = k - k % kAnchor;
+  GridWalk gw;
+  gw.start(ec, a + r, kWalk);
+  for (int q = (k - a) / kWalk; q > 0; --q) gw.step();
+  // from the lane's current point to kn = that point + nb
+  auto advance = [&](int kn) {
+    if (kn - a >= kAnchor) {
+      a = kn - kn % kAnchor;
+      gw.anchor(ec, a + r);
+      for (int q = (kn - a) / kWalk; q > 0; --q) gw.step();
+    } else {
+      for (int q = nb / kWalk; q > 0; --q) gw.step();
+    }
+  };
+  const int iters = (k1 - k0 + 2 * nb - 1) / (2 * nb);
+  for (int it = 0; it < iters; ++it, k += 2 * nb) {
+    asm volatile("" ::: "memory");   // constants are re-read rather than held in registers
+    // grid values of point kk, or of the item's last point where kk >= k1
+    auto values = [&](int kk, double* vv) {
+      if (kk < k1) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) vv[i] = gw.val[i];
+      } else {
+        const double L = fma((double)(k1 - 1), ec.dlnv, ec.lnv0);
+        vv[0] = exp(L);
+        vv[1] = exp(-L);
+        vv[2] = exp(-12.42 * L);
+      }
+    };
+    if (it > 0) advance(k);
+    AdjPoint p1, p2;
+    double v1[3], v2[3];
+    values(k, v1);
+    adjoint_point_setup<NPI, ROT>(ec, ae, k < k1 ? k : k1 - 1, p1, v1);
+    advance(k + nb);
+    values(k + nb, v2);
+    adjoint_point_setup<NPI, ROT>(ec, ae, k + nb < k1 ? k + nb : k1 - 1, p2, v2);
+    if (k >= k1) p1.q.w4A2 = 0.0;
+    if (k + nb >= k1) p2.q.w4A2 = 0.0;
+    for (int s = 0; s < n_site; ++s) {
+      asm volatile("" ::: "memory");
+      double acc[kAdjN];
+#pragma unroll
+      for (int i = 0; i < kAdjN; ++i) acc[i] = 0.0;
+      adjoint_site<TAB>(ae, sc[s], as[s], p1, acc);
+      adjoint_site<TAB>(ae, sc[s], as[s], p2, acc);
+#pragma unroll
+      for (int i = 0; i < kSlots; ++i) atomicAdd(&accl[(s * kSlots + i) * nb + tid], acc[i]);
+    }
+  }
+}
+
 // The site sums of the workgroup's columns (as adjoint_sums left them), in a
 // fixed order: wave w of the nb / 64 takes the values t = w, w + nb / 64, ...;
 // each lane adds its columns in column order, then the wavefront butterfly.
@@ -303,7 +370,10 @@ __global__ __launch_bounds__(kABlock, 2) void adjoint_items_kernel(AdjItemsArgs 
   }
   for (int t = tid; t < width * kABlock; t += kABlock) accl[t] = 0.0;
   __syncthreads();
-  adjoint_sums<NPI, ROT, TAB, false>(ec, ae, sc, as, n_site, k0, k1, kABlock, accl);
+  // two points per lane where both fit in the registers (the eccentric
+  // instantiations spill with two and keep one)
+  if (PhaseOnly<NPI>::ecc) adjoint_sums<NPI, ROT, TAB, false>(ec, ae, sc, as, n_site, k0, k1, kABlock, accl);
+  else adjoint_sums2<NPI, ROT, TAB>(ec, ae, sc, as, n_site, k0, k1, kABlock, accl);
   __syncthreads();
   adjoint_columns<false>(accl, width, kABlock, out);
 }

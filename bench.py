@@ -33,10 +33,10 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 MEASURED_TRAFFIC = {
     "items_kernel<tidal,rot>": 61.84e6,
     "items_kernel<tidal,rot,mixed>": 61.84e6,
-    "fisher_kernel<tidal,rot>": 77.84e6,
-    "waveform_kernel<rot,tidal>": 7854.93e6,
-    "waveform_kernel<rot,tidal,mixed>": 7883.11e6,
-    "waveform_deriv_kernel<rot,tidal>": 10306.09e6,
+    "fisher_kernel<tidal,rot>": 78.10e6,
+    "waveform_kernel<rot,tidal>": 7855.53e6,
+    "waveform_kernel<rot,tidal,mixed>": 7883.26e6,
+    "waveform_deriv_kernel<rot,tidal>": 10305.48e6,
 }
 
 # VALU instructions (wavefront instructions, SQ_INSTS_VALU, MFMA included) per
@@ -88,14 +88,16 @@ def log(msg):
 #                         moments); MFMA 128 (16 per 64 points)
 #   items_kernel (mixed)  the same with the PSD's rational part in FP32:
 #                         site 33 FP64 (+ 13 FP32)
-#   adjoint_items_kernel  point 418 (the point set-up and the Gbar inner
+#   adjoint_items_kernel  point 412 (the point set-up and the Gbar inner
 #                         products of the point's vectors), site 115, interferometer 294
+#                         (two points per lane and iteration; points past an item's
+#                         end run at zero weight and are not in the model)
 # The counter passes (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes and
 # SQ_INSTS_VALU_MFMA_MOPS_F64 x 512) confirm these per launch.
 KERNEL_FLOPS = {
     "items": {"point": 226, "site": 55, "ifo": 221, "mfma": 128},
     "items_mixed": {"point": 226, "site": 33, "ifo": 221, "mfma": 128},
-    "adjoint": {"point": 418, "site": 115, "ifo": 294, "mfma": 0},
+    "adjoint": {"point": 412, "site": 115, "ifo": 294, "mfma": 0},
 }
 # SURVEY's dense per-(point, interferometer) count (Gram 2P(P+1), weighting
 # 2P, SNR 4, derivative assembly 8P, projection 120, PN 200 per point): the

@@ -1,8 +1,9 @@
 // gwf_batched.hip -- batched form of the Fisher/SNR path for catalogues with
 // uneven grid lengths.
 //
-//   setup_kernel    one lane per event (and per event x site): the per-event
-//                   and per-site constants, written once to a workspace.
+//   setup_kernel    one lane per event and one per event x site: the
+//                   per-event and per-site constants, written once to a
+//                   workspace.
 //   items_kernel    one workgroup per work item (event, point range [k0, k1),
 //                   at most `chunk` points), dispatched in the plan's
 //                   longest-first order, writes the item's partial sums to its
@@ -30,26 +31,32 @@ __global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
-__global__ void setup_kernel(SetupArgs a) {
+// Lanes [0, n) take one event each (EventC and its status), lanes
+// [n, n + n n_site) one (event, site) pair each (SiteC, with pi M formed from
+// the parameters exactly as the event's lane forms it); both write straight
+// into the workspace.  A site of an event whose set-up fails is written
+// anyway and never read.
+__global__ __launch_bounds__(64) void setup_kernel(SetupArgs a) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.n) return;
+  const int n_site = a.net.n_site;
+  if (t >= a.n * (1 + n_site)) return;
+  const int64_t e = t < a.n ? t : (t - a.n) / n_site;
   const bool tidal = (a.flags & kFlagTidal) != 0;
   double p[kNparIn];
-  for (int r = 0; r < 13; ++r) p[r] = (r < 11 || tidal) ? a.par[r * a.ld + t] : 0.0;
-  p[13] = (a.flags & kFlagEcc) && a.ecc ? a.ecc[t] : 0.0;
-  p[14] = (a.flags & kFlagEcc) && a.fref ? a.fref[t] : 0.0;
-  EventC ec;
-  event_setup(p, a.fmin[t], a.fmax ? a.fmax[t] : 0.0, a.npts[t], a.flags, ec);
-  if (!ec.status && (a.npts[t] != a.npts_plan[t] || a.npts[t] > a.npts_max))
-    ec.status = kEvInvalid;   // grid changed since the items were built, or longer than they allow
-  a.evc[t] = ec;
-  if (a.status) a.status[t] = ec.status;
-  if (!ec.status)
-    for (int s = 0; s < a.net.n_site; ++s) {
-      SiteC sc;
-      site_setup(p, a.net.site[s], ec, sc, site_arms_on(a.active, a.ld, t, a.net, s));
-      a.sic[t * a.net.n_site + s] = sc;
-    }
+  for (int r = 0; r < 13; ++r) p[r] = (r < 11 || tidal) ? a.par[r * a.ld + e] : 0.0;
+  p[13] = (a.flags & kFlagEcc) && a.ecc ? a.ecc[e] : 0.0;
+  p[14] = (a.flags & kFlagEcc) && a.fref ? a.fref[e] : 0.0;
+  if (t < a.n) {
+    EventC& ec = a.evc[e];
+    event_setup(p, a.fmin[e], a.fmax ? a.fmax[e] : 0.0, a.npts[e], a.flags, ec);
+    if (!ec.status && (a.npts[e] != a.npts_plan[e] || a.npts[e] > a.npts_max))
+      ec.status = kEvInvalid;   // grid changed since the items were built, or longer than they allow
+    if (a.status) a.status[e] = ec.status;
+    return;
+  }
+  const int s = (int)(t - a.n - e * n_site);
+  site_setup(p, a.net.site[s], kPi * total_mass_s(p), a.sic[e * n_site + s],
+             site_arms_on(a.active, a.ld, e, a.net, s));
 }
 
 template <int NPI, bool ROT, bool MIXED, bool TAB>
@@ -182,7 +189,8 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(setup_kernel, dim3((unsigned)((a.n + 127) / 128)), dim3(128), 0, s, a);
+  const int64_t lanes = a.n * (1 + (int64_t)a.net.n_site);
+  hipLaunchKernelGGL(setup_kernel, dim3((unsigned)((lanes + 63) / 64)), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

@@ -345,13 +345,17 @@ __host__ __device__ inline int32_t check_event(const double* p, bool tidal, doub
 
 // Build the per-event constants.  p[13] are the parameters in boundary
 // order; fmax <= 0 selects the cut frequency.
+// The binary's total mass in seconds, M = Mc eta^(-3/5) G/c^3 (pi M sets the
+// grid's v = (pi M f)^(1/3) and the PSD's x = f/f0 of every site).
+__host__ __device__ inline double total_mass_s(const double* p) { return p[0] * pow(p[1], -0.6) * kTsun; }
+
 __host__ __device__ inline void event_setup(const double* p, double fmin, double fmax, int32_t n,
                                             uint32_t flags, EventC& ec) {
   const bool tidal = (flags & kFlagTidal) != 0;
   const bool rot = (flags & kFlagRot) != 0;
   const bool ecc = (flags & kFlagEcc) != 0;
   const double Mc = p[0], eta = p[1], dL = p[2];
-  const double Ms = Mc * pow(eta, -0.6) * kTsun;
+  const double Ms = total_mass_s(p);
   if (!(fmax > 0.0)) fmax = cut_frequency_of(Ms);
   ec.n = n;
   ec.fx = nullptr;
@@ -564,8 +568,10 @@ __host__ __device__ inline void pattern_map(double gamma, double zeta, double c2
 // interferometers with weights 3/2 and 1/2); with some arms off, every arm
 // that is on is its own effective interferometer.  A site with no arm on has
 // none (its patterns are still set for the strain).
-__host__ __device__ inline void site_setup(const double* p, const SiteDesc& sd, const EventC& ec,
-                                           SiteC& sc, uint32_t arm_on = 7u) {
+// piM: pi times the event's total mass in seconds (EventC::piM, the only
+// event constant a site needs).
+__host__ __device__ inline void site_setup(const double* p, const SiteDesc& sd, double piM, SiteC& sc,
+                                           uint32_t arm_on = 7u) {
   const double th = p[3], ph = p[4], psi = p[6];
   const double c2p = cos(2.0 * psi), s2p = sin(2.0 * psi);
   sc.cdl = cos(sd.lon - ph);
@@ -579,9 +585,9 @@ __host__ __device__ inline void site_setup(const double* p, const SiteDesc& sd, 
   sc.k0 = -kREarthS * sl * ct;
   sc.k1t = -kREarthS * cl * ct;
   sc.k0t = kREarthS * sl * st;
-  sc.lnx_off = -log(ec.piM) - log(sd.f0);
+  sc.lnx_off = -log(piM) - log(sd.f0);
   sc.xp_fac = exp(-4.14 * sc.lnx_off);
-  sc.ix_fac = sd.f0 * ec.piM;
+  sc.ix_fac = sd.f0 * piM;
   sc.x_fac = 1.0 / sc.ix_fac;
   sc.S0inv = 1.0 / sd.S0;
   sc.tab_f = sd.tab_f;
@@ -644,6 +650,11 @@ __host__ __device__ inline void site_setup(const double* p, const SiteDesc& sd, 
       sc.jk[j][3][m] = w * fxt;
     }
   }
+}
+
+__host__ __device__ inline void site_setup(const double* p, const SiteDesc& sd, const EventC& ec, SiteC& sc,
+                                           uint32_t arm_on = 7u) {
+  site_setup(p, sd, ec.piM, sc, arm_on);
 }
 
 // The arm mask of site s for event e from the per-interferometer flags

@@ -165,15 +165,17 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
   for (int i = 0; i < P; ++i) x[i] = h[i];
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
     bool rotated = false;
+    // squared column norms: exact at the start of each sweep, then carried
+    // through the rotations
+    double nx = col_dot<P>(x, x);
 #pragma unroll 1
     for (int t = 0; t < M - 1; ++t) {
       const int q = jacobi_partner<M>(j, t);
-      const double nx = col_dot<P>(x, x), sx = sqrt(nx);
       double y[P];
 #pragma unroll
       for (int i = 0; i < P; ++i) y[i] = __shfl(x[i], q, kGroup);
-      const double ny = __shfl(nx, q, kGroup), sy = __shfl(sx, q, kGroup);
-      if (jacobi_update<P>(x, y, nx, sx, ny, sy, j, q)) rotated = true;
+      const double ny = __shfl(nx, q, kGroup);
+      if (jacobi_update<P>(x, y, nx, ny, j, q)) rotated = true;
     }
     if (!__any(rotated)) break;
   }
@@ -280,23 +282,27 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
     for (int i = 0; i < P; ++i) vs[i] = (i == j) ? 1.0 : 0.0;
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
       bool rotated = false;
+      double nx = col_dot<P>(xs, xs);
 #pragma unroll 1
       for (int t = 0; t < M - 1; ++t) {
         const int q = jacobi_partner<M>(j, t);
-        const double nx = col_dot<P>(xs, xs), sx = sqrt(nx);
         double y[P], yv[P];
 #pragma unroll
         for (int i = 0; i < P; ++i) {
           y[i] = __shfl(xs[i], q, kGroup);
           yv[i] = __shfl(vs[i], q, kGroup);
         }
-        const double ny = __shfl(nx, q, kGroup), sy = __shfl(sx, q, kGroup);
-        double c, sg;
-        if (jacobi_pair<P>(xs, y, nx, sx, ny, sy, j, q, c, sg)) rotated = true;
+        const double ny = __shfl(nx, q, kGroup);
+        double c, sg, gam, tn;
+        const bool rot = jacobi_pair<P>(xs, y, nx, ny, j, q, c, sg, gam, tn);
 #pragma unroll
         for (int i = 0; i < P; ++i) {
           xs[i] = fma(sg, y[i], c * xs[i]);
           vs[i] = fma(sg, yv[i], c * vs[i]);
+        }
+        if (rot) {
+          nx = rotated_norm<P>(xs, nx, gam, tn, j < q);
+          rotated = true;
         }
       }
       if (!__any(rotated)) break;

@@ -30,31 +30,34 @@ __host__ __device__ inline int jacobi_partner(int j, int t) {
   return q;
 }
 
-// Rotation of the column pair (x_p, x_q) with ap = |x_p|^2, aq = |x_q|^2,
-// gam = x_p . x_q and spq = |x_p| |x_q|: x_p' = c x_p - s x_q,
-// x_q' = s x_p + c x_q makes x_p' . x_q' vanish when t = s/c is the smaller
-// root of t^2 + 2 zeta t - 1 = 0, zeta = (aq - ap) / (2 gam), i.e. with
-// d = aq - ap and r = sqrt(d^2 + 4 gam^2),
-//   t = sign(d) 2 gam / (|d| + r),   c^2 = (1 + |d|/r) / 2.
+// Rotation of the column pair (x_p, x_q) with ap = |x_p|^2, aq = |x_q|^2 and
+// gam = x_p . x_q: x_p' = c x_p - s x_q, x_q' = s x_p + c x_q makes
+// x_p' . x_q' vanish when t = s/c is the smaller root of
+// t^2 + 2 zeta t - 1 = 0, zeta = (aq - ap) / (2 gam), i.e. with d = aq - ap
+// and r = sqrt(d^2 + 4 gam^2),
+//   t = sign(d) 2 gam / (|d| + r),   c^2 = (1 + |d|/r) / 2,
+// and then |x_p'|^2 = ap - t gam, |x_q'|^2 = aq + t gam.
 // (d, 2 gam) are scaled by a power of two first (exact; keeps d^2 + 4 gam^2
 // in range).  c comes from its own square root rather than 1/sqrt(1 + t^2),
 // one division fewer on the dependent chain; c^2 (1 + t^2) = 1 exactly in
-// exact arithmetic.  Returns false (c = 1, s = 0) for a pair that is
-// already orthogonal to kJacobiTol.
-__host__ __device__ inline bool hestenes_rotation(double ap, double aq, double gam, double spq, double& c,
-                                                  double& s) {
+// exact arithmetic.  Returns false (c = 1, s = t = 0) for a pair that is
+// already orthogonal to kJacobiTol, tested as gam^2 <= kJacobiTol^2 ap aq
+// (no square root).
+__host__ __device__ inline bool hestenes_rotation(double ap, double aq, double gam, double& c, double& s,
+                                                  double& t) {
   c = 1.0;
   s = 0.0;
-  if (!(fabs(gam) > kJacobiTol * spq)) return false;
+  t = 0.0;
+  if (!(gam * gam > (kJacobiTol * kJacobiTol) * (ap * aq))) return false;
   const double dl = aq - ap, g2 = 2.0 * gam;
   int ex;
   frexp(fmax(fabs(dl), fabs(g2)), &ex);
   const double ds = ldexp(dl, -ex), gs = ldexp(g2, -ex);
   const double ad = fabs(ds);
   const double r = sqrt(fma(ds, ds, gs * gs));
-  const double tn = copysign(1.0, dl) * gs / (ad + r);
+  t = copysign(1.0, dl) * gs / (ad + r);
   c = sqrt(fma(0.5, ad / r, 0.5));
-  s = c * tn;
+  s = c * t;
   return true;
 }
 
@@ -74,32 +77,44 @@ __host__ __device__ inline double col_dot(const double* x, const double* y) {
 }
 
 // One column's part of a Jacobi step: x is column j, y its partner column q
-// (q == j: no partner), nx = x . x, sx = sqrt(nx) and ny, sy the same for y,
-// each as its owner computed them.  Both columns of a pair compute the same
-// rotation from the same bits; the new column is c x + sg y.  Returns true
-// if the pair was rotated (c = 1, sg = 0 otherwise).
+// (q == j: no partner), nx and ny their squared norms as their owners hold
+// them.  Both columns of a pair compute the same rotation from the same
+// bits; the new column is c x + sg y, gam = x . y and tn = t of the rotation.
+// Returns true if the pair was rotated (c = 1, sg = gam = tn = 0 otherwise).
 template <int P>
-__host__ __device__ inline bool jacobi_pair(const double* x, const double* y, double nx, double sx, double ny,
-                                            double sy, int j, int q, double& c, double& sg) {
+__host__ __device__ inline bool jacobi_pair(const double* x, const double* y, double nx, double ny, int j,
+                                            int q, double& c, double& sg, double& gam, double& tn) {
   c = 1.0;
   sg = 0.0;
+  gam = 0.0;
+  tn = 0.0;
   if (q == j) return false;
-  const double gam = col_dot<P>(x, y);
+  gam = col_dot<P>(x, y);
   const bool first = j < q;
   double s;
-  const bool rot = hestenes_rotation(first ? nx : ny, first ? ny : nx, gam, sx * sy, c, s);
+  const bool rot = hestenes_rotation(first ? nx : ny, first ? ny : nx, gam, c, s, tn);
   sg = first ? -s : s;
   return rot;
 }
 
-// The step applied to column j itself.
+// Column j's squared norm after the rotation of jacobi_pair (x already
+// rotated): ap - t gam for the lower-index column, aq + t gam for the other,
+// or the exact inner product where the update would have lost more than half
+// of the norm to cancellation.
 template <int P>
-__host__ __device__ inline bool jacobi_update(double* x, const double* y, double nx, double sx, double ny,
-                                              double sy, int j, int q) {
-  double c, sg;
-  const bool rot = jacobi_pair<P>(x, y, nx, sx, ny, sy, j, q, c, sg);
+__host__ __device__ inline double rotated_norm(const double* x, double nx, double gam, double tn, bool first) {
+  const double u = first ? fma(-tn, gam, nx) : fma(tn, gam, nx);
+  return u >= 0.5 * nx ? u : col_dot<P>(x, x);
+}
+
+// The step applied to column j itself; nx is updated to its new squared norm.
+template <int P>
+__host__ __device__ inline bool jacobi_update(double* x, const double* y, double& nx, double ny, int j, int q) {
+  double c, sg, gam, tn;
+  const bool rot = jacobi_pair<P>(x, y, nx, ny, j, q, c, sg, gam, tn);
 #pragma unroll
   for (int i = 0; i < P; ++i) x[i] = fma(sg, y[i], c * x[i]);
+  if (rot) nx = rotated_norm<P>(x, nx, gam, tn, j < q);
   return rot;
 }
 

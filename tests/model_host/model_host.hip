@@ -166,17 +166,18 @@ static void jacobi_cond_one(const double* F, int64_t n, int64_t e, double* cond,
   int sw = 0;
   for (; sw < 40; ++sw) {
     bool any = false;
+    double nrm[G];
+    for (int j = 0; j < G; ++j) nrm[j] = col_dot<P>(x[j], x[j]);
     for (int t = 0; t < M - 1; ++t) {
-      double nrm[G], sn[G];
-      for (int j = 0; j < G; ++j) {
-        nrm[j] = col_dot<P>(x[j], x[j]);
-        sn[j] = std::sqrt(nrm[j]);
-      }
-      for (int j = 0; j < G; ++j)
-        for (int i = 0; i < P; ++i) y[j][i] = x[jacobi_partner<M>(j, t)][i];
+      double ny[G];
       for (int j = 0; j < G; ++j) {
         const int q = jacobi_partner<M>(j, t);
-        if (jacobi_update<P>(x[j], y[j], nrm[j], sn[j], nrm[q], sn[q], j, q)) any = true;
+        for (int i = 0; i < P; ++i) y[j][i] = x[q][i];
+        ny[j] = nrm[q];
+      }
+      for (int j = 0; j < G; ++j) {
+        const int q = jacobi_partner<M>(j, t);
+        if (jacobi_update<P>(x[j], y[j], nrm[j], ny[j], j, q)) any = true;
       }
     }
     if (!any) break;

@@ -80,14 +80,15 @@ def log(msg):
 # instantiation the benchmarks run: tides, Earth rotation, analytic PSDs.
 # Split by where the work sits: once per point, per site, per effective
 # interferometer (n_eff = 1 per L site, 2 per closed triangle).
-#   items_kernel (FP64)   point 226 (grid, amplitude, PN series, sidereal
+#   items_kernel (FP64)   point 223 (grid, amplitude, PN series, sidereal
 #                         sin/cos, phase-only coefficients, staging),
-#                         site 55 (hour angle, PSD weight, arrival-time
-#                         derivatives), interferometer 221 (six pattern
+#                         site 57 (hour angle, root of the PSD weight and the
+#                         weighted trigonometric basis, arrival-time
+#                         derivatives), interferometer 213 (six pattern
 #                         polynomials, derivative vectors, 5x5 rank-2 update,
 #                         moments); MFMA 128 (16 per 64 points)
 #   items_kernel (mixed)  the same with the PSD's rational part in FP32:
-#                         site 33 FP64 (+ 13 FP32)
+#                         site 35 FP64 (+ 14 FP32)
 #   adjoint_items_kernel  point 412 (the point set-up and the Gbar inner
 #                         products of the point's vectors), site 115, interferometer 294
 #                         (two points per lane and iteration; points past an item's
@@ -95,8 +96,8 @@ def log(msg):
 # The counter passes (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes and
 # SQ_INSTS_VALU_MFMA_MOPS_F64 x 512) confirm these per launch.
 KERNEL_FLOPS = {
-    "items": {"point": 226, "site": 55, "ifo": 221, "mfma": 128},
-    "items_mixed": {"point": 226, "site": 33, "ifo": 221, "mfma": 128},
+    "items": {"point": 223, "site": 57, "ifo": 213, "mfma": 128},
+    "items_mixed": {"point": 223, "site": 35, "ifo": 213, "mfma": 128},
     "adjoint": {"point": 412, "site": 115, "ifo": 294, "mfma": 0},
 }
 # SURVEY's dense per-(point, interferometer) count (Gram 2P(P+1), weighting

@@ -89,6 +89,11 @@ enum { kTsTheta = 0, kTsMc, kTsEta };
 struct EventC {
   // grid: v_k = exp(lnv0 + k dlnv), f_k = v_k^3 / (pi M), trapezoid weights
   double lnv0, dlnv, inv_piM, piM, wint, wfirst, wlast;
+  // sqrt(w KA4 / (pi M)) for the three weights: sqrt(4 w_k A_k^2) = rw v_k^-2
+  // (the Fisher kernels' root weight), and a pad that keeps the 16-byte
+  // alignment of the fields below, which kernels holding the struct in LDS
+  // read in 16-byte pairs
+  double rwint, rwfirst, rwlast, pad_rw;
   // explicit grid: the event's frequencies (NULL on a log grid) and ln(pi M),
   // v_k = exp((ln(pi M) + ln f_k)/3), weights (f_{k+1} - f_{k-1})/2
   const double* fx;
@@ -125,6 +130,9 @@ struct SiteC {
   double lnx_off, ix_fac, x_fac;  // ln(f/f0) = 3 ln v + lnx_off; f0/f = ix_fac v^-3; f/f0 = x_fac v^3
   double xp_fac;               // (f/f0)^-4.14 = xp_fac v^-12.42
   double S0inv;                // 1/S0
+  // S0 times the PSD shape's coefficients (the root weight's form, see
+  // psd_root_weight), and sqrt(1/S0)
+  double xpS0, m5S0, k111S0, rS0inv;
   double alpha[2][4], beta[2][4], weff[2];  // effective interferometers (pattern maps)
   // the effective interferometers' F+, Fx and their theta derivatives as
   // trigonometric polynomials in the hour angle H: coefficients of
@@ -309,6 +317,30 @@ __host__ __device__ inline double recip(double x) {
 #endif
 }
 
+// 1/sqrt(x) for finite x > 0: the hardware estimate y (relative error up to
+// about 2^-23) refined by one third-order step, y (1 + e/2 + 3 e^2/8) with
+// e = 1 - x y^2 (the series of (1 - e)^-1/2; the first term left out, 5e^3/16,
+// is below 2^-66); the host build divides.
+__host__ __device__ inline double rsqrt_d(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(0.375, e, 0.5), y);
+#else
+  return 1.0 / sqrt(x);
+#endif
+}
+
+// sqrt(x) in FP32 from the hardware square root (about an ulp); the host
+// build calls sqrtf.
+__host__ __device__ inline float sqrtf_hw(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_sqrtf(x);
+#else
+  return sqrtf(x);
+#endif
+}
+
 // 1/x in FP32 from the hardware reciprocal (about an ulp); the host build divides.
 __host__ __device__ inline float recipf(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -377,6 +409,10 @@ __host__ __device__ inline void event_setup(const double* p, double fmin, double
   const double Mcs = Mc * kTsun, dLs = dL * kGpcS;
   ec.KA4 = 4.0 * (5.0 / 24.0) * pow(kPi, -4.0 / 3.0) * pow(Mcs, 5.0 / 3.0) * pow(ec.piM, 7.0 / 3.0) /
            (dLs * dLs);
+  ec.rwint = sqrt(ec.wint * ec.KA4 * ec.inv_piM);
+  ec.rwfirst = sqrt(ec.wfirst * ec.KA4 * ec.inv_piM);
+  ec.rwlast = sqrt(ec.wlast * ec.KA4 * ec.inv_piM);
+  ec.pad_rw = 0.0;
   ec.dlnA_dMc = 5.0 / (6.0 * Mc);
   ec.inv_dL = 1.0 / dL;
   // 2 pi tcoal reduced to [0, 2 pi)
@@ -590,6 +626,10 @@ __host__ __device__ inline void site_setup(const double* p, const SiteDesc& sd, 
   sc.ix_fac = sd.f0 * piM;
   sc.x_fac = 1.0 / sc.ix_fac;
   sc.S0inv = 1.0 / sd.S0;
+  sc.xpS0 = sd.S0 * sc.xp_fac;
+  sc.m5S0 = -5.0 * sd.S0;
+  sc.k111S0 = 111.0 * sd.S0;
+  sc.rS0inv = sqrt(sc.S0inv);
   sc.tab_f = sd.tab_f;
   sc.tab_S = sd.tab_S;
   sc.tab_n = sd.tab_n;
@@ -803,6 +843,7 @@ __host__ __device__ inline double eval_tau(const TauSeries& s, const VPow& w, do
 // Frequency-point quantities shared by all sites.
 struct Point {
   double v, iv, L, f, tf, w4A2;   // tf = 2 pi f; w4A2 = 4 w A^2 (PSD not yet applied)
+  double rw;                      // sqrt(w4A2)
   double cth, sth;                // cos, sin of the sidereal angle at t(f)
   double gMc, gEta;               // d(sidereal angle)/dMc, /deta
   double pMc, pEta;               // dPsi_PN/dMc, /deta
@@ -869,6 +910,7 @@ template <bool PSUM = true, bool EXPL = false, bool ECC = false>
 __host__ __device__ inline void point_setup(const EventC& ec, int32_t k, bool need_derivs, bool rot,
                                             Point& q, int psd = kPsdF64, const double* vrec = nullptr) {
   double L, v, f, wf;               // wf: the trapezoid weight
+  double rwe = 0.0;                 // log grid: sqrt(w KA4 / (pi M)) of the point's weight
   if (EXPL) {
     f = ec.fx[k];
     L = (ec.lnpiM + log(f)) / 3.0;
@@ -879,8 +921,15 @@ __host__ __device__ inline void point_setup(const EventC& ec, int32_t k, bool ne
     v = vrec ? vrec[0] : exp(L);
     f = (v * v * v) * ec.inv_piM;
     double w = ec.wint;
-    if (k == 0) w = ec.wfirst;
-    if (k == ec.n - 1) w = ec.wlast;
+    rwe = ec.rwint;
+    if (k == 0) {
+      w = ec.wfirst;
+      rwe = ec.rwfirst;
+    }
+    if (k == ec.n - 1) {
+      w = ec.wlast;
+      rwe = ec.rwlast;
+    }
     wf = w * f;
   }
   const double iv = (!EXPL && vrec) ? vrec[1] : recip(v);
@@ -890,6 +939,7 @@ __host__ __device__ inline void point_setup(const EventC& ec, int32_t k, bool ne
   q.iv3 = iv2 * iv;
   q.tf = kTwoPi * f;
   q.w4A2 = wf * ec.KA4 * iv7;
+  q.rw = EXPL ? sqrt(q.w4A2) : rwe * iv2;
   q.vpsd = 0.0;
   if (!EXPL && vrec && psd != kPsdNone) {
     q.vpsd = vrec[2];
@@ -1029,6 +1079,49 @@ __host__ __device__ inline void psd_weight_f32(const SiteC& sc, const Point& q, 
   om = q.w4A2 * sc.S0inv * (double)(den * recipf(top));
 }
 
+// The square root of the weight, r = sqrt(4 w A^2 / S_n(f)), which the
+// Fisher kernels fold into the pattern values: every Fisher entry is a sum of
+// w Re(D_a D_b^*), bilinear in the derivative vectors, and those are linear
+// in the pattern values, so the weighted sums follow from r D with no
+// per-entry weight product.  With S_n = S0 top / den (psd_weight_of),
+// r = sqrt(4 w A^2) den / sqrt(den S0 top); S0 top is formed from the site's
+// S0-scaled coefficients, so 1/S0 costs nothing per point.  A sampled curve,
+// and the per-site evaluation of the power law (PSUM = false), take the root
+// of the full weight.
+template <bool PSUM = true, bool TAB = true>
+__host__ __device__ inline double psd_root_weight(const SiteC& sc, const Point& q) {
+  if ((TAB && sc.tab_kind) || !PSUM) {
+    double om;
+    psd_weight<PSUM, TAB>(sc, q, om);
+    return sqrt(om);
+  }
+  const double ix = sc.ix_fac * q.iv3;             // f0/f
+  const double x = sc.x_fac * q.v3;                // f/f0
+  const double ix2 = ix * ix;
+  const double x2 = x * x;
+  const double num = fma(0.5 * x2, x2, 1.0 - x2);
+  const double den = fma(0.5, x2, 1.0);
+  const double topS = fma(fma(sc.m5S0, ix2, sc.xpS0 * q.vpsd), den, sc.k111S0 * num);
+  return (q.rw * den) * rsqrt_d(den * topS);
+}
+
+// The same root in the mixed form: the shape as in psd_weight_f32,
+// sqrt(den / top) in FP32 (den/top = S0/S_n stays within FP32's range), so a
+// relative error e in r is one of about 2e in the weight, the positive factor
+// whose error psd_weight_f32 bounds.
+template <bool TAB = true>
+__host__ __device__ inline double psd_root_weight_f32(const SiteC& sc, const Point& q) {
+  if (TAB && sc.tab_kind)
+    return sqrt(table_weight(sc.tab_f, sc.tab_S, sc.tab_n, sc.tab_kind, sc.S0inv, q.w4A2, q.f));
+  const float xp = (float)(sc.xp_fac * q.vpsd);
+  const double x = sc.x_fac * q.v3, ix = sc.ix_fac * q.iv3;
+  const float x2 = (float)(x * x), ix2 = (float)(ix * ix);
+  const float num = fmaf(0.5f * x2, x2, 1.0f - x2);
+  const float den = fmaf(0.5f, x2, 1.0f);
+  const float top = fmaf(fmaf(-5.0f, ix2, xp), den, 111.0f * num);
+  return (q.rw * sc.rS0inv) * (double)sqrtf_hw(den * recipf(top));
+}
+
 template <bool MIXED = false, bool PSUM = true, bool TAB = true>
 __host__ __device__ inline void site_point(const SiteC& sc, const Point& q, bool need_derivs,
                                            SitePoint& sp) {
@@ -1080,6 +1173,44 @@ __host__ __device__ inline void site_trig(const SiteC& sc, const Point& q, SiteT
   else psd_weight<PSUM, TAB>(sc, q, sp.om);
   sp.dH = -sc.k1 * sH;
   sp.dT = fma(sc.k1t, cH, sc.k0t);
+}
+
+// The Fisher kernels' site quantities: the patterns' trigonometric basis
+// scaled by the root weight r (psd_root_weight), so that SiteC::jk's
+// polynomials give r F+, r Fx and their derivatives directly; cos H and
+// sin H themselves for the arrival-time derivatives.
+struct SiteTrigR {
+  double cH, sH;
+  double r, rc, rs, rc2, rs2;   // r (1, cos H, sin H, cos 2H, sin 2H)
+  double p2c, m2s;              // r (2 cos 2H, -2 sin 2H)
+  double dH, dT;                // dDelta/dH, dDelta/dtheta
+};
+
+template <bool MIXED = false, bool PSUM = true, bool TAB = true>
+__host__ __device__ inline void site_trig_root(const SiteC& sc, const Point& q, SiteTrigR& sp) {
+  const double cH = q.cth * sc.cdl - q.sth * sc.sdl;
+  const double sH = q.sth * sc.cdl + q.cth * sc.sdl;
+  sp.cH = cH;
+  sp.sH = sH;
+  const double r = MIXED ? psd_root_weight_f32<TAB>(sc, q) : psd_root_weight<PSUM, TAB>(sc, q);
+  sp.r = r;
+  sp.rc = r * cH;
+  sp.rs = r * sH;
+  sp.rc2 = fma(sp.rc, cH, -sp.rs * sH);
+  sp.rs2 = 2.0 * (sp.rs * cH);
+  sp.p2c = 2.0 * sp.rc2;
+  sp.m2s = -2.0 * sp.rs2;
+  sp.dH = -sc.k1 * sH;
+  sp.dT = fma(sc.k1t, cH, sc.k0t);
+}
+
+// r times a trigonometric polynomial of SiteC::jk, and r times its H
+// derivative (the constant term last, as in trig_val).
+__host__ __device__ inline double trig_val_r(const double c[5], const SiteTrigR& sp) {
+  return fma(c[0], sp.r, fma(c[4], sp.rs2, fma(c[3], sp.rc2, fma(c[2], sp.rs, c[1] * sp.rc))));
+}
+__host__ __device__ inline double trig_dH_r(const double c[5], const SiteTrigR& sp) {
+  return fma(c[4], sp.p2c, fma(c[3], sp.m2s, fma(c[2], sp.rc, -c[1] * sp.rs)));
 }
 
 // A trigonometric polynomial of SiteC::jk at the point, and its H derivative.
@@ -1188,45 +1319,45 @@ __host__ __device__ inline void accumulate_point(const EventC& ec, const SiteC* 
   for (int b = 0; b < 5; ++b) UR[b] = 0.0;
   for (int s = 0; s < n_site; ++s) {
     const SiteC& st = sc[s];
-    SiteTrig sp;
-    site_trig<MIXED, PSUM, TAB>(st, q, sp);
+    SiteTrigR sp;
+    site_trig_root<MIXED, PSUM, TAB>(st, q, sp);
     const SitePhase ph = site_phase(q, sp.dH, sp.dT);
     // at most two effective interferometers per site; the count is the same
     // for every lane, so the second pass is skipped as a whole where unused.
     // The patterns are trigonometric polynomials in H whose coefficients
-    // carry sqrt(weff), so every product below is already weighted by weff.
+    // carry sqrt(weff), and the basis carries the root weight r, so Fp, Fx,
+    // the derivative vectors and Q below are r times their unweighted values
+    // and every product of two of them is weighted by w = weff r^2.
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       if (j >= st.n_eff) break;
-      const double om = sp.om;
       const double(*c)[5] = st.jk[j];
-      const double Fp = trig_val(c[0], sp), Fx = trig_val(c[1], sp);
+      const double Fp = trig_val_r(c[0], sp), Fx = trig_val_r(c[1], sp);
       double Dr[8], Di[8];
-      derivative_vector(am, q, ph, Fp, Fx, trig_dH(c[0], sp), trig_dH(c[1], sp), trig_val(c[2], sp),
-                        trig_val(c[3], sp), Dr, Di);
+      derivative_vector(am, q, ph, Fp, Fx, trig_dH_r(c[0], sp), trig_dH_r(c[1], sp), trig_val_r(c[2], sp),
+                        trig_val_r(c[3], sp), Dr, Di);
       const double Qr = am.cplus * Fp, Qi = am.ccross * Fx;
-      const double wp = om * Fp, wx = om * Fx;
       int g = 0;
 #pragma unroll
       for (int a = 0; a < 5; ++a) {
         const int r = kGramRows[a];
-        const double wr = om * Dr[r], wi = om * Di[r];
+        const double dr = Dr[r], di = Di[r];
 #pragma unroll
         for (int b = a; b < 5; ++b) {
           const int c = kGramRows[b];
-          G[g] = fma(wr, Dr[c], fma(wi, Di[c], G[g]));
+          G[g] = fma(dr, Dr[c], fma(di, Di[c], G[g]));
           ++g;
         }
-        G[15 + 4 * a + 0] = fma(wp, Dr[r], G[15 + 4 * a + 0]);
-        G[15 + 4 * a + 1] = fma(wp, Di[r], G[15 + 4 * a + 1]);
-        G[15 + 4 * a + 2] = fma(wx, Dr[r], G[15 + 4 * a + 2]);
-        G[15 + 4 * a + 3] = fma(wx, Di[r], G[15 + 4 * a + 3]);
-        // Re(i Q D_r^*) w = Qr (w Di_r) - Qi (w Dr_r), from the weighted row
-        UR[a] = fma(Qr, wi, fma(-Qi, wr, UR[a]));
+        G[15 + 4 * a + 0] = fma(Fp, dr, G[15 + 4 * a + 0]);
+        G[15 + 4 * a + 1] = fma(Fp, di, G[15 + 4 * a + 1]);
+        G[15 + 4 * a + 2] = fma(Fx, dr, G[15 + 4 * a + 2]);
+        G[15 + 4 * a + 3] = fma(Fx, di, G[15 + 4 * a + 3]);
+        // w Re(i Q D_r^*) = (r Qr)(r Di_r) - (r Qi)(r Dr_r)
+        UR[a] = fma(Qr, di, fma(-Qi, dr, UR[a]));
       }
-      spp = fma(wp, Fp, spp);
-      spx = fma(wp, Fx, spx);
-      sxx = fma(wx, Fx, sxx);
+      spp = fma(Fp, Fp, spp);
+      spx = fma(Fp, Fx, spx);
+      sxx = fma(Fx, Fx, sxx);
     }
   }
   G[35] += spp;

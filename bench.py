@@ -31,12 +31,12 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # profiles/bns1e4_hbm_counters.md (calibrated against a 256 MiB copy: fetch
 # x 2.000, write x 1.000).  Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
-    "items_kernel<tidal,rot>": 61.84e6,
-    "items_kernel<tidal,rot,mixed>": 61.84e6,
-    "fisher_kernel<tidal,rot>": 78.10e6,
-    "waveform_kernel<rot,tidal>": 7855.53e6,
-    "waveform_kernel<rot,tidal,mixed>": 7883.26e6,
-    "waveform_deriv_kernel<rot,tidal>": 10305.48e6,
+    "items_kernel<tidal,rot>": 63.60e6,
+    "items_kernel<tidal,rot,mixed>": 65.61e6,
+    "fisher_kernel<tidal,rot>": 74.65e6,
+    "waveform_kernel<rot,tidal>": 7853.33e6,
+    "waveform_kernel<rot,tidal,mixed>": 7888.54e6,
+    "waveform_deriv_kernel<rot,tidal>": 10306.97e6,
 }
 
 # VALU instructions (wavefront instructions, SQ_INSTS_VALU, MFMA included) per
@@ -46,9 +46,9 @@ MEASURED_TRAFFIC = {
 # clock is 4 x SQ_INSTS_VALU / (1024 SIMDs x 2.4 GHz x kernel time).  Set an
 # entry to None when its kernel changes.
 MEASURED_VALU_INSTS = {
-    "items_kernel<tidal,rot>": 1.3237e9,
-    "items_kernel<tidal,rot,mixed>": 1.3244e9,
-    "fisher_kernel<tidal,rot>": 1.3749e9,
+    "items_kernel<tidal,rot>": 1.2594e9,
+    "items_kernel<tidal,rot,mixed>": 1.2593e9,
+    "fisher_kernel<tidal,rot>": 1.3102e9,
 }
 N_SIMD, CLOCK_HZ = 1024, 2.4e9
 

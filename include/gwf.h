@@ -171,7 +171,8 @@ enum { GWF_PSD_ANALYTIC = 0, GWF_PSD_TABLE = 1, GWF_ASD_TABLE = 2 };
  * zero weight (the detector is blind there).  Both arrays are DEVICE
  * memory owned by the caller; their ordering and positivity are the
  * caller's (not checked: a value <= 0 inside the range makes that site's
- * weights infinite or negative, flagged GWF_EV_NONFINITE where it shows). */
+ * weights infinite or negative, or NaN in the Fisher kernels, which take the
+ * weight's square root; flagged GWF_EV_NONFINITE where it shows). */
 typedef struct gwf_site {
   double lat, lon, gamma, zeta;
   int32_t shape;

@@ -7,6 +7,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "gwf_arith.hpp"
+
 namespace gwf {
 
 // A column pair counts as orthogonal once |x_p . x_q| <= kJacobiTol |x_p| |x_q|:
@@ -37,12 +39,15 @@ __host__ __device__ inline int jacobi_partner(int j, int t) {
 // and r = sqrt(d^2 + 4 gam^2),
 //   t = sign(d) 2 gam / (|d| + r),   c^2 = (1 + |d|/r) / 2,
 // and then |x_p'|^2 = ap - t gam, |x_q'|^2 = aq + t gam.
-// (d, 2 gam) are scaled by a power of two first (exact; keeps d^2 + 4 gam^2
-// in range).  c comes from its own square root rather than 1/sqrt(1 + t^2),
-// one division fewer on the dependent chain; c^2 (1 + t^2) = 1 exactly in
-// exact arithmetic.  Returns false (c = 1, s = t = 0) for a pair that is
-// already orthogonal to kJacobiTol, tested as gam^2 <= kJacobiTol^2 ap aq
-// (no square root).
+// (d, 2 gam) are scaled by a power of two first (exact), so that
+// rho = d^2 + 4 gam^2 lies in [1/4, 2); then 1/r from the refined reciprocal
+// square root, u = |d| + r, t from the refined reciprocal of u, and
+// c = sqrt(h) = h / sqrt(h) with h = u / (2 r) in [1/2, 1]: each within a
+// few ulps, with no division and no library square root on the dependent
+// chain of the sweep.  c comes from its own square root rather than from
+// 1/sqrt(1 + t^2), one step shorter; c^2 (1 + t^2) = 1 in exact arithmetic.
+// Returns false (c = 1, s = t = 0) for a pair that is already orthogonal to
+// kJacobiTol, tested as gam^2 <= kJacobiTol^2 ap aq (no square root).
 __host__ __device__ inline bool hestenes_rotation(double ap, double aq, double gam, double& c, double& s,
                                                   double& t) {
   c = 1.0;
@@ -54,9 +59,12 @@ __host__ __device__ inline bool hestenes_rotation(double ap, double aq, double g
   frexp(fmax(fabs(dl), fabs(g2)), &ex);
   const double ds = ldexp(dl, -ex), gs = ldexp(g2, -ex);
   const double ad = fabs(ds);
-  const double r = sqrt(fma(ds, ds, gs * gs));
-  t = copysign(1.0, dl) * gs / (ad + r);
-  c = sqrt(fma(0.5, ad / r, 0.5));
+  const double rho = fma(ds, ds, gs * gs);
+  const double ri = rsqrt_d(rho);              // 1/r
+  const double u = fma(rho, ri, ad);           // |d| + r
+  t = (copysign(1.0, dl) * gs) * recip(u);
+  const double h = 0.5 * (u * ri);
+  c = h * rsqrt_d(h);
   s = c * t;
   return true;
 }

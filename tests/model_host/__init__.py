@@ -11,7 +11,8 @@ LIB = os.path.join(HERE, "libmodel_host.so")
 DEPS = [SRC, os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_model.hpp"),
         os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_adjoint.hpp"),
         os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_invert.hpp"),
-        os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_dd.hpp")]
+        os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_dd.hpp"),
+        os.path.join(HERE, "..", "..", "paper_2207_06910_amd", "csrc", "gwf_arith.hpp")]
 _lib = None
 
 

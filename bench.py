@@ -100,10 +100,10 @@ KERNEL_FLOPS = {
     "items_mixed": {"point": 223, "site": 35, "ifo": 213, "mfma": 128},
     "adjoint": {"point": 412, "site": 115, "ifo": 294, "mfma": 0},
 }
-# SURVEY's dense per-(point, interferometer) count (Gram 2P(P+1), weighting
-# 2P, SNR 4, derivative assembly 8P, projection 120, PN 200 per point): the
-# work of evaluating every interferometer's full P x P Gram, which the
-# kernels' exact identities avoid
+# A dense per-(point, interferometer) count (Gram 2P(P+1), weighting 2P,
+# SNR 4, derivative assembly 8P, projection 120, PN 200 per point): the work
+# of evaluating every interferometer's full P x P Gram, which the kernels'
+# exact identities avoid
 DENSE_PER_POINT_IFO = lambda P: 2 * P * (P + 1) + 2 * P + 4 + 8 * P + 120
 
 

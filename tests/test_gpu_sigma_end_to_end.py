@@ -125,7 +125,7 @@ def test_sigma_end_to_end_plan(lib, case, mixed):
     the plain form.  Mixed: its noise weight carries a relative error e of
     about 1e-7, a positive factor per point, so (1 - e) Gamma <= Gamma' <=
     (1 + e) Gamma and each sigma moves by at most e/2 whatever kappa; the bar
-    is 1e-3 (the benchmark spec's mixed tolerance) on events with kappa < 1e12, and
+    is 1e-3 (the mixed form's sigma tolerance) on events with kappa < 1e12, and
     1e-6 on the well-conditioned block."""
     wl, ref, inv13, inv9 = case
     dw = lib.DeviceWorkload(wl)

@@ -274,8 +274,8 @@ gwf_status gwf_snr(const gwf_events* ev, const gwf_network* net, const gwf_grid*
 
 /* Network Fisher matrix (sec. 3.2) and SNR of every event, fused.
  *   fisher  device [P][P][n], required, P = 13 with GWF_TIDAL else 11, the
- *           "array of matrices in the last dimension" layout of sec. 3.2;
- *           both triangles are written
+ *           the event index last, as the paper stacks its matrices
+ *           (sec. 3.2); both triangles are written
  *   snr, snr_ifo, status as in gwf_snr (snr required, status required)
  *   snr_th  <= 0: every event; > 0: the Fisher is computed only where the
  *           network SNR exceeds snr_th (decided by a first SNR pass), other

@@ -33,10 +33,10 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 MEASURED_TRAFFIC = {
     "items_kernel<tidal,rot>": 63.60e6,
     "items_kernel<tidal,rot,mixed>": 65.61e6,
-    "fisher_kernel<tidal,rot>": 74.65e6,
-    "waveform_kernel<rot,tidal>": 7853.33e6,
-    "waveform_kernel<rot,tidal,mixed>": 7888.54e6,
-    "waveform_deriv_kernel<rot,tidal>": 10306.97e6,
+    "fisher_kernel<tidal,rot>": 74.69e6,
+    "waveform_kernel<rot,tidal>": 7854.94e6,
+    "waveform_kernel<rot,tidal,mixed>": 7881.72e6,
+    "waveform_deriv_kernel<rot,tidal>": 10306.44e6,
 }
 
 # VALU instructions (wavefront instructions, SQ_INSTS_VALU, MFMA included) per

@@ -26,8 +26,8 @@ namespace gwf {
 
 // Declared for 2 x kBlock lanes so that the register budget is that of two
 // wavefronts per SIMD (256 registers); launched with kBlock lanes, two
-// workgroups (about 60 KB of LDS each: 54 KB of FisherLds, the event's
-// 1 KB of constants and 3.8 KB for eight sites) then share a compute unit,
+// workgroups (about 61 KB of LDS each: 53 KB of FisherLds, the event's
+// 1.1 KB of constants and 6.9 KB for eight sites) then share a compute unit,
 // which hides the latency of the LDS constant reads and of the
 // transcendental sequences.
 // (The P = 11 instantiation keeps the one-wavefront budget: under the

@@ -34,8 +34,13 @@ constexpr int kRowsA = 16;        // 7 U rows, up to 5 W c rows, zero rows to a 
 constexpr int kRowsB = 8;         // up to 5 c rows, zero rows to a whole tile
 constexpr int kZeroRowB = 7;      // a B row no point writes (operand of unused tile slots)
 constexpr int kZeroRowA = 15;
-constexpr int kTileLd = 64 + 4;   // row stride (doubles): an operand read touches 8 rows x
-                                  // 4 points, 2 (8 row + k) mod 64 distinct dword banks
+// Row stride of the staged operands, in doubles.  A 64-bit LDS read of a
+// wavefront is served 32 lanes at a time by 64 four-byte banks; the 32 lanes
+// of an MFMA operand read take rows 4 t + i (up to 16 rows, t the tile slot,
+// i = 0..3) at points 4 s + k (k = 0, 1), so row r starts on bank
+// 2 r LD mod 64: LD = 66 puts the 16 rows x 2 points on 32 distinct bank
+// pairs (no conflicts; the earlier stride of 68 doubled up rows 4 apart).
+constexpr int kTileLd = 64 + 2;
 constexpr int kNaccMax = 105;    // 36 + 8 NPI + NPI (NPI + 1)/2 at NPI = 6
 constexpr int kURow[7] = {0, 1, 3, 4, 5, 6, 7};   // the U rows staged (U_dL = 0)
 
@@ -199,18 +204,15 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
   if (full < iters) iteration(full, true);
 
   // ---- deterministic reduction: wavefront butterflies, then the waves in order
-  double F[NG];
-  gram_finish(ec, G, F);
-#pragma unroll
-  for (int i = 0; i < NG; ++i) {
-    const double t = wave_sum(F[i]);
-    if (lane == 0) L.red[wave][i] = t;
-  }
-  // the Phic column: Gamma_{b,Phic} = -sum U_b from the pattern moments,
-  // Gamma_{Phic,Phic} = sum W, Gamma_{Phic, 8+j} = -sum W c_j
+  // The 8x8 block (NG values) and the Phic column (7 + NPI values: -sum U_b
+  // from the pattern moments for the rows Mc, eta, theta, phi, tc, iota, psi,
+  // then Gamma_{Phic,Phic} = sum W and Gamma_{Phic, 8+j} = -sum W c_j).
+  constexpr int NR = NG + 7 + NPI;
+  double rv[NR];
+  gram_finish(ec, G, rv);
   {
     const AmpFactors am = amp_factors(ec);
-    double xc[10 + NPI - 1];
+    double* xc = rv + NG;
 #pragma unroll
     for (int a = 0; a < 5; ++a)
       xc[a] = fma(am.ccross, G[17 + 4 * a], -am.cplus * G[16 + 4 * a]);   // rows Mc, eta, theta, phi, tc
@@ -219,20 +221,32 @@ __device__ inline void fisher_sums(const EventC& ec, const SiteC* sc, int n_site
     xc[7] = fma(am.cplus * am.cplus, G[35], am.ccross * am.ccross * G[37]);   // Phic, Phic
 #pragma unroll
     for (int i = 1; i < NPI; ++i) xc[7 + i] = -wc[i - 1];
+  }
+  // Each value is summed over the wavefront as wave_sum does (the same
+  // additions in the same order), but step by step over all NR values, so
+  // that a step's cross-lane reads are in flight together rather than one
+  // value's six dependent exchanges after another's.
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) rv[i] += __shfl_xor(rv[i], off, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NG; ++i) L.red[wave][i] = rv[i];
     constexpr int rowof[5] = {0, 1, 3, 4, 7};
 #pragma unroll
     for (int x = 0; x < 7 + NPI; ++x) {
-      const double t = wave_sum(xc[x]);
       int slot;
       if (x < 5) slot = NG + rowof[x] * NPI;
       else if (x == 5) slot = NG + 5 * NPI;
       else if (x == 6) slot = NG + 6 * NPI;
       else slot = NG + NX + (x - 7);                 // row Phic: (8, 8 + x - 7)
-      if (lane == 0) L.red[wave][slot] = t;
+      L.red[wave][slot] = rv[NG + x];
     }
-    // the dL row of the phase-only block is exactly zero (U_dL = 0)
-    if (lane < NPI) L.red[wave][NG + 2 * NPI + lane] = 0.0;
   }
+  // the dL row of the phase-only block is exactly zero (U_dL = 0)
+  if (lane < NPI) L.red[wave][NG + 2 * NPI + lane] = 0.0;
   // lane 16 i + 4 q + j of accumulator m holds element (i, j) of tile 4 m + q:
   // rows 0..6 of X are U_0, U_1, U_3 .. U_7, rows 7.. the W c_i rows (i >= 1),
   // column c is c_{c+1}; the upper triangle of W c_i c_j is kept

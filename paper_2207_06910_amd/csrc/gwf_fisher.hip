@@ -26,7 +26,7 @@ namespace gwf {
 
 // Declared for 2 x kBlock lanes so that the register budget is that of two
 // wavefronts per SIMD (256 registers); launched with kBlock lanes, two
-// workgroups (about 61 KB of LDS each: 53 KB of FisherLds, the event's
+// workgroups (about 63 KB of LDS each: 54 KB of FisherLds, the event's
 // 1.1 KB of constants and 6.9 KB for eight sites) then share a compute unit,
 // which hides the latency of the LDS constant reads and of the
 // transcendental sequences.

@@ -34,13 +34,15 @@ constexpr int kRowsA = 16;        // 7 U rows, up to 5 W c rows, zero rows to a 
 constexpr int kRowsB = 8;         // up to 5 c rows, zero rows to a whole tile
 constexpr int kZeroRowB = 7;      // a B row no point writes (operand of unused tile slots)
 constexpr int kZeroRowA = 15;
-// Row stride of the staged operands, in doubles.  A 64-bit LDS read of a
-// wavefront is served 32 lanes at a time by 64 four-byte banks; the 32 lanes
-// of an MFMA operand read take rows 4 t + i (up to 16 rows, t the tile slot,
-// i = 0..3) at points 4 s + k (k = 0, 1), so row r starts on bank
-// 2 r LD mod 64: LD = 66 puts the 16 rows x 2 points on 32 distinct bank
-// pairs (no conflicts; the earlier stride of 68 doubled up rows 4 apart).
-constexpr int kTileLd = 64 + 2;
+// Row stride of the staged operands, in doubles.  The lanes of an MFMA
+// operand read take rows 4 t + i (up to 16 rows: t the tile slot, i = 0..3)
+// at points 4 s + k, and row r starts on four-byte bank 2 r LD mod 64.  With
+// LD odd, r LD mod 32 differs for all 16 rows (an odd factor permutes the
+// residues), so the rows of a read, and of the paired reads the compiler
+// forms, fall on distinct banks.  Measured on the BNS catalogue: strides 68
+// and 66 left 3.9e8 and 9.9e7 bank-conflict cycles per launch, 65 and 67 none
+// (67 the fastest).
+constexpr int kTileLd = 67;
 constexpr int kNaccMax = 105;    // 36 + 8 NPI + NPI (NPI + 1)/2 at NPI = 6
 constexpr int kURow[7] = {0, 1, 3, 4, 5, 6, 7};   // the U rows staged (U_dL = 0)
 

@@ -31,12 +31,12 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # profiles/bns1e4_hbm_counters.md (calibrated against a 256 MiB copy: fetch
 # x 2.000, write x 1.000).  Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
-    "items_kernel<tidal,rot>": 63.60e6,
-    "items_kernel<tidal,rot,mixed>": 65.61e6,
-    "fisher_kernel<tidal,rot>": 74.69e6,
-    "waveform_kernel<rot,tidal>": 7854.94e6,
-    "waveform_kernel<rot,tidal,mixed>": 7881.72e6,
-    "waveform_deriv_kernel<rot,tidal>": 10306.44e6,
+    "items_kernel<tidal,rot>": 63.58e6,
+    "items_kernel<tidal,rot,mixed>": 65.59e6,
+    "fisher_kernel<tidal,rot>": 76.31e6,
+    "waveform_kernel<rot,tidal>": 7853.20e6,
+    "waveform_kernel<rot,tidal,mixed>": 7880.95e6,
+    "waveform_deriv_kernel<rot,tidal>": 10305.77e6,
 }
 
 # VALU instructions (wavefront instructions, SQ_INSTS_VALU, MFMA included) per
@@ -47,7 +47,7 @@ MEASURED_TRAFFIC = {
 # entry to None when its kernel changes.
 MEASURED_VALU_INSTS = {
     "items_kernel<tidal,rot>": 1.2594e9,
-    "items_kernel<tidal,rot,mixed>": 1.2593e9,
+    "items_kernel<tidal,rot,mixed>": 1.2592e9,
     "fisher_kernel<tidal,rot>": 1.3102e9,
 }
 N_SIMD, CLOCK_HZ = 1024, 2.4e9

@@ -32,6 +32,8 @@ namespace gwf {
 // transcendental sequences.
 // (The P = 11 instantiation keeps the one-wavefront budget: under the
 // two-wavefront cap it spills.)
+static_assert(64 + kMaxSites <= kBlock, "site set-up lanes in the second wavefront");
+
 template <int NPI_, bool ROT, bool EXPL, bool TAB>
 __global__ __launch_bounds__(FisherDims<NPI_>::TIDAL ? 2 * kBlock : kBlock) void fisher_kernel(FisherArgs a) {
   using Dm = FisherDims<NPI_>;
@@ -49,12 +51,18 @@ __global__ __launch_bounds__(FisherDims<NPI_>::TIDAL ? 2 * kBlock : kBlock) void
   const int n_site = a.net.n_site;
   double p[kNparIn];
   load_par(a.par, a.ld, e, PO::tidal, PO::ecc ? a.ecc : nullptr, a.fref, p);
+  // the event's constants on lane 0 and the sites' on the second wavefront,
+  // at the same time (a site needs only the parameters and pi M)
   if (tid == 0) {
     event_setup_grid(p, a.fmin, a.fmax, a.npts, a.goff, a.gf, e, flags, ec);
     int32_t sk = ec.status;
     if (!sk && a.snr_pre && !(a.snr_pre[e] > a.snr_th)) sk = kEvSkipped;
     skip = sk;
     bad = 0;
+  } else if (tid >= 64 && tid < 64 + n_site) {
+    const int s = tid - 64;
+    site_setup(p, a.net.site[s], kPi * total_mass_s(p), sc[s],
+               select_ifo(site_arms_on(a.active, a.ld, e, a.net, s), a.net, s, a.ifo_sel));
   }
   __syncthreads();
   if (skip) {
@@ -65,10 +73,6 @@ __global__ __launch_bounds__(FisherDims<NPI_>::TIDAL ? 2 * kBlock : kBlock) void
     }
     return;
   }
-  if (tid < n_site)
-    site_setup(p, a.net.site[tid], ec, sc[tid],
-               select_ifo(site_arms_on(a.active, a.ld, e, a.net, tid), a.net, tid, a.ifo_sel));
-  __syncthreads();
 
   double t = 0.0;
   fisher_sums<NPI, ROT, false, true, EXPL, TAB>(ec, sc, n_site, 0, ec.n, L, &t);
@@ -102,8 +106,11 @@ __global__ __launch_bounds__(kBlock) void snr_kernel(SnrArgs a) {
   const int n_site = a.net.n_site;
   double p[kNparIn];
   load_par(a.par, a.ld, e, a.tidal, nullptr, nullptr, p);
+  // the event's constants on lane 0 and the sites' on the second wavefront, at once
   if (tid == 0)
     event_setup_grid(p, a.fmin, a.fmax, a.npts, a.goff, a.gf, e, flags | (a.tidal ? kFlagTidal : 0u), ec);
+  else if (tid >= 64 && tid < 64 + n_site)
+    site_setup(p, a.net.site[tid - 64], kPi * total_mass_s(p), sc[tid - 64]);
   __syncthreads();
   if (ec.status) {
     if (tid == 0) {
@@ -114,8 +121,6 @@ __global__ __launch_bounds__(kBlock) void snr_kernel(SnrArgs a) {
       for (int i = tid; i < a.net.n_ifo; i += kBlock) a.snr_ifo[(int64_t)i * a.n + e] = 0.0;
     return;
   }
-  if (tid < n_site) site_setup(p, a.net.site[tid], ec, sc[tid]);
-  __syncthreads();
   // slot 3 s + k holds arm k of site s
   double acc[3 * kMaxSites];
 #pragma unroll

@@ -33,7 +33,7 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 MEASURED_TRAFFIC = {
     "items_kernel<tidal,rot>": 63.58e6,
     "items_kernel<tidal,rot,mixed>": 65.59e6,
-    "fisher_kernel<tidal,rot>": 76.31e6,
+    "fisher_kernel<tidal,rot>": 68.57e6,
     "waveform_kernel<rot,tidal>": 7853.20e6,
     "waveform_kernel<rot,tidal,mixed>": 7880.95e6,
     "waveform_deriv_kernel<rot,tidal>": 10305.77e6,
@@ -48,7 +48,7 @@ MEASURED_TRAFFIC = {
 MEASURED_VALU_INSTS = {
     "items_kernel<tidal,rot>": 1.2594e9,
     "items_kernel<tidal,rot,mixed>": 1.2592e9,
-    "fisher_kernel<tidal,rot>": 1.3102e9,
+    "fisher_kernel<tidal,rot>": 1.3111e9,
 }
 N_SIMD, CLOCK_HZ = 1024, 2.4e9
 

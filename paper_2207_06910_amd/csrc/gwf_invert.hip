@@ -98,6 +98,24 @@ __device__ inline void load_col(const InvertArgs& a, int64_t e, uint32_t am, int
   }
 }
 
+// The condition number of the normalised matrix from the columns X of its
+// one-sided Jacobi (the norms are its singular values), the ill-conditioned
+// flag and whether the matrix is inverted by its Cholesky factor.
+template <int P>
+__device__ inline void condition_of(const double* x, bool own, bool go0, bool pd, double cond_max,
+                                    double& cond, bool& ill, bool& ok) {
+  double smax = 0.0, smin = INFINITY;
+  if (own) smax = smin = sqrt(col_dot<P>(x, x));
+#pragma unroll
+  for (int off = kGroup / 2; off >= 1; off >>= 1) {
+    smax = fmax(smax, __shfl_xor(smax, off, kGroup));
+    smin = fmin(smin, __shfl_xor(smin, off, kGroup));
+  }
+  cond = smin > 0.0 ? smax / smin : INFINITY;
+  ill = go0 && !(cond <= cond_max);
+  ok = go0 && !ill && pd;
+}
+
 __device__ inline dd shfl_dd(dd v, int src) { return dd{__shfl(v.hi, src, kGroup), __shfl(v.lo, src, kGroup)}; }
 
 // At least 3 waves per SIMD: left free, the compiler spends all 256 registers
@@ -159,35 +177,6 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
 #pragma unroll
   for (int i = 0; i < P; ++i) h[i] = go0 ? h[i] / (d[i] * dj) : 0.0;
 
-  // ---- condition number: one-sided Jacobi on a copy of the columns
-  double x[P];
-#pragma unroll
-  for (int i = 0; i < P; ++i) x[i] = h[i];
-  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-    bool rotated = false;
-    // squared column norms: exact at the start of each sweep, then carried
-    // through the rotations
-    double nx = col_dot<P>(x, x);
-#pragma unroll 1
-    for (int t = 0; t < M - 1; ++t) {
-      const int q = jacobi_partner<M>(j, t);
-      double y[P];
-#pragma unroll
-      for (int i = 0; i < P; ++i) y[i] = __shfl(x[i], q, kGroup);
-      const double ny = __shfl(nx, q, kGroup);
-      if (jacobi_update<P>(x, y, nx, ny, j, q)) rotated = true;
-    }
-    if (!__any(rotated)) break;
-  }
-  double smax = 0.0, smin = INFINITY;
-  if (own) smax = smin = sqrt(col_dot<P>(x, x));
-#pragma unroll
-  for (int off = kGroup / 2; off >= 1; off >>= 1) {
-    smax = fmax(smax, __shfl_xor(smax, off, kGroup));
-    smin = fmin(smin, __shfl_xor(smin, off, kGroup));
-  }
-  const double cond = smin > 0.0 ? smax / smin : INFINITY;
-  const bool ill = go0 && !(cond <= a.cond_max);
 
   // ---- Cholesky, right-looking over columns
   double l[P];
@@ -213,8 +202,6 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
       l[k] = inv;
     }
   }
-  bool ok = go0 && !ill && pd;
-
   // ln det Gamma = 2 sum_i ln(d_i L_ii)
   double ld = own ? log(dj * ljj) : 0.0;
 #pragma unroll
@@ -258,134 +245,165 @@ __global__ __launch_bounds__(kInvBlock, 3) void invert_kernel(InvertArgs a) {
   }
   __syncthreads();
 
-  // ---- SVD inversions and eigen-decomposition, on request: the one-sided
-  // Jacobi again from the normalised columns, now accumulating the rotations
-  // V, so that H V = X = U diag(s) with orthonormal U and V; then
-  // H^-1 = V diag(w) U^T with w = 1/s (or the paper's truncated or dropped
-  // small singular values), and eigenvalue j = sign(u_j . v_j) s_j with
-  // eigenvector v_j.  Only wavefronts holding such a matrix run it.
-  const bool svd_grp = go0 && !ill && (a.method == 2 || a.method == 3 || (a.method == 1 && !pd));
+  // ---- condition number: one-sided Jacobi on the normalised columns
+  // (reloaded: the same bits as h).  A wavefront that holds a matrix the SVD
+  // below inverts, or whose eigen-decomposition is wanted, accumulates the
+  // rotations V as well (H V = X), so that the SVD needs no second Jacobi; X
+  // and the condition number come out the same either way.
   const bool want_eig = a.eigval != nullptr || a.eigvec != nullptr;
-  bool svd_done = false;
-  if (__any(svd_grp) || want_eig) {
-    // the normalisation again from the stored diagonal (the same bits as d;
-    // recomputed so that d need not stay in registers through this block)
-    double dn[P], dnj = 1.0;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      dn[i] = (go0 && normalise) ? sqrt(gamma_rc(a, e, am, i, i)) : 1.0;
-      if (i == j) dnj = dn[i];
-    }
-    double xs[P], vs[P];
-    load_col<P>(a, e, am, j, go0 && j < P, dn, dnj, xs);
+  const bool need_v =
+      __any(go0 && (a.method == 2 || a.method == 3 || (a.method == 1 && !pd))) || want_eig;
+  double x[P];
+  load_col<P>(a, e, am, j, go0 && j < P, d, dj, x);
+  double cond;
+  bool ill, ok, svd_done = false;
+  if (need_v) {
+    double vs[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) vs[i] = (i == j) ? 1.0 : 0.0;
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
       bool rotated = false;
-      double nx = col_dot<P>(xs, xs);
+      double nx = col_dot<P>(x, x);
 #pragma unroll 1
       for (int t = 0; t < M - 1; ++t) {
         const int q = jacobi_partner<M>(j, t);
         double y[P], yv[P];
 #pragma unroll
         for (int i = 0; i < P; ++i) {
-          y[i] = __shfl(xs[i], q, kGroup);
+          y[i] = __shfl(x[i], q, kGroup);
           yv[i] = __shfl(vs[i], q, kGroup);
         }
         const double ny = __shfl(nx, q, kGroup);
         double c, sg, gam, tn;
-        const bool rot = jacobi_pair<P>(xs, y, nx, ny, j, q, c, sg, gam, tn);
+        const bool rot = jacobi_pair<P>(x, y, nx, ny, j, q, c, sg, gam, tn);
 #pragma unroll
         for (int i = 0; i < P; ++i) {
-          xs[i] = fma(sg, y[i], c * xs[i]);
+          x[i] = fma(sg, y[i], c * x[i]);
           vs[i] = fma(sg, yv[i], c * vs[i]);
         }
         if (rot) {
-          nx = rotated_norm<P>(xs, nx, gam, tn, j < q);
+          nx = rotated_norm<P>(x, nx, gam, tn, j < q);
           rotated = true;
         }
       }
       if (!__any(rotated)) break;
     }
-    const double sj = sqrt(col_dot<P>(xs, xs));
-    double smx = own ? sj : 0.0;
-#pragma unroll
-    for (int off = kGroup / 2; off >= 1; off >>= 1) smx = fmax(smx, __shfl_xor(smx, off, kGroup));
-    const double inv_s = sj > 0.0 ? 1.0 / sj : 0.0;
-#pragma unroll
-    for (int i = 0; i < P; ++i) xs[i] *= inv_s;                    // u_j
-    const double lam = col_dot<P>(xs, vs) >= 0.0 ? sj : -sj;
+    condition_of<P>(x, own, go0, pd, a.cond_max, cond, ill, ok);
 
-    if (want_eig) {
-      // ascending position of this eigenvalue; eigenvector signed so that
-      // its largest-magnitude component (the first, on ties) is positive
-      int rank = 0;
-#pragma unroll
-      for (int m = 0; m < P; ++m) {
-        const double lm = __shfl(lam, m, kGroup);
-        if (lm < lam || (lm == lam && m < j)) ++rank;
-      }
-      double bv = -1.0, bs = 1.0;
-#pragma unroll
-      for (int i = 0; i < P; ++i)
-        if (fabs(vs[i]) > bv) { bv = fabs(vs[i]); bs = vs[i]; }
-      const double fl = bs < 0.0 ? -1.0 : 1.0;
-      if (live && j < P) {
-        if (a.eigval) a.eigval[(int64_t)rank * a.n + e] = go0 ? lam : nan;
-        if (a.eigvec)
-#pragma unroll
-          for (int i = 0; i < P; ++i) a.eigvec[((int64_t)i * P + rank) * a.n + e] = go0 ? fl * vs[i] : nan;
-      }
-    }
-
-    // H^-1 = V diag(w) U^T: U and w into Gs (w in the padding column), V
-    // into Ls, then column j of the upper triangle, both triangles into Ls
-    const double thr = a.svals_thresh * smx;
-    double w = inv_s;
-    if (sj < thr) {
-      if (a.method == 3) w = 0.0;
-      else if (a.method == 2 && a.truncate) w = 1.0 / thr;
-    }
-    if (svd_grp && j < P) {
+    // ---- SVD inversions and eigen-decomposition, on request, from the Jacobi
+    // above with the rotations V accumulated: H V = X = U diag(s) with
+    // orthonormal U and V; then H^-1 = V diag(w) U^T with w = 1/s (or the
+    // paper's truncated or dropped small singular values), and eigenvalue
+    // j = sign(u_j . v_j) s_j with eigenvector v_j.  Only wavefronts holding
+    // such a matrix run it (need_v held for them).
+    const bool svd_grp = go0 && !ill && (a.method == 2 || a.method == 3 || (a.method == 1 && !pd));
+    if (__any(svd_grp) || want_eig) {
+      // the normalisation again from the stored diagonal (the same bits as d;
+      // recomputed so that d need not stay in registers through this block)
+      double dn[P], dnj = 1.0;
 #pragma unroll
       for (int i = 0; i < P; ++i) {
-        Gs[g][j][i] = xs[i];
-        Ls[g][j][i] = vs[i];
+        dn[i] = (go0 && normalise) ? sqrt(gamma_rc(a, e, am, i, i)) : 1.0;
+        if (i == j) dnj = dn[i];
       }
-      Gs[g][j][P] = w;
-    }
-    __syncthreads();
-    double cc[P];
+      const double sj = sqrt(col_dot<P>(x, x));
+      double smx = own ? sj : 0.0;
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-      double t = 0.0;
-      if (svd_grp && j < P)
+      for (int off = kGroup / 2; off >= 1; off >>= 1) smx = fmax(smx, __shfl_xor(smx, off, kGroup));
+      const double inv_s = sj > 0.0 ? 1.0 / sj : 0.0;
 #pragma unroll
-        for (int m = 0; m < P; ++m) t = fma(Ls[g][m][i] * Gs[g][m][P], Gs[g][m][j], t);
-      cc[i] = t;
-    }
-    __syncthreads();
-    if (svd_grp && j < P) {
+      for (int i = 0; i < P; ++i) x[i] *= inv_s;                    // u_j
+      const double lam = col_dot<P>(x, vs) >= 0.0 ? sj : -sj;
+
+      if (want_eig) {
+        // ascending position of this eigenvalue; eigenvector signed so that
+        // its largest-magnitude component (the first, on ties) is positive
+        int rank = 0;
 #pragma unroll
-      for (int i = 0; i < P; ++i)
-        if (i <= j) {
-          const double cij = cc[i] / (dn[i] * dnj);
-          Ls[g][j][i] = cij;
-          Ls[g][i][j] = cij;
+        for (int m = 0; m < P; ++m) {
+          const double lm = __shfl(lam, m, kGroup);
+          if (lm < lam || (lm == lam && m < j)) ++rank;
         }
-    }
-    __syncthreads();
-    // ln det Gamma from the singular values where the Cholesky failed and all
-    // eigenvalues are positive: lsv sums 2 ln d_j + ln s_j = ln det Gamma,
-    // while ld holds half of it on every path (the output doubles it)
-    double lsv = own ? fma(2.0, log(dnj), log(sj)) : 0.0;
+        double bv = -1.0, bs = 1.0;
 #pragma unroll
-    for (int off = kGroup / 2; off >= 1; off >>= 1) lsv += __shfl_xor(lsv, off, kGroup);
-    const uint64_t negm = __ballot(own && !(lam > 0.0));
-    const bool allpos = ((negm >> (g * kGroup)) & 0xffffull) == 0;
-    if (svd_grp && !pd) ld = allpos ? 0.5 * lsv : nan;
-    svd_done = svd_grp;
-    ok = ok || svd_done;
+        for (int i = 0; i < P; ++i)
+          if (fabs(vs[i]) > bv) { bv = fabs(vs[i]); bs = vs[i]; }
+        const double fl = bs < 0.0 ? -1.0 : 1.0;
+        if (live && j < P) {
+          if (a.eigval) a.eigval[(int64_t)rank * a.n + e] = go0 ? lam : nan;
+          if (a.eigvec)
+#pragma unroll
+            for (int i = 0; i < P; ++i) a.eigvec[((int64_t)i * P + rank) * a.n + e] = go0 ? fl * vs[i] : nan;
+        }
+      }
+
+      // H^-1 = V diag(w) U^T: U and w into Gs (w in the padding column), V
+      // into Ls, then column j of the upper triangle, both triangles into Ls
+      const double thr = a.svals_thresh * smx;
+      double w = inv_s;
+      if (sj < thr) {
+        if (a.method == 3) w = 0.0;
+        else if (a.method == 2 && a.truncate) w = 1.0 / thr;
+      }
+      if (svd_grp && j < P) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          Gs[g][j][i] = x[i];
+          Ls[g][j][i] = vs[i];
+        }
+        Gs[g][j][P] = w;
+      }
+      __syncthreads();
+      double cc[P];
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        double t = 0.0;
+        if (svd_grp && j < P)
+#pragma unroll
+          for (int m = 0; m < P; ++m) t = fma(Ls[g][m][i] * Gs[g][m][P], Gs[g][m][j], t);
+        cc[i] = t;
+      }
+      __syncthreads();
+      if (svd_grp && j < P) {
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+          if (i <= j) {
+            const double cij = cc[i] / (dn[i] * dnj);
+            Ls[g][j][i] = cij;
+            Ls[g][i][j] = cij;
+          }
+      }
+      __syncthreads();
+      // ln det Gamma from the singular values where the Cholesky failed and all
+      // eigenvalues are positive: lsv sums 2 ln d_j + ln s_j = ln det Gamma,
+      // while ld holds half of it on every path (the output doubles it)
+      double lsv = own ? fma(2.0, log(dnj), log(sj)) : 0.0;
+#pragma unroll
+      for (int off = kGroup / 2; off >= 1; off >>= 1) lsv += __shfl_xor(lsv, off, kGroup);
+      const uint64_t negm = __ballot(own && !(lam > 0.0));
+      const bool allpos = ((negm >> (g * kGroup)) & 0xffffull) == 0;
+      if (svd_grp && !pd) ld = allpos ? 0.5 * lsv : nan;
+      svd_done = svd_grp;
+      ok = ok || svd_done;
+    }
+  } else {
+    for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+      bool rotated = false;
+      // squared column norms: exact at the start of each sweep, then carried
+      // through the rotations
+      double nx = col_dot<P>(x, x);
+#pragma unroll 1
+      for (int t = 0; t < M - 1; ++t) {
+        const int q = jacobi_partner<M>(j, t);
+        double y[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) y[i] = __shfl(x[i], q, kGroup);
+        const double ny = __shfl(nx, q, kGroup);
+        if (jacobi_update<P>(x, y, nx, ny, j, q)) rotated = true;
+      }
+      if (!__any(rotated)) break;
+    }
+    condition_of<P>(x, own, go0, pd, a.cond_max, cond, ill, ok);
   }
   // ---- double-double Cholesky (method 4): normalisation, factorisation,
   // L^-1 and C = L^-T L^-1 again in double-double arithmetic (~106 bits), so
